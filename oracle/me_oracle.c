@@ -1,0 +1,588 @@
+/*
+ * CPU oracle for the shape-adaptive motion estimator of Benboubker, Abdi and
+ * Ahaitouf, "Shape-Adaptive Motion Estimation Algorithm for MPEG-4 Video
+ * Coding".
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain definition that the
+ * GPU library is checked against.  Only the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it; the product never does.  It
+ * shares no source with the GPU library: every routine is written out here
+ * from the paper, in scalar loops, with no blocking, fusion or reordering.
+ *
+ * Conventions (the paper leaves them open; each reading is listed in the
+ * design notes):
+ *   - frame W x H (multiples of 16), macroblock (MB) (h, v) has its top-left
+ *     pixel at (16h, 16v); MBs are visited in raster order, rows v outer,
+ *     columns h inner (Fig. 1 loops);
+ *   - a full-pel motion vector d = (dx, dy) predicts cur(x, y) by
+ *     ref(x + dx, y + dy);
+ *   - every motion vector at the interface is int16 (x, y) in half-pel units;
+ *     integer results are even;
+ *   - MB classes: 0 transparent, 1 opaque, 2 boundary (Section 1).
+ *
+ * Parity pins live in the tests (closed forms, brute force, invariants).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_TRANSPARENT 0
+#define OR_OPAQUE 1
+#define OR_BOUNDARY 2
+
+typedef struct {
+    const uint8_t *cur_luma, *ref_luma;   /* row stride `stride` bytes */
+    const uint8_t *cur_alpha, *ref_alpha; /* both NULL: rectangular frames */
+    int width, height, stride;
+} or_pair;
+
+typedef struct {
+    int search_range; /* S: |dx|, |dy| <= S (full-pel) */
+    int theta;        /* gradient dead zone of Eq. 4 */
+    int eps_q12;      /* convergence factor of Eq. 3 in Q.12 */
+    int max_step;     /* largest per-axis step of one recursion */
+    int k_max;        /* cap on the recursion count */
+    int half_pel;     /* 1: half-sample refinement of texture MBs */
+} or_params;
+
+/* ------------------------------------------------------------ helpers */
+static int iabs(int a) { return a < 0 ? -a : a; }
+static int imin(int a, int b) { return a < b ? a : b; }
+static int imax(int a, int b) { return a > b ? a : b; }
+static int iclamp(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
+
+/* half-pel component -> full-pel, rounding toward minus infinity */
+static int half_to_full(int v) { return (v >= 0) ? v / 2 : -((-v + 1) / 2); }
+
+static int luma_at(const uint8_t *p, int stride, int x, int y) { return p[(size_t)y * stride + x]; }
+
+/* the binary shape plane of a VOP as gray levels: 255 inside, 0 outside */
+static int shape_at(const uint8_t *a, int stride, int x, int y) {
+    return a[(size_t)y * stride + x] != 0 ? 255 : 0;
+}
+
+static int plane_cur(const or_pair *fp, int shape, int x, int y) {
+    return shape ? shape_at(fp->cur_alpha, fp->stride, x, y) : luma_at(fp->cur_luma, fp->stride, x, y);
+}
+
+static int plane_ref(const or_pair *fp, int shape, int x, int y) {
+    return shape ? shape_at(fp->ref_alpha, fp->stride, x, y) : luma_at(fp->ref_luma, fp->stride, x, y);
+}
+
+/* ------------------------------------------------- MB classification */
+/*
+ * Section 1: an MB is transparent (no pixel of the VOP), opaque (every pixel
+ * inside) or boundary.  Inside means alpha != 0.  `bab` (optional) receives
+ * the 16x16 binary alpha block of each MB as 8 words: word w holds rows 2w
+ * (bits 0..15) and 2w+1 (bits 16..31), column i at bit i of its half.
+ */
+int or_classify(const uint8_t *alpha, int width, int height, int stride, uint8_t *cls, uint32_t *bab) {
+    if (!alpha || !cls || width <= 0 || height <= 0 || width % 16 || height % 16 || stride < width) return -1;
+    int wm = width / 16, hm = height / 16;
+    for (int v = 0; v < hm; ++v) {
+        for (int h = 0; h < wm; ++h) {
+            int n = 0;
+            uint32_t words[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int j = 0; j < 16; ++j) {
+                for (int i = 0; i < 16; ++i) {
+                    int in = alpha[(size_t)(16 * v + j) * stride + 16 * h + i] != 0;
+                    n += in;
+                    if (in) words[j / 2] |= 1u << ((j % 2) * 16 + i);
+                }
+            }
+            int k = v * wm + h;
+            cls[k] = (uint8_t)(n == 0 ? OR_TRANSPARENT : (n == 256 ? OR_OPAQUE : OR_BOUNDARY));
+            if (bab) memcpy(bab + 8 * (size_t)k, words, sizeof(words));
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------ block costs */
+/* Section 2 / 3.1: sum of absolute luma differences of the 16x16 block at
+ * (x0, y0) against the reference block displaced by (dx, dy). */
+uint32_t or_sad(const or_pair *fp, int x0, int y0, int dx, int dy) {
+    uint32_t s = 0;
+    for (int j = 0; j < 16; ++j)
+        for (int i = 0; i < 16; ++i)
+            s += (uint32_t)iabs(luma_at(fp->cur_luma, fp->stride, x0 + i, y0 + j) -
+                                luma_at(fp->ref_luma, fp->stride, x0 + i + dx, y0 + j + dy));
+    return s;
+}
+
+/* Fig. 1, boundary branch: the distortion of two binary alpha blocks is the
+ * number of pixels whose inside/outside state differs. */
+uint32_t or_mismatch(const or_pair *fp, int x0, int y0, int dx, int dy) {
+    uint32_t s = 0;
+    for (int j = 0; j < 16; ++j)
+        for (int i = 0; i < 16; ++i) {
+            int a = fp->cur_alpha[(size_t)(y0 + j) * fp->stride + x0 + i] != 0;
+            int b = fp->ref_alpha[(size_t)(y0 + j + dy) * fp->stride + x0 + i + dx] != 0;
+            s += (uint32_t)(a != b);
+        }
+    return s;
+}
+
+static uint32_t block_cost(const or_pair *fp, int shape, int x0, int y0, int dx, int dy) {
+    return shape ? or_mismatch(fp, x0, y0, dx, dy) : or_sad(fp, x0, y0, dx, dy);
+}
+
+/* A full-pel vector is admissible when |dx|, |dy| <= S and the whole
+ * displaced block lies inside the reference frame. */
+static int feasible(const or_pair *fp, int S, int x0, int y0, int dx, int dy) {
+    return iabs(dx) <= S && iabs(dy) <= S && x0 + dx >= 0 && x0 + dx <= fp->width - 16 && y0 + dy >= 0 &&
+           y0 + dy <= fp->height - 16;
+}
+
+/* ------------------------------------ pel-recursive search (Section 3.2) */
+/*
+ * Eq. 4 with Eq. 5: u = 0 where |df/dx| < Theta, else 1/(df/dx), with
+ * df/dx = g / 2 for the central difference g = f(x+1) - f(x-1).  Hence
+ * u = 2/g for |g| >= 2 Theta.  Returned in Q.12, rounded half up on the
+ * magnitude: sgn(g) * floor((2^14 + |g|) / (2|g|)).
+ */
+int32_t or_recip(int g, int theta) {
+    int a = iabs(g);
+    if (a < 2 * theta || a == 0) return 0;
+    int32_t r = (int32_t)((16384 + a) / (2 * a));
+    return g < 0 ? -r : r;
+}
+
+/*
+ * One gradient pass at displacement d (Eqs. 3-5).  For every pixel p of the
+ * block: the displaced pixel difference e = cur(p) - ref(p + d) and the
+ * central differences of the reference at p + d (coordinates clamped to the
+ * frame).  The per-pixel updates e * u are averaged over the pixels whose
+ * gradient passes the threshold, per component, in Q.12 (C division).
+ */
+void or_prs_pass(const or_pair *fp, int shape, int theta, int x0, int y0, int dx, int dy, int32_t *ux, int32_t *uy) {
+    int32_t sx = 0, sy = 0;
+    int nx = 0, ny = 0;
+    for (int j = 0; j < 16; ++j) {
+        for (int i = 0; i < 16; ++i) {
+            int px = x0 + i, py = y0 + j;
+            int rx = px + dx, ry = py + dy;
+            int e = plane_cur(fp, shape, px, py) - plane_ref(fp, shape, rx, ry);
+            int gx = plane_ref(fp, shape, imin(rx + 1, fp->width - 1), ry) - plane_ref(fp, shape, imax(rx - 1, 0), ry);
+            int gy = plane_ref(fp, shape, rx, imin(ry + 1, fp->height - 1)) - plane_ref(fp, shape, rx, imax(ry - 1, 0));
+            int32_t rgx = or_recip(gx, theta);
+            int32_t rgy = or_recip(gy, theta);
+            sx += e * rgx;
+            sy += e * rgy;
+            nx += rgx != 0;
+            ny += rgy != 0;
+        }
+    }
+    *ux = nx ? sx / nx : 0;
+    *uy = ny ? sy / ny : 0;
+}
+
+/* Eq. 3 step in one axis: eps * U in Q.24, rounded half away from zero to
+ * whole pixels, limited to +-max_step. */
+int or_step(int32_t u, int eps_q12, int max_step) {
+    int64_t vq = (int64_t)eps_q12 * (int64_t)u;
+    int64_t a = vq < 0 ? -vq : vq;
+    int64_t s = (a + ((int64_t)1 << 23)) >> 24;
+    if (vq < 0) s = -s;
+    if (s > max_step) s = max_step;
+    if (s < -max_step) s = -max_step;
+    return (int)s;
+}
+
+/*
+ * Section 3.2: starting at the BRS winner, repeatedly take the Eq. 3 update
+ * as the next candidate (one of the eight neighbours for max_step 1), keep it
+ * when its distortion is strictly smaller, and stop at the first candidate
+ * that does not improve, at a zero update, at the search-window border, or
+ * after k_max candidates.  Returns the number of candidates evaluated.
+ */
+static int pel_recursion(const or_pair *fp, const or_params *p, int shape, int x0, int y0, int *dx, int *dy,
+                         uint32_t *cost) {
+    int S = p->search_range;
+    int lox = imax(-S, -x0), hix = imin(S, fp->width - 16 - x0);
+    int loy = imax(-S, -y0), hiy = imin(S, fp->height - 16 - y0);
+    int it = 0;
+    while (it < p->k_max) {
+        int32_t ux, uy;
+        or_prs_pass(fp, shape, p->theta, x0, y0, *dx, *dy, &ux, &uy);
+        int sx = or_step(ux, p->eps_q12, p->max_step);
+        int sy = or_step(uy, p->eps_q12, p->max_step);
+        if (sx == 0 && sy == 0) break;
+        int nx = iclamp(*dx + sx, lox, hix);
+        int ny = iclamp(*dy + sy, loy, hiy);
+        if (nx == *dx && ny == *dy) break;
+        ++it;
+        uint32_t c = block_cost(fp, shape, x0, y0, nx, ny);
+        if (c < *cost) {
+            *dx = nx;
+            *dy = ny;
+            *cost = c;
+        } else {
+            break;
+        }
+    }
+    return it;
+}
+
+/* ------------------------------------------- half-sample refinement */
+/* MPEG-4 bilinear half-sample prediction, rounding control 0.  (hx, hy) is
+ * a half-pel vector; reference coordinates are clamped to the frame. */
+static int pred_half(const or_pair *fp, int x, int y, int hx, int hy) {
+    int ix = half_to_full(hx), iy = half_to_full(hy);
+    int fx = hx - 2 * ix, fy = hy - 2 * iy;
+    int W = fp->width, H = fp->height;
+    int xa = iclamp(x + ix, 0, W - 1), xb = iclamp(x + ix + 1, 0, W - 1);
+    int ya = iclamp(y + iy, 0, H - 1), yb = iclamp(y + iy + 1, 0, H - 1);
+    int A = luma_at(fp->ref_luma, fp->stride, xa, ya);
+    if (!fx && !fy) return A;
+    int B = luma_at(fp->ref_luma, fp->stride, xb, ya);
+    int C = luma_at(fp->ref_luma, fp->stride, xa, yb);
+    if (fx && !fy) return (A + B + 1) >> 1;
+    if (!fx && fy) return (A + C + 1) >> 1;
+    int D = luma_at(fp->ref_luma, fp->stride, xb, yb);
+    return (A + B + C + D + 2) >> 2;
+}
+
+uint32_t or_sad_half(const or_pair *fp, int x0, int y0, int hx, int hy) {
+    uint32_t s = 0;
+    for (int j = 0; j < 16; ++j)
+        for (int i = 0; i < 16; ++i)
+            s += (uint32_t)iabs(luma_at(fp->cur_luma, fp->stride, x0 + i, y0 + j) - pred_half(fp, x0 + i, y0 + j, hx, hy));
+    return s;
+}
+
+static int half_feasible(const or_pair *fp, int S, int x0, int y0, int hx, int hy) {
+    if (iabs(hx) > 2 * S || iabs(hy) > 2 * S) return 0;
+    int ix = half_to_full(hx), iy = half_to_full(hy);
+    int fx = hx - 2 * ix, fy = hy - 2 * iy;
+    return x0 + ix >= 0 && x0 + ix + 15 + fx <= fp->width - 1 && y0 + iy >= 0 && y0 + iy + 15 + fy <= fp->height - 1;
+}
+
+static const int HALF_OFFS[8][2] = {{-1, -1}, {0, -1}, {1, -1}, {-1, 0}, {1, 0}, {-1, 1}, {0, 1}, {1, 1}};
+
+/* ----------------------------------------------- the proposed algorithm */
+/*
+ * Fig. 1 for one frame pair of one VOP.  `cls` from or_classify on the
+ * current alpha (NULL: every MB opaque).  `t_field` is the previous pair's
+ * full-pel field (half-pel units; NULL: zeros).  `seed` (NULL: plain method)
+ * is a learned per-MB starting vector for texture MBs.  `shape_only`
+ * scores every non-transparent MB on its alpha block.
+ */
+int or_pa(const or_pair *fp, const uint8_t *cls, const int16_t *t_field, const int16_t *seed, const or_params *p,
+          int shape_only, int16_t *mv, int16_t *mv_int, uint32_t *cost, uint8_t *iters, uint16_t *points) {
+    if (!fp || !p || !mv || !mv_int) return -1;
+    if (fp->width % 16 || fp->height % 16 || fp->width <= 0 || fp->height <= 0) return -1;
+    int has_alpha = fp->cur_alpha != NULL && fp->ref_alpha != NULL;
+    if (shape_only && !has_alpha) return -1;
+    int wm = fp->width / 16, hm = fp->height / 16;
+    int S = p->search_range;
+    for (int v = 0; v < hm; ++v) {
+        for (int h = 0; h < wm; ++h) {
+            int k = v * wm + h;
+            int c = cls ? cls[k] : OR_OPAQUE;
+            int x0 = 16 * h, y0 = 16 * v;
+            if (c == OR_TRANSPARENT) { /* no vector is computed */
+                mv[2 * k] = mv[2 * k + 1] = 0;
+                mv_int[2 * k] = mv_int[2 * k + 1] = 0;
+                if (cost) cost[k] = 0;
+                if (iters) iters[k] = 0;
+                if (points) points[k] = 0;
+                continue;
+            }
+            int shape = shape_only || c == OR_BOUNDARY;
+            if (shape && !has_alpha) return -1;
+            /* candidates A (left), B (up), C (up-right), T (same MB, previous
+             * pair); neighbours outside the MB grid contribute (0, 0) */
+            int cand[4][2];
+            cand[0][0] = h > 0 ? half_to_full(mv_int[2 * (k - 1)]) : 0;
+            cand[0][1] = h > 0 ? half_to_full(mv_int[2 * (k - 1) + 1]) : 0;
+            cand[1][0] = v > 0 ? half_to_full(mv_int[2 * (k - wm)]) : 0;
+            cand[1][1] = v > 0 ? half_to_full(mv_int[2 * (k - wm) + 1]) : 0;
+            cand[2][0] = (v > 0 && h + 1 < wm) ? half_to_full(mv_int[2 * (k - wm + 1)]) : 0;
+            cand[2][1] = (v > 0 && h + 1 < wm) ? half_to_full(mv_int[2 * (k - wm + 1) + 1]) : 0;
+            cand[3][0] = t_field ? half_to_full(t_field[2 * k]) : 0;
+            cand[3][1] = t_field ? half_to_full(t_field[2 * k + 1]) : 0;
+            /* admissible, distinct, in order A, B, C, T */
+            int list[4][2], n = 0;
+            for (int i = 0; i < 4; ++i) {
+                if (!feasible(fp, S, x0, y0, cand[i][0], cand[i][1])) continue;
+                int dup = 0;
+                for (int q = 0; q < n; ++q)
+                    if (list[q][0] == cand[i][0] && list[q][1] == cand[i][1]) dup = 1;
+                if (!dup) {
+                    list[n][0] = cand[i][0];
+                    list[n][1] = cand[i][1];
+                    ++n;
+                }
+            }
+            if (n == 0) {
+                list[0][0] = list[0][1] = 0;
+                n = 1;
+            }
+            /* Min[...] keeps the first minimum (MATLAB min semantics) */
+            int bx = list[0][0], by = list[0][1];
+            uint32_t bc = block_cost(fp, shape, x0, y0, bx, by);
+            for (int i = 1; i < n; ++i) {
+                uint32_t ci = block_cost(fp, shape, x0, y0, list[i][0], list[i][1]);
+                if (ci < bc) {
+                    bc = ci;
+                    bx = list[i][0];
+                    by = list[i][1];
+                }
+            }
+            int pts = n, its = 0;
+            int dx = bx, dy = by;
+            uint32_t dc = bc;
+            if (seed && !shape) {
+                /* learned start: clamp into the admissible window, refine,
+                 * and fall back to the plain recursion when the refined
+                 * distortion exceeds the BRS minimum by more than 5 % */
+                int lox = imax(-S, -x0), hix = imin(S, fp->width - 16 - x0);
+                int loy = imax(-S, -y0), hiy = imin(S, fp->height - 16 - y0);
+                int sx = iclamp(half_to_full(seed[2 * k]), lox, hix);
+                int sy = iclamp(half_to_full(seed[2 * k + 1]), loy, hiy);
+                uint32_t sc = block_cost(fp, shape, x0, y0, sx, sy);
+                pts += 1;
+                int it1 = pel_recursion(fp, p, shape, x0, y0, &sx, &sy, &sc);
+                its += it1;
+                pts += it1;
+                if ((uint64_t)20 * sc > (uint64_t)21 * bc) {
+                    int it2 = pel_recursion(fp, p, shape, x0, y0, &dx, &dy, &dc);
+                    its += it2;
+                    pts += it2;
+                } else {
+                    dx = sx;
+                    dy = sy;
+                    dc = sc;
+                }
+            } else {
+                int it1 = pel_recursion(fp, p, shape, x0, y0, &dx, &dy, &dc);
+                its += it1;
+                pts += it1;
+            }
+            int hx = 2 * dx, hy = 2 * dy;
+            if (p->half_pel && !shape) {
+                int bhx = hx, bhy = hy;
+                uint32_t hc = dc;
+                for (int o = 0; o < 8; ++o) {
+                    int qx = hx + HALF_OFFS[o][0], qy = hy + HALF_OFFS[o][1];
+                    if (!half_feasible(fp, S, x0, y0, qx, qy)) continue;
+                    ++pts;
+                    uint32_t c2 = or_sad_half(fp, x0, y0, qx, qy);
+                    if (c2 < hc) {
+                        hc = c2;
+                        bhx = qx;
+                        bhy = qy;
+                    }
+                }
+                hx = bhx;
+                hy = bhy;
+                dc = hc;
+            }
+            mv[2 * k] = (int16_t)hx;
+            mv[2 * k + 1] = (int16_t)hy;
+            mv_int[2 * k] = (int16_t)(2 * dx);
+            mv_int[2 * k + 1] = (int16_t)(2 * dy);
+            if (cost) cost[k] = dc;
+            if (iters) iters[k] = (uint8_t)its;
+            if (points) points[k] = (uint16_t)pts;
+        }
+    }
+    return 0;
+}
+
+/* --------------------------------------------------- baseline searches */
+/* Exhaustive search: every admissible vector; ties broken by the smaller
+ * |dx| + |dy|, then the smaller dy, then the smaller dx. */
+static void search_es(const or_pair *fp, int S, int x0, int y0, int *bx, int *by, uint32_t *bc, int *pts) {
+    int have = 0, n = 0;
+    for (int dy = -S; dy <= S; ++dy) {
+        for (int dx = -S; dx <= S; ++dx) {
+            if (!feasible(fp, S, x0, y0, dx, dy)) continue;
+            ++n;
+            uint32_t c = or_sad(fp, x0, y0, dx, dy);
+            int l1 = iabs(dx) + iabs(dy), bl1 = iabs(*bx) + iabs(*by);
+            int better = !have || c < *bc || (c == *bc && (l1 < bl1 || (l1 == bl1 && (dy < *by || (dy == *by && dx < *bx)))));
+            if (better) {
+                have = 1;
+                *bc = c;
+                *bx = dx;
+                *by = dy;
+            }
+        }
+    }
+    *pts = n;
+}
+
+/* evaluated-position memo over the (2S+1)^2 window */
+typedef struct {
+    int S;
+    uint8_t *seen;
+    int count;
+} memo;
+
+static void memo_visit(memo *m, int dx, int dy) {
+    size_t i = (size_t)(dy + m->S) * (2 * m->S + 1) + (dx + m->S);
+    if (!m->seen[i]) {
+        m->seen[i] = 1;
+        ++m->count;
+    }
+}
+
+/* Three-step search: first step 2^(ceil(log2(S+1)) - 1), halved down to 1;
+ * each round the eight points around the centre in row order; the centre
+ * moves only to a strictly better point (the first one on ties). */
+static void search_tss(const or_pair *fp, int S, int x0, int y0, memo *m, int *bx, int *by, uint32_t *bc) {
+    int p2 = 1;
+    while (p2 < S + 1) p2 *= 2;
+    int step = p2 / 2;
+    int cx = 0, cy = 0;
+    uint32_t cc = or_sad(fp, x0, y0, 0, 0);
+    memo_visit(m, 0, 0);
+    while (step >= 1) {
+        int nx = cx, ny = cy;
+        uint32_t nc = cc;
+        for (int j = -1; j <= 1; ++j) {
+            for (int i = -1; i <= 1; ++i) {
+                if (i == 0 && j == 0) continue;
+                int qx = cx + i * step, qy = cy + j * step;
+                if (!feasible(fp, S, x0, y0, qx, qy)) continue;
+                memo_visit(m, qx, qy);
+                uint32_t c = or_sad(fp, x0, y0, qx, qy);
+                if (c < nc) {
+                    nc = c;
+                    nx = qx;
+                    ny = qy;
+                }
+            }
+        }
+        cx = nx;
+        cy = ny;
+        cc = nc;
+        step /= 2;
+    }
+    *bx = cx;
+    *by = cy;
+    *bc = cc;
+}
+
+static const int LDSP[8][2] = {{0, -2}, {-1, -1}, {1, -1}, {-2, 0}, {2, 0}, {-1, 1}, {1, 1}, {0, 2}};
+static const int SDSP[4][2] = {{0, -1}, {-1, 0}, {1, 0}, {0, 1}};
+
+/* Diamond search: the large diamond is repeated until its centre is the
+ * best point (moves need a strictly smaller SAD), then one small diamond. */
+static void search_ds(const or_pair *fp, int S, int x0, int y0, memo *m, int *bx, int *by, uint32_t *bc) {
+    int cx = 0, cy = 0;
+    uint32_t cc = or_sad(fp, x0, y0, 0, 0);
+    memo_visit(m, 0, 0);
+    for (;;) {
+        int nx = cx, ny = cy;
+        uint32_t nc = cc;
+        for (int o = 0; o < 8; ++o) {
+            int qx = cx + LDSP[o][0], qy = cy + LDSP[o][1];
+            if (!feasible(fp, S, x0, y0, qx, qy)) continue;
+            memo_visit(m, qx, qy);
+            uint32_t c = or_sad(fp, x0, y0, qx, qy);
+            if (c < nc) {
+                nc = c;
+                nx = qx;
+                ny = qy;
+            }
+        }
+        if (nx == cx && ny == cy) break;
+        cx = nx;
+        cy = ny;
+        cc = nc;
+    }
+    int nx = cx, ny = cy;
+    uint32_t nc = cc;
+    for (int o = 0; o < 4; ++o) {
+        int qx = cx + SDSP[o][0], qy = cy + SDSP[o][1];
+        if (!feasible(fp, S, x0, y0, qx, qy)) continue;
+        memo_visit(m, qx, qy);
+        uint32_t c = or_sad(fp, x0, y0, qx, qy);
+        if (c < nc) {
+            nc = c;
+            nx = qx;
+            ny = qy;
+        }
+    }
+    *bx = nx;
+    *by = ny;
+    *bc = nc;
+}
+
+/* method 0 = exhaustive, 1 = three-step, 2 = diamond; texture SAD on every
+ * non-transparent MB, starting at (0, 0). */
+int or_search(int method, const or_pair *fp, const uint8_t *cls, const or_params *p, int16_t *mv, int16_t *mv_int,
+              uint32_t *cost, uint16_t *points) {
+    if (!fp || !p || !mv || !mv_int || method < 0 || method > 2) return -1;
+    if (fp->width % 16 || fp->height % 16 || fp->width <= 0 || fp->height <= 0) return -1;
+    int wm = fp->width / 16, hm = fp->height / 16;
+    int S = p->search_range;
+    size_t win = (size_t)(2 * S + 1) * (2 * S + 1);
+    uint8_t *seen = (uint8_t *)malloc(win);
+    if (!seen) return -1;
+    for (int v = 0; v < hm; ++v) {
+        for (int h = 0; h < wm; ++h) {
+            int k = v * wm + h;
+            int c = cls ? cls[k] : OR_OPAQUE;
+            int bx = 0, by = 0, pts = 0;
+            uint32_t bc = 0;
+            if (c != OR_TRANSPARENT) {
+                if (method == 0) {
+                    search_es(fp, S, 16 * h, 16 * v, &bx, &by, &bc, &pts);
+                } else {
+                    memo m = {S, seen, 0};
+                    memset(seen, 0, win);
+                    if (method == 1)
+                        search_tss(fp, S, 16 * h, 16 * v, &m, &bx, &by, &bc);
+                    else
+                        search_ds(fp, S, 16 * h, 16 * v, &m, &bx, &by, &bc);
+                    pts = m.count;
+                }
+            }
+            mv[2 * k] = mv_int[2 * k] = (int16_t)(2 * bx);
+            mv[2 * k + 1] = mv_int[2 * k + 1] = (int16_t)(2 * by);
+            if (cost) cost[k] = bc;
+            if (points) points[k] = (uint16_t)pts;
+        }
+    }
+    free(seen);
+    return 0;
+}
+
+/* ---------------------------------------- motion compensation and SSE */
+/* Section 4: the motion-compensated prediction of the current frame (each MB
+ * predicted by its half-pel vector, transparent MBs by (0, 0)) and its
+ * squared error against the current frame over the VOP pixels (every pixel
+ * for rectangular frames). */
+int or_mc_sse(const or_pair *fp, const uint8_t *cls, const int16_t *mv, uint8_t *pred, uint64_t *sse, uint64_t *npix) {
+    if (!fp || !mv || !sse || !npix) return -1;
+    int wm = fp->width / 16, hm = fp->height / 16;
+    uint64_t s = 0, n = 0;
+    for (int v = 0; v < hm; ++v) {
+        for (int h = 0; h < wm; ++h) {
+            int k = v * wm + h;
+            int c = cls ? cls[k] : OR_OPAQUE;
+            int hx = c == OR_TRANSPARENT ? 0 : mv[2 * k];
+            int hy = c == OR_TRANSPARENT ? 0 : mv[2 * k + 1];
+            for (int j = 0; j < 16; ++j) {
+                for (int i = 0; i < 16; ++i) {
+                    int x = 16 * h + i, y = 16 * v + j;
+                    int pv = pred_half(fp, x, y, hx, hy);
+                    if (pred) pred[(size_t)y * fp->stride + x] = (uint8_t)pv;
+                    int in = fp->cur_alpha ? fp->cur_alpha[(size_t)y * fp->stride + x] != 0 : 1;
+                    if (in) {
+                        int d = luma_at(fp->cur_luma, fp->stride, x, y) - pv;
+                        s += (uint64_t)(d * d);
+                        ++n;
+                    }
+                }
+            }
+        }
+    }
+    *sse = s;
+    *npix = n;
+    return 0;
+}
