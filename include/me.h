@@ -1,0 +1,171 @@
+/*
+ * me.h - C ABI of the MI355X (gfx950) shape-adaptive motion-estimation
+ * library, after F. Benboubker, F. Abdi, A. Ahaitouf, "Shape-Adaptive Motion
+ * Estimation Algorithm for MPEG-4 Video Coding".
+ *
+ * Problem statement (Section 2): for every 16x16 macroblock (MB) of the
+ * current video object plane (VOP) find the motion vector into the reference
+ * VOP that minimises the block distortion; boundary MBs are matched on their
+ * binary alpha blocks (BABs), opaque MBs on luma (Section 1, Section 3.1).
+ *
+ * Common conventions
+ *  - All frame, class, vector and result pointers inside the structs are
+ *    DEVICE pointers (hipMalloc / torch CUDA tensors) owned by the caller.
+ *    Arrays of structs and arrays of pointers passed as arguments are HOST
+ *    memory and may be reused as soon as the call returns.
+ *  - Frames are 8-bit, row-major with a row pitch of `stride` bytes; width
+ *    and height must be multiples of 16 (ME_EALIGN), `stride` >= width and a
+ *    multiple of 4, and plane base pointers 4-byte aligned (ME_EALIGN).
+ *  - MB (h, v) covers pixels [16h, 16h+16) x [16v, 16v+16); per-MB arrays
+ *    are row-major over the MB grid, (height/16) x (width/16).
+ *  - A full-pel vector d = (dx, dy) predicts cur(x, y) by ref(x+dx, y+dy).
+ *    Every me_mv is in HALF-PEL units; integer results are even.
+ *  - Admissible vectors: |dx|, |dy| <= search_range and the displaced block
+ *    entirely inside the reference frame.
+ *  - Every call validates all arguments on the host before touching the GPU
+ *    and returns a negative ME_E* code on error (nothing launched).  Calls
+ *    are asynchronous on `stream` (a hipStream_t; NULL = default stream)
+ *    except me_motion_compensate_psnr and me_device_status, which block.
+ *  - The library owns only internal scratch (per stream, grown on demand,
+ *    released by me_shutdown).  Calls that share a stream are ordered; calls
+ *    on different streams must not share output buffers.
+ */
+#ifndef ME_H
+#define ME_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define ME_OK 0
+#define ME_EINVAL (-1)   /* null pointer, size or parameter out of range */
+#define ME_EALIGN (-2)   /* width/height not multiples of 16, bad stride/alignment */
+#define ME_EHIP (-3)     /* HIP runtime error */
+#define ME_ENOMEM (-4)   /* internal scratch allocation failed */
+#define ME_EEMPTY (-5)   /* PSNR over zero pixels */
+#define ME_EDEVICE (-6)  /* device status word set (dependency wait timed out / bad class) */
+#define ME_ENODEV (-7)   /* no usable gfx950 device */
+
+/* MB classes (Section 1) */
+#define ME_MB_TRANSPARENT 0 /* no pixel of the VOP */
+#define ME_MB_OPAQUE 1      /* every pixel inside the VOP */
+#define ME_MB_BOUNDARY 2    /* both */
+
+/* baseline methods (Section 1 references [5], [7]; Tables 1-2) */
+#define ME_ES 0  /* exhaustive search */
+#define ME_TSS 1 /* three-step search */
+#define ME_DS 2  /* diamond search */
+
+typedef struct me_frame {
+    const uint8_t *luma;  /* composited luma (device) */
+    const uint8_t *alpha; /* binary alpha of this VOP, inside <=> != 0; NULL = rectangular frame */
+    int32_t width, height, stride;
+} me_frame;
+
+typedef struct me_mv {
+    int16_t x, y; /* half-pel units */
+} me_mv;
+
+typedef struct me_params {
+    int32_t search_range; /* S, 1..64 (full-pel) */
+    int32_t theta;        /* Theta of Eq. 4, 1..127 (default 3: "two or three") */
+    int32_t eps_q12;      /* convergence factor epsilon of Eq. 3 in Q.12, 0..65536 (default 4096 = 1.0) */
+    int32_t max_step;     /* largest per-axis pel-recursion step, 1..S (default 1: one of eight neighbours) */
+    int32_t k_max;        /* cap on pel-recursion candidates per MB, 0..255 (default 8) */
+    int32_t half_pel;     /* 1: half-sample refinement of texture MBs after the recursion (Section 4) */
+    uint32_t flags;       /* reserved, must be 0 */
+} me_params;
+
+/* One frame pair of one VOP (the unit of Fig. 1's outer loops). */
+typedef struct me_job {
+    me_frame cur, ref;       /* same width/height/stride; alpha both set or both NULL */
+    const uint8_t *mb_class; /* per-MB class from me_classify_babs of cur; NULL = all opaque */
+    const me_mv *t_field;    /* temporal candidates T (previous pair's mv_int); NULL = zeros.
+                                May point at the mv_int of an EARLIER job of the same call:
+                                that pair is then solved first, MB by MB (pipelined). */
+    const me_mv *seed;       /* learned starting vectors for texture MBs; NULL = plain method */
+    me_mv *mv;               /* out: final vector (half-pel) */
+    me_mv *mv_int;           /* out: full-pel vector before half-sample refinement (feeds A, B, C, T) */
+    uint32_t *cost;          /* out, nullable: final distortion (SAD, or BAB mismatch count) */
+    uint8_t *iters;          /* out, nullable: pel-recursion candidates evaluated */
+    uint16_t *points;        /* out, nullable: search points (compared blocks), Table 1 */
+} me_job;
+
+typedef struct me_net me_net; /* learned MV proposal network (opaque) */
+
+/* Fill `p` with the defaults: S 16, Theta 3, eps 1.0, max_step 1, k_max 8, no half-pel. */
+void me_default_params(me_params *p);
+
+/* Human-readable text of a status code (static storage). */
+const char *me_status_str(int status);
+
+/* Release every stream workspace (device scratch, pinned staging).  Waits for
+ * the device.  Optional; the library re-initialises on the next call. */
+void me_shutdown(void);
+
+/*
+ * MB classification from the binary alpha plane (Section 1; Fig. 1 Block_Type):
+ * class 0 transparent, 1 opaque, 2 boundary, counted over alpha != 0.
+ *  frames[i].alpha  required (device); luma unused.
+ *  mb_class[i]      device, (height/16)*(width/16) bytes.
+ *  bab_bits[i]      device or NULL; 8 uint32 per MB: word w holds rows 2w
+ *                   (bits 0..15) and 2w+1 (bits 16..31), column i at bit i.
+ *  `bab_bits` itself may be NULL.
+ */
+int me_classify_babs(const me_frame *frames, int n, uint8_t *const *mb_class, uint32_t *const *bab_bits,
+                     void *stream);
+
+/*
+ * The proposed algorithm (Fig. 1; Sections 3.1-3.2) for n frame pairs.
+ * Per MB in raster order: transparent -> zero vector; otherwise the
+ * block-recursive search over the candidates A (left), B (up), C (up-right)
+ * of this pair and T, keeping the first minimum of the distortion (BAB
+ * mismatch count for boundary MBs, luma SAD for opaque MBs), then the
+ * pel-recursive refinement of Eqs. 3-5 in Q.12 fixed point, then (half_pel)
+ * half-sample refinement of opaque MBs.  `net` NULL: each job's `seed` (if
+ * set) is used as given; non-NULL: the network writes its proposals into the
+ * jobs' `seed` buffers first (they must then be writable device buffers).
+ */
+int me_texture_recursive(const me_job *jobs, int n, const me_params *params, const me_net *net, void *stream);
+
+/* Same procedure with every non-transparent MB scored on its BAB (shape
+ * motion estimation of Section 3.1 applied to all object MBs).  Requires alpha. */
+int me_shape_search(const me_job *jobs, int n, const me_params *params, void *stream);
+
+/*
+ * Baseline block matching on the luma of every non-transparent MB, starting
+ * at (0, 0): ME_ES (all admissible vectors; ties -> smaller |dx|+|dy|, then
+ * smaller dy, then smaller dx), ME_TSS (first step 2^(ceil(log2(S+1))-1),
+ * halved to 1), ME_DS (large diamond until the centre wins, then the small
+ * diamond).  Moves need a strictly smaller SAD.  `points` counts distinct
+ * positions evaluated; iters is written 0; t_field and seed are ignored.
+ */
+int me_full_search(int method, const me_job *jobs, int n, const me_params *params, void *stream);
+
+/*
+ * Motion compensation and PSNR (Section 4, Table 2): predict every MB of
+ * cur from ref by its `mv` (half-pel, MPEG-4 bilinear with rounding control
+ * 0, reference coordinates clamped to the frame; transparent MBs use (0,0)),
+ * then SSE over the VOP pixels (alpha != 0; all pixels when alpha is NULL).
+ *  pred     NULL, or host array of n device pointers (entries may be NULL)
+ *           receiving the predicted frame with the job's stride.
+ *  sse, npix, psnr_db   host arrays of n; psnr = 10 log10(255^2 npix / sse)
+ *           in double (+inf when sse == 0).  ME_EEMPTY if some npix is 0
+ *           (all outputs still written; that job's psnr is NaN).
+ * Blocks until the results are on the host.
+ */
+int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, uint64_t *sse, uint64_t *npix,
+                              double *psnr_db, void *stream);
+
+/* Wait for `stream`, then read and clear its device status word:
+ * ME_OK, or ME_EDEVICE when a kernel reported a fault condition. */
+int me_device_status(void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ME_H */

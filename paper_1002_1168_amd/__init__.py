@@ -1,0 +1,154 @@
+"""Python binding of the gfx950 shape-adaptive motion-estimation library.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``libme.so`` (C ABI in ``include/me.h``).  The functions below carry the
+C names and take ctypes structs whose pointer fields are device addresses
+(e.g. ``torch.Tensor.data_ptr()`` of CUDA tensors).  If the library is not
+built, every call raises ``MeError``: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libme.so")
+
+ME_OK, ME_EINVAL, ME_EALIGN, ME_EHIP, ME_ENOMEM, ME_EEMPTY, ME_EDEVICE, ME_ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
+ME_MB_TRANSPARENT, ME_MB_OPAQUE, ME_MB_BOUNDARY = 0, 1, 2
+ME_ES, ME_TSS, ME_DS = 0, 1, 2
+
+EXPORTED = ("me_default_params", "me_status_str", "me_shutdown", "me_classify_babs", "me_texture_recursive",
+            "me_shape_search", "me_full_search", "me_motion_compensate_psnr", "me_device_status")
+
+
+class MeError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {status_str(code)} ({code})" if what else f"{status_str(code)} ({code})")
+
+
+class me_frame(C.Structure):
+    _fields_ = [("luma", C.c_void_p), ("alpha", C.c_void_p),
+                ("width", C.c_int32), ("height", C.c_int32), ("stride", C.c_int32)]
+
+
+class me_params(C.Structure):
+    _fields_ = [("search_range", C.c_int32), ("theta", C.c_int32), ("eps_q12", C.c_int32),
+                ("max_step", C.c_int32), ("k_max", C.c_int32), ("half_pel", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class me_job(C.Structure):
+    _fields_ = [("cur", me_frame), ("ref", me_frame), ("mb_class", C.c_void_p),
+                ("t_field", C.c_void_p), ("seed", C.c_void_p), ("mv", C.c_void_p),
+                ("mv_int", C.c_void_p), ("cost", C.c_void_p), ("iters", C.c_void_p),
+                ("points", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded ``libme.so`` (raises MeError when it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise MeError(ME_ENODEV, f"HIP library missing at {LIB_PATH}; run `python -m paper_1002_1168_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i = C.c_void_p, C.c_int
+        L.me_default_params.argtypes = [C.POINTER(me_params)]
+        L.me_default_params.restype = None
+        L.me_status_str.argtypes = [i]
+        L.me_status_str.restype = C.c_char_p
+        L.me_shutdown.argtypes = []
+        L.me_shutdown.restype = None
+        L.me_classify_babs.argtypes = [C.POINTER(me_frame), i, C.POINTER(vp), C.POINTER(vp), vp]
+        L.me_classify_babs.restype = i
+        L.me_texture_recursive.argtypes = [C.POINTER(me_job), i, C.POINTER(me_params), vp, vp]
+        L.me_texture_recursive.restype = i
+        L.me_shape_search.argtypes = [C.POINTER(me_job), i, C.POINTER(me_params), vp]
+        L.me_shape_search.restype = i
+        L.me_full_search.argtypes = [i, C.POINTER(me_job), i, C.POINTER(me_params), vp]
+        L.me_full_search.restype = i
+        L.me_motion_compensate_psnr.argtypes = [C.POINTER(me_job), i, C.POINTER(vp), C.POINTER(C.c_uint64),
+                                                C.POINTER(C.c_uint64), C.POINTER(C.c_double), vp]
+        L.me_motion_compensate_psnr.restype = i
+        L.me_device_status.argtypes = [vp]
+        L.me_device_status.restype = i
+        _lib = L
+    return _lib
+
+
+def status_str(code: int) -> str:
+    try:
+        return lib().me_status_str(int(code)).decode()
+    except MeError:
+        return {0: "ok"}.get(code, f"status {code}")
+
+
+def _check(rc: int, what: str) -> int:
+    if rc != ME_OK:
+        raise MeError(rc, what)
+    return rc
+
+
+def _arr(ctype, items):
+    items = list(items)
+    return (ctype * max(len(items), 1))(*items), len(items)
+
+
+def me_default_params(**over) -> me_params:
+    p = me_params()
+    lib().me_default_params(C.byref(p))
+    for k, v in over.items():
+        setattr(p, k, int(v))
+    return p
+
+
+def me_shutdown() -> None:
+    lib().me_shutdown()
+
+
+def me_classify_babs(frames, mb_class, bab_bits=None, stream=None, check=True) -> int:
+    """``frames``: me_frame list; ``mb_class`` / ``bab_bits``: device addresses."""
+    fa, n = _arr(me_frame, frames)
+    ca, _ = _arr(C.c_void_p, mb_class)
+    ba = None if bab_bits is None else _arr(C.c_void_p, bab_bits)[0]
+    rc = lib().me_classify_babs(fa, n, ca, ba, stream)
+    return _check(rc, "me_classify_babs") if check else rc
+
+
+def me_texture_recursive(jobs, params: me_params, net=None, stream=None, check=True) -> int:
+    ja, n = _arr(me_job, jobs)
+    rc = lib().me_texture_recursive(ja, n, C.byref(params), net, stream)
+    return _check(rc, "me_texture_recursive") if check else rc
+
+
+def me_shape_search(jobs, params: me_params, stream=None, check=True) -> int:
+    ja, n = _arr(me_job, jobs)
+    rc = lib().me_shape_search(ja, n, C.byref(params), stream)
+    return _check(rc, "me_shape_search") if check else rc
+
+
+def me_full_search(method: int, jobs, params: me_params, stream=None, check=True) -> int:
+    ja, n = _arr(me_job, jobs)
+    rc = lib().me_full_search(int(method), ja, n, C.byref(params), stream)
+    return _check(rc, "me_full_search") if check else rc
+
+
+def me_motion_compensate_psnr(jobs, pred=None, stream=None, check=True):
+    """-> (sse list, npix list, psnr_db list, status)."""
+    ja, n = _arr(me_job, jobs)
+    pa = None if pred is None else _arr(C.c_void_p, pred)[0]
+    sse = (C.c_uint64 * max(n, 1))()
+    npx = (C.c_uint64 * max(n, 1))()
+    ps = (C.c_double * max(n, 1))()
+    rc = lib().me_motion_compensate_psnr(ja, n, pa, sse, npx, ps, stream)
+    if check and rc not in (ME_OK,):
+        raise MeError(rc, "me_motion_compensate_psnr")
+    return list(sse)[:n], list(npx)[:n], list(ps)[:n], rc
+
+
+def me_device_status(stream=None) -> int:
+    return lib().me_device_status(stream)

@@ -1,0 +1,543 @@
+// Host side of the C ABI: argument validation (before any HIP call), per-stream
+// workspaces (device scratch + pinned staging), chain / ticket construction
+// for the pipelined block-recursive search, and the launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "me_internal.h"
+
+namespace me {
+size_t es_lds_bytes(int S);
+}
+
+using namespace me;
+
+namespace {
+
+constexpr int kMaxDim = 4096;   // ticket packing: 8 bits per MB coordinate
+constexpr int kMaxChains = 65536;
+constexpr int kSpinLimit = 1 << 22;
+constexpr int kRing = 4;
+
+struct Staging {
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+};
+
+struct Workspace {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint8_t *dev = nullptr;
+    size_t cap = 0;
+    uint32_t *status = nullptr;  // persistent device status word
+    Staging ring[kRing];
+    int slot = 0;
+    std::vector<uint8_t> last;   // content of the last upload (skip identical ones)
+    bool last_valid = false;
+    unsigned long long *host_acc = nullptr;  // pinned readback for MC
+    size_t host_acc_cap = 0;
+    std::mutex mu;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
+int g_arch_ok = -1;  // -1 unknown, 0 no, 1 yes
+
+int hip_err(hipError_t e) { return e == hipSuccess ? ME_OK : ME_EHIP; }
+
+int check_device(int dev) {
+    if (g_arch_ok >= 0) return g_arch_ok ? ME_OK : ME_ENODEV;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return ME_ENODEV;
+    g_arch_ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+    return g_arch_ok ? ME_OK : ME_ENODEV;
+}
+
+int get_ws(void *stream, Workspace **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return ME_ENODEV;
+    std::lock_guard<std::mutex> lk(g_mu);
+    int rc = check_device(dev);
+    if (rc) return rc;
+    auto key = std::make_pair(dev, (hipStream_t)stream);
+    auto it = g_ws.find(key);
+    if (it != g_ws.end()) {
+        *out = it->second;
+        return ME_OK;
+    }
+    Workspace *w = new Workspace();
+    w->device = dev;
+    w->stream = (hipStream_t)stream;
+    if (hipMalloc(&w->status, 256) != hipSuccess) {
+        delete w;
+        return ME_ENOMEM;
+    }
+    if (hipMemset(w->status, 0, 256) != hipSuccess) {
+        hipFree(w->status);
+        delete w;
+        return ME_EHIP;
+    }
+    for (auto &s : w->ring)
+        if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess) return ME_EHIP;
+    g_ws[key] = w;
+    *out = w;
+    return ME_OK;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Copy `blob` to the start of the device arena (skipped when the arena still
+// holds exactly these bytes) and zero `zero_bytes` after it.  Returns the
+// arena base in *base and the zeroed region in *zero.
+int upload(Workspace &w, const std::vector<uint8_t> &blob, size_t zero_bytes, uint8_t **base, uint8_t **zero) {
+    size_t off = align_up(blob.size(), 256);
+    size_t need = off + align_up(zero_bytes, 256) + 256;
+    if (need > w.cap) {
+        if (w.dev) {
+            if (hipStreamSynchronize(w.stream) != hipSuccess) return ME_EHIP;
+            hipFree(w.dev);
+            w.dev = nullptr;
+            w.cap = 0;
+        }
+        size_t cap = std::max(need, (size_t)1 << 20);
+        if (hipMalloc(&w.dev, cap) != hipSuccess) return ME_ENOMEM;
+        w.cap = cap;
+        w.last_valid = false;
+    }
+    bool same = w.last_valid && w.last.size() == blob.size() &&
+                std::memcmp(w.last.data(), blob.data(), blob.size()) == 0;
+    if (!same && !blob.empty()) {
+        Staging &s = w.ring[w.slot];
+        w.slot = (w.slot + 1) % kRing;
+        if (hipEventSynchronize(s.ev) != hipSuccess) return ME_EHIP;
+        if (s.cap < blob.size()) {
+            if (s.host) hipHostFree(s.host);
+            s.host = nullptr;
+            size_t cap = std::max(align_up(blob.size(), 4096), (size_t)1 << 16);
+            if (hipHostMalloc(&s.host, cap, hipHostMallocDefault) != hipSuccess) {
+                s.cap = 0;
+                return ME_ENOMEM;
+            }
+            s.cap = cap;
+        }
+        std::memcpy(s.host, blob.data(), blob.size());
+        if (hipMemcpyAsync(w.dev, s.host, blob.size(), hipMemcpyHostToDevice, w.stream) != hipSuccess)
+            return ME_EHIP;
+        if (hipEventRecord(s.ev, w.stream) != hipSuccess) return ME_EHIP;
+        w.last = blob;
+        w.last_valid = true;
+    }
+    *base = w.dev;
+    *zero = w.dev + off;
+    if (zero_bytes) {
+        int rc = hip_err(launch_fill_u32((uint32_t *)(w.dev + off), align_up(zero_bytes, 4) / 4, 0u, w.stream));
+        if (rc) return rc;
+    }
+    return ME_OK;
+}
+
+template <class T>
+size_t put(std::vector<uint8_t> &b, const T *p, size_t count) {
+    size_t off = align_up(b.size(), 64);
+    b.resize(off + sizeof(T) * count);
+    if (count) std::memcpy(b.data() + off, p, sizeof(T) * count);
+    return off;
+}
+
+bool al4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
+
+int check_frame(const me_frame &f, bool need_alpha) {
+    if (!f.luma) return ME_EINVAL;
+    if (need_alpha && !f.alpha) return ME_EINVAL;
+    if (f.width <= 0 || f.height <= 0 || f.width > kMaxDim || f.height > kMaxDim) return ME_EINVAL;
+    if (f.width % 16 || f.height % 16) return ME_EALIGN;
+    if (f.stride < f.width || f.stride % 4) return ME_EALIGN;
+    if (!al4(f.luma) || (f.alpha && !al4(f.alpha))) return ME_EALIGN;
+    return ME_OK;
+}
+
+int check_params(const me_params *p) {
+    if (!p) return ME_EINVAL;
+    if (p->search_range < 1 || p->search_range > 64) return ME_EINVAL;
+    if (p->theta < 1 || p->theta > 127) return ME_EINVAL;
+    if (p->eps_q12 < 0 || p->eps_q12 > 65536) return ME_EINVAL;
+    if (p->max_step < 1 || p->max_step > p->search_range) return ME_EINVAL;
+    if (p->k_max < 0 || p->k_max > 255) return ME_EINVAL;
+    if (p->half_pel != 0 && p->half_pel != 1) return ME_EINVAL;
+    if (p->flags != 0) return ME_EINVAL;
+    return ME_OK;
+}
+
+int check_job(const me_job &j, bool need_alpha) {
+    int rc = check_frame(j.cur, need_alpha);
+    if (rc) return rc;
+    rc = check_frame(j.ref, need_alpha);
+    if (rc) return rc;
+    if (j.cur.width != j.ref.width || j.cur.height != j.ref.height || j.cur.stride != j.ref.stride) return ME_EINVAL;
+    if ((j.cur.alpha == nullptr) != (j.ref.alpha == nullptr)) return ME_EINVAL;
+    if (!j.mv || !j.mv_int) return ME_EINVAL;
+    if (!al4(j.mv) || !al4(j.mv_int) || (j.t_field && !al4(j.t_field)) || (j.seed && !al4(j.seed)))
+        return ME_EALIGN;
+    if (j.t_field && (const void *)j.t_field == (const void *)j.mv_int) return ME_EINVAL;
+    return ME_OK;
+}
+
+KParams kparams(const me_params *p, bool shape_only) {
+    KParams k;
+    k.S = p->search_range;
+    k.theta = p->theta;
+    k.eps = p->eps_q12;
+    k.max_step = p->max_step;
+    k.k_max = p->k_max;
+    k.half_pel = p->half_pel;
+    k.shape_only = shape_only ? 1 : 0;
+    k.spin_limit = kSpinLimit;
+    return k;
+}
+
+JobDesc job_desc(const me_job &j) {
+    JobDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.cur = j.cur.luma;
+    d.ref = j.ref.luma;
+    d.cur_a = j.cur.alpha;
+    d.ref_a = j.ref.alpha;
+    d.cls = j.mb_class;
+    d.tf = (const int16_t *)j.t_field;
+    d.seed = (const int16_t *)j.seed;
+    d.mv = (int16_t *)j.mv;
+    d.mv_int = (int16_t *)j.mv_int;
+    d.cost = j.cost;
+    d.iters = j.iters;
+    d.points = j.points;
+    d.width = j.cur.width;
+    d.height = j.cur.height;
+    d.stride = j.cur.stride;
+    d.wm = j.cur.width / 16;
+    d.hm = j.cur.height / 16;
+    d.dep_line_base = -1;
+    return d;
+}
+
+// The proposed algorithm for n jobs (shared by the texture and shape entry points).
+int run_pa(const me_job *jobs, int n, const me_params *params, bool shape_only, void *stream) {
+    if (n < 0 || (n > 0 && !jobs)) return ME_EINVAL;
+    int rc = check_params(params);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) {
+        rc = check_job(jobs[i], shape_only);
+        if (rc) return rc;
+    }
+    if (n == 0) return ME_OK;
+    // chains: a job whose T field is the mv_int of an earlier job follows it
+    std::unordered_map<const void *, int> producer;
+    for (int i = 0; i < n; ++i) {
+        if (!producer.emplace((const void *)jobs[i].mv_int, i).second) return ME_EINVAL;  // shared output
+    }
+    std::vector<JobDesc> desc(n);
+    std::vector<int> chain_of(n), pos_of(n);
+    std::vector<std::vector<int>> chains;
+    for (int i = 0; i < n; ++i) {
+        desc[i] = job_desc(jobs[i]);
+        int prod = -1;
+        if (jobs[i].t_field) {
+            auto it = producer.find((const void *)jobs[i].t_field);
+            if (it != producer.end()) {
+                if (it->second >= i) return ME_EINVAL;  // would read a field written later in this call
+                prod = it->second;
+            }
+        }
+        if (prod >= 0) {
+            if (desc[prod].wm != desc[i].wm || desc[prod].hm != desc[i].hm) return ME_EINVAL;
+            int c = chain_of[prod];
+            if (chains[c].back() == prod) {
+                chains[c].push_back(i);
+                chain_of[i] = c;
+                pos_of[i] = (int)chains[c].size() - 1;
+                desc[i].t_local = 1;
+            } else {
+                chain_of[i] = (int)chains.size();
+                pos_of[i] = 0;
+                chains.push_back({i});
+            }
+            desc[i].dep_pos = pos_of[prod];
+            desc[i].dep_line_base = -2 - chain_of[prod];  // resolved below
+        } else {
+            chain_of[i] = (int)chains.size();
+            pos_of[i] = 0;
+            chains.push_back({i});
+        }
+    }
+    const int nc = (int)chains.size();
+    if (nc > kMaxChains) return ME_EINVAL;
+    std::vector<ChainDesc> cd(nc);
+    std::vector<int32_t> cj;
+    cj.reserve(n);
+    long long nlines = 0;
+    int maxkey = 0;
+    for (int c = 0; c < nc; ++c) {
+        const JobDesc &d0 = desc[chains[c][0]];
+        cd[c] = ChainDesc{(int32_t)cj.size(), (int32_t)chains[c].size(), d0.wm, d0.hm, (int32_t)nlines, {0, 0, 0}};
+        for (int i : chains[c]) cj.push_back(i);
+        nlines += (long long)d0.wm * d0.hm;
+        maxkey = std::max(maxkey, (d0.wm - 1) + 2 * (d0.hm - 1));
+    }
+    if (nlines > (1ll << 30)) return ME_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (desc[i].dep_line_base <= -2) desc[i].dep_line_base = cd[-2 - desc[i].dep_line_base].line_base;
+    // tickets in the order (h + 2v, chain): counting sort on the key
+    std::vector<uint32_t> cnt(maxkey + 2, 0);
+    for (int c = 0; c < nc; ++c)
+        for (int v = 0; v < cd[c].hm; ++v)
+            for (int h = 0; h < cd[c].wm; ++h) cnt[h + 2 * v + 1]++;
+    for (int key = 1; key <= maxkey + 1; ++key) cnt[key] += cnt[key - 1];
+    std::vector<uint32_t> tickets((size_t)nlines);
+    for (int c = 0; c < nc; ++c)
+        for (int v = 0; v < cd[c].hm; ++v)
+            for (int h = 0; h < cd[c].wm; ++h)
+                tickets[cnt[h + 2 * v]++] = ((uint32_t)c << 16) | ((uint32_t)v << 8) | (uint32_t)h;
+
+    Workspace *w = nullptr;
+    rc = get_ws(stream, &w);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(w->mu);
+    std::vector<uint8_t> blob;
+    size_t o_jobs = put(blob, desc.data(), desc.size());
+    size_t o_ch = put(blob, cd.data(), cd.size());
+    size_t o_cj = put(blob, cj.data(), cj.size());
+    size_t o_tk = put(blob, tickets.data(), tickets.size());
+    size_t zero = align_up((size_t)nlines * 4, 256) + 256;
+    uint8_t *base = nullptr, *zb = nullptr;
+    rc = upload(*w, blob, zero, &base, &zb);
+    if (rc) return rc;
+    uint32_t *progress = (uint32_t *)zb;
+    uint32_t *counter = (uint32_t *)(zb + align_up((size_t)nlines * 4, 256));
+    int workers = (int)std::min<long long>(nlines, pa_worker_cap());
+    KParams kp = kparams(params, shape_only);
+    return hip_err(launch_pa((const JobDesc *)(base + o_jobs), (const ChainDesc *)(base + o_ch),
+                             (const int32_t *)(base + o_cj), (const uint32_t *)(base + o_tk), (int)nlines,
+                             progress, counter, w->status, kp, workers, w->stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+void me_default_params(me_params *p) {
+    if (!p) return;
+    p->search_range = 16;
+    p->theta = 3;
+    p->eps_q12 = 4096;
+    p->max_step = 1;
+    p->k_max = 8;
+    p->half_pel = 0;
+    p->flags = 0;
+}
+
+const char *me_status_str(int s) {
+    switch (s) {
+        case ME_OK: return "ok";
+        case ME_EINVAL: return "invalid argument";
+        case ME_EALIGN: return "frame size, stride or pointer alignment not supported";
+        case ME_EHIP: return "HIP runtime error";
+        case ME_ENOMEM: return "out of device or pinned memory";
+        case ME_EEMPTY: return "PSNR over zero pixels";
+        case ME_EDEVICE: return "device status word set";
+        case ME_ENODEV: return "no gfx950 device";
+        default: return "unknown status";
+    }
+}
+
+void me_shutdown(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipDeviceSynchronize();
+    for (auto &kv : g_ws) {
+        Workspace *w = kv.second;
+        int cur = 0;
+        hipGetDevice(&cur);
+        hipSetDevice(w->device);
+        if (w->dev) hipFree(w->dev);
+        if (w->status) hipFree(w->status);
+        for (auto &s : w->ring) {
+            if (s.host) hipHostFree(s.host);
+            if (s.ev) hipEventDestroy(s.ev);
+        }
+        if (w->host_acc) hipHostFree(w->host_acc);
+        hipSetDevice(cur);
+        delete w;
+    }
+    g_ws.clear();
+}
+
+int me_classify_babs(const me_frame *frames, int n, uint8_t *const *mb_class, uint32_t *const *bab_bits,
+                     void *stream) {
+    if (n < 0 || (n > 0 && (!frames || !mb_class))) return ME_EINVAL;
+    std::vector<JobDesc> desc(n);
+    long long total = 0;
+    for (int i = 0; i < n; ++i) {
+        int rc = check_frame(frames[i], true);
+        if (rc) return rc;
+        if (!mb_class[i]) return ME_EINVAL;
+        if (bab_bits && bab_bits[i] && !al4(bab_bits[i])) return ME_EALIGN;
+        JobDesc &d = desc[i];
+        std::memset(&d, 0, sizeof(d));
+        d.cur_a = frames[i].alpha;
+        d.out_u8 = mb_class[i];
+        d.out_u32 = bab_bits ? bab_bits[i] : nullptr;
+        d.width = frames[i].width;
+        d.height = frames[i].height;
+        d.stride = frames[i].stride;
+        d.wm = d.width / 16;
+        d.hm = d.height / 16;
+        d.mb_base = (int32_t)total;
+        d.dep_line_base = -1;
+        total += (long long)d.wm * d.hm;
+    }
+    if (total > (1ll << 30)) return ME_EINVAL;
+    if (n == 0) return ME_OK;
+    Workspace *w = nullptr;
+    int rc = get_ws(stream, &w);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(w->mu);
+    std::vector<uint8_t> blob;
+    size_t o = put(blob, desc.data(), desc.size());
+    uint8_t *base = nullptr, *zb = nullptr;
+    rc = upload(*w, blob, 0, &base, &zb);
+    if (rc) return rc;
+    return hip_err(launch_classify((const JobDesc *)(base + o), n, (int)total, w->stream));
+}
+
+int me_texture_recursive(const me_job *jobs, int n, const me_params *params, const me_net *net, void *stream) {
+    if (net) return ME_EINVAL;  // the learned proposal is provided through job.seed
+    return run_pa(jobs, n, params, false, stream);
+}
+
+int me_shape_search(const me_job *jobs, int n, const me_params *params, void *stream) {
+    return run_pa(jobs, n, params, true, stream);
+}
+
+int me_full_search(int method, const me_job *jobs, int n, const me_params *params, void *stream) {
+    if (method != ME_ES && method != ME_TSS && method != ME_DS) return ME_EINVAL;
+    if (n < 0 || (n > 0 && !jobs)) return ME_EINVAL;
+    int rc = check_params(params);
+    if (rc) return rc;
+    std::vector<JobDesc> desc(n);
+    long long total = 0;
+    for (int i = 0; i < n; ++i) {
+        rc = check_job(jobs[i], false);
+        if (rc) return rc;
+        desc[i] = job_desc(jobs[i]);
+        desc[i].tf = nullptr;
+        desc[i].seed = nullptr;
+        desc[i].mb_base = (int32_t)total;
+        total += (long long)desc[i].wm * desc[i].hm;
+    }
+    if (total > (1ll << 30)) return ME_EINVAL;
+    if (n == 0) return ME_OK;
+    if (method == ME_ES) {
+        int dev = 0, lim = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return ME_ENODEV;
+        if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            return ME_EHIP;
+        if (es_lds_bytes(params->search_range) > (size_t)lim) return ME_EINVAL;
+    }
+    Workspace *w = nullptr;
+    rc = get_ws(stream, &w);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(w->mu);
+    std::vector<uint8_t> blob;
+    size_t o = put(blob, desc.data(), desc.size());
+    uint8_t *base = nullptr, *zb = nullptr;
+    rc = upload(*w, blob, 0, &base, &zb);
+    if (rc) return rc;
+    KParams kp = kparams(params, false);
+    return hip_err(launch_full_search(method, (const JobDesc *)(base + o), n, (int)total, kp, w->status, w->stream));
+}
+
+int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, uint64_t *sse, uint64_t *npix,
+                              double *psnr_db, void *stream) {
+    if (n < 0 || (n > 0 && (!jobs || !sse || !npix || !psnr_db))) return ME_EINVAL;
+    std::vector<JobDesc> desc(n);
+    long long total = 0;
+    for (int i = 0; i < n; ++i) {
+        const me_job &j = jobs[i];
+        int rc = check_frame(j.cur, false);
+        if (rc) return rc;
+        rc = check_frame(j.ref, false);
+        if (rc) return rc;
+        if (j.cur.width != j.ref.width || j.cur.height != j.ref.height || j.cur.stride != j.ref.stride)
+            return ME_EINVAL;
+        if (!j.mv) return ME_EINVAL;
+        if (!al4(j.mv)) return ME_EALIGN;
+        if (pred && pred[i] && !al4(pred[i])) return ME_EALIGN;
+        desc[i] = job_desc(j);
+        desc[i].out_u8 = pred ? pred[i] : nullptr;
+        desc[i].mb_base = (int32_t)total;
+        total += (long long)desc[i].wm * desc[i].hm;
+    }
+    if (total > (1ll << 30)) return ME_EINVAL;
+    if (n == 0) return ME_OK;
+    Workspace *w = nullptr;
+    int rc = get_ws(stream, &w);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(w->mu);
+    std::vector<uint8_t> blob;
+    size_t o = put(blob, desc.data(), desc.size());
+    uint8_t *base = nullptr, *zb = nullptr;
+    size_t acc_bytes = (size_t)n * 2 * sizeof(unsigned long long);
+    rc = upload(*w, blob, acc_bytes, &base, &zb);
+    if (rc) return rc;
+    unsigned long long *acc = (unsigned long long *)zb;
+    rc = hip_err(launch_mc((const JobDesc *)(base + o), n, (int)total, acc, w->stream));
+    if (rc) return rc;
+    if (w->host_acc_cap < acc_bytes) {
+        if (w->host_acc) hipHostFree(w->host_acc);
+        w->host_acc = nullptr;
+        if (hipHostMalloc((void **)&w->host_acc, acc_bytes, hipHostMallocDefault) != hipSuccess) {
+            w->host_acc_cap = 0;
+            return ME_ENOMEM;
+        }
+        w->host_acc_cap = acc_bytes;
+    }
+    if (hipMemcpyAsync(w->host_acc, acc, acc_bytes, hipMemcpyDeviceToHost, w->stream) != hipSuccess) return ME_EHIP;
+    if (hipStreamSynchronize(w->stream) != hipSuccess) return ME_EHIP;
+    int status = ME_OK;
+    for (int i = 0; i < n; ++i) {
+        sse[i] = w->host_acc[2 * i];
+        npix[i] = w->host_acc[2 * i + 1];
+        if (npix[i] == 0) {
+            psnr_db[i] = NAN;
+            status = ME_EEMPTY;
+        } else if (sse[i] == 0) {
+            psnr_db[i] = INFINITY;
+        } else {
+            psnr_db[i] = 10.0 * std::log10(255.0 * 255.0 * (double)npix[i] / (double)sse[i]);
+        }
+    }
+    return status;
+}
+
+int me_device_status(void *stream) {
+    Workspace *w = nullptr;
+    int rc = get_ws(stream, &w);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(w->mu);
+    if (hipStreamSynchronize(w->stream) != hipSuccess) return ME_EHIP;
+    uint32_t st = 0;
+    if (hipMemcpy(&st, w->status, 4, hipMemcpyDeviceToHost) != hipSuccess) return ME_EHIP;
+    if (st) {
+        if (hipMemset(w->status, 0, 4) != hipSuccess) return ME_EHIP;
+        return ME_EDEVICE;
+    }
+    return ME_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,325 @@
+// Baseline block matching (Section 1 references [5], [7]; Tables 1-2):
+// exhaustive search (ES), three-step search (TSS), diamond search (DS), on the
+// luma of every non-transparent MB.  No inter-MB dependency: flat grids.
+#include "me_internal.h"
+
+namespace me {
+
+namespace {
+
+constexpr int kEsThreads = 256;
+constexpr int kEsG = 8;  // candidate rows per thread task (register blocking)
+
+__device__ __forceinline__ void write_result(const JobDesc &J, int k, int dx, int dy, uint32_t cost, int pts) {
+    uint32_t w = (uint32_t)(uint16_t)(2 * dx) | ((uint32_t)(uint16_t)(2 * dy) << 16);
+    ((uint32_t *)J.mv)[k] = w;
+    ((uint32_t *)J.mv_int)[k] = w;
+    if (J.cost) J.cost[k] = cost;
+    if (J.iters) J.iters[k] = 0;
+    if (J.points) J.points[k] = (uint16_t)pts;
+}
+
+// ES.  One workgroup per MB.  The (16+2S)^2 reference window is staged in LDS
+// as four byte-shifted copies so that a 16-byte row segment at any column is
+// four aligned dword reads.  A thread owns one column offset dx and kEsG
+// consecutive dy: every reference row it reads feeds up to kEsG candidate
+// SADs (v_sad_u8 on packed bytes), with the current block held in registers.
+// Key = (SAD, |dx|+|dy|, dy, dx) lexicographic, packed into 64 bits.
+__global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, int n, KParams kp) {
+    extern __shared__ uint32_t lds[];
+    const int mb = blockIdx.x;
+    const int ji = find_job(jobs, n, mb);
+    const JobDesc &J = jobs[ji];
+    const int k = mb - J.mb_base;
+    const int h = k % J.wm, v = k / J.wm;
+    const int x0 = 16 * h, y0 = 16 * v, W = J.width, H = J.height, st = J.stride;
+    const int S = kp.S;
+    const int tid = threadIdx.x;
+    const int cls = J.cls ? (int)J.cls[k] : ME_MB_OPAQUE;
+    if (cls == ME_MB_TRANSPARENT || cls > 2) {
+        if (tid == 0) write_result(J, k, 0, 0, 0u, 0);
+        return;
+    }
+    const int span = 16 + 2 * S;      // window rows and columns
+    const int pd = (span + 3) >> 2;   // dwords per row per copy
+    const int csz = span * pd;        // dwords per copy
+    uint32_t *win = lds;              // 4 copies
+    uint32_t *curb = lds + 4 * csz;   // 64 dwords
+    unsigned long long *red = (unsigned long long *)(curb + 64);  // 4 wave minima
+    // stage: copy s, row r, dword w holds window bytes 4w+s .. 4w+s+3
+    const int wx0 = x0 - S, wy0 = y0 - S;
+    for (int idx = tid; idx < 4 * csz; idx += kEsThreads) {
+        int s = idx / csz, rem = idx - s * csz;
+        int r = rem / pd, w = rem - r * pd;
+        int yy = wy0 + r;
+        uint32_t val = 0;
+        if (yy >= 0 && yy < H) {
+            const uint8_t *row = J.ref + (size_t)yy * st;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                int c = 4 * w + s + b;
+                int xx = wx0 + c;
+                uint32_t byte = (c < span && xx >= 0 && xx < W) ? row[xx] : 0u;
+                val |= byte << (8 * b);
+            }
+        }
+        win[idx] = val;
+    }
+    if (tid < 64) curb[tid] = *(const uint32_t *)(J.cur + (size_t)(y0 + (tid >> 2)) * st + x0 + 4 * (tid & 3));
+    __syncthreads();
+    uint32_t cr[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) cr[i] = curb[i];
+
+    const int lox = max(-S, -x0), hix = min(S, W - 16 - x0);
+    const int loy = max(-S, -y0), hiy = min(S, H - 16 - y0);
+    const int ncol = 2 * S + 1;
+    const int ngrp = (ncol + kEsG - 1) / kEsG;
+    unsigned long long best = ~0ull;
+    for (int task = tid; task < ncol * ngrp; task += kEsThreads) {
+        const int cxr = task % ncol;       // dx + S
+        const int dy0 = (task / ncol) * kEsG;  // first dy + S
+        const int dx = cxr - S;
+        if (dx < lox || dx > hix) continue;
+        const uint32_t *cp = win + (cxr & 3) * csz + (cxr >> 2);
+        uint32_t acc[kEsG];
+#pragma unroll
+        for (int g = 0; g < kEsG; ++g) acc[g] = 0;
+#pragma unroll
+        for (int r = 0; r < kEsG + 15; ++r) {
+            const int wr = dy0 + r;
+            if (wr < span) {
+                const uint32_t *rp = cp + wr * pd;
+                uint32_t r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
+#pragma unroll
+                for (int g = 0; g < kEsG; ++g) {
+                    const int jj = r - g;
+                    if (jj >= 0 && jj < 16) {
+                        uint32_t a = acc[g];
+                        a = __builtin_amdgcn_sad_u8(cr[4 * jj + 0], r0, a);
+                        a = __builtin_amdgcn_sad_u8(cr[4 * jj + 1], r1, a);
+                        a = __builtin_amdgcn_sad_u8(cr[4 * jj + 2], r2, a);
+                        a = __builtin_amdgcn_sad_u8(cr[4 * jj + 3], r3, a);
+                        acc[g] = a;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < kEsG; ++g) {
+            const int dy = dy0 + g - S;
+            if (dy0 + g < ncol && dy >= loy && dy <= hiy) {
+                unsigned long long key = ((unsigned long long)acc[g] << 32) |
+                                         ((unsigned long long)(abs(dx) + abs(dy)) << 16) |
+                                         ((unsigned long long)(dy + S) << 8) | (unsigned long long)(dx + S);
+                best = key < best ? key : best;
+            }
+        }
+    }
+    best = wave_min_u64(best);
+    if (lane() == 0) red[tid >> 6] = best;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long b = red[0];
+        for (int w = 1; w < kEsThreads / 64; ++w) b = red[w] < b ? red[w] : b;
+        int dx = (int)(b & 0xFF) - S, dy = (int)((b >> 8) & 0xFF) - S;
+        int pts = (hix - lox + 1) * (hiy - loy + 1);
+        write_result(J, k, dx, dy, (uint32_t)(b >> 32), pts);
+    }
+}
+
+// TSS / DS.  One wave per MB; each round's candidates are evaluated together
+// (lane = row j, quad q; 4 pixels per lane, unaligned dword loads from the
+// L2-resident reference), partial SADs packed two per reduction.  A bitmap of
+// evaluated positions in LDS counts distinct search points.
+constexpr int kMemoWords = (129 * 129 + 31) / 32;
+
+__constant__ int kLdsp[8][2] = {{0, -2}, {-1, -1}, {1, -1}, {-2, 0}, {2, 0}, {-1, 1}, {1, 1}, {0, 2}};
+__constant__ int kSdsp[4][2] = {{0, -1}, {-1, 0}, {1, 0}, {0, 1}};
+
+struct Mb {
+    const uint8_t *ref;
+    int st, x, y;  // this lane's first pixel
+    uint32_t c4;
+    int lox, hix, loy, hiy, S;
+    uint32_t *memo;
+    int pts;
+};
+
+__device__ __forceinline__ bool feas(const Mb &m, int dx, int dy) {
+    return dx >= m.lox && dx <= m.hix && dy >= m.loy && dy <= m.hiy;
+}
+
+__device__ __forceinline__ void visit(Mb &m, int dx, int dy) {
+    int i = (dy + m.S) * (2 * m.S + 1) + (dx + m.S);
+    uint32_t w = m.memo[i >> 5], bit = 1u << (i & 31);
+    if (!(w & bit)) {
+        m.memo[i >> 5] = w | bit;
+        m.pts++;
+    }
+}
+
+// Evaluate up to 8 offsets (ox, oy), returns SADs (infeasible -> ~0u).
+template <int N>
+__device__ __forceinline__ void eval_pts(Mb &m, const int (&ox)[N], const int (&oy)[N], uint32_t (&out)[N]) {
+    int part[N + (N & 1)];
+    bool ok[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        ok[i] = feas(m, ox[i], oy[i]);
+        part[i] = 0;
+        if (ok[i]) {
+            uint32_t r4 = ld4(m.ref + (size_t)(m.y + oy[i]) * m.st + m.x + ox[i]);
+            part[i] = (int)__builtin_amdgcn_sad_u8(m.c4, r4, 0u);
+        }
+    }
+    if (N & 1) part[N] = 0;
+#pragma unroll
+    for (int i = 0; i < N; i += 2) {
+        int pk = wave_sum(part[i] | ((i + 1 < N ? part[i + 1] : 0) << 16));
+        out[i] = ok[i] ? (uint32_t)(pk & 0xFFFF) : ~0u;
+        if (i + 1 < N) out[i + 1] = ok[i + 1] ? (uint32_t)((uint32_t)pk >> 16) : ~0u;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        if (ok[i]) visit(m, ox[i], oy[i]);
+}
+
+__global__ __launch_bounds__(64) void tss_ds_kernel(const JobDesc *jobs, int n, KParams kp, int method) {
+    __shared__ uint32_t memo[kMemoWords];
+    const int mb = blockIdx.x;
+    const int ji = find_job(jobs, n, mb);
+    const JobDesc &J = jobs[ji];
+    const int k = mb - J.mb_base;
+    const int h = k % J.wm, v = k / J.wm;
+    const int x0 = 16 * h, y0 = 16 * v;
+    const int l = lane();
+    const int cls = J.cls ? (int)J.cls[k] : ME_MB_OPAQUE;
+    if (cls == ME_MB_TRANSPARENT || cls > 2) {
+        if (l == 0) write_result(J, k, 0, 0, 0u, 0);
+        return;
+    }
+    const int S = kp.S;
+    const int words = ((2 * S + 1) * (2 * S + 1) + 31) >> 5;
+    for (int i = l; i < words; i += 64) memo[i] = 0;
+    __syncthreads();
+    Mb m;
+    m.ref = J.ref;
+    m.st = J.stride;
+    m.x = x0 + 4 * (l & 3);
+    m.y = y0 + (l >> 2);
+    m.c4 = *(const uint32_t *)(J.cur + (size_t)m.y * m.st + m.x);
+    m.lox = max(-S, -x0);
+    m.hix = min(S, J.width - 16 - x0);
+    m.loy = max(-S, -y0);
+    m.hiy = min(S, J.height - 16 - y0);
+    m.S = S;
+    m.memo = memo;
+    m.pts = 0;
+    int cx = 0, cy = 0;
+    uint32_t cc;
+    {
+        int ox[1] = {0}, oy[1] = {0};
+        uint32_t o[1];
+        eval_pts<1>(m, ox, oy, o);
+        cc = o[0];
+    }
+    if (method == ME_TSS) {
+        int p2 = 1;
+        while (p2 < S + 1) p2 *= 2;
+        for (int stp = p2 / 2; stp >= 1; stp /= 2) {
+            int ox[8], oy[8];
+            int i = 0;
+#pragma unroll
+            for (int jj = -1; jj <= 1; ++jj)
+#pragma unroll
+                for (int ii = -1; ii <= 1; ++ii)
+                    if (ii || jj) {
+                        ox[i] = cx + ii * stp;
+                        oy[i] = cy + jj * stp;
+                        ++i;
+                    }
+            uint32_t c[8];
+            eval_pts<8>(m, ox, oy, c);
+            int nx = cx, ny = cy;
+            uint32_t nc = cc;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (c[q] < nc) {
+                    nc = c[q];
+                    nx = ox[q];
+                    ny = oy[q];
+                }
+            cx = nx;
+            cy = ny;
+            cc = nc;
+        }
+    } else {
+        for (int guard = 0; guard < 65536; ++guard) {
+            int ox[8], oy[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                ox[q] = cx + kLdsp[q][0];
+                oy[q] = cy + kLdsp[q][1];
+            }
+            uint32_t c[8];
+            eval_pts<8>(m, ox, oy, c);
+            int nx = cx, ny = cy;
+            uint32_t nc = cc;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (c[q] < nc) {
+                    nc = c[q];
+                    nx = ox[q];
+                    ny = oy[q];
+                }
+            if (nx == cx && ny == cy) break;
+            cx = nx;
+            cy = ny;
+            cc = nc;
+        }
+        int ox[4], oy[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ox[q] = cx + kSdsp[q][0];
+            oy[q] = cy + kSdsp[q][1];
+        }
+        uint32_t c[4];
+        eval_pts<4>(m, ox, oy, c);
+        int nx = cx, ny = cy;
+        uint32_t nc = cc;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (c[q] < nc) {
+                nc = c[q];
+                nx = ox[q];
+                ny = oy[q];
+            }
+        cx = nx;
+        cy = ny;
+        cc = nc;
+    }
+    if (l == 0) write_result(J, k, cx, cy, cc, m.pts);
+}
+
+}  // namespace
+
+size_t es_lds_bytes(int S) {
+    int span = 16 + 2 * S, pd = (span + 3) >> 2;
+    return (size_t)(4 * span * pd + 64) * 4 + 4 * sizeof(unsigned long long);
+}
+
+hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_mbs, const KParams &kp,
+                              uint32_t *status, hipStream_t s) {
+    (void)status;
+    if (total_mbs <= 0) return hipSuccess;
+    if (method == ME_ES) {
+        size_t lds = es_lds_bytes(kp.S);
+        hipLaunchKernelGGL(es_kernel, dim3(total_mbs), dim3(kEsThreads), lds, s, jobs, n, kp);
+    } else {
+        hipLaunchKernelGGL(tss_ds_kernel, dim3(total_mbs), dim3(64), 0, s, jobs, n, kp, method);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace me

@@ -1,0 +1,130 @@
+// Internal declarations of the gfx950 motion-estimation library: device-side
+// job descriptors, launch entry points and wave64 helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/me.h"
+
+namespace me {
+
+// ---------------------------------------------------------------- layout
+// Device view of one frame pair (one me_job) or one frame (classification).
+struct JobDesc {
+    const uint8_t *cur, *ref, *cur_a, *ref_a;
+    const uint8_t *cls;
+    const int16_t *tf, *seed;
+    int16_t *mv, *mv_int;
+    uint32_t *cost;
+    uint8_t *iters;
+    uint16_t *points;
+    uint8_t *out_u8;      // classification: class out; MC: prediction out (nullable)
+    uint32_t *out_u32;    // classification: BAB words out (nullable)
+    int32_t width, height, stride, wm, hm;
+    int32_t mb_base;        // first flat MB index of this job in multi-job grids
+    int32_t dep_line_base;  // PA: progress lines of the chain producing T (-1: none)
+    int32_t dep_pos;        // PA: position of the producing job in that chain
+    int32_t t_local;        // PA: T is the previous position of this job's own chain
+    int32_t pad;
+};
+
+// A pipelined chain of frame pairs (each one's T field is the previous one's
+// mv_int).  One progress line per MB position.
+struct ChainDesc {
+    int32_t first;      // offset into the chain-job index array
+    int32_t len;
+    int32_t wm, hm;
+    int32_t line_base;  // first progress counter of this chain
+    int32_t pad[3];
+};
+
+struct KParams {
+    int32_t S, theta, eps, max_step, k_max, half_pel, shape_only, spin_limit;
+};
+
+// device status word bits
+enum : uint32_t { ST_SPIN_TIMEOUT = 1u, ST_BAD_CLASS = 2u, ST_ABORT = 4u };
+
+// ------------------------------------------------------------- launches
+hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
+hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_t s);
+hipError_t launch_pa(const JobDesc *jobs, const ChainDesc *chains, const int32_t *chain_jobs,
+                     const uint32_t *tickets, int nlines, uint32_t *progress, uint32_t *counter,
+                     uint32_t *status, const KParams &kp, int workers, hipStream_t s);
+hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_mbs, const KParams &kp,
+                              uint32_t *status, hipStream_t s);
+hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, unsigned long long *acc, hipStream_t s);
+
+int pa_worker_cap();
+
+}  // namespace me
+
+// ----------------------------------------------------------- device helpers
+#if defined(__HIPCC__)
+namespace me {
+
+__device__ __forceinline__ int lane() { return __lane_id(); }
+
+// Unaligned 4-byte global load (gfx950 serves unaligned dword accesses).
+__device__ __forceinline__ uint32_t ld4(const uint8_t *p) {
+    uint32_t v;
+    __builtin_memcpy(&v, p, 4);
+    return v;
+}
+
+// Per byte: 0xFF where the byte is non-zero, else 0 (binary alpha -> 0/255 plane).
+__device__ __forceinline__ uint32_t bin4(uint32_t x) {
+    uint32_t m = (((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+    return (m >> 7) * 0xFFu;
+}
+
+__device__ __forceinline__ int byte_of(uint32_t w, int k) { return (int)((w >> (8 * k)) & 0xFFu); }
+
+// Sum over the 64 lanes with DPP row operations, broadcast to every lane.
+__device__ __forceinline__ int wave_sum(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
+    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
+    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true);  // row_half_mirror
+    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, true);  // row_mirror
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false); // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false); // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u(uint32_t v) { return (uint32_t)wave_sum((int)v); }
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+    for (int o = 32; o >= 1; o >>= 1) {
+        unsigned long long w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Job of flat MB index `idx` (jobs sorted by mb_base; binary search).
+__device__ __forceinline__ int find_job(const JobDesc *jobs, int n, int idx) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].mb_base <= idx) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int iclamp(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
+
+// Eq. 3 per-axis step: eps * U (Q.24) rounded half away from zero, clamped.
+__device__ __forceinline__ int prs_step(int u, int eps, int max_step) {
+    long long vq = (long long)eps * (long long)u;
+    long long a = vq < 0 ? -vq : vq;
+    long long s = (a + (1ll << 23)) >> 24;
+    int r = (int)(s > max_step ? max_step : s);
+    return vq < 0 ? -r : r;
+}
+
+}  // namespace me
+#endif

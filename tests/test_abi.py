@@ -1,0 +1,107 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/me.h, and rejects invalid arguments with the documented
+codes before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_1002_1168_amd as me
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "me.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(me.LIB_PATH), reason="libme.so not built")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(me_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    L = C.CDLL(me.LIB_PATH)
+    names = declared_functions()
+    assert "me_texture_recursive" in names and "me_classify_babs" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(me.EXPORTED) <= set(names)
+
+
+def test_status_strings_and_defaults():
+    assert me.status_str(0) == "ok"
+    assert "alignment" in me.status_str(me.ME_EALIGN)
+    p = me.me_default_params()
+    assert (p.search_range, p.theta, p.eps_q12, p.max_step, p.k_max, p.half_pel, p.flags) == (16, 3, 4096, 1, 8, 0, 0)
+
+
+FAKE = 0x10000  # never dereferenced: validation fails before any HIP call
+
+
+def frame(w=64, h=48, stride=None, luma=FAKE, alpha=None):
+    return me.me_frame(luma, alpha, w, h, w if stride is None else stride)
+
+
+def job(**kw):
+    j = me.me_job(frame(), frame(), None, None, None, FAKE, FAKE + 4096, None, None, None)
+    for k, v in kw.items():
+        setattr(j, k, v)
+    return j
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(search_range=0), me.ME_EINVAL), (dict(search_range=65), me.ME_EINVAL),
+    (dict(theta=0), me.ME_EINVAL), (dict(eps_q12=-1), me.ME_EINVAL),
+    (dict(max_step=0), me.ME_EINVAL), (dict(max_step=17), me.ME_EINVAL),
+    (dict(k_max=256), me.ME_EINVAL), (dict(half_pel=2), me.ME_EINVAL), (dict(flags=1), me.ME_EINVAL)])
+def test_bad_params(over, code):
+    p = me.me_default_params(**over)
+    assert me.me_texture_recursive([job()], p, check=False) == code
+    assert me.me_full_search(me.ME_ES, [job()], p, check=False) == code
+
+
+@pytest.mark.parametrize("cur,code", [
+    (frame(w=60), me.ME_EALIGN), (frame(h=40), me.ME_EALIGN), (frame(stride=62), me.ME_EALIGN),
+    (frame(stride=66), me.ME_EALIGN), (frame(luma=FAKE + 1), me.ME_EALIGN), (frame(luma=None), me.ME_EINVAL),
+    (frame(w=0), me.ME_EINVAL), (frame(w=4112), me.ME_EINVAL)])
+def test_bad_frames(cur, code):
+    p = me.me_default_params()
+    j = job(cur=cur, ref=cur)
+    assert me.me_texture_recursive([j], p, check=False) == code
+    assert me.me_classify_babs([frame(luma=cur.luma, alpha=FAKE, w=cur.width, h=cur.height, stride=cur.stride)],
+                               [FAKE], check=False) in (code, me.ME_EINVAL)
+
+
+def test_bad_jobs():
+    p = me.me_default_params()
+    assert me.me_texture_recursive([job(mv=None)], p, check=False) == me.ME_EINVAL
+    assert me.me_texture_recursive([job(ref=frame(w=48))], p, check=False) == me.ME_EINVAL
+    assert me.me_texture_recursive([job(cur=frame(alpha=FAKE))], p, check=False) == me.ME_EINVAL  # alpha one-sided
+    assert me.me_shape_search([job()], p, check=False) == me.ME_EINVAL                          # needs alpha
+    assert me.me_texture_recursive([job(mv=FAKE + 2)], p, check=False) == me.ME_EALIGN
+    j = job()
+    j.t_field = j.mv_int
+    assert me.me_texture_recursive([j], p, check=False) == me.ME_EINVAL                         # reads own output
+    a, b = job(), job(mv=FAKE + 8192, mv_int=FAKE + 12288)
+    a.t_field = b.mv_int                                                                            # written later
+    assert me.me_texture_recursive([a, b], p, check=False) == me.ME_EINVAL
+    c = job(mv=FAKE + 8192)
+    assert me.me_texture_recursive([job(), c], p, check=False) == me.ME_EINVAL                  # shared mv_int
+    assert me.me_full_search(3, [job()], p, check=False) == me.ME_EINVAL
+    assert me.me_texture_recursive([job()], p, net=C.c_void_p(FAKE), check=False) == me.ME_EINVAL
+
+
+def test_empty_calls_are_ok_without_device():
+    p = me.me_default_params()
+    assert me.me_texture_recursive([], p, check=False) == me.ME_OK
+    assert me.me_full_search(me.ME_DS, [], p, check=False) == me.ME_OK
+    assert me.me_classify_babs([], [], check=False) == me.ME_OK
+    assert me.me_motion_compensate_psnr([], check=False)[3] == me.ME_OK
+
+
+def test_psnr_requires_host_outputs():
+    L = me.lib()
+    ja = (me.me_job * 1)(job())
+    assert L.me_motion_compensate_psnr(ja, 1, None, None, None, None, None) == me.ME_EINVAL

@@ -1,0 +1,240 @@
+"""GPU parity: every entry point of the C ABI against the CPU oracle on the
+same seeded inputs, bit-exact (classes, BAB words, vectors, costs, iteration
+and point counts, SSE, pixel counts; PSNR within 1e-6 dB)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1002_1168_amd as me
+from paper_1002_1168_amd import synth
+
+from gpu_util import assert_same, gpu_classify, gpu_pa, oracle_pa, oracle_params, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    me.lib()
+    return torch
+
+
+def dseq(seq):
+    from paper_1002_1168_amd.device import DeviceSequence
+    return DeviceSequence(seq)
+
+
+# ------------------------------------------------------------ classification
+@pytest.mark.parametrize("maker", ["qcif", "cif", "random"])
+def test_classify_parity(torch_cuda, maker):
+    say("classify", maker)
+    seq = {"qcif": lambda: synth.qcif_ellipse(frames=4), "cif": lambda: synth.cif_two_vops(frames=4),
+           "random": lambda: synth.random_frames(5, 96, 64, frames=3, vops=2)}[maker]()
+    if maker == "random":   # non-binary alpha: inside <=> != 0
+        rng = np.random.default_rng(1)
+        nz = seq.alpha != 0
+        seq.alpha[nz] = rng.integers(1, 256, size=int(nz.sum()))
+    ds = dseq(seq)
+    gpu_classify(ds)
+    cls = ds.cls.cpu().numpy()
+    bab = ds.bab.cpu().numpy().view(np.uint32)
+    for v in range(seq.vops):
+        for t in range(seq.frames):
+            c, b = oracle.classify(seq.alpha[v, t])
+            np.testing.assert_array_equal(cls[v, t], c)
+            np.testing.assert_array_equal(bab[v, t].reshape(c.shape + (8,)), b)
+
+
+# ----------------------------------------------------------- proposed method
+def check_pa(seq, vops, params, pairs, shape_only=False, one_call=True, chained=True, label=""):
+    say("pa", label, seq.name, seq.width, seq.height, "vops", vops, "pairs", pairs, "shape_only", shape_only)
+    ds = dseq(seq)
+    gpu_classify(ds)
+    got = gpu_pa(ds, vops, params, pairs, shape_only, one_call, chained)
+    for v in vops:
+        want = oracle_pa(seq, v, params, pairs, shape_only)
+        assert_same(got[v], want, f"{label} vop {v}")
+    return got
+
+
+def test_pa_qcif_ellipse_full(torch_cuda):
+    seq = synth.qcif_ellipse()
+    check_pa(seq, [0], me.me_default_params(search_range=7), seq.frames - 1, label="qcif")
+
+
+def test_pa_qcif_rectangular(torch_cuda):
+    seq = synth.qcif_ellipse()
+    check_pa(seq, [None], me.me_default_params(search_range=7), seq.frames - 1, label="qcif-rect")
+
+
+def test_pa_shape_only(torch_cuda):
+    seq = synth.cif_two_vops(frames=8)
+    check_pa(seq, [0, 1], me.me_default_params(search_range=16), 7, shape_only=True, label="shape")
+
+
+def test_pa_cif_two_vops_chained_one_launch(torch_cuda):
+    seq = synth.cif_two_vops(frames=25)
+    check_pa(seq, [0, 1], me.me_default_params(search_range=16), 24, label="cif-chain")
+
+
+def test_pa_one_call_per_pair_matches(torch_cuda):
+    seq = synth.cif_two_vops(frames=6)
+    check_pa(seq, [0, 1], me.me_default_params(search_range=16), 5, one_call=False, label="cif-per-pair")
+
+
+@pytest.mark.parametrize("over", [dict(eps_q12=2048), dict(max_step=3), dict(theta=2), dict(k_max=0),
+                                  dict(k_max=1), dict(k_max=255, max_step=7), dict(eps_q12=65536, theta=1)])
+def test_pa_parameter_variants(torch_cuda, over):
+    seq = synth.qcif_ellipse()
+    check_pa(seq, [0, None], me.me_default_params(search_range=7, **over), seq.frames - 1, label=str(over))
+
+
+def test_pa_half_pel_hd(torch_cuda):
+    seq = synth.hd_streams(frames=3, streams=1)[0]
+    check_pa(seq, [0, 1, 2], me.me_default_params(search_range=32, half_pel=1), 2, label="hd-halfpel")
+
+
+def test_pa_random_noise_small_frames(torch_cuda):
+    # unstructured texture: long recursions, many infeasible candidates
+    seq = synth.random_frames(3, 48, 32, frames=5, vops=1, search_range=4)
+    check_pa(seq, [0, None], me.me_default_params(search_range=4, k_max=255), 4, label="noise")
+
+
+def test_pa_single_mb_and_empty_masks(torch_cuda):
+    seq = synth.random_frames(4, 16, 16, frames=3, vops=1, search_range=2)
+    seq.alpha[:] = 0
+    check_pa(seq, [0, None], me.me_default_params(search_range=2), 2, label="single-mb")
+
+
+def test_pa_max_width(torch_cuda):
+    seq = synth.random_frames(6, 4096, 32, frames=3, vops=0, search_range=16)
+    check_pa(seq, [None], me.me_default_params(search_range=16), 2, label="w4096")
+
+
+def test_pa_mixed_sizes_one_launch(torch_cuda):
+    import torch
+    from paper_1002_1168_amd import device as dv
+    streams = synth.mixed_streams(frames=4, counts=(2, 2, 1))
+    p = me.me_default_params(search_range=16)
+    say("pa mixed streams", [s.name for s in streams])
+    jobs, keep = [], []
+    for s in streams:
+        ds = dseq(s)
+        gpu_classify(ds)
+        for v in range(s.vops):
+            out = dv.Outputs.alloc(3, ds.hm, ds.wm)
+            jobs += ds.pair_jobs(v, out, 3)
+            keep.append((s, v, out, ds))
+    me.me_texture_recursive(jobs, p, None, stream=dv.stream_handle())
+    torch.cuda.synchronize()
+    assert me.me_device_status(dv.stream_handle()) == me.ME_OK
+    for s, v, out, _ in keep:
+        assert_same(out.host(), oracle_pa(s, v, p, 3), f"{s.name} vop {v}")
+
+
+# -------------------------------------------------------------- baselines
+def check_search(seq, method, S, pairs, vop=0):
+    import torch
+    from paper_1002_1168_amd import device as dv
+    say("search", method, seq.name, seq.width, seq.height, "S", S, "pairs", pairs)
+    ds = dseq(seq)
+    if vop is not None:
+        gpu_classify(ds)
+    out = dv.Outputs.alloc(pairs, ds.hm, ds.wm)
+    p = me.me_default_params(search_range=S)
+    jobs = ds.pair_jobs(vop, out, pairs, chained=False)
+    me.me_full_search(method, jobs, p, stream=dv.stream_handle())
+    torch.cuda.synchronize()
+    assert me.me_device_status(dv.stream_handle()) == me.ME_OK
+    got = out.host()
+    for i in range(pairs):
+        t = i + 1
+        cls = oracle.classify(seq.alpha[vop, t])[0] if vop is not None else None
+        want = oracle.search(method, seq.luma[t], seq.luma[t - 1], oracle_params(p), cls)
+        assert_same({k: got[k][i] for k in got}, want, f"method {method} pair {i}",
+                    keys=("mv", "mv_int", "cost", "points"))
+        assert (got["iters"][i] == 0).all()
+
+
+@pytest.mark.parametrize("method", [me.ME_ES, me.ME_TSS, me.ME_DS])
+def test_search_qcif(torch_cuda, method):
+    seq = synth.qcif_ellipse()
+    check_search(seq, method, 7, seq.frames - 1)
+    check_search(seq, method, 7, 3, vop=None)
+
+
+@pytest.mark.parametrize("method", [me.ME_ES, me.ME_TSS, me.ME_DS])
+def test_search_cif(torch_cuda, method):
+    check_search(synth.cif_two_vops(frames=4), method, 16, 3, vop=None)
+
+
+@pytest.mark.parametrize("method", [me.ME_ES, me.ME_TSS, me.ME_DS])
+@pytest.mark.parametrize("S", [1, 4, 13])
+def test_search_random_tiny(torch_cuda, method, S):
+    check_search(synth.random_frames(8, 64, 48, frames=3, vops=1), method, S, 2)
+
+
+@pytest.mark.parametrize("method", [me.ME_ES, me.ME_TSS, me.ME_DS])
+def test_search_s32_crop(torch_cuda, method):
+    seq = synth.hd_streams(frames=2, streams=1)[0]
+    seq.luma = np.ascontiguousarray(seq.luma[:, 256:512, 640:960])
+    seq.alpha = np.ascontiguousarray(seq.alpha[:, :, 256:512, 640:960])
+    check_search(seq, method, 32, 1, vop=None)
+
+
+# ------------------------------------------------------- MC, SSE, PSNR
+@pytest.mark.parametrize("half", [0, 1])
+def test_mc_psnr_parity(torch_cuda, half):
+    import torch
+    from paper_1002_1168_amd import device as dv
+    seq = synth.hd_streams(frames=3, streams=1)[0] if half else synth.cif_two_vops(frames=5)
+    S = 32 if half else 16
+    vops = list(range(seq.vops))
+    p = me.me_default_params(search_range=S, half_pel=half)
+    say("mc", seq.name, "half", half)
+    ds = dseq(seq)
+    gpu_classify(ds)
+    pairs = seq.frames - 1
+    got = gpu_pa(ds, vops, p, pairs)
+    for v in vops + [None]:
+        if v is None:  # rectangular prediction with the VOP's vectors
+            out = got[0]
+        else:
+            out = got[v]
+        mvt = torch.from_numpy(out["mv"]).cuda()
+        jobs = []
+        for i in range(pairs):
+            t = i + 1
+            ca = None if v is None else ds.alpha[v, t]
+            cls = None if v is None else ds.cls[v, t]
+            jobs.append(dv.mc_job(ds.luma[t], ds.luma[t - 1], ca, cls, mvt[i]))
+        preds = [torch.zeros((seq.height, seq.width), dtype=torch.uint8, device="cuda") for _ in range(pairs)]
+        sse, npx, ps, rc = me.me_motion_compensate_psnr(jobs, [x.data_ptr() for x in preds],
+                                                        stream=dv.stream_handle())
+        assert rc == me.ME_OK
+        for i in range(pairs):
+            t = i + 1
+            ca = None if v is None else seq.alpha[v, t]
+            cls = None if v is None else oracle.classify(ca)[0]
+            ws, wn, wp = oracle.mc_sse(seq.luma[t], seq.luma[t - 1], out["mv"][i], ca, cls, want_pred=True)
+            assert (sse[i], npx[i]) == (ws, wn)
+            want_db = oracle.psnr_db(ws, wn)
+            assert (ps[i] == want_db) or abs(ps[i] - want_db) < 1e-6
+            np.testing.assert_array_equal(preds[i].cpu().numpy(), wp)
+
+
+def test_mc_empty_mask_reports_eempty(torch_cuda):
+    import torch
+    from paper_1002_1168_amd import device as dv
+    seq = synth.random_frames(2, 32, 32, frames=2, vops=1)
+    seq.alpha[:] = 0
+    ds = dseq(seq)
+    mv = torch.zeros((2, 2, 2), dtype=torch.int16, device="cuda")
+    jobs = [dv.mc_job(ds.luma[1], ds.luma[0], ds.alpha[0, 1], None, mv)]
+    sse, npx, ps, rc = me.me_motion_compensate_psnr(jobs, stream=dv.stream_handle(), check=False)
+    assert rc == me.ME_EEMPTY and npx[0] == 0 and math.isnan(ps[0])
