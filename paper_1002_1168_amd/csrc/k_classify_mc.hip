@@ -15,10 +15,12 @@ __global__ __launch_bounds__(64) void fill_u32_kernel(uint32_t *p, size_t n, uin
 
 // n = number of pixels with alpha != 0 -> transparent (0), opaque (256),
 // boundary; BAB word w = rows 2w, 2w+1 with column i at bit (row&1)*16 + i.
-__global__ __launch_bounds__(256) void classify_kernel(const JobDesc *jobs, int n, int total) {
-    const int mb = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (mb >= total) return;
-    const int ji = find_job(jobs, n, mb);
+__global__ __launch_bounds__(256) void classify_kernel(const JobDesc *jobs, int n, int total, int chunk) {
+    const int first = blockIdx.x * chunk + (threadIdx.x >> 6);
+    const int last = min(blockIdx.x * chunk + chunk, total);
+    int ji = first < total ? find_job(jobs, n, first) : 0;
+    for (int mb = first; mb < last; mb += 4) {
+    ji = next_job(jobs, n, ji, mb);
     const JobDesc &J = jobs[ji];
     const int k = mb - J.mb_base;
     const int h = k % J.wm, v = k / J.wm;
@@ -35,6 +37,7 @@ __global__ __launch_bounds__(256) void classify_kernel(const JobDesc *jobs, int 
     w += __builtin_amdgcn_update_dpp(0, w, 0x141, 0xF, 0xF, true);
     if (J.out_u32 && (l & 7) == 0) J.out_u32[(size_t)k * 8 + (l >> 3)] = (uint32_t)w;
     if (l == 0) J.out_u8[k] = (uint8_t)(tot == 0 ? ME_MB_TRANSPARENT : (tot == 256 ? ME_MB_OPAQUE : ME_MB_BOUNDARY));
+    }
 }
 
 __device__ __forceinline__ int pix(const uint8_t *p, int st, int W, int H, int x, int y) {
@@ -44,10 +47,13 @@ __device__ __forceinline__ int pix(const uint8_t *p, int st, int W, int H, int x
 // Prediction of MB k by its half-pel vector (transparent: zero vector),
 // written to out_u8 when set; SSE and pixel count over the mask accumulate
 // into acc[2 * job] (exact integer sums, order-independent).
-__global__ __launch_bounds__(256) void mc_kernel(const JobDesc *jobs, int n, int total, unsigned long long *acc) {
-    const int mb = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (mb >= total) return;
-    const int ji = find_job(jobs, n, mb);
+__global__ __launch_bounds__(256) void mc_kernel(const JobDesc *jobs, int n, int total, int chunk,
+                                                 unsigned long long *acc) {
+    const int first = blockIdx.x * chunk + (threadIdx.x >> 6);
+    const int last = min(blockIdx.x * chunk + chunk, total);
+    int ji = first < total ? find_job(jobs, n, first) : 0;
+    for (int mb = first; mb < last; mb += 4) {
+    ji = next_job(jobs, n, ji, mb);
     const JobDesc &J = jobs[ji];
     const int k = mb - J.mb_base;
     const int h = k % J.wm, v = k / J.wm;
@@ -91,6 +97,7 @@ __global__ __launch_bounds__(256) void mc_kernel(const JobDesc *jobs, int n, int
         if (tsse) atomicAdd(acc + 2 * ji, (unsigned long long)(uint32_t)tsse);
         if (tcnt) atomicAdd(acc + 2 * ji + 1, (unsigned long long)tcnt);
     }
+    }
 }
 
 }  // namespace
@@ -103,15 +110,28 @@ hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
+// MBs per block so that a flat grid has about per_cu blocks per CU.
+int flat_chunk(int total_mbs, int per_cu) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    long long blocks = (long long)(cus > 0 ? cus : 256) * per_cu;
+    long long c = (total_mbs + blocks - 1) / blocks;
+    return (int)(c < 1 ? 1 : c);
+}
+
 hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_t s) {
     if (total_mbs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(classify_kernel, dim3((total_mbs + 3) / 4), dim3(256), 0, s, jobs, n, total_mbs);
+    int chunk = (flat_chunk(total_mbs, 8) + 3) / 4 * 4;
+    hipLaunchKernelGGL(classify_kernel, dim3((total_mbs + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs,
+                       chunk);
     return hipGetLastError();
 }
 
 hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, unsigned long long *acc, hipStream_t s) {
     if (total_mbs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mc_kernel, dim3((total_mbs + 3) / 4), dim3(256), 0, s, jobs, n, total_mbs, acc);
+    int chunk = (flat_chunk(total_mbs, 8) + 3) / 4 * 4;
+    hipLaunchKernelGGL(mc_kernel, dim3((total_mbs + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk,
+                       acc);
     return hipGetLastError();
 }
 

@@ -9,9 +9,20 @@
 // are handed out by an atomic ticket in the order (h + 2v, chain), which is a
 // topological order of the dependencies, so the ticket holder of the oldest
 // unfinished work never waits on a worker that has not started: the schedule
-// cannot deadlock whatever the residency.  Per-line progress counters (agent
-// scope release/acquire) publish "pairs done".  Every wait is bounded; on
-// timeout a status bit is raised and all workers leave.
+// cannot deadlock whatever the residency.  Per-line progress counters publish
+// "pairs done".  Every wait is bounded; on timeout a status bit is raised and
+// all workers leave.
+//
+// Coherence without cache maintenance.  The only data that crosses workers
+// is the full-pel field mv_int (candidates A, B, C and cross-chain T) and the
+// progress counters.  Both are written and read with device-scope atomic
+// accesses (sc1: performed at the device coherence point, never served from
+// a per-XCD L2 copy), and a producer waits for its mv_int store to complete
+// (s_waitcnt vmcnt(0)) before it stores the counter.  A consumer issues its
+// mv_int loads only after the counter load has returned the awaited value.
+// No acquire/release fences are needed, so no L2 invalidate or write-back is
+// ever issued and the frames stay L2-resident.  Frames, classes and external
+// T fields are read-only during the launch and use ordinary cached loads.
 #include "me_internal.h"
 
 namespace me {
@@ -30,19 +41,28 @@ struct PaArgs {
     KParams kp;
 };
 
-__device__ __forceinline__ uint32_t ld_acquire(const uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ __forceinline__ uint32_t ld_relaxed(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_relaxed(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publish `v` after every earlier store of this wave has completed.
+__device__ __forceinline__ void publish(uint32_t *p, uint32_t v) {
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    st_relaxed(p, v);
 }
 
 __device__ bool wait_ge(const uint32_t *p, uint32_t need, uint32_t *status, int spin_limit) {
     int spins = 0;
     for (;;) {
-        uint32_t v = (uint32_t)uni((int)ld_acquire(p));
-        if (v >= need) return true;
+        uint32_t v = (uint32_t)uni((int)ld_relaxed(p));
+        if (v >= need) {
+            asm volatile("" ::: "memory");  // later loads stay after the counter load
+            return true;
+        }
         if ((spins & 31) == 31 && (uni((int)ld_relaxed(status)) & ST_ABORT)) return false;
         if (++spins > spin_limit) {
             if (lane() == 0) atomicOr(status, ST_SPIN_TIMEOUT | ST_ABORT);
@@ -205,31 +225,16 @@ __device__ __forceinline__ uint32_t pack_mv(int x, int y) { return (uint32_t)(ui
 __device__ __forceinline__ int mvx_full(uint32_t w) { return ((int)(int16_t)(w & 0xFFFF)) >> 1; }
 __device__ __forceinline__ int mvy_full(uint32_t w) { return ((int)(int16_t)(w >> 16)) >> 1; }
 
-// Fig. 1 for MB (h, v) of job J.  (tx, ty): T candidate (full-pel) when
-// `t_reg`; returns the MB's full-pel vector in (tx, ty).
-__device__ void process_mb(const JobDesc &J, int h, int v, bool t_reg, int &tx, int &ty, const int *R,
-                           const KParams &kp, uint32_t *status) {
+// Fig. 1 for the non-transparent MB (h, v) of job J with class `cls`.
+// (tx, ty): T candidate (full-pel) when `t_reg`; returns the MB's full-pel
+// vector in (tx, ty).
+__device__ void process_mb(const JobDesc &J, int h, int v, int cls, bool t_reg, int &tx, int &ty, const int *R,
+                           const KParams &kp) {
     const int l = lane(), j = l >> 2, q = l & 3;
     const int wm = J.wm, k = v * wm + h;
     const int x0 = 16 * h, y0 = 16 * v;
-    int cls = J.cls ? (int)J.cls[k] : ME_MB_OPAQUE;
-    if (cls > 2) {
-        if (l == 0) atomicOr(status, ST_BAD_CLASS);
-        cls = ME_MB_TRANSPARENT;
-    }
     uint32_t *mv = (uint32_t *)J.mv;
     uint32_t *mvi = (uint32_t *)J.mv_int;
-    if (cls == ME_MB_TRANSPARENT) {
-        if (l == 0) {
-            mv[k] = 0u;
-            mvi[k] = 0u;
-            if (J.cost) J.cost[k] = 0u;
-            if (J.iters) J.iters[k] = 0;
-            if (J.points) J.points[k] = 0;
-        }
-        tx = ty = 0;
-        return;
-    }
     Ctx c;
     c.shape = kp.shape_only || cls == ME_MB_BOUNDARY;
     c.Pc = c.shape ? J.cur_a : J.cur;
@@ -349,7 +354,7 @@ __device__ void process_mb(const JobDesc &J, int h, int v, bool t_reg, int &tx, 
     if (kp.half_pel && !c.shape) pts += half_refine(c, kp, dx, dy, hx, hy, dc);
     if (l == 0) {
         mv[k] = pack_mv(hx, hy);
-        mvi[k] = pack_mv(2 * dx, 2 * dy);
+        st_relaxed(mvi + k, pack_mv(2 * dx, 2 * dy));
         if (J.cost) J.cost[k] = (uint32_t)dc;
         if (J.iters) J.iters[k] = (uint8_t)its;
         if (J.points) J.points[k] = (uint16_t)pts;
@@ -384,16 +389,38 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
         for (int p = 0; p < ch.len; ++p) {
             const JobDesc &J = a.jobs[a.chain_jobs[ch.first + p]];
             const uint32_t need = (uint32_t)(p + 1);
+            const int k = v * wm + h;
+            int cls = J.cls ? (int)J.cls[k] : ME_MB_OPAQUE;
+            if (cls > 2) {
+                if (l == 0) atomicOr(a.status, ST_BAD_CLASS);
+                cls = ME_MB_TRANSPARENT;
+            }
+            if (cls == ME_MB_TRANSPARENT) {
+                // no vector is computed: the result depends on nothing, so
+                // it is published without waiting for the neighbours
+                if (l == 0) {
+                    ((uint32_t *)J.mv)[k] = 0u;
+                    st_relaxed((uint32_t *)J.mv_int + k, 0u);
+                    if (J.cost) J.cost[k] = 0u;
+                    if (J.iters) J.iters[k] = 0;
+                    if (J.points) J.points[k] = 0;
+                    publish(a.progress + line, need);
+                }
+                tx = ty = 0;
+                continue;
+            }
+            // A, B and C each waited for directly: a transparent MB publishes
+            // without waiting, so no neighbour's progress implies another's
             bool ok = true;
             if (h > 0) ok = wait_ge(a.progress + line - 1, need, a.status, kp.spin_limit);
-            if (ok && v > 0)
-                ok = wait_ge(a.progress + line - wm + (h + 1 < wm ? 1 : 0), need, a.status, kp.spin_limit);
+            if (ok && v > 0) ok = wait_ge(a.progress + line - wm, need, a.status, kp.spin_limit);
+            if (ok && v > 0 && h + 1 < wm) ok = wait_ge(a.progress + line - wm + 1, need, a.status, kp.spin_limit);
             if (ok && J.dep_line_base >= 0 && !J.t_local)
                 ok = wait_ge(a.progress + J.dep_line_base + v * wm + h, (uint32_t)(J.dep_pos + 1), a.status,
                              kp.spin_limit);
             if (!ok) return;
-            process_mb(J, h, v, J.t_local != 0 && p > 0, tx, ty, R, kp, a.status);
-            if (l == 0) __hip_atomic_store(a.progress + line, need, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            process_mb(J, h, v, cls, J.t_local != 0 && p > 0, tx, ty, R, kp);
+            if (l == 0) publish(a.progress + line, need);
         }
     }
 }

@@ -25,21 +25,25 @@ __device__ __forceinline__ void write_result(const JobDesc &J, int k, int dx, in
 // consecutive dy: every reference row it reads feeds up to kEsG candidate
 // SADs (v_sad_u8 on packed bytes), with the current block held in registers.
 // Key = (SAD, |dx|+|dy|, dy, dx) lexicographic, packed into 64 bits.
-__global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, int n, KParams kp) {
+__global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, int n, int total, int chunk, KParams kp) {
     extern __shared__ uint32_t lds[];
-    const int mb = blockIdx.x;
-    const int ji = find_job(jobs, n, mb);
+    const int first = blockIdx.x * chunk;
+    const int last = min(first + chunk, total);
+    const int tid = threadIdx.x;
+    const int S = kp.S;
+    int ji = first < total ? find_job(jobs, n, first) : 0;
+    for (int mb = first; mb < last; ++mb) {
+    ji = next_job(jobs, n, ji, mb);
     const JobDesc &J = jobs[ji];
     const int k = mb - J.mb_base;
     const int h = k % J.wm, v = k / J.wm;
     const int x0 = 16 * h, y0 = 16 * v, W = J.width, H = J.height, st = J.stride;
-    const int S = kp.S;
-    const int tid = threadIdx.x;
     const int cls = J.cls ? (int)J.cls[k] : ME_MB_OPAQUE;
     if (cls == ME_MB_TRANSPARENT || cls > 2) {
         if (tid == 0) write_result(J, k, 0, 0, 0u, 0);
-        return;
+        continue;
     }
+    __syncthreads();  // the previous MB's readers are done with the window
     const int span = 16 + 2 * S;      // window rows and columns
     const int pd = (span + 3) >> 2;   // dwords per row per copy
     const int csz = span * pd;        // dwords per copy
@@ -52,15 +56,19 @@ __global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, int
         int s = idx / csz, rem = idx - s * csz;
         int r = rem / pd, w = rem - r * pd;
         int yy = wy0 + r;
+        int c0 = 4 * w + s, xx0 = wx0 + c0;
         uint32_t val = 0;
         if (yy >= 0 && yy < H) {
             const uint8_t *row = J.ref + (size_t)yy * st;
+            if (xx0 >= 0 && xx0 + 3 < W && c0 + 3 < span) {
+                val = ld4(row + xx0);
+            } else {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                int c = 4 * w + s + b;
-                int xx = wx0 + c;
-                uint32_t byte = (c < span && xx >= 0 && xx < W) ? row[xx] : 0u;
-                val |= byte << (8 * b);
+                for (int b = 0; b < 4; ++b) {
+                    int c = c0 + b, xx = xx0 + b;
+                    uint32_t byte = (c < span && xx >= 0 && xx < W) ? row[xx] : 0u;
+                    val |= byte << (8 * b);
+                }
             }
         }
         win[idx] = val;
@@ -126,6 +134,7 @@ __global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, int
         int pts = (hix - lox + 1) * (hiy - loy + 1);
         write_result(J, k, dx, dy, (uint32_t)(b >> 32), pts);
     }
+    }
 }
 
 // TSS / DS.  One wave per MB; each round's candidates are evaluated together
@@ -185,10 +194,14 @@ __device__ __forceinline__ void eval_pts(Mb &m, const int (&ox)[N], const int (&
         if (ok[i]) visit(m, ox[i], oy[i]);
 }
 
-__global__ __launch_bounds__(64) void tss_ds_kernel(const JobDesc *jobs, int n, KParams kp, int method) {
+__global__ __launch_bounds__(64) void tss_ds_kernel(const JobDesc *jobs, int n, int total, int chunk, KParams kp,
+                                                    int method) {
     __shared__ uint32_t memo[kMemoWords];
-    const int mb = blockIdx.x;
-    const int ji = find_job(jobs, n, mb);
+    const int first = blockIdx.x * chunk;
+    const int last = min(first + chunk, total);
+    int ji = first < total ? find_job(jobs, n, first) : 0;
+    for (int mb = first; mb < last; ++mb) {
+    ji = next_job(jobs, n, ji, mb);
     const JobDesc &J = jobs[ji];
     const int k = mb - J.mb_base;
     const int h = k % J.wm, v = k / J.wm;
@@ -197,7 +210,7 @@ __global__ __launch_bounds__(64) void tss_ds_kernel(const JobDesc *jobs, int n, 
     const int cls = J.cls ? (int)J.cls[k] : ME_MB_OPAQUE;
     if (cls == ME_MB_TRANSPARENT || cls > 2) {
         if (l == 0) write_result(J, k, 0, 0, 0u, 0);
-        return;
+        continue;
     }
     const int S = kp.S;
     const int words = ((2 * S + 1) * (2 * S + 1) + 31) >> 5;
@@ -300,6 +313,8 @@ __global__ __launch_bounds__(64) void tss_ds_kernel(const JobDesc *jobs, int n, 
         cc = nc;
     }
     if (l == 0) write_result(J, k, cx, cy, cc, m.pts);
+    __syncthreads();
+    }
 }
 
 }  // namespace
@@ -315,9 +330,13 @@ hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_
     if (total_mbs <= 0) return hipSuccess;
     if (method == ME_ES) {
         size_t lds = es_lds_bytes(kp.S);
-        hipLaunchKernelGGL(es_kernel, dim3(total_mbs), dim3(kEsThreads), lds, s, jobs, n, kp);
+        int chunk = flat_chunk(total_mbs, 8);
+        int blocks = (total_mbs + chunk - 1) / chunk;
+        hipLaunchKernelGGL(es_kernel, dim3(blocks), dim3(kEsThreads), lds, s, jobs, n, total_mbs, chunk, kp);
     } else {
-        hipLaunchKernelGGL(tss_ds_kernel, dim3(total_mbs), dim3(64), 0, s, jobs, n, kp, method);
+        int chunk = flat_chunk(total_mbs, 32);
+        int blocks = (total_mbs + chunk - 1) / chunk;
+        hipLaunchKernelGGL(tss_ds_kernel, dim3(blocks), dim3(64), 0, s, jobs, n, total_mbs, chunk, kp, method);
     }
     return hipGetLastError();
 }

@@ -50,6 +50,7 @@ enum : uint32_t { ST_SPIN_TIMEOUT = 1u, ST_BAD_CLASS = 2u, ST_ABORT = 4u };
 // ------------------------------------------------------------- launches
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_t s);
+int flat_chunk(int total_mbs, int per_cu);
 hipError_t launch_pa(const JobDesc *jobs, const ChainDesc *chains, const int32_t *chain_jobs,
                      const uint32_t *tickets, int nlines, uint32_t *progress, uint32_t *counter,
                      uint32_t *status, const KParams &kp, int workers, hipStream_t s);
@@ -113,6 +114,12 @@ __device__ __forceinline__ int find_job(const JobDesc *jobs, int n, int idx) {
         if (jobs[mid].mb_base <= idx) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// Advance the job cursor `ji` to the job holding flat MB `mb` (mb only grows).
+__device__ __forceinline__ int next_job(const JobDesc *jobs, int n, int ji, int mb) {
+    while (ji + 1 < n && jobs[ji + 1].mb_base <= mb) ++ji;
+    return ji;
 }
 
 __device__ __forceinline__ int iclamp(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }

@@ -238,3 +238,26 @@ def test_mc_empty_mask_reports_eempty(torch_cuda):
     jobs = [dv.mc_job(ds.luma[1], ds.luma[0], ds.alpha[0, 1], None, mv)]
     sse, npx, ps, rc = me.me_motion_compensate_psnr(jobs, stream=dv.stream_handle(), check=False)
     assert rc == me.ME_EEMPTY and npx[0] == 0 and math.isnan(ps[0])
+
+
+# ------------------------------------------- full size, repeated launches
+def test_pa_full_bench_workload(torch_cuda):
+    """The benchmark's workload and launch (CIF, 300 frames, two VOPs, all
+    598 pairs in one pipelined call), every output against the oracle."""
+    seq = synth.cif_two_vops(seed=2, frames=300)
+    check_pa(seq, [0, 1], me.me_default_params(search_range=16), 299, label="bench-full")
+
+
+def test_pa_repeat_launches_identical(torch_cuda):
+    """Schedule perturbation: the worker interleaving differs run to run; the
+    result must not."""
+    seq = synth.mixed_streams(seed=11, frames=40, counts=(1, 1, 1))[2]
+    p = me.me_default_params(search_range=16)
+    ds = dseq(seq)
+    gpu_classify(ds)
+    want = {v: oracle_pa(seq, v, p, 39) for v in range(seq.vops)}
+    for rep in range(4):
+        say("repeat", rep, seq.name)
+        got = gpu_pa(ds, list(range(seq.vops)), p, 39)
+        for v in range(seq.vops):
+            assert_same(got[v], want[v], f"rep {rep} vop {v}")
