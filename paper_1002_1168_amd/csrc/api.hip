@@ -97,9 +97,10 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // Copy `blob` to the start of the device arena (skipped when the arena still
 // holds exactly these bytes) and zero `zero_bytes` after it.  Returns the
 // arena base in *base and the zeroed region in *zero.
-int upload(Workspace &w, const std::vector<uint8_t> &blob, size_t zero_bytes, uint8_t **base, uint8_t **zero) {
+int upload(Workspace &w, const std::vector<uint8_t> &blob, size_t zero_bytes, uint8_t **base, uint8_t **zero,
+           size_t scratch_bytes = 0, uint8_t **scratch = nullptr) {
     size_t off = align_up(blob.size(), 256);
-    size_t need = off + align_up(zero_bytes, 256) + 256;
+    size_t need = off + align_up(zero_bytes, 256) + align_up(scratch_bytes, 256) + 256;
     if (need > w.cap) {
         if (w.dev) {
             if (hipStreamSynchronize(w.stream) != hipSuccess) return ME_EHIP;
@@ -137,6 +138,7 @@ int upload(Workspace &w, const std::vector<uint8_t> &blob, size_t zero_bytes, ui
     }
     *base = w.dev;
     *zero = w.dev + off;
+    if (scratch) *scratch = w.dev + off + align_up(zero_bytes, 256);
     if (zero_bytes) {
         int rc = hip_err(launch_fill_u32((uint32_t *)(w.dev + off), align_up(zero_bytes, 4) / 4, 0u, w.stream));
         if (rc) return rc;
@@ -278,21 +280,34 @@ int run_pa(const me_job *jobs, int n, const me_params *params, bool shape_only, 
     }
     const int nc = (int)chains.size();
     if (nc > kMaxChains) return ME_EINVAL;
+    // descriptors in chain order: chain c's pair p at cd[c].first + p
     std::vector<ChainDesc> cd(nc);
-    std::vector<int32_t> cj;
-    cj.reserve(n);
+    std::vector<JobDesc> ordered;
+    ordered.reserve(n);
     long long nlines = 0;
     int maxkey = 0;
+    int maxlen = 0;
+    long long total_mbs = 0;
     for (int c = 0; c < nc; ++c) {
         const JobDesc &d0 = desc[chains[c][0]];
-        cd[c] = ChainDesc{(int32_t)cj.size(), (int32_t)chains[c].size(), d0.wm, d0.hm, (int32_t)nlines, {0, 0, 0}};
-        for (int i : chains[c]) cj.push_back(i);
+        cd[c] = ChainDesc{(int32_t)ordered.size(), (int32_t)chains[c].size(), d0.wm, d0.hm, (int32_t)nlines, {0, 0, 0}};
+        int pos = 0;
+        for (int i : chains[c]) {
+            ordered.push_back(desc[i]);
+            JobDesc &d = ordered.back();
+            d.chain_line_base = (int32_t)nlines;
+            d.chain_pos = pos++;
+            d.mb_base = (int32_t)total_mbs;
+            total_mbs += (long long)d.wm * d.hm;
+        }
         nlines += (long long)d0.wm * d0.hm;
         maxkey = std::max(maxkey, (d0.wm - 1) + 2 * (d0.hm - 1));
+        maxlen = std::max(maxlen, (int)chains[c].size());
     }
+    if (total_mbs > (1ll << 30)) return ME_EINVAL;
     if (nlines > (1ll << 30)) return ME_EINVAL;
-    for (int i = 0; i < n; ++i)
-        if (desc[i].dep_line_base <= -2) desc[i].dep_line_base = cd[-2 - desc[i].dep_line_base].line_base;
+    for (auto &d : ordered)
+        if (d.dep_line_base <= -2) d.dep_line_base = cd[-2 - d.dep_line_base].line_base;
     // tickets in the order (h + 2v, chain): counting sort on the key
     std::vector<uint32_t> cnt(maxkey + 2, 0);
     for (int c = 0; c < nc; ++c)
@@ -310,21 +325,25 @@ int run_pa(const me_job *jobs, int n, const me_params *params, bool shape_only, 
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(w->mu);
     std::vector<uint8_t> blob;
-    size_t o_jobs = put(blob, desc.data(), desc.size());
+    size_t o_jobs = put(blob, ordered.data(), ordered.size());
     size_t o_ch = put(blob, cd.data(), cd.size());
-    size_t o_cj = put(blob, cj.data(), cj.size());
     size_t o_tk = put(blob, tickets.data(), tickets.size());
-    size_t zero = align_up((size_t)nlines * 4, 256) + 256;
+    // zeroed scratch: progress words, ticket counter, transparent and
+    // boundary masks (one bit per pair, 32 pairs per word, per line)
+    const int mask_words = (maxlen + 31) / 32;
+    const size_t o_prog = 0;
+    const size_t o_ctr = align_up((size_t)nlines * 8, 256);
+    const size_t o_mask = o_ctr + 256;
+    const size_t zero = o_mask + align_up((size_t)nlines * mask_words * 2 * 4, 256);
     uint8_t *base = nullptr, *zb = nullptr;
     rc = upload(*w, blob, zero, &base, &zb);
     if (rc) return rc;
-    uint32_t *progress = (uint32_t *)zb;
-    uint32_t *counter = (uint32_t *)(zb + align_up((size_t)nlines * 4, 256));
     int workers = (int)std::min<long long>(nlines, pa_worker_cap());
     KParams kp = kparams(params, shape_only);
-    return hip_err(launch_pa((const JobDesc *)(base + o_jobs), (const ChainDesc *)(base + o_ch),
-                             (const int32_t *)(base + o_cj), (const uint32_t *)(base + o_tk), (int)nlines,
-                             progress, counter, w->status, kp, workers, w->stream));
+    return hip_err(launch_pa((const JobDesc *)(base + o_jobs), n, (int)total_mbs, (const ChainDesc *)(base + o_ch),
+                             (const uint32_t *)(base + o_tk), (int)nlines, (unsigned long long *)(zb + o_prog),
+                             (uint32_t *)(zb + o_ctr), (uint32_t *)(zb + o_mask), mask_words, w->status, kp, workers,
+                             w->stream));
 }
 
 }  // namespace
@@ -442,6 +461,7 @@ int me_full_search(int method, const me_job *jobs, int n, const me_params *param
     }
     if (total > (1ll << 30)) return ME_EINVAL;
     if (n == 0) return ME_OK;
+    if (n > 65536) return ME_EINVAL;  // queue entries pack the job index in 16 bits
     if (method == ME_ES) {
         int dev = 0, lim = 0;
         if (hipGetDevice(&dev) != hipSuccess) return ME_ENODEV;
@@ -455,11 +475,12 @@ int me_full_search(int method, const me_job *jobs, int n, const me_params *param
     std::lock_guard<std::mutex> lk(w->mu);
     std::vector<uint8_t> blob;
     size_t o = put(blob, desc.data(), desc.size());
-    uint8_t *base = nullptr, *zb = nullptr;
-    rc = upload(*w, blob, 0, &base, &zb);
+    uint8_t *base = nullptr, *zb = nullptr, *sb = nullptr;
+    rc = upload(*w, blob, 256, &base, &zb, full_search_scratch((int)total), &sb);
     if (rc) return rc;
     KParams kp = kparams(params, false);
-    return hip_err(launch_full_search(method, (const JobDesc *)(base + o), n, (int)total, kp, w->status, w->stream));
+    return hip_err(launch_full_search(method, (const JobDesc *)(base + o), n, (int)total, kp, (uint32_t *)zb,
+                                      (uint32_t *)sb, w->stream));
 }
 
 int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, uint64_t *sse, uint64_t *npix,

@@ -9,20 +9,29 @@
 // are handed out by an atomic ticket in the order (h + 2v, chain), which is a
 // topological order of the dependencies, so the ticket holder of the oldest
 // unfinished work never waits on a worker that has not started: the schedule
-// cannot deadlock whatever the residency.  Per-line progress counters publish
-// "pairs done".  Every wait is bounded; on timeout a status bit is raised and
-// all workers leave.
+// cannot deadlock whatever the residency.  Every wait is bounded; on timeout
+// a status bit is raised and all workers leave.
 //
-// Coherence without cache maintenance.  The only data that crosses workers
-// is the full-pel field mv_int (candidates A, B, C and cross-chain T) and the
-// progress counters.  Both are written and read with device-scope atomic
-// accesses (sc1: performed at the device coherence point, never served from
-// a per-XCD L2 copy), and a producer waits for its mv_int store to complete
-// (s_waitcnt vmcnt(0)) before it stores the counter.  A consumer issues its
-// mv_int loads only after the counter load has returned the awaited value.
-// No acquire/release fences are needed, so no L2 invalidate or write-back is
-// ever issued and the frames stay L2-resident.  Frames, classes and external
-// T fields are read-only during the launch and use ordinary cached loads.
+// Coherence without cache maintenance.  Each line owns one 64-bit progress
+// word: the number of pairs done in the low half and the full-pel vector of
+// the latest one in the high half, stored by a single device-scope atomic.
+// A consumer that needs pair p of a neighbour polls the word; when it reads
+// exactly p+1 the vector comes with it, when the neighbour has moved on the
+// vector is read from that pair's mv_int array.  A producer publishes pair p
+// and only then writes pair p's result arrays; it waits for all its earlier
+// stores to complete (s_waitcnt) before every publish, so arrays of pairs
+// < p are complete whenever the word says p+1.  All these accesses are
+// device-scope atomics (sc1: served at the device coherence point, never from
+// a per-XCD L2 copy), so no L2 invalidate or write-back is ever issued and the
+// read-only frames stay L2-resident.  A neighbour that is transparent in the
+// pair contributes (0, 0) and is not waited for.
+//
+// Data path.  Before polling, the worker stages the reference plane around
+// its MB, rows and columns [-S-1, 16+S] with coordinates clamped to the frame
+// (the clamped central differences of Eq. 5 then need no edge logic), into
+// LDS; the poll and the staging loads are in flight together.  The candidate
+// costs and every gradient pass then read LDS only.  Lane = (row j, quad q)
+// holds 4 pixels; block sums use DPP wave reductions.
 #include "me_internal.h"
 
 namespace me {
@@ -30,15 +39,19 @@ namespace me {
 namespace {
 
 struct PaArgs {
-    const JobDesc *jobs;
+    const JobDesc *jobs;  // in chain order: chain c's pair p is jobs[chains[c].first + p]
     const ChainDesc *chains;
-    const int32_t *chain_jobs;
     const uint32_t *tickets;
     int nlines;
-    uint32_t *progress;
+    unsigned long long *progress;
     uint32_t *counter;
+    const uint32_t *tmask;  // per line, per 32 pairs: bit set = MB transparent in that pair
+    const uint32_t *bmask;  // per line, per 32 pairs: bit set = MB scored on its alpha block
+    int mw;                 // mask words per line
     uint32_t *status;
     KParams kp;
+    int pitch;  // window row pitch in bytes (multiple of 4)
+    int rows;   // window rows = columns = 2S + 18
 };
 
 __device__ __forceinline__ uint32_t ld_relaxed(const uint32_t *p) {
@@ -49,61 +62,164 @@ __device__ __forceinline__ void st_relaxed(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Publish `v` after every earlier store of this wave has completed.
-__device__ __forceinline__ void publish(uint32_t *p, uint32_t v) {
-    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
-    st_relaxed(p, v);
+__device__ __forceinline__ unsigned long long ld64(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ bool wait_ge(const uint32_t *p, uint32_t need, uint32_t *status, int spin_limit) {
-    int spins = 0;
-    for (;;) {
-        uint32_t v = (uint32_t)uni((int)ld_relaxed(p));
-        if (v >= need) {
-            asm volatile("" ::: "memory");  // later loads stay after the counter load
-            return true;
+// Publish (pairs done, vector of the latest pair) after every earlier
+// memory access of this wave has completed.
+__device__ __forceinline__ void publish(unsigned long long *p, uint32_t done, uint32_t mvi) {
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    __hip_atomic_store(p, ((unsigned long long)mvi << 32) | done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t pack_mv(int x, int y) { return (uint32_t)(uint16_t)x | ((uint32_t)(uint16_t)y << 16); }
+__device__ __forceinline__ int mvx_full(uint32_t w) { return ((int)(int16_t)(w & 0xFFFF)) >> 1; }
+__device__ __forceinline__ int mvy_full(uint32_t w) { return ((int)(int16_t)(w >> 16)) >> 1; }
+
+// Vector of pair `need-1` of a line whose progress word is `w`: carried by the
+// word when the line is exactly there, else read from that pair's array.
+__device__ __forceinline__ uint32_t mv_of(unsigned long long w, uint32_t need, const uint32_t *arr) {
+    if ((uint32_t)w == need) return (uint32_t)(w >> 32);
+    return (uint32_t)uni((int)ld_relaxed(arr));
+}
+
+// ---------------------------------------------------------------- window
+// Window byte (r, c) = plane(clamp(y0-S-1+r), clamp(x0-S-1+c)), binarised
+// (0/255) for shape MBs.  Branch-free: every lane loads an in-frame dword at
+// the clamped column and, at the frame edge, replicates the edge bytes with a
+// byte permute.  Loads are issued twelve at a time (one round trip for a
+// +-16 window), not one per dword.
+__device__ __forceinline__ void stage_window(uint32_t *win, int pitch, int rows, const uint8_t *P, int st, int W,
+                                             int H, int x0, int y0, int S, bool shape) {
+    const int l = lane();
+    const int dw = pitch >> 2, total = rows * dw;
+    const int wx0 = x0 - S - 1, wy0 = y0 - S - 1;
+    int r = l / dw, c = l - (l / dw) * dw;
+    const int dr = 64 / dw, dc = 64 - (64 / dw) * dw;
+    constexpr int kB = 12;
+    for (int base = 0; base < total; base += kB * 64) {
+        uint32_t v[kB], sel[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const int rr = iclamp(wy0 + r, 0, H - 1);
+            const int xx = wx0 + 4 * c;
+            const int xc = iclamp(xx, 0, W - 4);
+            sel[u] = (uint32_t)(iclamp(xx, 0, W - 1) - xc) | ((uint32_t)(iclamp(xx + 1, 0, W - 1) - xc) << 8) |
+                     ((uint32_t)(iclamp(xx + 2, 0, W - 1) - xc) << 16) | ((uint32_t)(iclamp(xx + 3, 0, W - 1) - xc) << 24);
+            v[u] = ld4(P + (size_t)rr * st + xc);  // clamped: in frame even past the window end
+            r += dr;
+            c += dc;
+            if (c >= dw) {
+                c -= dw;
+                r += 1;
+            }
         }
-        if ((spins & 31) == 31 && (uni((int)ld_relaxed(status)) & ST_ABORT)) return false;
-        if (++spins > spin_limit) {
-            if (lane() == 0) atomicOr(status, ST_SPIN_TIMEOUT | ST_ABORT);
-            return false;
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const int i = base + u * 64 + l;
+            uint32_t x = __builtin_amdgcn_perm(v[u], v[u], sel[u]);
+            if (i < total) win[i] = shape ? bin4(x) : x;
         }
-        __builtin_amdgcn_s_sleep(2);
     }
+}
+
+// Per-lane staging plan of a line's window: the window geometry is the same
+// for every pair of the line, so each lane's dword positions (clamped frame
+// row and column) and edge byte selectors are computed once per line.  A
+// pair then costs one load, one permute and one LDS write per element, and
+// the loads of the next pair's window can be in flight during this pair's
+// search.  EM = elements per lane (window dwords / 64, rounded up).
+template <int EM>
+struct Plan {
+    uint32_t loc[EM];  // clamped frame row << 16 | clamped column of the dword
+    uint32_t sel[EM];  // byte selectors replicating the frame edge
+    int total;
+
+    __device__ __forceinline__ void init(int pitch, int rows, int x0, int y0, int S, int W, int H) {
+        const int l = lane();
+        const int dw = pitch >> 2;
+        total = rows * dw;
+        const int wx0 = x0 - S - 1, wy0 = y0 - S - 1;
+#pragma unroll
+        for (int u = 0; u < EM; ++u) {
+            const int i = u * 64 + l;
+            const int r = i < total ? i / dw : 0, c = i < total ? i - (i / dw) * dw : 0;
+            const int rr = iclamp(wy0 + r, 0, H - 1);
+            const int xx = wx0 + 4 * c;
+            const int xc = iclamp(xx, 0, W - 4);
+            loc[u] = ((uint32_t)rr << 16) | (uint32_t)xc;
+            sel[u] = (uint32_t)(iclamp(xx, 0, W - 1) - xc) | ((uint32_t)(iclamp(xx + 1, 0, W - 1) - xc) << 8) |
+                     ((uint32_t)(iclamp(xx + 2, 0, W - 1) - xc) << 16) |
+                     ((uint32_t)(iclamp(xx + 3, 0, W - 1) - xc) << 24);
+        }
+    }
+    // loads only; every address is in frame, elements past the window
+    // re-read the window origin and are never written
+    __device__ __forceinline__ void issue(const uint8_t *P, int st, uint32_t (&v)[EM]) const {
+#pragma unroll
+        for (int u = 0; u < EM; ++u) v[u] = ld4(P + (size_t)(loc[u] >> 16) * st + (loc[u] & 0xFFFFu));
+    }
+    __device__ __forceinline__ void write(uint32_t *win, const uint32_t (&v)[EM], bool shape) const {
+        const int l = lane();
+#pragma unroll
+        for (int u = 0; u < EM; ++u) {
+            const int i = u * 64 + l;
+            const uint32_t x = __builtin_amdgcn_perm(v[u], v[u], sel[u]);
+            if (i < total) win[i] = shape ? bin4(x) : x;
+        }
+    }
+};
+
+// 4 window bytes starting at byte offset `off` (any alignment).
+__device__ __forceinline__ uint32_t lds4(const uint32_t *win, int off) {
+    const uint32_t a = win[off >> 2], b = win[(off >> 2) + 1];
+    return __builtin_amdgcn_alignbyte(b, a, off & 3);
+}
+
+// 8 window bytes starting at byte offset `off` (lo = bytes 0..3, hi = 4..7).
+__device__ __forceinline__ void lds8(const uint32_t *win, int off, uint32_t &lo, uint32_t &hi) {
+    const uint32_t a = win[off >> 2], b = win[(off >> 2) + 1], c = win[(off >> 2) + 2];
+    lo = __builtin_amdgcn_alignbyte(b, a, off & 3);
+    hi = __builtin_amdgcn_alignbyte(c, b, off & 3);
 }
 
 struct Sweep {
     int sad, sx, sy, nxy;  // nxy = nx | ny << 16
 };
 
+struct Ctx {
+    const uint32_t *win;
+    const short *R;
+    int pitch, S;
+    int off0;          // window byte offset of this lane's first pixel at d = 0
+    int x0, y0, W, H;
+    uint32_t c4;       // this lane's 4 current pixels
+    bool shape;
+    int lox, hix, loy, hiy;
+};
+
+__device__ __forceinline__ int cost_of(const Ctx &c, int sad) { return c.shape ? sad / 255 : sad; }
+
 // One fused pass at full-pel offset (dx, dy): SAD of the block and the
-// gradient sums of Eqs. 3-5 (reference central differences at the displaced
-// position, coordinates clamped to the frame).  Lane = (row j, quad q).
-__device__ __forceinline__ Sweep sweep(const uint8_t *Pr, int st, int W, int H, int x, int y, int dx, int dy,
-                                       uint32_t c4, bool shape, const int *R) {
-    const int rx = x + dx, ry = y + dy;
-    const uint8_t *row = Pr + (size_t)ry * st;
-    uint32_t m = ld4(row + rx);
-    int lf = row[rx > 0 ? rx - 1 : 0];
-    int rt = row[rx + 4 < W ? rx + 4 : W - 1];
-    uint32_t up = ld4(Pr + (size_t)(ry > 0 ? ry - 1 : 0) * st + rx);
-    uint32_t dn = ld4(Pr + (size_t)(ry + 1 < H ? ry + 1 : H - 1) * st + rx);
-    if (shape) {
-        m = bin4(m);
-        up = bin4(up);
-        dn = bin4(dn);
-        lf = lf ? 255 : 0;
-        rt = rt ? 255 : 0;
-    }
-    int sad = (int)__builtin_amdgcn_sad_u8(c4, m, 0u);
+// gradient sums of Eqs. 3-5 (central differences of the reference at the
+// displaced position).
+__device__ __forceinline__ Sweep sweep(const Ctx &c, int dx, int dy) {
+    const int off = c.off0 + dy * c.pitch + dx;
+    uint32_t lo, hi;
+    lds8(c.win, off - 1, lo, hi);                 // bytes rx-1 .. rx+6
+    const uint32_t m = __builtin_amdgcn_alignbyte(hi, lo, 1);
+    const int lf = (int)(lo & 0xFF), rt = (int)((hi >> 8) & 0xFF);
+    const uint32_t up = lds4(c.win, off - c.pitch), dn = lds4(c.win, off + c.pitch);
+    int sad = (int)__builtin_amdgcn_sad_u8(c.c4, m, 0u);
     int sx = 0, sy = 0, nn = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        int e = byte_of(c4, k) - byte_of(m, k);
-        int left = k == 0 ? lf : byte_of(m, k - 1);
-        int right = k == 3 ? rt : byte_of(m, k + 1);
-        int rgx = R[right - left + 255];
-        int rgy = R[byte_of(dn, k) - byte_of(up, k) + 255];
+        const int e = byte_of(c.c4, k) - byte_of(m, k);
+        const int left = k == 0 ? lf : byte_of(m, k - 1);
+        const int right = k == 3 ? rt : byte_of(m, k + 1);
+        const int rgx = c.R[right - left + 255];
+        const int rgy = c.R[byte_of(dn, k) - byte_of(up, k) + 255];
         sx += e * rgx;
         sy += e * rgy;
         nn += (rgx != 0) + ((rgy != 0) << 16);
@@ -116,35 +232,23 @@ __device__ __forceinline__ Sweep sweep(const uint8_t *Pr, int st, int W, int H, 
     return s;
 }
 
-struct Ctx {
-    const uint8_t *Pc, *Pr;
-    int st, W, H, x, y;  // x, y: this lane's first pixel
-    int x0, y0;
-    uint32_t c4;
-    bool shape;
-    const int *R;
-    int lox, hix, loy, hiy;
-};
-
-__device__ __forceinline__ int cost_of(const Ctx &c, int sad) { return c.shape ? sad / 255 : sad; }
-
 // Section 3.2 recursion from (dx, dy) with distortion `cost` and pass `sw`
 // at that point.  Returns the number of candidates evaluated.
 __device__ int pel_recursion(const Ctx &c, const KParams &kp, int &dx, int &dy, int &cost, Sweep sw) {
     int it = 0;
     while (it < kp.k_max) {
-        int nx = sw.nxy & 0xFFFF, ny = sw.nxy >> 16;
-        int ux = nx ? sw.sx / nx : 0;
-        int uy = ny ? sw.sy / ny : 0;
-        int sx = prs_step(ux, kp.eps, kp.max_step);
-        int sy = prs_step(uy, kp.eps, kp.max_step);
+        const int nx = sw.nxy & 0xFFFF, ny = sw.nxy >> 16;
+        const int ux = nx ? sw.sx / nx : 0;
+        const int uy = ny ? sw.sy / ny : 0;
+        const int sx = prs_step(ux, kp.eps, kp.max_step);
+        const int sy = prs_step(uy, kp.eps, kp.max_step);
         if (sx == 0 && sy == 0) break;
-        int tx = iclamp(dx + sx, c.lox, c.hix);
-        int ty = iclamp(dy + sy, c.loy, c.hiy);
+        const int tx = iclamp(dx + sx, c.lox, c.hix);
+        const int ty = iclamp(dy + sy, c.loy, c.hiy);
         if (tx == dx && ty == dy) break;
         ++it;
-        Sweep s2 = sweep(c.Pr, c.st, c.W, c.H, c.x, c.y, tx, ty, c.c4, c.shape, c.R);
-        int c2 = cost_of(c, s2.sad);
+        const Sweep s2 = sweep(c, tx, ty);
+        const int c2 = cost_of(c, s2.sad);
         if (c2 < cost) {
             dx = tx;
             dy = ty;
@@ -163,18 +267,19 @@ constexpr int kHalfX[8] = {-1, 0, 1, -1, 1, -1, 0, 1};
 constexpr int kHalfY[8] = {-1, -1, -1, 0, 0, 1, 1, 1};
 
 // Half-sample refinement around the full-pel vector d (MPEG-4 bilinear,
-// rounding control 0).  Updates (hx, hy), cost; returns feasible count.
+// rounding control 0).  Updates (hx, hy), cost; returns the feasible count.
 __device__ int half_refine(const Ctx &c, const KParams &kp, int dx, int dy, int &hx, int &hy, int &cost) {
-    const int W = c.W, H = c.H, st = c.st;
-    // 3 x 6 neighbourhood: rows ry-1..ry+1, columns rx-1..rx+4 (clamped)
+    // 3 x 6 neighbourhood: rows ry-1..ry+1, columns rx-1..rx+4
     int nb[3][6];
-    const int rx = c.x + dx, ry = c.y + dy;
+    const int off = c.off0 + dy * c.pitch + dx;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-        int yy = iclamp(ry - 1 + r, 0, H - 1);
-        const uint8_t *row = c.Pr + (size_t)yy * st;
+        uint32_t lo, hi;
+        lds8(c.win, off + (r - 1) * c.pitch - 1, lo, hi);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) nb[r][q] = row[iclamp(rx - 1 + q, 0, W - 1)];
+        for (int q = 0; q < 4; ++q) nb[r][q] = byte_of(lo, q);
+        nb[r][4] = byte_of(hi, 0);
+        nb[r][5] = byte_of(hi, 1);
     }
     int part[8];
     bool feas[8];
@@ -186,15 +291,16 @@ __device__ int half_refine(const Ctx &c, const KParams &kp, int dx, int dy, int 
         const int oxr = ox < 0 ? 0 : 1, oyr = oy < 0 ? 0 : 1;  // neighbourhood origin of A
         const int qx = 2 * dx + ox, qy = 2 * dy + oy;
         const int ix = dx + (ox < 0 ? -1 : 0), iy = dy + (oy < 0 ? -1 : 0);
-        feas[o] = abs(qx) <= 2 * kp.S && abs(qy) <= 2 * kp.S && c.x0 + ix >= 0 && c.x0 + ix + 15 + fx <= W - 1 &&
-                  c.y0 + iy >= 0 && c.y0 + iy + 15 + fy <= H - 1;
+        feas[o] = abs(qx) <= 2 * kp.S && abs(qy) <= 2 * kp.S && c.x0 + ix >= 0 && c.x0 + ix + 15 + fx <= c.W - 1 &&
+                  c.y0 + iy >= 0 && c.y0 + iy + 15 + fy <= c.H - 1;
         nfeas += feas[o];
         int s = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            int A = nb[oyr][oxr + k], B = nb[oyr][oxr + k + 1];
-            int Cc = nb[oyr + 1][oxr + k], D = nb[oyr + 1][oxr + k + 1];
-            int p = (fx && fy) ? ((A + B + Cc + D + 2) >> 2) : fx ? ((A + B + 1) >> 1) : fy ? ((A + Cc + 1) >> 1) : A;
+            const int A = nb[oyr][oxr + k], B = nb[oyr][oxr + k + 1];
+            const int Cc = nb[oyr + 1][oxr + k], D = nb[oyr + 1][oxr + k + 1];
+            const int p = (fx && fy) ? ((A + B + Cc + D + 2) >> 2)
+                                     : fx ? ((A + B + 1) >> 1) : fy ? ((A + Cc + 1) >> 1) : A;
             s += abs(byte_of(c.c4, k) - p);
         }
         part[o] = s;
@@ -202,7 +308,7 @@ __device__ int half_refine(const Ctx &c, const KParams &kp, int dx, int dy, int 
     int tot[8];
 #pragma unroll
     for (int o = 0; o < 8; o += 2) {
-        int pk = wave_sum(part[o] | (part[o + 1] << 16));
+        const int pk = wave_sum(part[o] | (part[o + 1] << 16));
         tot[o] = pk & 0xFFFF;
         tot[o + 1] = (int)((uint32_t)pk >> 16);
     }
@@ -221,67 +327,15 @@ __device__ int half_refine(const Ctx &c, const KParams &kp, int dx, int dy, int 
     return nfeas;
 }
 
-__device__ __forceinline__ uint32_t pack_mv(int x, int y) { return (uint32_t)(uint16_t)x | ((uint32_t)(uint16_t)y << 16); }
-__device__ __forceinline__ int mvx_full(uint32_t w) { return ((int)(int16_t)(w & 0xFFFF)) >> 1; }
-__device__ __forceinline__ int mvy_full(uint32_t w) { return ((int)(int16_t)(w >> 16)) >> 1; }
+struct MbOut {
+    uint32_t mv, mvi, cost;
+    int iters, points, dx, dy;
+};
 
-// Fig. 1 for the non-transparent MB (h, v) of job J with class `cls`.
-// (tx, ty): T candidate (full-pel) when `t_reg`; returns the MB's full-pel
-// vector in (tx, ty).
-__device__ void process_mb(const JobDesc &J, int h, int v, int cls, bool t_reg, int &tx, int &ty, const int *R,
-                           const KParams &kp) {
-    const int l = lane(), j = l >> 2, q = l & 3;
-    const int wm = J.wm, k = v * wm + h;
-    const int x0 = 16 * h, y0 = 16 * v;
-    uint32_t *mv = (uint32_t *)J.mv;
-    uint32_t *mvi = (uint32_t *)J.mv_int;
-    Ctx c;
-    c.shape = kp.shape_only || cls == ME_MB_BOUNDARY;
-    c.Pc = c.shape ? J.cur_a : J.cur;
-    c.Pr = c.shape ? J.ref_a : J.ref;
-    c.st = J.stride;
-    c.W = J.width;
-    c.H = J.height;
-    c.x0 = x0;
-    c.y0 = y0;
-    c.x = x0 + 4 * q;
-    c.y = y0 + j;
-    c.R = R;
-    const int S = kp.S;
-    c.lox = max(-S, -x0);
-    c.hix = min(S, c.W - 16 - x0);
-    c.loy = max(-S, -y0);
-    c.hiy = min(S, c.H - 16 - y0);
-    uint32_t c4 = *(const uint32_t *)(c.Pc + (size_t)c.y * c.st + c.x);
-    c.c4 = c.shape ? bin4(c4) : c4;
-
-    // candidates A, B, C, T (neighbours outside the grid: (0, 0))
-    int cx[4] = {0, 0, 0, 0}, cy[4] = {0, 0, 0, 0};
-    if (h > 0) {
-        uint32_t w = (uint32_t)uni((int)ld_relaxed(mvi + k - 1));
-        cx[0] = mvx_full(w);
-        cy[0] = mvy_full(w);
-    }
-    if (v > 0) {
-        uint32_t w = (uint32_t)uni((int)ld_relaxed(mvi + k - wm));
-        cx[1] = mvx_full(w);
-        cy[1] = mvy_full(w);
-        if (h + 1 < wm) {
-            uint32_t w2 = (uint32_t)uni((int)ld_relaxed(mvi + k - wm + 1));
-            cx[2] = mvx_full(w2);
-            cy[2] = mvy_full(w2);
-        }
-    }
-    if (t_reg) {
-        cx[3] = tx;
-        cy[3] = ty;
-    } else if (J.tf) {
-        uint32_t w = (uint32_t)uni((int)ld_relaxed((const uint32_t *)J.tf + k));
-        cx[3] = mvx_full(w);
-        cy[3] = mvy_full(w);
-    }
-    // admissible and distinct, in the order A, B, C, T (compile-time indices
-    // only, so the list lives in registers)
+// Fig. 1 after the candidates are known: the admissible distinct list in the
+// order A, B, C, T, its first minimum, the recursion (from a learned seed
+// with the 5 % fallback when the job carries seeds), half-sample refinement.
+__device__ MbOut search_mb(const uint32_t *seed, const Ctx &c, int k, int (&cx)[4], int (&cy)[4], const KParams &kp) {
     bool keep[4];
     int n = 0;
 #pragma unroll
@@ -300,21 +354,16 @@ __device__ void process_mb(const JobDesc &J, int h, int v, int cls, bool t_reg, 
     // block costs of the list, two 16-bit partial SADs per reduction
     int part[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        if (keep[i]) {
-            uint32_t r4 = ld4(c.Pr + (size_t)(c.y + cy[i]) * c.st + c.x + cx[i]);
-            if (c.shape) r4 = bin4(r4);
-            part[i] = (int)__builtin_amdgcn_sad_u8(c.c4, r4, 0u);
-        }
-    }
-    int p01 = wave_sum(part[0] | (part[1] << 16));
-    int p23 = (keep[2] || keep[3]) ? wave_sum(part[2] | (part[3] << 16)) : 0;
-    int costs[4] = {p01 & 0xFFFF, (int)((uint32_t)p01 >> 16), p23 & 0xFFFF, (int)((uint32_t)p23 >> 16)};
+    for (int i = 0; i < 4; ++i)
+        if (keep[i]) part[i] = (int)__builtin_amdgcn_sad_u8(c.c4, lds4(c.win, c.off0 + cy[i] * c.pitch + cx[i]), 0u);
+    const int p01 = wave_sum(part[0] | (part[1] << 16));
+    const int p23 = (keep[2] || keep[3]) ? wave_sum(part[2] | (part[3] << 16)) : 0;
+    const int costs[4] = {p01 & 0xFFFF, (int)((uint32_t)p01 >> 16), p23 & 0xFFFF, (int)((uint32_t)p23 >> 16)};
     // Min[...]: the first minimum in list order
     int dx = 0, dy = 0, bc = 0x7FFFFFFF;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        int ci = cost_of(c, costs[i]);
+        const int ci = cost_of(c, costs[i]);
         if (keep[i] && ci < bc) {
             bc = ci;
             dx = cx[i];
@@ -323,19 +372,18 @@ __device__ void process_mb(const JobDesc &J, int h, int v, int cls, bool t_reg, 
     }
     int dc = bc;
     int pts = n, its = 0;
-    if (J.seed && !c.shape) {
-        uint32_t w = (uint32_t)uni((int)ld_relaxed((const uint32_t *)J.seed + k));
+    if (seed && !c.shape) {
+        const uint32_t w = (uint32_t)uni((int)ldg32(seed + k));
         int sx = iclamp(mvx_full(w), c.lox, c.hix), sy = iclamp(mvy_full(w), c.loy, c.hiy);
-        Sweep sw = sweep(c.Pr, c.st, c.W, c.H, c.x, c.y, sx, sy, c.c4, c.shape, c.R);
+        const Sweep sw = sweep(c, sx, sy);
         int sc = cost_of(c, sw.sad);
         pts += 1;
-        int it1 = pel_recursion(c, kp, sx, sy, sc, sw);
+        const int it1 = pel_recursion(c, kp, sx, sy, sc, sw);
         its += it1;
         pts += it1;
         if (20ll * sc > 21ll * bc) {
             if (kp.k_max > 0) {
-                Sweep s0 = sweep(c.Pr, c.st, c.W, c.H, c.x, c.y, dx, dy, c.c4, c.shape, c.R);
-                int it2 = pel_recursion(c, kp, dx, dy, dc, s0);
+                const int it2 = pel_recursion(c, kp, dx, dy, dc, sweep(c, dx, dy));
                 its += it2;
                 pts += it2;
             }
@@ -345,84 +393,301 @@ __device__ void process_mb(const JobDesc &J, int h, int v, int cls, bool t_reg, 
             dc = sc;
         }
     } else if (kp.k_max > 0) {
-        Sweep s0 = sweep(c.Pr, c.st, c.W, c.H, c.x, c.y, dx, dy, c.c4, c.shape, c.R);
-        int it1 = pel_recursion(c, kp, dx, dy, dc, s0);
+        const int it1 = pel_recursion(c, kp, dx, dy, dc, sweep(c, dx, dy));
         its += it1;
         pts += it1;
     }
     int hx = 2 * dx, hy = 2 * dy;
     if (kp.half_pel && !c.shape) pts += half_refine(c, kp, dx, dy, hx, hy, dc);
-    if (l == 0) {
-        mv[k] = pack_mv(hx, hy);
-        st_relaxed(mvi + k, pack_mv(2 * dx, 2 * dy));
-        if (J.cost) J.cost[k] = (uint32_t)dc;
-        if (J.iters) J.iters[k] = (uint8_t)its;
-        if (J.points) J.points[k] = (uint16_t)pts;
-    }
-    tx = dx;
-    ty = dy;
+    MbOut o;
+    o.mv = pack_mv(hx, hy);
+    o.mvi = pack_mv(2 * dx, 2 * dy);
+    o.cost = (uint32_t)dc;
+    o.iters = its;
+    o.points = pts;
+    o.dx = dx;
+    o.dy = dy;
+    return o;
 }
 
+// A job descriptor held across the wave: lane i (< 40) holds dword i, so a
+// field is one v_readlane.  Loading the next pair's descriptor this way costs
+// one load per lane, issued a whole pair ahead.
+struct DescReg {
+    uint32_t d;
+    __device__ __forceinline__ uint32_t u32(int i) const { return (uint32_t)__builtin_amdgcn_readlane((int)d, i); }
+    __device__ __forceinline__ int i32(int i) const { return (int)u32(i); }
+    template <class T>
+    __device__ __forceinline__ T *ptr(int i) const {
+        return (T *)(uintptr_t)((unsigned long long)u32(i) | ((unsigned long long)u32(i + 1) << 32));
+    }
+};
+
+#define DW(f) ((int)(offsetof(JobDesc, f) / 4))
+
+__device__ __forceinline__ uint32_t load_desc(const JobDesc *J) {
+    const int l = lane();
+    return ldg32((const uint32_t *)J + (l < 40 ? l : 39));
+}
+
+__device__ __forceinline__ void store_result(const DescReg &D, int k, uint32_t mv, uint32_t mvi, uint32_t cost,
+                                             int iters, int points) {
+    D.ptr<uint32_t>(DW(mv))[k] = mv;
+    st_relaxed(D.ptr<uint32_t>(DW(mv_int)) + k, mvi);
+    uint32_t *co = D.ptr<uint32_t>(DW(cost));
+    uint8_t *it = D.ptr<uint8_t>(DW(iters));
+    uint16_t *pt = D.ptr<uint16_t>(DW(points));
+    if (co) co[k] = cost;
+    if (it) it[k] = (uint8_t)iters;
+    if (pt) pt[k] = (uint16_t)points;
+}
+
+// Pre-pass over every MB of every pair: a transparent MB gets its (zero)
+// result here, and each line's 32-pair mask words record which pairs are
+// transparent and which are scored on the alpha block.  The line workers
+// then skip transparent runs with one publish and never wait for a
+// neighbour that is transparent in the pair.
+__global__ __launch_bounds__(256) void pa_prepass(const JobDesc *jobs, int n, int total, uint32_t *tmask,
+                                                 uint32_t *bmask, int mw, int shape_only, uint32_t *status) {
+    const int l = lane();
+    const int base = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
+    if (base >= total) return;
+    const int mb = base + l;
+    int ji = find_job(jobs, n, base);
+    if (mb < total) {
+        ji = next_job(jobs, n, ji, mb);
+        const JobDesc &J = jobs[ji];
+        const int k = mb - J.mb_base;
+        int c = J.cls ? (int)J.cls[k] : ME_MB_OPAQUE;
+        if (c > 2) {
+            atomicOr(status, ST_BAD_CLASS);
+            c = ME_MB_TRANSPARENT;
+        }
+        const size_t wi = (size_t)(J.chain_line_base + k) * mw + (J.chain_pos >> 5);
+        const uint32_t bit = 1u << (J.chain_pos & 31);
+        if (c == ME_MB_TRANSPARENT) {
+            ((uint32_t *)J.mv)[k] = 0u;
+            ((uint32_t *)J.mv_int)[k] = 0u;
+            if (J.cost) J.cost[k] = 0u;
+            if (J.iters) J.iters[k] = 0;
+            if (J.points) J.points[k] = 0;
+            atomicOr(tmask + wi, bit);
+        } else if (c == ME_MB_BOUNDARY || shape_only) {
+            atomicOr(bmask + wi, bit);
+        }
+    }
+}
+
+template <int EM>
 __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
-    __shared__ int R[512];
+    extern __shared__ uint32_t lds[];
+    __shared__ int slot;
+    short *R = (short *)lds;                     // 511 reciprocal entries (Eq. 4-5, Q.12)
+    const int wwords = (a.rows * a.pitch + 16) >> 2;
+    uint32_t *const win0 = lds + 256;            // staged reference windows (two when EM > 0)
+    uint32_t *const win1 = lds + 256 + (EM > 0 ? wwords : 0);
     const KParams kp = a.kp;
     for (int g = lane(); g < 511; g += 64) {
-        int m = abs(g - 255);
-        int r = (m == 0 || m < 2 * kp.theta) ? 0 : (16384 + m) / (2 * m);
-        R[g] = g < 255 ? -r : r;
+        const int m = abs(g - 255);
+        const int r = (m == 0 || m < 2 * kp.theta) ? 0 : (16384 + m) / (2 * m);
+        R[g] = (short)(g < 255 ? -r : r);
     }
-    __syncthreads();
-    const int l = lane();
+    const int l = lane(), j = l >> 2, q = l & 3;
+    const int S = kp.S;
     for (;;) {
-        int t = 0;
-        if (l == 0) t = (int)atomicAdd(a.counter, 1u);
-        t = __shfl(t, 0, 64);
-        t = uni(t);
+        // ticket: lane 0 draws, LDS + barriers broadcast (barriers keep the
+        // wave converged across loop trips)
+        __syncthreads();
+        if (l == 0) slot = (int)atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const int t = uni(slot);
         if (t >= a.nlines) break;
         if (uni((int)ld_relaxed(a.status)) & ST_ABORT) break;
         const uint32_t tk = a.tickets[t];
         const int ci = (int)(tk >> 16), v = (int)((tk >> 8) & 0xFF), h = (int)(tk & 0xFF);
         const ChainDesc ch = a.chains[ci];
         const int wm = ch.wm;
-        const int line = ch.line_base + v * wm + h;
+        const int k = v * wm + h;
+        const JobDesc *jobs = a.jobs + ch.first;
+        const int line = ch.line_base + k;
+        unsigned long long *const own = a.progress + line;
+        const int x0 = 16 * h, y0 = 16 * v;
+        const int W = 16 * ch.wm, H = 16 * ch.hm;
+        const bool inA = h > 0, inB = v > 0, inC = v > 0 && h + 1 < wm;
+        // mask rows of this line and of A, B, C (absent ones alias this line)
+        const uint32_t *mo = a.tmask + (size_t)line * a.mw;
+        const uint32_t *mbd = a.bmask + (size_t)line * a.mw;
+        const uint32_t *ma = a.tmask + (size_t)(inA ? line - 1 : line) * a.mw;
+        const uint32_t *mb = a.tmask + (size_t)(inB ? line - wm : line) * a.mw;
+        const uint32_t *mc = a.tmask + (size_t)(inC ? line - wm + 1 : line) * a.mw;
+        Plan<(EM > 0 ? EM : 1)> plan;
+        if (EM > 0) plan.init(a.pitch, a.rows, x0, y0, S, W, H);
+        uint32_t wT = 0, wB = 0, wA = 0, wBn = 0, wC = 0;
+        int wi = -1;
         int tx = 0, ty = 0;
-        for (int p = 0; p < ch.len; ++p) {
-            const JobDesc &J = a.jobs[a.chain_jobs[ch.first + p]];
-            const uint32_t need = (uint32_t)(p + 1);
-            const int k = v * wm + h;
-            int cls = J.cls ? (int)J.cls[k] : ME_MB_OPAQUE;
-            if (cls > 2) {
-                if (l == 0) atomicOr(a.status, ST_BAD_CLASS);
-                cls = ME_MB_TRANSPARENT;
+        uint32_t dnext = 0;
+        bool have_next = false;
+        bool staged = false;   // this pair's window is already in `cur_win`
+        uint32_t *cur_win = win0, *alt_win = win1;
+        int p = 0;
+        while (p < ch.len) {
+            if ((p >> 5) != wi) {
+                wi = p >> 5;
+                wT = (uint32_t)uni((int)ldg32(mo + wi));
+                wB = (uint32_t)uni((int)ldg32(mbd + wi));
+                wA = (uint32_t)uni((int)ldg32(ma + wi));
+                wBn = (uint32_t)uni((int)ldg32(mb + wi));
+                wC = (uint32_t)uni((int)ldg32(mc + wi));
             }
-            if (cls == ME_MB_TRANSPARENT) {
-                // no vector is computed: the result depends on nothing, so
-                // it is published without waiting for the neighbours
-                if (l == 0) {
-                    ((uint32_t *)J.mv)[k] = 0u;
-                    st_relaxed((uint32_t *)J.mv_int + k, 0u);
-                    if (J.cost) J.cost[k] = 0u;
-                    if (J.iters) J.iters[k] = 0;
-                    if (J.points) J.points[k] = 0;
-                    publish(a.progress + line, need);
-                }
+            const int b = p & 31;
+            if ((wT >> b) & 1u) {
+                // a run of transparent pairs (results written by the pre-pass):
+                // one publish covers it
+                const uint32_t ones = ~(wT >> b);
+                int r = ones ? __builtin_ctz(ones) : 32 - b;
+                r = min(r, min(32 - b, ch.len - p));
+                p += r;
                 tx = ty = 0;
+                have_next = false;
+                staged = false;
+                if (l == 0) publish(own, (uint32_t)p, 0u);
                 continue;
             }
-            // A, B and C each waited for directly: a transparent MB publishes
-            // without waiting, so no neighbour's progress implies another's
-            bool ok = true;
-            if (h > 0) ok = wait_ge(a.progress + line - 1, need, a.status, kp.spin_limit);
-            if (ok && v > 0) ok = wait_ge(a.progress + line - wm, need, a.status, kp.spin_limit);
-            if (ok && v > 0 && h + 1 < wm) ok = wait_ge(a.progress + line - wm + 1, need, a.status, kp.spin_limit);
-            if (ok && J.dep_line_base >= 0 && !J.t_local)
-                ok = wait_ge(a.progress + J.dep_line_base + v * wm + h, (uint32_t)(J.dep_pos + 1), a.status,
-                             kp.spin_limit);
-            if (!ok) return;
-            process_mb(J, h, v, cls, J.t_local != 0 && p > 0, tx, ty, R, kp);
-            if (l == 0) publish(a.progress + line, need);
+            const uint32_t dcur = have_next ? dnext : load_desc(jobs + p);
+            const DescReg D{dcur};
+            have_next = p + 1 < ch.len && !(b < 31 && ((wT >> (b + 1)) & 1u));
+            if (have_next) dnext = load_desc(jobs + p + 1);   // in flight during this pair
+            // the next pair is known to be searched: its window is loaded
+            // during this pair's search
+            const bool pre = EM > 0 && p + 1 < ch.len && b < 31 && !((wT >> (b + 1)) & 1u);
+            const uint32_t need = (uint32_t)(p + 1);
+            // neighbours in this pair; transparent ones contribute (0, 0)
+            // without a wait
+            const int dep_line = D.i32(DW(dep_line_base));
+            const bool t_local = D.i32(DW(t_local)) != 0;
+            const bool hasT = dep_line >= 0 && !t_local;
+            const bool use[4] = {inA && !((wA >> b) & 1u), inB && !((wBn >> b) & 1u), inC && !((wC >> b) & 1u),
+                                 hasT};
+            // unused slots poll this line's own word (always readable) and are
+            // ignored: branch-free polls stay in flight with the staging loads
+            const unsigned long long *const w[4] = {use[0] ? own - 1 : own, use[1] ? own - wm : own,
+                                                    use[2] ? own - wm + 1 : own,
+                                                    hasT ? a.progress + dep_line + k : own};
+            const uint32_t nd[4] = {need, need, need, (uint32_t)(D.i32(DW(dep_pos)) + 1)};
+            // first poll, in flight together with the window staging
+            unsigned long long val[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) val[i] = ld64(w[i]);
+            Ctx c;
+            c.shape = ((wB >> b) & 1u) != 0;
+            const uint8_t *Pc = c.shape ? D.ptr<const uint8_t>(DW(cur_a)) : D.ptr<const uint8_t>(DW(cur));
+            const uint8_t *Pr = c.shape ? D.ptr<const uint8_t>(DW(ref_a)) : D.ptr<const uint8_t>(DW(ref));
+            const int st = D.i32(DW(stride));
+            c.win = cur_win;
+            c.R = R;
+            c.pitch = a.pitch;
+            c.S = S;
+            c.off0 = (j + S + 1) * a.pitch + 4 * q + S + 1;
+            c.x0 = x0;
+            c.y0 = y0;
+            c.W = W;
+            c.H = H;
+            c.lox = max(-S, -x0);
+            c.hix = min(S, W - 16 - x0);
+            c.loy = max(-S, -y0);
+            c.hiy = min(S, H - 16 - y0);
+            const uint32_t cur4 = ldg32((const uint32_t *)(Pc + (size_t)(y0 + j) * st + x0 + 4 * q));
+            if (!staged) {
+                if constexpr (EM > 0) {
+                    uint32_t wv[EM];
+                    plan.issue(Pr, st, wv);
+                    plan.write(cur_win, wv, c.shape);
+                } else {
+                    stage_window(cur_win, a.pitch, a.rows, Pr, st, W, H, x0, y0, S, c.shape);
+                }
+            }
+            c.c4 = c.shape ? bin4(cur4) : cur4;
+            // remaining polls
+            int spins = 0;
+            for (;;) {
+                bool ok = true;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (use[i]) ok = ok && (uint32_t)uni((int)(uint32_t)val[i]) >= nd[i];
+                if (ok) break;
+                if ((spins & 31) == 31 && (uni((int)ld_relaxed(a.status)) & ST_ABORT)) return;
+                if (++spins > kp.spin_limit) {
+                    if (l == 0) atomicOr(a.status, ST_SPIN_TIMEOUT | ST_ABORT);
+                    return;
+                }
+                __builtin_amdgcn_s_sleep(2);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) val[i] = ld64(w[i]);
+            }
+            asm volatile("" ::: "memory");  // vector reads stay after the polls
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t lo = (uint32_t)uni((int)(uint32_t)val[i]);
+                const uint32_t hi = (uint32_t)uni((int)(uint32_t)(val[i] >> 32));
+                val[i] = ((unsigned long long)hi << 32) | lo;
+            }
+            const uint32_t *mvi = D.ptr<const uint32_t>(DW(mv_int));
+            const uint32_t *tf = D.ptr<const uint32_t>(DW(tf));
+            uint32_t m[4] = {0u, 0u, 0u, 0u};
+            if (use[0]) m[0] = mv_of(val[0], need, mvi + k - 1);
+            if (use[1]) m[1] = mv_of(val[1], need, mvi + k - wm);
+            if (use[2]) m[2] = mv_of(val[2], need, mvi + k - wm + 1);
+            if (hasT) m[3] = mv_of(val[3], nd[3], tf + k);
+            else if (tf && !(t_local && p > 0)) m[3] = (uint32_t)uni((int)ldg32(tf + k));
+            int cx[4], cy[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                cx[i] = mvx_full(m[i]);
+                cy[i] = mvy_full(m[i]);
+            }
+            if (t_local && p > 0) {
+                cx[3] = tx;
+                cy[3] = ty;
+            }
+            __syncthreads();  // window writes visible to every lane
+            // next pair's window loads fly during this search
+            uint32_t nv[EM > 0 ? EM : 1];
+            bool nshape = false;
+            if constexpr (EM > 0) {
+                if (pre) {
+                    const DescReg Dn{dnext};
+                    nshape = ((wB >> (b + 1)) & 1u) != 0;
+                    plan.issue(nshape ? Dn.ptr<const uint8_t>(DW(ref_a)) : Dn.ptr<const uint8_t>(DW(ref)),
+                               Dn.i32(DW(stride)), nv);
+                }
+            }
+            const MbOut o = search_mb(D.ptr<const uint32_t>(DW(seed)), c, k, cx, cy, kp);
+            staged = false;
+            if constexpr (EM > 0) {
+                if (pre) {
+                    plan.write(alt_win, nv, nshape);
+                    uint32_t *tw = cur_win;
+                    cur_win = alt_win;
+                    alt_win = tw;
+                    staged = true;
+                }
+            }
+            if (l == 0) {
+                publish(own, need, o.mvi);
+                store_result(D, k, o.mv, o.mvi, o.cost, o.iters, o.points);
+            }
+            tx = o.dx;
+            ty = o.dy;
+            ++p;
         }
     }
+}
+
+// elements per lane of the staging plan for range S (0: generic loop)
+int plan_elems(int S) {
+    const int rows = 2 * S + 18, dw = ((rows + 3) & ~3) >> 2;
+    const int e = (rows * dw + 63) / 64;
+    return e <= 4 ? 4 : e <= 12 ? 12 : e <= 28 ? 28 : 0;
 }
 
 }  // namespace
@@ -434,11 +699,32 @@ int pa_worker_cap() {
     return cus * 16;
 }
 
-hipError_t launch_pa(const JobDesc *jobs, const ChainDesc *chains, const int32_t *chain_jobs,
-                     const uint32_t *tickets, int nlines, uint32_t *progress, uint32_t *counter,
+size_t pa_lds_bytes(int S) {
+    const int rows = 2 * S + 18, pitch = (rows + 3) & ~3;
+    const size_t one = (size_t)rows * pitch + 16;
+    return 1024 + (plan_elems(S) > 0 ? 2 : 1) * one;
+}
+
+hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainDesc *chains, const uint32_t *tickets,
+                     int nlines, unsigned long long *progress, uint32_t *counter, uint32_t *masks, int mask_words,
                      uint32_t *status, const KParams &kp, int workers, hipStream_t s) {
-    PaArgs a{jobs, chains, chain_jobs, tickets, nlines, progress, counter, status, kp};
-    hipLaunchKernelGGL(pa_kernel, dim3(workers), dim3(64), 0, s, a);
+    uint32_t *tmask = masks, *bmask = masks + (size_t)nlines * mask_words;
+    if (total_mbs > 0) {
+        hipLaunchKernelGGL(pa_prepass, dim3((total_mbs + 255) / 256), dim3(256), 0, s, jobs, njobs, total_mbs, tmask,
+                           bmask, mask_words, kp.shape_only, status);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int rows = 2 * kp.S + 18;
+    PaArgs a{jobs, chains, tickets, nlines, progress, counter, tmask, bmask, mask_words, status, kp,
+             (rows + 3) & ~3, rows};
+    const size_t lds = pa_lds_bytes(kp.S);
+    switch (plan_elems(kp.S)) {
+        case 4: hipLaunchKernelGGL(pa_kernel<4>, dim3(workers), dim3(64), lds, s, a); break;
+        case 12: hipLaunchKernelGGL(pa_kernel<12>, dim3(workers), dim3(64), lds, s, a); break;
+        case 28: hipLaunchKernelGGL(pa_kernel<28>, dim3(workers), dim3(64), lds, s, a); break;
+        default: hipLaunchKernelGGL(pa_kernel<0>, dim3(workers), dim3(64), lds, s, a); break;
+    }
     return hipGetLastError();
 }
 

@@ -1,6 +1,8 @@
 // Baseline block matching (Section 1 references [5], [7]; Tables 1-2):
 // exhaustive search (ES), three-step search (TSS), diamond search (DS), on the
 // luma of every non-transparent MB.  No inter-MB dependency: flat grids.
+#include <algorithm>
+
 #include "me_internal.h"
 
 namespace me {
@@ -25,25 +27,61 @@ __device__ __forceinline__ void write_result(const JobDesc &J, int k, int dx, in
 // consecutive dy: every reference row it reads feeds up to kEsG candidate
 // SADs (v_sad_u8 on packed bytes), with the current block held in registers.
 // Key = (SAD, |dx|+|dy|, dy, dx) lexicographic, packed into 64 bits.
-__global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, int n, int total, int chunk, KParams kp) {
+// Compaction: one lane per MB.  Transparent MBs get their (zero) result at
+// once; the others are appended to `list` as (job << 16 | MB index).
+__global__ __launch_bounds__(256) void compact_kernel(const JobDesc *jobs, int n, int total, uint32_t *list,
+                                                     uint32_t *count) {
+    const int l = lane();
+    const int base = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
+    if (base >= total) return;
+    const int mb = base + l;
+    int ji = find_job(jobs, n, base);
+    bool searched = false;
+    int k = 0;
+    if (mb < total) {
+        ji = next_job(jobs, n, ji, mb);
+        const JobDesc &J = jobs[ji];
+        k = mb - J.mb_base;
+        const int cls = J.cls ? (int)J.cls[k] : ME_MB_OPAQUE;
+        searched = cls == ME_MB_OPAQUE || cls == ME_MB_BOUNDARY;
+        if (!searched) write_result(J, k, 0, 0, 0u, 0);
+    }
+    const unsigned long long ball = __ballot(searched);
+    const int cnt = __popcll(ball);
+    uint32_t slot = 0;
+    if (l == 0 && cnt) slot = atomicAdd(count, (uint32_t)cnt);
+    slot = (uint32_t)__shfl((int)slot, 0, 64);
+    if (searched) {
+        const int before = __popcll(ball & ((1ull << l) - 1ull));
+        list[slot + before] = ((uint32_t)ji << 16) | (uint32_t)k;
+    }
+}
+
+// Next queued MB for a workgroup: thread 0 takes it and shares it through
+// LDS between two barriers.  (Barriers, unlike a lane-0 branch feeding a
+// shuffle, keep the compiler from splitting the wave across loop trips.)
+__device__ __forceinline__ int take(uint32_t *queue, int *slot) {
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    return *slot;
+}
+
+__global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, const uint32_t *list,
+                                                       const uint32_t *count, uint32_t *queue, KParams kp) {
     extern __shared__ uint32_t lds[];
-    const int first = blockIdx.x * chunk;
-    const int last = min(first + chunk, total);
+    __shared__ int slot;
     const int tid = threadIdx.x;
     const int S = kp.S;
-    int ji = first < total ? find_job(jobs, n, first) : 0;
-    for (int mb = first; mb < last; ++mb) {
-    ji = next_job(jobs, n, ji, mb);
-    const JobDesc &J = jobs[ji];
-    const int k = mb - J.mb_base;
+    const int nitems = (int)*count;
+    for (;;) {
+    const int it = take(queue, &slot);
+    if (it >= nitems) break;
+    const uint32_t e = list[it];
+    const JobDesc &J = jobs[e >> 16];
+    const int k = (int)(e & 0xFFFF);
     const int h = k % J.wm, v = k / J.wm;
     const int x0 = 16 * h, y0 = 16 * v, W = J.width, H = J.height, st = J.stride;
-    const int cls = J.cls ? (int)J.cls[k] : ME_MB_OPAQUE;
-    if (cls == ME_MB_TRANSPARENT || cls > 2) {
-        if (tid == 0) write_result(J, k, 0, 0, 0u, 0);
-        continue;
-    }
-    __syncthreads();  // the previous MB's readers are done with the window
     const int span = 16 + 2 * S;      // window rows and columns
     const int pd = (span + 3) >> 2;   // dwords per row per copy
     const int csz = span * pd;        // dwords per copy
@@ -194,28 +232,23 @@ __device__ __forceinline__ void eval_pts(Mb &m, const int (&ox)[N], const int (&
         if (ok[i]) visit(m, ox[i], oy[i]);
 }
 
-__global__ __launch_bounds__(64) void tss_ds_kernel(const JobDesc *jobs, int n, int total, int chunk, KParams kp,
-                                                    int method) {
+__global__ __launch_bounds__(64) void tss_ds_kernel(const JobDesc *jobs, const uint32_t *list,
+                                                    const uint32_t *count, uint32_t *queue, KParams kp, int method) {
     __shared__ uint32_t memo[kMemoWords];
-    const int first = blockIdx.x * chunk;
-    const int last = min(first + chunk, total);
-    int ji = first < total ? find_job(jobs, n, first) : 0;
-    for (int mb = first; mb < last; ++mb) {
-    ji = next_job(jobs, n, ji, mb);
-    const JobDesc &J = jobs[ji];
-    const int k = mb - J.mb_base;
+    __shared__ int slot;
+    const int l = lane();
+    const int nitems = (int)*count;
+    for (;;) {
+    const int it = take(queue, &slot);
+    if (it >= nitems) break;
+    const uint32_t e = list[it];
+    const JobDesc &J = jobs[e >> 16];
+    const int k = (int)(e & 0xFFFF);
     const int h = k % J.wm, v = k / J.wm;
     const int x0 = 16 * h, y0 = 16 * v;
-    const int l = lane();
-    const int cls = J.cls ? (int)J.cls[k] : ME_MB_OPAQUE;
-    if (cls == ME_MB_TRANSPARENT || cls > 2) {
-        if (l == 0) write_result(J, k, 0, 0, 0u, 0);
-        continue;
-    }
     const int S = kp.S;
     const int words = ((2 * S + 1) * (2 * S + 1) + 31) >> 5;
     for (int i = l; i < words; i += 64) memo[i] = 0;
-    __syncthreads();
     Mb m;
     m.ref = J.ref;
     m.st = J.stride;
@@ -313,7 +346,6 @@ __global__ __launch_bounds__(64) void tss_ds_kernel(const JobDesc *jobs, int n, 
         cc = nc;
     }
     if (l == 0) write_result(J, k, cx, cy, cc, m.pts);
-    __syncthreads();
     }
 }
 
@@ -324,19 +356,25 @@ size_t es_lds_bytes(int S) {
     return (size_t)(4 * span * pd + 64) * 4 + 4 * sizeof(unsigned long long);
 }
 
+size_t full_search_scratch(int total_mbs) { return (size_t)total_mbs * 4; }
+
 hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_mbs, const KParams &kp,
-                              uint32_t *status, hipStream_t s) {
-    (void)status;
+                              uint32_t *counters, uint32_t *list, hipStream_t s) {
     if (total_mbs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(compact_kernel, dim3((total_mbs + 255) / 256), dim3(256), 0, s, jobs, n, total_mbs, list,
+                       counters);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (method == ME_ES) {
         size_t lds = es_lds_bytes(kp.S);
-        int chunk = flat_chunk(total_mbs, 8);
-        int blocks = (total_mbs + chunk - 1) / chunk;
-        hipLaunchKernelGGL(es_kernel, dim3(blocks), dim3(kEsThreads), lds, s, jobs, n, total_mbs, chunk, kp);
+        int blocks = std::min(total_mbs, cus * 8);
+        hipLaunchKernelGGL(es_kernel, dim3(blocks), dim3(kEsThreads), lds, s, jobs, list, counters, counters + 1, kp);
     } else {
-        int chunk = flat_chunk(total_mbs, 32);
-        int blocks = (total_mbs + chunk - 1) / chunk;
-        hipLaunchKernelGGL(tss_ds_kernel, dim3(blocks), dim3(64), 0, s, jobs, n, total_mbs, chunk, kp, method);
+        int blocks = std::min(total_mbs, cus * 16);
+        hipLaunchKernelGGL(tss_ds_kernel, dim3(blocks), dim3(64), 0, s, jobs, list, counters, counters + 1, kp,
+                           method);
     }
     return hipGetLastError();
 }

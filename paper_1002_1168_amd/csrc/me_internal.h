@@ -27,13 +27,16 @@ struct JobDesc {
     int32_t dep_line_base;  // PA: progress lines of the chain producing T (-1: none)
     int32_t dep_pos;        // PA: position of the producing job in that chain
     int32_t t_local;        // PA: T is the previous position of this job's own chain
+    int32_t chain_line_base;  // PA: first progress line of this job's chain
+    int32_t chain_pos;        // PA: position of this job in its chain
     int32_t pad;
 };
+static_assert(sizeof(JobDesc) == 160, "JobDesc is read as 40 dwords");
 
 // A pipelined chain of frame pairs (each one's T field is the previous one's
 // mv_int).  One progress line per MB position.
 struct ChainDesc {
-    int32_t first;      // offset into the chain-job index array
+    int32_t first;      // index of the chain's first pair in the chain-ordered job array
     int32_t len;
     int32_t wm, hm;
     int32_t line_base;  // first progress counter of this chain
@@ -51,11 +54,13 @@ enum : uint32_t { ST_SPIN_TIMEOUT = 1u, ST_BAD_CLASS = 2u, ST_ABORT = 4u };
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_t s);
 int flat_chunk(int total_mbs, int per_cu);
-hipError_t launch_pa(const JobDesc *jobs, const ChainDesc *chains, const int32_t *chain_jobs,
-                     const uint32_t *tickets, int nlines, uint32_t *progress, uint32_t *counter,
+hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainDesc *chains, const uint32_t *tickets,
+                     int nlines, unsigned long long *progress, uint32_t *counter, uint32_t *masks, int mask_words,
                      uint32_t *status, const KParams &kp, int workers, hipStream_t s);
+size_t pa_lds_bytes(int S);
 hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_mbs, const KParams &kp,
-                              uint32_t *status, hipStream_t s);
+                              uint32_t *counters, uint32_t *list, hipStream_t s);
+size_t full_search_scratch(int total_mbs);
 hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, unsigned long long *acc, hipStream_t s);
 
 int pa_worker_cap();
@@ -68,11 +73,20 @@ namespace me {
 
 __device__ __forceinline__ int lane() { return __lane_id(); }
 
-// Unaligned 4-byte global load (gfx950 serves unaligned dword accesses).
+// Unaligned 4-byte load from global memory (gfx950 serves unaligned dword
+// accesses).  The explicit global address space makes it a global_load, not a
+// flat_load, so independent loads can be in flight together.
+typedef uint32_t __attribute__((aligned(1))) u32_unaligned;
 __device__ __forceinline__ uint32_t ld4(const uint8_t *p) {
-    uint32_t v;
-    __builtin_memcpy(&v, p, 4);
-    return v;
+    return *(const __attribute__((address_space(1))) u32_unaligned *)(p);
+}
+
+__device__ __forceinline__ uint32_t ldg32(const uint32_t *p) {
+    return *(const __attribute__((address_space(1))) uint32_t *)(p);
+}
+
+__device__ __forceinline__ uint32_t ldg8(const uint8_t *p) {
+    return *(const __attribute__((address_space(1))) uint8_t *)(p);
 }
 
 // Per byte: 0xFF where the byte is non-zero, else 0 (binary alpha -> 0/255 plane).
