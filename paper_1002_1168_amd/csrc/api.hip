@@ -512,12 +512,12 @@ int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, u
     std::lock_guard<std::mutex> lk(w->mu);
     std::vector<uint8_t> blob;
     size_t o = put(blob, desc.data(), desc.size());
-    uint8_t *base = nullptr, *zb = nullptr;
+    uint8_t *base = nullptr, *zb = nullptr, *sb = nullptr;
     size_t acc_bytes = (size_t)n * 2 * sizeof(unsigned long long);
-    rc = upload(*w, blob, acc_bytes, &base, &zb);
+    rc = upload(*w, blob, 0, &base, &zb, acc_bytes + mc_scratch((int)total), &sb);
     if (rc) return rc;
-    unsigned long long *acc = (unsigned long long *)zb;
-    rc = hip_err(launch_mc((const JobDesc *)(base + o), n, (int)total, acc, w->stream));
+    unsigned long long *acc = (unsigned long long *)sb;
+    rc = hip_err(launch_mc((const JobDesc *)(base + o), n, (int)total, (uint32_t *)(sb + acc_bytes), acc, w->stream));
     if (rc) return rc;
     if (w->host_acc_cap < acc_bytes) {
         if (w->host_acc) hipHostFree(w->host_acc);

@@ -496,7 +496,8 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
     const int S = kp.S;
     for (;;) {
         // ticket: lane 0 draws, LDS + barriers broadcast (barriers keep the
-        // wave converged across loop trips)
+        // wave converged across loop trips).  Only a running worker ever
+        // holds a ticket, which the deadlock-freedom argument needs.
         __syncthreads();
         if (l == 0) slot = (int)atomicAdd(a.counter, 1u);
         __syncthreads();

@@ -12,6 +12,21 @@ namespace {
 constexpr int kEsThreads = 256;
 constexpr int kEsG = 8;  // candidate rows per thread task (register blocking)
 
+// ES window geometry: rows and columns 16 + 2S, row pitch a power of two
+// (>= (16+2S+3)/4 dwords) so staging needs no divisions, and each of the four
+// byte-shifted copies padded to 8 mod 32 dwords so that the four copies of a
+// dword fall on four different LDS banks.
+__host__ __device__ inline int es_pitch_log2(int S) {
+    const int need = (16 + 2 * S + 3) >> 2;
+    int lg = 0;
+    while ((1 << lg) < need) ++lg;
+    return lg;
+}
+__host__ __device__ inline int es_copy_dwords(int S) {
+    const int raw = (16 + 2 * S) << es_pitch_log2(S);
+    return raw + ((8 - raw % 32) + 32) % 32;
+}
+
 __device__ __forceinline__ void write_result(const JobDesc &J, int k, int dx, int dy, uint32_t cost, int pts) {
     uint32_t w = (uint32_t)(uint16_t)(2 * dx) | ((uint32_t)(uint16_t)(2 * dy) << 16);
     ((uint32_t *)J.mv)[k] = w;
@@ -57,59 +72,51 @@ __global__ __launch_bounds__(256) void compact_kernel(const JobDesc *jobs, int n
     }
 }
 
-// Next queued MB for a workgroup: thread 0 takes it and shares it through
-// LDS between two barriers.  (Barriers, unlike a lane-0 branch feeding a
-// shuffle, keep the compiler from splitting the wave across loop trips.)
-__device__ __forceinline__ int take(uint32_t *queue, int *slot) {
-    __syncthreads();
-    if (threadIdx.x == 0) *slot = (int)atomicAdd(queue, 1u);
-    __syncthreads();
-    return *slot;
-}
-
 __global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, const uint32_t *list,
-                                                       const uint32_t *count, uint32_t *queue, KParams kp) {
+                                                       const uint32_t *count, KParams kp) {
     extern __shared__ uint32_t lds[];
-    __shared__ int slot;
     const int tid = threadIdx.x;
     const int S = kp.S;
     const int nitems = (int)*count;
-    for (;;) {
-    const int it = take(queue, &slot);
-    if (it >= nitems) break;
+    // every searched MB costs the same: static striding, no shared counter
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    __syncthreads();  // the previous MB's readers are done with the window
     const uint32_t e = list[it];
     const JobDesc &J = jobs[e >> 16];
     const int k = (int)(e & 0xFFFF);
     const int h = k % J.wm, v = k / J.wm;
     const int x0 = 16 * h, y0 = 16 * v, W = J.width, H = J.height, st = J.stride;
     const int span = 16 + 2 * S;      // window rows and columns
-    const int pd = (span + 3) >> 2;   // dwords per row per copy
-    const int csz = span * pd;        // dwords per copy
+    const int lgp = es_pitch_log2(S);
+    const int pd = 1 << lgp;          // dwords per row per copy
+    const int csz = es_copy_dwords(S);
     uint32_t *win = lds;              // 4 copies
     uint32_t *curb = lds + 4 * csz;   // 64 dwords
     unsigned long long *red = (unsigned long long *)(curb + 64);  // 4 wave minima
-    // stage: copy s, row r, dword w holds window bytes 4w+s .. 4w+s+3
+    // copy 0 from the frame (rows clamped, edge dwords permuted: bytes outside
+    // the frame are never read by an admissible candidate), eight loads in
+    // flight per thread; copy s dword w = window bytes 4w+s .. 4w+s+3 is then
+    // built from copy 0 in LDS
     const int wx0 = x0 - S, wy0 = y0 - S;
-    for (int idx = tid; idx < 4 * csz; idx += kEsThreads) {
-        int s = idx / csz, rem = idx - s * csz;
-        int r = rem / pd, w = rem - r * pd;
-        int yy = wy0 + r;
-        int c0 = 4 * w + s, xx0 = wx0 + c0;
-        uint32_t val = 0;
-        if (yy >= 0 && yy < H) {
-            const uint8_t *row = J.ref + (size_t)yy * st;
-            if (xx0 >= 0 && xx0 + 3 < W && c0 + 3 < span) {
-                val = ld4(row + xx0);
-            } else {
+    const int per = span << lgp;
+    for (int base = 0; base < per; base += 8 * kEsThreads) {
+        uint32_t v[8];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    int c = c0 + b, xx = xx0 + b;
-                    uint32_t byte = (c < span && xx >= 0 && xx < W) ? row[xx] : 0u;
-                    val |= byte << (8 * b);
-                }
-            }
+        for (int u = 0; u < 8; ++u) {
+            const int idx = min(base + u * kEsThreads + tid, per - 1);
+            const int r = idx >> lgp, w = idx & (pd - 1);
+            v[u] = ld4_clamped(J.ref + (size_t)iclamp(wy0 + r, 0, H - 1) * st, wx0 + 4 * w, W);
         }
-        win[idx] = val;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (base + u * kEsThreads + tid < per) win[base + u * kEsThreads + tid] = v[u];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < per; idx += kEsThreads) {
+        const uint32_t a = win[idx], b = (idx & (pd - 1)) + 1 < pd ? win[idx + 1] : 0u;
+        win[csz + idx] = __builtin_amdgcn_alignbyte(b, a, 1);
+        win[2 * csz + idx] = __builtin_amdgcn_alignbyte(b, a, 2);
+        win[3 * csz + idx] = __builtin_amdgcn_alignbyte(b, a, 3);
     }
     if (tid < 64) curb[tid] = *(const uint32_t *)(J.cur + (size_t)(y0 + (tid >> 2)) * st + x0 + 4 * (tid & 3));
     __syncthreads();
@@ -233,14 +240,13 @@ __device__ __forceinline__ void eval_pts(Mb &m, const int (&ox)[N], const int (&
 }
 
 __global__ __launch_bounds__(64) void tss_ds_kernel(const JobDesc *jobs, const uint32_t *list,
-                                                    const uint32_t *count, uint32_t *queue, KParams kp, int method) {
+                                                    const uint32_t *count, KParams kp, int method) {
     __shared__ uint32_t memo[kMemoWords];
-    __shared__ int slot;
     const int l = lane();
     const int nitems = (int)*count;
-    for (;;) {
-    const int it = take(queue, &slot);
-    if (it >= nitems) break;
+    // static striding over the searched MBs (a shared counter would
+    // serialise every pick at one L2 atomic)
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const uint32_t e = list[it];
     const JobDesc &J = jobs[e >> 16];
     const int k = (int)(e & 0xFFFF);
@@ -351,10 +357,7 @@ __global__ __launch_bounds__(64) void tss_ds_kernel(const JobDesc *jobs, const u
 
 }  // namespace
 
-size_t es_lds_bytes(int S) {
-    int span = 16 + 2 * S, pd = (span + 3) >> 2;
-    return (size_t)(4 * span * pd + 64) * 4 + 4 * sizeof(unsigned long long);
-}
+size_t es_lds_bytes(int S) { return (size_t)(4 * es_copy_dwords(S) + 64) * 4 + 4 * sizeof(unsigned long long); }
 
 size_t full_search_scratch(int total_mbs) { return (size_t)total_mbs * 4; }
 
@@ -370,11 +373,10 @@ hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_
     if (method == ME_ES) {
         size_t lds = es_lds_bytes(kp.S);
         int blocks = std::min(total_mbs, cus * 8);
-        hipLaunchKernelGGL(es_kernel, dim3(blocks), dim3(kEsThreads), lds, s, jobs, list, counters, counters + 1, kp);
+        hipLaunchKernelGGL(es_kernel, dim3(blocks), dim3(kEsThreads), lds, s, jobs, list, counters, kp);
     } else {
         int blocks = std::min(total_mbs, cus * 16);
-        hipLaunchKernelGGL(tss_ds_kernel, dim3(blocks), dim3(64), 0, s, jobs, list, counters, counters + 1, kp,
-                           method);
+        hipLaunchKernelGGL(tss_ds_kernel, dim3(blocks), dim3(64), 0, s, jobs, list, counters, kp, method);
     }
     return hipGetLastError();
 }

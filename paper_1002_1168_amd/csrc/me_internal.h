@@ -61,7 +61,9 @@ size_t pa_lds_bytes(int S);
 hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_mbs, const KParams &kp,
                               uint32_t *counters, uint32_t *list, hipStream_t s);
 size_t full_search_scratch(int total_mbs);
-hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, unsigned long long *acc, hipStream_t s);
+hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, unsigned long long *acc,
+                     hipStream_t s);
+size_t mc_scratch(int total_mbs);
 
 int pa_worker_cap();
 
@@ -80,6 +82,11 @@ typedef uint32_t __attribute__((aligned(1))) u32_unaligned;
 __device__ __forceinline__ uint32_t ld4(const uint8_t *p) {
     return *(const __attribute__((address_space(1))) u32_unaligned *)(p);
 }
+
+// 4 frame bytes of `row` starting at column xx, edge replicated: an
+// in-frame dword at the clamped column, then a byte permute (branch-free, so
+// independent loads stay in flight together).
+__device__ __forceinline__ uint32_t ld4_clamped(const uint8_t *row, int xx, int W);
 
 __device__ __forceinline__ uint32_t ldg32(const uint32_t *p) {
     return *(const __attribute__((address_space(1))) uint32_t *)(p);
@@ -137,6 +144,15 @@ __device__ __forceinline__ int next_job(const JobDesc *jobs, int n, int ji, int 
 }
 
 __device__ __forceinline__ int iclamp(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
+
+__device__ __forceinline__ uint32_t ld4_clamped(const uint8_t *row, int xx, int W) {
+    const int xc = iclamp(xx, 0, W - 4);
+    const uint32_t sel = (uint32_t)(iclamp(xx, 0, W - 1) - xc) | ((uint32_t)(iclamp(xx + 1, 0, W - 1) - xc) << 8) |
+                         ((uint32_t)(iclamp(xx + 2, 0, W - 1) - xc) << 16) |
+                         ((uint32_t)(iclamp(xx + 3, 0, W - 1) - xc) << 24);
+    const uint32_t v = ld4(row + xc);
+    return __builtin_amdgcn_perm(v, v, sel);
+}
 
 // Eq. 3 per-axis step: eps * U (Q.24) rounded half away from zero, clamped.
 __device__ __forceinline__ int prs_step(int u, int eps, int max_step) {
