@@ -15,6 +15,7 @@ Prints one JSON line (rank 0).  Only one GPU is used: --gpus above 1 exits.
 from __future__ import annotations
 
 import argparse
+import ctypes as C
 import json
 import os
 import sys
@@ -66,12 +67,16 @@ class Workload:
         self.params = me.me_default_params(search_range=self.S)
         self.pairs = frames - 1
         self.V = self.seq.vops
-        self.cls_frames, self.cls_ptrs, self.bab_ptrs = self.ds.classify_frames()
+        fr, cp, bp = self.ds.classify_frames()
+        self.cls_frames = (me.me_frame * len(fr))(*fr)
+        self.cls_ptrs = (C.c_void_p * len(cp))(*cp)
+        self.bab_ptrs = (C.c_void_p * len(bp))(*bp)
         self.out = [dv.Outputs.alloc(self.pairs, self.ds.hm, self.ds.wm) for _ in range(self.V)]
-        self.jobs = [j for v in range(self.V) for j in self.ds.pair_jobs(v, self.out[v], self.pairs)]
+        self.jobs = me.job_array([j for v in range(self.V) for j in self.ds.pair_jobs(v, self.out[v], self.pairs)])
         self.base_out = {m: [dv.Outputs.alloc(self.pairs, self.ds.hm, self.ds.wm) for _ in range(self.V)]
                          for m in (me.ME_ES, me.ME_TSS, me.ME_DS)}
-        self.base_jobs = {m: [j for v in range(self.V) for j in self.ds.pair_jobs(v, o[v], self.pairs, chained=False)]
+        self.base_jobs = {m: me.job_array([j for v in range(self.V)
+                                           for j in self.ds.pair_jobs(v, o[v], self.pairs, chained=False)])
                           for m, o in self.base_out.items()}
         self.grid_mbs = self.V * self.pairs * self.ds.hm * self.ds.wm
 

@@ -94,8 +94,18 @@ def _check(rc: int, what: str) -> int:
 
 
 def _arr(ctype, items):
+    """ctypes array of `items`; a ctypes array of `ctype` is used as is."""
+    if isinstance(items, C.Array) and items._type_ is ctype:
+        return items, len(items)
     items = list(items)
     return (ctype * max(len(items), 1))(*items), len(items)
+
+
+def job_array(jobs) -> C.Array:
+    """Prebuilt me_job array: pass it instead of a list to skip per-call
+    marshalling when the same job set is launched repeatedly."""
+    jobs = list(jobs)
+    return (me_job * len(jobs))(*jobs)
 
 
 def me_default_params(**over) -> me_params:

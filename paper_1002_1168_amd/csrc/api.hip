@@ -32,16 +32,36 @@ struct Staging {
     hipEvent_t ev = nullptr;
 };
 
+// Device scratch of one kind of call (classification, search, baselines,
+// MC): descriptors stay resident between calls of the same kind, so a
+// repeated call with the same jobs uploads nothing.
+struct Arena {
+    uint8_t *dev = nullptr;
+    size_t cap = 0;
+    std::vector<uint8_t> last;  // content of the last upload
+    bool last_valid = false;
+};
+
+enum ArenaKind { A_CLASSIFY = 0, A_PA = 1, A_SEARCH = 2, A_MC = 3, A_COUNT = 4 };
+
+// The last search call's prepared launch (reused when the next call passes
+// byte-identical jobs and parameters).
+struct PaMemo {
+    std::vector<uint8_t> key;  // jobs + params + mode
+    std::vector<uint8_t> blob;
+    size_t o_jobs = 0, o_ch = 0, o_tk = 0;
+    int n = 0, total_mbs = 0, nlines = 0, mask_words = 0;
+    bool valid = false;
+};
+
 struct Workspace {
     int device = 0;
     hipStream_t stream = nullptr;
-    uint8_t *dev = nullptr;
-    size_t cap = 0;
+    Arena arena[A_COUNT];
     uint32_t *status = nullptr;  // persistent device status word
     Staging ring[kRing];
     int slot = 0;
-    std::vector<uint8_t> last;   // content of the last upload (skip identical ones)
-    bool last_valid = false;
+    PaMemo pa;
     unsigned long long *host_acc = nullptr;  // pinned readback for MC
     size_t host_acc_cap = 0;
     std::mutex mu;
@@ -94,27 +114,28 @@ int get_ws(void *stream, Workspace **out) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// Copy `blob` to the start of the device arena (skipped when the arena still
-// holds exactly these bytes) and zero `zero_bytes` after it.  Returns the
-// arena base in *base and the zeroed region in *zero.
-int upload(Workspace &w, const std::vector<uint8_t> &blob, size_t zero_bytes, uint8_t **base, uint8_t **zero,
-           size_t scratch_bytes = 0, uint8_t **scratch = nullptr) {
+// Copy `blob` to the start of the arena of `kind` (skipped when the arena
+// still holds exactly these bytes), zero `zero_bytes` after it and reserve
+// `scratch_bytes` more.  Returns the arena base, zeroed and scratch regions.
+int upload(Workspace &w, int kind, const std::vector<uint8_t> &blob, size_t zero_bytes, uint8_t **base,
+           uint8_t **zero, size_t scratch_bytes = 0, uint8_t **scratch = nullptr) {
+    Arena &ar = w.arena[kind];
     size_t off = align_up(blob.size(), 256);
     size_t need = off + align_up(zero_bytes, 256) + align_up(scratch_bytes, 256) + 256;
-    if (need > w.cap) {
-        if (w.dev) {
+    if (need > ar.cap) {
+        if (ar.dev) {
             if (hipStreamSynchronize(w.stream) != hipSuccess) return ME_EHIP;
-            hipFree(w.dev);
-            w.dev = nullptr;
-            w.cap = 0;
+            hipFree(ar.dev);
+            ar.dev = nullptr;
+            ar.cap = 0;
         }
-        size_t cap = std::max(need, (size_t)1 << 20);
-        if (hipMalloc(&w.dev, cap) != hipSuccess) return ME_ENOMEM;
-        w.cap = cap;
-        w.last_valid = false;
+        size_t cap = std::max(need + need / 4, (size_t)1 << 20);
+        if (hipMalloc(&ar.dev, cap) != hipSuccess) return ME_ENOMEM;
+        ar.cap = cap;
+        ar.last_valid = false;
     }
-    bool same = w.last_valid && w.last.size() == blob.size() &&
-                std::memcmp(w.last.data(), blob.data(), blob.size()) == 0;
+    bool same = ar.last_valid && ar.last.size() == blob.size() &&
+                std::memcmp(ar.last.data(), blob.data(), blob.size()) == 0;
     if (!same && !blob.empty()) {
         Staging &s = w.ring[w.slot];
         w.slot = (w.slot + 1) % kRing;
@@ -130,17 +151,17 @@ int upload(Workspace &w, const std::vector<uint8_t> &blob, size_t zero_bytes, ui
             s.cap = cap;
         }
         std::memcpy(s.host, blob.data(), blob.size());
-        if (hipMemcpyAsync(w.dev, s.host, blob.size(), hipMemcpyHostToDevice, w.stream) != hipSuccess)
+        if (hipMemcpyAsync(ar.dev, s.host, blob.size(), hipMemcpyHostToDevice, w.stream) != hipSuccess)
             return ME_EHIP;
         if (hipEventRecord(s.ev, w.stream) != hipSuccess) return ME_EHIP;
-        w.last = blob;
-        w.last_valid = true;
+        ar.last = blob;
+        ar.last_valid = true;
     }
-    *base = w.dev;
-    *zero = w.dev + off;
-    if (scratch) *scratch = w.dev + off + align_up(zero_bytes, 256);
+    *base = ar.dev;
+    *zero = ar.dev + off;
+    if (scratch) *scratch = ar.dev + off + align_up(zero_bytes, 256);
     if (zero_bytes) {
-        int rc = hip_err(launch_fill_u32((uint32_t *)(w.dev + off), align_up(zero_bytes, 4) / 4, 0u, w.stream));
+        int rc = hip_err(launch_fill_u32((uint32_t *)(ar.dev + off), align_up(zero_bytes, 4) / 4, 0u, w.stream));
         if (rc) return rc;
     }
     return ME_OK;
@@ -229,16 +250,8 @@ JobDesc job_desc(const me_job &j) {
     return d;
 }
 
-// The proposed algorithm for n jobs (shared by the texture and shape entry points).
-int run_pa(const me_job *jobs, int n, const me_params *params, bool shape_only, void *stream) {
-    if (n < 0 || (n > 0 && !jobs)) return ME_EINVAL;
-    int rc = check_params(params);
-    if (rc) return rc;
-    for (int i = 0; i < n; ++i) {
-        rc = check_job(jobs[i], shape_only);
-        if (rc) return rc;
-    }
-    if (n == 0) return ME_OK;
+// Chains, chain-ordered descriptors and the ticket order of a job set.
+int build_pa(const me_job *jobs, int n, PaMemo &m) {
     // chains: a job whose T field is the mv_int of an earlier job follows it
     std::unordered_map<const void *, int> producer;
     for (int i = 0; i < n; ++i) {
@@ -320,30 +333,63 @@ int run_pa(const me_job *jobs, int n, const me_params *params, bool shape_only, 
             for (int h = 0; h < cd[c].wm; ++h)
                 tickets[cnt[h + 2 * v]++] = ((uint32_t)c << 16) | ((uint32_t)v << 8) | (uint32_t)h;
 
+    m.blob.clear();
+    m.o_jobs = put(m.blob, ordered.data(), ordered.size());
+    m.o_ch = put(m.blob, cd.data(), cd.size());
+    m.o_tk = put(m.blob, tickets.data(), tickets.size());
+    m.n = n;
+    m.total_mbs = (int)total_mbs;
+    m.nlines = (int)nlines;
+    m.mask_words = (maxlen + 31) / 32;
+    return ME_OK;
+}
+
+// The proposed algorithm for n jobs (shared by the texture and shape entry points).
+int run_pa(const me_job *jobs, int n, const me_params *params, bool shape_only, void *stream) {
+    if (n < 0 || (n > 0 && !jobs)) return ME_EINVAL;
+    int rc = check_params(params);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) {
+        rc = check_job(jobs[i], shape_only);
+        if (rc) return rc;
+    }
+    if (n == 0) return ME_OK;
     Workspace *w = nullptr;
     rc = get_ws(stream, &w);
-    if (rc) return rc;
+    if (rc) {
+        PaMemo probe;  // structural errors of the job set take precedence
+        int vr = build_pa(jobs, n, probe);
+        return vr ? vr : rc;
+    }
     std::lock_guard<std::mutex> lk(w->mu);
-    std::vector<uint8_t> blob;
-    size_t o_jobs = put(blob, ordered.data(), ordered.size());
-    size_t o_ch = put(blob, cd.data(), cd.size());
-    size_t o_tk = put(blob, tickets.data(), tickets.size());
+    // a repeated call with byte-identical jobs reuses the prepared launch
+    std::vector<uint8_t> key(sizeof(me_job) * (size_t)n + sizeof(me_params) + 1);
+    std::memcpy(key.data(), jobs, sizeof(me_job) * (size_t)n);
+    std::memcpy(key.data() + sizeof(me_job) * (size_t)n, params, sizeof(me_params));
+    key.back() = shape_only ? 1 : 0;
+    PaMemo &m = w->pa;
+    if (!(m.valid && m.key == key)) {
+        m.valid = false;
+        rc = build_pa(jobs, n, m);
+        if (rc) return rc;
+        m.key.swap(key);
+        m.valid = true;
+    }
     // zeroed scratch: progress words, ticket counter, transparent and
     // boundary masks (one bit per pair, 32 pairs per word, per line)
-    const int mask_words = (maxlen + 31) / 32;
     const size_t o_prog = 0;
-    const size_t o_ctr = align_up((size_t)nlines * 8, 256);
+    const size_t o_ctr = align_up((size_t)m.nlines * 8, 256);
     const size_t o_mask = o_ctr + 256;
-    const size_t zero = o_mask + align_up((size_t)nlines * mask_words * 2 * 4, 256);
+    const size_t zero = o_mask + align_up((size_t)m.nlines * m.mask_words * 2 * 4, 256);
     uint8_t *base = nullptr, *zb = nullptr;
-    rc = upload(*w, blob, zero, &base, &zb);
+    rc = upload(*w, A_PA, m.blob, zero, &base, &zb);
     if (rc) return rc;
-    int workers = (int)std::min<long long>(nlines, pa_worker_cap());
+    int workers = std::min(m.nlines, pa_worker_cap());
     KParams kp = kparams(params, shape_only);
-    return hip_err(launch_pa((const JobDesc *)(base + o_jobs), n, (int)total_mbs, (const ChainDesc *)(base + o_ch),
-                             (const uint32_t *)(base + o_tk), (int)nlines, (unsigned long long *)(zb + o_prog),
-                             (uint32_t *)(zb + o_ctr), (uint32_t *)(zb + o_mask), mask_words, w->status, kp, workers,
-                             w->stream));
+    return hip_err(launch_pa((const JobDesc *)(base + m.o_jobs), m.n, m.total_mbs, (const ChainDesc *)(base + m.o_ch),
+                             (const uint32_t *)(base + m.o_tk), m.nlines, (unsigned long long *)(zb + o_prog),
+                             (uint32_t *)(zb + o_ctr), (uint32_t *)(zb + o_mask), m.mask_words, w->status, kp,
+                             workers, w->stream));
 }
 
 }  // namespace
@@ -383,7 +429,8 @@ void me_shutdown(void) {
         int cur = 0;
         hipGetDevice(&cur);
         hipSetDevice(w->device);
-        if (w->dev) hipFree(w->dev);
+        for (auto &ar : w->arena)
+            if (ar.dev) hipFree(ar.dev);
         if (w->status) hipFree(w->status);
         for (auto &s : w->ring) {
             if (s.host) hipHostFree(s.host);
@@ -429,7 +476,7 @@ int me_classify_babs(const me_frame *frames, int n, uint8_t *const *mb_class, ui
     std::vector<uint8_t> blob;
     size_t o = put(blob, desc.data(), desc.size());
     uint8_t *base = nullptr, *zb = nullptr;
-    rc = upload(*w, blob, 0, &base, &zb);
+    rc = upload(*w, A_CLASSIFY, blob, 0, &base, &zb);
     if (rc) return rc;
     return hip_err(launch_classify((const JobDesc *)(base + o), n, (int)total, w->stream));
 }
@@ -476,7 +523,7 @@ int me_full_search(int method, const me_job *jobs, int n, const me_params *param
     std::vector<uint8_t> blob;
     size_t o = put(blob, desc.data(), desc.size());
     uint8_t *base = nullptr, *zb = nullptr, *sb = nullptr;
-    rc = upload(*w, blob, 256, &base, &zb, full_search_scratch((int)total), &sb);
+    rc = upload(*w, A_SEARCH, blob, 256, &base, &zb, full_search_scratch((int)total), &sb);
     if (rc) return rc;
     KParams kp = kparams(params, false);
     return hip_err(launch_full_search(method, (const JobDesc *)(base + o), n, (int)total, kp, (uint32_t *)zb,
@@ -514,7 +561,7 @@ int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, u
     size_t o = put(blob, desc.data(), desc.size());
     uint8_t *base = nullptr, *zb = nullptr, *sb = nullptr;
     size_t acc_bytes = (size_t)n * 2 * sizeof(unsigned long long);
-    rc = upload(*w, blob, 0, &base, &zb, acc_bytes + mc_scratch((int)total), &sb);
+    rc = upload(*w, A_MC, blob, 0, &base, &zb, acc_bytes + mc_scratch((int)total), &sb);
     if (rc) return rc;
     unsigned long long *acc = (unsigned long long *)sb;
     rc = hip_err(launch_mc((const JobDesc *)(base + o), n, (int)total, (uint32_t *)(sb + acc_bytes), acc, w->stream));
