@@ -40,6 +40,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel: str, sources, summary: str):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 PMC
+    summary, or None when the kernel's sources changed since it was taken."""
+    import hashlib
+    try:
+        h = hashlib.sha256()
+        for f in sources:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        with open(os.path.join(ROOT, summary)) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    for ln in lines:
+        t = ln.split()
+        if len(t) == 4 and t[0] == "traffic" and t[1] == kernel:
+            kv = dict(x.split("=", 1) for x in t[2:])
+            if kv.get("source_sha256") == h.hexdigest():
+                return int(kv["bytes_per_launch"])
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -48,6 +70,8 @@ def parse():
     ap.add_argument("--frames", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run 3 device copies of this many MiB (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
 
 
@@ -80,41 +104,38 @@ class Workload:
                           for m, o in self.base_out.items()}
         self.grid_mbs = self.V * self.pairs * self.ds.hm * self.ds.wm
 
-    def step(self, stream, ev=None):
-        """classify -> proposed search -> MC/PSNR.  `ev` = (start, end)
-        HIP events bracketing the search launch on the same stream."""
+    def step(self, stream):
+        """classify -> proposed search -> MC/PSNR."""
         me = self.me
         me.me_classify_babs(self.cls_frames, self.cls_ptrs, self.bab_ptrs, stream=stream)
-        if ev is not None:
-            ev[0].record()
         me.me_texture_recursive(self.jobs, self.params, None, stream=stream)
-        if ev is not None:
-            ev[1].record()
         return me.me_motion_compensate_psnr(self.jobs, stream=stream)
 
-    def baseline_step(self, method, stream, ev=None):
+    def baseline_step(self, method, stream):
         me = self.me
-        if ev is not None:
-            ev[0].record()
         me.me_full_search(method, self.base_jobs[method], self.params, stream=stream)
-        if ev is not None:
-            ev[1].record()
         return me.me_motion_compensate_psnr(self.base_jobs[method], stream=stream)
 
 
-def timed(fn, steps, warmup, torch):
+def timed(fn, steps, warmup, torch, me, stream, kind):
+    """Wall time of `steps` calls of fn, and the mean duration of the main
+    kernel of call kind `kind` over the same calls (HIP events recorded by
+    the library on `stream` around that kernel)."""
     for _ in range(warmup):
-        fn(None)
+        fn()
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    me.me_kernel_timing(True)
+    me.me_kernel_time_ms(kind, stream)  # restart the sums
     t0 = time.perf_counter()
     res = None
-    for i in range(steps):
-        res = fn(evs[i])
+    for _ in range(steps):
+        res = fn()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    return dt, kern_ms, res
+    total, count = me.me_kernel_time_ms(kind, stream)
+    me.me_kernel_timing(False)
+    assert count == steps, (count, steps)
+    return dt, total / count, res
 
 
 def summarize(out_list, classes, searched_only=True):
@@ -128,22 +149,28 @@ def summarize(out_list, classes, searched_only=True):
     return pts, its, n
 
 
-def cpu_baseline(wl, gpu_hosts):
-    """The oracle on the whole workload, single thread; also checks the GPU
-    result of the last timed step bit-exactly."""
+def cpu_baseline(wl, gpu_hosts, min_seconds=10.0):
+    """The oracle on the whole workload, single thread, repeated until
+    `min_seconds` have passed; also checks the GPU result of the last timed
+    step bit-exactly.  -> (seconds per pass, passes, exact)."""
     import oracle
     seq, p = wl.seq, wl.params
     op = oracle.Params(p.search_range, p.theta, p.eps_q12, p.max_step, p.k_max, p.half_pel)
     t0 = time.perf_counter()
-    res = [oracle.pa_sequence(seq, v, op, pairs=wl.pairs) for v in range(wl.V)]
-    dt = time.perf_counter() - t0
+    reps = 0
+    while True:
+        res = [oracle.pa_sequence(seq, v, op, pairs=wl.pairs) for v in range(wl.V)]
+        reps += 1
+        if time.perf_counter() - t0 >= min_seconds:
+            break
+    dt = (time.perf_counter() - t0) / reps
     exact = True
     for v in range(wl.V):
         for i, r in enumerate(res[v]):
             for k in ("mv", "mv_int", "cost", "iters", "points"):
                 if not np.array_equal(gpu_hosts[v][k][i], r[k]):
                     exact = False
-    return dt, exact
+    return dt, reps, exact
 
 
 def main():
@@ -154,11 +181,19 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if a.copy_mib:
+        src = torch.randint(0, 255, (a.copy_mib << 20,), dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {a.copy_mib} MiB x3")
+        return
     wl = Workload(a.frames)
     me = wl.me
     stream = wl.dv.stream_handle()
 
-    dt, kern_ms, res = timed(lambda ev: wl.step(stream, ev), a.steps, a.warmup, torch)
+    dt, kern_ms, res = timed(lambda: wl.step(stream), a.steps, a.warmup, torch, me, stream, me.ME_KT_SEARCH)
     assert me.me_device_status(stream) == me.ME_OK
     sse, npx, ps, _ = res
     ms = 1000.0 * dt / a.steps
@@ -175,7 +210,8 @@ def main():
     baselines = {}
     if not a.no_baselines:
         for m, name in ((me.ME_ES, "es"), (me.ME_TSS, "tss"), (me.ME_DS, "ds")):
-            bdt, bk, bres = timed(lambda ev, m=m: wl.baseline_step(m, stream, ev), max(a.steps // 2, 1), 1, torch)
+            bdt, bk, bres = timed(lambda m=m: wl.baseline_step(m, stream), max(a.steps // 2, 1), 1, torch, me, stream,
+                                  me.ME_KT_FULL)
             bpts, _, bn = summarize(wl.base_out[m], classes)
             steps_b = max(a.steps // 2, 1)
             entry = {"mb_per_s": wl.grid_mbs * steps_b / bdt, "ms_per_step": 1000.0 * bdt / steps_b,
@@ -194,10 +230,10 @@ def main():
     cpu = None
     if not a.no_cpu_baseline:
         hosts = [o.host() for o in wl.out]
-        cdt, exact = cpu_baseline(wl, hosts)
+        cdt, reps, exact = cpu_baseline(wl, hosts)
         cpu = {"value": wl.grid_mbs / cdt, "unit": "MB/s", "cores": 1, "kind": "oracle",
-               "sample": f"whole workload once: classification, proposed search and MC/SSE for "
-                         f"{wl.V} VOPs x {wl.pairs} pairs (single thread, C oracle -O2)",
+               "sample": f"the whole workload ({wl.V} VOPs x {wl.pairs} pairs: classification, proposed search, "
+                         f"MC/SSE) {reps}x back to back, mean per pass (single thread, C oracle built -O2)",
                "parity_vs_gpu": "bit-exact" if exact else "MISMATCH"}
         log(f"oracle: {cdt:.2f}s -> {cpu['value'] / 1e6:.3f} M MB/s, GPU parity {'ok' if exact else 'MISMATCH'}")
 
@@ -212,7 +248,10 @@ def main():
         "psnr_db": psnr, "iters_per_mb": its / max(nsearch, 1), "points_per_mb": pts / max(nsearch, 1),
         "searched_mb_per_s": nsearch * a.steps / dt,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS, "unit": "Tops/s",
-                     "frac": achieved / PEAK_INT_TOPS, "traffic": None,
+                     "frac": achieved / PEAK_INT_TOPS,
+                     "traffic": measured_traffic("pa_kernel", ("paper_1002_1168_amd/csrc/k_pa.hip",
+                                                               "paper_1002_1168_amd/csrc/me_internal.h"),
+                                                 "profiles/pa_kernel_traffic_cif352x288_2vop_300f_S16.md"),
                      "kernel": "pa_kernel", "kernel_ms": kern_ms},
         "cpu_baseline": cpu,
         "baselines": baselines,

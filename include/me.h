@@ -160,6 +160,26 @@ int me_full_search(int method, const me_job *jobs, int n, const me_params *param
 int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, uint64_t *sse, uint64_t *npix,
                               double *psnr_db, void *stream);
 
+/*
+ * Kernel timing (a profiling aid, off by default).  While on, every call
+ * records a HIP event pair on its stream around its main kernel:
+ *  ME_KT_CLASSIFY  me_classify_babs           classification kernel
+ *  ME_KT_SEARCH    me_texture_recursive,      pipelined search kernel (not the
+ *                  me_shape_search            transparent pre-pass before it)
+ *  ME_KT_FULL      me_full_search             ES / TSS / DS kernel (not the compaction)
+ *  ME_KT_MC        me_motion_compensate_psnr  prediction + SSE kernel (not the per-job sum)
+ * me_kernel_timing: on = 0 or 1 (ME_EINVAL otherwise); affects later calls.
+ * me_kernel_time_ms: waits for every timed call of `kind` on `stream`, writes
+ * the sum of their main-kernel durations in milliseconds (host double) and
+ * their number (host int), and restarts both sums at zero.
+ */
+#define ME_KT_CLASSIFY 0
+#define ME_KT_SEARCH 1
+#define ME_KT_FULL 2
+#define ME_KT_MC 3
+int me_kernel_timing(int on);
+int me_kernel_time_ms(int kind, void *stream, double *total_ms, int *count);
+
 /* Wait for `stream`, then read and clear its device status word:
  * ME_OK, or ME_EDEVICE when a kernel reported a fault condition. */
 int me_device_status(void *stream);

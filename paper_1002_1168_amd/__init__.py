@@ -17,9 +17,11 @@ LIB_PATH = os.path.join(_HERE, "libme.so")
 ME_OK, ME_EINVAL, ME_EALIGN, ME_EHIP, ME_ENOMEM, ME_EEMPTY, ME_EDEVICE, ME_ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
 ME_MB_TRANSPARENT, ME_MB_OPAQUE, ME_MB_BOUNDARY = 0, 1, 2
 ME_ES, ME_TSS, ME_DS = 0, 1, 2
+ME_KT_CLASSIFY, ME_KT_SEARCH, ME_KT_FULL, ME_KT_MC = 0, 1, 2, 3
 
 EXPORTED = ("me_default_params", "me_status_str", "me_shutdown", "me_classify_babs", "me_texture_recursive",
-            "me_shape_search", "me_full_search", "me_motion_compensate_psnr", "me_device_status")
+            "me_shape_search", "me_full_search", "me_motion_compensate_psnr", "me_device_status",
+            "me_kernel_timing", "me_kernel_time_ms")
 
 
 class MeError(RuntimeError):
@@ -76,6 +78,10 @@ def lib():
         L.me_motion_compensate_psnr.restype = i
         L.me_device_status.argtypes = [vp]
         L.me_device_status.restype = i
+        L.me_kernel_timing.argtypes = [i]
+        L.me_kernel_timing.restype = i
+        L.me_kernel_time_ms.argtypes = [i, vp, C.POINTER(C.c_double), C.POINTER(i)]
+        L.me_kernel_time_ms.restype = i
         _lib = L
     return _lib
 
@@ -162,3 +168,15 @@ def me_motion_compensate_psnr(jobs, pred=None, stream=None, check=True):
 
 def me_device_status(stream=None) -> int:
     return lib().me_device_status(stream)
+
+
+def me_kernel_timing(on: bool) -> int:
+    return _check(lib().me_kernel_timing(1 if on else 0), "me_kernel_timing")
+
+
+def me_kernel_time_ms(kind: int, stream=None):
+    """-> (total ms, launches) of the main kernel of `kind` (ME_KT_*) over the
+    timed calls since the previous read."""
+    ms, cnt = C.c_double(), C.c_int()
+    _check(lib().me_kernel_time_ms(int(kind), stream, C.byref(ms), C.byref(cnt)), "me_kernel_time_ms")
+    return float(ms.value), int(cnt.value)

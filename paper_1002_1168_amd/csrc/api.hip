@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -54,6 +55,31 @@ struct PaMemo {
     bool valid = false;
 };
 
+// Event pairs of timed launches of one call kind: in flight until their
+// stop event has completed, then summed.
+struct TimerPool {
+    std::vector<KernelTimer> free, inflight;
+    double total_ms = 0.0;
+    int count = 0;
+    void harvest(bool wait) {
+        size_t k = 0;
+        for (auto &t : inflight) {
+            hipError_t q = wait ? hipEventSynchronize(t.stop) : hipEventQuery(t.stop);
+            if (q == hipErrorNotReady) {
+                inflight[k++] = t;
+                continue;
+            }
+            float ms = 0.f;
+            if (q == hipSuccess && hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
+                total_ms += ms;
+                count++;
+            }
+            free.push_back(t);
+        }
+        inflight.resize(k);
+    }
+};
+
 struct Workspace {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -64,12 +90,14 @@ struct Workspace {
     PaMemo pa;
     unsigned long long *host_acc = nullptr;  // pinned readback for MC
     size_t host_acc_cap = 0;
+    TimerPool timers[A_COUNT];  // main-kernel events per call kind (timing on)
     std::mutex mu;
 };
 
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 int g_arch_ok = -1;  // -1 unknown, 0 no, 1 yes
+std::atomic<int> g_timing{0};
 
 int hip_err(hipError_t e) { return e == hipSuccess ? ME_OK : ME_EHIP; }
 
@@ -113,6 +141,27 @@ int get_ws(void *stream, Workspace **out) {
 }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Event pair for the main kernel of a call of `kind` (false when timing is off).
+bool timer_for(Workspace &w, int kind, KernelTimer *out) {
+    if (!g_timing.load(std::memory_order_relaxed)) return false;
+    TimerPool &p = w.timers[kind];
+    p.harvest(false);
+    KernelTimer t;
+    if (!p.free.empty()) {
+        t = p.free.back();
+        p.free.pop_back();
+    } else {
+        if (hipEventCreate(&t.start) != hipSuccess) return false;
+        if (hipEventCreate(&t.stop) != hipSuccess) {
+            hipEventDestroy(t.start);
+            return false;
+        }
+    }
+    p.inflight.push_back(t);
+    *out = t;
+    return true;
+}
 
 // Copy `blob` to the start of the arena of `kind` (skipped when the arena
 // still holds exactly these bytes), zero `zero_bytes` after it and reserve
@@ -385,11 +434,12 @@ int run_pa(const me_job *jobs, int n, const me_params *params, bool shape_only, 
     rc = upload(*w, A_PA, m.blob, zero, &base, &zb);
     if (rc) return rc;
     int workers = std::min(m.nlines, pa_worker_cap());
+    KernelTimer kt;
     KParams kp = kparams(params, shape_only);
     return hip_err(launch_pa((const JobDesc *)(base + m.o_jobs), m.n, m.total_mbs, (const ChainDesc *)(base + m.o_ch),
                              (const uint32_t *)(base + m.o_tk), m.nlines, (unsigned long long *)(zb + o_prog),
                              (uint32_t *)(zb + o_ctr), (uint32_t *)(zb + o_mask), m.mask_words, w->status, kp,
-                             workers, w->stream));
+                             workers, w->stream, timer_for(*w, A_PA, &kt) ? &kt : nullptr));
 }
 
 }  // namespace
@@ -437,6 +487,13 @@ void me_shutdown(void) {
             if (s.ev) hipEventDestroy(s.ev);
         }
         if (w->host_acc) hipHostFree(w->host_acc);
+        for (auto &p : w->timers) {
+            for (auto *v : {&p.free, &p.inflight})
+                for (auto &t : *v) {
+                    hipEventDestroy(t.start);
+                    hipEventDestroy(t.stop);
+                }
+        }
         hipSetDevice(cur);
         delete w;
     }
@@ -478,7 +535,9 @@ int me_classify_babs(const me_frame *frames, int n, uint8_t *const *mb_class, ui
     uint8_t *base = nullptr, *zb = nullptr;
     rc = upload(*w, A_CLASSIFY, blob, 0, &base, &zb);
     if (rc) return rc;
-    return hip_err(launch_classify((const JobDesc *)(base + o), n, (int)total, w->stream));
+    KernelTimer kt;
+    return hip_err(launch_classify((const JobDesc *)(base + o), n, (int)total, w->stream,
+                                   timer_for(*w, A_CLASSIFY, &kt) ? &kt : nullptr));
 }
 
 int me_texture_recursive(const me_job *jobs, int n, const me_params *params, const me_net *net, void *stream) {
@@ -526,8 +585,9 @@ int me_full_search(int method, const me_job *jobs, int n, const me_params *param
     rc = upload(*w, A_SEARCH, blob, 256, &base, &zb, full_search_scratch((int)total), &sb);
     if (rc) return rc;
     KParams kp = kparams(params, false);
+    KernelTimer kt;
     return hip_err(launch_full_search(method, (const JobDesc *)(base + o), n, (int)total, kp, (uint32_t *)zb,
-                                      (uint32_t *)sb, w->stream));
+                                      (uint32_t *)sb, w->stream, timer_for(*w, A_SEARCH, &kt) ? &kt : nullptr));
 }
 
 int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, uint64_t *sse, uint64_t *npix,
@@ -564,7 +624,9 @@ int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, u
     rc = upload(*w, A_MC, blob, 0, &base, &zb, acc_bytes + mc_scratch((int)total), &sb);
     if (rc) return rc;
     unsigned long long *acc = (unsigned long long *)sb;
-    rc = hip_err(launch_mc((const JobDesc *)(base + o), n, (int)total, (uint32_t *)(sb + acc_bytes), acc, w->stream));
+    KernelTimer kt;
+    rc = hip_err(launch_mc((const JobDesc *)(base + o), n, (int)total, (uint32_t *)(sb + acc_bytes), acc, w->stream,
+                           timer_for(*w, A_MC, &kt) ? &kt : nullptr));
     if (rc) return rc;
     if (w->host_acc_cap < acc_bytes) {
         if (w->host_acc) hipHostFree(w->host_acc);
@@ -591,6 +653,27 @@ int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, u
         }
     }
     return status;
+}
+
+int me_kernel_timing(int on) {
+    if (on != 0 && on != 1) return ME_EINVAL;
+    g_timing.store(on, std::memory_order_relaxed);
+    return ME_OK;
+}
+
+int me_kernel_time_ms(int kind, void *stream, double *total_ms, int *count) {
+    if (kind < 0 || kind >= A_COUNT || !total_ms || !count) return ME_EINVAL;
+    Workspace *w = nullptr;
+    int rc = get_ws(stream, &w);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(w->mu);
+    TimerPool &p = w->timers[kind];
+    p.harvest(true);
+    *total_ms = p.total_ms;
+    *count = p.count;
+    p.total_ms = 0.0;
+    p.count = 0;
+    return ME_OK;
 }
 
 int me_device_status(void *stream) {

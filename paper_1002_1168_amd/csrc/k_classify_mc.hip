@@ -216,23 +216,28 @@ int flat_chunk(int total_units, int per_cu) {
     return (int)(c < 1 ? 1 : c);
 }
 
-hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_t s) {
+hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_t s, const KernelTimer *t) {
     if (total_mbs <= 0) return hipSuccess;
     const int nq = (total_mbs + 3) / 4;
     const int chunk = (flat_chunk(nq, 8) + 3) / 4 * 4;
+    timer_mark(t, true, s);
     hipLaunchKernelGGL(classify_kernel, dim3((nq + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    timer_mark(t, false, s);
+    return e;
 }
 
 size_t mc_scratch(int total_mbs) { return (size_t)total_mbs * 8; }
 
 hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, unsigned long long *acc,
-                     hipStream_t s) {
+                     hipStream_t s, const KernelTimer *t) {
     if (total_mbs <= 0) return hipSuccess;
     const int nq = (total_mbs + 3) / 4;
     const int chunk = (flat_chunk(nq, 8) + 3) / 4 * 4;
+    timer_mark(t, true, s);
     hipLaunchKernelGGL(mc_kernel, dim3((nq + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk, part);
     hipError_t e = hipGetLastError();
+    timer_mark(t, false, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(mc_reduce_kernel, dim3(n), dim3(256), 0, s, jobs, part, acc);
     return hipGetLastError();

@@ -708,7 +708,7 @@ size_t pa_lds_bytes(int S) {
 
 hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainDesc *chains, const uint32_t *tickets,
                      int nlines, unsigned long long *progress, uint32_t *counter, uint32_t *masks, int mask_words,
-                     uint32_t *status, const KParams &kp, int workers, hipStream_t s) {
+                     uint32_t *status, const KParams &kp, int workers, hipStream_t s, const KernelTimer *t) {
     uint32_t *tmask = masks, *bmask = masks + (size_t)nlines * mask_words;
     if (total_mbs > 0) {
         hipLaunchKernelGGL(pa_prepass, dim3((total_mbs + 255) / 256), dim3(256), 0, s, jobs, njobs, total_mbs, tmask,
@@ -720,13 +720,16 @@ hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainD
     PaArgs a{jobs, chains, tickets, nlines, progress, counter, tmask, bmask, mask_words, status, kp,
              (rows + 3) & ~3, rows};
     const size_t lds = pa_lds_bytes(kp.S);
+    timer_mark(t, true, s);
     switch (plan_elems(kp.S)) {
         case 4: hipLaunchKernelGGL(pa_kernel<4>, dim3(workers), dim3(64), lds, s, a); break;
         case 12: hipLaunchKernelGGL(pa_kernel<12>, dim3(workers), dim3(64), lds, s, a); break;
         case 28: hipLaunchKernelGGL(pa_kernel<28>, dim3(workers), dim3(64), lds, s, a); break;
         default: hipLaunchKernelGGL(pa_kernel<0>, dim3(workers), dim3(64), lds, s, a); break;
     }
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    timer_mark(t, false, s);
+    return e;
 }
 
 }  // namespace me

@@ -362,7 +362,7 @@ size_t es_lds_bytes(int S) { return (size_t)(4 * es_copy_dwords(S) + 64) * 4 + 4
 size_t full_search_scratch(int total_mbs) { return (size_t)total_mbs * 4; }
 
 hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_mbs, const KParams &kp,
-                              uint32_t *counters, uint32_t *list, hipStream_t s) {
+                              uint32_t *counters, uint32_t *list, hipStream_t s, const KernelTimer *t) {
     if (total_mbs <= 0) return hipSuccess;
     hipLaunchKernelGGL(compact_kernel, dim3((total_mbs + 255) / 256), dim3(256), 0, s, jobs, n, total_mbs, list,
                        counters);
@@ -370,6 +370,7 @@ hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_
     if (e != hipSuccess) return e;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    timer_mark(t, true, s);
     if (method == ME_ES) {
         size_t lds = es_lds_bytes(kp.S);
         int blocks = std::min(total_mbs, cus * 8);
@@ -378,7 +379,9 @@ hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_
         int blocks = std::min(total_mbs, cus * 16);
         hipLaunchKernelGGL(tss_ds_kernel, dim3(blocks), dim3(64), 0, s, jobs, list, counters, kp, method);
     }
-    return hipGetLastError();
+    e = hipGetLastError();
+    timer_mark(t, false, s);
+    return e;
 }
 
 }  // namespace me

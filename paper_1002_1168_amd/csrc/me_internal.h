@@ -51,18 +51,27 @@ struct KParams {
 enum : uint32_t { ST_SPIN_TIMEOUT = 1u, ST_BAD_CLASS = 2u, ST_ABORT = 4u };
 
 // ------------------------------------------------------------- launches
+// Optional event pair recorded around the main kernel of a launch (profiling).
+struct KernelTimer {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+inline void timer_mark(const KernelTimer *t, bool start, hipStream_t s) {
+    if (t) hipEventRecord(start ? t->start : t->stop, s);
+}
+
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
-hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_t s);
+hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_t s, const KernelTimer *t = nullptr);
 int flat_chunk(int total_mbs, int per_cu);
 hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainDesc *chains, const uint32_t *tickets,
                      int nlines, unsigned long long *progress, uint32_t *counter, uint32_t *masks, int mask_words,
-                     uint32_t *status, const KParams &kp, int workers, hipStream_t s);
+                     uint32_t *status, const KParams &kp, int workers, hipStream_t s,
+                     const KernelTimer *t = nullptr);
 size_t pa_lds_bytes(int S);
 hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_mbs, const KParams &kp,
-                              uint32_t *counters, uint32_t *list, hipStream_t s);
+                              uint32_t *counters, uint32_t *list, hipStream_t s, const KernelTimer *t = nullptr);
 size_t full_search_scratch(int total_mbs);
 hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, unsigned long long *acc,
-                     hipStream_t s);
+                     hipStream_t s, const KernelTimer *t = nullptr);
 size_t mc_scratch(int total_mbs);
 
 int pa_worker_cap();

@@ -105,3 +105,13 @@ def test_psnr_requires_host_outputs():
     L = me.lib()
     ja = (me.me_job * 1)(job())
     assert L.me_motion_compensate_psnr(ja, 1, None, None, None, None, None) == me.ME_EINVAL
+
+
+def test_kernel_timing_validation():
+    L = me.lib()
+    assert L.me_kernel_timing(2) == me.ME_EINVAL
+    assert L.me_kernel_timing(0) == me.ME_OK
+    ms, cnt = C.c_double(), C.c_int()
+    assert L.me_kernel_time_ms(4, None, C.byref(ms), C.byref(cnt)) == me.ME_EINVAL
+    assert L.me_kernel_time_ms(-1, None, C.byref(ms), C.byref(cnt)) == me.ME_EINVAL
+    assert L.me_kernel_time_ms(me.ME_KT_SEARCH, None, None, C.byref(cnt)) == me.ME_EINVAL

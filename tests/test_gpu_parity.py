@@ -261,3 +261,26 @@ def test_pa_repeat_launches_identical(torch_cuda):
         got = gpu_pa(ds, list(range(seq.vops)), p, 39)
         for v in range(seq.vops):
             assert_same(got[v], want[v], f"rep {rep} vop {v}")
+
+
+def test_kernel_timing_counts_each_launch(torch_cuda):
+    """The library's kernel events: one duration per timed call, positive,
+    and the timed results still equal the oracle's."""
+    seq = synth.qcif_ellipse(seed=1, frames=4)
+    p = me.me_default_params(search_range=7)
+    ds = dseq(seq)
+    gpu_classify(ds)
+    from paper_1002_1168_amd.device import stream_handle
+    s = stream_handle()
+    me.me_kernel_timing(True)
+    try:
+        me.me_kernel_time_ms(me.ME_KT_SEARCH, s)
+        got = None
+        for _ in range(3):
+            got = gpu_pa(ds, [0], p, 3)
+        total, count = me.me_kernel_time_ms(me.ME_KT_SEARCH, s)
+    finally:
+        me.me_kernel_timing(False)
+    assert count == 3 and total > 0.0
+    assert_same(got[0], oracle_pa(seq, 0, p, 3), "timed")
+    assert me.me_kernel_time_ms(me.ME_KT_SEARCH, s) == (0.0, 0)
