@@ -18,9 +18,11 @@
 // A consumer that needs pair p of a neighbour polls the word; when it reads
 // exactly p+1 the vector comes with it, when the neighbour has moved on the
 // vector is read from that pair's mv_int array.  A producer publishes pair p
-// and only then writes pair p's result arrays; it waits for all its earlier
-// stores to complete (s_waitcnt) before every publish, so arrays of pairs
-// < p are complete whenever the word says p+1.  All these accesses are
+// and only then writes pair p's result arrays; before every publish it waits
+// (s_waitcnt) until all its earlier stores have completed, so arrays of
+// pairs < p are complete whenever the word says p+1.  The only loads that
+// may still be in flight at a publish are the next pair's window loads,
+// issued after those stores; the wait leaves them in flight.  All these accesses are
 // device-scope atomics (sc1: served at the device coherence point, never from
 // a per-XCD L2 copy), so no L2 invalidate or write-back is ever issued and the
 // read-only frames stay L2-resident.  A neighbour that is transparent in the
@@ -66,10 +68,25 @@ __device__ __forceinline__ unsigned long long ld64(const unsigned long long *p) 
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Publish (pairs done, vector of the latest pair) after every earlier
-// memory access of this wave has completed.
+// Wait until at most N vector-memory operations of this wave are in flight
+// (and no LDS / scalar-memory operation).  The vector-memory counter
+// completes in issue order, loads and stores alike, so every operation
+// issued before the N most recent ones has completed.
+template <int N>
+__device__ __forceinline__ void wait_vm_at_most() {
+    static_assert(N == 0 || N == 4 || N == 12 || N == 28, "wait count");
+    if constexpr (N == 0) asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    if constexpr (N == 4) asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)" ::: "memory");
+    if constexpr (N == 12) asm volatile("s_waitcnt vmcnt(12) lgkmcnt(0)" ::: "memory");
+    if constexpr (N == 28) asm volatile("s_waitcnt vmcnt(28) lgkmcnt(0)" ::: "memory");
+}
+
+// Publish (pairs done, vector of the latest pair) once every memory access
+// of this wave older than its N most recent vector-memory operations has
+// completed.
+template <int N = 0>
 __device__ __forceinline__ void publish(unsigned long long *p, uint32_t done, uint32_t mvi) {
-    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    wait_vm_at_most<N>();
     __hip_atomic_store(p, ((unsigned long long)mvi << 32) | done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -663,6 +680,14 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
                 }
             }
             const MbOut o = search_mb(D.ptr<const uint32_t>(DW(seed)), c, k, cx, cy, kp);
+            // publish first: the next window's loads (the EM most recent
+            // vector-memory operations) stay in flight across it
+            if (l == 0) {
+                if (EM > 0 && pre)
+                    publish<(EM > 0 ? EM : 0)>(own, need, o.mvi);
+                else
+                    publish(own, need, o.mvi);
+            }
             staged = false;
             if constexpr (EM > 0) {
                 if (pre) {
@@ -673,10 +698,7 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
                     staged = true;
                 }
             }
-            if (l == 0) {
-                publish(own, need, o.mvi);
-                store_result(D, k, o.mv, o.mvi, o.cost, o.iters, o.points);
-            }
+            if (l == 0) store_result(D, k, o.mv, o.mvi, o.cost, o.iters, o.points);
             tx = o.dx;
             ty = o.dy;
             ++p;
