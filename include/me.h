@@ -161,6 +161,51 @@ int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, u
                               double *psnr_db, void *stream);
 
 /*
+ * Batched frame step: many frame pairs (VOP streams of any sizes) per launch,
+ * replayed once per frame step as one HIP graph (Fig. 1 applied to every job
+ * of the step; classification as in me_classify_babs, search as in
+ * me_texture_recursive / me_shape_search, MC + SSE as in
+ * me_motion_compensate_psnr).
+ *
+ * me_batch_create fixes the STRUCTURE of a job set: n, each job's frame
+ * size and stride, which of alpha / mb_class / seed / t_field are set, and
+ * which jobs take an earlier job's mv_int as T (pipelined as in
+ * me_texture_recursive).  Parameters and flags are fixed too:
+ *  ME_BATCH_SHAPE     score every non-transparent MB on its BAB (as me_shape_search; alpha required)
+ *  ME_BATCH_AUTOTUNE  pick the launch configuration by timing candidates on
+ *                     `jobs` (their outputs and mb_class are written; every
+ *                     configuration gives the same results)
+ * The batch is bound to `stream` and to the current device.  *out receives
+ * the handle (NULL on error).
+ *
+ * me_batch_step runs one frame step for `jobs` (same n and structure; any
+ * device buffers): for every job with alpha and mb_class, the classes of
+ * its cur alpha are WRITTEN to mb_class (so mb_class is an output here);
+ * then the search writes mv, mv_int, cost, iters, points; then the SSE and
+ * pixel counts over the VOP are summed on the device.  Asynchronous; the
+ * `jobs` array may be reused on return.  ME_EINVAL if the structure differs.
+ *
+ * me_batch_results waits for the last step and writes its per-job SSE,
+ * pixel count and PSNR (host arrays of n, in job order; as
+ * me_motion_compensate_psnr), ME_EEMPTY if a job has no VOP pixel,
+ * ME_EDEVICE if a kernel raised the device status word (then cleared).
+ *
+ * me_batch_config writes the launch configuration in use (ncfg >= 4):
+ * search workers, window staging (1 staged plan, 0 generic), dependency-poll
+ * back-off (s_sleep units), MB blocks per CU of the flat kernels.
+ * me_batch_destroy waits for the batch's stream and frees it (NULL is a no-op).
+ */
+typedef struct me_batch me_batch;
+#define ME_BATCH_SHAPE 1u
+#define ME_BATCH_AUTOTUNE 2u
+int me_batch_create(const me_job *jobs, int n, const me_params *params, uint32_t flags, void *stream,
+                    me_batch **out);
+int me_batch_step(me_batch *b, const me_job *jobs, int n);
+int me_batch_results(me_batch *b, uint64_t *sse, uint64_t *npix, double *psnr_db, int n);
+int me_batch_config(const me_batch *b, int32_t *cfg, int ncfg);
+void me_batch_destroy(me_batch *b);
+
+/*
  * Kernel timing (a profiling aid, off by default).  While on, every call
  * records a HIP event pair on its stream around its main kernel:
  *  ME_KT_CLASSIFY  me_classify_babs           classification kernel

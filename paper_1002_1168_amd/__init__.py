@@ -18,10 +18,12 @@ ME_OK, ME_EINVAL, ME_EALIGN, ME_EHIP, ME_ENOMEM, ME_EEMPTY, ME_EDEVICE, ME_ENODE
 ME_MB_TRANSPARENT, ME_MB_OPAQUE, ME_MB_BOUNDARY = 0, 1, 2
 ME_ES, ME_TSS, ME_DS = 0, 1, 2
 ME_KT_CLASSIFY, ME_KT_SEARCH, ME_KT_FULL, ME_KT_MC = 0, 1, 2, 3
+ME_BATCH_SHAPE, ME_BATCH_AUTOTUNE = 1, 2
 
 EXPORTED = ("me_default_params", "me_status_str", "me_shutdown", "me_classify_babs", "me_texture_recursive",
             "me_shape_search", "me_full_search", "me_motion_compensate_psnr", "me_device_status",
-            "me_kernel_timing", "me_kernel_time_ms")
+            "me_kernel_timing", "me_kernel_time_ms", "me_batch_create", "me_batch_step", "me_batch_results",
+            "me_batch_config", "me_batch_destroy")
 
 
 class MeError(RuntimeError):
@@ -82,6 +84,16 @@ def lib():
         L.me_kernel_timing.restype = i
         L.me_kernel_time_ms.argtypes = [i, vp, C.POINTER(C.c_double), C.POINTER(i)]
         L.me_kernel_time_ms.restype = i
+        L.me_batch_create.argtypes = [C.POINTER(me_job), i, C.POINTER(me_params), C.c_uint32, vp, C.POINTER(vp)]
+        L.me_batch_create.restype = i
+        L.me_batch_step.argtypes = [vp, C.POINTER(me_job), i]
+        L.me_batch_step.restype = i
+        L.me_batch_results.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_double), i]
+        L.me_batch_results.restype = i
+        L.me_batch_config.argtypes = [vp, C.POINTER(C.c_int32), i]
+        L.me_batch_config.restype = i
+        L.me_batch_destroy.argtypes = [vp]
+        L.me_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -180,3 +192,44 @@ def me_kernel_time_ms(kind: int, stream=None):
     ms, cnt = C.c_double(), C.c_int()
     _check(lib().me_kernel_time_ms(int(kind), stream, C.byref(ms), C.byref(cnt)), "me_kernel_time_ms")
     return float(ms.value), int(cnt.value)
+
+
+class Batch:
+    """A batched frame step (``me_batch_*``): created from one job set,
+    stepped with job sets of the same structure, one graph launch per step."""
+
+    def __init__(self, jobs, params: me_params, flags: int = 0, stream=None):
+        ja, n = _arr(me_job, jobs)
+        h = C.c_void_p()
+        _check(lib().me_batch_create(ja, n, C.byref(params), int(flags), stream, C.byref(h)), "me_batch_create")
+        self.handle, self.n = h, n
+
+    def step(self, jobs, check=True) -> int:
+        ja, n = _arr(me_job, jobs)
+        rc = lib().me_batch_step(self.handle, ja, n)
+        return _check(rc, "me_batch_step") if check else rc
+
+    def results(self, check=True):
+        """-> (sse list, npix list, psnr_db list, status) of the last step."""
+        n = self.n
+        sse, npx, ps = (C.c_uint64 * n)(), (C.c_uint64 * n)(), (C.c_double * n)()
+        rc = lib().me_batch_results(self.handle, sse, npx, ps, n)
+        if check and rc != ME_OK:
+            raise MeError(rc, "me_batch_results")
+        return list(sse), list(npx), list(ps), rc
+
+    def config(self) -> dict:
+        c = (C.c_int32 * 4)()
+        _check(lib().me_batch_config(self.handle, c, 4), "me_batch_config")
+        return {"workers": c[0], "staging": "plan" if c[1] else "generic", "poll_sleep": c[2], "flat_per_cu": c[3]}
+
+    def close(self) -> None:
+        if self.handle:
+            lib().me_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,420 @@
+// Batched frame step: classification, the proposed search and motion
+// compensation + SSE for a fixed job structure (many VOP streams of any
+// sizes), captured once into a HIP graph and replayed per frame step with
+// only the job table rewritten.  The launch configuration (search workers,
+// window staging, dependency-poll back-off, MBs per block of the flat
+// kernels) is chosen at creation, optionally by timing the candidates on
+// the first step's data.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "host.h"
+#include "me_internal.h"
+
+using namespace me;
+using namespace me::host;
+
+struct me_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int n = 0;
+    bool shape = false;
+    me_params params{};
+    PaMemo plan;                    // chain structure, tickets, descriptor template
+    std::vector<JobDesc> tmpl;      // chain-ordered descriptors of the creating job set
+    uint8_t *dev = nullptr;         // one allocation, layout below
+    size_t o_zero = 0, zero_bytes = 0, o_part = 0, o_acc = 0, o_status = 0;
+    void *host[2] = {nullptr, nullptr};  // pinned job-table staging
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int slot = 0;
+    unsigned long long *host_acc = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t cfg[4] = {0, 1, 2, 8};  // workers, window staging (1 plan, 0 generic), poll sleep, flat MBs/CU
+    bool stepped = false;
+    std::mutex mu;
+};
+
+namespace {
+
+constexpr uint32_t kFlagsKnown = ME_BATCH_SHAPE | ME_BATCH_AUTOTUNE;
+
+// Same structure as the creating job set: sizes, strides, which optional
+// buffers are present, and which job feeds which T field.
+int check_structure(const me_batch &b, const me_job *jobs, int n) {
+    if (n != b.n || !jobs) return ME_EINVAL;
+    std::unordered_map<const void *, int> producer;
+    producer.reserve((size_t)n * 2);
+    for (int i = 0; i < n; ++i) {
+        int rc = check_job(jobs[i], b.shape);
+        if (rc) return rc;
+        if (!producer.emplace((const void *)jobs[i].mv_int, i).second) return ME_EINVAL;
+    }
+    for (int p = 0; p < n; ++p) {
+        const int i = b.plan.order[p];
+        const me_job &j = jobs[i];
+        const JobDesc &d = b.tmpl[p];
+        if (j.cur.width != d.width || j.cur.height != d.height || j.cur.stride != d.stride) return ME_EINVAL;
+        if ((j.cur.alpha != nullptr) != (d.cur_a != nullptr)) return ME_EINVAL;
+        if ((j.mb_class != nullptr) != (d.cls != nullptr)) return ME_EINVAL;
+        if ((j.seed != nullptr) != (d.seed != nullptr)) return ME_EINVAL;
+        if ((j.t_field != nullptr) != (d.tf != nullptr)) return ME_EINVAL;
+        int prod = -1;
+        if (j.t_field) {
+            auto it = producer.find((const void *)j.t_field);
+            if (it != producer.end()) prod = it->second;
+        }
+        if (prod != b.plan.prod[i]) return ME_EINVAL;
+    }
+    return ME_OK;
+}
+
+// Chain-ordered job table for `jobs` (structure already checked).
+void fill_table(const me_batch &b, const me_job *jobs, JobDesc *out) {
+    for (int p = 0; p < b.n; ++p) {
+        const me_job &j = jobs[b.plan.order[p]];
+        JobDesc d = b.tmpl[p];
+        d.cur = j.cur.luma;
+        d.ref = j.ref.luma;
+        d.cur_a = j.cur.alpha;
+        d.ref_a = j.ref.alpha;
+        d.cls = j.mb_class;
+        d.tf = (const int16_t *)j.t_field;
+        d.seed = (const int16_t *)j.seed;
+        d.mv = (int16_t *)j.mv;
+        d.mv_int = (int16_t *)j.mv_int;
+        d.cost = j.cost;
+        d.iters = j.iters;
+        d.points = j.points;
+        d.out_u8 = nullptr;
+        d.out_u32 = nullptr;
+        out[p] = d;
+    }
+}
+
+struct Bufs {
+    const JobDesc *jobs;
+    const ChainDesc *chains;
+    const uint32_t *tickets;
+    uint8_t *zero;
+    unsigned long long *progress;
+    uint32_t *counter, *masks, *part, *status;
+    unsigned long long *acc;
+};
+
+Bufs bufs(const me_batch &b) {
+    Bufs r;
+    const PaMemo &m = b.plan;
+    r.jobs = (const JobDesc *)(b.dev + m.o_jobs);
+    r.chains = (const ChainDesc *)(b.dev + m.o_ch);
+    r.tickets = (const uint32_t *)(b.dev + m.o_tk);
+    r.zero = b.dev + b.o_zero;
+    r.progress = (unsigned long long *)r.zero;
+    r.counter = (uint32_t *)(r.zero + align_up((size_t)m.nlines * 8, 256));
+    r.masks = (uint32_t *)((uint8_t *)r.counter + 256);
+    r.part = (uint32_t *)(b.dev + b.o_part);
+    r.acc = (unsigned long long *)(b.dev + b.o_acc);
+    r.status = (uint32_t *)(b.dev + b.o_status);
+    return r;
+}
+
+KParams batch_kparams(const me_batch &b, int sleep) {
+    KParams kp = kparams(&b.params, b.shape);
+    kp.poll_sleep = sleep;
+    return kp;
+}
+
+hipError_t launch_search(const me_batch &b, const Bufs &u, const int32_t *cfg, hipStream_t s) {
+    hipError_t e = launch_fill_u32((uint32_t *)u.zero, b.zero_bytes / 4, 0u, s);
+    if (e != hipSuccess) return e;
+    return launch_pa(u.jobs, b.n, b.plan.total_mbs, u.chains, u.tickets, b.plan.nlines, u.progress, u.counter, u.masks,
+                     b.plan.mask_words, u.status, batch_kparams(b, cfg[2]), cfg[0], s, nullptr, cfg[1] == 0);
+}
+
+// The whole frame step with configuration `cfg` on stream `s`.
+hipError_t launch_step(const me_batch &b, const int32_t *cfg, hipStream_t s) {
+    const Bufs u = bufs(b);
+    hipError_t e = launch_classify(u.jobs, b.n, b.plan.total_mbs, s, nullptr, cfg[3]);
+    if (e != hipSuccess) return e;
+    e = launch_search(b, u, cfg, s);
+    if (e != hipSuccess) return e;
+    return launch_mc(u.jobs, b.n, b.plan.total_mbs, u.part, u.acc, s, nullptr, cfg[3]);
+}
+
+// Fastest of three timed runs of `fn` on the batch's stream (ms), or -1.
+template <class F>
+float time_min(const me_batch &b, hipEvent_t e0, hipEvent_t e1, F fn) {
+    float best = -1.f;
+    for (int r = 0; r < 3; ++r) {
+        if (hipEventRecord(e0, b.stream) != hipSuccess) return -1.f;
+        if (fn() != hipSuccess) return -1.f;
+        if (hipEventRecord(e1, b.stream) != hipSuccess) return -1.f;
+        if (hipEventSynchronize(e1) != hipSuccess) return -1.f;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.f;
+        if (best < 0.f || ms < best) best = ms;
+    }
+    return best;
+}
+
+// Pick the launch configuration by timing the candidates on the creating
+// job set (its outputs are written; every configuration computes the same
+// results).
+int autotune(me_batch &b) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return ME_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return ME_EHIP;
+    }
+    const Bufs u = bufs(b);
+    int rc = ME_OK;
+    int32_t best[4] = {b.cfg[0], b.cfg[1], b.cfg[2], b.cfg[3]};
+    if (launch_classify(u.jobs, b.n, b.plan.total_mbs, b.stream, nullptr, best[3]) != hipSuccess) rc = ME_EHIP;
+    const int cap = std::min(b.plan.nlines, pa_worker_cap());
+    std::vector<int> workers = {cap};
+    for (int w : {cap / 2, cap / 4})
+        if (w >= 64 && w != workers.back()) workers.push_back(w);
+    std::vector<int> staging = {1};
+    if (plan_elems(b.params.search_range) > 0) staging.push_back(0);
+    float best_ms = -1.f;
+    for (int w : workers)
+        for (int st : staging)
+            for (int sl : {1, 2, 4}) {
+                if (rc) break;
+                const int32_t c[4] = {w, st, sl, best[3]};
+                float ms = time_min(b, e0, e1, [&] { return launch_search(b, u, c, b.stream); });
+                if (ms < 0.f) {
+                    rc = ME_EHIP;
+                    break;
+                }
+                if (best_ms < 0.f || ms < best_ms) {
+                    best_ms = ms;
+                    best[0] = w;
+                    best[1] = st;
+                    best[2] = sl;
+                }
+            }
+    best_ms = -1.f;
+    for (int pc : {4, 8, 16}) {
+        if (rc) break;
+        float ms = time_min(b, e0, e1, [&] {
+            hipError_t e = launch_classify(u.jobs, b.n, b.plan.total_mbs, b.stream, nullptr, pc);
+            if (e != hipSuccess) return e;
+            return launch_mc(u.jobs, b.n, b.plan.total_mbs, u.part, u.acc, b.stream, nullptr, pc);
+        });
+        if (ms < 0.f) {
+            rc = ME_EHIP;
+            break;
+        }
+        if (best_ms < 0.f || ms < best_ms) {
+            best_ms = ms;
+            best[3] = pc;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc == ME_OK)
+        for (int i = 0; i < 4; ++i) b.cfg[i] = best[i];
+    return rc;
+}
+
+int capture(me_batch &b) {
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return ME_EHIP;
+    int rc = ME_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        rc = ME_EHIP;
+    } else {
+        hipError_t e = launch_step(b, b.cfg, cs);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (e != hipSuccess || e2 != hipSuccess || !g) {
+            rc = ME_EHIP;
+            if (g) hipGraphDestroy(g);
+        } else if (hipGraphInstantiate(&b.exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            rc = ME_EHIP;
+            hipGraphDestroy(g);
+            b.exec = nullptr;
+        } else {
+            b.graph = g;
+        }
+    }
+    hipStreamDestroy(cs);
+    return rc;
+}
+
+int upload_table(me_batch &b, const me_job *jobs) {
+    const size_t bytes = sizeof(JobDesc) * (size_t)b.n;
+    const int s = b.slot;
+    b.slot ^= 1;
+    if (hipEventSynchronize(b.ev[s]) != hipSuccess) return ME_EHIP;
+    fill_table(b, jobs, (JobDesc *)b.host[s]);
+    if (hipMemcpyAsync(b.dev + b.plan.o_jobs, b.host[s], bytes, hipMemcpyHostToDevice, b.stream) != hipSuccess)
+        return ME_EHIP;
+    if (hipEventRecord(b.ev[s], b.stream) != hipSuccess) return ME_EHIP;
+    return ME_OK;
+}
+
+void release(me_batch *b) {
+    if (!b) return;
+    if (b->stream || b->dev) hipStreamSynchronize(b->stream);
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    for (int s = 0; s < 2; ++s) {
+        if (b->ev[s]) hipEventDestroy(b->ev[s]);
+        if (b->host[s]) hipHostFree(b->host[s]);
+    }
+    if (b->host_acc) hipHostFree(b->host_acc);
+    if (b->dev) hipFree(b->dev);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int me_batch_create(const me_job *jobs, int n, const me_params *params, uint32_t flags, void *stream,
+                    me_batch **out) {
+    if (!out) return ME_EINVAL;
+    *out = nullptr;
+    if (n <= 0 || !jobs || (flags & ~kFlagsKnown)) return ME_EINVAL;
+    int rc = check_params(params);
+    if (rc) return rc;
+    const bool shape = (flags & ME_BATCH_SHAPE) != 0;
+    for (int i = 0; i < n; ++i) {
+        rc = check_job(jobs[i], shape);
+        if (rc) return rc;
+    }
+    me_batch *b = new me_batch();
+    b->n = n;
+    b->shape = shape;
+    b->params = *params;
+    b->stream = (hipStream_t)stream;
+    rc = build_pa(jobs, n, b->plan);
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    if (hipGetDevice(&b->device) != hipSuccess || check_device(b->device) != ME_OK) {
+        delete b;
+        return ME_ENODEV;
+    }
+    const PaMemo &m = b->plan;
+    b->tmpl.resize(n);
+    std::memcpy(b->tmpl.data(), m.blob.data() + m.o_jobs, sizeof(JobDesc) * (size_t)n);
+    // device layout: [jobs | chains | tickets] [zeroed search scratch] [MC partials] [per-job sums] [status]
+    b->o_zero = align_up(m.blob.size(), 256);
+    b->zero_bytes = align_up(align_up((size_t)m.nlines * 8, 256) + 256 + (size_t)m.nlines * m.mask_words * 2 * 4, 256);
+    b->o_part = b->o_zero + b->zero_bytes;
+    b->o_acc = b->o_part + align_up(mc_scratch(m.total_mbs), 256);
+    b->o_status = b->o_acc + align_up((size_t)n * 16, 256);
+    const size_t total = b->o_status + 256;
+    const size_t table = sizeof(JobDesc) * (size_t)n;
+    b->cfg[0] = std::min(m.nlines, pa_worker_cap());
+    b->cfg[1] = 1;
+    b->cfg[2] = 2;
+    b->cfg[3] = 8;
+    if (hipMalloc(&b->dev, total) != hipSuccess) {
+        b->dev = nullptr;
+        release(b);
+        return ME_ENOMEM;
+    }
+    for (int s = 0; s < 2; ++s) {
+        if (hipHostMalloc(&b->host[s], table, hipHostMallocDefault) != hipSuccess) {
+            b->host[s] = nullptr;
+            release(b);
+            return ME_ENOMEM;
+        }
+        if (hipEventCreateWithFlags(&b->ev[s], hipEventDisableTiming) != hipSuccess) {
+            b->ev[s] = nullptr;
+            release(b);
+            return ME_EHIP;
+        }
+    }
+    if (hipHostMalloc((void **)&b->host_acc, (size_t)n * 16, hipHostMallocDefault) != hipSuccess) {
+        b->host_acc = nullptr;
+        release(b);
+        return ME_ENOMEM;
+    }
+    // static tables once; the status word starts clear
+    if (hipMemcpy(b->dev, m.blob.data(), m.blob.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        launch_fill_u32((uint32_t *)(b->dev + b->o_status), 64, 0u, b->stream) != hipSuccess) {
+        release(b);
+        return ME_EHIP;
+    }
+    if (flags & ME_BATCH_AUTOTUNE) {
+        rc = upload_table(*b, jobs);
+        if (!rc) rc = autotune(*b);
+        if (rc) {
+            release(b);
+            return rc;
+        }
+    }
+    rc = capture(*b);
+    if (rc) {
+        release(b);
+        return rc;
+    }
+    *out = b;
+    return ME_OK;
+}
+
+int me_batch_step(me_batch *b, const me_job *jobs, int n) {
+    if (!b) return ME_EINVAL;
+    std::lock_guard<std::mutex> lk(b->mu);
+    int rc = check_structure(*b, jobs, n);
+    if (rc) return rc;
+    rc = upload_table(*b, jobs);
+    if (rc) return rc;
+    if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return ME_EHIP;
+    b->stepped = true;
+    return ME_OK;
+}
+
+int me_batch_results(me_batch *b, uint64_t *sse, uint64_t *npix, double *psnr_db, int n) {
+    if (!b || !sse || !npix || !psnr_db || n != b->n) return ME_EINVAL;
+    std::lock_guard<std::mutex> lk(b->mu);
+    if (!b->stepped) return ME_EINVAL;
+    const Bufs u = bufs(*b);
+    if (hipMemcpyAsync(b->host_acc, u.acc, (size_t)n * 16, hipMemcpyDeviceToHost, b->stream) != hipSuccess)
+        return ME_EHIP;
+    uint32_t st = 0;
+    if (hipMemcpyAsync(&st, u.status, 4, hipMemcpyDeviceToHost, b->stream) != hipSuccess) return ME_EHIP;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return ME_EHIP;
+    int status = ME_OK;
+    for (int p = 0; p < n; ++p) {
+        const int i = b->plan.order[p];
+        sse[i] = b->host_acc[2 * p];
+        npix[i] = b->host_acc[2 * p + 1];
+        if (npix[i] == 0) {
+            psnr_db[i] = NAN;
+            status = ME_EEMPTY;
+        } else if (sse[i] == 0) {
+            psnr_db[i] = INFINITY;
+        } else {
+            psnr_db[i] = 10.0 * std::log10(255.0 * 255.0 * (double)npix[i] / (double)sse[i]);
+        }
+    }
+    if (st) {
+        if (launch_fill_u32(u.status, 64, 0u, b->stream) != hipSuccess) return ME_EHIP;
+        if (hipStreamSynchronize(b->stream) != hipSuccess) return ME_EHIP;
+        return ME_EDEVICE;
+    }
+    return status;
+}
+
+int me_batch_config(const me_batch *b, int32_t *cfg, int ncfg) {
+    if (!b || !cfg || ncfg < 4) return ME_EINVAL;
+    for (int i = 0; i < 4; ++i) cfg[i] = b->cfg[i];
+    return ME_OK;
+}
+
+void me_batch_destroy(me_batch *b) { release(b); }
+
+}  // extern "C"

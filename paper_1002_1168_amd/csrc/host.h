@@ -1,0 +1,56 @@
+// Host-side helpers shared by the C-ABI entry points: argument validation,
+// job descriptors, and the chain / ticket tables of the pipelined search.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <vector>
+
+#include "me.h"
+#include "me_internal.h"
+
+namespace me {
+namespace host {
+
+constexpr int kMaxDim = 4096;  // ticket packing: 8 bits per MB coordinate
+constexpr int kMaxChains = 65536;
+constexpr int kSpinLimit = 1 << 22;
+
+// The last search call's prepared launch (reused when the next call passes
+// byte-identical jobs and parameters).
+struct PaMemo {
+    std::vector<uint8_t> key;  // jobs + params + mode
+    std::vector<uint8_t> blob;
+    size_t o_jobs = 0, o_ch = 0, o_tk = 0;
+    int n = 0, total_mbs = 0, nlines = 0, mask_words = 0;
+    std::vector<int> order;  // chain-ordered descriptor i describes job order[i]
+    std::vector<int> prod;   // per job: the earlier job whose mv_int is its T field, or -1
+    bool valid = false;
+};
+
+int hip_err(hipError_t e);
+// ME_OK when `dev` is a gfx950 device (cached after the first query).
+int check_device(int dev);
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline bool al4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
+
+// Append `count` objects to `b` at a 64-byte boundary; returns their offset.
+template <class T>
+inline size_t put(std::vector<uint8_t> &b, const T *p, size_t count) {
+    size_t off = align_up(b.size(), 64);
+    b.resize(off + sizeof(T) * count);
+    if (count) std::memcpy(b.data() + off, p, sizeof(T) * count);
+    return off;
+}
+
+int check_frame(const me_frame &f, bool need_alpha);
+int check_params(const me_params *p);
+int check_job(const me_job &j, bool need_alpha);
+KParams kparams(const me_params *p, bool shape_only);
+JobDesc job_desc(const me_job &j);
+// Chains, chain-ordered descriptors and the ticket order of a job set.
+int build_pa(const me_job *jobs, int n, PaMemo &m);
+
+}  // namespace host
+}  // namespace me

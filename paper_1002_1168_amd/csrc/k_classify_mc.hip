@@ -50,7 +50,9 @@ __device__ __forceinline__ QuadIter quads(int total, int chunk) {
 }
 
 // n = number of pixels with alpha != 0 -> transparent (0), opaque (256),
-// boundary; BAB word w = rows 2w, 2w+1 with column i at bit (row&1)*16 + i.
+// boundary, written to the job's class array; BAB word w = rows 2w, 2w+1
+// with column i at bit (row&1)*16 + i.  Jobs without alpha or without a
+// class array (rectangular frames) are skipped.
 __global__ __launch_bounds__(256) void classify_kernel(const JobDesc *jobs, int n, int total, int chunk) {
     const int l = lane(), r = l & 15;
     QuadIter it = quads(total, chunk);
@@ -64,16 +66,21 @@ __global__ __launch_bounds__(256) void classify_kernel(const JobDesc *jobs, int 
         const JobDesc &J = jobs[ji];
         const int k = m - J.mb_base;
         const int h = k % J.wm, v = k / J.wm;
-        const uint32_t *row = (const uint32_t *)(J.cur_a + (size_t)(16 * v + r) * J.stride + 16 * h);
-        uint32_t a[4];
+        const bool has = J.cur_a != nullptr && J.cls != nullptr;
+        uint32_t a[4] = {0u, 0u, 0u, 0u};
+        if (has) {
+            const uint32_t *row = (const uint32_t *)(J.cur_a + (size_t)(16 * v + r) * J.stride + 16 * h);
 #pragma unroll
-        for (int w = 0; w < 4; ++w) a[w] = ldg32(row + w);
+            for (int w = 0; w < 4; ++w) a[w] = ldg32(row + w);
+        }
         const uint32_t bits = nz16(a);
         const int tot = row_sum(__builtin_popcount(bits));
         const uint32_t odd = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0xB1, 0xF, 0xF, true);
-        if (valid) {
+        if (valid && has) {
             if (J.out_u32 && (r & 1) == 0) J.out_u32[(size_t)k * 8 + (r >> 1)] = bits | (odd << 16);
-            if (r == 0) J.out_u8[k] = (uint8_t)(tot == 0 ? ME_MB_TRANSPARENT : (tot == 256 ? ME_MB_OPAQUE : ME_MB_BOUNDARY));
+            if (r == 0)
+                const_cast<uint8_t *>(J.cls)[k] =
+                    (uint8_t)(tot == 0 ? ME_MB_TRANSPARENT : (tot == 256 ? ME_MB_OPAQUE : ME_MB_BOUNDARY));
         }
     }
 }
@@ -216,10 +223,11 @@ int flat_chunk(int total_units, int per_cu) {
     return (int)(c < 1 ? 1 : c);
 }
 
-hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_t s, const KernelTimer *t) {
+hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_t s, const KernelTimer *t,
+                           int per_cu) {
     if (total_mbs <= 0) return hipSuccess;
     const int nq = (total_mbs + 3) / 4;
-    const int chunk = (flat_chunk(nq, 8) + 3) / 4 * 4;
+    const int chunk = (flat_chunk(nq, per_cu) + 3) / 4 * 4;
     timer_mark(t, true, s);
     hipLaunchKernelGGL(classify_kernel, dim3((nq + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk);
     hipError_t e = hipGetLastError();
@@ -230,10 +238,10 @@ hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_
 size_t mc_scratch(int total_mbs) { return (size_t)total_mbs * 8; }
 
 hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, unsigned long long *acc,
-                     hipStream_t s, const KernelTimer *t) {
+                     hipStream_t s, const KernelTimer *t, int per_cu) {
     if (total_mbs <= 0) return hipSuccess;
     const int nq = (total_mbs + 3) / 4;
-    const int chunk = (flat_chunk(nq, 8) + 3) / 4 * 4;
+    const int chunk = (flat_chunk(nq, per_cu) + 3) / 4 * 4;
     timer_mark(t, true, s);
     hipLaunchKernelGGL(mc_kernel, dim3((nq + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk, part);
     hipError_t e = hipGetLastError();

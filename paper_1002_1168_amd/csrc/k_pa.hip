@@ -638,7 +638,12 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
                     if (l == 0) atomicOr(a.status, ST_SPIN_TIMEOUT | ST_ABORT);
                     return;
                 }
-                __builtin_amdgcn_s_sleep(2);
+                if (kp.poll_sleep == 1)
+                    __builtin_amdgcn_s_sleep(1);
+                else if (kp.poll_sleep == 2)
+                    __builtin_amdgcn_s_sleep(2);
+                else if (kp.poll_sleep >= 4)
+                    __builtin_amdgcn_s_sleep(4);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) val[i] = ld64(w[i]);
             }
@@ -706,14 +711,14 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
     }
 }
 
+}  // namespace
+
 // elements per lane of the staging plan for range S (0: generic loop)
 int plan_elems(int S) {
     const int rows = 2 * S + 18, dw = ((rows + 3) & ~3) >> 2;
     const int e = (rows * dw + 63) / 64;
     return e <= 4 ? 4 : e <= 12 ? 12 : e <= 28 ? 28 : 0;
 }
-
-}  // namespace
 
 int pa_worker_cap() {
     int dev = 0, cus = 0;
@@ -722,15 +727,16 @@ int pa_worker_cap() {
     return cus * 16;
 }
 
-size_t pa_lds_bytes(int S) {
+size_t pa_lds_bytes(int S, bool generic) {
     const int rows = 2 * S + 18, pitch = (rows + 3) & ~3;
     const size_t one = (size_t)rows * pitch + 16;
-    return 1024 + (plan_elems(S) > 0 ? 2 : 1) * one;
+    return 1024 + (plan_elems(S) > 0 && !generic ? 2 : 1) * one;
 }
 
 hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainDesc *chains, const uint32_t *tickets,
                      int nlines, unsigned long long *progress, uint32_t *counter, uint32_t *masks, int mask_words,
-                     uint32_t *status, const KParams &kp, int workers, hipStream_t s, const KernelTimer *t) {
+                     uint32_t *status, const KParams &kp, int workers, hipStream_t s, const KernelTimer *t,
+                     bool generic) {
     uint32_t *tmask = masks, *bmask = masks + (size_t)nlines * mask_words;
     if (total_mbs > 0) {
         hipLaunchKernelGGL(pa_prepass, dim3((total_mbs + 255) / 256), dim3(256), 0, s, jobs, njobs, total_mbs, tmask,
@@ -741,9 +747,9 @@ hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainD
     const int rows = 2 * kp.S + 18;
     PaArgs a{jobs, chains, tickets, nlines, progress, counter, tmask, bmask, mask_words, status, kp,
              (rows + 3) & ~3, rows};
-    const size_t lds = pa_lds_bytes(kp.S);
+    const size_t lds = pa_lds_bytes(kp.S, generic);
     timer_mark(t, true, s);
-    switch (plan_elems(kp.S)) {
+    switch (generic ? 0 : plan_elems(kp.S)) {
         case 4: hipLaunchKernelGGL(pa_kernel<4>, dim3(workers), dim3(64), lds, s, a); break;
         case 12: hipLaunchKernelGGL(pa_kernel<12>, dim3(workers), dim3(64), lds, s, a); break;
         case 28: hipLaunchKernelGGL(pa_kernel<28>, dim3(workers), dim3(64), lds, s, a); break;

@@ -14,13 +14,13 @@ namespace me {
 // Device view of one frame pair (one me_job) or one frame (classification).
 struct JobDesc {
     const uint8_t *cur, *ref, *cur_a, *ref_a;
-    const uint8_t *cls;
+    const uint8_t *cls;   // MB classes (written by the classification kernel)
     const int16_t *tf, *seed;
     int16_t *mv, *mv_int;
     uint32_t *cost;
     uint8_t *iters;
     uint16_t *points;
-    uint8_t *out_u8;      // classification: class out; MC: prediction out (nullable)
+    uint8_t *out_u8;      // MC: prediction out (nullable)
     uint32_t *out_u32;    // classification: BAB words out (nullable)
     int32_t width, height, stride, wm, hm;
     int32_t mb_base;        // first flat MB index of this job in multi-job grids
@@ -45,6 +45,7 @@ struct ChainDesc {
 
 struct KParams {
     int32_t S, theta, eps, max_step, k_max, half_pel, shape_only, spin_limit;
+    int32_t poll_sleep;  // s_sleep units between dependency polls (0, 1, 2 or 4)
 };
 
 // device status word bits
@@ -60,18 +61,21 @@ inline void timer_mark(const KernelTimer *t, bool start, hipStream_t s) {
 }
 
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
-hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_t s, const KernelTimer *t = nullptr);
+hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_t s, const KernelTimer *t = nullptr,
+                           int per_cu = 8);
 int flat_chunk(int total_mbs, int per_cu);
 hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainDesc *chains, const uint32_t *tickets,
                      int nlines, unsigned long long *progress, uint32_t *counter, uint32_t *masks, int mask_words,
                      uint32_t *status, const KParams &kp, int workers, hipStream_t s,
-                     const KernelTimer *t = nullptr);
-size_t pa_lds_bytes(int S);
+                     const KernelTimer *t = nullptr, bool generic = false);
+// LDS bytes of one search worker; `generic`: single-buffered generic staging
+size_t pa_lds_bytes(int S, bool generic = false);
+int plan_elems(int S);
 hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_mbs, const KParams &kp,
                               uint32_t *counters, uint32_t *list, hipStream_t s, const KernelTimer *t = nullptr);
 size_t full_search_scratch(int total_mbs);
 hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, unsigned long long *acc,
-                     hipStream_t s, const KernelTimer *t = nullptr);
+                     hipStream_t s, const KernelTimer *t = nullptr, int per_cu = 8);
 size_t mc_scratch(int total_mbs);
 
 int pa_worker_cap();

@@ -115,3 +115,25 @@ def test_kernel_timing_validation():
     assert L.me_kernel_time_ms(4, None, C.byref(ms), C.byref(cnt)) == me.ME_EINVAL
     assert L.me_kernel_time_ms(-1, None, C.byref(ms), C.byref(cnt)) == me.ME_EINVAL
     assert L.me_kernel_time_ms(me.ME_KT_SEARCH, None, None, C.byref(cnt)) == me.ME_EINVAL
+
+
+def test_batch_argument_validation():
+    L = me.lib()
+    p = me.me_default_params()
+    h = C.c_void_p(1)
+    ja = (me.me_job * 1)(job())
+    assert L.me_batch_create(ja, 1, C.byref(p), 0, None, None) == me.ME_EINVAL          # no handle out
+    assert L.me_batch_create(ja, 0, C.byref(p), 0, None, C.byref(h)) == me.ME_EINVAL    # empty
+    assert h.value is None                                                              # cleared on error
+    assert L.me_batch_create(ja, 1, C.byref(p), 8, None, C.byref(h)) == me.ME_EINVAL    # unknown flag
+    assert L.me_batch_create(ja, 1, None, 0, None, C.byref(h)) == me.ME_EINVAL          # no params
+    bad = (me.me_job * 1)(job(mv=None))
+    assert L.me_batch_create(bad, 1, C.byref(p), 0, None, C.byref(h)) == me.ME_EINVAL
+    noalpha = (me.me_job * 1)(job())
+    assert L.me_batch_create(noalpha, 1, C.byref(p), me.ME_BATCH_SHAPE, None, C.byref(h)) == me.ME_EINVAL
+    assert L.me_batch_step(None, ja, 1) == me.ME_EINVAL
+    s, n_, d = (C.c_uint64 * 1)(), (C.c_uint64 * 1)(), (C.c_double * 1)()
+    assert L.me_batch_results(None, s, n_, d, 1) == me.ME_EINVAL
+    cfg = (C.c_int32 * 4)()
+    assert L.me_batch_config(None, cfg, 4) == me.ME_EINVAL
+    L.me_batch_destroy(None)
