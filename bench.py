@@ -70,6 +70,7 @@ def parse():
     ap.add_argument("--frames", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched frame-step measurement")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 3 device copies of this many MiB (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
@@ -115,6 +116,85 @@ class Workload:
         me = self.me
         me.me_full_search(method, self.base_jobs[method], self.params, stream=stream)
         return me.me_motion_compensate_psnr(self.base_jobs[method], stream=stream)
+
+
+class MixedWorkload:
+    """64 streams (24 QCIF, 24 CIF, 16 4CIF 704x576), 1-4 VOPs each, S=16:
+    one batched frame step = every (stream, VOP) pair of one frame step."""
+
+    def __init__(self, frames=31, counts=(24, 24, 16)):
+        import torch
+        import paper_1002_1168_amd as me
+        from paper_1002_1168_amd import device as dv
+        from paper_1002_1168_amd import synth
+        self.me, self.dv = me, dv
+        t0 = time.time()
+        self.seqs = synth.mixed_streams(seed=3, frames=frames, counts=counts)
+        log(f"generated {len(self.seqs)} mixed streams x{frames} frames in {time.time() - t0:.1f}s")
+        self.pairs = frames - 1
+        self.ds = [dv.DeviceSequence(q) for q in self.seqs]
+        self.units = [(si, v) for si, q in enumerate(self.seqs) for v in range(q.vops)]
+        self.out = [dv.Outputs.alloc(self.pairs, self.ds[si].hm, self.ds[si].wm) for si, _ in self.units]
+        self.zero = [torch.zeros((self.ds[si].hm, self.ds[si].wm, 2), dtype=torch.int16, device="cuda")
+                     for si, _ in self.units]
+        self.params = me.me_default_params(search_range=16)
+        self.steps = [me.job_array(self.jobs(i)) for i in range(self.pairs)]
+        self.grid_mbs = sum(self.ds[si].hm * self.ds[si].wm for si, _ in self.units)
+        self.layer_mbs = sum(d.hm * d.wm for d in self.ds)
+
+    def jobs(self, i, chained_in_call=False):
+        """Jobs of frame step i; T = the previous step's mv_int (zero at step 0)."""
+        js = []
+        for u, (si, v) in enumerate(self.units):
+            d, t = self.ds[si], i + 1
+            tf = self.out[u].mv_int[i - 1] if i > 0 else (None if chained_in_call else self.zero[u])
+            js.append(self.dv.job(d.luma[t], d.luma[t - 1], d.alpha[v, t], d.alpha[v, t - 1], d.cls[v, t], tf,
+                                  self.out[u], i))
+        return js
+
+
+def batched_measurement(torch, steps, warmup):
+    """Per-frame-step graph launches over the mixed streams, and the same
+    frames as one pipelined launch over all steps."""
+    me = __import__("paper_1002_1168_amd")
+    mw = MixedWorkload()
+    stream = mw.dv.stream_handle()
+    b = me.Batch(mw.steps[0], mw.params, me.ME_BATCH_AUTOTUNE, stream=stream)
+    cfg = b.config()
+    n = len(mw.steps)
+    for i in range(warmup):
+        b.step(mw.steps[i % n])
+    torch.cuda.synchronize()
+    k = max(steps, n)
+    t0 = time.perf_counter()
+    for i in range(k):
+        b.step(mw.steps[i % n])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    status = b.results(check=False)[3]
+    assert status in (me.ME_OK, me.ME_EEMPTY), status
+    b.close()
+    per_step = {"mb_per_s": mw.grid_mbs * k / dt, "ms_per_frame_step": 1000.0 * dt / k, "frame_steps": k,
+                "config": cfg}
+    # all frame steps of all streams in one pipelined launch (T chained in the call)
+    allj = me.job_array([j for i in range(n) for j in mw.jobs(i, chained_in_call=True)])
+    for _ in range(2):
+        me.me_texture_recursive(allj, mw.params, None, stream=stream)
+    torch.cuda.synchronize()
+    reps = max(steps // 4, 2)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        me.me_texture_recursive(allj, mw.params, None, stream=stream)
+    torch.cuda.synchronize()
+    dtp = time.perf_counter() - t0
+    assert me.me_device_status(stream) == me.ME_OK
+    pipelined = {"mb_per_s": mw.grid_mbs * n * reps / dtp, "ms_per_launch": 1000.0 * dtp / reps,
+                 "frame_steps_per_launch": n, "search_only": True}
+    log(f"batched mixed streams: {per_step['mb_per_s'] / 1e6:.1f} M MB/s per-step graph "
+        f"({per_step['ms_per_frame_step']:.3f} ms/step, cfg {cfg}); pipelined search over {n} steps "
+        f"{pipelined['mb_per_s'] / 1e6:.1f} M MB/s")
+    return {"workload": f"mixed64_{len(mw.seqs)}streams_{len(mw.units)}vops_S16", "grid_mbs_per_frame_step": mw.grid_mbs,
+            "grid_mbs_per_vop_layer": mw.layer_mbs, "per_step_graph": per_step, "pipelined_all_steps": pipelined}
 
 
 def timed(fn, steps, warmup, torch, me, stream, kind):
@@ -227,6 +307,10 @@ def main():
                 f"points/MB {entry['points_per_mb']:.2f}")
         assert me.me_device_status(stream) == me.ME_OK
 
+    batched = None
+    if not a.no_batched:
+        batched = batched_measurement(torch, a.steps, a.warmup)
+
     cpu = None
     if not a.no_cpu_baseline:
         hosts = [o.host() for o in wl.out]
@@ -255,6 +339,7 @@ def main():
                      "kernel": "pa_kernel", "kernel_ms": kern_ms},
         "cpu_baseline": cpu,
         "baselines": baselines,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
 

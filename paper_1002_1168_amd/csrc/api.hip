@@ -241,15 +241,15 @@ int run_pa(const me_job *jobs, int n, const me_params *params, bool shape_only, 
     const size_t o_ctr = align_up((size_t)m.nlines * 8, 256);
     const size_t o_mask = o_ctr + 256;
     const size_t zero = o_mask + align_up((size_t)m.nlines * m.mask_words * 2 * 4, 256);
-    uint8_t *base = nullptr, *zb = nullptr;
-    rc = upload(*w, A_PA, m.blob, zero, &base, &zb);
+    uint8_t *base = nullptr, *zb = nullptr, *sb = nullptr;
+    rc = upload(*w, A_PA, m.blob, zero, &base, &zb, pa_scratch_bytes(m.nlines), &sb);
     if (rc) return rc;
     int workers = std::min(m.nlines, pa_worker_cap());
     KernelTimer kt;
     KParams kp = kparams(params, shape_only);
     return hip_err(launch_pa((const JobDesc *)(base + m.o_jobs), m.n, m.total_mbs, (const ChainDesc *)(base + m.o_ch),
                              (const uint32_t *)(base + m.o_tk), m.nlines, (unsigned long long *)(zb + o_prog),
-                             (uint32_t *)(zb + o_ctr), (uint32_t *)(zb + o_mask), m.mask_words, w->status, kp,
+                             (uint32_t *)(zb + o_ctr), (uint32_t *)(zb + o_mask), m.mask_words, sb, w->status, kp,
                              workers, w->stream, timer_for(*w, A_PA, &kt) ? &kt : nullptr));
 }
 

@@ -28,7 +28,7 @@ struct me_batch {
     PaMemo plan;                    // chain structure, tickets, descriptor template
     std::vector<JobDesc> tmpl;      // chain-ordered descriptors of the creating job set
     uint8_t *dev = nullptr;         // one allocation, layout below
-    size_t o_zero = 0, zero_bytes = 0, o_part = 0, o_acc = 0, o_status = 0;
+    size_t o_zero = 0, zero_bytes = 0, o_pscr = 0, o_part = 0, o_acc = 0, o_status = 0;
     void *host[2] = {nullptr, nullptr};  // pinned job-table staging
     hipEvent_t ev[2] = {nullptr, nullptr};
     int slot = 0;
@@ -104,6 +104,7 @@ struct Bufs {
     uint8_t *zero;
     unsigned long long *progress;
     uint32_t *counter, *masks, *part, *status;
+    uint8_t *pscr;
     unsigned long long *acc;
 };
 
@@ -117,6 +118,7 @@ Bufs bufs(const me_batch &b) {
     r.progress = (unsigned long long *)r.zero;
     r.counter = (uint32_t *)(r.zero + align_up((size_t)m.nlines * 8, 256));
     r.masks = (uint32_t *)((uint8_t *)r.counter + 256);
+    r.pscr = b.dev + b.o_pscr;
     r.part = (uint32_t *)(b.dev + b.o_part);
     r.acc = (unsigned long long *)(b.dev + b.o_acc);
     r.status = (uint32_t *)(b.dev + b.o_status);
@@ -133,7 +135,8 @@ hipError_t launch_search(const me_batch &b, const Bufs &u, const int32_t *cfg, h
     hipError_t e = launch_fill_u32((uint32_t *)u.zero, b.zero_bytes / 4, 0u, s);
     if (e != hipSuccess) return e;
     return launch_pa(u.jobs, b.n, b.plan.total_mbs, u.chains, u.tickets, b.plan.nlines, u.progress, u.counter, u.masks,
-                     b.plan.mask_words, u.status, batch_kparams(b, cfg[2]), cfg[0], s, nullptr, cfg[1] == 0);
+                     b.plan.mask_words, u.pscr, u.status, batch_kparams(b, cfg[2]), cfg[0], s, nullptr,
+                     cfg[1] == 0);
 }
 
 // The whole frame step with configuration `cfg` on stream `s`.
@@ -308,10 +311,12 @@ int me_batch_create(const me_job *jobs, int n, const me_params *params, uint32_t
     const PaMemo &m = b->plan;
     b->tmpl.resize(n);
     std::memcpy(b->tmpl.data(), m.blob.data() + m.o_jobs, sizeof(JobDesc) * (size_t)n);
-    // device layout: [jobs | chains | tickets] [zeroed search scratch] [MC partials] [per-job sums] [status]
+    // device layout: [jobs | chains | tickets] [zeroed search scratch] [ticket compaction] [MC partials]
+    // [per-job sums] [status]
     b->o_zero = align_up(m.blob.size(), 256);
     b->zero_bytes = align_up(align_up((size_t)m.nlines * 8, 256) + 256 + (size_t)m.nlines * m.mask_words * 2 * 4, 256);
-    b->o_part = b->o_zero + b->zero_bytes;
+    b->o_pscr = b->o_zero + b->zero_bytes;
+    b->o_part = b->o_pscr + align_up(pa_scratch_bytes(m.nlines), 256);
     b->o_acc = b->o_part + align_up(mc_scratch(m.total_mbs), 256);
     b->o_status = b->o_acc + align_up((size_t)n * 16, 256);
     const size_t total = b->o_status + 256;

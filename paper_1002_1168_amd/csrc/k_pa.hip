@@ -43,8 +43,8 @@ namespace {
 struct PaArgs {
     const JobDesc *jobs;  // in chain order: chain c's pair p is jobs[chains[c].first + p]
     const ChainDesc *chains;
-    const uint32_t *tickets;
-    int nlines;
+    const uint32_t *tickets;  // lines with work, in ticket order
+    const uint32_t *nactive;  // number of those tickets
     unsigned long long *progress;
     uint32_t *counter;
     const uint32_t *tmask;  // per line, per 32 pairs: bit set = MB transparent in that pair
@@ -495,6 +495,75 @@ __global__ __launch_bounds__(256) void pa_prepass(const JobDesc *jobs, int n, in
     }
 }
 
+// Lines transparent in every pair of their chain need no worker: their
+// final progress word (all pairs done, zero vector) is stored here and they
+// leave the ticket list; the others keep their ticket order (an order-
+// preserving compaction: per-wave keep ballots and per-block counts, a scan
+// of the block counts, then the scatter).
+__global__ __launch_bounds__(256) void pa_line_flags(const ChainDesc *chains, const uint32_t *tickets, int nlines,
+                                                    const uint32_t *tmask, int mw, unsigned long long *progress,
+                                                    unsigned long long *keepw, uint32_t *bcount) {
+    __shared__ int wcnt[4];
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    bool keep = false;
+    if (t < nlines) {
+        const uint32_t tk = tickets[t];
+        const ChainDesc ch = chains[tk >> 16];
+        const int line = ch.line_base + (int)((tk >> 8) & 0xFF) * ch.wm + (int)(tk & 0xFF);
+        const uint32_t *m = tmask + (size_t)line * mw;
+        bool all = true;
+        for (int w = 0; w < mw && all; ++w) {
+            const int bits = min(32, ch.len - 32 * w);
+            const uint32_t full = bits >= 32 ? 0xFFFFFFFFu : ((1u << bits) - 1u);
+            all = (m[w] & full) == full;
+        }
+        if (all) progress[line] = (unsigned long long)(uint32_t)ch.len;
+        keep = !all;
+    }
+    const unsigned long long bal = __ballot(keep);
+    if (lane() == 0) {
+        keepw[t >> 6] = bal;
+        wcnt[threadIdx.x >> 6] = __popcll(bal);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) bcount[blockIdx.x] = (uint32_t)(wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3]);
+}
+
+// Exclusive scan of the nb block counts in place; the total to *nactive.
+__global__ __launch_bounds__(1024) void pa_scan_counts(uint32_t *bcount, int nb, uint32_t *nactive) {
+    __shared__ uint32_t sh[1024];
+    const int tid = threadIdx.x;
+    uint32_t carry = 0;
+    for (int base = 0; base < nb; base += 1024) {
+        const int i = base + tid;
+        const uint32_t v = i < nb ? bcount[i] : 0u;
+        sh[tid] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint32_t x = tid >= off ? sh[tid - off] : 0u;
+            __syncthreads();
+            sh[tid] += x;
+            __syncthreads();
+        }
+        if (i < nb) bcount[i] = carry + sh[tid] - v;
+        carry += sh[1023];
+        __syncthreads();
+    }
+    if (tid == 0) *nactive = carry;
+}
+
+__global__ __launch_bounds__(256) void pa_scatter_tickets(const uint32_t *tickets, int nlines,
+                                                         const unsigned long long *keepw, const uint32_t *boff,
+                                                         uint32_t *out) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= nlines) return;
+    const unsigned long long bal = keepw[t >> 6];
+    if (!((bal >> (t & 63)) & 1ull)) return;
+    uint32_t pos = boff[blockIdx.x] + (uint32_t)__popcll(bal & ((1ull << (t & 63)) - 1ull));
+    for (int w = (blockIdx.x * 256) >> 6; w < (t >> 6); ++w) pos += (uint32_t)__popcll(keepw[w]);
+    out[pos] = tickets[t];
+}
+
 template <int EM>
 __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
     extern __shared__ uint32_t lds[];
@@ -511,6 +580,7 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
     }
     const int l = lane(), j = l >> 2, q = l & 3;
     const int S = kp.S;
+    const int nact = (int)uni((int)ldg32(a.nactive));
     for (;;) {
         // ticket: lane 0 draws, LDS + barriers broadcast (barriers keep the
         // wave converged across loop trips).  Only a running worker ever
@@ -519,7 +589,7 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
         if (l == 0) slot = (int)atomicAdd(a.counter, 1u);
         __syncthreads();
         const int t = uni(slot);
-        if (t >= a.nlines) break;
+        if (t >= nact) break;
         if (uni((int)ld_relaxed(a.status)) & ST_ABORT) break;
         const uint32_t tk = a.tickets[t];
         const int ci = (int)(tk >> 16), v = (int)((tk >> 8) & 0xFF), h = (int)(tk & 0xFF);
@@ -733,19 +803,35 @@ size_t pa_lds_bytes(int S, bool generic) {
     return 1024 + (plan_elems(S) > 0 && !generic ? 2 : 1) * one;
 }
 
+size_t pa_scratch_bytes(int nlines) {
+    const size_t nb = ((size_t)nlines + 255) / 256;
+    return 256 + nb * 4 * 8 + 256 + nb * 4 + 256 + (size_t)nlines * 4 + 256;
+}
+
 hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainDesc *chains, const uint32_t *tickets,
                      int nlines, unsigned long long *progress, uint32_t *counter, uint32_t *masks, int mask_words,
-                     uint32_t *status, const KParams &kp, int workers, hipStream_t s, const KernelTimer *t,
-                     bool generic) {
+                     uint8_t *scratch, uint32_t *status, const KParams &kp, int workers, hipStream_t s,
+                     const KernelTimer *t, bool generic) {
+    if (total_mbs <= 0 || nlines <= 0) return hipSuccess;
     uint32_t *tmask = masks, *bmask = masks + (size_t)nlines * mask_words;
-    if (total_mbs > 0) {
-        hipLaunchKernelGGL(pa_prepass, dim3((total_mbs + 255) / 256), dim3(256), 0, s, jobs, njobs, total_mbs, tmask,
-                           bmask, mask_words, kp.shape_only, status);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
+    hipLaunchKernelGGL(pa_prepass, dim3((total_mbs + 255) / 256), dim3(256), 0, s, jobs, njobs, total_mbs, tmask,
+                       bmask, mask_words, kp.shape_only, status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // scratch: [nactive] [keep ballots, 4 per block] [block counts] [active tickets]
+    const int nb = (nlines + 255) / 256;
+    uint32_t *nactive = (uint32_t *)scratch;
+    unsigned long long *keepw = (unsigned long long *)(scratch + 256);
+    uint32_t *bcount = (uint32_t *)((uint8_t *)keepw + (((size_t)nb * 32 + 255) & ~(size_t)255));
+    uint32_t *active = (uint32_t *)((uint8_t *)bcount + (((size_t)nb * 4 + 255) & ~(size_t)255));
+    hipLaunchKernelGGL(pa_line_flags, dim3(nb), dim3(256), 0, s, chains, tickets, nlines, tmask, mask_words, progress,
+                       keepw, bcount);
+    hipLaunchKernelGGL(pa_scan_counts, dim3(1), dim3(1024), 0, s, bcount, nb, nactive);
+    hipLaunchKernelGGL(pa_scatter_tickets, dim3(nb), dim3(256), 0, s, tickets, nlines, keepw, bcount, active);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const int rows = 2 * kp.S + 18;
-    PaArgs a{jobs, chains, tickets, nlines, progress, counter, tmask, bmask, mask_words, status, kp,
+    PaArgs a{jobs, chains, active, nactive, progress, counter, tmask, bmask, mask_words, status, kp,
              (rows + 3) & ~3, rows};
     const size_t lds = pa_lds_bytes(kp.S, generic);
     timer_mark(t, true, s);
@@ -755,7 +841,7 @@ hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainD
         case 28: hipLaunchKernelGGL(pa_kernel<28>, dim3(workers), dim3(64), lds, s, a); break;
         default: hipLaunchKernelGGL(pa_kernel<0>, dim3(workers), dim3(64), lds, s, a); break;
     }
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     timer_mark(t, false, s);
     return e;
 }

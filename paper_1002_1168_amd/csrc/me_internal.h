@@ -57,7 +57,7 @@ struct KernelTimer {
     hipEvent_t start = nullptr, stop = nullptr;
 };
 inline void timer_mark(const KernelTimer *t, bool start, hipStream_t s) {
-    if (t) hipEventRecord(start ? t->start : t->stop, s);
+    if (t) (void)hipEventRecord(start ? t->start : t->stop, s);
 }
 
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
@@ -66,8 +66,10 @@ hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_
 int flat_chunk(int total_mbs, int per_cu);
 hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainDesc *chains, const uint32_t *tickets,
                      int nlines, unsigned long long *progress, uint32_t *counter, uint32_t *masks, int mask_words,
-                     uint32_t *status, const KParams &kp, int workers, hipStream_t s,
+                     uint8_t *scratch, uint32_t *status, const KParams &kp, int workers, hipStream_t s,
                      const KernelTimer *t = nullptr, bool generic = false);
+// bytes of the `scratch` argument of launch_pa (256-aligned base; no zeroing needed)
+size_t pa_scratch_bytes(int nlines);
 // LDS bytes of one search worker; `generic`: single-buffered generic staging
 size_t pa_lds_bytes(int S, bool generic = false);
 int plan_elems(int S);
