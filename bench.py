@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched frame-step measurement")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the 64-stream batched measurement (for profiling) and print it")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 3 device copies of this many MiB (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
@@ -162,10 +164,10 @@ def batched_measurement(torch, steps, warmup):
     b = me.Batch(mw.steps[0], mw.params, me.ME_BATCH_AUTOTUNE, stream=stream)
     cfg = b.config()
     n = len(mw.steps)
-    for i in range(warmup):
+    for i in range(max(warmup, n)):   # one pass over every step's job table first
         b.step(mw.steps[i % n])
     torch.cuda.synchronize()
-    k = max(steps, n)
+    k = max(steps, 3 * n)
     t0 = time.perf_counter()
     for i in range(k):
         b.step(mw.steps[i % n])
@@ -268,6 +270,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copied {a.copy_mib} MiB x3")
+        return
+    if a.only_batched:
+        print(json.dumps({"batched": batched_measurement(torch, a.steps, a.warmup)}), flush=True)
         return
     wl = Workload(a.frames)
     me = wl.me
