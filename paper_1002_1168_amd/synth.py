@@ -410,3 +410,24 @@ def random_frames(seed: int, W: int, H: int, frames: int = 2, vops: int = 0,
             m = ((xs + 0.5 - cx) / a) ** 2 + ((ys + 0.5 - cy) / b) ** 2 <= 1.0
             alpha[k, t] = np.where(m, 255, 0)
     return Sequence(luma, alpha, search_range, False, "random", int(seed))
+
+
+# ---------------------------------------------------------------- network
+# Fan-ins of the proposal network's three 3x3 convolutions (2, 32, 32 input
+# channels) and their output channels, in parameter-vector order:
+# W1 (32,3,3,2) | b1 (32) | W2 (32,3,3,32) | b2 (32) | W3 (2,3,3,32) | b3 (2).
+_NET_TENSORS = ((32 * 9 * 2, 9 * 2, 2.0), (32, 0, 0.0), (32 * 9 * 32, 9 * 32, 2.0), (32, 0, 0.0),
+                (2 * 9 * 32, 9 * 32, 0.5), (2, 0, 0.0))
+
+
+def net_init(seed: int) -> np.ndarray:
+    """Seeded initial weights of the proposal network (float32): normal
+    weights with variance gain / fan-in, zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for n, fan_in, gain in _NET_TENSORS:
+        if fan_in:
+            parts.append(rng.normal(0.0, np.sqrt(gain / fan_in), size=n))
+        else:
+            parts.append(np.zeros(n))
+    return np.concatenate(parts).astype(np.float32)

@@ -284,3 +284,31 @@ def test_kernel_timing_counts_each_launch(torch_cuda):
     assert count == 3 and total > 0.0
     assert_same(got[0], oracle_pa(seq, 0, p, 3), "timed")
     assert me.me_kernel_time_ms(me.ME_KT_SEARCH, s) == (0.0, 0)
+
+
+@pytest.mark.parametrize("maker,S", [("qcif", 7), ("cif", 16)])
+def test_pa_seeded_start_parity(torch_cuda, maker, S):
+    """Learned-seed start with the 5 % fallback (seeds = random vectors,
+    half of them near the plain result) against the oracle."""
+    import torch
+    from paper_1002_1168_amd.device import Outputs, stream_handle
+    seq = synth.qcif_ellipse(seed=31, frames=6) if maker == "qcif" else synth.cif_two_vops(seed=32, frames=6)
+    p = me.me_default_params(search_range=S)
+    ds = dseq(seq)
+    gpu_classify(ds)
+    P = 5
+    plain = oracle_pa(seq, 0, p, P)
+    rng = np.random.default_rng(S)
+    seeds = rng.integers(-S, S + 1, size=(P, ds.hm, ds.wm, 2)).astype(np.int16) * 2
+    near = rng.random((P, ds.hm, ds.wm)) < 0.5
+    jitter = rng.integers(-1, 2, size=(P, ds.hm, ds.wm, 2)).astype(np.int16) * 2
+    seeds[near] = (plain["mv_int"] + jitter)[near]
+    seeds = np.clip(seeds, -2 * S, 2 * S).astype(np.int16)
+    want = oracle.pa_sequence(seq, 0, oracle_params(p), pairs=P, seeds=list(seeds))
+    want = {k: np.stack([r[k] for r in want]) for k in ("mv", "mv_int", "cost", "iters", "points")}
+    out = Outputs.alloc(P, ds.hm, ds.wm)
+    sd = torch.from_numpy(seeds).cuda()
+    me.me_texture_recursive(ds.pair_jobs(0, out, P, seeds=sd), p, None, stream=stream_handle())
+    torch.cuda.synchronize()
+    assert me.me_device_status(stream_handle()) == me.ME_OK
+    assert_same(out.host(), want, f"seeded {maker}")

@@ -562,3 +562,45 @@ def test_psnr_constant_offset(orc, c):
     assert (sse, n) == (c * c * 32 * 48, 32 * 48)
     assert abs(orc.psnr_db(sse, n) - 20 * math.log10(255 / c)) < 1e-9
     assert orc.psnr_db(0, n) == float("inf")
+
+
+# ------------------------------------------------------- learned-seed start
+def translated_pair(d, H=128, W=176, seed=5):
+    rng = np.random.default_rng(seed)
+    big = synth.smoothed_noise(rng, H + 32, W + 32)
+    ref = big[16:16 + H, 16:16 + W].copy()
+    cur = big[16 + d[1]:16 + d[1] + H, 16 + d[0]:16 + d[0] + W].copy()
+    return cur, ref
+
+
+def test_pa_true_seed_is_taken(orc):
+    """A seed at the true translation costs 0: the seeded start is kept (no
+    fallback), the vector is exact, and the seed adds one compared block."""
+    d = (5, -4)
+    cur, ref = translated_pair(d)
+    seed = np.zeros((8, 11, 2), np.int16)
+    seed[..., 0], seed[..., 1] = 2 * d[0], 2 * d[1]
+    p = orc.Params(search_range=7)
+    plain = orc.pa(cur, ref, p)
+    got = orc.pa(cur, ref, p, seed=seed)
+    for v in range(8):
+        for h in range(11):
+            x0, y0 = 16 * h, 16 * v
+            if 0 <= x0 + d[0] <= 176 - 16 and 0 <= y0 + d[1] <= 128 - 16:
+                assert tuple(got["mv_int"][v, h]) == (2 * d[0], 2 * d[1]) and got["cost"][v, h] == 0
+                assert got["cost"][v, h] <= plain["cost"][v, h]
+                # the BRS list of this run's own neighbours, plus the seed;
+                # the seed's recursion stops at once (cost 0)
+                lst, _, _ = np_brs(cur, ref, got["mv_int"], None, None, None, None, 7, v, h)
+                assert got["points"][v, h] == len(lst) + 1 and got["iters"][v, h] == 0
+
+
+def test_pa_bad_seed_falls_back_to_plain(orc):
+    """Identical frames: the BRS minimum is 0 at (0, 0), so any seed with a
+    positive cost fails the 5 % test and the plain result stands."""
+    seq = synth.qcif_ellipse(frames=2)
+    f = seq.luma[0]
+    seed = np.full((9, 11, 2), 2 * 6, np.int16)
+    out = orc.pa(f, f, orc.Params(search_range=7), seed=seed)
+    assert (out["mv"] == 0).all() and (out["cost"] == 0).all()
+    assert (out["points"] >= 2).all()
