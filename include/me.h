@@ -99,6 +99,44 @@ typedef struct me_net me_net; /* learned MV proposal network (opaque) */
 /* Fill `p` with the defaults: S 16, Theta 3, eps 1.0, max_step 1, k_max 8, no half-pel. */
 void me_default_params(me_params *p);
 
+/*
+ * Learned motion-vector proposal network (an addition to the paper's
+ * method: it seeds the pel-recursive search of Section 3.2 for opaque MBs;
+ * the block-recursive result stays the fallback, see me_job.seed).
+ * Per MB: input 2 x 24 x 24 (the current MB and the frame-clamped
+ * reference window [-16, 32) around it, both box-averaged 2x2, a 2x2 sum s
+ * as (s - 512) / 512 in bfloat16); conv 3x3 2->32 stride 1 + ReLU; conv 3x3
+ * 32->32 stride 2 + ReLU; conv 3x3 32->2 stride 2; mean over the 6 x 6
+ * positions = predicted full-pel vector p; seed = 2 * clamp(rint(p), -16, 16)
+ * (half-pel).  bfloat16 weights and activations, fp32 accumulation.
+ * Parameters (ME_NET_PARAMS floats): W1 (32,3,3,2) | b1 (32) | W2 (32,3,3,32)
+ * | b2 (32) | W3 (2,3,3,32) | b3 (2), weights laid out [out][ky][kx][in].
+ * The MBs served are the opaque ones (every MB of a job whose mb_class is NULL).
+ *
+ * me_net_create: fp32 master weights from the host array `init` on the
+ *   current device (momentum zero).  *out = handle (NULL on error).
+ * me_net_forward: for every served MB, writes the seed into job.seed (if
+ *   set) and p (2 floats at 2*k) into pred[i] (host array of n device
+ *   pointers, itself nullable, entries nullable).  Only cur/ref/mb_class/seed
+ *   of the jobs are read.  Asynchronous on `stream`.
+ * me_net_train_step: one momentum-SGD step on the served MBs of `jobs`,
+ *   labels[i] = device field of full-pel vectors in half-pel units (the plain
+ *   method's mv_int).  Loss = sum |p - label/2|^2 / (2 B) over the B served
+ *   MBs; v = momentum * v + g; w = w - lr * v (0 <= momentum < 1, lr >= 0).
+ *   grad (device, ME_NET_PARAMS floats, nullable) receives g; loss (host,
+ *   nullable) the loss before the step - then the call blocks.  The gradient
+ *   sum is deterministic for a given device and job set.
+ * me_net_weights: blocking copy of the master weights (and momentum, nullable).
+ * me_net_destroy: waits for the device and frees (NULL is a no-op).
+ */
+#define ME_NET_PARAMS 10434
+int me_net_create(const float *init, me_net **out);
+int me_net_forward(me_net *net, const me_job *jobs, int n, float *const *pred, void *stream);
+int me_net_train_step(me_net *net, const me_job *jobs, int n, const me_mv *const *labels, float lr, float momentum,
+                      float *grad, double *loss, void *stream);
+int me_net_weights(me_net *net, float *weights, float *momentum);
+void me_net_destroy(me_net *net);
+
 /* Human-readable text of a status code (static storage). */
 const char *me_status_str(int status);
 

@@ -19,11 +19,13 @@ ME_MB_TRANSPARENT, ME_MB_OPAQUE, ME_MB_BOUNDARY = 0, 1, 2
 ME_ES, ME_TSS, ME_DS = 0, 1, 2
 ME_KT_CLASSIFY, ME_KT_SEARCH, ME_KT_FULL, ME_KT_MC = 0, 1, 2, 3
 ME_BATCH_SHAPE, ME_BATCH_AUTOTUNE = 1, 2
+ME_NET_PARAMS = 10434
 
 EXPORTED = ("me_default_params", "me_status_str", "me_shutdown", "me_classify_babs", "me_texture_recursive",
             "me_shape_search", "me_full_search", "me_motion_compensate_psnr", "me_device_status",
             "me_kernel_timing", "me_kernel_time_ms", "me_batch_create", "me_batch_step", "me_batch_results",
-            "me_batch_config", "me_batch_destroy")
+            "me_batch_config", "me_batch_destroy", "me_net_create", "me_net_forward", "me_net_train_step",
+            "me_net_weights", "me_net_destroy")
 
 
 class MeError(RuntimeError):
@@ -94,6 +96,17 @@ def lib():
         L.me_batch_config.restype = i
         L.me_batch_destroy.argtypes = [vp]
         L.me_batch_destroy.restype = None
+        L.me_net_create.argtypes = [C.POINTER(C.c_float), C.POINTER(vp)]
+        L.me_net_create.restype = i
+        L.me_net_forward.argtypes = [vp, C.POINTER(me_job), i, C.POINTER(vp), vp]
+        L.me_net_forward.restype = i
+        L.me_net_train_step.argtypes = [vp, C.POINTER(me_job), i, C.POINTER(vp), C.c_float, C.c_float, vp,
+                                        C.POINTER(C.c_double), vp]
+        L.me_net_train_step.restype = i
+        L.me_net_weights.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.me_net_weights.restype = i
+        L.me_net_destroy.argtypes = [vp]
+        L.me_net_destroy.restype = None
         _lib = L
     return _lib
 
@@ -148,8 +161,11 @@ def me_classify_babs(frames, mb_class, bab_bits=None, stream=None, check=True) -
 
 
 def me_texture_recursive(jobs, params: me_params, net=None, stream=None, check=True) -> int:
+    """``net``: None (plain method) or a :class:`Net` whose proposals are
+    written into the jobs' seed buffers first."""
     ja, n = _arr(me_job, jobs)
-    rc = lib().me_texture_recursive(ja, n, C.byref(params), net, stream)
+    h = net.handle if isinstance(net, Net) else net
+    rc = lib().me_texture_recursive(ja, n, C.byref(params), h, stream)
     return _check(rc, "me_texture_recursive") if check else rc
 
 
@@ -226,6 +242,56 @@ class Batch:
     def close(self) -> None:
         if self.handle:
             lib().me_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Net:
+    """The learned motion-vector proposal network (``me_net_*``)."""
+
+    def __init__(self, init):
+        import numpy as np
+        w = np.ascontiguousarray(init, dtype=np.float32)
+        if w.shape != (ME_NET_PARAMS,):
+            raise MeError(ME_EINVAL, "Net: init must hold ME_NET_PARAMS floats")
+        h = C.c_void_p()
+        _check(lib().me_net_create(w.ctypes.data_as(C.POINTER(C.c_float)), C.byref(h)), "me_net_create")
+        self.handle = h
+
+    def forward(self, jobs, pred=None, stream=None, check=True) -> int:
+        """Seeds into the jobs' seed buffers; ``pred``: per-job device
+        pointers (or None) receiving the raw predictions."""
+        ja, n = _arr(me_job, jobs)
+        pa = None if pred is None else _arr(C.c_void_p, pred)[0]
+        rc = lib().me_net_forward(self.handle, ja, n, pa, stream)
+        return _check(rc, "me_net_forward") if check else rc
+
+    def train_step(self, jobs, labels, lr: float, momentum: float, grad=None, want_loss=True, stream=None):
+        """One SGD step; -> loss before the step (None unless want_loss)."""
+        ja, n = _arr(me_job, jobs)
+        la, _ = _arr(C.c_void_p, labels)
+        loss = C.c_double()
+        _check(lib().me_net_train_step(self.handle, ja, n, la, float(lr), float(momentum), grad,
+                                       C.byref(loss) if want_loss else None, stream), "me_net_train_step")
+        return float(loss.value) if want_loss else None
+
+    def weights(self, momentum=False):
+        import numpy as np
+        w = np.empty(ME_NET_PARAMS, np.float32)
+        v = np.empty(ME_NET_PARAMS, np.float32) if momentum else None
+        _check(lib().me_net_weights(self.handle, w.ctypes.data_as(C.POINTER(C.c_float)),
+                                    None if v is None else v.ctypes.data_as(C.POINTER(C.c_float))),
+               "me_net_weights")
+        return (w, v) if momentum else w
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib().me_net_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -352,7 +352,20 @@ int me_classify_babs(const me_frame *frames, int n, uint8_t *const *mb_class, ui
 }
 
 int me_texture_recursive(const me_job *jobs, int n, const me_params *params, const me_net *net, void *stream) {
-    if (net) return ME_EINVAL;  // the learned proposal is provided through job.seed
+    if (net) {
+        // everything is validated before the network writes any seed
+        if (n < 0 || (n > 0 && !jobs)) return ME_EINVAL;
+        int rc = check_params(params);
+        if (rc) return rc;
+        for (int i = 0; i < n; ++i) {
+            rc = check_job(jobs[i], false);
+            if (rc) return rc;
+            if (!jobs[i].seed) return ME_EINVAL;
+        }
+        if (n == 0) return ME_OK;
+        rc = net_seed_jobs(const_cast<me_net *>(net), jobs, n, stream);
+        if (rc) return rc;
+    }
     return run_pa(jobs, n, params, false, stream);
 }
 

@@ -51,6 +51,8 @@ KParams kparams(const me_params *p, bool shape_only);
 JobDesc job_desc(const me_job &j);
 // Chains, chain-ordered descriptors and the ticket order of a job set.
 int build_pa(const me_job *jobs, int n, PaMemo &m);
+// Proposal-network seeds into every job's seed buffer (all must be set).
+int net_seed_jobs(me_net *net, const me_job *jobs, int n, void *stream);
 
 }  // namespace host
 }  // namespace me

@@ -803,6 +803,11 @@ size_t pa_lds_bytes(int S, bool generic) {
     return 1024 + (plan_elems(S) > 0 && !generic ? 2 : 1) * one;
 }
 
+hipError_t launch_scan_counts(uint32_t *counts, int n, uint32_t *total, hipStream_t s) {
+    hipLaunchKernelGGL(pa_scan_counts, dim3(1), dim3(1024), 0, s, counts, n, total);
+    return hipGetLastError();
+}
+
 size_t pa_scratch_bytes(int nlines) {
     const size_t nb = ((size_t)nlines + 255) / 256;
     return 256 + nb * 4 * 8 + 256 + nb * 4 + 256 + (size_t)nlines * 4 + 256;

@@ -81,6 +81,26 @@ hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, 
 size_t mc_scratch(int total_mbs);
 
 int pa_worker_cap();
+// exclusive scan of n counts in place (one block), total to *total
+hipError_t launch_scan_counts(uint32_t *counts, int n, uint32_t *total, hipStream_t s);
+
+// ------------------------------------------------ learned proposal network
+// parameter vector: W1 (32,3,3,2) | b1 (32) | W2 (32,3,3,32) | b2 (32) | W3 (2,3,3,32) | b3 (2)
+constexpr int kNetOW1 = 0, kNetOB1 = 576, kNetOW2 = 608, kNetOB2 = 9824, kNetOW3 = 9856, kNetOB3 = 10432;
+constexpr int kNetParams = 10434;
+constexpr int kNetBf16 = 576 + 2 * 9216 + 576;  // bf16 copies: W1 | W2 | W2 as [tap][ci][co] | W3
+size_t net_lds_bytes(bool train);
+size_t net_list_scratch(int total_mbs);
+// list of opaque MBs (all MBs of jobs without classes) in flat order, into `scratch`
+hipError_t launch_net_list(const JobDesc *jobs, int n, int total_mbs, uint8_t *scratch, const uint32_t **list,
+                           const uint32_t **count, hipStream_t s);
+// forward (seeds / predictions) or forward + backward into per-workgroup partials
+hipError_t launch_net(bool train, const JobDesc *jobs, int n, const uint32_t *list, const uint32_t *count,
+                      const float *P, const uint16_t *wb, float *part, int groups, hipStream_t s,
+                      const KernelTimer *t = nullptr);
+hipError_t launch_net_sgd(float *P, float *V, uint16_t *wb, const float *part, int nparts, float lr, float mu,
+                          float *grad, double *loss, hipStream_t s);
+hipError_t launch_net_refresh(const float *P, uint16_t *wb, hipStream_t s);
 
 }  // namespace me
 

@@ -1,0 +1,257 @@
+// C ABI of the learned motion-vector proposal network: creation from given
+// initial weights, inference (seeds for the pel-recursive start), one
+// momentum-SGD training step on labelled MBs, weight read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "host.h"
+#include "me_internal.h"
+
+using namespace me;
+using namespace me::host;
+
+struct me_net {
+    int device = 0;
+    float *P = nullptr, *V = nullptr;  // fp32 master weights and momentum
+    uint16_t *wb = nullptr;            // bf16 copies
+    uint8_t *buf = nullptr;            // per-call scratch
+    size_t cap = 0;
+    void *host[2] = {nullptr, nullptr};  // pinned job-table staging
+    size_t host_cap[2] = {0, 0};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int slot = 0;
+    double *host_loss = nullptr;
+    int cus = 256;
+    std::mutex mu;
+};
+
+namespace {
+
+void release(me_net *m) {
+    if (!m) return;
+    hipDeviceSynchronize();
+    if (m->P) hipFree(m->P);
+    if (m->V) hipFree(m->V);
+    if (m->wb) hipFree(m->wb);
+    if (m->buf) hipFree(m->buf);
+    for (int s = 0; s < 2; ++s) {
+        if (m->host[s]) hipHostFree(m->host[s]);
+        if (m->ev[s]) hipEventDestroy(m->ev[s]);
+    }
+    if (m->host_loss) hipHostFree(m->host_loss);
+    delete m;
+}
+
+// Validated job table (flat MB order) for the network calls; `aux` per job
+// is the label field (training) or the prediction output (inference).
+int net_table(const me_job *jobs, int n, const void *const *aux, bool need_aux, std::vector<JobDesc> &desc,
+              long long &total) {
+    if (n <= 0 || !jobs) return ME_EINVAL;
+    desc.resize(n);
+    total = 0;
+    for (int i = 0; i < n; ++i) {
+        const me_job &j = jobs[i];
+        int rc = check_frame(j.cur, false);
+        if (rc) return rc;
+        rc = check_frame(j.ref, false);
+        if (rc) return rc;
+        if (j.cur.width != j.ref.width || j.cur.height != j.ref.height || j.cur.stride != j.ref.stride)
+            return ME_EINVAL;
+        const void *x = aux ? aux[i] : nullptr;
+        if (need_aux && !x) return ME_EINVAL;
+        if ((x && !al4(x)) || (j.seed && !al4(j.seed))) return ME_EALIGN;
+        JobDesc d;
+        std::memset(&d, 0, sizeof(d));
+        d.cur = j.cur.luma;
+        d.ref = j.ref.luma;
+        d.cls = j.mb_class;
+        d.seed = (const int16_t *)j.seed;
+        if (need_aux)
+            d.tf = (const int16_t *)x;
+        else
+            d.out_u32 = (uint32_t *)const_cast<void *>(x);
+        d.width = j.cur.width;
+        d.height = j.cur.height;
+        d.stride = j.cur.stride;
+        d.wm = d.width / 16;
+        d.hm = d.height / 16;
+        d.mb_base = (int32_t)total;
+        d.dep_line_base = -1;
+        total += (long long)d.wm * d.hm;
+        desc[i] = d;
+    }
+    if (total > (1ll << 30) || n > 65535) return ME_EINVAL;
+    for (const auto &d : desc)
+        if (d.wm * d.hm > 65536) return ME_EINVAL;  // list entries keep 16 bits of MB index
+    return ME_OK;
+}
+
+int ensure(me_net &m, size_t bytes, hipStream_t s) {
+    if (bytes <= m.cap) return ME_OK;
+    if (m.buf) {
+        if (hipStreamSynchronize(s) != hipSuccess) return ME_EHIP;
+        hipFree(m.buf);
+        m.buf = nullptr;
+        m.cap = 0;
+    }
+    const size_t cap = std::max(bytes + bytes / 4, (size_t)1 << 20);
+    if (hipMalloc(&m.buf, cap) != hipSuccess) return ME_ENOMEM;
+    m.cap = cap;
+    return ME_OK;
+}
+
+int upload_table(me_net &m, const std::vector<JobDesc> &desc, hipStream_t s) {
+    const size_t bytes = desc.size() * sizeof(JobDesc);
+    const int k = m.slot;
+    m.slot ^= 1;
+    if (hipEventSynchronize(m.ev[k]) != hipSuccess) return ME_EHIP;
+    if (m.host_cap[k] < bytes) {
+        if (m.host[k]) hipHostFree(m.host[k]);
+        m.host[k] = nullptr;
+        m.host_cap[k] = 0;
+        if (hipHostMalloc(&m.host[k], std::max(bytes, (size_t)4096), hipHostMallocDefault) != hipSuccess)
+            return ME_ENOMEM;
+        m.host_cap[k] = std::max(bytes, (size_t)4096);
+    }
+    std::memcpy(m.host[k], desc.data(), bytes);
+    if (hipMemcpyAsync(m.buf, m.host[k], bytes, hipMemcpyHostToDevice, s) != hipSuccess) return ME_EHIP;
+    if (hipEventRecord(m.ev[k], s) != hipSuccess) return ME_EHIP;
+    return ME_OK;
+}
+
+int check_lds(int dev, bool train) {
+    int lim = 0;
+    if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return ME_EHIP;
+    return net_lds_bytes(train) <= (size_t)lim ? ME_OK : ME_ENOMEM;
+}
+
+}  // namespace
+
+namespace me {
+namespace host {
+
+// Seeds of every opaque MB of `jobs` (their `seed` buffers) from `net`
+// (used by me_texture_recursive before the search).
+int net_seed_jobs(me_net *net, const me_job *jobs, int n, void *stream) {
+    for (int i = 0; i < n; ++i)
+        if (!jobs[i].seed) return ME_EINVAL;
+    return me_net_forward(net, jobs, n, nullptr, stream);
+}
+
+}  // namespace host
+}  // namespace me
+
+extern "C" {
+
+int me_net_create(const float *init, me_net **out) {
+    if (!out) return ME_EINVAL;
+    *out = nullptr;
+    if (!init) return ME_EINVAL;
+    for (int i = 0; i < kNetParams; ++i)
+        if (!std::isfinite(init[i])) return ME_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || check_device(dev) != ME_OK) return ME_ENODEV;
+    int rc = check_lds(dev, false);
+    if (rc) return rc;
+    me_net *m = new me_net();
+    m->device = dev;
+    hipDeviceGetAttribute(&m->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (m->cus <= 0) m->cus = 256;
+    if (hipMalloc(&m->P, kNetParams * 4) != hipSuccess || hipMalloc(&m->V, kNetParams * 4) != hipSuccess ||
+        hipMalloc(&m->wb, kNetBf16 * 2) != hipSuccess ||
+        hipHostMalloc((void **)&m->host_loss, sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        release(m);
+        return ME_ENOMEM;
+    }
+    for (int s = 0; s < 2; ++s)
+        if (hipEventCreateWithFlags(&m->ev[s], hipEventDisableTiming) != hipSuccess) {
+            release(m);
+            return ME_EHIP;
+        }
+    std::vector<float> zero(kNetParams, 0.f);
+    if (hipMemcpy(m->P, init, kNetParams * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->V, zero.data(), kNetParams * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        launch_net_refresh(m->P, m->wb, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        release(m);
+        return ME_EHIP;
+    }
+    *out = m;
+    return ME_OK;
+}
+
+void me_net_destroy(me_net *net) { release(net); }
+
+int me_net_weights(me_net *net, float *weights, float *momentum) {
+    if (!net || !weights) return ME_EINVAL;
+    std::lock_guard<std::mutex> lk(net->mu);
+    if (hipDeviceSynchronize() != hipSuccess) return ME_EHIP;
+    if (hipMemcpy(weights, net->P, kNetParams * 4, hipMemcpyDeviceToHost) != hipSuccess) return ME_EHIP;
+    if (momentum && hipMemcpy(momentum, net->V, kNetParams * 4, hipMemcpyDeviceToHost) != hipSuccess) return ME_EHIP;
+    return ME_OK;
+}
+
+int me_net_forward(me_net *net, const me_job *jobs, int n, float *const *pred, void *stream) {
+    if (!net) return ME_EINVAL;
+    std::vector<JobDesc> desc;
+    long long total = 0;
+    int rc = net_table(jobs, n, (const void *const *)pred, false, desc, total);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(net->mu);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t o_list = align_up(desc.size() * sizeof(JobDesc), 256);
+    rc = ensure(*net, o_list + net_list_scratch((int)total), s);
+    if (rc) return rc;
+    rc = upload_table(*net, desc, s);
+    if (rc) return rc;
+    const uint32_t *list = nullptr, *count = nullptr;
+    const JobDesc *tab = (const JobDesc *)net->buf;
+    if (launch_net_list(tab, n, (int)total, net->buf + o_list, &list, &count, s) != hipSuccess) return ME_EHIP;
+    const int groups = (int)std::min<long long>(total, (long long)net->cus * 3);
+    return hip_err(launch_net(false, tab, n, list, count, net->P, net->wb, nullptr, groups, s));
+}
+
+int me_net_train_step(me_net *net, const me_job *jobs, int n, const me_mv *const *labels, float lr, float momentum,
+                      float *grad, double *loss, void *stream) {
+    if (!net || !labels) return ME_EINVAL;
+    if (!std::isfinite(lr) || lr < 0.f || !std::isfinite(momentum) || momentum < 0.f || momentum >= 1.f)
+        return ME_EINVAL;
+    if (grad && !al4(grad)) return ME_EALIGN;
+    std::vector<JobDesc> desc;
+    long long total = 0;
+    int rc = net_table(jobs, n, (const void *const *)labels, true, desc, total);
+    if (rc) return rc;
+    rc = check_lds(net->device, true);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(net->mu);
+    hipStream_t s = (hipStream_t)stream;
+    const int groups = (int)std::min<long long>(total, (long long)net->cus);
+    const size_t o_list = align_up(desc.size() * sizeof(JobDesc), 256);
+    const size_t o_part = o_list + align_up(net_list_scratch((int)total), 256);
+    const size_t o_loss = o_part + align_up((size_t)groups * (kNetParams + 1) * 4, 256);
+    rc = ensure(*net, o_loss + 256, s);
+    if (rc) return rc;
+    rc = upload_table(*net, desc, s);
+    if (rc) return rc;
+    const uint32_t *list = nullptr, *count = nullptr;
+    const JobDesc *tab = (const JobDesc *)net->buf;
+    if (launch_net_list(tab, n, (int)total, net->buf + o_list, &list, &count, s) != hipSuccess) return ME_EHIP;
+    float *part = (float *)(net->buf + o_part);
+    double *dloss = (double *)(net->buf + o_loss);
+    if (launch_net(true, tab, n, list, count, net->P, net->wb, part, groups, s) != hipSuccess) return ME_EHIP;
+    if (launch_net_sgd(net->P, net->V, net->wb, part, groups, lr, momentum, grad, dloss, s) != hipSuccess)
+        return ME_EHIP;
+    if (loss) {
+        if (hipMemcpyAsync(net->host_loss, dloss, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+            return ME_EHIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return ME_EHIP;
+        *loss = *net->host_loss;
+    }
+    return ME_OK;
+}
+
+}  // extern "C"

@@ -137,3 +137,20 @@ def test_batch_argument_validation():
     cfg = (C.c_int32 * 4)()
     assert L.me_batch_config(None, cfg, 4) == me.ME_EINVAL
     L.me_batch_destroy(None)
+
+
+def test_net_argument_validation():
+    L = me.lib()
+    h = C.c_void_p(1)
+    w = (C.c_float * me.ME_NET_PARAMS)()
+    assert L.me_net_create(w, None) == me.ME_EINVAL
+    assert L.me_net_create(None, C.byref(h)) == me.ME_EINVAL and h.value is None
+    w[5] = float("nan")
+    assert L.me_net_create(w, C.byref(h)) == me.ME_EINVAL
+    ja = (me.me_job * 1)(job())
+    assert L.me_net_forward(None, ja, 1, None, None) == me.ME_EINVAL
+    labels = (C.c_void_p * 1)(FAKE)
+    assert L.me_net_train_step(None, ja, 1, labels, 0.1, 0.9, None, None, None) == me.ME_EINVAL
+    s = (C.c_float * me.ME_NET_PARAMS)()
+    assert L.me_net_weights(None, s, None) == me.ME_EINVAL
+    L.me_net_destroy(None)
