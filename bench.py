@@ -71,6 +71,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched frame-step measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-seed measurement")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the 64-stream batched measurement (for profiling) and print it")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -153,6 +154,48 @@ class MixedWorkload:
             js.append(self.dv.job(d.luma[t], d.luma[t - 1], d.alpha[v, t], d.alpha[v, t - 1], d.cls[v, t], tf,
                                   self.out[u], i))
         return js
+
+
+def learned_measurement(wl, torch, steps, warmup, plain_psnr, plain_iters):
+    """The same CIF step with the proposal network seeding the recursion
+    (weights trained by paper_1002_1168_amd.train on generated CIF
+    sequences): classification, network forward, seeded search, MC/PSNR."""
+    me, dv = wl.me, wl.dv
+    path = os.path.join(ROOT, "paper_1002_1168_amd", "weights", "proposal_cif_s16.npy")
+    if not os.path.exists(path):
+        return None
+    net = me.Net(np.load(path, allow_pickle=False))
+    stream = dv.stream_handle()
+    outs = [dv.Outputs.alloc(wl.pairs, wl.ds.hm, wl.ds.wm) for _ in range(wl.V)]
+    seeds = [torch.zeros((wl.pairs, wl.ds.hm, wl.ds.wm, 2), dtype=torch.int16, device="cuda") for _ in range(wl.V)]
+    jobs = me.job_array([j for v in range(wl.V) for j in wl.ds.pair_jobs(v, outs[v], wl.pairs, seeds=seeds[v])])
+
+    def step():
+        me.me_classify_babs(wl.cls_frames, wl.cls_ptrs, wl.bab_ptrs, stream=stream)
+        me.me_texture_recursive(jobs, wl.params, net, stream=stream)
+        return me.me_motion_compensate_psnr(jobs, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = None
+    for _ in range(steps):
+        res = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert me.me_device_status(stream) == me.ME_OK
+    net.close()
+    classes = wl.ds.cls[:, 1:].cpu().numpy()
+    pts, its, n = summarize(outs, classes)
+    psnr = float(np.mean(res[2]))
+    out = {"mb_per_s": wl.grid_mbs * steps / dt, "ms_per_step": 1000.0 * dt / steps, "psnr_db": psnr,
+           "psnr_delta_vs_plain_db": psnr - plain_psnr, "iters_per_mb": its / max(n, 1),
+           "iters_per_mb_plain": plain_iters, "points_per_mb": pts / max(n, 1),
+           "admitted": bool(psnr >= plain_psnr - 0.05), "weights": "paper_1002_1168_amd/weights/proposal_cif_s16.npy"}
+    log(f"learned seeds: {out['mb_per_s'] / 1e6:.1f} M MB/s, PSNR {psnr:.3f} dB ({out['psnr_delta_vs_plain_db']:+.4f}), "
+        f"iters/MB {out['iters_per_mb']:.3f}")
+    return out
 
 
 def batched_measurement(torch, steps, warmup):
@@ -312,6 +355,10 @@ def main():
                 f"points/MB {entry['points_per_mb']:.2f}")
         assert me.me_device_status(stream) == me.ME_OK
 
+    learned = None
+    if not a.no_learned:
+        learned = learned_measurement(wl, torch, a.steps, a.warmup, psnr, its / max(nsearch, 1))
+
     batched = None
     if not a.no_batched:
         batched = batched_measurement(torch, a.steps, a.warmup)
@@ -344,6 +391,7 @@ def main():
                      "kernel": "pa_kernel", "kernel_ms": kern_ms},
         "cpu_baseline": cpu,
         "baselines": baselines,
+        "learned": learned,
         "batched": batched,
     }
     print(json.dumps(line), flush=True)
