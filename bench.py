@@ -31,6 +31,10 @@ PEAK_HBM_GBS = 8000.0
 CUS, CLOCK_GHZ = 256, 2.4
 PEAK_INT_TOPS = CUS * 4 * 16 * CLOCK_GHZ / 1000.0   # 32-bit VALU lane-ops/s (T), 39.3
 
+PEAK_BF16_TFLOPS = 2500.0   # dense bf16 MFMA
+# proposal network forward per MB: conv1 24x24x32x18, conv2 12x12x32x288, conv3 6x6x2x288 multiply-adds
+NET_FWD_FLOP = 2 * (576 * 32 * 18 + 144 * 32 * 288 + 36 * 2 * 288)
+
 # algorithmic VALU lane-ops of the proposed method per searched MB
 SAD_OPS = 64          # 256 absolute differences, 4 per v_sad_u8 lane-op
 PASS_OPS = 256 * 12   # gradient pass: e, gx, gy, two reciprocal lookups, two products, two counts, ...
@@ -178,23 +182,32 @@ def learned_measurement(wl, torch, steps, warmup, plain_psnr, plain_iters):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    me.me_kernel_timing(True)
+    me.me_kernel_time_ms(me.ME_KT_NET, stream)
     t0 = time.perf_counter()
     res = None
     for _ in range(steps):
         res = step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    net_ms, net_n = me.me_kernel_time_ms(me.ME_KT_NET, stream)
+    me.me_kernel_timing(False)
     assert me.me_device_status(stream) == me.ME_OK
     net.close()
     classes = wl.ds.cls[:, 1:].cpu().numpy()
+    served = int((classes == 1).sum())
+    net_ms /= max(net_n, 1)
+    tflops = served * NET_FWD_FLOP / (net_ms * 1e-3) / 1e12
     pts, its, n = summarize(outs, classes)
     psnr = float(np.mean(res[2]))
     out = {"mb_per_s": wl.grid_mbs * steps / dt, "ms_per_step": 1000.0 * dt / steps, "psnr_db": psnr,
            "psnr_delta_vs_plain_db": psnr - plain_psnr, "iters_per_mb": its / max(n, 1),
            "iters_per_mb_plain": plain_iters, "points_per_mb": pts / max(n, 1),
-           "admitted": bool(psnr >= plain_psnr - 0.05), "weights": "paper_1002_1168_amd/weights/proposal_cif_s16.npy"}
+           "admitted": bool(psnr >= plain_psnr - 0.05), "weights": "paper_1002_1168_amd/weights/proposal_cif_s16.npy",
+           "network_forward": {"kernel_ms": net_ms, "mbs": served, "bound": "mfma", "achieved": tflops,
+                               "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": tflops / PEAK_BF16_TFLOPS}}
     log(f"learned seeds: {out['mb_per_s'] / 1e6:.1f} M MB/s, PSNR {psnr:.3f} dB ({out['psnr_delta_vs_plain_db']:+.4f}), "
-        f"iters/MB {out['iters_per_mb']:.3f}")
+        f"iters/MB {out['iters_per_mb']:.3f}; network forward {net_ms:.3f} ms for {served} MBs = {tflops:.1f} TFLOP/s")
     return out
 
 

@@ -241,6 +241,14 @@ int me_batch_create(const me_job *jobs, int n, const me_params *params, uint32_t
 int me_batch_step(me_batch *b, const me_job *jobs, int n);
 int me_batch_results(me_batch *b, uint64_t *sse, uint64_t *npix, double *psnr_db, int n);
 int me_batch_config(const me_batch *b, int32_t *cfg, int ncfg);
+/* Seed the batch's searches with a proposal network (NULL detaches):
+ * every step then runs the network on the opaque MBs between the
+ * classification and the search, writing the jobs' seed buffers (so every
+ * job of the structure must carry one; ME_EINVAL otherwise).  The network
+ * must outlive the batch or be detached first; training it between steps
+ * is allowed (the graph reads its current weights).  Waits for the batch's
+ * stream and re-captures the graph. */
+int me_batch_set_net(me_batch *b, me_net *net);
 void me_batch_destroy(me_batch *b);
 
 /*
@@ -251,6 +259,9 @@ void me_batch_destroy(me_batch *b);
  *                  me_shape_search            transparent pre-pass before it)
  *  ME_KT_FULL      me_full_search             ES / TSS / DS kernel (not the compaction)
  *  ME_KT_MC        me_motion_compensate_psnr  prediction + SSE kernel (not the per-job sum)
+ *  ME_KT_NET       me_net_forward (also via   network forward kernel (not the MB list)
+ *                  me_texture_recursive)
+ *  ME_KT_NET_TRAIN me_net_train_step          forward + backward kernel (not the SGD update)
  * me_kernel_timing: on = 0 or 1 (ME_EINVAL otherwise); affects later calls.
  * me_kernel_time_ms: waits for every timed call of `kind` on `stream`, writes
  * the sum of their main-kernel durations in milliseconds (host double) and
@@ -260,6 +271,8 @@ void me_batch_destroy(me_batch *b);
 #define ME_KT_SEARCH 1
 #define ME_KT_FULL 2
 #define ME_KT_MC 3
+#define ME_KT_NET 4
+#define ME_KT_NET_TRAIN 5
 int me_kernel_timing(int on);
 int me_kernel_time_ms(int kind, void *stream, double *total_ms, int *count);
 

@@ -17,14 +17,14 @@ LIB_PATH = os.path.join(_HERE, "libme.so")
 ME_OK, ME_EINVAL, ME_EALIGN, ME_EHIP, ME_ENOMEM, ME_EEMPTY, ME_EDEVICE, ME_ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
 ME_MB_TRANSPARENT, ME_MB_OPAQUE, ME_MB_BOUNDARY = 0, 1, 2
 ME_ES, ME_TSS, ME_DS = 0, 1, 2
-ME_KT_CLASSIFY, ME_KT_SEARCH, ME_KT_FULL, ME_KT_MC = 0, 1, 2, 3
+ME_KT_CLASSIFY, ME_KT_SEARCH, ME_KT_FULL, ME_KT_MC, ME_KT_NET, ME_KT_NET_TRAIN = 0, 1, 2, 3, 4, 5
 ME_BATCH_SHAPE, ME_BATCH_AUTOTUNE = 1, 2
 ME_NET_PARAMS = 10434
 
 EXPORTED = ("me_default_params", "me_status_str", "me_shutdown", "me_classify_babs", "me_texture_recursive",
             "me_shape_search", "me_full_search", "me_motion_compensate_psnr", "me_device_status",
             "me_kernel_timing", "me_kernel_time_ms", "me_batch_create", "me_batch_step", "me_batch_results",
-            "me_batch_config", "me_batch_destroy", "me_net_create", "me_net_forward", "me_net_train_step",
+            "me_batch_config", "me_batch_set_net", "me_batch_destroy", "me_net_create", "me_net_forward", "me_net_train_step",
             "me_net_weights", "me_net_destroy")
 
 
@@ -94,6 +94,8 @@ def lib():
         L.me_batch_results.restype = i
         L.me_batch_config.argtypes = [vp, C.POINTER(C.c_int32), i]
         L.me_batch_config.restype = i
+        L.me_batch_set_net.argtypes = [vp, vp]
+        L.me_batch_set_net.restype = i
         L.me_batch_destroy.argtypes = [vp]
         L.me_batch_destroy.restype = None
         L.me_net_create.argtypes = [C.POINTER(C.c_float), C.POINTER(vp)]
@@ -233,6 +235,11 @@ class Batch:
         if check and rc != ME_OK:
             raise MeError(rc, "me_batch_results")
         return list(sse), list(npx), list(ps), rc
+
+    def set_net(self, net) -> None:
+        """Seed every step's search with proposal network ``net`` (None: plain)."""
+        _check(lib().me_batch_set_net(self.handle, None if net is None else net.handle), "me_batch_set_net")
+        self._net = net   # keep it alive while attached
 
     def config(self) -> dict:
         c = (C.c_int32 * 4)()

@@ -43,6 +43,7 @@ struct Arena {
 };
 
 enum ArenaKind { A_CLASSIFY = 0, A_PA = 1, A_SEARCH = 2, A_MC = 3, A_COUNT = 4 };
+constexpr int kTimerKinds = 6;  // the four arena kinds (ME_KT_*), then the network forward and training kernels
 
 
 // Event pairs of timed launches of one call kind: in flight until their
@@ -80,7 +81,7 @@ struct Workspace {
     PaMemo pa;
     unsigned long long *host_acc = nullptr;  // pinned readback for MC
     size_t host_acc_cap = 0;
-    TimerPool timers[A_COUNT];  // main-kernel events per call kind (timing on)
+    TimerPool timers[kTimerKinds];  // main-kernel events per call kind (timing on)
     std::mutex mu;
 };
 
@@ -254,6 +255,20 @@ int run_pa(const me_job *jobs, int n, const me_params *params, bool shape_only, 
 }
 
 }  // namespace
+
+namespace me {
+namespace host {
+
+bool kernel_timer(void *stream, int kind, KernelTimer *out) {
+    if (!g_timing.load(std::memory_order_relaxed) || kind < 0 || kind >= kTimerKinds) return false;
+    Workspace *w = nullptr;
+    if (get_ws(stream, &w) != ME_OK) return false;
+    std::lock_guard<std::mutex> lk(w->mu);
+    return timer_for(*w, kind, out);
+}
+
+}  // namespace host
+}  // namespace me
 
 extern "C" {
 
@@ -486,7 +501,7 @@ int me_kernel_timing(int on) {
 }
 
 int me_kernel_time_ms(int kind, void *stream, double *total_ms, int *count) {
-    if (kind < 0 || kind >= A_COUNT || !total_ms || !count) return ME_EINVAL;
+    if (kind < 0 || kind >= kTimerKinds || !total_ms || !count) return ME_EINVAL;
     Workspace *w = nullptr;
     int rc = get_ws(stream, &w);
     if (rc) return rc;

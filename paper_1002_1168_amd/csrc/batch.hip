@@ -36,6 +36,8 @@ struct me_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int32_t cfg[4] = {0, 1, 2, 8};  // workers, window staging (1 plan, 0 generic), poll sleep, flat MBs/CU
+    me_net *net = nullptr;          // proposal network seeding the search (optional)
+    uint8_t *net_scratch = nullptr;
     bool stepped = false;
     std::mutex mu;
 };
@@ -144,6 +146,10 @@ hipError_t launch_step(const me_batch &b, const int32_t *cfg, hipStream_t s) {
     const Bufs u = bufs(b);
     hipError_t e = launch_classify(u.jobs, b.n, b.plan.total_mbs, s, nullptr, cfg[3]);
     if (e != hipSuccess) return e;
+    if (b.net) {
+        e = net_forward_table(b.net, u.jobs, b.n, b.plan.total_mbs, b.net_scratch, s);
+        if (e != hipSuccess) return e;
+    }
     e = launch_search(b, u, cfg, s);
     if (e != hipSuccess) return e;
     return launch_mc(u.jobs, b.n, b.plan.total_mbs, u.part, u.acc, s, nullptr, cfg[3]);
@@ -274,6 +280,7 @@ void release(me_batch *b) {
         if (b->host[s]) hipHostFree(b->host[s]);
     }
     if (b->host_acc) hipHostFree(b->host_acc);
+    if (b->net_scratch) hipFree(b->net_scratch);
     if (b->dev) hipFree(b->dev);
     delete b;
 }
@@ -412,6 +419,30 @@ int me_batch_results(me_batch *b, uint64_t *sse, uint64_t *npix, double *psnr_db
         return ME_EDEVICE;
     }
     return status;
+}
+
+int me_batch_set_net(me_batch *b, me_net *net) {
+    if (!b) return ME_EINVAL;
+    std::lock_guard<std::mutex> lk(b->mu);
+    if (net) {
+        for (const auto &d : b->tmpl)
+            if (!d.seed) return ME_EINVAL;  // the seeds are written into the jobs' seed buffers
+        if (b->n > 65535) return ME_EINVAL;
+        for (const auto &d : b->tmpl)
+            if (d.wm * d.hm > 65536) return ME_EINVAL;
+    }
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return ME_EHIP;
+    if (net && !b->net_scratch &&
+        hipMalloc(&b->net_scratch, align_up(net_table_scratch(b->plan.total_mbs), 256)) != hipSuccess) {
+        b->net_scratch = nullptr;
+        return ME_ENOMEM;
+    }
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->net = net;
+    return capture(*b);
 }
 
 int me_batch_config(const me_batch *b, int32_t *cfg, int ncfg) {

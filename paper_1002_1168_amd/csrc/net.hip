@@ -143,6 +143,19 @@ int net_seed_jobs(me_net *net, const me_job *jobs, int n, void *stream) {
     return me_net_forward(net, jobs, n, nullptr, stream);
 }
 
+size_t net_table_scratch(int total_mbs) { return net_list_scratch(total_mbs); }
+
+// Seeds for an already uploaded job table (used inside captured graphs: no
+// allocation, no host synchronisation, no timing events).
+hipError_t net_forward_table(me_net *net, const JobDesc *table, int n, int total_mbs, uint8_t *scratch,
+                             hipStream_t s) {
+    const uint32_t *list = nullptr, *count = nullptr;
+    hipError_t e = launch_net_list(table, n, total_mbs, scratch, &list, &count, s);
+    if (e != hipSuccess) return e;
+    const int groups = (int)std::min<long long>(total_mbs, (long long)net->cus * 3);
+    return launch_net(false, table, n, list, count, net->P, net->wb, nullptr, groups, s);
+}
+
 }  // namespace host
 }  // namespace me
 
@@ -212,7 +225,9 @@ int me_net_forward(me_net *net, const me_job *jobs, int n, float *const *pred, v
     const JobDesc *tab = (const JobDesc *)net->buf;
     if (launch_net_list(tab, n, (int)total, net->buf + o_list, &list, &count, s) != hipSuccess) return ME_EHIP;
     const int groups = (int)std::min<long long>(total, (long long)net->cus * 3);
-    return hip_err(launch_net(false, tab, n, list, count, net->P, net->wb, nullptr, groups, s));
+    KernelTimer kt;
+    const bool timed = kernel_timer(stream, ME_KT_NET, &kt);
+    return hip_err(launch_net(false, tab, n, list, count, net->P, net->wb, nullptr, groups, s, timed ? &kt : nullptr));
 }
 
 int me_net_train_step(me_net *net, const me_job *jobs, int n, const me_mv *const *labels, float lr, float momentum,
@@ -242,7 +257,10 @@ int me_net_train_step(me_net *net, const me_job *jobs, int n, const me_mv *const
     if (launch_net_list(tab, n, (int)total, net->buf + o_list, &list, &count, s) != hipSuccess) return ME_EHIP;
     float *part = (float *)(net->buf + o_part);
     double *dloss = (double *)(net->buf + o_loss);
-    if (launch_net(true, tab, n, list, count, net->P, net->wb, part, groups, s) != hipSuccess) return ME_EHIP;
+    KernelTimer kt;
+    const bool timed = kernel_timer(stream, ME_KT_NET_TRAIN, &kt);
+    if (launch_net(true, tab, n, list, count, net->P, net->wb, part, groups, s, timed ? &kt : nullptr) != hipSuccess)
+        return ME_EHIP;
     if (launch_net_sgd(net->P, net->V, net->wb, part, groups, lr, momentum, grad, dloss, s) != hipSuccess)
         return ME_EHIP;
     if (loss) {

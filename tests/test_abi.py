@@ -112,7 +112,7 @@ def test_kernel_timing_validation():
     assert L.me_kernel_timing(2) == me.ME_EINVAL
     assert L.me_kernel_timing(0) == me.ME_OK
     ms, cnt = C.c_double(), C.c_int()
-    assert L.me_kernel_time_ms(4, None, C.byref(ms), C.byref(cnt)) == me.ME_EINVAL
+    assert L.me_kernel_time_ms(6, None, C.byref(ms), C.byref(cnt)) == me.ME_EINVAL
     assert L.me_kernel_time_ms(-1, None, C.byref(ms), C.byref(cnt)) == me.ME_EINVAL
     assert L.me_kernel_time_ms(me.ME_KT_SEARCH, None, None, C.byref(cnt)) == me.ME_EINVAL
 

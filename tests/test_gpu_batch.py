@@ -166,3 +166,49 @@ def test_batch_rejects_other_structure(torch_cuda):
         assert b.results(check=False)[3] in (me.ME_OK, me.ME_EEMPTY)   # a VOP may be empty in a frame
     finally:
         b.close()
+
+
+def test_batch_with_proposal_network(torch_cuda):
+    """A network attached to the batch: every step's seeds and results equal
+    the eager network-seeded search, and the oracle's search fed those seeds."""
+    import torch
+    from paper_1002_1168_amd.device import Outputs, job, stream_handle
+    seqs = synth.mixed_streams(seed=28, frames=4, counts=(1, 1, 1))
+    st = Streams(seqs, 3)
+    p = me.me_default_params(search_range=16)
+    w = synth.net_init(5)
+    w[-2:] = [0.7, -1.3]
+    seeds = [torch.zeros((st.pairs, st.ds[si].hm, st.ds[si].wm, 2), dtype=torch.int16, device="cuda")
+             for si, _ in st.units]
+    eager_out = [Outputs.alloc(st.pairs, st.ds[si].hm, st.ds[si].wm) for si, _ in st.units]
+    eager_seeds = [torch.zeros_like(x) for x in seeds]
+
+    def jobs(i, outs, sd):
+        js = st.jobs(i, outs)
+        for u, j in enumerate(js):
+            j.seed = sd[u][i].data_ptr()
+        return js
+
+    s = stream_handle()
+    net = me.Net(w)
+    b = me.Batch(jobs(0, st.out, seeds), p, 0, stream=s)
+    try:
+        b.set_net(net)
+        for i in range(st.pairs):
+            b.step(jobs(i, st.out, seeds))
+            b.results(check=False)
+            me.me_texture_recursive(jobs(i, eager_out, eager_seeds), p, net, stream=s)
+            torch.cuda.synchronize()
+            for u in range(len(st.units)):
+                assert torch.equal(seeds[u][i], eager_seeds[u][i]), f"step {i} unit {u}: seeds"
+                g = {k: a[i:i + 1] for k, a in st.out[u].host().items()}
+                e = {k: a[i:i + 1] for k, a in eager_out[u].host().items()}
+                assert_same(g, e, f"net batch step {i} unit {u}")
+    finally:
+        b.close()
+        net.close()
+    for u, (si, v) in enumerate(st.units):
+        res = oracle.pa_sequence(st.seqs[si], v, oracle_params(p), pairs=st.pairs,
+                                 seeds=list(seeds[u].cpu().numpy()))
+        want = {k: np.stack([r[k] for r in res]) for k in ("mv", "mv_int", "cost", "iters", "points")}
+        assert_same(st.out[u].host(), want, f"net batch unit {u} vs oracle")
