@@ -85,7 +85,8 @@ typedef struct me_job {
     const uint8_t *mb_class; /* per-MB class from me_classify_babs of cur; NULL = all opaque */
     const me_mv *t_field;    /* temporal candidates T (previous pair's mv_int); NULL = zeros.
                                 May point at the mv_int of an EARLIER job of the same call:
-                                that pair is then solved first, MB by MB (pipelined). */
+                                that pair is then solved first, MB by MB (pipelined); such a
+                                chain holds at most 65535 pairs (ME_EINVAL otherwise). */
     const me_mv *seed;       /* learned starting vectors for texture MBs; NULL = plain method */
     me_mv *mv;               /* out: final vector (half-pel) */
     me_mv *mv_int;           /* out: full-pel vector before half-sample refinement (feeds A, B, C, T) */

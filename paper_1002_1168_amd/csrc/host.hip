@@ -72,6 +72,8 @@ KParams kparams(const me_params *p, bool shape_only) {
     k.shape_only = shape_only ? 1 : 0;
     k.spin_limit = kSpinLimit;
     k.poll_sleep = 2;
+    // eps * U rounds to a zero step iff |eps * U| < 2^23, i.e. |U| < ceil(2^23 / eps)
+    k.zero_t = p->eps_q12 > 0 ? (int32_t)(((1ll << 23) + p->eps_q12 - 1) / p->eps_q12) : 0x7FFFFFFF;
     return k;
 }
 
@@ -142,6 +144,8 @@ int build_pa(const me_job *jobs, int n, PaMemo &m) {
     }
     const int nc = (int)chains.size();
     if (nc > kMaxChains) return ME_EINVAL;
+    for (const auto &ch : chains)
+        if (ch.size() > 65535) return ME_EINVAL;  // progress words count pairs in 16 bits
     // descriptors in chain order: chain c's pair p at cd[c].first + p
     std::vector<ChainDesc> cd(nc);
     std::vector<JobDesc> ordered;

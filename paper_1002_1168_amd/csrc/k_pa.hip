@@ -56,16 +56,24 @@ struct PaArgs {
     int rows;   // window rows = columns = 2S + 18
 };
 
+// Device-scope relaxed accesses through global (not flat) addresses: flat
+// operations also count in the LDS counter, and an outstanding flat store
+// would then delay every later LDS read of the search.
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+typedef __attribute__((address_space(1))) uint16_t g_u16;
+typedef __attribute__((address_space(1))) uint8_t g_u8;
+
 __device__ __forceinline__ uint32_t ld_relaxed(const uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load((g_u32 *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void st_relaxed(uint32_t *p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store((g_u32 *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ unsigned long long ld64(const unsigned long long *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    typedef __attribute__((address_space(1))) unsigned long long g_u64;
+    return __hip_atomic_load((const g_u64 *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Wait until at most N vector-memory operations of this wave are in flight
@@ -74,30 +82,41 @@ __device__ __forceinline__ unsigned long long ld64(const unsigned long long *p) 
 // issued before the N most recent ones has completed.
 template <int N>
 __device__ __forceinline__ void wait_vm_at_most() {
-    static_assert(N == 0 || N == 4 || N == 12 || N == 28, "wait count");
+    static_assert(N == 0 || N == 9 || N == 17 || N == 33, "wait count");
     if constexpr (N == 0) asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
-    if constexpr (N == 4) asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)" ::: "memory");
-    if constexpr (N == 12) asm volatile("s_waitcnt vmcnt(12) lgkmcnt(0)" ::: "memory");
-    if constexpr (N == 28) asm volatile("s_waitcnt vmcnt(28) lgkmcnt(0)" ::: "memory");
+    if constexpr (N == 9) asm volatile("s_waitcnt vmcnt(9) lgkmcnt(0)" ::: "memory");
+    if constexpr (N == 17) asm volatile("s_waitcnt vmcnt(17) lgkmcnt(0)" ::: "memory");
+    if constexpr (N == 33) asm volatile("s_waitcnt vmcnt(33) lgkmcnt(0)" ::: "memory");
 }
 
-// Publish (pairs done, vector of the latest pair) once every memory access
-// of this wave older than its N most recent vector-memory operations has
-// completed.
+// Progress word of a line: pairs done (bits 0-15) and the full-pel vectors
+// of the last three pairs done (bits 16-31 latest, 32-47, 48-63), each as two
+// signed bytes (|d| <= 64).  Published once every memory access of this wave
+// older than its N most recent vector-memory operations has completed.
 template <int N = 0>
-__device__ __forceinline__ void publish(unsigned long long *p, uint32_t done, uint32_t mvi) {
+__device__ __forceinline__ void publish(unsigned long long *p, unsigned long long word) {
     wait_vm_at_most<N>();
-    __hip_atomic_store(p, ((unsigned long long)mvi << 32) | done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint32_t pack_mv(int x, int y) { return (uint32_t)(uint16_t)x | ((uint32_t)(uint16_t)y << 16); }
 __device__ __forceinline__ int mvx_full(uint32_t w) { return ((int)(int16_t)(w & 0xFFFF)) >> 1; }
 __device__ __forceinline__ int mvy_full(uint32_t w) { return ((int)(int16_t)(w >> 16)) >> 1; }
+__device__ __forceinline__ uint32_t enc8(int dx, int dy) { return (uint32_t)(uint8_t)dx | ((uint32_t)(uint8_t)dy << 8); }
+__device__ __forceinline__ unsigned long long progress_word(uint32_t done, uint32_t h0, uint32_t h1, uint32_t h2) {
+    return (unsigned long long)done | ((unsigned long long)h0 << 16) | ((unsigned long long)h1 << 32) |
+           ((unsigned long long)h2 << 48);
+}
 
-// Vector of pair `need-1` of a line whose progress word is `w`: carried by the
-// word when the line is exactly there, else read from that pair's array.
+// Vector (half-pel pair) of pair `need-1` of a line whose progress word is
+// `w`: carried by the word when the line is at most three pairs past it,
+// else read from that pair's array.
 __device__ __forceinline__ uint32_t mv_of(unsigned long long w, uint32_t need, const uint32_t *arr) {
-    if ((uint32_t)w == need) return (uint32_t)(w >> 32);
+    const uint32_t age = ((uint32_t)w & 0xFFFFu) - need;
+    if (age < 3) {
+        const uint32_t e = (uint32_t)(w >> (16 + 16 * age)) & 0xFFFFu;
+        return pack_mv(2 * (int)(int8_t)(e & 0xFF), 2 * (int)(int8_t)(e >> 8));
+    }
     return (uint32_t)uni((int)ld_relaxed(arr));
 }
 
@@ -151,7 +170,8 @@ template <int EM>
 struct Plan {
     uint32_t loc[EM];  // clamped frame row << 16 | clamped column of the dword
     uint32_t sel[EM];  // byte selectors replicating the frame edge
-    int total;
+    uint32_t off[EM];  // byte offsets row * stride + column for stride `st`
+    int total, st;
 
     __device__ __forceinline__ void init(int pitch, int rows, int x0, int y0, int S, int W, int H) {
         const int l = lane();
@@ -170,12 +190,21 @@ struct Plan {
                      ((uint32_t)(iclamp(xx + 2, 0, W - 1) - xc) << 16) |
                      ((uint32_t)(iclamp(xx + 3, 0, W - 1) - xc) << 24);
         }
+        st = -1;
+    }
+    // byte offsets for row pitch `stride` (kept while the pitch repeats)
+    __device__ __forceinline__ void offsets(int stride) {
+        if (stride == st) return;
+        st = stride;
+#pragma unroll
+        for (int u = 0; u < EM; ++u) off[u] = (loc[u] >> 16) * (uint32_t)stride + (loc[u] & 0xFFFFu);
     }
     // loads only; every address is in frame, elements past the window
     // re-read the window origin and are never written
-    __device__ __forceinline__ void issue(const uint8_t *P, int st, uint32_t (&v)[EM]) const {
+    __device__ __forceinline__ void issue(const uint8_t *P, int stride, uint32_t (&v)[EM]) {
+        offsets(stride);
 #pragma unroll
-        for (int u = 0; u < EM; ++u) v[u] = ld4(P + (size_t)(loc[u] >> 16) * st + (loc[u] & 0xFFFFu));
+        for (int u = 0; u < EM; ++u) v[u] = ld4(P + off[u]);
     }
     __device__ __forceinline__ void write(uint32_t *win, const uint32_t (&v)[EM], bool shape) const {
         const int l = lane();
@@ -255,10 +284,13 @@ __device__ int pel_recursion(const Ctx &c, const KParams &kp, int &dx, int &dy, 
     int it = 0;
     while (it < kp.k_max) {
         const int nx = sw.nxy & 0xFFFF, ny = sw.nxy >> 16;
-        const int ux = nx ? sw.sx / nx : 0;
-        const int uy = ny ? sw.sy / ny : 0;
-        const int sx = prs_step(ux, kp.eps, kp.max_step);
-        const int sy = prs_step(uy, kp.eps, kp.max_step);
+        // U = trunc(S / n) gives a zero step iff |U| < zero_t, i.e. |S| < zero_t * n:
+        // decided without the divisions, which most MBs then skip
+        const bool zx = nx == 0 || llabs((long long)sw.sx) < (long long)kp.zero_t * nx;
+        const bool zy = ny == 0 || llabs((long long)sw.sy) < (long long)kp.zero_t * ny;
+        if (zx && zy) break;
+        const int sx = zx ? 0 : prs_step(sw.sx / nx, kp.eps, kp.max_step);
+        const int sy = zy ? 0 : prs_step(sw.sy / ny, kp.eps, kp.max_step);
         if (sx == 0 && sy == 0) break;
         const int tx = iclamp(dx + sx, c.lox, c.hix);
         const int ty = iclamp(dy + sy, c.loy, c.hiy);
@@ -449,14 +481,14 @@ __device__ __forceinline__ uint32_t load_desc(const JobDesc *J) {
 
 __device__ __forceinline__ void store_result(const DescReg &D, int k, uint32_t mv, uint32_t mvi, uint32_t cost,
                                              int iters, int points) {
-    D.ptr<uint32_t>(DW(mv))[k] = mv;
+    ((g_u32 *)D.ptr<uint32_t>(DW(mv)))[k] = mv;
     st_relaxed(D.ptr<uint32_t>(DW(mv_int)) + k, mvi);
     uint32_t *co = D.ptr<uint32_t>(DW(cost));
     uint8_t *it = D.ptr<uint8_t>(DW(iters));
     uint16_t *pt = D.ptr<uint16_t>(DW(points));
-    if (co) co[k] = cost;
-    if (it) it[k] = (uint8_t)iters;
-    if (pt) pt[k] = (uint16_t)points;
+    if (co) ((g_u32 *)co)[k] = cost;
+    if (it) ((g_u8 *)it)[k] = (uint8_t)iters;
+    if (pt) ((g_u16 *)pt)[k] = (uint16_t)points;
 }
 
 // Pre-pass over every MB of every pair: a transparent MB gets its (zero)
@@ -569,9 +601,7 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
     extern __shared__ uint32_t lds[];
     __shared__ int slot;
     short *R = (short *)lds;                     // 511 reciprocal entries (Eq. 4-5, Q.12)
-    const int wwords = (a.rows * a.pitch + 16) >> 2;
-    uint32_t *const win0 = lds + 256;            // staged reference windows (two when EM > 0)
-    uint32_t *const win1 = lds + 256 + (EM > 0 ? wwords : 0);
+    uint32_t *const win0 = lds + 256;            // staged reference window
     const KParams kp = a.kp;
     for (int g = lane(); g < 511; g += 64) {
         const int m = abs(g - 255);
@@ -613,10 +643,15 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
         uint32_t wT = 0, wB = 0, wA = 0, wBn = 0, wC = 0;
         int wi = -1;
         int tx = 0, ty = 0;
-        uint32_t dnext = 0;
-        bool have_next = false;
-        bool staged = false;   // this pair's window is already in `cur_win`
-        uint32_t *cur_win = win0, *alt_win = win1;
+        uint32_t hist1 = 0, hist2 = 0;  // encoded vectors of the two pairs before the latest
+        // descriptors of pairs p and p + 1 (valid flags v0, v1), fetched ahead
+        uint32_t d0 = 0, d1 = 0;
+        bool v0 = false, v1 = false;
+        // pf: pair p's polls, current pixels and window were issued during pair p - 1
+        bool pf = false;
+        unsigned long long pval[4] = {0ull, 0ull, 0ull, 0ull};
+        uint32_t pcur4 = 0;
+        uint32_t pnv[EM > 0 ? EM : 1];
         int p = 0;
         while (p < ch.len) {
             if ((p >> 5) != wi) {
@@ -635,19 +670,27 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
                 int r = ones ? __builtin_ctz(ones) : 32 - b;
                 r = min(r, min(32 - b, ch.len - p));
                 p += r;
+                // the newest history entries are the run's zero vectors
+                const uint32_t h0n = enc8(tx, ty);
+                const uint32_t g1 = r >= 2 ? 0u : h0n, g2 = r >= 3 ? 0u : (r == 2 ? h0n : hist1);
+                hist1 = g1;
+                hist2 = g2;
                 tx = ty = 0;
-                have_next = false;
-                staged = false;
-                if (l == 0) publish(own, (uint32_t)p, 0u);
+                v0 = v1 = pf = false;
+                if (l == 0) publish(own, progress_word((uint32_t)p, 0u, hist1, hist2));
                 continue;
             }
-            const uint32_t dcur = have_next ? dnext : load_desc(jobs + p);
+            const uint32_t dcur = v0 ? d0 : load_desc(jobs + p);
             const DescReg D{dcur};
-            have_next = p + 1 < ch.len && !(b < 31 && ((wT >> (b + 1)) & 1u));
-            if (have_next) dnext = load_desc(jobs + p + 1);   // in flight during this pair
-            // the next pair is known to be searched: its window is loaded
-            // during this pair's search
-            const bool pre = EM > 0 && p + 1 < ch.len && b < 31 && !((wT >> (b + 1)) & 1u);
+            // the next pair is searched and in this mask word: its descriptor
+            // is fetched now unless it already was, and (staged plan) its
+            // polls, current pixels and window are issued during this search
+            const bool nxt = p + 1 < ch.len && b < 31 && !((wT >> (b + 1)) & 1u);
+            const bool pre = EM > 0 && nxt;
+            if (nxt && !v1) {
+                d1 = load_desc(jobs + p + 1);
+                v1 = true;
+            }
             const uint32_t need = (uint32_t)(p + 1);
             // neighbours in this pair; transparent ones contribute (0, 0)
             // without a wait
@@ -662,16 +705,15 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
                                                     use[2] ? own - wm + 1 : own,
                                                     hasT ? a.progress + dep_line + k : own};
             const uint32_t nd[4] = {need, need, need, (uint32_t)(D.i32(DW(dep_pos)) + 1)};
-            // first poll, in flight together with the window staging
             unsigned long long val[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) val[i] = ld64(w[i]);
+            for (int i = 0; i < 4; ++i) val[i] = pf ? pval[i] : ld64(w[i]);
             Ctx c;
             c.shape = ((wB >> b) & 1u) != 0;
             const uint8_t *Pc = c.shape ? D.ptr<const uint8_t>(DW(cur_a)) : D.ptr<const uint8_t>(DW(cur));
             const uint8_t *Pr = c.shape ? D.ptr<const uint8_t>(DW(ref_a)) : D.ptr<const uint8_t>(DW(ref));
             const int st = D.i32(DW(stride));
-            c.win = cur_win;
+            c.win = win0;
             c.R = R;
             c.pitch = a.pitch;
             c.S = S;
@@ -684,24 +726,23 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
             c.hix = min(S, W - 16 - x0);
             c.loy = max(-S, -y0);
             c.hiy = min(S, H - 16 - y0);
-            const uint32_t cur4 = ldg32((const uint32_t *)(Pc + (size_t)(y0 + j) * st + x0 + 4 * q));
-            if (!staged) {
+            const uint32_t cur4 = pf ? pcur4 : ldg32((const uint32_t *)(Pc + (size_t)(y0 + j) * st + x0 + 4 * q));
+            if (!pf) {
                 if constexpr (EM > 0) {
                     uint32_t wv[EM];
                     plan.issue(Pr, st, wv);
-                    plan.write(cur_win, wv, c.shape);
+                    plan.write(win0, wv, c.shape);
                 } else {
-                    stage_window(cur_win, a.pitch, a.rows, Pr, st, W, H, x0, y0, S, c.shape);
+                    stage_window(win0, a.pitch, a.rows, Pr, st, W, H, x0, y0, S, c.shape);
                 }
             }
-            c.c4 = c.shape ? bin4(cur4) : cur4;
             // remaining polls
             int spins = 0;
             for (;;) {
                 bool ok = true;
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    if (use[i]) ok = ok && (uint32_t)uni((int)(uint32_t)val[i]) >= nd[i];
+                    if (use[i]) ok = ok && ((uint32_t)uni((int)(uint32_t)val[i]) & 0xFFFFu) >= nd[i];
                 if (ok) break;
                 if ((spins & 31) == 31 && (uni((int)ld_relaxed(a.status)) & ST_ABORT)) return;
                 if (++spins > kp.spin_limit) {
@@ -718,6 +759,12 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
                 for (int i = 0; i < 4; ++i) val[i] = ld64(w[i]);
             }
             asm volatile("" ::: "memory");  // vector reads stay after the polls
+            // the window prefetched during the previous pair (a single wave:
+            // that pair's reads of the buffer have all returned)
+            if constexpr (EM > 0) {
+                if (pf) plan.write(win0, pnv, c.shape);
+            }
+            c.c4 = c.shape ? bin4(cur4) : cur4;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const uint32_t lo = (uint32_t)uni((int)(uint32_t)val[i]);
@@ -742,40 +789,56 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
                 cx[3] = tx;
                 cy[3] = ty;
             }
-            __syncthreads();  // window writes visible to every lane
-            // next pair's window loads fly during this search
-            uint32_t nv[EM > 0 ? EM : 1];
-            bool nshape = false;
+            // window writes visible to every lane: the workgroup is one wave,
+            // so completing its LDS writes (and a compiler fence) suffices
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            // pair p + 1 while this one is searched: the descriptor of p + 2,
+            // then the polls, current pixels and window of p + 1
+            bool v2 = false;
+            uint32_t d2 = 0;
             if constexpr (EM > 0) {
                 if (pre) {
-                    const DescReg Dn{dnext};
-                    nshape = ((wB >> (b + 1)) & 1u) != 0;
-                    plan.issue(nshape ? Dn.ptr<const uint8_t>(DW(ref_a)) : Dn.ptr<const uint8_t>(DW(ref)),
-                               Dn.i32(DW(stride)), nv);
+                    if (p + 2 < ch.len && b < 30 && !((wT >> (b + 2)) & 1u)) {
+                        d2 = load_desc(jobs + p + 2);
+                        v2 = true;
+                    }
+                    const DescReg Dn{d1};
+                    const int bn = b + 1;
+                    const int dl_n = Dn.i32(DW(dep_line_base));
+                    const bool hasT_n = dl_n >= 0 && Dn.i32(DW(t_local)) == 0;
+                    const unsigned long long *const wn[4] = {
+                        inA && !((wA >> bn) & 1u) ? own - 1 : own, inB && !((wBn >> bn) & 1u) ? own - wm : own,
+                        inC && !((wC >> bn) & 1u) ? own - wm + 1 : own, hasT_n ? a.progress + dl_n + k : own};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) pval[i] = ld64(wn[i]);
+                    const bool nshape = ((wB >> bn) & 1u) != 0;
+                    const uint8_t *Pcn = nshape ? Dn.ptr<const uint8_t>(DW(cur_a)) : Dn.ptr<const uint8_t>(DW(cur));
+                    const uint8_t *Prn = nshape ? Dn.ptr<const uint8_t>(DW(ref_a)) : Dn.ptr<const uint8_t>(DW(ref));
+                    const int stn = Dn.i32(DW(stride));
+                    pcur4 = ldg32((const uint32_t *)(Pcn + (size_t)(y0 + j) * stn + x0 + 4 * q));
+                    plan.issue(Prn, stn, pnv);
                 }
             }
             const MbOut o = search_mb(D.ptr<const uint32_t>(DW(seed)), c, k, cx, cy, kp);
-            // publish first: the next window's loads (the EM most recent
-            // vector-memory operations) stay in flight across it
+            // publish: the wait leaves the next pair's loads (at least the
+            // EM + 5 most recent vector-memory operations) in flight
+            const unsigned long long word = progress_word(need, enc8(o.dx, o.dy), enc8(tx, ty), hist1);
             if (l == 0) {
-                if (EM > 0 && pre)
-                    publish<(EM > 0 ? EM : 0)>(own, need, o.mvi);
+                if (pre)
+                    publish<(EM > 0 ? EM + 5 : 0)>(own, word);
                 else
-                    publish(own, need, o.mvi);
+                    publish(own, word);
             }
-            staged = false;
-            if constexpr (EM > 0) {
-                if (pre) {
-                    plan.write(alt_win, nv, nshape);
-                    uint32_t *tw = cur_win;
-                    cur_win = alt_win;
-                    alt_win = tw;
-                    staged = true;
-                }
-            }
+            hist2 = hist1;
+            hist1 = enc8(tx, ty);
             if (l == 0) store_result(D, k, o.mv, o.mvi, o.cost, o.iters, o.points);
             tx = o.dx;
             ty = o.dy;
+            pf = pre;
+            d0 = d1;
+            v0 = v1;
+            d1 = d2;
+            v1 = v2;
             ++p;
         }
     }
@@ -800,7 +863,8 @@ int pa_worker_cap() {
 size_t pa_lds_bytes(int S, bool generic) {
     const int rows = 2 * S + 18, pitch = (rows + 3) & ~3;
     const size_t one = (size_t)rows * pitch + 16;
-    return 1024 + (plan_elems(S) > 0 && !generic ? 2 : 1) * one;
+    (void)generic;
+    return 1024 + one;
 }
 
 hipError_t launch_scan_counts(uint32_t *counts, int n, uint32_t *total, hipStream_t s) {
