@@ -400,13 +400,19 @@ __device__ MbOut search_mb(const uint32_t *seed, const Ctx &c, int k, int (&cx)[
         keep[0] = true;
         n = 1;
     }
-    // block costs of the list, two 16-bit partial SADs per reduction
-    int part[4] = {0, 0, 0, 0};
+    // block costs of the list, two 16-bit partial SADs per reduction.  All
+    // four are computed without branches (their LDS reads in flight
+    // together): an offset clamped to +-S lies inside the staged window, and
+    // the cost of a dropped candidate is never used.
+    uint32_t blk[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-        if (keep[i]) part[i] = (int)__builtin_amdgcn_sad_u8(c.c4, lds4(c.win, c.off0 + cy[i] * c.pitch + cx[i]), 0u);
+        blk[i] = lds4(c.win, c.off0 + iclamp(cy[i], -c.S, c.S) * c.pitch + iclamp(cx[i], -c.S, c.S));
+    int part[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) part[i] = (int)__builtin_amdgcn_sad_u8(c.c4, blk[i], 0u);
     const int p01 = wave_sum(part[0] | (part[1] << 16));
-    const int p23 = (keep[2] || keep[3]) ? wave_sum(part[2] | (part[3] << 16)) : 0;
+    const int p23 = wave_sum(part[2] | (part[3] << 16));
     const int costs[4] = {p01 & 0xFFFF, (int)((uint32_t)p01 >> 16), p23 & 0xFFFF, (int)((uint32_t)p23 >> 16)};
     // Min[...]: the first minimum in list order
     int dx = 0, dy = 0, bc = 0x7FFFFFFF;
