@@ -229,9 +229,11 @@ int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, u
  * me_motion_compensate_psnr), ME_EEMPTY if a job has no VOP pixel,
  * ME_EDEVICE if a kernel raised the device status word (then cleared).
  *
- * me_batch_config writes the launch configuration in use (ncfg >= 4):
- * search workers, window staging (1 staged plan, 0 generic), dependency-poll
- * back-off (s_sleep units), MB blocks per CU of the flat kernels.
+ * me_batch_config writes the launch configuration in use (ncfg >= 4; a
+ * fifth entry when ncfg >= 5): search workers, window staging (1 staged
+ * plan, 0 generic), dependency-poll back-off (s_sleep units), MB blocks per
+ * CU of the flat kernels, waves per line worker (1, or 2: one works ahead on
+ * the next searched pair).
  * me_batch_destroy waits for the batch's stream and frees it (NULL is a no-op).
  */
 typedef struct me_batch me_batch;

@@ -242,9 +242,10 @@ class Batch:
         self._net = net   # keep it alive while attached
 
     def config(self) -> dict:
-        c = (C.c_int32 * 4)()
-        _check(lib().me_batch_config(self.handle, c, 4), "me_batch_config")
-        return {"workers": c[0], "staging": "plan" if c[1] else "generic", "poll_sleep": c[2], "flat_per_cu": c[3]}
+        c = (C.c_int32 * 5)()
+        _check(lib().me_batch_config(self.handle, c, 5), "me_batch_config")
+        return {"workers": c[0], "staging": "plan" if c[1] else "generic", "poll_sleep": c[2], "flat_per_cu": c[3],
+                "waves_per_line": c[4]}
 
     def close(self) -> None:
         if self.handle:

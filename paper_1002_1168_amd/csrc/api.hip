@@ -245,13 +245,16 @@ int run_pa(const me_job *jobs, int n, const me_params *params, bool shape_only, 
     uint8_t *base = nullptr, *zb = nullptr, *sb = nullptr;
     rc = upload(*w, A_PA, m.blob, zero, &base, &zb, pa_scratch_bytes(m.nlines), &sb);
     if (rc) return rc;
-    int workers = std::min(m.nlines, pa_worker_cap());
+    // two waves per line (one works ahead on the next searched pair) while
+    // every line still gets a worker; one wave per line when lines are many
+    const int waves = m.nlines <= pa_worker_cap() / 2 ? 2 : 1;
+    int workers = std::min(m.nlines, pa_worker_cap() / waves);
     KernelTimer kt;
     KParams kp = kparams(params, shape_only);
     return hip_err(launch_pa((const JobDesc *)(base + m.o_jobs), m.n, m.total_mbs, (const ChainDesc *)(base + m.o_ch),
                              (const uint32_t *)(base + m.o_tk), m.nlines, (unsigned long long *)(zb + o_prog),
                              (uint32_t *)(zb + o_ctr), (uint32_t *)(zb + o_mask), m.mask_words, sb, w->status, kp,
-                             workers, w->stream, timer_for(*w, A_PA, &kt) ? &kt : nullptr));
+                             workers, w->stream, timer_for(*w, A_PA, &kt) ? &kt : nullptr, false, waves));
 }
 
 }  // namespace

@@ -35,7 +35,7 @@ struct me_batch {
     unsigned long long *host_acc = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int32_t cfg[4] = {0, 1, 2, 8};  // workers, window staging (1 plan, 0 generic), poll sleep, flat MBs/CU
+    int32_t cfg[5] = {0, 1, 2, 8, 1};  // workers, window staging (1 plan, 0 generic), poll sleep, flat MBs/CU, waves per line
     me_net *net = nullptr;          // proposal network seeding the search (optional)
     uint8_t *net_scratch = nullptr;
     bool stepped = false;
@@ -138,7 +138,7 @@ hipError_t launch_search(const me_batch &b, const Bufs &u, const int32_t *cfg, h
     if (e != hipSuccess) return e;
     return launch_pa(u.jobs, b.n, b.plan.total_mbs, u.chains, u.tickets, b.plan.nlines, u.progress, u.counter, u.masks,
                      b.plan.mask_words, u.pscr, u.status, batch_kparams(b, cfg[2]), cfg[0], s, nullptr,
-                     cfg[1] == 0);
+                     cfg[1] == 0, cfg[4]);
 }
 
 // The whole frame step with configuration `cfg` on stream `s`.
@@ -183,32 +183,37 @@ int autotune(me_batch &b) {
     }
     const Bufs u = bufs(b);
     int rc = ME_OK;
-    int32_t best[4] = {b.cfg[0], b.cfg[1], b.cfg[2], b.cfg[3]};
+    int32_t best[5] = {b.cfg[0], b.cfg[1], b.cfg[2], b.cfg[3], b.cfg[4]};
     if (launch_classify(u.jobs, b.n, b.plan.total_mbs, b.stream, nullptr, best[3]) != hipSuccess) rc = ME_EHIP;
-    const int cap = std::min(b.plan.nlines, pa_worker_cap());
-    std::vector<int> workers = {cap};
-    for (int w : {cap / 2, cap / 4})
-        if (w >= 64 && w != workers.back()) workers.push_back(w);
     std::vector<int> staging = {1};
     if (plan_elems(b.params.search_range) > 0) staging.push_back(0);
     float best_ms = -1.f;
-    for (int w : workers)
-        for (int st : staging)
-            for (int sl : {1, 2, 4}) {
-                if (rc) break;
-                const int32_t c[4] = {w, st, sl, best[3]};
-                float ms = time_min(b, e0, e1, [&] { return launch_search(b, u, c, b.stream); });
-                if (ms < 0.f) {
-                    rc = ME_EHIP;
-                    break;
+    for (int wavesn : {1, 2}) {
+        // workgroups of `wavesn` waves; the same wave budget
+        const int cap = std::min(b.plan.nlines, pa_worker_cap() / wavesn);
+        std::vector<int> workers = {cap};
+        for (int w : {cap / 2, cap / 4})
+            if (w >= 64 && w != workers.back()) workers.push_back(w);
+        for (int w : workers)
+            for (int st : staging)
+                for (int sl : {1, 2, 4}) {
+                    if (rc) break;
+                    if (wavesn == 2 && sl != 1) continue;  // the two-wave worker polls with a fixed back-off
+                    const int32_t c[5] = {w, st, sl, best[3], wavesn};
+                    float ms = time_min(b, e0, e1, [&] { return launch_search(b, u, c, b.stream); });
+                    if (ms < 0.f) {
+                        rc = ME_EHIP;
+                        break;
+                    }
+                    if (best_ms < 0.f || ms < best_ms) {
+                        best_ms = ms;
+                        best[0] = w;
+                        best[1] = st;
+                        best[2] = sl;
+                        best[4] = wavesn;
+                    }
                 }
-                if (best_ms < 0.f || ms < best_ms) {
-                    best_ms = ms;
-                    best[0] = w;
-                    best[1] = st;
-                    best[2] = sl;
-                }
-            }
+    }
     best_ms = -1.f;
     for (int pc : {4, 8, 16}) {
         if (rc) break;
@@ -229,7 +234,7 @@ int autotune(me_batch &b) {
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc == ME_OK)
-        for (int i = 0; i < 4; ++i) b.cfg[i] = best[i];
+        for (int i = 0; i < 5; ++i) b.cfg[i] = best[i];
     return rc;
 }
 
@@ -328,9 +333,10 @@ int me_batch_create(const me_job *jobs, int n, const me_params *params, uint32_t
     b->o_status = b->o_acc + align_up((size_t)n * 16, 256);
     const size_t total = b->o_status + 256;
     const size_t table = sizeof(JobDesc) * (size_t)n;
-    b->cfg[0] = std::min(m.nlines, pa_worker_cap());
+    b->cfg[4] = m.nlines <= pa_worker_cap() / 2 ? 2 : 1;
+    b->cfg[0] = std::min(m.nlines, pa_worker_cap() / b->cfg[4]);
     b->cfg[1] = 1;
-    b->cfg[2] = 2;
+    b->cfg[2] = b->cfg[4] == 2 ? 1 : 2;
     b->cfg[3] = 8;
     if (hipMalloc(&b->dev, total) != hipSuccess) {
         b->dev = nullptr;
@@ -447,7 +453,7 @@ int me_batch_set_net(me_batch *b, me_net *net) {
 
 int me_batch_config(const me_batch *b, int32_t *cfg, int ncfg) {
     if (!b || !cfg || ncfg < 4) return ME_EINVAL;
-    for (int i = 0; i < 4; ++i) cfg[i] = b->cfg[i];
+    for (int i = 0; i < std::min(ncfg, 5); ++i) cfg[i] = b->cfg[i];
     return ME_OK;
 }
 

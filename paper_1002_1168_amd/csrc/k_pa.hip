@@ -89,10 +89,11 @@ __device__ __forceinline__ void wait_vm_at_most() {
     if constexpr (N == 33) asm volatile("s_waitcnt vmcnt(33) lgkmcnt(0)" ::: "memory");
 }
 
-// Progress word of a line: pairs done (bits 0-15) and the full-pel vectors
-// of the last three pairs done (bits 16-31 latest, 32-47, 48-63), each as two
-// signed bytes (|d| <= 64).  Published once every memory access of this wave
-// older than its N most recent vector-memory operations has completed.
+// Progress word of a line: pairs done in bits 48-63 (so a larger word is a
+// later one) and the full-pel vectors of the last three pairs done in bits
+// 0-15 (latest), 16-31 and 32-47, each as two signed bytes (|d| <= 64).
+// Published once every memory access of this wave older than its N most
+// recent vector-memory operations has completed.
 template <int N = 0>
 __device__ __forceinline__ void publish(unsigned long long *p, unsigned long long word) {
     wait_vm_at_most<N>();
@@ -104,17 +105,19 @@ __device__ __forceinline__ int mvx_full(uint32_t w) { return ((int)(int16_t)(w &
 __device__ __forceinline__ int mvy_full(uint32_t w) { return ((int)(int16_t)(w >> 16)) >> 1; }
 __device__ __forceinline__ uint32_t enc8(int dx, int dy) { return (uint32_t)(uint8_t)dx | ((uint32_t)(uint8_t)dy << 8); }
 __device__ __forceinline__ unsigned long long progress_word(uint32_t done, uint32_t h0, uint32_t h1, uint32_t h2) {
-    return (unsigned long long)done | ((unsigned long long)h0 << 16) | ((unsigned long long)h1 << 32) |
-           ((unsigned long long)h2 << 48);
+    return ((unsigned long long)done << 48) | (unsigned long long)h0 | ((unsigned long long)h1 << 16) |
+           ((unsigned long long)h2 << 32);
 }
+__device__ __forceinline__ uint32_t count_of(unsigned long long w) { return (uint32_t)(w >> 48); }
+__device__ __forceinline__ uint32_t hist_of(unsigned long long w, uint32_t k) { return (uint32_t)(w >> (16 * k)) & 0xFFFFu; }
 
 // Vector (half-pel pair) of pair `need-1` of a line whose progress word is
 // `w`: carried by the word when the line is at most three pairs past it,
 // else read from that pair's array.
 __device__ __forceinline__ uint32_t mv_of(unsigned long long w, uint32_t need, const uint32_t *arr) {
-    const uint32_t age = ((uint32_t)w & 0xFFFFu) - need;
+    const uint32_t age = count_of(w) - need;
     if (age < 3) {
-        const uint32_t e = (uint32_t)(w >> (16 + 16 * age)) & 0xFFFFu;
+        const uint32_t e = hist_of(w, age);
         return pack_mv(2 * (int)(int8_t)(e & 0xFF), 2 * (int)(int8_t)(e >> 8));
     }
     return (uint32_t)uni((int)ld_relaxed(arr));
@@ -555,7 +558,7 @@ __global__ __launch_bounds__(256) void pa_line_flags(const ChainDesc *chains, co
             const uint32_t full = bits >= 32 ? 0xFFFFFFFFu : ((1u << bits) - 1u);
             all = (m[w] & full) == full;
         }
-        if (all) progress[line] = (unsigned long long)(uint32_t)ch.len;
+        if (all) progress[line] = (unsigned long long)(uint32_t)ch.len << 48;
         keep = !all;
     }
     const unsigned long long bal = __ballot(keep);
@@ -748,7 +751,7 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
                 bool ok = true;
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    if (use[i]) ok = ok && ((uint32_t)uni((int)(uint32_t)val[i]) & 0xFFFFu) >= nd[i];
+                    if (use[i]) ok = ok && (uint32_t)uni((int)(uint32_t)(val[i] >> 48)) >= nd[i];
                 if (ok) break;
                 if ((spins & 31) == 31 && (uni((int)ld_relaxed(a.status)) & ST_ABORT)) return;
                 if (++spins > kp.spin_limit) {
@@ -850,6 +853,387 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
     }
 }
 
+
+// ----------------------------------------------------- two waves per line
+// Shifted history: the three vectors of pairs c-1+g, c-2+g, c-3+g given the
+// word of count c (the g pairs in between are transparent: zero vectors).
+__device__ __forceinline__ void shift_hist(unsigned long long w, uint32_t g, uint32_t (&h)[3]) {
+#pragma unroll
+    for (uint32_t k = 0; k < 3; ++k) h[k] = k >= g ? hist_of(w, k - g) : 0u;
+}
+
+__device__ __forceinline__ void publish_max(unsigned long long *p, unsigned long long word) {
+    typedef __attribute__((address_space(1))) unsigned long long g_u64;
+    __hip_atomic_fetch_max((g_u64 *)p, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The recursion of Section 3.2 from (dx, dy) at distortion dc (nothing when k_max = 0).
+__device__ __forceinline__ int recurse_from(const Ctx &c, const KParams &kp, int &dx, int &dy, int &dc) {
+    if (kp.k_max <= 0) return 0;
+    return pel_recursion(c, kp, dx, dy, dc, sweep(c, dx, dy));
+}
+
+// Two waves per line.  The i-th searched pair of the line (in pair order)
+// belongs to wave i & 1.  Everything of a pair that does not need its T
+// candidate (the previous pair's vector, which the other wave produces) is
+// done first: polls, window staging, the costs of A, B, C, the recursion from
+// their first minimum (and from the learned seed).  T then arrives through
+// LDS; its cost decides whether that speculative result stands (T is last in
+// the list, so it wins only with a strictly lower cost) or the recursion is
+// redone from T.  The vector is handed to the other wave at once; the
+// progress word is published with a 64-bit atomic max (count in the top
+// bits, so publishes from the two waves can land in any order), and the
+// half-sample refinement and the result stores follow.
+template <int EM>
+__global__ __launch_bounds__(128) void pa2_kernel(PaArgs a) {
+    extern __shared__ uint32_t lds[];
+    __shared__ int slot;
+    __shared__ unsigned long long hword;  // progress word after the latest handed-off pair
+    __shared__ int hseq;                  // its index among the line's searched pairs (-1: none)
+    __shared__ int sdone[2];              // per wave: latest own pair whose result stores completed
+    __shared__ int ab;                    // a wave left the line on an abort
+    __shared__ int stop;                  // the status word asked every worker to leave
+    short *R = (short *)lds;              // 511 reciprocal entries (Eq. 4-5, Q.12)
+    const int wv = threadIdx.x >> 6;
+    const int wwords = ((a.rows * a.pitch + 16) >> 2) + 4;
+    uint32_t *const win = lds + 256 + wv * wwords;  // this wave's staged reference window
+    const KParams kp = a.kp;
+    for (int g = threadIdx.x; g < 511; g += 128) {
+        const int m = abs(g - 255);
+        const int r = (m == 0 || m < 2 * kp.theta) ? 0 : (16384 + m) / (2 * m);
+        R[g] = (short)(g < 255 ? -r : r);
+    }
+    volatile int *const vhseq = &hseq;
+    volatile unsigned long long *const vhword = &hword;
+    volatile int *const vsdone = sdone;
+    const int l = lane(), j = l >> 2, q = l & 3;
+    const int S = kp.S;
+    const int nact = (int)uni((int)ldg32(a.nactive));
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            slot = (int)atomicAdd(a.counter, 1u);
+            hseq = -1;
+            hword = 0ull;
+            sdone[0] = sdone[1] = -1;
+            ab = 0;
+            stop = (int)(ld_relaxed(a.status) & ST_ABORT);
+        }
+        __syncthreads();
+        const int t = uni(slot);
+        if (t >= nact || uni(stop)) break;  // LDS values: the same decision in both waves
+        const uint32_t tk = a.tickets[t];
+        const int ci = (int)(tk >> 16), v = (int)((tk >> 8) & 0xFF), h = (int)(tk & 0xFF);
+        const ChainDesc ch = a.chains[ci];
+        const int wm = ch.wm;
+        const int k = v * wm + h;
+        const JobDesc *jobs = a.jobs + ch.first;
+        const int line = ch.line_base + k;
+        unsigned long long *const own = a.progress + line;
+        const int x0 = 16 * h, y0 = 16 * v;
+        const int W = 16 * ch.wm, H = 16 * ch.hm;
+        const bool inA = h > 0, inB = v > 0, inC = v > 0 && h + 1 < wm;
+        const uint32_t *mo = a.tmask + (size_t)line * a.mw;
+        const uint32_t *mbd = a.bmask + (size_t)line * a.mw;
+        const uint32_t *ma = a.tmask + (size_t)(inA ? line - 1 : line) * a.mw;
+        const uint32_t *mb = a.tmask + (size_t)(inB ? line - wm : line) * a.mw;
+        const uint32_t *mc = a.tmask + (size_t)(inC ? line - wm + 1 : line) * a.mw;
+        Plan<(EM > 0 ? EM : 1)> plan;
+        if (EM > 0) plan.init(a.pitch, a.rows, x0, y0, S, W, H);
+        uint32_t wT = 0, wB = 0, wA = 0, wBn = 0, wC = 0;
+        int wi = -1;
+        int i = 0;        // searched pairs seen so far on this line
+        int myprev = -1;  // index of this wave's latest pair (its stores may be in flight)
+        bool aborted = false;
+        int p = 0;
+        while (p < ch.len) {
+            if ((p >> 5) != wi) {
+                wi = p >> 5;
+                wT = (uint32_t)uni((int)ldg32(mo + wi));
+                wB = (uint32_t)uni((int)ldg32(mbd + wi));
+                wA = (uint32_t)uni((int)ldg32(ma + wi));
+                wBn = (uint32_t)uni((int)ldg32(mb + wi));
+                wC = (uint32_t)uni((int)ldg32(mc + wi));
+            }
+            const int b = p & 31;
+            if ((wT >> b) & 1u) {
+                const uint32_t ones = ~(wT >> b);
+                int r = ones ? __builtin_ctz(ones) : 32 - b;
+                p += min(r, min(32 - b, ch.len - p));
+                continue;
+            }
+            if ((i & 1) != wv) {  // the other wave's pair
+                ++i;
+                ++p;
+                continue;
+            }
+            // ---- this wave's pair p (the i-th searched one): work without T
+            const DescReg D{load_desc(jobs + p)};
+            const uint32_t need = (uint32_t)(p + 1);
+            const int dep_line = D.i32(DW(dep_line_base));
+            const bool t_local = D.i32(DW(t_local)) != 0;
+            const bool hasT = dep_line >= 0 && !t_local;
+            const bool use[4] = {inA && !((wA >> b) & 1u), inB && !((wBn >> b) & 1u), inC && !((wC >> b) & 1u),
+                                 hasT};
+            const unsigned long long *const w[4] = {use[0] ? own - 1 : own, use[1] ? own - wm : own,
+                                                    use[2] ? own - wm + 1 : own,
+                                                    hasT ? a.progress + dep_line + k : own};
+            const uint32_t nd[4] = {need, need, need, (uint32_t)(D.i32(DW(dep_pos)) + 1)};
+            unsigned long long val[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) val[u] = ld64(w[u]);
+            Ctx c;
+            c.shape = ((wB >> b) & 1u) != 0;
+            const uint8_t *Pc = c.shape ? D.ptr<const uint8_t>(DW(cur_a)) : D.ptr<const uint8_t>(DW(cur));
+            const uint8_t *Pr = c.shape ? D.ptr<const uint8_t>(DW(ref_a)) : D.ptr<const uint8_t>(DW(ref));
+            const int st = D.i32(DW(stride));
+            c.win = win;
+            c.R = R;
+            c.pitch = a.pitch;
+            c.S = S;
+            c.off0 = (j + S + 1) * a.pitch + 4 * q + S + 1;
+            c.x0 = x0;
+            c.y0 = y0;
+            c.W = W;
+            c.H = H;
+            c.lox = max(-S, -x0);
+            c.hix = min(S, W - 16 - x0);
+            c.loy = max(-S, -y0);
+            c.hiy = min(S, H - 16 - y0);
+            const uint32_t cur4 = ldg32((const uint32_t *)(Pc + (size_t)(y0 + j) * st + x0 + 4 * q));
+            if constexpr (EM > 0) {
+                uint32_t wv4[EM];
+                plan.issue(Pr, st, wv4);
+                plan.write(win, wv4, c.shape);
+            } else {
+                stage_window(win, a.pitch, a.rows, Pr, st, W, H, x0, y0, S, c.shape);
+            }
+            // the window loads have returned, so this wave's earlier result
+            // stores (issued before them) have completed
+            if (l == 0) vsdone[wv] = myprev;
+            c.c4 = c.shape ? bin4(cur4) : cur4;
+            int spins = 0;
+            for (;;) {
+                bool ok = true;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (use[u]) ok = ok && (uint32_t)uni((int)(uint32_t)(val[u] >> 48)) >= nd[u];
+                if (ok) break;
+                if ((spins & 31) == 31 && (uni((int)ld_relaxed(a.status)) & ST_ABORT)) {
+                    aborted = true;
+                    break;
+                }
+                if (++spins > kp.spin_limit) {
+                    if (l == 0) atomicOr(a.status, ST_SPIN_TIMEOUT | ST_ABORT);
+                    aborted = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) val[u] = ld64(w[u]);
+            }
+            if (aborted) break;
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t lo = (uint32_t)uni((int)(uint32_t)val[u]);
+                const uint32_t hi = (uint32_t)uni((int)(uint32_t)(val[u] >> 32));
+                val[u] = ((unsigned long long)hi << 32) | lo;
+            }
+            const uint32_t *mvi = D.ptr<const uint32_t>(DW(mv_int));
+            const uint32_t *tf = D.ptr<const uint32_t>(DW(tf));
+            uint32_t m[3] = {0u, 0u, 0u};
+            if (use[0]) m[0] = mv_of(val[0], need, mvi + k - 1);
+            if (use[1]) m[1] = mv_of(val[1], need, mvi + k - wm);
+            if (use[2]) m[2] = mv_of(val[2], need, mvi + k - wm + 1);
+            // T when it does not come from the other wave
+            uint32_t tm = 0u;
+            if (hasT) tm = mv_of(val[3], nd[3], tf + k);
+            else if (tf && !(t_local && p > 0)) tm = (uint32_t)uni((int)ldg32(tf + k));
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // window visible to the whole wave
+            // A, B, C: admissible distinct entries, first minimum
+            int cx[3], cy[3];
+            bool keep[3];
+            int nabc = 0;
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                cx[u] = mvx_full(m[u]);
+                cy[u] = mvy_full(m[u]);
+                bool ok = cx[u] >= c.lox && cx[u] <= c.hix && cy[u] >= c.loy && cy[u] <= c.hiy;
+#pragma unroll
+                for (int pq = 0; pq < u; ++pq) ok = ok && !(keep[pq] && cx[pq] == cx[u] && cy[pq] == cy[u]);
+                keep[u] = ok;
+                nabc += ok;
+            }
+            uint32_t blk[3];
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+                blk[u] = lds4(c.win, c.off0 + iclamp(cy[u], -S, S) * c.pitch + iclamp(cx[u], -S, S));
+            const int p01 = wave_sum((int)__builtin_amdgcn_sad_u8(c.c4, blk[0], 0u) |
+                                     ((int)__builtin_amdgcn_sad_u8(c.c4, blk[1], 0u) << 16));
+            const int p2 = wave_sum((int)__builtin_amdgcn_sad_u8(c.c4, blk[2], 0u));
+            const int craw[3] = {p01 & 0xFFFF, (int)((uint32_t)p01 >> 16), p2};
+            int bx = 0, by = 0, bc = 0x7FFFFFFF;
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const int cu = cost_of(c, craw[u]);
+                if (keep[u] && cu < bc) {
+                    bc = cu;
+                    bx = cx[u];
+                    by = cy[u];
+                }
+            }
+            // speculative recursion from the A/B/C winner, and the learned start
+            int sdx = bx, sdy = by, sdc = bc, sits = 0;
+            if (nabc > 0) sits = recurse_from(c, kp, sdx, sdy, sdc);
+            const uint32_t *seed = D.ptr<const uint32_t>(DW(seed));
+            const bool seeded = seed && !c.shape;
+            int lx = 0, ly = 0, lc = 0, lits = 0;
+            if (seeded) {
+                const uint32_t sw0 = (uint32_t)uni((int)ldg32(seed + k));
+                lx = iclamp(mvx_full(sw0), c.lox, c.hix);
+                ly = iclamp(mvy_full(sw0), c.loy, c.hiy);
+                const Sweep sws = sweep(c, lx, ly);
+                lc = cost_of(c, sws.sad);
+                lits = pel_recursion(c, kp, lx, ly, lc, sws);
+            }
+            // ---- T: from the other wave's hand-off (or known already)
+            for (int sp = 0; uni(*vhseq) != i - 1; ++sp) {
+                if (sp > kp.spin_limit) {
+                    if (l == 0) atomicOr(a.status, ST_SPIN_TIMEOUT | ST_ABORT);
+                    aborted = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (aborted) break;
+            asm volatile("" ::: "memory");
+            const unsigned long long hw = *vhword;
+            const unsigned long long prevw = (unsigned long long)(uint32_t)uni((int)(uint32_t)hw) |
+                                             ((unsigned long long)(uint32_t)uni((int)(uint32_t)(hw >> 32)) << 32);
+            const uint32_t gap = need - 1 - count_of(prevw);  // transparent pairs since the previous searched one
+            uint32_t hs[3];
+            shift_hist(prevw, gap, hs);  // vectors of pairs p-1, p-2, p-3
+            int tx = 0, ty = 0;
+            if (t_local && p > 0) {
+                tx = (int)(int8_t)(hs[0] & 0xFF);
+                ty = (int)(int8_t)(hs[0] >> 8);
+            } else {
+                tx = mvx_full(tm);
+                ty = mvy_full(tm);
+            }
+            bool keepT = tx >= c.lox && tx <= c.hix && ty >= c.loy && ty <= c.hiy;
+#pragma unroll
+            for (int u = 0; u < 3; ++u) keepT = keepT && !(keep[u] && cx[u] == tx && cy[u] == ty);
+            int n = nabc + (keepT ? 1 : 0);
+            int dx, dy, dc, its;
+            int wx = bx, wy = by, wc = bc;  // BRS winner
+            bool from_spec = nabc > 0;
+            if (keepT) {
+                const int ct = cost_of(c, wave_sum((int)__builtin_amdgcn_sad_u8(
+                                              c.c4, lds4(c.win, c.off0 + ty * c.pitch + tx), 0u)));
+                if (ct < wc) {
+                    wx = tx;
+                    wy = ty;
+                    wc = ct;
+                    from_spec = false;
+                }
+            }
+            if (n == 0) {  // nothing admissible: (0, 0)
+                n = 1;
+                wx = wy = 0;
+                wc = cost_of(c, wave_sum((int)__builtin_amdgcn_sad_u8(c.c4, lds4(c.win, c.off0), 0u)));
+                from_spec = false;
+            }
+            int pts = n;
+            if (seeded) {
+                pts += 1 + lits;
+                its = lits;
+                if (20ll * lc > 21ll * wc) {
+                    dx = wx;
+                    dy = wy;
+                    dc = wc;
+                    int it2;
+                    if (from_spec) {
+                        dx = sdx;
+                        dy = sdy;
+                        dc = sdc;
+                        it2 = sits;
+                    } else {
+                        it2 = recurse_from(c, kp, dx, dy, dc);
+                    }
+                    its += it2;
+                    pts += it2;
+                } else {
+                    dx = lx;
+                    dy = ly;
+                    dc = lc;
+                }
+            } else if (from_spec) {
+                dx = sdx;
+                dy = sdy;
+                dc = sdc;
+                its = sits;
+                pts += its;
+            } else {
+                dx = wx;
+                dy = wy;
+                dc = wc;
+                its = recurse_from(c, kp, dx, dy, dc);
+                pts += its;
+            }
+            const unsigned long long word = progress_word(need, enc8(dx, dy), hs[0], hs[1]);
+            // count `need` promises the stores of pairs <= need - 4; only the
+            // other wave's previous pair can be one still in flight
+            if (gap >= 2 && i > 0) {
+                for (int sp = 0; uni(vsdone[wv ^ 1]) < i - 1; ++sp) {
+                    if (sp > kp.spin_limit) {
+                        if (l == 0) atomicOr(a.status, ST_SPIN_TIMEOUT | ST_ABORT);
+                        aborted = true;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                if (aborted) break;
+            }
+            if (l == 0) {
+                publish_max(own, word);
+                *vhword = word;
+                asm volatile("" ::: "memory");
+                *vhseq = i;
+            }
+            // ---- after the hand-off: half-sample refinement, results
+            int hx = 2 * dx, hy = 2 * dy;
+            if (kp.half_pel && !c.shape) pts += half_refine(c, kp, dx, dy, hx, hy, dc);
+            if (l == 0) {
+                const DescReg &Dr = D;
+                store_result(Dr, k, pack_mv(hx, hy), pack_mv(2 * dx, 2 * dy), (uint32_t)dc, its, pts);
+            }
+            myprev = i;
+            ++i;
+            ++p;
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        if (l == 0) {
+            vsdone[wv] = myprev;
+            if (aborted) *(volatile int *)&ab = 1;
+        }
+        __syncthreads();
+        const bool any_abort = uni(*(volatile int *)&ab) != 0;
+        if (threadIdx.x == 0 && !any_abort) {
+            // trailing transparent pairs: the line's final count
+            const unsigned long long wlast = hword;
+            const uint32_t cnt = count_of(wlast);
+            if (cnt < (uint32_t)ch.len) {
+                uint32_t hs[3];
+                shift_hist(wlast, (uint32_t)ch.len - cnt, hs);
+                publish_max(own, progress_word((uint32_t)ch.len, hs[0], hs[1], hs[2]));
+            }
+        }
+        if (any_abort) break;  // the same decision in both waves
+    }
+}
+
 }  // namespace
 
 // elements per lane of the staging plan for range S (0: generic loop)
@@ -883,10 +1267,15 @@ size_t pa_scratch_bytes(int nlines) {
     return 256 + nb * 4 * 8 + 256 + nb * 4 + 256 + (size_t)nlines * 4 + 256;
 }
 
+size_t pa2_lds_bytes(int S) {
+    const int rows = 2 * S + 18, pitch = (rows + 3) & ~3;
+    return 1024 + 2 * ((size_t)(((rows * pitch + 16) >> 2) + 4) * 4);
+}
+
 hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainDesc *chains, const uint32_t *tickets,
                      int nlines, unsigned long long *progress, uint32_t *counter, uint32_t *masks, int mask_words,
                      uint8_t *scratch, uint32_t *status, const KParams &kp, int workers, hipStream_t s,
-                     const KernelTimer *t, bool generic) {
+                     const KernelTimer *t, bool generic, int waves) {
     if (total_mbs <= 0 || nlines <= 0) return hipSuccess;
     uint32_t *tmask = masks, *bmask = masks + (size_t)nlines * mask_words;
     hipLaunchKernelGGL(pa_prepass, dim3((total_mbs + 255) / 256), dim3(256), 0, s, jobs, njobs, total_mbs, tmask,
@@ -908,8 +1297,20 @@ hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainD
     const int rows = 2 * kp.S + 18;
     PaArgs a{jobs, chains, active, nactive, progress, counter, tmask, bmask, mask_words, status, kp,
              (rows + 3) & ~3, rows};
-    const size_t lds = pa_lds_bytes(kp.S, generic);
     timer_mark(t, true, s);
+    if (waves == 2) {
+        const size_t lds2 = pa2_lds_bytes(kp.S);
+        switch (generic ? 0 : plan_elems(kp.S)) {
+            case 4: hipLaunchKernelGGL(pa2_kernel<4>, dim3(workers), dim3(128), lds2, s, a); break;
+            case 12: hipLaunchKernelGGL(pa2_kernel<12>, dim3(workers), dim3(128), lds2, s, a); break;
+            case 28: hipLaunchKernelGGL(pa2_kernel<28>, dim3(workers), dim3(128), lds2, s, a); break;
+            default: hipLaunchKernelGGL(pa2_kernel<0>, dim3(workers), dim3(128), lds2, s, a); break;
+        }
+        e = hipGetLastError();
+        timer_mark(t, false, s);
+        return e;
+    }
+    const size_t lds = pa_lds_bytes(kp.S, generic);
     switch (generic ? 0 : plan_elems(kp.S)) {
         case 4: hipLaunchKernelGGL(pa_kernel<4>, dim3(workers), dim3(64), lds, s, a); break;
         case 12: hipLaunchKernelGGL(pa_kernel<12>, dim3(workers), dim3(64), lds, s, a); break;

@@ -68,7 +68,7 @@ int flat_chunk(int total_mbs, int per_cu);
 hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainDesc *chains, const uint32_t *tickets,
                      int nlines, unsigned long long *progress, uint32_t *counter, uint32_t *masks, int mask_words,
                      uint8_t *scratch, uint32_t *status, const KParams &kp, int workers, hipStream_t s,
-                     const KernelTimer *t = nullptr, bool generic = false);
+                     const KernelTimer *t = nullptr, bool generic = false, int waves = 1);
 // bytes of the `scratch` argument of launch_pa (256-aligned base; no zeroing needed)
 size_t pa_scratch_bytes(int nlines);
 // LDS bytes of one search worker; `generic`: single-buffered generic staging

@@ -312,3 +312,29 @@ def test_pa_seeded_start_parity(torch_cuda, maker, S):
     torch.cuda.synchronize()
     assert me.me_device_status(stream_handle()) == me.ME_OK
     assert_same(out.host(), want, f"seeded {maker}")
+
+
+def test_pa_many_lines_one_wave_per_line(torch_cuda):
+    """More lines than half the worker budget: the one-wave-per-line worker
+    (the two-wave worker runs every smaller case), against the oracle."""
+    import torch
+    from paper_1002_1168_amd import device as dv
+    streams = synth.mixed_streams(seed=33, frames=3, counts=(0, 0, 3))
+    p = me.me_default_params(search_range=16)
+    jobs, keep, alive, lines = [], [], [], 0
+    for s in streams:
+        ds = dseq(s)
+        alive.append(ds)  # the jobs point into these device frames
+        gpu_classify(ds)
+        for v in range(s.vops):
+            out = dv.Outputs.alloc(2, ds.hm, ds.wm)
+            jobs += ds.pair_jobs(v, out, 2)
+            keep.append((s, v, out))
+            lines += ds.hm * ds.wm
+    say("lines", lines)
+    assert lines > 256 * 16 // 2
+    me.me_texture_recursive(jobs, p, None, stream=dv.stream_handle())
+    torch.cuda.synchronize()
+    assert me.me_device_status(dv.stream_handle()) == me.ME_OK
+    for s, v, out in keep:
+        assert_same(out.host(), oracle_pa(s, v, p, 2), f"{s.name} vop {v}")
