@@ -111,16 +111,28 @@ __device__ __forceinline__ unsigned long long progress_word(uint32_t done, uint3
 __device__ __forceinline__ uint32_t count_of(unsigned long long w) { return (uint32_t)(w >> 48); }
 __device__ __forceinline__ uint32_t hist_of(unsigned long long w, uint32_t k) { return (uint32_t)(w >> (16 * k)) & 0xFFFFu; }
 
-// Vector (half-pel pair) of pair `need-1` of a line whose progress word is
+// Vectors (half-pel pairs) of pair `need-1` of lines whose progress words are
 // `w`: carried by the word when the line is at most three pairs past it,
 // else read from that pair's array.
-__device__ __forceinline__ uint32_t mv_of(unsigned long long w, uint32_t need, const uint32_t *arr) {
-    const uint32_t age = count_of(w) - need;
-    if (age < 3) {
-        const uint32_t e = hist_of(w, age);
-        return pack_mv(2 * (int)(int8_t)(e & 0xFF), 2 * (int)(int8_t)(e >> 8));
+// For the four slots u with use[u] (others give 0); the array reads are all
+// issued before any is used, so they cost one memory round trip together.
+__device__ __forceinline__ void vectors_of(const unsigned long long (&w)[4], const uint32_t (&need)[4],
+                                           const bool (&use)[4], const uint32_t *const (&arr)[4], uint32_t (&m)[4]) {
+    bool far[4];
+    uint32_t raw[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        far[u] = use[u] && count_of(w[u]) - need[u] >= 3u;
+        raw[u] = 0u;
+        if (far[u]) raw[u] = ld_relaxed(arr[u]);
     }
-    return (uint32_t)uni((int)ld_relaxed(arr));
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const uint32_t age = count_of(w[u]) - need[u];
+        const uint32_t e = hist_of(w[u], age < 3u ? age : 0u);
+        const uint32_t near = pack_mv(2 * (int)(int8_t)(e & 0xFF), 2 * (int)(int8_t)(e >> 8));
+        m[u] = !use[u] ? 0u : far[u] ? (uint32_t)uni((int)raw[u]) : near;
+    }
 }
 
 // ---------------------------------------------------------------- window
@@ -782,12 +794,10 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
             }
             const uint32_t *mvi = D.ptr<const uint32_t>(DW(mv_int));
             const uint32_t *tf = D.ptr<const uint32_t>(DW(tf));
-            uint32_t m[4] = {0u, 0u, 0u, 0u};
-            if (use[0]) m[0] = mv_of(val[0], need, mvi + k - 1);
-            if (use[1]) m[1] = mv_of(val[1], need, mvi + k - wm);
-            if (use[2]) m[2] = mv_of(val[2], need, mvi + k - wm + 1);
-            if (hasT) m[3] = mv_of(val[3], nd[3], tf + k);
-            else if (tf && !(t_local && p > 0)) m[3] = (uint32_t)uni((int)ldg32(tf + k));
+            uint32_t m[4];
+            const uint32_t *const arr[4] = {mvi + k - 1, mvi + k - wm, mvi + k - wm + 1, tf + k};
+            vectors_of(val, nd, use, arr, m);
+            if (!hasT && tf && !(t_local && p > 0)) m[3] = (uint32_t)uni((int)ldg32(tf + k));
             int cx[4], cy[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -862,6 +872,9 @@ __device__ __forceinline__ void shift_hist(unsigned long long w, uint32_t g, uin
     for (uint32_t k = 0; k < 3; ++k) h[k] = k >= g ? hist_of(w, k - g) : 0u;
 }
 
+typedef __attribute__((address_space(3))) volatile int l_vint;
+typedef __attribute__((address_space(3))) volatile unsigned long long l_vu64;
+
 __device__ __forceinline__ void publish_max(unsigned long long *p, unsigned long long word) {
     typedef __attribute__((address_space(1))) unsigned long long g_u64;
     __hip_atomic_fetch_max((g_u64 *)p, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -903,9 +916,13 @@ __global__ __launch_bounds__(128) void pa2_kernel(PaArgs a) {
         const int r = (m == 0 || m < 2 * kp.theta) ? 0 : (16384 + m) / (2 * m);
         R[g] = (short)(g < 255 ? -r : r);
     }
-    volatile int *const vhseq = &hseq;
-    volatile unsigned long long *const vhword = &hword;
-    volatile int *const vsdone = sdone;
+    // LDS (not generic) pointers: a volatile access through a generic pointer
+    // becomes a flat access that waits for every outstanding vector-memory
+    // operation, the progress atomic and the prefetches included
+    l_vint *const vhseq = (l_vint *)&hseq;
+    l_vu64 *const vhword = (l_vu64 *)&hword;
+    l_vint *const vsdone = (l_vint *)sdone;
+    l_vint *const vab = (l_vint *)&ab;
     const int l = lane(), j = l >> 2, q = l & 3;
     const int S = kp.S;
     const int nact = (int)uni((int)ldg32(a.nactive));
@@ -1042,14 +1059,12 @@ __global__ __launch_bounds__(128) void pa2_kernel(PaArgs a) {
             }
             const uint32_t *mvi = D.ptr<const uint32_t>(DW(mv_int));
             const uint32_t *tf = D.ptr<const uint32_t>(DW(tf));
-            uint32_t m[3] = {0u, 0u, 0u};
-            if (use[0]) m[0] = mv_of(val[0], need, mvi + k - 1);
-            if (use[1]) m[1] = mv_of(val[1], need, mvi + k - wm);
-            if (use[2]) m[2] = mv_of(val[2], need, mvi + k - wm + 1);
+            uint32_t m[4];
+            const uint32_t *const arr[4] = {mvi + k - 1, mvi + k - wm, mvi + k - wm + 1, tf + k};
+            vectors_of(val, nd, use, arr, m);
             // T when it does not come from the other wave
-            uint32_t tm = 0u;
-            if (hasT) tm = mv_of(val[3], nd[3], tf + k);
-            else if (tf && !(t_local && p > 0)) tm = (uint32_t)uni((int)ldg32(tf + k));
+            uint32_t tm = m[3];
+            if (!hasT && tf && !(t_local && p > 0)) tm = (uint32_t)uni((int)ldg32(tf + k));
             asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // window visible to the whole wave
             // A, B, C: admissible distinct entries, first minimum
             int cx[3], cy[3];
@@ -1216,10 +1231,10 @@ __global__ __launch_bounds__(128) void pa2_kernel(PaArgs a) {
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         if (l == 0) {
             vsdone[wv] = myprev;
-            if (aborted) *(volatile int *)&ab = 1;
+            if (aborted) *vab = 1;
         }
         __syncthreads();
-        const bool any_abort = uni(*(volatile int *)&ab) != 0;
+        const bool any_abort = uni(*vab) != 0;
         if (threadIdx.x == 0 && !any_abort) {
             // trailing transparent pairs: the line's final count
             const unsigned long long wlast = hword;
