@@ -398,10 +398,10 @@ def main():
         "searched_mb_per_s": nsearch * a.steps / dt,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS, "unit": "Tops/s",
                      "frac": achieved / PEAK_INT_TOPS,
-                     "traffic": measured_traffic("pa_kernel", ("paper_1002_1168_amd/csrc/k_pa.hip",
-                                                               "paper_1002_1168_amd/csrc/me_internal.h"),
-                                                 "profiles/pa_kernel_traffic_cif352x288_2vop_300f_S16.md"),
-                     "kernel": "pa_kernel", "kernel_ms": kern_ms},
+                     "traffic": measured_traffic("pa2_kernel", ("paper_1002_1168_amd/csrc/k_pa.hip",
+                                                                "paper_1002_1168_amd/csrc/me_internal.h"),
+                                                 "profiles/pa2_kernel_traffic_cif352x288_2vop_300f_S16.md"),
+                     "kernel": "pa2_kernel", "kernel_ms": kern_ms},
         "cpu_baseline": cpu,
         "baselines": baselines,
         "learned": learned,

@@ -1029,25 +1029,64 @@ __global__ __launch_bounds__(128) void pa2_kernel(PaArgs a) {
             // stores (issued before them) have completed
             if (l == 0) vsdone[wv] = myprev;
             c.c4 = c.shape ? bin4(cur4) : cur4;
+            // polls: the first slot still short of its count is read with three
+            // loads in flight (a new one every few hundred cycles), so a
+            // publish is seen about a third of a memory round trip after it
+            // lands rather than up to a whole one
             int spins = 0;
+            unsigned long long g0 = 0, g1 = 0, g2 = 0;  // the last two may still be in flight
             for (;;) {
-                bool ok = true;
+                int ms = -1;
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (use[u]) ok = ok && (uint32_t)uni((int)(uint32_t)(val[u] >> 48)) >= nd[u];
-                if (ok) break;
-                if ((spins & 31) == 31 && (uni((int)ld_relaxed(a.status)) & ST_ABORT)) {
-                    aborted = true;
-                    break;
+                for (int u = 3; u >= 0; --u)
+                    if (use[u] && (uint32_t)uni((int)(uint32_t)(val[u] >> 48)) < nd[u]) ms = u;
+                if (ms < 0) break;
+                const unsigned long long *pw = ms == 0 ? w[0] : ms == 1 ? w[1] : ms == 2 ? w[2] : w[3];
+                const uint32_t want = ms == 0 ? nd[0] : ms == 1 ? nd[1] : ms == 2 ? nd[2] : nd[3];
+                unsigned long long got = 0ull;
+                g0 = ld64(pw);
+                __builtin_amdgcn_s_sleep(3);
+                g1 = ld64(pw);
+                __builtin_amdgcn_s_sleep(3);
+                for (;;) {
+                    g2 = ld64(pw);
+                    if ((uint32_t)uni((int)(uint32_t)(g0 >> 48)) >= want) {
+                        got = g0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(3);
+                    g0 = ld64(pw);
+                    if ((uint32_t)uni((int)(uint32_t)(g1 >> 48)) >= want) {
+                        got = g1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(3);
+                    g1 = ld64(pw);
+                    if ((uint32_t)uni((int)(uint32_t)(g2 >> 48)) >= want) {
+                        got = g2;
+                        break;
+                    }
+                    spins += 3;
+                    if ((spins & 31) < 3 && (uni((int)ld_relaxed(a.status)) & ST_ABORT)) {
+                        aborted = true;
+                        break;
+                    }
+                    if (spins > kp.spin_limit) {
+                        if (l == 0) atomicOr(a.status, ST_SPIN_TIMEOUT | ST_ABORT);
+                        aborted = true;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(3);
                 }
-                if (++spins > kp.spin_limit) {
-                    if (l == 0) atomicOr(a.status, ST_SPIN_TIMEOUT | ST_ABORT);
-                    aborted = true;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-                for (int u = 0; u < 4; ++u) val[u] = ld64(w[u]);
+                if (aborted) break;
+                if (ms == 0)
+                    val[0] = got;
+                else if (ms == 1)
+                    val[1] = got;
+                else if (ms == 2)
+                    val[2] = got;
+                else
+                    val[3] = got;
             }
             if (aborted) break;
             asm volatile("" ::: "memory");
@@ -1224,6 +1263,7 @@ __global__ __launch_bounds__(128) void pa2_kernel(PaArgs a) {
                 const DescReg &Dr = D;
                 store_result(Dr, k, pack_mv(hx, hy), pack_mv(2 * dx, 2 * dy), (uint32_t)dc, its, pts);
             }
+            asm volatile("" ::"v"(g0), "v"(g1), "v"(g2));  // poll loads still in flight complete here
             myprev = i;
             ++i;
             ++p;
