@@ -74,6 +74,7 @@ struct NetLds {
     alignas(16) uint16_t a1[576 * 32];  // conv1 output
     alignas(16) uint16_t a2[144 * 32];  // conv2 output
     alignas(16) float red[4][64];       // cross-wave reductions
+    alignas(16) float bias[64];         // conv1 and conv2 biases
     float pv[2];                        // prediction of the current MB
 };
 struct NetLdsTrain : NetLds {
@@ -85,22 +86,86 @@ static_assert(sizeof(NetLds) % 16 == 0 && sizeof(NetLdsTrain) % 16 == 0, "LDS la
 
 // --------------------------------------------------------------- stages
 // Input of MB (x0, y0): 576 reference-window values and 64 current values.
-__device__ void stage_input(uint16_t *x0s, const JobDesc &J, int x0, int y0) {
-    const int W = J.width, H = J.height, st = J.stride;
-    for (int q = threadIdx.x; q < 576; q += kThreads) {
+// The pixels are loaded into registers first (`issue_input`, up to three
+// positions per thread) and summed into LDS later (`write_input`), so the
+// next MB's loads can fly while the current MB is computed.
+struct InPix {
+    uint32_t r[3][4];  // the 2x2 reference pixels of each position
+    uint32_t c[3][2];  // the current pixel pairs of the two rows (centre positions only)
+};
+
+// The fields of a job the network reads, as wave-uniform values (frame
+// pointers then address global memory directly).
+struct InJob {
+    const uint8_t *cur, *ref;
+    int W, H, st, wm, hm;
+};
+
+__device__ __forceinline__ uint32_t dword_of(const JobDesc *J, int i) {
+    return (uint32_t)uni((int)ldg32((const uint32_t *)J + i));
+}
+
+__device__ __forceinline__ InJob in_job(const JobDesc *J) {
+    const int o_cur = (int)(offsetof(JobDesc, cur) / 4), o_ref = (int)(offsetof(JobDesc, ref) / 4);
+    const int o_w = (int)(offsetof(JobDesc, width) / 4);
+    InJob j;
+    j.cur = (const uint8_t *)(uintptr_t)((unsigned long long)dword_of(J, o_cur) |
+                                         ((unsigned long long)dword_of(J, o_cur + 1) << 32));
+    j.ref = (const uint8_t *)(uintptr_t)((unsigned long long)dword_of(J, o_ref) |
+                                         ((unsigned long long)dword_of(J, o_ref + 1) << 32));
+    j.W = (int)dword_of(J, o_w);
+    j.H = (int)dword_of(J, o_w + 1);
+    j.st = (int)dword_of(J, o_w + 2);
+    j.wm = (int)dword_of(J, o_w + 3);
+    j.hm = (int)dword_of(J, o_w + 4);
+    return j;
+}
+
+__device__ __forceinline__ void issue_input(InPix &v, const InJob &J, int x0, int y0) {
+    const int W = J.W, H = J.H, st = J.st;
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+        const int q = threadIdx.x + kThreads * sl;
         const int y = q / 24, x = q - (q / 24) * 24;
         const int ya = iclamp(y0 - 16 + 2 * y, 0, H - 1), yb = iclamp(y0 - 15 + 2 * y, 0, H - 1);
         const int xa = iclamp(x0 - 16 + 2 * x, 0, W - 1), xb = iclamp(x0 - 15 + 2 * x, 0, W - 1);
-        const int s = (int)J.ref[(size_t)ya * st + xa] + (int)J.ref[(size_t)ya * st + xb] +
-                      (int)J.ref[(size_t)yb * st + xa] + (int)J.ref[(size_t)yb * st + xb];
+        const bool in = q < 576;
+        // clamped coordinates: every address is in the frame
+        v.r[sl][0] = in ? ldg8(J.ref + (size_t)ya * st + xa) : 0u;
+        v.r[sl][1] = in ? ldg8(J.ref + (size_t)ya * st + xb) : 0u;
+        v.r[sl][2] = in ? ldg8(J.ref + (size_t)yb * st + xa) : 0u;
+        v.r[sl][3] = in ? ldg8(J.ref + (size_t)yb * st + xb) : 0u;
+        v.c[sl][0] = v.c[sl][1] = 0u;
+        if (in && y >= 8 && y < 16 && x >= 8 && x < 16) {
+            const uint8_t *c = J.cur + (size_t)(y0 + 2 * (y - 8)) * st + x0 + 2 * (x - 8);
+            v.c[sl][0] = *(const __attribute__((address_space(1))) uint16_t *)c;
+            v.c[sl][1] = *(const __attribute__((address_space(1))) uint16_t *)(c + st);
+        }
+    }
+}
+
+__device__ __forceinline__ void write_input(uint16_t *x0s, const InPix &v) {
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+        const int q = threadIdx.x + kThreads * sl;
+        if (q >= 576) continue;
+        const int y = q / 24, x = q - (q / 24) * 24;
+        const int s = (int)(v.r[sl][0] + v.r[sl][1] + v.r[sl][2] + v.r[sl][3]);
         uint32_t c0 = 0;
         if (y >= 8 && y < 16 && x >= 8 && x < 16) {
-            const uint8_t *c = J.cur + (size_t)(y0 + 2 * (y - 8)) * st + x0 + 2 * (x - 8);
-            const int sc = (int)c[0] + (int)c[1] + (int)c[st] + (int)c[st + 1];
+            const int sc = (int)((v.c[sl][0] & 0xFFu) + (v.c[sl][0] >> 8) + (v.c[sl][1] & 0xFFu) + (v.c[sl][1] >> 8));
             c0 = bf16_bits((float)(sc - 512) * (1.0f / 512.0f));
         }
         x0s[2 * q] = (uint16_t)c0;
         x0s[2 * q + 1] = (uint16_t)bf16_bits((float)(s - 512) * (1.0f / 512.0f));
+    }
+    // every register consumed on every path (lanes past the input included), so
+    // no load into them is left in flight for the next MB's loads to wait on
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) asm volatile("" ::"v"(v.r[sl][t]));
+        asm volatile("" ::"v"(v.c[sl][0]), "v"(v.c[sl][1]));
     }
 }
 
@@ -141,64 +206,95 @@ __device__ __forceinline__ u16x8 conv1_b(const uint16_t *w1b, int nt, int r16, i
     return u16x8{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
 }
 
+// The weight operands and biases a wave uses, loaded once per launch.  The
+// convolutions run as out^T = W x im2col(in)^T: the weights are the MFMA A
+// operand (rows = output channels) and the input patches the B operand
+// (columns = output pixels), so a lane's four results are four consecutive
+// channels of one pixel and leave as one 8-byte LDS store.
+struct NetOps {
+    u16x8 w1[2], w2[9], w3[9];  // conv1 row tiles 0, 1; conv2 row tile wv & 1 per tap; conv3 per tap
+};
+
+__device__ __forceinline__ void load_ops(NetOps &o, const uint16_t *w1b, const uint16_t *w2b, const uint16_t *w3b,
+                                         const float *P) {
+    const int l = lane(), wv = threadIdx.x >> 6, r16 = l & 15, g = l >> 4;
+    const int n2 = (wv & 1) * 16 + r16;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) o.w1[nt] = conv1_b(w1b, nt, r16, g);
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        o.w2[tap] = ld16(w2b + (n2 * 9 + tap) * 32 + 8 * g);
+        o.w3[tap] = r16 < 2 ? ld16(w3b + (r16 * 9 + tap) * 32 + 8 * g) : zero8();
+    }
+    // consumed here, once: otherwise the first use inside the MB loop waits
+    // for every load in flight, the next MB's prefetched pixels included
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) asm volatile("" : "+v"(o.w1[nt]));
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        asm volatile("" : "+v"(o.w2[tap]));
+        asm volatile("" : "+v"(o.w3[tap]));
+    }
+}
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// bias + ReLU of four consecutive channels, rounded to bfloat16 (to nearest
+// even, as the bit-level rounding above) and stored as 8 bytes
+__device__ __forceinline__ void store4_relu(uint16_t *dst, const f32x4 &acc, const float *bias) {
+    const f32x4 b = *(const f32x4 *)bias;
+    const f32x2 lo = {relu(acc[0] + b[0]), relu(acc[1] + b[1])};
+    const f32x2 hi = {relu(acc[2] + b[2]), relu(acc[3] + b[3])};
+    const uint32_t plo = __builtin_bit_cast(uint32_t, __builtin_convertvector(lo, bf16x2));
+    const uint32_t phi = __builtin_bit_cast(uint32_t, __builtin_convertvector(hi, bf16x2));
+    *(uint2 *)dst = make_uint2(plo, phi);
+}
+
 template <class L>
-__device__ void forward_mb(L &S, const uint16_t *w1b, const uint16_t *w2b, const uint16_t *w3b, const float *P) {
+__device__ void forward_mb(L &S, const NetOps &o, const float *P) {
     NetLds &F = S;
     const int l = lane(), wv = threadIdx.x >> 6, r16 = l & 15, g = l >> 4;
-    const u16x8 b1op[2] = {conv1_b(w1b, 0, r16, g), conv1_b(w1b, 1, r16, g)};
-    // conv1: 36 row tiles x 2 column tiles
+    // conv1: 36 pixel tiles x 2 channel tiles
     for (int mt = wv; mt < 36; mt += 4) {
-        const u16x8 a = conv1_a(F.x0, mt * 16 + r16, g);
+        const u16x8 x = conv1_a(F.x0, mt * 16 + r16, g);
+        const int m = mt * 16 + r16;
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            acc = mfma(a, b1op[nt], acc);
-            const int n = nt * 16 + r16;
-            const float bias = P[kNetOB1 + n];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int m = mt * 16 + 4 * g + i;
-                F.a1[m * 32 + n] = (uint16_t)bf16_bits(relu(acc[i] + bias));
-            }
+            const f32x4 acc = mfma(o.w1[nt], x, f32x4{0.f, 0.f, 0.f, 0.f});
+            store4_relu(F.a1 + m * 32 + nt * 16 + 4 * g, acc, F.bias + nt * 16 + 4 * g);
         }
     }
     __syncthreads();
-    // conv2: 9 row tiles x 2 column tiles; wave -> column tile wv & 1
+    // conv2: 9 pixel tiles x 2 channel tiles; wave -> channel tile wv & 1
     {
-        const int nt = wv & 1, n = nt * 16 + r16;
-        const float bias = P[kNetOB2 + n];
+        const int nt = wv & 1;
         for (int mt = wv >> 1; mt < 9; mt += 2) {
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int tap = 0; tap < 9; ++tap)
-                acc = mfma(conv_s2_a(F.a1, 24, 12, mt * 16 + r16, tap, g), ld16(w2b + (n * 9 + tap) * 32 + 8 * g), acc);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int m = mt * 16 + 4 * g + i;
-                F.a2[m * 32 + n] = (uint16_t)bf16_bits(relu(acc[i] + bias));
-            }
+            for (int tap = 0; tap < 9; ++tap) acc = mfma(o.w2[tap], conv_s2_a(F.a1, 24, 12, mt * 16 + r16, tap, g), acc);
+            store4_relu(F.a2 + (mt * 16 + r16) * 32 + nt * 16 + 4 * g, acc, F.bias + 32 + nt * 16 + 4 * g);
         }
     }
     __syncthreads();
-    // conv3: 3 row tiles (36 rows used) x 1 column tile (2 used), then the mean
-    float s = 0.f;
+    // conv3: 3 pixel tiles (36 used) x 1 channel tile (2 used), then the mean
+    // over the pixels: lanes of g = 0 hold channels 0 and 1 of pixel r16
     if (wv < 3) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap)
-            acc = mfma(conv_s2_a(F.a2, 12, 6, wv * 16 + r16, tap, g),
-                       r16 < 2 ? ld16(w3b + (r16 * 9 + tap) * 32 + 8 * g) : zero8(), acc);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (wv * 16 + 4 * g + i < 36) s += acc[i];
+        for (int tap = 0; tap < 9; ++tap) acc = mfma(o.w3[tap], conv_s2_a(F.a2, 12, 6, wv * 16 + r16, tap, g), acc);
+        const bool ok = g == 0 && wv * 16 + r16 < 36;
+        if (g == 0) {
+            F.red[wv][r16] = ok ? acc[0] : 0.f;
+            F.red[wv][16 + r16] = ok ? acc[1] : 0.f;
+        }
     }
-    F.red[wv][l] = s;
     __syncthreads();
     if (threadIdx.x < 2) {
         const int c = threadIdx.x;
         float t = 0.f;
         for (int w = 0; w < 3; ++w)
-            for (int gg = 0; gg < 4; ++gg) t += F.red[w][16 * gg + c];
+            for (int r = 0; r < 16; ++r) t += F.red[w][16 * c + r];
         F.pv[c] = P[kNetOB3 + c] + t * (1.0f / 36.0f);
     }
     __syncthreads();
@@ -214,8 +310,9 @@ struct NetArgs {
     float *part;            // training: per-workgroup gradient partials (kNetParams + 1 floats each)
 };
 
+// inference: three workgroups per CU (their LDS fits), so at most 168 VGPRs
 template <bool TRAIN>
-__global__ __launch_bounds__(kThreads) void net_kernel(NetArgs a) {
+__global__ __launch_bounds__(kThreads, TRAIN ? 1 : 3) void net_kernel(NetArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds_raw[];
     using L = typename std::conditional<TRAIN, NetLdsTrain, NetLds>::type;
     L &S = *(L *)lds_raw;
@@ -233,142 +330,176 @@ __global__ __launch_bounds__(kThreads) void net_kernel(NetArgs a) {
         for (int u = 0; u < 9; ++u) gw2[u] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
     const float inv_b = count > 0 ? 1.0f / (float)count : 0.f;
+    NetOps ops;
+    load_ops(ops, w1b, w2b, w3b, a.P);
+    if (threadIdx.x < 64) F.bias[threadIdx.x] = a.P[(threadIdx.x < 32 ? kNetOB1 : kNetOB2 - 32) + threadIdx.x];
+    // MB `e` of the list: its job and index (false for an entry the list
+    // kernel never produces)
+    auto decode = [&](int e, const JobDesc *&J, int &k, InJob &ij) {
+        const uint32_t ent = (uint32_t)uni((int)ldg32(a.list + e));
+        if ((int)(ent >> 16) >= a.njobs) return false;
+        J = a.jobs + (ent >> 16);
+        k = (int)(ent & 0xFFFF);
+        ij = in_job(J);
+        return ij.wm > 0 && k < ij.wm * ij.hm;
+    };
+    // this workgroup's MBs e = blockIdx.x + j * gridDim.x; the pixels of the
+    // next one are loaded while the current one is computed
+    InPix pix;
+    const JobDesc *Jc = nullptr;
+    int kc = 0;
+    InJob ic{};
+    bool vc = (int)blockIdx.x < count && decode(blockIdx.x, Jc, kc, ic);
+    if (vc) {
+        issue_input(pix, ic, 16 * (kc % ic.wm), 16 * (kc / ic.wm));
+        write_input(F.x0, pix);
+    }
     for (int e = blockIdx.x; e < count; e += gridDim.x) {
-        const uint32_t ent = a.list[e];
-        if ((int)(ent >> 16) >= a.njobs) continue;  // (uniform) never produced by the list kernel
-        const JobDesc &J = a.jobs[ent >> 16];
-        const int k = (int)(ent & 0xFFFF);
-        if (J.wm <= 0 || k >= J.wm * J.hm) continue;
-        const int h = k % J.wm, v = k / J.wm;
-        stage_input(F.x0, J, 16 * h, 16 * v);
-        __syncthreads();
-        forward_mb(S, w1b, w2b, w3b, a.P);
-        const float p0 = F.pv[0], p1 = F.pv[1];
-        if constexpr (!TRAIN) {
-            if (threadIdx.x == 0) {
-                if (J.seed) {
-                    const int sx = 2 * iclamp((int)rintf(p0), -16, 16), sy = 2 * iclamp((int)rintf(p1), -16, 16);
-                    ((uint32_t *)J.seed)[k] = (uint32_t)(uint16_t)sx | ((uint32_t)(uint16_t)sy << 16);
-                }
-                if (J.out_u32) {
-                    ((float *)J.out_u32)[2 * k] = p0;
-                    ((float *)J.out_u32)[2 * k + 1] = p1;
-                }
-            }
-        } else {
-            NetLdsTrain &T = S;
-            const uint32_t lab = ((const uint32_t *)J.tf)[k];
-            const float y0 = (float)(((int)(int16_t)(lab & 0xFFFF)) >> 1);
-            const float y1 = (float)(((int)(int16_t)(lab >> 16)) >> 1);
-            const float dp0 = (p0 - y0) * inv_b, dp1 = (p1 - y1) * inv_b;
-            if (threadIdx.x == 0) {
-                loss += 0.5f * ((p0 - y0) * (p0 - y0) + (p1 - y1) * (p1 - y1)) * inv_b;
-                gb3[0] += dp0;
-                gb3[1] += dp1;
-            }
-            const float dz0 = dp0 * (1.0f / 36.0f), dz1 = dp1 * (1.0f / 36.0f);
-            // dW3[c][tap][ci] += dz_c * (sum of the tap-shifted conv2 outputs)
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const int q = threadIdx.x + kThreads * r;
-                if (q < 288) {
-                    const int tap = q >> 5, ci = q & 31;
-                    float s = 0.f;
-                    for (int m = 0; m < 36; ++m) {
-                        const int yy = 2 * (m / 6) + tap / 3 - 1, xx = 2 * (m % 6) + tap % 3 - 1;
-                        if (yy >= 0 && yy < 12 && xx >= 0 && xx < 12) s += bf16_val(F.a2[(yy * 12 + xx) * 32 + ci]);
+        const int en = e + gridDim.x;
+        const JobDesc *Jn = nullptr;
+        int kn = 0;
+        InJob in{};
+        const bool vn = en < count && decode(en, Jn, kn, in);
+        __syncthreads();  // MB e's input is in LDS
+        if (vn) issue_input(pix, in, 16 * (kn % in.wm), 16 * (kn / in.wm));
+        if (vc) {
+            const JobDesc &J = *Jc;
+            const int k = kc;
+            forward_mb(S, ops, a.P);
+            const float p0 = F.pv[0], p1 = F.pv[1];
+            if constexpr (!TRAIN) {
+                if (threadIdx.x == 0) {
+                    if (J.seed) {
+                        const int sx = 2 * iclamp((int)rintf(p0), -16, 16), sy = 2 * iclamp((int)rintf(p1), -16, 16);
+                        *(__attribute__((address_space(1))) uint32_t *)((uint32_t *)J.seed + k) =
+                            (uint32_t)(uint16_t)sx | ((uint32_t)(uint16_t)sy << 16);
                     }
-                    gw3[r][0] += dz0 * s;
-                    gw3[r][1] += dz1 * s;
-                }
-            }
-            // dA2 (uniform dz3) -> ReLU mask -> bias gradient, bf16 copy
-            for (int q = threadIdx.x; q < 144 * 32; q += kThreads) {
-                const int pix = q >> 5, ci = q & 31;
-                const int iy = pix / 12, ix = pix % 12;
-                float d = 0.f;
-                for (int ky = 0; ky < 3; ++ky) {
-                    const int ty = iy + 1 - ky;
-                    if (ty < 0 || (ty & 1) || (ty >> 1) >= 6) continue;
-                    for (int kx = 0; kx < 3; ++kx) {
-                        const int tx = ix + 1 - kx;
-                        if (tx < 0 || (tx & 1) || (tx >> 1) >= 6) continue;
-                        const int tap = ky * 3 + kx;
-                        d += dz0 * bf16_val(w3b[tap * 32 + ci]) + dz1 * bf16_val(w3b[(9 + tap) * 32 + ci]);
+                    if (J.out_u32) {
+                        __attribute__((address_space(1))) float *o = (__attribute__((address_space(1))) float *)J.out_u32;
+                        o[2 * k] = p0;
+                        o[2 * k + 1] = p1;
                     }
                 }
-                if (F.a2[q] == 0) d = 0.f;
-                gb2 += d;
-                T.d2[q] = (uint16_t)bf16_bits(d);
-            }
-            __syncthreads();
-            // dW2 += a1 (shifted) x d2: rows (tap, ci) = 18 tiles, columns co = 2 tiles, K = 144 pixels
-#pragma unroll
-            for (int u = 0; u < 9; ++u) {
-                const int t = wv * 9 + u, mt = t >> 1, nt = t & 1;
-                const int row = mt * 16 + r16, tap = row >> 5, ci = row & 31;
-                const int co = nt * 16 + r16;
-#pragma unroll 1
-                for (int ks = 0; ks < 5; ++ks) {
-                    uint16_t av[8], bv[8];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const int q = ks * 32 + 8 * g + j;
-                        const int oy = q / 12, ox = q % 12;
-                        const int yy = 2 * oy + tap / 3 - 1, xx = 2 * ox + tap % 3 - 1;
-                        const bool ok = q < 144 && yy >= 0 && yy < 24 && xx >= 0 && xx < 24;
-                        av[j] = ok ? F.a1[(yy * 24 + xx) * 32 + ci] : (uint16_t)0;
-                        bv[j] = q < 144 ? T.d2[q * 32 + co] : (uint16_t)0;
-                    }
-                    gw2[u] = mfma(u16x8{av[0], av[1], av[2], av[3], av[4], av[5], av[6], av[7]},
-                                  u16x8{bv[0], bv[1], bv[2], bv[3], bv[4], bv[5], bv[6], bv[7]}, gw2[u]);
+            } else {
+                NetLdsTrain &T = S;
+                const uint32_t lab = ((const uint32_t *)J.tf)[k];
+                const float y0 = (float)(((int)(int16_t)(lab & 0xFFFF)) >> 1);
+                const float y1 = (float)(((int)(int16_t)(lab >> 16)) >> 1);
+                const float dp0 = (p0 - y0) * inv_b, dp1 = (p1 - y1) * inv_b;
+                if (threadIdx.x == 0) {
+                    loss += 0.5f * ((p0 - y0) * (p0 - y0) + (p1 - y1) * (p1 - y1)) * inv_b;
+                    gb3[0] += dp0;
+                    gb3[1] += dp1;
                 }
-            }
-            // dA1 = transposed conv of d2 with W2: rows = 576 input pixels, columns ci (tile wv & 1)
-            {
-                const int nt = wv & 1, n = nt * 16 + r16;
-                for (int mt = wv >> 1; mt < 36; mt += 2) {
-                    const int m = mt * 16 + r16, iy = m / 24, ix = m % 24;
-                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int tap = 0; tap < 9; ++tap) {
-                        const int ty = iy + 1 - tap / 3, tx = ix + 1 - tap % 3;
-                        const bool ok = ty >= 0 && !(ty & 1) && (ty >> 1) < 12 && tx >= 0 && !(tx & 1) && (tx >> 1) < 12;
-                        const u16x8 av = ok ? ld16(T.d2 + ((ty >> 1) * 12 + (tx >> 1)) * 32 + 8 * g) : zero8();
-                        acc = mfma(av, ld16(w2t + (tap * 32 + n) * 32 + 8 * g), acc);
-                    }
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int mm = mt * 16 + 4 * g + i;
-                        const float d = F.a1[mm * 32 + n] != 0 ? acc[i] : 0.f;
-                        gb1 += d;
-                        T.d1[mm * 32 + n] = (uint16_t)bf16_bits(d);
+                const float dz0 = dp0 * (1.0f / 36.0f), dz1 = dp1 * (1.0f / 36.0f);
+                // dW3[c][tap][ci] += dz_c * (sum of the tap-shifted conv2 outputs)
+    #pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int q = threadIdx.x + kThreads * r;
+                    if (q < 288) {
+                        const int tap = q >> 5, ci = q & 31;
+                        float s = 0.f;
+                        for (int m = 0; m < 36; ++m) {
+                            const int yy = 2 * (m / 6) + tap / 3 - 1, xx = 2 * (m % 6) + tap % 3 - 1;
+                            if (yy >= 0 && yy < 12 && xx >= 0 && xx < 12) s += bf16_val(F.a2[(yy * 12 + xx) * 32 + ci]);
+                        }
+                        gw3[r][0] += dz0 * s;
+                        gw3[r][1] += dz1 * s;
                     }
                 }
-            }
-            __syncthreads();
-            // dW1 += d1^T x x0 (shifted): rows co (tile wv >> 1), columns (tap, ci) (tile wv & 1), K = 576
-            {
-                const int co = (wv >> 1) * 16 + r16;
-                const int col = (wv & 1) * 16 + r16, tap = col >> 1, ci = col & 1;
-#pragma unroll 1
-                for (int ks = 0; ks < 18; ++ks) {
-                    uint16_t av[8], bv[8];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const int q = ks * 32 + 8 * g + j;
-                        const int y = q / 24, x = q % 24;
-                        const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-                        av[j] = T.d1[q * 32 + co];
-                        bv[j] = (col < 18 && yy >= 0 && yy < 24 && xx >= 0 && xx < 24) ? F.x0[2 * (yy * 24 + xx) + ci]
-                                                                                         : (uint16_t)0;
+                // dA2 (uniform dz3) -> ReLU mask -> bias gradient, bf16 copy
+                for (int q = threadIdx.x; q < 144 * 32; q += kThreads) {
+                    const int pix = q >> 5, ci = q & 31;
+                    const int iy = pix / 12, ix = pix % 12;
+                    float d = 0.f;
+                    for (int ky = 0; ky < 3; ++ky) {
+                        const int ty = iy + 1 - ky;
+                        if (ty < 0 || (ty & 1) || (ty >> 1) >= 6) continue;
+                        for (int kx = 0; kx < 3; ++kx) {
+                            const int tx = ix + 1 - kx;
+                            if (tx < 0 || (tx & 1) || (tx >> 1) >= 6) continue;
+                            const int tap = ky * 3 + kx;
+                            d += dz0 * bf16_val(w3b[tap * 32 + ci]) + dz1 * bf16_val(w3b[(9 + tap) * 32 + ci]);
+                        }
                     }
-                    gw1 = mfma(u16x8{av[0], av[1], av[2], av[3], av[4], av[5], av[6], av[7]},
-                               u16x8{bv[0], bv[1], bv[2], bv[3], bv[4], bv[5], bv[6], bv[7]}, gw1);
+                    if (F.a2[q] == 0) d = 0.f;
+                    gb2 += d;
+                    T.d2[q] = (uint16_t)bf16_bits(d);
+                }
+                __syncthreads();
+                // dW2 += a1 (shifted) x d2: rows (tap, ci) = 18 tiles, columns co = 2 tiles, K = 144 pixels
+    #pragma unroll
+                for (int u = 0; u < 9; ++u) {
+                    const int t = wv * 9 + u, mt = t >> 1, nt = t & 1;
+                    const int row = mt * 16 + r16, tap = row >> 5, ci = row & 31;
+                    const int co = nt * 16 + r16;
+    #pragma unroll 1
+                    for (int ks = 0; ks < 5; ++ks) {
+                        uint16_t av[8], bv[8];
+    #pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            const int q = ks * 32 + 8 * g + j;
+                            const int oy = q / 12, ox = q % 12;
+                            const int yy = 2 * oy + tap / 3 - 1, xx = 2 * ox + tap % 3 - 1;
+                            const bool ok = q < 144 && yy >= 0 && yy < 24 && xx >= 0 && xx < 24;
+                            av[j] = ok ? F.a1[(yy * 24 + xx) * 32 + ci] : (uint16_t)0;
+                            bv[j] = q < 144 ? T.d2[q * 32 + co] : (uint16_t)0;
+                        }
+                        gw2[u] = mfma(u16x8{av[0], av[1], av[2], av[3], av[4], av[5], av[6], av[7]},
+                                      u16x8{bv[0], bv[1], bv[2], bv[3], bv[4], bv[5], bv[6], bv[7]}, gw2[u]);
+                    }
+                }
+                // dA1 = transposed conv of d2 with W2: rows = 576 input pixels, columns ci (tile wv & 1)
+                {
+                    const int nt = wv & 1, n = nt * 16 + r16;
+                    for (int mt = wv >> 1; mt < 36; mt += 2) {
+                        const int m = mt * 16 + r16, iy = m / 24, ix = m % 24;
+                        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    #pragma unroll
+                        for (int tap = 0; tap < 9; ++tap) {
+                            const int ty = iy + 1 - tap / 3, tx = ix + 1 - tap % 3;
+                            const bool ok = ty >= 0 && !(ty & 1) && (ty >> 1) < 12 && tx >= 0 && !(tx & 1) && (tx >> 1) < 12;
+                            const u16x8 av = ok ? ld16(T.d2 + ((ty >> 1) * 12 + (tx >> 1)) * 32 + 8 * g) : zero8();
+                            acc = mfma(av, ld16(w2t + (tap * 32 + n) * 32 + 8 * g), acc);
+                        }
+    #pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int mm = mt * 16 + 4 * g + i;
+                            const float d = F.a1[mm * 32 + n] != 0 ? acc[i] : 0.f;
+                            gb1 += d;
+                            T.d1[mm * 32 + n] = (uint16_t)bf16_bits(d);
+                        }
+                    }
+                }
+                __syncthreads();
+                // dW1 += d1^T x x0 (shifted): rows co (tile wv >> 1), columns (tap, ci) (tile wv & 1), K = 576
+                {
+                    const int co = (wv >> 1) * 16 + r16;
+                    const int col = (wv & 1) * 16 + r16, tap = col >> 1, ci = col & 1;
+    #pragma unroll 1
+                    for (int ks = 0; ks < 18; ++ks) {
+                        uint16_t av[8], bv[8];
+    #pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            const int q = ks * 32 + 8 * g + j;
+                            const int y = q / 24, x = q % 24;
+                            const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+                            av[j] = T.d1[q * 32 + co];
+                            bv[j] = (col < 18 && yy >= 0 && yy < 24 && xx >= 0 && xx < 24) ? F.x0[2 * (yy * 24 + xx) + ci]
+                                                                                             : (uint16_t)0;
+                        }
+                        gw1 = mfma(u16x8{av[0], av[1], av[2], av[3], av[4], av[5], av[6], av[7]},
+                                   u16x8{bv[0], bv[1], bv[2], bv[3], bv[4], bv[5], bv[6], bv[7]}, gw1);
+                    }
                 }
             }
         }
         __syncthreads();  // LDS is reused by the next MB
+        if (vn) write_input(F.x0, pix);
+        Jc = Jn;
+        kc = kn;
+        ic = in;
+        vc = vn;
     }
     if constexpr (TRAIN) {
         NetLdsTrain &T = S;
