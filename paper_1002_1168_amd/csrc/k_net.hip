@@ -185,13 +185,22 @@ __device__ __forceinline__ u16x8 conv1_a(const uint16_t *x0s, int m, int g) {
     return u16x8{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
 }
 
+// Activation maps (conv1 and conv2 outputs) are NHWC with 32 bf16 channels
+// per pixel, the four 16-byte channel chunks of pixel p XOR-rotated by
+// (p >> 1) & 3.  A stride-2 convolution reads every other pixel; without the
+// rotation the 16 pixels of one operand read start 128 bytes apart and share
+// LDS banks, with it four consecutive ones fall in different banks.
+__device__ __forceinline__ int act_off(int pix, int ch) {
+    return pix * 32 + ((((ch >> 3) ^ (pix >> 1)) & 3) << 3) + (ch & 7);
+}
+
 // A operand of a stride-2 convolution over a 32-channel NHWC map `in`
 // (size Hi x Hi, output Ho x Ho): row m, tap, channels 8g..8g+7.
 __device__ __forceinline__ u16x8 conv_s2_a(const uint16_t *in, int Hi, int Ho, int m, int tap, int g) {
     const int oy = m / Ho, ox = m - (m / Ho) * Ho;
     const int yy = 2 * oy + tap / 3 - 1, xx = 2 * ox + tap % 3 - 1;
     if (m >= Ho * Ho || yy < 0 || yy >= Hi || xx < 0 || xx >= Hi) return zero8();
-    return ld16(in + (yy * Hi + xx) * 32 + 8 * g);
+    return ld16(in + act_off(yy * Hi + xx, 8 * g));
 }
 
 // forward pass of one MB; returns with lds.pv holding p (all threads)
@@ -262,7 +271,7 @@ __device__ void forward_mb(L &S, const NetOps &o, const float *P) {
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
             const f32x4 acc = mfma(o.w1[nt], x, f32x4{0.f, 0.f, 0.f, 0.f});
-            store4_relu(F.a1 + m * 32 + nt * 16 + 4 * g, acc, F.bias + nt * 16 + 4 * g);
+            store4_relu(F.a1 + act_off(m, nt * 16 + 4 * g), acc, F.bias + nt * 16 + 4 * g);
         }
     }
     __syncthreads();
@@ -273,7 +282,7 @@ __device__ void forward_mb(L &S, const NetOps &o, const float *P) {
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int tap = 0; tap < 9; ++tap) acc = mfma(o.w2[tap], conv_s2_a(F.a1, 24, 12, mt * 16 + r16, tap, g), acc);
-            store4_relu(F.a2 + (mt * 16 + r16) * 32 + nt * 16 + 4 * g, acc, F.bias + 32 + nt * 16 + 4 * g);
+            store4_relu(F.a2 + act_off(mt * 16 + r16, nt * 16 + 4 * g), acc, F.bias + 32 + nt * 16 + 4 * g);
         }
     }
     __syncthreads();
@@ -401,7 +410,7 @@ __global__ __launch_bounds__(kThreads, TRAIN ? 1 : 3) void net_kernel(NetArgs a)
                         float s = 0.f;
                         for (int m = 0; m < 36; ++m) {
                             const int yy = 2 * (m / 6) + tap / 3 - 1, xx = 2 * (m % 6) + tap % 3 - 1;
-                            if (yy >= 0 && yy < 12 && xx >= 0 && xx < 12) s += bf16_val(F.a2[(yy * 12 + xx) * 32 + ci]);
+                            if (yy >= 0 && yy < 12 && xx >= 0 && xx < 12) s += bf16_val(F.a2[act_off(yy * 12 + xx, ci)]);
                         }
                         gw3[r][0] += dz0 * s;
                         gw3[r][1] += dz1 * s;
@@ -422,7 +431,7 @@ __global__ __launch_bounds__(kThreads, TRAIN ? 1 : 3) void net_kernel(NetArgs a)
                             d += dz0 * bf16_val(w3b[tap * 32 + ci]) + dz1 * bf16_val(w3b[(9 + tap) * 32 + ci]);
                         }
                     }
-                    if (F.a2[q] == 0) d = 0.f;
+                    if (F.a2[act_off(pix, ci)] == 0) d = 0.f;
                     gb2 += d;
                     T.d2[q] = (uint16_t)bf16_bits(d);
                 }
@@ -442,7 +451,7 @@ __global__ __launch_bounds__(kThreads, TRAIN ? 1 : 3) void net_kernel(NetArgs a)
                             const int oy = q / 12, ox = q % 12;
                             const int yy = 2 * oy + tap / 3 - 1, xx = 2 * ox + tap % 3 - 1;
                             const bool ok = q < 144 && yy >= 0 && yy < 24 && xx >= 0 && xx < 24;
-                            av[j] = ok ? F.a1[(yy * 24 + xx) * 32 + ci] : (uint16_t)0;
+                            av[j] = ok ? F.a1[act_off(yy * 24 + xx, ci)] : (uint16_t)0;
                             bv[j] = q < 144 ? T.d2[q * 32 + co] : (uint16_t)0;
                         }
                         gw2[u] = mfma(u16x8{av[0], av[1], av[2], av[3], av[4], av[5], av[6], av[7]},
@@ -465,7 +474,7 @@ __global__ __launch_bounds__(kThreads, TRAIN ? 1 : 3) void net_kernel(NetArgs a)
     #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             const int mm = mt * 16 + 4 * g + i;
-                            const float d = F.a1[mm * 32 + n] != 0 ? acc[i] : 0.f;
+                            const float d = F.a1[act_off(mm, n)] != 0 ? acc[i] : 0.f;
                             gb1 += d;
                             T.d1[mm * 32 + n] = (uint16_t)bf16_bits(d);
                         }
