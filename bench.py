@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched frame-step measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-seed measurement")
+    ap.add_argument("--no-hd", action="store_true",
+                    help="skip the 8-stream 1920x1088 batched measurement (plain and network-seeded)")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the 64-stream batched measurement (for profiling) and print it")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -255,6 +257,99 @@ def batched_measurement(torch, steps, warmup):
             "grid_mbs_per_vop_layer": mw.layer_mbs, "per_step_graph": per_step, "pipelined_all_steps": pipelined}
 
 
+class HDWorkload:
+    """8 streams of 1920x1088, 3-6 VOPs each (sub-pixel motion up to 24 px
+    per frame), S=32 with half-pel: one batched frame step = every
+    (stream, VOP) pair of one frame step, plain or with seed buffers."""
+
+    def __init__(self, frames=6, streams=8):
+        import torch
+        import paper_1002_1168_amd as me
+        from paper_1002_1168_amd import device as dv
+        from paper_1002_1168_amd import synth
+        self.me, self.dv, self.torch = me, dv, torch
+        t0 = time.time()
+        self.seqs = synth.hd_streams(seed=5, frames=frames, streams=streams)
+        log(f"generated {len(self.seqs)} 1920x1088 streams x{frames} frames in {time.time() - t0:.1f}s")
+        self.pairs = frames - 1
+        self.ds = [dv.DeviceSequence(q) for q in self.seqs]
+        self.units = [(si, v) for si, q in enumerate(self.seqs) for v in range(q.vops)]
+        self.params = me.me_default_params(search_range=32, half_pel=1)
+        self.grid_mbs = sum(self.ds[si].hm * self.ds[si].wm for si, _ in self.units)
+
+    def outputs(self):
+        return [self.dv.Outputs.alloc(self.pairs, self.ds[si].hm, self.ds[si].wm) for si, _ in self.units]
+
+    def jobs(self, i, out, zero, seeds=None):
+        """Jobs of frame step i; T = the previous step's mv_int (zero at step 0)."""
+        js = []
+        for u, (si, v) in enumerate(self.units):
+            d, t = self.ds[si], i + 1
+            tf = out[u].mv_int[i - 1] if i > 0 else zero[u]
+            js.append(self.dv.job(d.luma[t], d.luma[t - 1], d.alpha[v, t], d.alpha[v, t - 1], d.cls[v, t], tf,
+                                  out[u], i, None if seeds is None else seeds[u]))
+        return js
+
+
+def hd_measurement(torch, steps):
+    """The batched frame step on the 1920x1088 streams, plain and with the
+    proposal network attached (weights trained on CIF at S=16; the seed is
+    clamped to +-16 and refined by the recursion at S=32): MB/s, PSNR,
+    recursion iterations per searched MB."""
+    me = __import__("paper_1002_1168_amd")
+    hw = HDWorkload()
+    stream = hw.dv.stream_handle()
+    zero = [torch.zeros((hw.ds[si].hm, hw.ds[si].wm, 2), dtype=torch.int16, device="cuda") for si, _ in hw.units]
+    path = os.path.join(ROOT, "paper_1002_1168_amd", "weights", "proposal_cif_s16.npy")
+    net = me.Net(np.load(path, allow_pickle=False)) if os.path.exists(path) else None
+    res = {}
+    for form in ("plain", "learned"):
+        if form == "learned" and net is None:
+            break
+        out = hw.outputs()
+        seeds = None
+        if form == "learned":
+            seeds = [torch.zeros((hw.ds[si].hm, hw.ds[si].wm, 2), dtype=torch.int16, device="cuda")
+                     for si, _ in hw.units]
+        step_jobs = [me.job_array(hw.jobs(i, out, zero, seeds)) for i in range(hw.pairs)]
+        b = me.Batch(step_jobs[0], hw.params, 0, stream=stream)
+        if form == "learned":
+            b.set_net(net)
+        # one pass with the per-step results: quality
+        psnr = []
+        for i in range(hw.pairs):
+            b.step(step_jobs[i])
+            sse, npx, ps, status = b.results(check=False)
+            assert status in (me.ME_OK, me.ME_EEMPTY), status
+            psnr += [x for x, n in zip(ps, npx) if n > 0 and np.isfinite(x)]
+        torch.cuda.synchronize()
+        its = n = 0
+        for u, (si, v) in enumerate(hw.units):
+            h = out[u].host()
+            m = hw.ds[si].cls[v, 1:].cpu().numpy() != 0
+            its += int(h["iters"][m].astype(np.int64).sum())
+            n += int(m.sum())
+        # timed passes
+        k = max(steps // hw.pairs, 2) * hw.pairs
+        t0 = time.perf_counter()
+        for i in range(k):
+            b.step(step_jobs[i % hw.pairs])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b.close()
+        res[form] = {"mb_per_s": hw.grid_mbs * k / dt, "ms_per_frame_step": 1000.0 * dt / k, "frame_steps": k,
+                     "psnr_db": float(np.mean(psnr)), "iters_per_mb": its / max(n, 1), "searched_mbs_per_pass": n}
+    if net is not None:
+        net.close()
+        res["psnr_delta_db"] = res["learned"]["psnr_db"] - res["plain"]["psnr_db"]
+        res["admitted"] = bool(res["psnr_delta_db"] >= -0.05)
+    log("hd batched: " + "; ".join(f"{f} {r['mb_per_s'] / 1e6:.1f} M MB/s, {r['ms_per_frame_step']:.3f} ms/step, "
+                                     f"PSNR {r['psnr_db']:.3f} dB, iters/MB {r['iters_per_mb']:.3f}"
+                                     for f, r in res.items() if isinstance(r, dict)))
+    return {"workload": f"hd1920x1088_{len(hw.seqs)}streams_{len(hw.units)}vops_S32_halfpel",
+            "grid_mbs_per_frame_step": hw.grid_mbs, **res}
+
+
 def timed(fn, steps, warmup, torch, me, stream, kind):
     """Wall time of `steps` calls of fn, and the mean duration of the main
     kernel of call kind `kind` over the same calls (HIP events recorded by
@@ -376,6 +471,10 @@ def main():
     if not a.no_batched:
         batched = batched_measurement(torch, a.steps, a.warmup)
 
+    hd = None
+    if not a.no_hd:
+        hd = hd_measurement(torch, a.steps)
+
     cpu = None
     if not a.no_cpu_baseline:
         hosts = [o.host() for o in wl.out]
@@ -406,6 +505,7 @@ def main():
         "baselines": baselines,
         "learned": learned,
         "batched": batched,
+        "hd_batched": hd,
     }
     print(json.dumps(line), flush=True)
 
