@@ -245,9 +245,7 @@ int run_pa(const me_job *jobs, int n, const me_params *params, bool shape_only, 
     uint8_t *base = nullptr, *zb = nullptr, *sb = nullptr;
     rc = upload(*w, A_PA, m.blob, zero, &base, &zb, pa_scratch_bytes(m.nlines), &sb);
     if (rc) return rc;
-    // two waves per line (one works ahead on the next searched pair) while
-    // every line still gets a worker; one wave per line when lines are many
-    const int waves = m.nlines <= pa_worker_cap() / 2 ? 2 : 1;
+    const int waves = lines_waves(m.nlines);
     int workers = std::min(m.nlines, pa_worker_cap() / waves);
     KernelTimer kt;
     KParams kp = kparams(params, shape_only);

@@ -188,7 +188,7 @@ int autotune(me_batch &b) {
     std::vector<int> staging = {1};
     if (plan_elems(b.params.search_range) > 0) staging.push_back(0);
     float best_ms = -1.f;
-    for (int wavesn : {1, 2}) {
+    for (int wavesn : {1, 2, 4}) {
         // workgroups of `wavesn` waves; the same wave budget
         const int cap = std::min(b.plan.nlines, pa_worker_cap() / wavesn);
         std::vector<int> workers = {cap};
@@ -198,7 +198,7 @@ int autotune(me_batch &b) {
             for (int st : staging)
                 for (int sl : {1, 2, 4}) {
                     if (rc) break;
-                    if (wavesn == 2 && sl != 1) continue;  // the two-wave worker polls with a fixed back-off
+                    if (wavesn > 1 && sl != 1) continue;  // the several-wave worker polls with a fixed back-off
                     const int32_t c[5] = {w, st, sl, best[3], wavesn};
                     float ms = time_min(b, e0, e1, [&] { return launch_search(b, u, c, b.stream); });
                     if (ms < 0.f) {
@@ -333,10 +333,10 @@ int me_batch_create(const me_job *jobs, int n, const me_params *params, uint32_t
     b->o_status = b->o_acc + align_up((size_t)n * 16, 256);
     const size_t total = b->o_status + 256;
     const size_t table = sizeof(JobDesc) * (size_t)n;
-    b->cfg[4] = m.nlines <= pa_worker_cap() / 2 ? 2 : 1;
+    b->cfg[4] = lines_waves(m.nlines);
     b->cfg[0] = std::min(m.nlines, pa_worker_cap() / b->cfg[4]);
     b->cfg[1] = 1;
-    b->cfg[2] = b->cfg[4] == 2 ? 1 : 2;
+    b->cfg[2] = b->cfg[4] > 1 ? 1 : 2;
     b->cfg[3] = 8;
     if (hipMalloc(&b->dev, total) != hipSuccess) {
         b->dev = nullptr;

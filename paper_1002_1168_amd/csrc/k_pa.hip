@@ -864,7 +864,7 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
 }
 
 
-// ----------------------------------------------------- two waves per line
+// ------------------------------------------------- several waves per line
 // Shifted history: the three vectors of pairs c-1+g, c-2+g, c-3+g given the
 // word of count c (the g pairs in between are transparent: zero vectors).
 __device__ __forceinline__ void shift_hist(unsigned long long w, uint32_t g, uint32_t (&h)[3]) {
@@ -886,24 +886,25 @@ __device__ __forceinline__ int recurse_from(const Ctx &c, const KParams &kp, int
     return pel_recursion(c, kp, dx, dy, dc, sweep(c, dx, dy));
 }
 
-// Two waves per line.  The i-th searched pair of the line (in pair order)
-// belongs to wave i & 1.  Everything of a pair that does not need its T
-// candidate (the previous pair's vector, which the other wave produces) is
+// NW (2 to 8) waves per line.  The i-th searched pair of the line (in pair
+// order) belongs to wave i % NW.  Everything of a pair that does not need its T
+// candidate (the previous pair's vector, which the preceding wave produces) is
 // done first: polls, window staging, the costs of A, B, C, the recursion from
 // their first minimum (and from the learned seed).  T then arrives through
 // LDS; its cost decides whether that speculative result stands (T is last in
 // the list, so it wins only with a strictly lower cost) or the recursion is
-// redone from T.  The vector is handed to the other wave at once; the
+// redone from T.  The vector is handed to the next wave at once; the
 // progress word is published with a 64-bit atomic max (count in the top
-// bits, so publishes from the two waves can land in any order), and the
+// bits, so publishes from the waves can land in any order), and the
 // half-sample refinement and the result stores follow.
-template <int EM>
-__global__ __launch_bounds__(128) void pa2_kernel(PaArgs a) {
+template <int EM, int NW>
+__global__ __launch_bounds__(64 * NW) void pa2_kernel(PaArgs a) {
     extern __shared__ uint32_t lds[];
     __shared__ int slot;
     __shared__ unsigned long long hword;  // progress word after the latest handed-off pair
     __shared__ int hseq;                  // its index among the line's searched pairs (-1: none)
-    __shared__ int sdone[2];              // per wave: latest own pair whose result stores completed
+    __shared__ int sdone[NW];             // per wave: latest own pair whose result stores completed
+    __shared__ int hpos[8];               // pair position of searched pair j, at j & 7
     __shared__ int ab;                    // a wave left the line on an abort
     __shared__ int stop;                  // the status word asked every worker to leave
     short *R = (short *)lds;              // 511 reciprocal entries (Eq. 4-5, Q.12)
@@ -911,7 +912,7 @@ __global__ __launch_bounds__(128) void pa2_kernel(PaArgs a) {
     const int wwords = ((a.rows * a.pitch + 16) >> 2) + 4;
     uint32_t *const win = lds + 256 + wv * wwords;  // this wave's staged reference window
     const KParams kp = a.kp;
-    for (int g = threadIdx.x; g < 511; g += 128) {
+    for (int g = threadIdx.x; g < 511; g += 64 * NW) {
         const int m = abs(g - 255);
         const int r = (m == 0 || m < 2 * kp.theta) ? 0 : (16384 + m) / (2 * m);
         R[g] = (short)(g < 255 ? -r : r);
@@ -923,6 +924,7 @@ __global__ __launch_bounds__(128) void pa2_kernel(PaArgs a) {
     l_vu64 *const vhword = (l_vu64 *)&hword;
     l_vint *const vsdone = (l_vint *)sdone;
     l_vint *const vab = (l_vint *)&ab;
+    l_vint *const vhpos = (l_vint *)hpos;
     const int l = lane(), j = l >> 2, q = l & 3;
     const int S = kp.S;
     const int nact = (int)uni((int)ldg32(a.nactive));
@@ -932,13 +934,13 @@ __global__ __launch_bounds__(128) void pa2_kernel(PaArgs a) {
             slot = (int)atomicAdd(a.counter, 1u);
             hseq = -1;
             hword = 0ull;
-            sdone[0] = sdone[1] = -1;
+            for (int u = 0; u < NW; ++u) sdone[u] = -1;
             ab = 0;
             stop = (int)(ld_relaxed(a.status) & ST_ABORT);
         }
         __syncthreads();
         const int t = uni(slot);
-        if (t >= nact || uni(stop)) break;  // LDS values: the same decision in both waves
+        if (t >= nact || uni(stop)) break;  // LDS values: the same decision in every wave
         const uint32_t tk = a.tickets[t];
         const int ci = (int)(tk >> 16), v = (int)((tk >> 8) & 0xFF), h = (int)(tk & 0xFF);
         const ChainDesc ch = a.chains[ci];
@@ -979,7 +981,7 @@ __global__ __launch_bounds__(128) void pa2_kernel(PaArgs a) {
                 p += min(r, min(32 - b, ch.len - p));
                 continue;
             }
-            if ((i & 1) != wv) {  // the other wave's pair
+            if (i % NW != wv) {  // another wave's pair
                 ++i;
                 ++p;
                 continue;
@@ -1101,7 +1103,7 @@ __global__ __launch_bounds__(128) void pa2_kernel(PaArgs a) {
             uint32_t m[4];
             const uint32_t *const arr[4] = {mvi + k - 1, mvi + k - wm, mvi + k - wm + 1, tf + k};
             vectors_of(val, nd, use, arr, m);
-            // T when it does not come from the other wave
+            // T when it does not come from the preceding wave
             uint32_t tm = m[3];
             if (!hasT && tf && !(t_local && p > 0)) tm = (uint32_t)uni((int)ldg32(tf + k));
             asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // window visible to the whole wave
@@ -1151,7 +1153,7 @@ __global__ __launch_bounds__(128) void pa2_kernel(PaArgs a) {
                 lc = cost_of(c, sws.sad);
                 lits = pel_recursion(c, kp, lx, ly, lc, sws);
             }
-            // ---- T: from the other wave's hand-off (or known already)
+            // ---- T: from the preceding wave's hand-off (or known already)
             for (int sp = 0; uni(*vhseq) != i - 1; ++sp) {
                 if (sp > kp.spin_limit) {
                     if (l == 0) atomicOr(a.status, ST_SPIN_TIMEOUT | ST_ABORT);
@@ -1237,10 +1239,19 @@ __global__ __launch_bounds__(128) void pa2_kernel(PaArgs a) {
                 pts += its;
             }
             const unsigned long long word = progress_word(need, enc8(dx, dy), hs[0], hs[1]);
-            // count `need` promises the stores of pairs <= need - 4; only the
-            // other wave's previous pair can be one still in flight
-            if (gap >= 2 && i > 0) {
-                for (int sp = 0; uni(vsdone[wv ^ 1]) < i - 1; ++sp) {
+            // count `need` promises the stores of pairs <= need - 4 (p - 3).
+            // This wave's earlier pairs are complete (its window loads came
+            // after their stores); so are the other waves' pairs before their
+            // latest ones (handed off after their own window loads).  What
+            // may still be in flight: the other waves' latest pairs i - 1 ..
+            // i - NW + 1, which count only when a transparent run puts them
+            // three or more pairs back.
+#pragma unroll
+            for (int d = 1; d < NW; ++d) {
+                const int jj = i - d;
+                if (jj < 0 || aborted) break;
+                if ((int)uni(vhpos[jj & 7]) > p - 3) continue;
+                for (int sp = 0; uni(vsdone[jj % NW]) < jj; ++sp) {
                     if (sp > kp.spin_limit) {
                         if (l == 0) atomicOr(a.status, ST_SPIN_TIMEOUT | ST_ABORT);
                         aborted = true;
@@ -1248,11 +1259,12 @@ __global__ __launch_bounds__(128) void pa2_kernel(PaArgs a) {
                     }
                     __builtin_amdgcn_s_sleep(1);
                 }
-                if (aborted) break;
             }
+            if (aborted) break;
             if (l == 0) {
                 publish_max(own, word);
                 *vhword = word;
+                vhpos[i & 7] = p;
                 asm volatile("" ::: "memory");
                 *vhseq = i;
             }
@@ -1285,7 +1297,7 @@ __global__ __launch_bounds__(128) void pa2_kernel(PaArgs a) {
                 publish_max(own, progress_word((uint32_t)ch.len, hs[0], hs[1], hs[2]));
             }
         }
-        if (any_abort) break;  // the same decision in both waves
+        if (any_abort) break;  // the same decision in every wave
     }
 }
 
@@ -1322,10 +1334,23 @@ size_t pa_scratch_bytes(int nlines) {
     return 256 + nb * 4 * 8 + 256 + nb * 4 + 256 + (size_t)nlines * 4 + 256;
 }
 
-size_t pa2_lds_bytes(int S) {
+size_t pa2_lds_bytes(int S, int waves) {
     const int rows = 2 * S + 18, pitch = (rows + 3) & ~3;
-    return 1024 + 2 * ((size_t)(((rows * pitch + 16) >> 2) + 4) * 4);
+    return 1024 + (size_t)waves * ((size_t)(((rows * pitch + 16) >> 2) + 4) * 4);
 }
+
+namespace {
+template <int NW>
+void launch_lines(int em, int workers, size_t lds, hipStream_t s, const PaArgs &a) {
+    const dim3 blk(64 * NW);
+    switch (em) {
+        case 4: hipLaunchKernelGGL((pa2_kernel<4, NW>), dim3(workers), blk, lds, s, a); break;
+        case 12: hipLaunchKernelGGL((pa2_kernel<12, NW>), dim3(workers), blk, lds, s, a); break;
+        case 28: hipLaunchKernelGGL((pa2_kernel<28, NW>), dim3(workers), blk, lds, s, a); break;
+        default: hipLaunchKernelGGL((pa2_kernel<0, NW>), dim3(workers), blk, lds, s, a); break;
+    }
+}
+}  // namespace
 
 hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainDesc *chains, const uint32_t *tickets,
                      int nlines, unsigned long long *progress, uint32_t *counter, uint32_t *masks, int mask_words,
@@ -1353,13 +1378,16 @@ hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainD
     PaArgs a{jobs, chains, active, nactive, progress, counter, tmask, bmask, mask_words, status, kp,
              (rows + 3) & ~3, rows};
     timer_mark(t, true, s);
-    if (waves == 2) {
-        const size_t lds2 = pa2_lds_bytes(kp.S);
-        switch (generic ? 0 : plan_elems(kp.S)) {
-            case 4: hipLaunchKernelGGL(pa2_kernel<4>, dim3(workers), dim3(128), lds2, s, a); break;
-            case 12: hipLaunchKernelGGL(pa2_kernel<12>, dim3(workers), dim3(128), lds2, s, a); break;
-            case 28: hipLaunchKernelGGL(pa2_kernel<28>, dim3(workers), dim3(128), lds2, s, a); break;
-            default: hipLaunchKernelGGL(pa2_kernel<0>, dim3(workers), dim3(128), lds2, s, a); break;
+    if (waves >= 2) {
+        const size_t lds2 = pa2_lds_bytes(kp.S, waves);
+        const int em = generic ? 0 : plan_elems(kp.S);
+        switch (waves) {
+            case 2: launch_lines<2>(em, workers, lds2, s, a); break;
+            case 3: launch_lines<3>(em, workers, lds2, s, a); break;
+            case 4: launch_lines<4>(em, workers, lds2, s, a); break;
+            case 6: launch_lines<6>(em, workers, lds2, s, a); break;
+            case 8: launch_lines<8>(em, workers, lds2, s, a); break;
+            default: return hipErrorInvalidValue;  // no worker of that width
         }
         e = hipGetLastError();
         timer_mark(t, false, s);

@@ -82,6 +82,12 @@ hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, 
 size_t mc_scratch(int total_mbs);
 
 int pa_worker_cap();
+// Waves per line worker for `nlines` lines: 4 while every line still gets
+// a worker (each wave then has four pairs' time for its own pair), 2 while
+// that holds at two, else 1 (more lines than workers: one wave per line)
+inline int lines_waves(int nlines) {
+    return nlines <= pa_worker_cap() / 4 ? 4 : nlines <= pa_worker_cap() / 2 ? 2 : 1;
+}
 // exclusive scan of n counts in place (one block), total to *total
 hipError_t launch_scan_counts(uint32_t *counts, int n, uint32_t *total, hipStream_t s);
 

@@ -316,7 +316,8 @@ def test_pa_seeded_start_parity(torch_cuda, maker, S):
 
 def test_pa_many_lines_one_wave_per_line(torch_cuda):
     """More lines than half the worker budget: the one-wave-per-line worker
-    (the two-wave worker runs every smaller case), against the oracle."""
+    (the four-wave worker runs every case up to a quarter of it, the two-wave
+    one the cases up to half), against the oracle."""
     import torch
     from paper_1002_1168_amd import device as dv
     streams = synth.mixed_streams(seed=33, frames=3, counts=(0, 0, 3))
@@ -338,3 +339,22 @@ def test_pa_many_lines_one_wave_per_line(torch_cuda):
     assert me.me_device_status(dv.stream_handle()) == me.ME_OK
     for s, v, out in keep:
         assert_same(out.host(), oracle_pa(s, v, p, 2), f"{s.name} vop {v}")
+
+
+def test_pa_two_waves_per_line(torch_cuda):
+    """Between a quarter and half the worker budget in lines (one 4CIF VOP
+    layer: 1584 lines): the two-wave worker, against the oracle."""
+    import torch
+    from paper_1002_1168_amd import device as dv
+    s = synth.mixed_streams(seed=34, frames=4, counts=(0, 0, 1))[0]
+    p = me.me_default_params(search_range=16)
+    ds = dseq(s)
+    gpu_classify(ds)
+    lines = ds.hm * ds.wm
+    say("lines", lines)
+    assert 256 * 16 // 4 < lines <= 256 * 16 // 2
+    out = dv.Outputs.alloc(3, ds.hm, ds.wm)
+    me.me_texture_recursive(ds.pair_jobs(0, out, 3), p, None, stream=dv.stream_handle())
+    torch.cuda.synchronize()
+    assert me.me_device_status(dv.stream_handle()) == me.ME_OK
+    assert_same(out.host(), oracle_pa(s, 0, p, 3), f"{s.name} vop 0")
