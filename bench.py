@@ -114,17 +114,45 @@ class Workload:
                           for m, o in self.base_out.items()}
         self.grid_mbs = self.V * self.pairs * self.ds.hm * self.ds.wm
 
-    def step(self, stream):
-        """classify -> proposed search -> MC/PSNR."""
+    def step(self, stream, ring, slot):
+        """classify -> proposed search -> MC/SSE (sums read back by `ring`)."""
         me = self.me
         me.me_classify_babs(self.cls_frames, self.cls_ptrs, self.bab_ptrs, stream=stream)
         me.me_texture_recursive(self.jobs, self.params, None, stream=stream)
-        return me.me_motion_compensate_psnr(self.jobs, stream=stream)
+        ring.queue(self.jobs, slot, stream)
 
-    def baseline_step(self, method, stream):
+    def baseline_step(self, method, stream, ring, slot):
         me = self.me
         me.me_full_search(method, self.base_jobs[method], self.params, stream=stream)
-        return me.me_motion_compensate_psnr(self.base_jobs[method], stream=stream)
+        ring.queue(self.base_jobs[method], slot, stream)
+
+
+class SumsRing:
+    """Per-job (SSE, pixel count) sums of two frame steps: device buffers
+    written by me_motion_compensate_sse, copied to pinned host memory on the
+    same stream, so that one step's PSNR is read while the next step runs."""
+
+    def __init__(self, torch, me, n):
+        self.me = me
+        self.dev = [torch.zeros(2 * n, dtype=torch.int64, device="cuda") for _ in range(2)]
+        self.host = [torch.zeros(2 * n, dtype=torch.int64, pin_memory=True) for _ in range(2)]
+        self.ev = [torch.cuda.Event() for _ in range(2)]
+
+    def queue(self, jobs, slot, stream):
+        self.me.me_motion_compensate_sse(jobs, self.dev[slot].data_ptr(), stream=stream)
+        self.host[slot].copy_(self.dev[slot], non_blocking=True)
+        self.ev[slot].record()
+
+    def result(self, slot):
+        """-> (sse list, npix list, psnr_db list, status) of the step in `slot`."""
+        self.ev[slot].synchronize()
+        s = self.host[slot].numpy().view(np.uint64)
+        sse, npx = s[0::2].copy(), s[1::2].copy()
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ps = 10.0 * np.log10(255.0 * 255.0 * npx.astype(np.float64) / sse.astype(np.float64))
+        ps[npx == 0] = np.nan
+        rc = self.me.ME_EEMPTY if (npx == 0).any() else self.me.ME_OK
+        return [int(x) for x in sse], [int(x) for x in npx], [float(x) for x in ps], rc
 
 
 class MixedWorkload:
@@ -176,29 +204,18 @@ def learned_measurement(wl, torch, steps, warmup, plain_psnr, plain_iters):
     seeds = [torch.zeros((wl.pairs, wl.ds.hm, wl.ds.wm, 2), dtype=torch.int16, device="cuda") for _ in range(wl.V)]
     jobs = me.job_array([j for v in range(wl.V) for j in wl.ds.pair_jobs(v, outs[v], wl.pairs, seeds=seeds[v])])
 
-    def step():
+    ring = SumsRing(torch, me, len(jobs))
+
+    def step(slot):
         me.me_classify_babs(wl.cls_frames, wl.cls_ptrs, wl.bab_ptrs, stream=stream)
         me.me_texture_recursive(jobs, wl.params, net, stream=stream)
-        return me.me_motion_compensate_psnr(jobs, stream=stream)
+        ring.queue(jobs, slot, stream)
 
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    me.me_kernel_timing(True)
-    me.me_kernel_time_ms(me.ME_KT_NET, stream)
-    t0 = time.perf_counter()
-    res = None
-    for _ in range(steps):
-        res = step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    net_ms, net_n = me.me_kernel_time_ms(me.ME_KT_NET, stream)
-    me.me_kernel_timing(False)
+    dt, net_ms, res = timed(step, ring, steps, warmup, torch, me, stream, me.ME_KT_NET)
     assert me.me_device_status(stream) == me.ME_OK
     net.close()
     classes = wl.ds.cls[:, 1:].cpu().numpy()
     served = int((classes == 1).sum())
-    net_ms /= max(net_n, 1)
     tflops = served * NET_FWD_FLOP / (net_ms * 1e-3) / 1e12
     pts, its, n = summarize(outs, classes)
     psnr = float(np.mean(res[2]))
@@ -350,19 +367,26 @@ def hd_measurement(torch, steps):
             "grid_mbs_per_frame_step": hw.grid_mbs, **res}
 
 
-def timed(fn, steps, warmup, torch, me, stream, kind):
-    """Wall time of `steps` calls of fn, and the mean duration of the main
-    kernel of call kind `kind` over the same calls (HIP events recorded by
-    the library on `stream` around that kernel)."""
-    for _ in range(warmup):
-        fn()
+def timed(fn, ring, steps, warmup, torch, me, stream, kind):
+    """Wall time of `steps` frame steps fn(slot), and the mean duration of
+    the main kernel of call kind `kind` over the same steps (HIP events
+    recorded by the library on `stream` around that kernel).  Step i is
+    queued before the host waits for step i-1's sums and computes its PSNR,
+    so the GPU does not idle while the host reads results back; every
+    step's PSNR is still computed.  Returns the last step's results."""
+    def run(n):
+        for i in range(n):
+            fn(i & 1)
+            if i:
+                ring.result((i - 1) & 1)
+        return ring.result((n - 1) & 1)
+
+    run(warmup)
     torch.cuda.synchronize()
     me.me_kernel_timing(True)
     me.me_kernel_time_ms(kind, stream)  # restart the sums
     t0 = time.perf_counter()
-    res = None
-    for _ in range(steps):
-        res = fn()
+    res = run(steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     total, count = me.me_kernel_time_ms(kind, stream)
@@ -429,7 +453,9 @@ def main():
     me = wl.me
     stream = wl.dv.stream_handle()
 
-    dt, kern_ms, res = timed(lambda: wl.step(stream), a.steps, a.warmup, torch, me, stream, me.ME_KT_SEARCH)
+    ring = SumsRing(torch, me, len(wl.jobs))
+    dt, kern_ms, res = timed(lambda slot: wl.step(stream, ring, slot), ring, a.steps, a.warmup, torch, me, stream,
+                             me.ME_KT_SEARCH)
     assert me.me_device_status(stream) == me.ME_OK
     sse, npx, ps, _ = res
     ms = 1000.0 * dt / a.steps
@@ -446,7 +472,8 @@ def main():
     baselines = {}
     if not a.no_baselines:
         for m, name in ((me.ME_ES, "es"), (me.ME_TSS, "tss"), (me.ME_DS, "ds")):
-            bdt, bk, bres = timed(lambda m=m: wl.baseline_step(m, stream), max(a.steps // 2, 1), 1, torch, me, stream,
+            bdt, bk, bres = timed(lambda slot, m=m: wl.baseline_step(m, stream, ring, slot), ring,
+                                  max(a.steps // 2, 1), 1, torch, me, stream,
                                   me.ME_KT_FULL)
             bpts, _, bn = summarize(wl.base_out[m], classes)
             steps_b = max(a.steps // 2, 1)

@@ -200,6 +200,21 @@ int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, u
                               double *psnr_db, void *stream);
 
 /*
+ * The same motion compensation and masked SSE (Section 4, Table 2) without
+ * waiting: the per-job sums land in DEVICE memory when the stream reaches
+ * them, and the call returns once the work is queued, so a caller can queue
+ * the next frame step before reading these results.
+ *  pred     as in me_motion_compensate_psnr.
+ *  sums     device array of 2n uint64 (8-byte aligned, ME_EALIGN otherwise),
+ *           owned by the caller: sums[2i] = SSE of job i, sums[2i+1] = its
+ *           pixel count over the VOP (0 for a job without VOP pixels; no
+ *           ME_EEMPTY here).  PSNR = 10 log10(255^2 npix / sse).
+ * Errors are those of me_motion_compensate_psnr found on the host; the jobs
+ * array may be reused on return.
+ */
+int me_motion_compensate_sse(const me_job *jobs, int n, uint8_t *const *pred, uint64_t *sums, void *stream);
+
+/*
  * Batched frame step: many frame pairs (VOP streams of any sizes) per launch,
  * replayed once per frame step as one HIP graph (Fig. 1 applied to every job
  * of the step; classification as in me_classify_babs, search as in

@@ -430,11 +430,13 @@ int me_full_search(int method, const me_job *jobs, int n, const me_params *param
                                       (uint32_t *)sb, w->stream, timer_for(*w, A_SEARCH, &kt) ? &kt : nullptr));
 }
 
-int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, uint64_t *sse, uint64_t *npix,
-                              double *psnr_db, void *stream) {
-    if (n < 0 || (n > 0 && (!jobs || !sse || !npix || !psnr_db))) return ME_EINVAL;
-    std::vector<JobDesc> desc(n);
-    long long total = 0;
+namespace {
+
+// Descriptors of the jobs of an MC call, checked on the host (nothing
+// touches the device); *total = their MB count.
+int mc_descs(const me_job *jobs, int n, uint8_t *const *pred, std::vector<JobDesc> &desc, long long *total) {
+    desc.resize(n);
+    long long t = 0;
     for (int i = 0; i < n; ++i) {
         const me_job &j = jobs[i];
         int rc = check_frame(j.cur, false);
@@ -448,26 +450,50 @@ int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, u
         if (pred && pred[i] && !al4(pred[i])) return ME_EALIGN;
         desc[i] = job_desc(j);
         desc[i].out_u8 = pred ? pred[i] : nullptr;
-        desc[i].mb_base = (int32_t)total;
-        total += (long long)desc[i].wm * desc[i].hm;
+        desc[i].mb_base = (int32_t)t;
+        t += (long long)desc[i].wm * desc[i].hm;
     }
-    if (total > (1ll << 30)) return ME_EINVAL;
-    if (n == 0) return ME_OK;
-    Workspace *w = nullptr;
-    int rc = get_ws(stream, &w);
-    if (rc) return rc;
-    std::lock_guard<std::mutex> lk(w->mu);
+    *total = t;
+    return t > (1ll << 30) ? ME_EINVAL : ME_OK;
+}
+
+// Uploads the descriptors and queues the MC + SSE kernels on w's stream
+// (w's lock held by the caller); the per-job sums (SSE, pixel count) land in
+// `sums` (device, 2n), or in the workspace's scratch when `sums` is NULL
+// (*acc_out: where they land).
+int mc_enqueue(Workspace &w, const std::vector<JobDesc> &desc, long long total, unsigned long long *sums,
+               unsigned long long **acc_out) {
+    const int n = (int)desc.size();
     std::vector<uint8_t> blob;
     size_t o = put(blob, desc.data(), desc.size());
     uint8_t *base = nullptr, *zb = nullptr, *sb = nullptr;
-    size_t acc_bytes = (size_t)n * 2 * sizeof(unsigned long long);
-    rc = upload(*w, A_MC, blob, 0, &base, &zb, acc_bytes + mc_scratch((int)total), &sb);
+    const size_t acc_bytes = sums ? 0 : (size_t)n * 2 * sizeof(unsigned long long);
+    int rc = upload(w, A_MC, blob, 0, &base, &zb, acc_bytes + mc_scratch((int)total), &sb);
     if (rc) return rc;
-    unsigned long long *acc = (unsigned long long *)sb;
+    unsigned long long *acc = sums ? sums : (unsigned long long *)sb;
+    *acc_out = acc;
     KernelTimer kt;
-    rc = hip_err(launch_mc((const JobDesc *)(base + o), n, (int)total, (uint32_t *)(sb + acc_bytes), acc, w->stream,
-                           timer_for(*w, A_MC, &kt) ? &kt : nullptr));
+    return hip_err(launch_mc((const JobDesc *)(base + o), n, (int)total, (uint32_t *)(sb + acc_bytes), acc,
+                             w.stream, timer_for(w, A_MC, &kt) ? &kt : nullptr));
+}
+
+}  // namespace
+
+int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, uint64_t *sse, uint64_t *npix,
+                              double *psnr_db, void *stream) {
+    if (n < 0 || (n > 0 && (!jobs || !sse || !npix || !psnr_db))) return ME_EINVAL;
+    std::vector<JobDesc> desc;
+    long long total = 0;
+    int rc = mc_descs(jobs, n, pred, desc, &total);
+    if (rc || n == 0) return rc;
+    Workspace *w = nullptr;
+    rc = get_ws(stream, &w);
     if (rc) return rc;
+    std::lock_guard<std::mutex> lk(w->mu);
+    unsigned long long *acc = nullptr;
+    rc = mc_enqueue(*w, desc, total, nullptr, &acc);
+    if (rc) return rc;
+    const size_t acc_bytes = (size_t)n * 2 * sizeof(unsigned long long);
     if (w->host_acc_cap < acc_bytes) {
         if (w->host_acc) hipHostFree(w->host_acc);
         w->host_acc = nullptr;
@@ -493,6 +519,21 @@ int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, u
         }
     }
     return status;
+}
+
+int me_motion_compensate_sse(const me_job *jobs, int n, uint8_t *const *pred, uint64_t *sums, void *stream) {
+    if (n < 0 || (n > 0 && (!jobs || !sums))) return ME_EINVAL;
+    if (((uintptr_t)sums & 7u) != 0) return ME_EALIGN;
+    std::vector<JobDesc> desc;
+    long long total = 0;
+    int rc = mc_descs(jobs, n, pred, desc, &total);
+    if (rc || n == 0) return rc;
+    Workspace *w = nullptr;
+    rc = get_ws(stream, &w);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(w->mu);
+    unsigned long long *acc = nullptr;
+    return mc_enqueue(*w, desc, total, (unsigned long long *)sums, &acc);
 }
 
 int me_kernel_timing(int on) {

@@ -1,7 +1,9 @@
 // MB classification from the binary alpha plane (Section 1) and motion
-// compensation + squared error (Section 4).  Both read each pixel once and
-// are bound by HBM.  Layout: 16 lanes per MB, lane = one 16-pixel row, four
-// MBs per wave; per-MB sums are 16-lane DPP reductions (no atomics).
+// compensation + squared error (Section 4).  Both stream each pixel once and
+// are bound by the memory system.  Layout: a few lanes per MB (four for classification,
+// eight for MC), each lane whole 16-pixel rows, per-MB sums DPP reductions
+// over those lanes (no atomics); the job of a wave's MBs is a wave-uniform
+// cursor, so descriptor fields live in scalar registers.
 #include "me_internal.h"
 
 namespace me {
@@ -12,15 +14,6 @@ __global__ __launch_bounds__(64) void fill_u32_kernel(uint32_t *p, size_t n, uin
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t stride = (size_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) p[i] = v;
-}
-
-// Sum over each group of 16 lanes (a DPP row), result in every lane of the row.
-__device__ __forceinline__ int row_sum(int v) {
-    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
-    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
-    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true);  // row_half_mirror
-    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, true);  // row_mirror
-    return v;
 }
 
 // bit i set where byte i of the 4 words (16 bytes) is non-zero
@@ -34,75 +27,144 @@ __device__ __forceinline__ uint32_t nz16(const uint32_t (&a)[4]) {
     return bits;
 }
 
-// Quads of 4 consecutive MBs per wave; a block strides its waves over a
-// contiguous range of quads.  Each lane tracks the job of its own MB.
-struct QuadIter {
-    int q, qend, step;
+// 16 bytes of global memory at a 4-byte aligned address.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef u32x4 __attribute__((aligned(4))) u32x4_a4;
+__device__ __forceinline__ u32x4 ld16(const uint8_t *p) {
+    return *(const __attribute__((address_space(1))) u32x4_a4 *)p;
+}
+__device__ __forceinline__ void st16(uint8_t *p, const uint32_t (&v)[4]) {
+    *(__attribute__((address_space(1))) u32x4_a4 *)p = u32x4{v[0], v[1], v[2], v[3]};
+}
+__device__ __forceinline__ void st32(uint32_t *p, uint32_t v) { *(__attribute__((address_space(1))) uint32_t *)p = v; }
+__device__ __forceinline__ void st8(uint8_t *p, uint8_t v) { *(__attribute__((address_space(1))) uint8_t *)p = v; }
+
+#define DWI(f) ((int)(offsetof(JobDesc, f) / 4))
+
+// Wave-uniform job cursor of the flat-MB kernels: the job index, its flat MB
+// range [base, end), and its descriptor one dword per lane (lane l holds
+// dword l of the 40), read out with readlane.
+struct JobCursor {
+    int j, base, end;
+    uint32_t d;
+    __device__ __forceinline__ int i32(int i) const { return __builtin_amdgcn_readlane((int)d, i); }
+    template <class T>
+    __device__ __forceinline__ T *ptr(int i) const {
+        return (T *)(uintptr_t)((unsigned long long)(uint32_t)i32(i) | ((unsigned long long)(uint32_t)i32(i + 1) << 32));
+    }
 };
 
-__device__ __forceinline__ QuadIter quads(int total, int chunk) {
-    const int nq = (total + 3) >> 2;
-    QuadIter it;
-    it.q = blockIdx.x * chunk + (threadIdx.x >> 6);
-    it.qend = min(blockIdx.x * chunk + chunk, nq);
-    it.step = 4;
-    return it;
+// Last job in [lo, n) whose mb_base <= idx, given jobs[lo].mb_base <= idx
+// (mb_base is the running sum of the jobs' MB counts).  Each round every
+// lane reads one candidate's mb_base and a ballot narrows the range 64-fold:
+// one round for up to 64 jobs, two for up to 4096.
+__device__ __forceinline__ int seek_job(const JobDesc *jobs, int lo, int n, int idx) {
+    int hi = n - 1;
+    while (lo < hi) {
+        const int step = (hi - lo + 64) >> 6;
+        const int c = lo + lane() * step;
+        const bool ok = c <= hi && *(const __attribute__((address_space(1))) int32_t *)&jobs[c].mb_base <= idx;
+        const unsigned long long b = __ballot(ok);
+        lo += (63 - __builtin_clzll(b)) * step;
+        hi = min(hi, lo + step - 1);
+    }
+    return lo;
+}
+
+// Move the cursor to the job of flat MB idx (idx never decreases).
+__device__ __forceinline__ void seek(JobCursor &c, const JobDesc *jobs, int n, int idx) {
+    if (idx < c.end) return;
+    c.j = seek_job(jobs, c.j + 1, n, idx);
+    c.d = ldg32((const uint32_t *)(jobs + c.j) + min(lane(), 39));
+    c.base = c.i32(DWI(mb_base));
+    c.end = c.base + c.i32(DWI(wm)) * c.i32(DWI(hm));
+}
+
+// The flat MB range is cut into units of 64 / LPM consecutive MBs (LPM
+// lanes per MB), one unit per wave per iteration; a block strides its four
+// waves over `chunk` consecutive units.  body(c, k, mb, on) runs once per
+// job a unit touches (nearly always one), `on` set in the lanes whose MB
+// belongs to the cursor's job (k: that MB's index within the job, else 0).
+template <int LPM, class Body>
+__device__ __forceinline__ void for_units(const JobDesc *jobs, int n, int total, int chunk, Body &&body) {
+    constexpr int PER = 64 / LPM;
+    const int nu = (total + PER - 1) / PER;
+    const int u0 = (int)blockIdx.x * chunk;
+    const int uend = min(u0 + chunk, nu);
+    JobCursor c{-1, 0, 0, 0u};
+    for (int u = u0 + uni((int)threadIdx.x >> 6); u < uend; u += 4) {
+        const int m0 = u * PER, mlast = min(m0 + PER, total) - 1;
+        const int mb = m0 + lane() / LPM;
+        seek(c, jobs, n, m0);
+        for (;;) {
+            const bool on = mb <= mlast && mb >= c.base && mb < c.end;
+            body(c, on ? mb - c.base : 0, mb, on);
+            if (mlast < c.end) break;
+            seek(c, jobs, n, c.end);
+        }
+    }
+}
+
+// Sums over groups of 4 and of 8 lanes, result in every lane of the group.
+__device__ __forceinline__ int sum4(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
+    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
+    return v;
+}
+__device__ __forceinline__ int sum8(int v) {
+    v = sum4(v);
+    return v + __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true);  // row_half_mirror
+}
+
+__device__ __forceinline__ uint32_t nz16v(const u32x4 a) {
+    const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+    return nz16(w);
 }
 
 // n = number of pixels with alpha != 0 -> transparent (0), opaque (256),
 // boundary, written to the job's class array; BAB word w = rows 2w, 2w+1
 // with column i at bit (row&1)*16 + i.  Jobs without alpha or without a
-// class array (rectangular frames) are skipped.
+// class array (rectangular frames) are skipped.  Four lanes per MB, lane
+// t reads rows 4t .. 4t+3 and writes BAB words 2t and 2t+1.
 __global__ __launch_bounds__(256) void classify_kernel(const JobDesc *jobs, int n, int total, int chunk) {
-    const int l = lane(), r = l & 15;
-    QuadIter it = quads(total, chunk);
-    if (it.q >= it.qend) return;
-    int ji = find_job(jobs, n, min(4 * it.q, total - 1));
-    for (; it.q < it.qend; it.q += it.step) {
-        const int mb = 4 * it.q + (l >> 4);
-        const bool valid = mb < total;
-        const int m = valid ? mb : total - 1;
-        ji = next_job(jobs, n, ji, m);
-        const JobDesc &J = jobs[ji];
-        const int k = m - J.mb_base;
-        const int h = k % J.wm, v = k / J.wm;
-        const bool has = J.cur_a != nullptr && J.cls != nullptr;
-        uint32_t a[4] = {0u, 0u, 0u, 0u};
-        if (has) {
-            const uint32_t *row = (const uint32_t *)(J.cur_a + (size_t)(16 * v + r) * J.stride + 16 * h);
+    const int t = lane() & 3;
+    for_units<4>(jobs, n, total, chunk, [&](const JobCursor &c, int k, int, bool on) {
+        const uint8_t *alpha = c.ptr<const uint8_t>(DWI(cur_a));
+        uint8_t *cls = c.ptr<uint8_t>(DWI(cls));
+        if (!alpha || !cls) return;
+        uint32_t *bab = c.ptr<uint32_t>(DWI(out_u32));
+        const int wm = c.i32(DWI(wm)), st = c.i32(DWI(stride));
+        const int h = k % wm, v = k / wm;
+        const uint8_t *row = alpha + (size_t)(16 * v + 4 * t) * st + 16 * h;
+        u32x4 a[4];
 #pragma unroll
-            for (int w = 0; w < 4; ++w) a[w] = ldg32(row + w);
+        for (int i = 0; i < 4; ++i) a[i] = ld16(row + (size_t)i * st);
+        uint32_t bits[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bits[i] = nz16v(a[i]);
+        const int tot = sum4(__builtin_popcount(bits[0]) + __builtin_popcount(bits[1]) +
+                             __builtin_popcount(bits[2]) + __builtin_popcount(bits[3]));
+        if (on) {
+            if (bab) {
+                st32(bab + (size_t)k * 8 + 2 * t, bits[0] | (bits[1] << 16));
+                st32(bab + (size_t)k * 8 + 2 * t + 1, bits[2] | (bits[3] << 16));
+            }
+            if (t == 0)
+                st8(cls + k, (uint8_t)(tot == 0 ? ME_MB_TRANSPARENT : (tot == 256 ? ME_MB_OPAQUE : ME_MB_BOUNDARY)));
         }
-        const uint32_t bits = nz16(a);
-        const int tot = row_sum(__builtin_popcount(bits));
-        const uint32_t odd = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0xB1, 0xF, 0xF, true);
-        if (valid && has) {
-            if (J.out_u32 && (r & 1) == 0) J.out_u32[(size_t)k * 8 + (r >> 1)] = bits | (odd << 16);
-            if (r == 0)
-                const_cast<uint8_t *>(J.cls)[k] =
-                    (uint8_t)(tot == 0 ? ME_MB_TRANSPARENT : (tot == 256 ? ME_MB_OPAQUE : ME_MB_BOUNDARY));
-        }
-    }
+    });
 }
 
-// Prediction of one 16-pixel row by the half-pel vector (ix, fx; iy, fy),
-// MPEG-4 bilinear with rounding control 0, coordinates clamped to the frame.
-__device__ __forceinline__ void predict_row(const uint8_t *ref, int st, int W, int H, int x, int y, int hx, int hy,
-                                            uint32_t (&out)[4]) {
-    const int ix = hx >> 1, iy = hy >> 1, fx = hx & 1, fy = hy & 1;
-    const uint8_t *ra = ref + (size_t)iclamp(y + iy, 0, H - 1) * st;
-    uint32_t a[5];
-#pragma unroll
-    for (int w = 0; w < 5; ++w) a[w] = ld4_clamped(ra, x + ix + 4 * w, W);
+// One row of the prediction from reference rows a (at the row's own vertical
+// offset) and c (the row below), 20 bytes each from the integer column:
+// MPEG-4 bilinear interpolation with rounding control 0.
+__device__ __forceinline__ void bilinear_row(const uint32_t (&a)[5], const uint32_t (&c)[5], int fx, int fy,
+                                             uint32_t (&out)[4]) {
     if (!fx && !fy) {
 #pragma unroll
         for (int w = 0; w < 4; ++w) out[w] = a[w];
         return;
     }
-    const uint8_t *rb = ref + (size_t)iclamp(y + iy + 1, 0, H - 1) * st;
-    uint32_t c[5];
-#pragma unroll
-    for (int w = 0; w < 5; ++w) c[w] = fy ? ld4_clamped(rb, x + ix + 4 * w, W) : 0u;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
         uint32_t o = 0;
@@ -118,63 +180,100 @@ __device__ __forceinline__ void predict_row(const uint8_t *ref, int st, int W, i
     }
 }
 
+// Rows y and y+1 (16 pixels from column x) of the prediction by the half-pel
+// vector (hx, hy): reference rows y+iy .. y+iy+2, coordinates clamped to the
+// frame.  The last row is used only for a vertical half-pel; it is read when
+// some lane of the wave has one (a branch per lane would wait for each of its
+// loads on its own).
+__device__ __forceinline__ void predict_rows2(const uint8_t *ref, int st, int W, int H, int x, int y, int hx,
+                                              int hy, uint32_t (&p0)[4], uint32_t (&p1)[4]) {
+    const int ix = hx >> 1, iy = hy >> 1, fx = hx & 1, fy = hy & 1;
+    uint32_t r[3][5];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const uint8_t *row = ref + (size_t)iclamp(y + iy + t, 0, H - 1) * st;
+#pragma unroll
+        for (int w = 0; w < 5; ++w) r[t][w] = ld4_clamped(row, x + ix + 4 * w, W);
+    }
+    // the loads of the last row in one block, their byte permutes after it
+    uint32_t raw[5] = {0u, 0u, 0u, 0u, 0u}, sel[5];
+    const uint8_t *row2 = ref + (size_t)iclamp(y + iy + 2, 0, H - 1) * st;
+#pragma unroll
+    for (int w = 0; w < 5; ++w) {
+        const int xx = x + ix + 4 * w, xc = iclamp(xx, 0, W - 4);
+        sel[w] = (uint32_t)(iclamp(xx, 0, W - 1) - xc) | ((uint32_t)(iclamp(xx + 1, 0, W - 1) - xc) << 8) |
+                 ((uint32_t)(iclamp(xx + 2, 0, W - 1) - xc) << 16) | ((uint32_t)(iclamp(xx + 3, 0, W - 1) - xc) << 24);
+        raw[w] = (uint32_t)xc;
+    }
+    if (__ballot(fy) != 0) {
+#pragma unroll
+        for (int w = 0; w < 5; ++w) raw[w] = ld4(row2 + raw[w]);
+    }
+#pragma unroll
+    for (int w = 0; w < 5; ++w) r[2][w] = __builtin_amdgcn_perm(raw[w], raw[w], sel[w]);
+    bilinear_row(r[0], r[1], fx, fy, p0);
+    bilinear_row(r[1], r[2], fx, fy, p1);
+}
+
+// Squared error of one 16-pixel row over the pixels whose alpha is set.
+__device__ __forceinline__ int row_sse(const u32x4 cur, const uint32_t (&p)[4], uint32_t in) {
+    const uint32_t c[4] = {cur.x, cur.y, cur.z, cur.w};
+    int sse = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int d = byte_of(c[i >> 2], i & 3) - byte_of(p[i >> 2], i & 3);
+        sse += ((in >> i) & 1u) ? d * d : 0;
+    }
+    return sse;
+}
+
 // Prediction of MB k by its half-pel vector (transparent: zero vector),
 // written to out_u8 when set; per-MB SSE and pixel count over the mask to
-// part[2 * mb], part[2 * mb + 1].
+// part[2 * mb], part[2 * mb + 1].  Eight lanes per MB, lane t predicts rows
+// 2t and 2t+1 (three reference rows at most).
 __global__ __launch_bounds__(256) void mc_kernel(const JobDesc *jobs, int n, int total, int chunk, uint32_t *part) {
-    const int l = lane(), r = l & 15;
-    QuadIter it = quads(total, chunk);
-    if (it.q >= it.qend) return;
-    int ji = find_job(jobs, n, min(4 * it.q, total - 1));
-    for (; it.q < it.qend; it.q += it.step) {
-        const int mb = 4 * it.q + (l >> 4);
-        const bool valid = mb < total;
-        const int m = valid ? mb : total - 1;
-        ji = next_job(jobs, n, ji, m);
-        const JobDesc &J = jobs[ji];
-        const int k = m - J.mb_base;
-        const int h = k % J.wm, v = k / J.wm;
-        const int W = J.width, H = J.height, st = J.stride;
-        const int cls = J.cls ? (int)J.cls[k] : ME_MB_OPAQUE;
+    const int t = lane() & 7;
+    for_units<8>(jobs, n, total, chunk, [&](const JobCursor &c, int k, int mb, bool on) {
+        const uint8_t *cur = c.ptr<const uint8_t>(DWI(cur));
+        const uint8_t *ref = c.ptr<const uint8_t>(DWI(ref));
+        const uint8_t *alpha = c.ptr<const uint8_t>(DWI(cur_a));
+        const uint8_t *cls = c.ptr<const uint8_t>(DWI(cls));
+        const uint32_t *mv = c.ptr<const uint32_t>(DWI(mv));
+        uint8_t *out = c.ptr<uint8_t>(DWI(out_u8));
+        const int W = c.i32(DWI(width)), H = c.i32(DWI(height)), st = c.i32(DWI(stride)), wm = c.i32(DWI(wm));
+        const int h = k % wm, v = k / wm;
+        const int x = 16 * h, y = 16 * v + 2 * t;
+        // the class byte is read unconditionally (from the vector array when
+        // there is no class array) so that it shares one round trip with the
+        // vector and the current rows
+        const uint32_t cb = ldg8(cls ? cls + k : (const uint8_t *)(mv + k));
+        const int cl = cls ? (int)cb : ME_MB_OPAQUE;
+        const uint32_t w = ldg32(mv + k);
+        const size_t o0 = (size_t)y * st + x, o1 = o0 + st;
+        const u32x4 c0 = ld16(cur + o0), c1 = ld16(cur + o1);
+        uint32_t in0 = 0xFFFFu, in1 = 0xFFFFu;
+        if (alpha) {
+            in0 = nz16v(ld16(alpha + o0));
+            in1 = nz16v(ld16(alpha + o1));
+        }
         int hx = 0, hy = 0;
-        if (cls != ME_MB_TRANSPARENT) {
-            const uint32_t w = ((const uint32_t *)J.mv)[k];
+        if (cl != ME_MB_TRANSPARENT) {
             hx = (int)(int16_t)(w & 0xFFFF);
             hy = (int)(int16_t)(w >> 16);
         }
-        const int x = 16 * h, y = 16 * v + r;
-        const uint32_t *crow = (const uint32_t *)(J.cur + (size_t)y * st + x);
-        uint32_t c[4], mk[4], p[4];
-#pragma unroll
-        for (int w = 0; w < 4; ++w) c[w] = ldg32(crow + w);
-        if (J.cur_a) {
-            const uint32_t *arow = (const uint32_t *)(J.cur_a + (size_t)y * st + x);
-#pragma unroll
-            for (int w = 0; w < 4; ++w) mk[w] = ldg32(arow + w);
-        } else {
-#pragma unroll
-            for (int w = 0; w < 4; ++w) mk[w] = 0xFFFFFFFFu;
+        uint32_t p0[4], p1[4];
+        predict_rows2(ref, st, W, H, x, y, hx, hy, p0, p1);
+        if (on && out) {
+            st16(out + o0, p0);
+            st16(out + o1, p1);
         }
-        predict_row(J.ref, st, W, H, x, y, hx, hy, p);
-        if (valid && J.out_u8) {
-            uint32_t *prow = (uint32_t *)(J.out_u8 + (size_t)y * st + x);
-#pragma unroll
-            for (int w = 0; w < 4; ++w) prow[w] = p[w];
+        const int sse = sum8(row_sse(c0, p0, in0) + row_sse(c1, p1, in1));
+        const int cnt = sum8(__builtin_popcount(in0) + __builtin_popcount(in1));
+        if (on && t == 0) {
+            st32(part + 2 * (size_t)mb, (uint32_t)sse);
+            st32(part + 2 * (size_t)mb + 1, (uint32_t)cnt);
         }
-        const uint32_t in = nz16(mk);
-        int sse = 0;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int d = byte_of(c[i >> 2], i & 3) - byte_of(p[i >> 2], i & 3);
-            sse += ((in >> i) & 1u) ? d * d : 0;
-        }
-        const int tsse = row_sum(sse);
-        const int tcnt = row_sum(__builtin_popcount(in));
-        if (valid && r == 0) {
-            part[2 * (size_t)mb] = (uint32_t)tsse;
-            part[2 * (size_t)mb + 1] = (uint32_t)tcnt;
-        }
-    }
+    });
 }
 
 // Per job: the exact 64-bit sums of its MBs' SSE and pixel counts.
@@ -226,10 +325,10 @@ int flat_chunk(int total_units, int per_cu) {
 hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_t s, const KernelTimer *t,
                            int per_cu) {
     if (total_mbs <= 0) return hipSuccess;
-    const int nq = (total_mbs + 3) / 4;
-    const int chunk = (flat_chunk(nq, per_cu) + 3) / 4 * 4;
+    const int nu = (total_mbs + 15) / 16;
+    const int chunk = (flat_chunk(nu, per_cu) + 3) / 4 * 4;
     timer_mark(t, true, s);
-    hipLaunchKernelGGL(classify_kernel, dim3((nq + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk);
+    hipLaunchKernelGGL(classify_kernel, dim3((nu + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk);
     hipError_t e = hipGetLastError();
     timer_mark(t, false, s);
     return e;
@@ -240,10 +339,10 @@ size_t mc_scratch(int total_mbs) { return (size_t)total_mbs * 8; }
 hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, unsigned long long *acc,
                      hipStream_t s, const KernelTimer *t, int per_cu) {
     if (total_mbs <= 0) return hipSuccess;
-    const int nq = (total_mbs + 3) / 4;
-    const int chunk = (flat_chunk(nq, per_cu) + 3) / 4 * 4;
+    const int nu = (total_mbs + 7) / 8;
+    const int chunk = (flat_chunk(nu, per_cu) + 3) / 4 * 4;
     timer_mark(t, true, s);
-    hipLaunchKernelGGL(mc_kernel, dim3((nq + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk, part);
+    hipLaunchKernelGGL(mc_kernel, dim3((nu + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk, part);
     hipError_t e = hipGetLastError();
     timer_mark(t, false, s);
     if (e != hipSuccess) return e;

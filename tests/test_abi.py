@@ -107,6 +107,19 @@ def test_psnr_requires_host_outputs():
     assert L.me_motion_compensate_psnr(ja, 1, None, None, None, None, None) == me.ME_EINVAL
 
 
+def test_async_sse_argument_validation():
+    """The queued MC/SSE call checks its arguments on the host first."""
+    L = me.lib()
+    ja = (me.me_job * 1)(job())
+    assert L.me_motion_compensate_sse(ja, 1, None, None, None) == me.ME_EINVAL      # no sums
+    assert L.me_motion_compensate_sse(ja, 1, None, FAKE + 4, None) == me.ME_EALIGN  # sums not 8-aligned
+    assert L.me_motion_compensate_sse(ja, -1, None, FAKE, None) == me.ME_EINVAL
+    assert me.me_motion_compensate_sse([job(mv=None)], FAKE, check=False) == me.ME_EINVAL
+    assert me.me_motion_compensate_sse([job(ref=frame(w=48))], FAKE, check=False) == me.ME_EINVAL
+    assert me.me_motion_compensate_sse([job(mv=FAKE + 2)], FAKE, check=False) == me.ME_EALIGN
+    assert me.me_motion_compensate_sse([], FAKE, check=False) == me.ME_OK
+
+
 def test_kernel_timing_validation():
     L = me.lib()
     assert L.me_kernel_timing(2) == me.ME_EINVAL

@@ -240,6 +240,59 @@ def test_mc_empty_mask_reports_eempty(torch_cuda):
     assert rc == me.ME_EEMPTY and npx[0] == 0 and math.isnan(ps[0])
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_classify_mc_many_small_jobs(torch_cuda, seed):
+    """150 frames of 1 to 12 MBs each, padded strides, in one call each of
+    classification and MC: the kernels' units of 16 and 8 consecutive MBs
+    straddle many jobs, and finding a unit's job takes two 64-way rounds."""
+    import torch
+    from paper_1002_1168_amd import device as dv
+    rng = np.random.default_rng(seed)
+    say("classify+mc many small jobs, seed", seed)
+    n = 150
+    host, dev = [], []
+    for i in range(n):
+        W, H = 16 * int(rng.integers(1, 5)), 16 * int(rng.integers(1, 4))
+        st = W + 4 * int(rng.integers(0, 5))
+        cur = rng.integers(0, 256, size=(H, st), dtype=np.uint8)
+        ref = rng.integers(0, 256, size=(H, st), dtype=np.uint8)
+        kind = i % 3   # all inside, all outside, mixed
+        alpha = np.full((H, st), 255 if kind == 0 else 0, np.uint8)
+        if kind == 2:
+            alpha = (rng.random((H, st)) < 0.5).astype(np.uint8) * rng.integers(1, 256, size=(H, st), dtype=np.uint8)
+        mv = rng.integers(-9, 10, size=(H // 16, W // 16, 2)).astype(np.int16)
+        host.append((cur[:, :W], ref[:, :W], alpha[:, :W], mv))
+        t = [torch.from_numpy(x).cuda() for x in (cur, ref, alpha)]
+        d = dict(cur=t[0][:, :W], ref=t[1][:, :W], alpha=t[2][:, :W], mv=torch.from_numpy(mv).cuda(),
+                 cls=torch.full((H // 16, W // 16), 7, dtype=torch.uint8, device="cuda"),
+                 bab=torch.zeros((H // 16, W // 16, 8), dtype=torch.int32, device="cuda"),
+                 pred=torch.zeros((H, st), dtype=torch.uint8, device="cuda"))
+        assert d["cur"].stride(0) == st
+        dev.append(d)
+    s = dv.stream_handle()
+    me.me_classify_babs([dv.frame(d["cur"], d["alpha"]) for d in dev], [d["cls"].data_ptr() for d in dev],
+                        [d["bab"].data_ptr() for d in dev], stream=s)
+    jobs = [dv.mc_job(d["cur"], d["ref"], d["alpha"], d["cls"], d["mv"]) for d in dev]
+    sse, npx, ps, rc = me.me_motion_compensate_psnr(jobs, [d["pred"].data_ptr() for d in dev], stream=s,
+                                                    check=False)
+    torch.cuda.synchronize()
+    for i, ((cur, ref, alpha, mv), d) in enumerate(zip(host, dev)):
+        c, b = oracle.classify(alpha)
+        np.testing.assert_array_equal(d["cls"].cpu().numpy(), c, err_msg=f"job {i}")
+        np.testing.assert_array_equal(d["bab"].cpu().numpy().view(np.uint32), b, err_msg=f"job {i}")
+        ws, wn, wp = oracle.mc_sse(cur, ref, mv, alpha, c, want_pred=True)
+        assert (sse[i], npx[i]) == (ws, wn), f"job {i}"
+        np.testing.assert_array_equal(d["pred"].cpu().numpy()[:, :cur.shape[1]], wp, err_msg=f"job {i}")
+    # every third job has no pixel inside: the call reports it
+    assert rc == me.ME_EEMPTY
+    # the queued form leaves the same sums in device memory (no ME_EEMPTY)
+    sums = torch.full((2 * n,), -1, dtype=torch.int64, device="cuda")
+    assert me.me_motion_compensate_sse(jobs, sums.data_ptr(), stream=s) == me.ME_OK
+    torch.cuda.synchronize()
+    got = sums.cpu().numpy().view(np.uint64)
+    assert [int(x) for x in got[0::2]] == list(sse) and [int(x) for x in got[1::2]] == list(npx)
+
+
 # ------------------------------------------- full size, repeated launches
 def test_pa_full_bench_workload(torch_cuda):
     """The benchmark's workload and launch (CIF, 300 frames, two VOPs, all
