@@ -383,7 +383,7 @@ def timed(fn, ring, steps, warmup, torch, me, stream, kind):
 
     run(warmup)
     torch.cuda.synchronize()
-    me.me_kernel_timing(True)
+    me.me_kernel_timing(True, kinds=[kind])  # events around this kind's kernel only
     me.me_kernel_time_ms(kind, stream)  # restart the sums
     t0 = time.perf_counter()
     res = run(steps)

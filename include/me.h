@@ -276,11 +276,15 @@ void me_batch_destroy(me_batch *b);
  *  ME_KT_SEARCH    me_texture_recursive,      pipelined search kernel (not the
  *                  me_shape_search            transparent pre-pass before it)
  *  ME_KT_FULL      me_full_search             ES / TSS / DS kernel (not the compaction)
- *  ME_KT_MC        me_motion_compensate_psnr  prediction + SSE kernel (not the per-job sum)
+ *  ME_KT_MC        me_motion_compensate_psnr, prediction + SSE kernel (not the per-job sum)
+ *                  me_motion_compensate_sse
  *  ME_KT_NET       me_net_forward (also via   network forward kernel (not the MB list)
  *                  me_texture_recursive)
  *  ME_KT_NET_TRAIN me_net_train_step          forward + backward kernel (not the SGD update)
- * me_kernel_timing: on = 0 or 1 (ME_EINVAL otherwise); affects later calls.
+ * me_kernel_timing: on = 0 (off), 1 (every kind), or ME_KT_ONLY(kind) bits
+ * OR-ed together (only those kinds: the others record no events, which
+ * add a few microseconds between kernels each); ME_EINVAL otherwise.
+ * Affects later calls.
  * me_kernel_time_ms: waits for every timed call of `kind` on `stream`, writes
  * the sum of their main-kernel durations in milliseconds (host double) and
  * their number (host int), and restarts both sums at zero.
@@ -291,6 +295,7 @@ void me_batch_destroy(me_batch *b);
 #define ME_KT_MC 3
 #define ME_KT_NET 4
 #define ME_KT_NET_TRAIN 5
+#define ME_KT_ONLY(kind) (2 << (kind))
 int me_kernel_timing(int on);
 int me_kernel_time_ms(int kind, void *stream, double *total_ms, int *count);
 

@@ -212,8 +212,10 @@ def me_device_status(stream=None) -> int:
     return lib().me_device_status(stream)
 
 
-def me_kernel_timing(on: bool) -> int:
-    return _check(lib().me_kernel_timing(1 if on else 0), "me_kernel_timing")
+def me_kernel_timing(on: bool, kinds=None) -> int:
+    """Timing on for every call kind, or only for the ME_KT_* in ``kinds``."""
+    mask = (sum(2 << k for k in set(kinds)) if kinds else 1) if on else 0
+    return _check(lib().me_kernel_timing(mask), "me_kernel_timing")
 
 
 def me_kernel_time_ms(kind: int, stream=None):

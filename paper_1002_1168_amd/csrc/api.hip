@@ -124,8 +124,15 @@ int get_ws(void *stream, Workspace **out) {
 
 
 // Event pair for the main kernel of a call of `kind` (false when timing is off).
+// Whether calls of `kind` are timed: timing mask 1 = every kind, else bit
+// kind + 1.
+bool timing_on(int kind) {
+    const int m = g_timing.load(std::memory_order_relaxed);
+    return m == 1 || ((m >> (kind + 1)) & 1);
+}
+
 bool timer_for(Workspace &w, int kind, KernelTimer *out) {
-    if (!g_timing.load(std::memory_order_relaxed)) return false;
+    if (!timing_on(kind)) return false;
     TimerPool &p = w.timers[kind];
     p.harvest(false);
     KernelTimer t;
@@ -261,7 +268,7 @@ namespace me {
 namespace host {
 
 bool kernel_timer(void *stream, int kind, KernelTimer *out) {
-    if (!g_timing.load(std::memory_order_relaxed) || kind < 0 || kind >= kTimerKinds) return false;
+    if (kind < 0 || kind >= kTimerKinds || !timing_on(kind)) return false;
     Workspace *w = nullptr;
     if (get_ws(stream, &w) != ME_OK) return false;
     std::lock_guard<std::mutex> lk(w->mu);
@@ -537,7 +544,8 @@ int me_motion_compensate_sse(const me_job *jobs, int n, uint8_t *const *pred, ui
 }
 
 int me_kernel_timing(int on) {
-    if (on != 0 && on != 1) return ME_EINVAL;
+    // 0, 1, or kind bits 1 .. kTimerKinds only
+    if (on < 0 || (on > 1 && ((on & 1) || (on >> (kTimerKinds + 1)) != 0))) return ME_EINVAL;
     g_timing.store(on, std::memory_order_relaxed);
     return ME_OK;
 }

@@ -39,47 +39,6 @@ __device__ __forceinline__ void st16(uint8_t *p, const uint32_t (&v)[4]) {
 __device__ __forceinline__ void st32(uint32_t *p, uint32_t v) { *(__attribute__((address_space(1))) uint32_t *)p = v; }
 __device__ __forceinline__ void st8(uint8_t *p, uint8_t v) { *(__attribute__((address_space(1))) uint8_t *)p = v; }
 
-#define DWI(f) ((int)(offsetof(JobDesc, f) / 4))
-
-// Wave-uniform job cursor of the flat-MB kernels: the job index, its flat MB
-// range [base, end), and its descriptor one dword per lane (lane l holds
-// dword l of the 40), read out with readlane.
-struct JobCursor {
-    int j, base, end;
-    uint32_t d;
-    __device__ __forceinline__ int i32(int i) const { return __builtin_amdgcn_readlane((int)d, i); }
-    template <class T>
-    __device__ __forceinline__ T *ptr(int i) const {
-        return (T *)(uintptr_t)((unsigned long long)(uint32_t)i32(i) | ((unsigned long long)(uint32_t)i32(i + 1) << 32));
-    }
-};
-
-// Last job in [lo, n) whose mb_base <= idx, given jobs[lo].mb_base <= idx
-// (mb_base is the running sum of the jobs' MB counts).  Each round every
-// lane reads one candidate's mb_base and a ballot narrows the range 64-fold:
-// one round for up to 64 jobs, two for up to 4096.
-__device__ __forceinline__ int seek_job(const JobDesc *jobs, int lo, int n, int idx) {
-    int hi = n - 1;
-    while (lo < hi) {
-        const int step = (hi - lo + 64) >> 6;
-        const int c = lo + lane() * step;
-        const bool ok = c <= hi && *(const __attribute__((address_space(1))) int32_t *)&jobs[c].mb_base <= idx;
-        const unsigned long long b = __ballot(ok);
-        lo += (63 - __builtin_clzll(b)) * step;
-        hi = min(hi, lo + step - 1);
-    }
-    return lo;
-}
-
-// Move the cursor to the job of flat MB idx (idx never decreases).
-__device__ __forceinline__ void seek(JobCursor &c, const JobDesc *jobs, int n, int idx) {
-    if (idx < c.end) return;
-    c.j = seek_job(jobs, c.j + 1, n, idx);
-    c.d = ldg32((const uint32_t *)(jobs + c.j) + min(lane(), 39));
-    c.base = c.i32(DWI(mb_base));
-    c.end = c.base + c.i32(DWI(wm)) * c.i32(DWI(hm));
-}
-
 // The flat MB range is cut into units of 64 / LPM consecutive MBs (LPM
 // lanes per MB), one unit per wave per iteration; a block strides its four
 // waves over `chunk` consecutive units.  body(c, k, mb, on) runs once per

@@ -590,13 +590,13 @@ __global__ __launch_bounds__(256) void net_flags_kernel(const JobDesc *jobs, int
                                                        unsigned long long *keepw, uint32_t *bcount) {
     __shared__ int wcnt[4];
     const int mb = blockIdx.x * 256 + threadIdx.x;
+    const int wbase = (int)blockIdx.x * 256 + 64 * uni((int)threadIdx.x >> 6);
     bool keep = false;
-    if (mb < total) {
-        const int ji = find_job(jobs, n, mb);
-        const JobDesc &J = jobs[ji];
-        const int k = mb - J.mb_base;
-        keep = J.cls ? J.cls[k] == ME_MB_OPAQUE : true;
-    }
+    if (wbase < total)
+        for_lane_mbs(jobs, n, wbase, min(wbase + 64, total) - 1, [&](const JobCursor &c, int k) {
+            const uint8_t *cls = c.ptr<const uint8_t>(DWI(cls));
+            keep = cls ? ldg8(cls + k) == ME_MB_OPAQUE : true;
+        });
     const unsigned long long bal = __ballot(keep);
     if (lane() == 0) {
         keepw[mb >> 6] = bal;
@@ -610,13 +610,16 @@ __global__ __launch_bounds__(256) void net_scatter_kernel(const JobDesc *jobs, i
                                                          const unsigned long long *keepw, const uint32_t *boff,
                                                          uint32_t *list) {
     const int mb = blockIdx.x * 256 + threadIdx.x;
-    if (mb >= total) return;
-    const unsigned long long bal = keepw[mb >> 6];
-    if (!((bal >> (mb & 63)) & 1ull)) return;
+    const int wbase = (int)blockIdx.x * 256 + 64 * uni((int)threadIdx.x >> 6);
+    if (wbase >= total) return;
+    const unsigned long long bal = keepw[wbase >> 6];
+    if (bal == 0ull) return;  // uniform: nothing kept in this wave
+    const bool keep = mb < total && ((bal >> (mb & 63)) & 1ull);
     uint32_t pos = boff[blockIdx.x] + (uint32_t)__popcll(bal & ((1ull << (mb & 63)) - 1ull));
     for (int w = (blockIdx.x * 256) >> 6; w < (mb >> 6); ++w) pos += (uint32_t)__popcll(keepw[w]);
-    const int ji = find_job(jobs, n, mb);
-    list[pos] = ((uint32_t)ji << 16) | (uint32_t)(mb - jobs[ji].mb_base);
+    for_lane_mbs(jobs, n, wbase, min(wbase + 64, total) - 1, [&](const JobCursor &c, int k) {
+        if (keep) list[pos] = ((uint32_t)c.j << 16) | (uint32_t)k;
+    });
 }
 
 }  // namespace

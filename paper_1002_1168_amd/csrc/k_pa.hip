@@ -519,33 +519,34 @@ __device__ __forceinline__ void store_result(const DescReg &D, int k, uint32_t m
 // neighbour that is transparent in the pair.
 __global__ __launch_bounds__(256) void pa_prepass(const JobDesc *jobs, int n, int total, uint32_t *tmask,
                                                  uint32_t *bmask, int mw, int shape_only, uint32_t *status) {
-    const int l = lane();
-    const int base = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
+    // one MB per lane, 64 consecutive flat MBs per wave; their job (nearly
+    // always one) is a wave-uniform cursor
+    const int base = ((int)blockIdx.x * 4 + uni((int)threadIdx.x >> 6)) * 64;
     if (base >= total) return;
-    const int mb = base + l;
-    int ji = find_job(jobs, n, base);
-    if (mb < total) {
-        ji = next_job(jobs, n, ji, mb);
-        const JobDesc &J = jobs[ji];
-        const int k = mb - J.mb_base;
-        int c = J.cls ? (int)J.cls[k] : ME_MB_OPAQUE;
-        if (c > 2) {
+    for_lane_mbs(jobs, n, base, min(base + 64, total) - 1, [&](const JobCursor &c, int k) {
+        const uint8_t *cls = c.ptr<const uint8_t>(DWI(cls));
+        int cl = cls ? (int)ldg8(cls + k) : ME_MB_OPAQUE;
+        if (cl > 2) {
             atomicOr(status, ST_BAD_CLASS);
-            c = ME_MB_TRANSPARENT;
+            cl = ME_MB_TRANSPARENT;
         }
-        const size_t wi = (size_t)(J.chain_line_base + k) * mw + (J.chain_pos >> 5);
-        const uint32_t bit = 1u << (J.chain_pos & 31);
-        if (c == ME_MB_TRANSPARENT) {
-            ((uint32_t *)J.mv)[k] = 0u;
-            ((uint32_t *)J.mv_int)[k] = 0u;
-            if (J.cost) J.cost[k] = 0u;
-            if (J.iters) J.iters[k] = 0;
-            if (J.points) J.points[k] = 0;
+        const int pos = c.i32(DWI(chain_pos));
+        const size_t wi = (size_t)(c.i32(DWI(chain_line_base)) + k) * mw + (pos >> 5);
+        const uint32_t bit = 1u << (pos & 31);
+        if (cl == ME_MB_TRANSPARENT) {
+            ((g_u32 *)c.ptr<uint32_t>(DWI(mv)))[k] = 0u;
+            ((g_u32 *)c.ptr<uint32_t>(DWI(mv_int)))[k] = 0u;
+            uint32_t *co = c.ptr<uint32_t>(DWI(cost));
+            uint8_t *it = c.ptr<uint8_t>(DWI(iters));
+            uint16_t *pt = c.ptr<uint16_t>(DWI(points));
+            if (co) ((g_u32 *)co)[k] = 0u;
+            if (it) ((g_u8 *)it)[k] = 0;
+            if (pt) ((g_u16 *)pt)[k] = 0;
             atomicOr(tmask + wi, bit);
-        } else if (c == ME_MB_BOUNDARY || shape_only) {
+        } else if (cl == ME_MB_BOUNDARY || shape_only) {
             atomicOr(bmask + wi, bit);
         }
-    }
+    });
 }
 
 // Lines transparent in every pair of their chain need no worker: their

@@ -47,20 +47,18 @@ __device__ __forceinline__ void write_result(const JobDesc &J, int k, int dx, in
 __global__ __launch_bounds__(256) void compact_kernel(const JobDesc *jobs, int n, int total, uint32_t *list,
                                                      uint32_t *count) {
     const int l = lane();
-    const int base = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
+    const int base = ((int)blockIdx.x * 4 + uni((int)threadIdx.x >> 6)) * 64;
     if (base >= total) return;
-    const int mb = base + l;
-    int ji = find_job(jobs, n, base);
     bool searched = false;
-    int k = 0;
-    if (mb < total) {
-        ji = next_job(jobs, n, ji, mb);
-        const JobDesc &J = jobs[ji];
-        k = mb - J.mb_base;
-        const int cls = J.cls ? (int)J.cls[k] : ME_MB_OPAQUE;
-        searched = cls == ME_MB_OPAQUE || cls == ME_MB_BOUNDARY;
-        if (!searched) write_result(J, k, 0, 0, 0u, 0);
-    }
+    int k = 0, ji = 0;
+    for_lane_mbs(jobs, n, base, min(base + 64, total) - 1, [&](const JobCursor &c, int kk) {
+        k = kk;
+        ji = c.j;
+        const uint8_t *cls = c.ptr<const uint8_t>(DWI(cls));
+        const int cl = cls ? (int)ldg8(cls + k) : ME_MB_OPAQUE;
+        searched = cl == ME_MB_OPAQUE || cl == ME_MB_BOUNDARY;
+        if (!searched) write_result(jobs[c.j], k, 0, 0, 0u, 0);
+    });
     const unsigned long long ball = __ballot(searched);
     const int cnt = __popcll(ball);
     uint32_t slot = 0;

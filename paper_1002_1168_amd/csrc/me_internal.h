@@ -169,20 +169,61 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Job of flat MB index `idx` (jobs sorted by mb_base; binary search).
-__device__ __forceinline__ int find_job(const JobDesc *jobs, int n, int idx) {
-    int lo = 0, hi = n - 1;
+#define DWI(f) ((int)(offsetof(JobDesc, f) / 4))
+
+// Wave-uniform job cursor of the flat-MB kernels: the job index, its flat MB
+// range [base, end), and its descriptor one dword per lane (lane l holds
+// dword l of the 40), read out with readlane.
+struct JobCursor {
+    int j, base, end;
+    uint32_t d;
+    __device__ __forceinline__ int i32(int i) const { return __builtin_amdgcn_readlane((int)d, i); }
+    template <class T>
+    __device__ __forceinline__ T *ptr(int i) const {
+        return (T *)(uintptr_t)((unsigned long long)(uint32_t)i32(i) | ((unsigned long long)(uint32_t)i32(i + 1) << 32));
+    }
+};
+
+// Last job in [lo, n) whose mb_base <= idx, given jobs[lo].mb_base <= idx
+// (mb_base is the running sum of the jobs' MB counts).  Each round every
+// lane reads one candidate's mb_base and a ballot narrows the range 64-fold:
+// one round for up to 64 jobs, two for up to 4096.
+__device__ __forceinline__ int seek_job(const JobDesc *jobs, int lo, int n, int idx) {
+    int hi = n - 1;
     while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].mb_base <= idx) lo = mid; else hi = mid - 1;
+        const int step = (hi - lo + 64) >> 6;
+        const int c = lo + lane() * step;
+        const bool ok = c <= hi && *(const __attribute__((address_space(1))) int32_t *)&jobs[c].mb_base <= idx;
+        const unsigned long long b = __ballot(ok);
+        lo += (63 - __builtin_clzll(b)) * step;
+        hi = min(hi, lo + step - 1);
     }
     return lo;
 }
 
-// Advance the job cursor `ji` to the job holding flat MB `mb` (mb only grows).
-__device__ __forceinline__ int next_job(const JobDesc *jobs, int n, int ji, int mb) {
-    while (ji + 1 < n && jobs[ji + 1].mb_base <= mb) ++ji;
-    return ji;
+// Move the cursor to the job of flat MB idx (idx never decreases).
+__device__ __forceinline__ void seek(JobCursor &c, const JobDesc *jobs, int n, int idx) {
+    if (idx < c.end) return;
+    c.j = seek_job(jobs, c.j + 1, n, idx);
+    c.d = ldg32((const uint32_t *)(jobs + c.j) + min(lane(), 39));
+    c.base = c.i32(DWI(mb_base));
+    c.end = c.base + c.i32(DWI(wm)) * c.i32(DWI(hm));
+}
+
+// One flat MB per lane, the wave's 64 consecutive MBs [base, last]: calls
+// f(c, k) in the lanes whose MB belongs to the cursor's job c (k = its index
+// within the job), once per job the range touches.  f runs in a subset of
+// the lanes: no wave-level operations inside it.
+template <class F>
+__device__ __forceinline__ void for_lane_mbs(const JobDesc *jobs, int n, int base, int last, F &&f) {
+    const int mb = base + lane();
+    JobCursor c{-1, 0, 0, 0u};
+    seek(c, jobs, n, base);
+    for (;;) {
+        if (mb <= last && mb >= c.base && mb < c.end) f(c, mb - c.base);
+        if (last < c.end) break;
+        seek(c, jobs, n, c.end);
+    }
 }
 
 __device__ __forceinline__ int iclamp(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
