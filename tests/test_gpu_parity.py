@@ -111,6 +111,32 @@ def test_pa_single_mb_and_empty_masks(torch_cuda):
     check_pa(seq, [0, None], me.me_default_params(search_range=2), 2, label="single-mb")
 
 
+def test_pa_bad_class_raises_status(torch_cuda):
+    """A class byte outside 0..2 sets the device status word (ME_EDEVICE on
+    the next status read, which clears it); that MB is given the transparent
+    result and the other MBs of the pair are still solved."""
+    import torch
+    from paper_1002_1168_amd import device as dv
+    seq = synth.qcif_ellipse(frames=3)
+    say("pa bad class", seq.name)
+    ds = dseq(seq)
+    gpu_classify(ds)
+    cls = ds.cls[0, 1]
+    opaque = (cls == me.ME_MB_OPAQUE).nonzero()
+    v, h = (int(x) for x in opaque[len(opaque) // 2])
+    cls[v, h] = 7
+    out = dv.Outputs.alloc(2, ds.hm, ds.wm)
+    s = dv.stream_handle()
+    me.me_texture_recursive(ds.pair_jobs(0, out, 2), me.me_default_params(search_range=7), None, stream=s)
+    torch.cuda.synchronize()
+    assert me.me_device_status(s) == me.ME_EDEVICE
+    assert me.me_device_status(s) == me.ME_OK
+    got = out.host()
+    assert (got["mv"][0][v, h] == 0).all() and (got["mv_int"][0][v, h] == 0).all()
+    assert got["cost"][0][v, h] == 0 and got["iters"][0][v, h] == 0 and got["points"][0][v, h] == 0
+    assert (got["points"][0][cls.cpu().numpy() == me.ME_MB_OPAQUE] > 0).all()
+
+
 def test_pa_max_width(torch_cuda):
     seq = synth.random_frames(6, 4096, 32, frames=3, vops=0, search_range=16)
     check_pa(seq, [None], me.me_default_params(search_range=16), 2, label="w4096")
