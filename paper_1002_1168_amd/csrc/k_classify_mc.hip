@@ -1,9 +1,9 @@
 // MB classification from the binary alpha plane (Section 1) and motion
 // compensation + squared error (Section 4).  Both stream each pixel once and
-// are bound by the memory system.  Layout: a few lanes per MB (four for classification,
-// eight for MC), each lane whole 16-pixel rows, per-MB sums DPP reductions
-// over those lanes (no atomics); the job of a wave's MBs is a wave-uniform
-// cursor, so descriptor fields live in scalar registers.
+// are bound by the memory system.  Layout: a few lanes per MB (four for
+// classification, eight for MC), each lane whole 16-pixel rows, per-MB sums
+// DPP reductions over those lanes (no atomics); the job of a wave's MBs is a
+// wave-uniform cursor, so descriptor fields live in scalar registers.
 #include "me_internal.h"
 
 namespace me {

@@ -365,6 +365,27 @@ def test_kernel_timing_counts_each_launch(torch_cuda):
     assert me.me_kernel_time_ms(me.ME_KT_SEARCH, s) == (0.0, 0)
 
 
+def test_kernel_timing_selected_kinds_only(torch_cuda):
+    """With ME_KT_ONLY bits only the selected call kinds record events."""
+    seq = synth.qcif_ellipse(seed=1, frames=3)
+    p = me.me_default_params(search_range=7)
+    ds = dseq(seq)
+    from paper_1002_1168_amd.device import stream_handle
+    s = stream_handle()
+    me.me_kernel_timing(True, kinds=[me.ME_KT_SEARCH])
+    try:
+        for k in (me.ME_KT_CLASSIFY, me.ME_KT_SEARCH):
+            me.me_kernel_time_ms(k, s)
+        gpu_classify(ds)
+        gpu_pa(ds, [0], p, 2)
+        cls_total, cls_count = me.me_kernel_time_ms(me.ME_KT_CLASSIFY, s)
+        total, count = me.me_kernel_time_ms(me.ME_KT_SEARCH, s)
+    finally:
+        me.me_kernel_timing(False)
+    assert (cls_total, cls_count) == (0.0, 0)
+    assert count == 1 and total > 0.0
+
+
 @pytest.mark.parametrize("maker,S", [("qcif", 7), ("cif", 16)])
 def test_pa_seeded_start_parity(torch_cuda, maker, S):
     """Learned-seed start with the 5 % fallback (seeds = random vectors,
