@@ -254,6 +254,46 @@ def test_mc_psnr_parity(torch_cuda, half):
             np.testing.assert_array_equal(preds[i].cpu().numpy(), wp)
 
 
+def test_classify_mc_five_thousand_one_mb_jobs(torch_cuda):
+    """5,000 one-MB frames (16x16 windows of one wide plane): finding a
+    unit's job takes three 64-way rounds, and every unit spans 8 or 16 jobs."""
+    import torch
+    from paper_1002_1168_amd import device as dv
+    rng = np.random.default_rng(7)
+    n = 5000
+    say("classify+mc 5000 one-MB jobs")
+    W = 16 * n
+    cur = rng.integers(0, 256, size=(16, W), dtype=np.uint8)
+    ref = rng.integers(0, 256, size=(16, W), dtype=np.uint8)
+    alpha = (rng.random((16, W)) < 0.6).astype(np.uint8) * 255
+    alpha[:, 16 * np.arange(0, n, 5)[:, None] + np.arange(16)] = 0      # some transparent MBs
+    alpha[:, 16 * np.arange(1, n, 5)[:, None] + np.arange(16)] = 255    # some opaque MBs
+    mv = rng.integers(-6, 7, size=(n, 1, 1, 2)).astype(np.int16)
+    tc, tr, ta = (torch.from_numpy(x).cuda() for x in (cur, ref, alpha))
+    tmv = torch.from_numpy(mv).cuda()
+    cls = torch.full((n, 1, 1), 9, dtype=torch.uint8, device="cuda")
+    bab = torch.zeros((n, 8), dtype=torch.int32, device="cuda")
+    pred = torch.zeros((16, W), dtype=torch.uint8, device="cuda")
+    win = lambda t, i: t[:, 16 * i:16 * i + 16]
+    s = dv.stream_handle()
+    me.me_classify_babs([dv.frame(win(tc, i), win(ta, i)) for i in range(n)], [cls[i].data_ptr() for i in range(n)],
+                        [bab[i].data_ptr() for i in range(n)], stream=s)
+    jobs = [dv.mc_job(win(tc, i), win(tr, i), win(ta, i), cls[i], tmv[i]) for i in range(n)]
+    sse, npx, ps, rc = me.me_motion_compensate_psnr(jobs, [win(pred, i).data_ptr() for i in range(n)], stream=s,
+                                                    check=False)
+    torch.cuda.synchronize()
+    assert rc == me.ME_EEMPTY
+    gc, gb, gp = cls.cpu().numpy(), bab.cpu().numpy().view(np.uint32), pred.cpu().numpy()
+    for i in range(n):
+        sl = slice(16 * i, 16 * i + 16)
+        c, b = oracle.classify(np.ascontiguousarray(alpha[:, sl]))
+        assert gc[i, 0, 0] == c[0, 0] and (gb[i] == b[0, 0]).all(), f"job {i}"
+        ws, wn, wp = oracle.mc_sse(np.ascontiguousarray(cur[:, sl]), np.ascontiguousarray(ref[:, sl]), mv[i],
+                                   np.ascontiguousarray(alpha[:, sl]), c, want_pred=True)
+        assert (sse[i], npx[i]) == (ws, wn), f"job {i}"
+        np.testing.assert_array_equal(gp[:, sl], wp, err_msg=f"job {i}")
+
+
 def test_mc_empty_mask_reports_eempty(torch_cuda):
     import torch
     from paper_1002_1168_amd import device as dv
