@@ -549,6 +549,33 @@ __global__ __launch_bounds__(256) void pa_prepass(const JobDesc *jobs, int n, in
     });
 }
 
+// Line of ticket tk, and whether it is transparent in every pair of its
+// chain (its mask bits of pairs 0 .. len-1 all set).  The mask words are
+// read four at a time (in-range loads past the last word are ignored), so a
+// transparent line costs one round trip per four words, not per word.
+__device__ __forceinline__ bool line_all_transparent(const ChainDesc *chains, uint32_t tk, const uint32_t *tmask,
+                                                     int mw, int &line, int &len) {
+    const ChainDesc ch = chains[tk >> 16];
+    line = ch.line_base + (int)((tk >> 8) & 0xFF) * ch.wm + (int)(tk & 0xFF);
+    len = ch.len;
+    const uint32_t *m = tmask + (size_t)line * mw;
+    const int nw = min(mw, (ch.len + 31) >> 5);
+    for (int w0 = 0; w0 < nw; w0 += 4) {
+        uint32_t word[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) word[d] = m[min(w0 + d, nw - 1)];
+        bool ok = true;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const int bits = min(32, ch.len - 32 * (w0 + d));
+            const uint32_t full = bits >= 32 ? 0xFFFFFFFFu : bits > 0 ? ((1u << bits) - 1u) : 0u;
+            ok = ok && (w0 + d >= nw || (word[d] & full) == full);
+        }
+        if (!ok) return false;
+    }
+    return true;
+}
+
 // Lines transparent in every pair of their chain need no worker: their
 // final progress word (all pairs done, zero vector) is stored here and they
 // leave the ticket list; the others keep their ticket order (an order-
@@ -561,17 +588,9 @@ __global__ __launch_bounds__(256) void pa_line_flags(const ChainDesc *chains, co
     const int t = blockIdx.x * 256 + threadIdx.x;
     bool keep = false;
     if (t < nlines) {
-        const uint32_t tk = tickets[t];
-        const ChainDesc ch = chains[tk >> 16];
-        const int line = ch.line_base + (int)((tk >> 8) & 0xFF) * ch.wm + (int)(tk & 0xFF);
-        const uint32_t *m = tmask + (size_t)line * mw;
-        bool all = true;
-        for (int w = 0; w < mw && all; ++w) {
-            const int bits = min(32, ch.len - 32 * w);
-            const uint32_t full = bits >= 32 ? 0xFFFFFFFFu : ((1u << bits) - 1u);
-            all = (m[w] & full) == full;
-        }
-        if (all) progress[line] = (unsigned long long)(uint32_t)ch.len << 48;
+        int line = 0, len = 0;
+        const bool all = line_all_transparent(chains, tickets[t], tmask, mw, line, len);
+        if (all) progress[line] = (unsigned long long)(uint32_t)len << 48;
         keep = !all;
     }
     const unsigned long long bal = __ballot(keep);
@@ -581,6 +600,43 @@ __global__ __launch_bounds__(256) void pa_line_flags(const ChainDesc *chains, co
     }
     __syncthreads();
     if (threadIdx.x == 0) bcount[blockIdx.x] = (uint32_t)(wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3]);
+}
+
+// The same flags and order-preserving compaction in one workgroup, for at
+// most kCompactOneBlock lines: chunks of 1024 tickets, one per thread, a
+// scan of the keep flags in LDS gives each kept ticket its output slot after
+// the earlier chunks' total.
+constexpr int kCompactOneBlock = 4096;
+__global__ __launch_bounds__(1024) void pa_compact_lines(const ChainDesc *chains, const uint32_t *tickets, int nlines,
+                                                        const uint32_t *tmask, int mw, unsigned long long *progress,
+                                                        uint32_t *out, uint32_t *nactive) {
+    __shared__ uint32_t sh[1024];
+    const int tid = threadIdx.x;
+    uint32_t carry = 0u;
+    for (int base = 0; base < nlines; base += 1024) {
+        const int t = base + tid;
+        uint32_t tk = 0u, keep = 0u;
+        if (t < nlines) {
+            tk = tickets[t];
+            int line = 0, len = 0;
+            if (line_all_transparent(chains, tk, tmask, mw, line, len))
+                progress[line] = (unsigned long long)(uint32_t)len << 48;
+            else
+                keep = 1u;
+        }
+        sh[tid] = keep;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint32_t x = tid >= off ? sh[tid - off] : 0u;
+            __syncthreads();
+            sh[tid] += x;
+            __syncthreads();
+        }
+        if (keep) out[carry + sh[tid] - 1u] = tk;  // exclusive prefix = inclusive - 1
+        carry += sh[1023];
+        __syncthreads();
+    }
+    if (tid == 0) *nactive = carry;
 }
 
 // Exclusive scan of the nb block counts in place; the total to *nactive.
@@ -1369,10 +1425,15 @@ hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainD
     unsigned long long *keepw = (unsigned long long *)(scratch + 256);
     uint32_t *bcount = (uint32_t *)((uint8_t *)keepw + (((size_t)nb * 32 + 255) & ~(size_t)255));
     uint32_t *active = (uint32_t *)((uint8_t *)bcount + (((size_t)nb * 4 + 255) & ~(size_t)255));
-    hipLaunchKernelGGL(pa_line_flags, dim3(nb), dim3(256), 0, s, chains, tickets, nlines, tmask, mask_words, progress,
-                       keepw, bcount);
-    hipLaunchKernelGGL(pa_scan_counts, dim3(1), dim3(1024), 0, s, bcount, nb, nactive);
-    hipLaunchKernelGGL(pa_scatter_tickets, dim3(nb), dim3(256), 0, s, tickets, nlines, keepw, bcount, active);
+    if (nlines <= kCompactOneBlock) {
+        hipLaunchKernelGGL(pa_compact_lines, dim3(1), dim3(1024), 0, s, chains, tickets, nlines, tmask, mask_words,
+                           progress, active, nactive);
+    } else {
+        hipLaunchKernelGGL(pa_line_flags, dim3(nb), dim3(256), 0, s, chains, tickets, nlines, tmask, mask_words,
+                           progress, keepw, bcount);
+        hipLaunchKernelGGL(pa_scan_counts, dim3(1), dim3(1024), 0, s, bcount, nb, nactive);
+        hipLaunchKernelGGL(pa_scatter_tickets, dim3(nb), dim3(256), 0, s, tickets, nlines, keepw, bcount, active);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int rows = 2 * kp.S + 18;
