@@ -10,10 +10,20 @@ namespace me {
 
 namespace {
 
-__global__ __launch_bounds__(64) void fill_u32_kernel(uint32_t *p, size_t n, uint32_t v) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) p[i] = v;
+// n words of value v from p: 16-byte stores over the whole quads when p is
+// 16-byte aligned, single words for the rest.
+__global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *p, size_t n, uint32_t v) {
+    const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t done = 0;
+    if (((uintptr_t)p & 15u) == 0) {
+        typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+        u32x4v *q = (u32x4v *)p;
+        const size_t nq = n / 4;
+        for (size_t i = i0; i < nq; i += stride) q[i] = u32x4v{v, v, v, v};
+        done = nq * 4;
+    }
+    for (size_t i = done + i0; i < n; i += stride) p[i] = v;
 }
 
 // bit i set where byte i of the 4 words (16 bytes) is non-zero
@@ -265,13 +275,13 @@ __global__ __launch_bounds__(256) void mc_reduce_kernel(const JobDesc *jobs, con
 
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    size_t blocks = (n + 63) / 64;
+    size_t blocks = (n + 1023) / 1024;  // about four words per thread
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(64), 0, s, p, n, v);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 
-// Units (MBs, or quads of MBs) per block so that a flat grid has about
+// Units (runs of consecutive MBs) per block so that a flat grid has about
 // per_cu blocks per CU.
 int flat_chunk(int total_units, int per_cu) {
     int dev = 0, cus = 256;
