@@ -128,19 +128,19 @@ class Workload:
 
 
 class SumsRing:
-    """Per-job (SSE, pixel count) sums of two frame steps: device buffers
-    written by me_motion_compensate_sse, copied to pinned host memory on the
-    same stream, so that one step's PSNR is read while the next step runs."""
+    """Per-job (SSE, pixel count) sums of two frame steps, written by
+    me_motion_compensate_sse straight into pinned host memory, so that one
+    step's PSNR is read while the next step runs (no copy kernel)."""
 
     def __init__(self, torch, me, n):
         self.me = me
-        self.dev = [torch.zeros(2 * n, dtype=torch.int64, device="cuda") for _ in range(2)]
         self.host = [torch.zeros(2 * n, dtype=torch.int64, pin_memory=True) for _ in range(2)]
         self.ev = [torch.cuda.Event() for _ in range(2)]
 
     def queue(self, jobs, slot, stream):
-        self.me.me_motion_compensate_sse(jobs, self.dev[slot].data_ptr(), stream=stream)
-        self.host[slot].copy_(self.dev[slot], non_blocking=True)
+        """MC/SSE of `jobs` on `stream`, which must be torch's current stream
+        (the event follows it there)."""
+        self.me.me_motion_compensate_sse(jobs, self.host[slot].data_ptr(), stream=stream)
         self.ev[slot].record()
 
     def result(self, slot):

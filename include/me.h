@@ -205,10 +205,13 @@ int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, u
  * them, and the call returns once the work is queued, so a caller can queue
  * the next frame step before reading these results.
  *  pred     as in me_motion_compensate_psnr.
- *  sums     device array of 2n uint64 (8-byte aligned, ME_EALIGN otherwise),
- *           owned by the caller: sums[2i] = SSE of job i, sums[2i+1] = its
- *           pixel count over the VOP (0 for a job without VOP pixels; no
- *           ME_EEMPTY here).  PSNR = 10 log10(255^2 npix / sse).
+ *  sums     2n uint64 in device-accessible memory: device memory, or pinned
+ *           host memory from hipHostMalloc (then readable on the host once
+ *           the stream has passed this call, with no copy); 8-byte aligned
+ *           (ME_EALIGN otherwise); owned by the caller.  sums[2i] = SSE of
+ *           job i, sums[2i+1] = its pixel count over the VOP (0 for a job
+ *           without VOP pixels; no ME_EEMPTY here).
+ *           PSNR = 10 log10(255^2 npix / sse).
  * Errors are those of me_motion_compensate_psnr found on the host; the jobs
  * array may be reused on return.
  */

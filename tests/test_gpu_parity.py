@@ -357,6 +357,12 @@ def test_classify_mc_many_small_jobs(torch_cuda, seed):
     torch.cuda.synchronize()
     got = sums.cpu().numpy().view(np.uint64)
     assert [int(x) for x in got[0::2]] == list(sse) and [int(x) for x in got[1::2]] == list(npx)
+    # ... or in pinned host memory, readable once the stream has passed it
+    hsums = torch.full((2 * n,), -1, dtype=torch.int64, pin_memory=True)
+    assert me.me_motion_compensate_sse(jobs, hsums.data_ptr(), stream=s) == me.ME_OK
+    torch.cuda.synchronize()
+    got = hsums.numpy().view(np.uint64)
+    assert [int(x) for x in got[0::2]] == list(sse) and [int(x) for x in got[1::2]] == list(npx)
 
 
 # ------------------------------------------- full size, repeated launches
