@@ -184,16 +184,21 @@ __device__ __forceinline__ void predict_rows2(const uint8_t *ref, int st, int W,
     bilinear_row(r[1], r[2], fx, fy, p1);
 }
 
-// Squared error of one 16-pixel row over the pixels whose alpha is set.
+// Squared error of one 16-pixel row over the pixels whose alpha is set: with
+// c, p masked to those bytes (mask bit i -> byte i all ones), the sum of
+// (c - p)^2 is c.c + p.p - 2 c.p, each a 4-byte dot product, exact in 32 bits.
 __device__ __forceinline__ int row_sse(const u32x4 cur, const uint32_t (&p)[4], uint32_t in) {
     const uint32_t c[4] = {cur.x, cur.y, cur.z, cur.w};
-    int sse = 0;
+    uint32_t sq = 0u, cross = 0u;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int d = byte_of(c[i >> 2], i & 3) - byte_of(p[i >> 2], i & 3);
-        sse += ((in >> i) & 1u) ? d * d : 0;
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t m = (((in >> (4 * w)) & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
+        const uint32_t cm = c[w] & m, pm = p[w] & m;
+        sq = __builtin_amdgcn_udot4(cm, cm, sq, false);
+        sq = __builtin_amdgcn_udot4(pm, pm, sq, false);
+        cross = __builtin_amdgcn_udot4(cm, pm, cross, false);
     }
-    return sse;
+    return (int)(sq - 2u * cross);
 }
 
 // Prediction of MB k by its half-pel vector (transparent: zero vector),
