@@ -74,7 +74,9 @@ typedef struct me_params {
     int32_t theta;        /* Theta of Eq. 4, 1..127 (default 3: "two or three") */
     int32_t eps_q12;      /* convergence factor epsilon of Eq. 3 in Q.12, 0..65536 (default 4096 = 1.0) */
     int32_t max_step;     /* largest per-axis pel-recursion step, 1..S (default 1: one of eight neighbours) */
-    int32_t k_max;        /* cap on pel-recursion candidates per MB, 0..255 (default 8) */
+    int32_t k_max;        /* cap on pel-recursion candidates per MB, 0..255 (default 8); at most 127
+                             when any job carries seeds (a dropped seed counts both recursions, and
+                             `iters` is a byte), ME_EINVAL otherwise */
     int32_t half_pel;     /* 1: half-sample refinement of texture MBs after the recursion (Section 4) */
     uint32_t flags;       /* reserved, must be 0 */
 } me_params;
@@ -301,6 +303,22 @@ void me_batch_destroy(me_batch *b);
 #define ME_KT_ONLY(kind) (2 << (kind))
 int me_kernel_timing(int on);
 int me_kernel_time_ms(int kind, void *stream, double *total_ms, int *count);
+
+/*
+ * Schedule of the pipelined search (host only, no device access): the order
+ * in which me_texture_recursive / me_shape_search hand out MB "lines" (one MB
+ * position of one chain of frame pairs, a chain being pairs linked by their
+ * t_field) to the device workers.  The search needs this order to be
+ * topological over the dependencies of Fig. 1 (A, B, C of the same pair, T of
+ * the producing pair); it is exposed so that this can be checked.
+ *  job_info  host, 3n: per job its chain, its position in the chain, and the
+ *            index of the job whose mv_int is its t_field (-1: none).
+ *  lines     host, cap entries: line i = chain << 16 | v << 8 | h, in order.
+ *  *nlines   number of lines (also written when cap is too small, which
+ *            returns ME_EINVAL).
+ * Job validation and errors as me_texture_recursive.
+ */
+int me_search_schedule(const me_job *jobs, int n, int32_t *job_info, uint32_t *lines, int cap, int *nlines);
 
 /* Wait for `stream`, then read and clear its device status word:
  * ME_OK, or ME_EDEVICE when a kernel reported a fault condition. */

@@ -89,6 +89,9 @@ def lib():
         L.or_pa.argtypes = [C.POINTER(_Pair), vp, vp, vp, C.POINTER(_Params), i,
                             vp, vp, vp, vp, vp]
         L.or_pa.restype = i
+        L.or_pa_order.argtypes = [C.POINTER(_Pair), vp, vp, vp, C.POINTER(_Params), i, vp,
+                                  vp, vp, vp, vp, vp]
+        L.or_pa_order.restype = i
         L.or_search.argtypes = [i, C.POINTER(_Pair), vp, C.POINTER(_Params), vp, vp, vp, vp]
         L.or_search.restype = i
         L.or_mc_sse.argtypes = [C.POINTER(_Pair), vp, vp, vp,
@@ -178,6 +181,28 @@ def pa(cur, ref, params: Params, cur_alpha=None, ref_alpha=None, cls=None, t_fie
                      _ptr(out["iters"]), _ptr(out["points"]))
     if rc:
         raise ValueError("or_pa rejected its arguments")
+    return out
+
+
+def pa_order(cur, ref, params: Params, order, cur_alpha=None, ref_alpha=None, cls=None, t_field=None,
+             seed=None, shape_only=False):
+    """The proposed algorithm with the MBs visited in ``order`` (flat MB
+    indices, each once) instead of the raster scan."""
+    p, keep = _pair(cur, ref, cur_alpha, ref_alpha)
+    H, W = keep[0].shape
+    out = _outputs(H, W)
+    cls = _u8(cls)
+    tf = None if t_field is None else np.ascontiguousarray(t_field, dtype=np.int16)
+    sd = None if seed is None else np.ascontiguousarray(seed, dtype=np.int16)
+    od = np.ascontiguousarray(order, dtype=np.int32)
+    if od.shape != ((H // 16) * (W // 16),):
+        raise ValueError("order must list every MB once")
+    prm = params._c()
+    rc = lib().or_pa_order(C.byref(p), _ptr(cls), _ptr(tf), _ptr(sd), C.byref(prm), int(shape_only), _ptr(od),
+                           _ptr(out["mv"]), _ptr(out["mv_int"]), _ptr(out["cost"]),
+                           _ptr(out["iters"]), _ptr(out["points"]))
+    if rc:
+        raise ValueError("or_pa_order rejected its arguments")
     return out
 
 

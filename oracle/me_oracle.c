@@ -262,131 +262,170 @@ static const int HALF_OFFS[8][2] = {{-1, -1}, {0, -1}, {1, -1}, {-1, 0}, {1, 0},
 
 /* ----------------------------------------------- the proposed algorithm */
 /*
- * Fig. 1 for one frame pair of one VOP.  `cls` from or_classify on the
- * current alpha (NULL: every MB opaque).  `t_field` is the previous pair's
- * full-pel field (half-pel units; NULL: zeros).  `seed` (NULL: plain method)
- * is a learned per-MB starting vector for texture MBs.  `shape_only`
- * scores every non-transparent MB on its alpha block.
+ * Fig. 1 for one MB (h, v) of one frame pair of one VOP: the candidates come
+ * from the vectors already in `mv_int` (left, upper, upper-right neighbours)
+ * and from `t_field`.
+ */
+static int pa_mb(const or_pair *fp, const uint8_t *cls, const int16_t *t_field, const int16_t *seed,
+                 const or_params *p, int shape_only, int h, int v, int16_t *mv, int16_t *mv_int, uint32_t *cost,
+                 uint8_t *iters, uint16_t *points) {
+    int has_alpha = fp->cur_alpha != NULL && fp->ref_alpha != NULL;
+    int wm = fp->width / 16;
+    int S = p->search_range;
+    int k = v * wm + h;
+    int c = cls ? cls[k] : OR_OPAQUE;
+    int x0 = 16 * h, y0 = 16 * v;
+    if (c == OR_TRANSPARENT) { /* no vector is computed */
+        mv[2 * k] = mv[2 * k + 1] = 0;
+        mv_int[2 * k] = mv_int[2 * k + 1] = 0;
+        if (cost) cost[k] = 0;
+        if (iters) iters[k] = 0;
+        if (points) points[k] = 0;
+        return 0;
+    }
+    int shape = shape_only || c == OR_BOUNDARY;
+    if (shape && !has_alpha) return -1;
+    /* candidates A (left), B (up), C (up-right), T (same MB, previous
+     * pair); neighbours outside the MB grid contribute (0, 0) */
+    int cand[4][2];
+    cand[0][0] = h > 0 ? half_to_full(mv_int[2 * (k - 1)]) : 0;
+    cand[0][1] = h > 0 ? half_to_full(mv_int[2 * (k - 1) + 1]) : 0;
+    cand[1][0] = v > 0 ? half_to_full(mv_int[2 * (k - wm)]) : 0;
+    cand[1][1] = v > 0 ? half_to_full(mv_int[2 * (k - wm) + 1]) : 0;
+    cand[2][0] = (v > 0 && h + 1 < wm) ? half_to_full(mv_int[2 * (k - wm + 1)]) : 0;
+    cand[2][1] = (v > 0 && h + 1 < wm) ? half_to_full(mv_int[2 * (k - wm + 1) + 1]) : 0;
+    cand[3][0] = t_field ? half_to_full(t_field[2 * k]) : 0;
+    cand[3][1] = t_field ? half_to_full(t_field[2 * k + 1]) : 0;
+    /* admissible, distinct, in order A, B, C, T */
+    int list[4][2], n = 0;
+    for (int i = 0; i < 4; ++i) {
+        if (!feasible(fp, S, x0, y0, cand[i][0], cand[i][1])) continue;
+        int dup = 0;
+        for (int q = 0; q < n; ++q)
+            if (list[q][0] == cand[i][0] && list[q][1] == cand[i][1]) dup = 1;
+        if (!dup) {
+            list[n][0] = cand[i][0];
+            list[n][1] = cand[i][1];
+            ++n;
+        }
+    }
+    if (n == 0) {
+        list[0][0] = list[0][1] = 0;
+        n = 1;
+    }
+    /* Min[...] keeps the first minimum (MATLAB min semantics) */
+    int bx = list[0][0], by = list[0][1];
+    uint32_t bc = block_cost(fp, shape, x0, y0, bx, by);
+    for (int i = 1; i < n; ++i) {
+        uint32_t ci = block_cost(fp, shape, x0, y0, list[i][0], list[i][1]);
+        if (ci < bc) {
+            bc = ci;
+            bx = list[i][0];
+            by = list[i][1];
+        }
+    }
+    int pts = n, its = 0;
+    int dx = bx, dy = by;
+    uint32_t dc = bc;
+    if (seed && !shape) {
+        /* learned start: clamp into the admissible window, refine,
+         * and fall back to the plain recursion when the refined
+         * distortion exceeds the BRS minimum by more than 5 % */
+        int lox = imax(-S, -x0), hix = imin(S, fp->width - 16 - x0);
+        int loy = imax(-S, -y0), hiy = imin(S, fp->height - 16 - y0);
+        int sx = iclamp(half_to_full(seed[2 * k]), lox, hix);
+        int sy = iclamp(half_to_full(seed[2 * k + 1]), loy, hiy);
+        uint32_t sc = block_cost(fp, shape, x0, y0, sx, sy);
+        pts += 1;
+        int it1 = pel_recursion(fp, p, shape, x0, y0, &sx, &sy, &sc);
+        its += it1;
+        pts += it1;
+        if ((uint64_t)20 * sc > (uint64_t)21 * bc) {
+            int it2 = pel_recursion(fp, p, shape, x0, y0, &dx, &dy, &dc);
+            its += it2;
+            pts += it2;
+        } else {
+            dx = sx;
+            dy = sy;
+            dc = sc;
+        }
+    } else {
+        int it1 = pel_recursion(fp, p, shape, x0, y0, &dx, &dy, &dc);
+        its += it1;
+        pts += it1;
+    }
+    int hx = 2 * dx, hy = 2 * dy;
+    if (p->half_pel && !shape) {
+        int bhx = hx, bhy = hy;
+        uint32_t hc = dc;
+        for (int o = 0; o < 8; ++o) {
+            int qx = hx + HALF_OFFS[o][0], qy = hy + HALF_OFFS[o][1];
+            if (!half_feasible(fp, S, x0, y0, qx, qy)) continue;
+            ++pts;
+            uint32_t c2 = or_sad_half(fp, x0, y0, qx, qy);
+            if (c2 < hc) {
+                hc = c2;
+                bhx = qx;
+                bhy = qy;
+            }
+        }
+        hx = bhx;
+        hy = bhy;
+        dc = hc;
+    }
+    mv[2 * k] = (int16_t)hx;
+    mv[2 * k + 1] = (int16_t)hy;
+    mv_int[2 * k] = (int16_t)(2 * dx);
+    mv_int[2 * k + 1] = (int16_t)(2 * dy);
+    if (cost) cost[k] = dc;
+    if (iters) iters[k] = (uint8_t)its;
+    if (points) points[k] = (uint16_t)pts;
+    return 0;
+}
+
+static int pa_args_ok(const or_pair *fp, const int16_t *seed, const or_params *p, int shape_only, const int16_t *mv,
+                      const int16_t *mv_int) {
+    if (!fp || !p || !mv || !mv_int) return 0;
+    if (fp->width % 16 || fp->height % 16 || fp->width <= 0 || fp->height <= 0) return 0;
+    if (shape_only && !(fp->cur_alpha != NULL && fp->ref_alpha != NULL)) return 0;
+    /* a dropped seed counts both recursions (up to 2 k_max) in a byte */
+    if (seed && p->k_max > 127) return 0;
+    return 1;
+}
+
+/*
+ * Fig. 1 for one frame pair of one VOP, MBs in raster order.  `cls` from
+ * or_classify on the current alpha (NULL: every MB opaque).  `t_field` is the
+ * previous pair's full-pel field (half-pel units; NULL: zeros).  `seed` (NULL:
+ * plain method) is a learned per-MB starting vector for texture MBs.
+ * `shape_only` scores every non-transparent MB on its alpha block.
  */
 int or_pa(const or_pair *fp, const uint8_t *cls, const int16_t *t_field, const int16_t *seed, const or_params *p,
           int shape_only, int16_t *mv, int16_t *mv_int, uint32_t *cost, uint8_t *iters, uint16_t *points) {
-    if (!fp || !p || !mv || !mv_int) return -1;
-    if (fp->width % 16 || fp->height % 16 || fp->width <= 0 || fp->height <= 0) return -1;
-    int has_alpha = fp->cur_alpha != NULL && fp->ref_alpha != NULL;
-    if (shape_only && !has_alpha) return -1;
+    if (!pa_args_ok(fp, seed, p, shape_only, mv, mv_int)) return -1;
     int wm = fp->width / 16, hm = fp->height / 16;
-    int S = p->search_range;
-    for (int v = 0; v < hm; ++v) {
-        for (int h = 0; h < wm; ++h) {
-            int k = v * wm + h;
-            int c = cls ? cls[k] : OR_OPAQUE;
-            int x0 = 16 * h, y0 = 16 * v;
-            if (c == OR_TRANSPARENT) { /* no vector is computed */
-                mv[2 * k] = mv[2 * k + 1] = 0;
-                mv_int[2 * k] = mv_int[2 * k + 1] = 0;
-                if (cost) cost[k] = 0;
-                if (iters) iters[k] = 0;
-                if (points) points[k] = 0;
-                continue;
-            }
-            int shape = shape_only || c == OR_BOUNDARY;
-            if (shape && !has_alpha) return -1;
-            /* candidates A (left), B (up), C (up-right), T (same MB, previous
-             * pair); neighbours outside the MB grid contribute (0, 0) */
-            int cand[4][2];
-            cand[0][0] = h > 0 ? half_to_full(mv_int[2 * (k - 1)]) : 0;
-            cand[0][1] = h > 0 ? half_to_full(mv_int[2 * (k - 1) + 1]) : 0;
-            cand[1][0] = v > 0 ? half_to_full(mv_int[2 * (k - wm)]) : 0;
-            cand[1][1] = v > 0 ? half_to_full(mv_int[2 * (k - wm) + 1]) : 0;
-            cand[2][0] = (v > 0 && h + 1 < wm) ? half_to_full(mv_int[2 * (k - wm + 1)]) : 0;
-            cand[2][1] = (v > 0 && h + 1 < wm) ? half_to_full(mv_int[2 * (k - wm + 1) + 1]) : 0;
-            cand[3][0] = t_field ? half_to_full(t_field[2 * k]) : 0;
-            cand[3][1] = t_field ? half_to_full(t_field[2 * k + 1]) : 0;
-            /* admissible, distinct, in order A, B, C, T */
-            int list[4][2], n = 0;
-            for (int i = 0; i < 4; ++i) {
-                if (!feasible(fp, S, x0, y0, cand[i][0], cand[i][1])) continue;
-                int dup = 0;
-                for (int q = 0; q < n; ++q)
-                    if (list[q][0] == cand[i][0] && list[q][1] == cand[i][1]) dup = 1;
-                if (!dup) {
-                    list[n][0] = cand[i][0];
-                    list[n][1] = cand[i][1];
-                    ++n;
-                }
-            }
-            if (n == 0) {
-                list[0][0] = list[0][1] = 0;
-                n = 1;
-            }
-            /* Min[...] keeps the first minimum (MATLAB min semantics) */
-            int bx = list[0][0], by = list[0][1];
-            uint32_t bc = block_cost(fp, shape, x0, y0, bx, by);
-            for (int i = 1; i < n; ++i) {
-                uint32_t ci = block_cost(fp, shape, x0, y0, list[i][0], list[i][1]);
-                if (ci < bc) {
-                    bc = ci;
-                    bx = list[i][0];
-                    by = list[i][1];
-                }
-            }
-            int pts = n, its = 0;
-            int dx = bx, dy = by;
-            uint32_t dc = bc;
-            if (seed && !shape) {
-                /* learned start: clamp into the admissible window, refine,
-                 * and fall back to the plain recursion when the refined
-                 * distortion exceeds the BRS minimum by more than 5 % */
-                int lox = imax(-S, -x0), hix = imin(S, fp->width - 16 - x0);
-                int loy = imax(-S, -y0), hiy = imin(S, fp->height - 16 - y0);
-                int sx = iclamp(half_to_full(seed[2 * k]), lox, hix);
-                int sy = iclamp(half_to_full(seed[2 * k + 1]), loy, hiy);
-                uint32_t sc = block_cost(fp, shape, x0, y0, sx, sy);
-                pts += 1;
-                int it1 = pel_recursion(fp, p, shape, x0, y0, &sx, &sy, &sc);
-                its += it1;
-                pts += it1;
-                if ((uint64_t)20 * sc > (uint64_t)21 * bc) {
-                    int it2 = pel_recursion(fp, p, shape, x0, y0, &dx, &dy, &dc);
-                    its += it2;
-                    pts += it2;
-                } else {
-                    dx = sx;
-                    dy = sy;
-                    dc = sc;
-                }
-            } else {
-                int it1 = pel_recursion(fp, p, shape, x0, y0, &dx, &dy, &dc);
-                its += it1;
-                pts += it1;
-            }
-            int hx = 2 * dx, hy = 2 * dy;
-            if (p->half_pel && !shape) {
-                int bhx = hx, bhy = hy;
-                uint32_t hc = dc;
-                for (int o = 0; o < 8; ++o) {
-                    int qx = hx + HALF_OFFS[o][0], qy = hy + HALF_OFFS[o][1];
-                    if (!half_feasible(fp, S, x0, y0, qx, qy)) continue;
-                    ++pts;
-                    uint32_t c2 = or_sad_half(fp, x0, y0, qx, qy);
-                    if (c2 < hc) {
-                        hc = c2;
-                        bhx = qx;
-                        bhy = qy;
-                    }
-                }
-                hx = bhx;
-                hy = bhy;
-                dc = hc;
-            }
-            mv[2 * k] = (int16_t)hx;
-            mv[2 * k + 1] = (int16_t)hy;
-            mv_int[2 * k] = (int16_t)(2 * dx);
-            mv_int[2 * k + 1] = (int16_t)(2 * dy);
-            if (cost) cost[k] = dc;
-            if (iters) iters[k] = (uint8_t)its;
-            if (points) points[k] = (uint16_t)pts;
-        }
+    for (int v = 0; v < hm; ++v)
+        for (int h = 0; h < wm; ++h)
+            if (pa_mb(fp, cls, t_field, seed, p, shape_only, h, v, mv, mv_int, cost, iters, points)) return -1;
+    return 0;
+}
+
+/*
+ * The same pair with the MBs visited in the order `order` (MB indices v*W_mb+h,
+ * each exactly once).  Any order in which every MB comes after its left,
+ * upper and upper-right neighbours reads the same candidates as the raster
+ * scan and so gives the same result; a test uses this to show that the
+ * wavefront order of a parallel schedule is legal.
+ */
+int or_pa_order(const or_pair *fp, const uint8_t *cls, const int16_t *t_field, const int16_t *seed,
+                const or_params *p, int shape_only, const int32_t *order, int16_t *mv, int16_t *mv_int,
+                uint32_t *cost, uint8_t *iters, uint16_t *points) {
+    if (!pa_args_ok(fp, seed, p, shape_only, mv, mv_int) || !order) return -1;
+    int wm = fp->width / 16, hm = fp->height / 16;
+    for (int i = 0; i < wm * hm; ++i) {
+        int k = order[i];
+        if (k < 0 || k >= wm * hm) return -1;
+        if (pa_mb(fp, cls, t_field, seed, p, shape_only, k % wm, k / wm, mv, mv_int, cost, iters, points)) return -1;
     }
     return 0;
 }

@@ -26,7 +26,7 @@ EXPORTED = ("me_default_params", "me_status_str", "me_shutdown", "me_classify_ba
             "me_device_status",
             "me_kernel_timing", "me_kernel_time_ms", "me_batch_create", "me_batch_step", "me_batch_results",
             "me_batch_config", "me_batch_set_net", "me_batch_destroy", "me_net_create", "me_net_forward", "me_net_train_step",
-            "me_net_weights", "me_net_destroy")
+            "me_net_weights", "me_net_destroy", "me_search_schedule")
 
 
 class MeError(RuntimeError):
@@ -110,6 +110,8 @@ def lib():
         L.me_net_train_step.restype = i
         L.me_net_weights.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]
         L.me_net_weights.restype = i
+        L.me_search_schedule.argtypes = [C.POINTER(me_job), i, vp, vp, i, C.POINTER(i)]
+        L.me_search_schedule.restype = i
         L.me_net_destroy.argtypes = [vp]
         L.me_net_destroy.restype = None
         _lib = L

@@ -220,6 +220,7 @@ int run_pa(const me_job *jobs, int n, const me_params *params, bool shape_only, 
     for (int i = 0; i < n; ++i) {
         rc = check_job(jobs[i], shape_only);
         if (rc) return rc;
+        if (jobs[i].seed && params->k_max > kMaxSeededKmax) return ME_EINVAL;
     }
     if (n == 0) return ME_OK;
     Workspace *w = nullptr;
@@ -385,6 +386,7 @@ int me_texture_recursive(const me_job *jobs, int n, const me_params *params, con
             if (rc) return rc;
             if (!jobs[i].seed) return ME_EINVAL;
         }
+        if (params->k_max > kMaxSeededKmax) return ME_EINVAL;
         if (n == 0) return ME_OK;
         rc = net_seed_jobs(const_cast<me_net *>(net), jobs, n, stream);
         if (rc) return rc;
@@ -434,7 +436,8 @@ int me_full_search(int method, const me_job *jobs, int n, const me_params *param
     KParams kp = kparams(params, false);
     KernelTimer kt;
     return hip_err(launch_full_search(method, (const JobDesc *)(base + o), n, (int)total, kp, (uint32_t *)zb,
-                                      (uint32_t *)sb, w->stream, timer_for(*w, A_SEARCH, &kt) ? &kt : nullptr));
+                                      (uint32_t *)sb, w->status, w->stream,
+                                      timer_for(*w, A_SEARCH, &kt) ? &kt : nullptr));
 }
 
 namespace {
@@ -481,7 +484,7 @@ int mc_enqueue(Workspace &w, const std::vector<JobDesc> &desc, long long total, 
     *acc_out = acc;
     KernelTimer kt;
     return hip_err(launch_mc((const JobDesc *)(base + o), n, (int)total, (uint32_t *)(sb + acc_bytes), acc,
-                             w.stream, timer_for(w, A_MC, &kt) ? &kt : nullptr));
+                             w.status, w.stream, timer_for(w, A_MC, &kt) ? &kt : nullptr));
 }
 
 }  // namespace
@@ -541,6 +544,33 @@ int me_motion_compensate_sse(const me_job *jobs, int n, uint8_t *const *pred, ui
     std::lock_guard<std::mutex> lk(w->mu);
     unsigned long long *acc = nullptr;
     return mc_enqueue(*w, desc, total, (unsigned long long *)sums, &acc);
+}
+
+int me_search_schedule(const me_job *jobs, int n, int32_t *job_info, uint32_t *lines, int cap, int *nlines) {
+    if (n <= 0 || !jobs || !job_info || !nlines || cap < 0 || (cap > 0 && !lines)) return ME_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        int rc = check_job(jobs[i], false);
+        if (rc) return rc;
+    }
+    PaMemo m;
+    int rc = build_pa(jobs, n, m);
+    if (rc) return rc;
+    const ChainDesc *cd = (const ChainDesc *)(m.blob.data() + m.o_ch);
+    const JobDesc *od = (const JobDesc *)(m.blob.data() + m.o_jobs);
+    for (int c = 0; c < m.nchains; ++c) {
+        for (int p = 0; p < cd[c].len; ++p) {
+            const int q = cd[c].first + p;
+            if (q >= n) return ME_EINVAL;
+            const int j = m.order[q];
+            job_info[3 * j] = c;
+            job_info[3 * j + 1] = od[q].chain_pos;
+            job_info[3 * j + 2] = m.prod[j];
+        }
+    }
+    *nlines = m.nlines;
+    if (cap < m.nlines) return ME_EINVAL;
+    std::memcpy(lines, m.blob.data() + m.o_tk, sizeof(uint32_t) * (size_t)m.nlines);
+    return ME_OK;
 }
 
 int me_kernel_timing(int on) {

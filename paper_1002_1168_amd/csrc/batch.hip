@@ -152,7 +152,7 @@ hipError_t launch_step(const me_batch &b, const int32_t *cfg, hipStream_t s) {
     }
     e = launch_search(b, u, cfg, s);
     if (e != hipSuccess) return e;
-    return launch_mc(u.jobs, b.n, b.plan.total_mbs, u.part, u.acc, s, nullptr, cfg[3]);
+    return launch_mc(u.jobs, b.n, b.plan.total_mbs, u.part, u.acc, u.status, s, nullptr, cfg[3]);
 }
 
 // Fastest of three timed runs of `fn` on the batch's stream (ms), or -1.
@@ -220,7 +220,7 @@ int autotune(me_batch &b) {
         float ms = time_min(b, e0, e1, [&] {
             hipError_t e = launch_classify(u.jobs, b.n, b.plan.total_mbs, b.stream, nullptr, pc);
             if (e != hipSuccess) return e;
-            return launch_mc(u.jobs, b.n, b.plan.total_mbs, u.part, u.acc, b.stream, nullptr, pc);
+            return launch_mc(u.jobs, b.n, b.plan.total_mbs, u.part, u.acc, u.status, b.stream, nullptr, pc);
         });
         if (ms < 0.f) {
             rc = ME_EHIP;
@@ -305,6 +305,7 @@ int me_batch_create(const me_job *jobs, int n, const me_params *params, uint32_t
     for (int i = 0; i < n; ++i) {
         rc = check_job(jobs[i], shape);
         if (rc) return rc;
+        if (jobs[i].seed && params->k_max > kMaxSeededKmax) return ME_EINVAL;
     }
     me_batch *b = new me_batch();
     b->n = n;

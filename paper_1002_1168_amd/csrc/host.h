@@ -16,6 +16,9 @@ namespace host {
 constexpr int kMaxDim = 4096;  // ticket packing: 8 bits per MB coordinate
 constexpr int kMaxChains = 65536;
 constexpr int kSpinLimit = 1 << 22;
+// With learned seeds a dropped seed adds the plain recursion's candidates to
+// its own (at most 2 k_max), and iteration counts are stored in a byte.
+constexpr int kMaxSeededKmax = 127;
 
 // The last search call's prepared launch (reused when the next call passes
 // byte-identical jobs and parameters).
@@ -23,7 +26,7 @@ struct PaMemo {
     std::vector<uint8_t> key;  // jobs + params + mode
     std::vector<uint8_t> blob;
     size_t o_jobs = 0, o_ch = 0, o_tk = 0;
-    int n = 0, total_mbs = 0, nlines = 0, mask_words = 0;
+    int n = 0, total_mbs = 0, nlines = 0, mask_words = 0, nchains = 0;
     std::vector<int> order;  // chain-ordered descriptor i describes job order[i]
     std::vector<int> prod;   // per job: the earlier job whose mv_int is its T field, or -1
     bool valid = false;

@@ -197,6 +197,7 @@ int build_pa(const me_job *jobs, int n, PaMemo &m) {
     m.total_mbs = (int)total_mbs;
     m.nlines = (int)nlines;
     m.mask_words = (maxlen + 31) / 32;
+    m.nchains = nc;
     m.order.swap(order);
     m.prod.swap(prod_of);
     return ME_OK;

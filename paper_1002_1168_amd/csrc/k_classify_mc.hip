@@ -204,8 +204,10 @@ __device__ __forceinline__ int row_sse(const u32x4 cur, const uint32_t (&p)[4], 
 // Prediction of MB k by its half-pel vector (transparent: zero vector),
 // written to out_u8 when set; per-MB SSE and pixel count over the mask to
 // part[2 * mb], part[2 * mb + 1].  Eight lanes per MB, lane t predicts rows
-// 2t and 2t+1 (three reference rows at most).
-__global__ __launch_bounds__(256) void mc_kernel(const JobDesc *jobs, int n, int total, int chunk, uint32_t *part) {
+// 2t and 2t+1 (three reference rows at most).  A class byte above 2 raises
+// ST_BAD_CLASS (the MB is still predicted by its vector).
+__global__ __launch_bounds__(256) void mc_kernel(const JobDesc *jobs, int n, int total, int chunk, uint32_t *part,
+                                                 uint32_t *status) {
     const int t = lane() & 7;
     for_units<8>(jobs, n, total, chunk, [&](const JobCursor &c, int k, int mb, bool on) {
         const uint8_t *cur = c.ptr<const uint8_t>(DWI(cur));
@@ -222,6 +224,7 @@ __global__ __launch_bounds__(256) void mc_kernel(const JobDesc *jobs, int n, int
         // vector and the current rows
         const uint32_t cb = ldg8(cls ? cls + k : (const uint8_t *)(mv + k));
         const int cl = cls ? (int)cb : ME_MB_OPAQUE;
+        if (on && t == 0 && cl > ME_MB_BOUNDARY) atomicOr(status, ST_BAD_CLASS);
         const uint32_t w = ldg32(mv + k);
         const size_t o0 = (size_t)y * st + x, o1 = o0 + st;
         const u32x4 c0 = ld16(cur + o0), c1 = ld16(cur + o1);
@@ -311,12 +314,13 @@ hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_
 size_t mc_scratch(int total_mbs) { return (size_t)total_mbs * 8; }
 
 hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, unsigned long long *acc,
-                     hipStream_t s, const KernelTimer *t, int per_cu) {
+                     uint32_t *status, hipStream_t s, const KernelTimer *t, int per_cu) {
     if (total_mbs <= 0) return hipSuccess;
     const int nu = (total_mbs + 7) / 8;
     const int chunk = (flat_chunk(nu, per_cu) + 3) / 4 * 4;
     timer_mark(t, true, s);
-    hipLaunchKernelGGL(mc_kernel, dim3((nu + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk, part);
+    hipLaunchKernelGGL(mc_kernel, dim3((nu + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk, part,
+                       status);
     hipError_t e = hipGetLastError();
     timer_mark(t, false, s);
     if (e != hipSuccess) return e;

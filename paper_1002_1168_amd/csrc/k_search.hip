@@ -43,9 +43,11 @@ __device__ __forceinline__ void write_result(const JobDesc &J, int k, int dx, in
 // SADs (v_sad_u8 on packed bytes), with the current block held in registers.
 // Key = (SAD, |dx|+|dy|, dy, dx) lexicographic, packed into 64 bits.
 // Compaction: one lane per MB.  Transparent MBs get their (zero) result at
-// once; the others are appended to `list` as (job << 16 | MB index).
+// once; the others are appended to `list` as (job << 16 | MB index).  A class
+// byte above 2 raises ST_BAD_CLASS and the MB is treated as transparent (as
+// the search pre-pass does).
 __global__ __launch_bounds__(256) void compact_kernel(const JobDesc *jobs, int n, int total, uint32_t *list,
-                                                     uint32_t *count) {
+                                                     uint32_t *count, uint32_t *status) {
     const int l = lane();
     const int base = ((int)blockIdx.x * 4 + uni((int)threadIdx.x >> 6)) * 64;
     if (base >= total) return;
@@ -56,6 +58,7 @@ __global__ __launch_bounds__(256) void compact_kernel(const JobDesc *jobs, int n
         ji = c.j;
         const uint8_t *cls = c.ptr<const uint8_t>(DWI(cls));
         const int cl = cls ? (int)ldg8(cls + k) : ME_MB_OPAQUE;
+        if (cl > ME_MB_BOUNDARY) atomicOr(status, ST_BAD_CLASS);
         searched = cl == ME_MB_OPAQUE || cl == ME_MB_BOUNDARY;
         if (!searched) write_result(jobs[c.j], k, 0, 0, 0u, 0);
     });
@@ -360,10 +363,11 @@ size_t es_lds_bytes(int S) { return (size_t)(4 * es_copy_dwords(S) + 64) * 4 + 4
 size_t full_search_scratch(int total_mbs) { return (size_t)total_mbs * 4; }
 
 hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_mbs, const KParams &kp,
-                              uint32_t *counters, uint32_t *list, hipStream_t s, const KernelTimer *t) {
+                              uint32_t *counters, uint32_t *list, uint32_t *status, hipStream_t s,
+                              const KernelTimer *t) {
     if (total_mbs <= 0) return hipSuccess;
     hipLaunchKernelGGL(compact_kernel, dim3((total_mbs + 255) / 256), dim3(256), 0, s, jobs, n, total_mbs, list,
-                       counters);
+                       counters, status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int dev = 0, cus = 256;

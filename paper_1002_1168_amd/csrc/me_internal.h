@@ -75,10 +75,11 @@ size_t pa_scratch_bytes(int nlines);
 size_t pa_lds_bytes(int S, bool generic = false);
 int plan_elems(int S);
 hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_mbs, const KParams &kp,
-                              uint32_t *counters, uint32_t *list, hipStream_t s, const KernelTimer *t = nullptr);
+                              uint32_t *counters, uint32_t *list, uint32_t *status, hipStream_t s,
+                              const KernelTimer *t = nullptr);
 size_t full_search_scratch(int total_mbs);
 hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, unsigned long long *acc,
-                     hipStream_t s, const KernelTimer *t = nullptr, int per_cu = 8);
+                     uint32_t *status, hipStream_t s, const KernelTimer *t = nullptr, int per_cu = 8);
 size_t mc_scratch(int total_mbs);
 
 int pa_worker_cap();

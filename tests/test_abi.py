@@ -93,6 +93,23 @@ def test_bad_jobs():
     assert me.me_texture_recursive([job()], p, net=C.c_void_p(FAKE), check=False) == me.ME_EINVAL
 
 
+def test_seeded_search_caps_k_max():
+    # a dropped seed counts both recursions in the byte-wide iteration count,
+    # so seeded calls take k_max <= 127 (plain calls keep 0..255)
+    p = me.me_default_params(k_max=128)
+    assert me.me_texture_recursive([job(seed=FAKE + 8192)], p, check=False) == me.ME_EINVAL
+    assert me.me_shape_search([job(seed=FAKE + 8192, cur=frame(alpha=FAKE), ref=frame(alpha=FAKE))], p,
+                              check=False) == me.ME_EINVAL
+    assert me.me_texture_recursive([job(seed=FAKE + 8192)], p, net=C.c_void_p(FAKE), check=False) == me.ME_EINVAL
+    L = me.lib()
+    h = C.c_void_p()
+    ja = (me.me_job * 1)(job(seed=FAKE + 8192))
+    assert L.me_batch_create(ja, 1, C.byref(p), 0, None, C.byref(h)) == me.ME_EINVAL
+    # at 127 validation passes (the call then fails only for want of a device)
+    p127 = me.me_default_params(k_max=127)
+    assert me.me_texture_recursive([job(seed=FAKE + 8192)], p127, check=False) != me.ME_EINVAL
+
+
 def test_empty_calls_are_ok_without_device():
     p = me.me_default_params()
     assert me.me_texture_recursive([], p, check=False) == me.ME_OK

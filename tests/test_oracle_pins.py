@@ -604,3 +604,32 @@ def test_pa_bad_seed_falls_back_to_plain(orc):
     out = orc.pa(f, f, orc.Params(search_range=7), seed=seed)
     assert (out["mv"] == 0).all() and (out["cost"] == 0).all()
     assert (out["points"] >= 2).all()
+
+
+@pytest.mark.parametrize("k_max,its,pts", [(5, 5 + 3, 1 + 1 + 5 + 3), (127, 10, 1 + 1 + 10)])
+def test_pa_seed_iteration_count_closed_form(orc, k_max, its, pts):
+    """Ramp ref = 20 + 3x, cur displaced by +3, one opaque MB at (16, 16),
+    S 7.  The block-recursive list is the single zero vector (SAD 9 * 256).
+    A seed at -7 walks one pixel per recursion step toward +3.  With k_max 5
+    it stops at -2 (SAD 15 * 256): 20 * 3840 > 21 * 2304, so the seed is
+    dropped and the plain recursion from 0 takes 3 more steps; iterations
+    count both recursions and points add the seed.  With k_max 127 the seed
+    reaches +3 in 10 steps with SAD 0 and is kept."""
+    cur, ref = ramp_pair(3)
+    a = one_mb_alpha()
+    cls, _ = orc.classify(a)
+    seed = np.zeros((4, 4, 2), np.int16)
+    seed[1, 1] = (-14, 0)
+    out = orc.pa(cur, ref, orc.Params(search_range=7, k_max=k_max), a, a, cls, seed=seed)
+    assert tuple(out["mv_int"][1, 1]) == (6, 0) and out["cost"][1, 1] == 0
+    assert out["iters"][1, 1] == its and out["points"][1, 1] == pts
+
+
+def test_pa_seeded_k_max_above_127_rejected(orc):
+    cur, ref = ramp_pair(3)
+    a = one_mb_alpha()
+    cls, _ = orc.classify(a)
+    seed = np.zeros((4, 4, 2), np.int16)
+    with pytest.raises(ValueError):
+        orc.pa(cur, ref, orc.Params(search_range=7, k_max=128), a, a, cls, seed=seed)
+    orc.pa(cur, ref, orc.Params(search_range=7, k_max=255), a, a, cls)   # plain: the full range
