@@ -1,16 +1,25 @@
 #!/usr/bin/env python3
 """Throughput of the shape-adaptive motion estimator on one MI355X.
 
-Workload (default): CIF 352x288, 300 frames, two VOPs (a polygon and an
-ellipse with occlusion over a panning background), search range +-16,
-seeded synthetic data resident in HBM.  One timed step is one pass of the
-paper's path over the whole sequence: MB classification of every VOP frame,
-the proposed block/pel-recursive search for all 2 x 299 frame pairs (one
-pipelined launch), and motion compensation + PSNR.  `value` counts grid MBs
-of every (VOP, frame pair) per second.  The baselines (ES, TSS, DS) run on
-the same frames and are timed the same way, reported under "baselines".
+Headline workload: 8 concurrent 1920x1088 streams, 3-6 VOPs each (37 VOP
+layers) with occlusion and sub-pixel motion up to 24 px per frame, 60
+frames, search range +-32 with half-sample refinement; seeded synthetic data
+resident in HBM.  One timed step is one pass of the paper's path over the
+whole workload: 59 batched frame steps, each one HIP-graph replay of MB
+classification, (optionally) the learned proposal network, the
+block/pel-recursive search and motion compensation + SSE for every
+(stream, VOP) pair of that frame step.  `value` counts grid MBs of every
+(VOP, frame pair) per second, for the fastest form admitted by the metric
+(the plain method, or the network-seeded form when its PSNR is within
+0.05 dB of plain).
 
-Prints one JSON line (rank 0).  Only one GPU is used: --gpus above 1 exits.
+Also reported (under "extras"): the CIF two-VOP sequence (300 frames, +-16)
+as one pipelined launch with the ES / TSS / 4SS / DS baselines, the QCIF
+sequence in the paper's geometry (+-7) and CIF in rectangular mode with
+every method's PSNR, points per MB and figure of merit (Eq. 6), and the
+64-stream mixed-size batch.
+
+Prints one JSON line.  Only one GPU is used: --gpus above 1 exits.
 """
 from __future__ import annotations
 
@@ -39,6 +48,9 @@ NET_FWD_FLOP = 2 * (576 * 32 * 18 + 144 * 32 * 288 + 36 * 2 * 288)
 SAD_OPS = 64          # 256 absolute differences, 4 per v_sad_u8 lane-op
 PASS_OPS = 256 * 12   # gradient pass: e, gx, gy, two reciprocal lookups, two products, two counts, ...
 
+METRIC = "macroblocks/sec estimated at <=0.05 dB PSNR vs plain; mean iterations/MB"
+KIND_NAMES = {0: "classify_kernel", 1: "pa_kernel", 3: "mc_kernel", 4: "net_kernel"}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -66,18 +78,27 @@ def measured_traffic(kernel: str, sources, summary: str):
     return None
 
 
+def figure_of_merit(psnr_db, points_per_mb, S):
+    """Eq. 6: I = PSNR (2S+1)^2 / C with the PSNR averaged in linear scale
+    (10^(dB/10) per frame and VOP) and C the mean compared blocks per MB."""
+    ps = [x for x in psnr_db if np.isfinite(x)]
+    if not ps or points_per_mb <= 0:
+        return None
+    lin = float(np.mean([10.0 ** (x / 10.0) for x in ps]))
+    return lin * (2 * S + 1) ** 2 / points_per_mb
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20, help="timed passes over the headline workload")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--frames", type=int, default=300)
+    ap.add_argument("--frames", type=int, default=60, help="frames per 1920x1088 stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-baselines", action="store_true")
-    ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched frame-step measurement")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-seed measurement")
-    ap.add_argument("--no-hd", action="store_true",
-                    help="skip the 8-stream 1920x1088 batched measurement (plain and network-seeded)")
+    ap.add_argument("--no-extras", action="store_true", help="headline only (for profiling)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the network-seeded forms")
+    ap.add_argument("--only-cif", action="store_true",
+                    help="only the CIF pipelined step (for profiling its search kernel) and print it")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the 64-stream batched measurement (for profiling) and print it")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -85,17 +106,199 @@ def parse():
     return ap.parse_args()
 
 
-class Workload:
-    """Device buffers and job lists of the CIF two-VOP sequence."""
+def net_weights(name):
+    path = os.path.join(ROOT, "paper_1002_1168_amd", "weights", name)
+    return (np.load(path, allow_pickle=False), os.path.relpath(path, ROOT)) if os.path.exists(path) else (None, None)
 
-    def __init__(self, frames: int):
+
+# ------------------------------------------------------------------ headline
+class HDWorkload:
+    """8 streams of 1920x1088, 3-6 VOPs each, S=32 with half-pel: one frame
+    step = every (stream, VOP) pair of one frame pair; a pass = every frame
+    step of the sequences."""
+
+    def __init__(self, seqs):
+        import torch
+        import paper_1002_1168_amd as me
+        from paper_1002_1168_amd import device as dv
+        self.me, self.dv, self.torch = me, dv, torch
+        self.seqs = seqs
+        self.frames = seqs[0].frames
+        self.pairs = self.frames - 1
+        self.ds = [dv.DeviceSequence(q) for q in self.seqs]
+        self.units = [(si, v) for si, q in enumerate(self.seqs) for v in range(q.vops)]
+        self.params = me.me_default_params(search_range=32, half_pel=1)
+        self.grid_mbs = sum(self.ds[si].hm * self.ds[si].wm for si, _ in self.units)   # per frame step
+        self.zero = [torch.zeros((self.ds[si].hm, self.ds[si].wm, 2), dtype=torch.int16, device="cuda")
+                     for si, _ in self.units]
+
+    def outputs(self):
+        return [self.dv.Outputs.alloc(self.pairs, self.ds[si].hm, self.ds[si].wm) for si, _ in self.units]
+
+    def jobs(self, i, out, seeds=None):
+        """Jobs of frame step i; T = the previous step's mv_int (zero at step 0)."""
+        js = []
+        for u, (si, v) in enumerate(self.units):
+            d, t = self.ds[si], i + 1
+            tf = out[u].mv_int[i - 1] if i > 0 else self.zero[u]
+            js.append(self.dv.job(d.luma[t], d.luma[t - 1], d.alpha[v, t], d.alpha[v, t - 1], d.cls[v, t], tf,
+                                  out[u], i, None if seeds is None else seeds[u][i]))
+        return js
+
+
+def hd_form(hw, form, net, steps, warmup):
+    """One form (plain / learned) of the headline: a quality pass with every
+    frame step's PSNR and a per-kernel breakdown (events inside the graph),
+    then `steps` timed passes with events around the dominant kernel only."""
+    me, torch, dv = hw.me, hw.torch, hw.dv
+    stream = dv.stream_handle()
+    out = hw.outputs()
+    seeds = None
+    if form == "learned":
+        seeds = [torch.zeros((hw.pairs, hw.ds[si].hm, hw.ds[si].wm, 2), dtype=torch.int16, device="cuda")
+                 for si, _ in hw.units]
+    step_jobs = [me.job_array(hw.jobs(i, out, seeds)) for i in range(hw.pairs)]
+    kinds = [me.ME_KT_CLASSIFY, me.ME_KT_SEARCH, me.ME_KT_MC] + ([me.ME_KT_NET] if net is not None else [])
+    me.me_kernel_timing(True, kinds=kinds)
+    try:
+        b = me.Batch(step_jobs[0], hw.params, 0, stream=stream)
+        if net is not None:
+            b.set_net(net)
+    finally:
+        me.me_kernel_timing(False)
+    cfg = b.config()
+    # quality pass: per-step results
+    psnr, jobs_db = [], []
+    for i in range(hw.pairs):
+        b.step(step_jobs[i])
+        sse, npx, ps, status = b.results(check=False)
+        assert status in (me.ME_OK, me.ME_EEMPTY), status
+        jobs_db += [x for x, n in zip(ps, npx) if n > 0 and np.isfinite(x)]
+    torch.cuda.synchronize()
+    breakdown = {}
+    for k in kinds:
+        ms, cnt = b.kernel_time_ms(k)
+        breakdown[KIND_NAMES[k]] = ms / max(cnt, 1)
+    dom_kind = max(kinds, key=lambda k: breakdown[KIND_NAMES[k]])
+    pts = its = n = 0
+    for u, (si, v) in enumerate(hw.units):
+        h = out[u].host()
+        m = hw.ds[si].cls[v, 1:].cpu().numpy() != 0
+        pts += int(h["points"][m].astype(np.int64).sum())
+        its += int(h["iters"][m].astype(np.int64).sum())
+        n += int(m.sum())
+    # timed passes: events around the dominant kernel only
+    me.me_kernel_timing(True, kinds=[dom_kind])
+    try:
+        b.set_config(cfg)
+    finally:
+        me.me_kernel_timing(False)
+    for _ in range(warmup):
+        for i in range(hw.pairs):
+            b.step(step_jobs[i])
+    torch.cuda.synchronize()
+    b.kernel_time_ms(dom_kind)   # restart the sums
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for i in range(hw.pairs):
+            b.step(step_jobs[i])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kms, kcnt = b.kernel_time_ms(dom_kind)
+    assert kcnt == steps * hw.pairs, (kcnt, steps * hw.pairs)
+    status = b.results(check=False)[3]
+    assert status in (me.ME_OK, me.ME_EEMPTY), status
+    b.close()
+    grid = hw.grid_mbs * hw.pairs
+    res = {"mb_per_s": grid * steps / dt, "ms_per_step": 1000.0 * dt / steps,
+           "ms_per_frame_step": 1000.0 * dt / (steps * hw.pairs), "psnr_db": float(np.mean(jobs_db)),
+           "iters_per_mb": its / max(n, 1), "points_per_mb": pts / max(n, 1), "searched_mbs_per_step": n,
+           "searched_mb_per_s": n * steps / dt, "launch_config": cfg,
+           "kernel_ms_per_frame_step": breakdown, "dominant_kernel": KIND_NAMES[dom_kind],
+           "dominant_kernel_ms": kms / kcnt, "outputs": out, "pts": pts, "its": its, "n": n}
+    if net is not None:
+        served = int(sum(int((hw.ds[si].cls[v, 1:] == 1).sum()) for si, v in hw.units))
+        net_ms = breakdown["net_kernel"] * hw.pairs
+        tf = served * NET_FWD_FLOP / (net_ms * 1e-3) / 1e12
+        res["network_forward"] = {"mbs_per_step": served, "kernel_ms_per_frame_step": breakdown["net_kernel"],
+                                  "bound": "mfma", "achieved": tf, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": tf / PEAK_BF16_TFLOPS}
+    log(f"hd {form}: {res['mb_per_s'] / 1e6:.1f} M MB/s, {res['ms_per_step']:.2f} ms/pass "
+        f"({res['ms_per_frame_step']:.3f} ms/frame step), PSNR {res['psnr_db']:.3f} dB, "
+        f"iters/MB {res['iters_per_mb']:.3f}, points/MB {res['points_per_mb']:.2f}; "
+        f"kernels/frame step {({k: round(v, 4) for k, v in breakdown.items()})}, cfg {cfg}")
+    return res
+
+
+def search_roofline(r, kernel, traffic=None):
+    """Integer-VALU roofline of the pipelined search from its algorithmic
+    work: one SAD per compared block, one gradient pass at the block-recursive
+    winner and one per pel-recursion candidate."""
+    ops = SAD_OPS * r["pts"] + PASS_OPS * (r["n"] + r["its"])
+    launches_ops = ops  # per pass
+    ach = launches_ops / (r["dominant_kernel_ms"] * 1e-3 * r["frame_steps"]) / 1e12
+    return {"bound": "alu", "achieved": ach, "peak": PEAK_INT_TOPS, "unit": "Tops/s", "frac": ach / PEAK_INT_TOPS,
+            "traffic": traffic, "kernel": kernel, "kernel_ms": r["dominant_kernel_ms"],
+            "work_per_launch": ops / r["frame_steps"], "work_unit": "int lane-ops"}
+
+
+def cpu_baseline_hd(hw, plain_out, nsteps, threads):
+    """The oracle on the first `nsteps` frame steps of every (stream, VOP)
+    (classification, the proposed search, MC/SSE per pair; T chained), once
+    on one thread and once on `threads` threads (one task per (stream, VOP)
+    chain); checks the GPU's plain results of those steps bit-exactly."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    p = hw.params
+    op = oracle.Params(p.search_range, p.theta, p.eps_q12, p.max_step, p.k_max, p.half_pel)
+
+    def task(u):
+        si, v = hw.units[u]
+        return oracle.pa_sequence(hw.seqs[si], v, op, pairs=nsteps)
+
+    t0 = time.perf_counter()
+    res1 = [task(u) for u in range(len(hw.units))]
+    t1 = time.perf_counter() - t0
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            resn = list(ex.map(task, range(len(hw.units))))
+        reps += 1
+        if time.perf_counter() - t0 >= 3.0:
+            break
+    tn = (time.perf_counter() - t0) / reps
+    exact = True
+    for u in range(len(hw.units)):
+        h = plain_out[u].host()
+        for i in range(nsteps):
+            for k in ("mv", "mv_int", "cost", "iters", "points"):
+                if not (np.array_equal(h[k][i], res1[u][i][k]) and np.array_equal(h[k][i], resn[u][i][k])):
+                    exact = False
+    return t1, tn, exact
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+# --------------------------------------------------------------------- extras
+class CifWorkload:
+    """Device buffers and job lists of the CIF two-VOP sequence (300 frames)."""
+
+    def __init__(self, frames=300):
         import paper_1002_1168_amd as me
         from paper_1002_1168_amd import device as dv
         from paper_1002_1168_amd import synth
         self.me, self.dv = me, dv
-        t0 = time.time()
         self.seq = synth.cif_two_vops(seed=2, frames=frames)
-        log(f"generated {self.seq.name} {self.seq.width}x{self.seq.height} x{frames} in {time.time() - t0:.1f}s")
         self.ds = dv.DeviceSequence(self.seq)
         self.S = self.seq.search_range
         self.params = me.me_default_params(search_range=self.S)
@@ -107,11 +310,6 @@ class Workload:
         self.bab_ptrs = (C.c_void_p * len(bp))(*bp)
         self.out = [dv.Outputs.alloc(self.pairs, self.ds.hm, self.ds.wm) for _ in range(self.V)]
         self.jobs = me.job_array([j for v in range(self.V) for j in self.ds.pair_jobs(v, self.out[v], self.pairs)])
-        self.base_out = {m: [dv.Outputs.alloc(self.pairs, self.ds.hm, self.ds.wm) for _ in range(self.V)]
-                         for m in (me.ME_ES, me.ME_TSS, me.ME_DS)}
-        self.base_jobs = {m: me.job_array([j for v in range(self.V)
-                                           for j in self.ds.pair_jobs(v, o[v], self.pairs, chained=False)])
-                          for m, o in self.base_out.items()}
         self.grid_mbs = self.V * self.pairs * self.ds.hm * self.ds.wm
 
     def step(self, stream, ring, slot):
@@ -120,11 +318,6 @@ class Workload:
         me.me_classify_babs(self.cls_frames, self.cls_ptrs, self.bab_ptrs, stream=stream)
         me.me_texture_recursive(self.jobs, self.params, None, stream=stream)
         ring.queue(self.jobs, slot, stream)
-
-    def baseline_step(self, method, stream, ring, slot):
-        me = self.me
-        me.me_full_search(method, self.base_jobs[method], self.params, stream=stream)
-        ring.queue(self.base_jobs[method], slot, stream)
 
 
 class SumsRing:
@@ -155,225 +348,12 @@ class SumsRing:
         return [int(x) for x in sse], [int(x) for x in npx], [float(x) for x in ps], rc
 
 
-class MixedWorkload:
-    """64 streams (24 QCIF, 24 CIF, 16 4CIF 704x576), 1-4 VOPs each, S=16:
-    one batched frame step = every (stream, VOP) pair of one frame step."""
-
-    def __init__(self, frames=31, counts=(24, 24, 16)):
-        import torch
-        import paper_1002_1168_amd as me
-        from paper_1002_1168_amd import device as dv
-        from paper_1002_1168_amd import synth
-        self.me, self.dv = me, dv
-        t0 = time.time()
-        self.seqs = synth.mixed_streams(seed=3, frames=frames, counts=counts)
-        log(f"generated {len(self.seqs)} mixed streams x{frames} frames in {time.time() - t0:.1f}s")
-        self.pairs = frames - 1
-        self.ds = [dv.DeviceSequence(q) for q in self.seqs]
-        self.units = [(si, v) for si, q in enumerate(self.seqs) for v in range(q.vops)]
-        self.out = [dv.Outputs.alloc(self.pairs, self.ds[si].hm, self.ds[si].wm) for si, _ in self.units]
-        self.zero = [torch.zeros((self.ds[si].hm, self.ds[si].wm, 2), dtype=torch.int16, device="cuda")
-                     for si, _ in self.units]
-        self.params = me.me_default_params(search_range=16)
-        self.steps = [me.job_array(self.jobs(i)) for i in range(self.pairs)]
-        self.grid_mbs = sum(self.ds[si].hm * self.ds[si].wm for si, _ in self.units)
-        self.layer_mbs = sum(d.hm * d.wm for d in self.ds)
-
-    def jobs(self, i, chained_in_call=False):
-        """Jobs of frame step i; T = the previous step's mv_int (zero at step 0)."""
-        js = []
-        for u, (si, v) in enumerate(self.units):
-            d, t = self.ds[si], i + 1
-            tf = self.out[u].mv_int[i - 1] if i > 0 else (None if chained_in_call else self.zero[u])
-            js.append(self.dv.job(d.luma[t], d.luma[t - 1], d.alpha[v, t], d.alpha[v, t - 1], d.cls[v, t], tf,
-                                  self.out[u], i))
-        return js
-
-
-def learned_measurement(wl, torch, steps, warmup, plain_psnr, plain_iters):
-    """The same CIF step with the proposal network seeding the recursion
-    (weights trained by paper_1002_1168_amd.train on generated CIF
-    sequences): classification, network forward, seeded search, MC/PSNR."""
-    me, dv = wl.me, wl.dv
-    path = os.path.join(ROOT, "paper_1002_1168_amd", "weights", "proposal_cif_s16.npy")
-    if not os.path.exists(path):
-        return None
-    net = me.Net(np.load(path, allow_pickle=False))
-    stream = dv.stream_handle()
-    outs = [dv.Outputs.alloc(wl.pairs, wl.ds.hm, wl.ds.wm) for _ in range(wl.V)]
-    seeds = [torch.zeros((wl.pairs, wl.ds.hm, wl.ds.wm, 2), dtype=torch.int16, device="cuda") for _ in range(wl.V)]
-    jobs = me.job_array([j for v in range(wl.V) for j in wl.ds.pair_jobs(v, outs[v], wl.pairs, seeds=seeds[v])])
-
-    ring = SumsRing(torch, me, len(jobs))
-
-    def step(slot):
-        me.me_classify_babs(wl.cls_frames, wl.cls_ptrs, wl.bab_ptrs, stream=stream)
-        me.me_texture_recursive(jobs, wl.params, net, stream=stream)
-        ring.queue(jobs, slot, stream)
-
-    dt, net_ms, res = timed(step, ring, steps, warmup, torch, me, stream, me.ME_KT_NET)
-    assert me.me_device_status(stream) == me.ME_OK
-    net.close()
-    classes = wl.ds.cls[:, 1:].cpu().numpy()
-    served = int((classes == 1).sum())
-    tflops = served * NET_FWD_FLOP / (net_ms * 1e-3) / 1e12
-    pts, its, n = summarize(outs, classes)
-    psnr = float(np.mean(res[2]))
-    out = {"mb_per_s": wl.grid_mbs * steps / dt, "ms_per_step": 1000.0 * dt / steps, "psnr_db": psnr,
-           "psnr_delta_vs_plain_db": psnr - plain_psnr, "iters_per_mb": its / max(n, 1),
-           "iters_per_mb_plain": plain_iters, "points_per_mb": pts / max(n, 1),
-           "admitted": bool(psnr >= plain_psnr - 0.05), "weights": "paper_1002_1168_amd/weights/proposal_cif_s16.npy",
-           "network_forward": {"kernel_ms": net_ms, "mbs": served, "bound": "mfma", "achieved": tflops,
-                               "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": tflops / PEAK_BF16_TFLOPS}}
-    log(f"learned seeds: {out['mb_per_s'] / 1e6:.1f} M MB/s, PSNR {psnr:.3f} dB ({out['psnr_delta_vs_plain_db']:+.4f}), "
-        f"iters/MB {out['iters_per_mb']:.3f}; network forward {net_ms:.3f} ms for {served} MBs = {tflops:.1f} TFLOP/s")
-    return out
-
-
-def batched_measurement(torch, steps, warmup):
-    """Per-frame-step graph launches over the mixed streams, and the same
-    frames as one pipelined launch over all steps."""
-    me = __import__("paper_1002_1168_amd")
-    mw = MixedWorkload()
-    stream = mw.dv.stream_handle()
-    b = me.Batch(mw.steps[0], mw.params, me.ME_BATCH_AUTOTUNE, stream=stream)
-    cfg = b.config()
-    n = len(mw.steps)
-    for i in range(max(warmup, n)):   # one pass over every step's job table first
-        b.step(mw.steps[i % n])
-    torch.cuda.synchronize()
-    k = max(steps, 3 * n)
-    t0 = time.perf_counter()
-    for i in range(k):
-        b.step(mw.steps[i % n])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    status = b.results(check=False)[3]
-    assert status in (me.ME_OK, me.ME_EEMPTY), status
-    b.close()
-    per_step = {"mb_per_s": mw.grid_mbs * k / dt, "ms_per_frame_step": 1000.0 * dt / k, "frame_steps": k,
-                "config": cfg}
-    # all frame steps of all streams in one pipelined launch (T chained in the call)
-    allj = me.job_array([j for i in range(n) for j in mw.jobs(i, chained_in_call=True)])
-    for _ in range(2):
-        me.me_texture_recursive(allj, mw.params, None, stream=stream)
-    torch.cuda.synchronize()
-    reps = max(steps // 4, 2)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        me.me_texture_recursive(allj, mw.params, None, stream=stream)
-    torch.cuda.synchronize()
-    dtp = time.perf_counter() - t0
-    assert me.me_device_status(stream) == me.ME_OK
-    pipelined = {"mb_per_s": mw.grid_mbs * n * reps / dtp, "ms_per_launch": 1000.0 * dtp / reps,
-                 "frame_steps_per_launch": n, "search_only": True}
-    log(f"batched mixed streams: {per_step['mb_per_s'] / 1e6:.1f} M MB/s per-step graph "
-        f"({per_step['ms_per_frame_step']:.3f} ms/step, cfg {cfg}); pipelined search over {n} steps "
-        f"{pipelined['mb_per_s'] / 1e6:.1f} M MB/s")
-    return {"workload": f"mixed64_{len(mw.seqs)}streams_{len(mw.units)}vops_S16", "grid_mbs_per_frame_step": mw.grid_mbs,
-            "grid_mbs_per_vop_layer": mw.layer_mbs, "per_step_graph": per_step, "pipelined_all_steps": pipelined}
-
-
-class HDWorkload:
-    """8 streams of 1920x1088, 3-6 VOPs each (sub-pixel motion up to 24 px
-    per frame), S=32 with half-pel: one batched frame step = every
-    (stream, VOP) pair of one frame step, plain or with seed buffers."""
-
-    def __init__(self, frames=6, streams=8):
-        import torch
-        import paper_1002_1168_amd as me
-        from paper_1002_1168_amd import device as dv
-        from paper_1002_1168_amd import synth
-        self.me, self.dv, self.torch = me, dv, torch
-        t0 = time.time()
-        self.seqs = synth.hd_streams(seed=5, frames=frames, streams=streams)
-        log(f"generated {len(self.seqs)} 1920x1088 streams x{frames} frames in {time.time() - t0:.1f}s")
-        self.pairs = frames - 1
-        self.ds = [dv.DeviceSequence(q) for q in self.seqs]
-        self.units = [(si, v) for si, q in enumerate(self.seqs) for v in range(q.vops)]
-        self.params = me.me_default_params(search_range=32, half_pel=1)
-        self.grid_mbs = sum(self.ds[si].hm * self.ds[si].wm for si, _ in self.units)
-
-    def outputs(self):
-        return [self.dv.Outputs.alloc(self.pairs, self.ds[si].hm, self.ds[si].wm) for si, _ in self.units]
-
-    def jobs(self, i, out, zero, seeds=None):
-        """Jobs of frame step i; T = the previous step's mv_int (zero at step 0)."""
-        js = []
-        for u, (si, v) in enumerate(self.units):
-            d, t = self.ds[si], i + 1
-            tf = out[u].mv_int[i - 1] if i > 0 else zero[u]
-            js.append(self.dv.job(d.luma[t], d.luma[t - 1], d.alpha[v, t], d.alpha[v, t - 1], d.cls[v, t], tf,
-                                  out[u], i, None if seeds is None else seeds[u]))
-        return js
-
-
-def hd_measurement(torch, steps):
-    """The batched frame step on the 1920x1088 streams, plain and with the
-    proposal network attached (weights trained on CIF at S=16; the seed is
-    clamped to +-16 and refined by the recursion at S=32): MB/s, PSNR,
-    recursion iterations per searched MB."""
-    me = __import__("paper_1002_1168_amd")
-    hw = HDWorkload()
-    stream = hw.dv.stream_handle()
-    zero = [torch.zeros((hw.ds[si].hm, hw.ds[si].wm, 2), dtype=torch.int16, device="cuda") for si, _ in hw.units]
-    path = os.path.join(ROOT, "paper_1002_1168_amd", "weights", "proposal_cif_s16.npy")
-    net = me.Net(np.load(path, allow_pickle=False)) if os.path.exists(path) else None
-    res = {}
-    for form in ("plain", "learned"):
-        if form == "learned" and net is None:
-            break
-        out = hw.outputs()
-        seeds = None
-        if form == "learned":
-            seeds = [torch.zeros((hw.ds[si].hm, hw.ds[si].wm, 2), dtype=torch.int16, device="cuda")
-                     for si, _ in hw.units]
-        step_jobs = [me.job_array(hw.jobs(i, out, zero, seeds)) for i in range(hw.pairs)]
-        b = me.Batch(step_jobs[0], hw.params, 0, stream=stream)
-        if form == "learned":
-            b.set_net(net)
-        # one pass with the per-step results: quality
-        psnr = []
-        for i in range(hw.pairs):
-            b.step(step_jobs[i])
-            sse, npx, ps, status = b.results(check=False)
-            assert status in (me.ME_OK, me.ME_EEMPTY), status
-            psnr += [x for x, n in zip(ps, npx) if n > 0 and np.isfinite(x)]
-        torch.cuda.synchronize()
-        its = n = 0
-        for u, (si, v) in enumerate(hw.units):
-            h = out[u].host()
-            m = hw.ds[si].cls[v, 1:].cpu().numpy() != 0
-            its += int(h["iters"][m].astype(np.int64).sum())
-            n += int(m.sum())
-        # timed passes
-        k = max(steps // hw.pairs, 2) * hw.pairs
-        t0 = time.perf_counter()
-        for i in range(k):
-            b.step(step_jobs[i % hw.pairs])
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        b.close()
-        res[form] = {"mb_per_s": hw.grid_mbs * k / dt, "ms_per_frame_step": 1000.0 * dt / k, "frame_steps": k,
-                     "psnr_db": float(np.mean(psnr)), "iters_per_mb": its / max(n, 1), "searched_mbs_per_pass": n}
-    if net is not None:
-        net.close()
-        res["psnr_delta_db"] = res["learned"]["psnr_db"] - res["plain"]["psnr_db"]
-        res["admitted"] = bool(res["psnr_delta_db"] >= -0.05)
-    log("hd batched: " + "; ".join(f"{f} {r['mb_per_s'] / 1e6:.1f} M MB/s, {r['ms_per_frame_step']:.3f} ms/step, "
-                                     f"PSNR {r['psnr_db']:.3f} dB, iters/MB {r['iters_per_mb']:.3f}"
-                                     for f, r in res.items() if isinstance(r, dict)))
-    return {"workload": f"hd1920x1088_{len(hw.seqs)}streams_{len(hw.units)}vops_S32_halfpel",
-            "grid_mbs_per_frame_step": hw.grid_mbs, **res}
-
-
 def timed(fn, ring, steps, warmup, torch, me, stream, kind):
-    """Wall time of `steps` frame steps fn(slot), and the mean duration of
-    the main kernel of call kind `kind` over the same steps (HIP events
-    recorded by the library on `stream` around that kernel).  Step i is
-    queued before the host waits for step i-1's sums and computes its PSNR,
-    so the GPU does not idle while the host reads results back; every
-    step's PSNR is still computed.  Returns the last step's results."""
+    """Wall time of `steps` steps fn(slot), and the mean duration of the main
+    kernel of call kind `kind` over the same steps (HIP events recorded by
+    the library on `stream` around that kernel).  Step i is queued before the
+    host waits for step i-1's sums, so the GPU does not idle while the host
+    reads results back.  Returns the last step's results."""
     def run(n):
         for i in range(n):
             fn(i & 1)
@@ -383,8 +363,8 @@ def timed(fn, ring, steps, warmup, torch, me, stream, kind):
 
     run(warmup)
     torch.cuda.synchronize()
-    me.me_kernel_timing(True, kinds=[kind])  # events around this kind's kernel only
-    me.me_kernel_time_ms(kind, stream)  # restart the sums
+    me.me_kernel_timing(True, kinds=[kind])
+    me.me_kernel_time_ms(kind, stream)
     t0 = time.perf_counter()
     res = run(steps)
     torch.cuda.synchronize()
@@ -395,7 +375,7 @@ def timed(fn, ring, steps, warmup, torch, me, stream, kind):
     return dt, total / count, res
 
 
-def summarize(out_list, classes, searched_only=True):
+def summarize(out_list, classes):
     pts = its = n = 0
     for v, o in enumerate(out_list):
         h = o.host()
@@ -406,38 +386,190 @@ def summarize(out_list, classes, searched_only=True):
     return pts, its, n
 
 
-def cpu_baseline(wl, gpu_hosts, min_seconds=10.0):
-    """The oracle on the whole workload, single thread, repeated until
-    `min_seconds` have passed; also checks the GPU result of the last timed
-    step bit-exactly.  -> (seconds per pass, passes, exact)."""
-    import oracle
-    seq, p = wl.seq, wl.params
-    op = oracle.Params(p.search_range, p.theta, p.eps_q12, p.max_step, p.k_max, p.half_pel)
+def cif_measurement(torch, steps, warmup, learned=True):
+    """CIF two-VOP sequence, 300 frames, +-16: the proposed search for all 598
+    pairs in one pipelined launch, the baselines, and the network-seeded form."""
+    import paper_1002_1168_amd as me
+    wl = CifWorkload()
+    stream = wl.dv.stream_handle()
+    ring = SumsRing(torch, me, len(wl.jobs))
+    dt, kern_ms, res = timed(lambda slot: wl.step(stream, ring, slot), ring, steps, warmup, torch, me, stream,
+                             me.ME_KT_SEARCH)
+    assert me.me_device_status(stream) == me.ME_OK
+    classes = wl.ds.cls[:, 1:].cpu().numpy()
+    pts, its, nsearch = summarize(wl.out, classes)
+    psnr_list = res[2]
+    psnr = float(np.mean(psnr_list))
+    ops = SAD_OPS * pts + PASS_OPS * (nsearch + its)
+    ach = ops / (kern_ms * 1e-3) / 1e12
+    out = {"workload": f"cif352x288_{wl.V}vop_300f_S{wl.S}", "mb_per_s": wl.grid_mbs * steps / dt,
+           "ms_per_step": 1000.0 * dt / steps, "grid_mbs_per_step": wl.grid_mbs, "searched_mbs_per_step": nsearch,
+           "searched_mb_per_s": nsearch * steps / dt, "psnr_db": psnr, "iters_per_mb": its / max(nsearch, 1),
+           "points_per_mb": pts / max(nsearch, 1),
+           "figure_of_merit": figure_of_merit(psnr_list, pts / max(nsearch, 1), wl.S),
+           "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_INT_TOPS, "unit": "Tops/s",
+                        "frac": ach / PEAK_INT_TOPS, "kernel": "pa2_kernel", "kernel_ms": kern_ms,
+                        "traffic": measured_traffic("pa2_kernel", ("paper_1002_1168_amd/csrc/k_pa.hip",
+                                                                   "paper_1002_1168_amd/csrc/me_internal.h"),
+                                                    "profiles/pa2_kernel_traffic_cif352x288_2vop_300f_S16.md")}}
+    log(f"cif: step {out['ms_per_step']:.3f} ms, search kernel {kern_ms:.3f} ms, {out['mb_per_s'] / 1e6:.1f} M MB/s, "
+        f"PSNR {psnr:.2f} dB, iters/MB {out['iters_per_mb']:.3f}, points/MB {out['points_per_mb']:.3f}")
+    baselines = {}
+    for m, name in ((me.ME_ES, "es"), (me.ME_TSS, "tss"), (me.ME_4SS, "4ss"), (me.ME_DS, "ds")):
+        bout = [wl.dv.Outputs.alloc(wl.pairs, wl.ds.hm, wl.ds.wm) for _ in range(wl.V)]
+        bj = me.job_array([j for v in range(wl.V) for j in wl.ds.pair_jobs(v, bout[v], wl.pairs, chained=False)])
+        bsteps = max(steps // 2, 1)
+
+        def bstep(slot, bj=bj, m=m):
+            me.me_full_search(m, bj, wl.params, stream=stream)
+            ring.queue(bj, slot, stream)
+
+        bdt, bk, bres = timed(bstep, ring, bsteps, 1, torch, me, stream, me.ME_KT_FULL)
+        bpts, _, bn = summarize(bout, classes)
+        entry = {"mb_per_s": wl.grid_mbs * bsteps / bdt, "ms_per_step": 1000.0 * bdt / bsteps, "search_kernel_ms": bk,
+                 "psnr_db": float(np.mean(bres[2])), "points_per_mb": bpts / max(bn, 1),
+                 "figure_of_merit": figure_of_merit(bres[2], bpts / max(bn, 1), wl.S)}
+        if m == me.ME_ES:
+            a2 = SAD_OPS * bpts / (bk * 1e-3) / 1e12
+            entry["roofline"] = {"bound": "alu", "achieved": a2, "peak": PEAK_INT_TOPS, "unit": "Tops/s",
+                                 "frac": a2 / PEAK_INT_TOPS, "kernel": "es_kernel"}
+        baselines[name] = entry
+        log(f"cif {name}: {entry['mb_per_s'] / 1e6:.1f} M MB/s, kernel {bk:.3f} ms, PSNR {entry['psnr_db']:.2f}, "
+            f"points/MB {entry['points_per_mb']:.2f}")
+    assert me.me_device_status(stream) == me.ME_OK
+    out["baselines"] = baselines
+    w, wpath = net_weights("proposal_cif_s16.npy")
+    if learned and w is not None:
+        net = me.Net(w)
+        outs = [wl.dv.Outputs.alloc(wl.pairs, wl.ds.hm, wl.ds.wm) for _ in range(wl.V)]
+        seeds = [torch.zeros((wl.pairs, wl.ds.hm, wl.ds.wm, 2), dtype=torch.int16, device="cuda") for _ in range(wl.V)]
+        jobs = me.job_array([j for v in range(wl.V) for j in wl.ds.pair_jobs(v, outs[v], wl.pairs, seeds=seeds[v])])
+
+        def lstep(slot):
+            me.me_classify_babs(wl.cls_frames, wl.cls_ptrs, wl.bab_ptrs, stream=stream)
+            me.me_texture_recursive(jobs, wl.params, net, stream=stream)
+            ring.queue(jobs, slot, stream)
+
+        ldt, net_ms, lres = timed(lstep, ring, steps, warmup, torch, me, stream, me.ME_KT_NET)
+        assert me.me_device_status(stream) == me.ME_OK
+        net.close()
+        served = int((classes == 1).sum())
+        tflops = served * NET_FWD_FLOP / (net_ms * 1e-3) / 1e12
+        lp, li, ln = summarize(outs, classes)
+        lps = float(np.mean(lres[2]))
+        out["learned"] = {"mb_per_s": wl.grid_mbs * steps / ldt, "ms_per_step": 1000.0 * ldt / steps, "psnr_db": lps,
+                          "psnr_delta_vs_plain_db": lps - psnr, "iters_per_mb": li / max(ln, 1),
+                          "points_per_mb": lp / max(ln, 1), "admitted": bool(lps >= psnr - 0.05), "weights": wpath,
+                          "network_forward": {"kernel_ms": net_ms, "mbs": served, "bound": "mfma", "achieved": tflops,
+                                              "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                                              "frac": tflops / PEAK_BF16_TFLOPS}}
+        log(f"cif learned: {out['learned']['mb_per_s'] / 1e6:.1f} M MB/s, PSNR {lps:.3f} "
+            f"({lps - psnr:+.4f}), iters/MB {out['learned']['iters_per_mb']:.3f}")
+    return out
+
+
+def quality_grid(seq, S, rect, torch):
+    """Every method on one sequence (VOP mode, or rectangular mode with no
+    alpha): mean per-frame PSNR, points and iterations per searched MB and
+    the figure of merit (Eq. 6), as in Tables 1-2."""
+    import paper_1002_1168_amd as me
+    from paper_1002_1168_amd import device as dv
+    ds = dv.DeviceSequence(seq)
+    s = dv.stream_handle()
+    pairs = seq.frames - 1
+    vops = [None] if rect else list(range(seq.vops))
+    if not rect:
+        fr, cp, bp = ds.classify_frames()
+        me.me_classify_babs(fr, cp, bp, stream=s)
+    p = me.me_default_params(search_range=S, half_pel=int(seq.half_pel))
+    res = {}
+    for name, m in (("pa", None), ("es", me.ME_ES), ("tss", me.ME_TSS), ("4ss", me.ME_4SS), ("ds", me.ME_DS)):
+        outs = [dv.Outputs.alloc(pairs, ds.hm, ds.wm) for _ in vops]
+        jobs = [j for v, o in zip(vops, outs) for j in ds.pair_jobs(v, o, pairs, chained=m is None)]
+        if m is None:
+            me.me_texture_recursive(jobs, p, None, stream=s)
+        else:
+            me.me_full_search(m, jobs, p, stream=s)
+        _, npx, ps, rc = me.me_motion_compensate_psnr(jobs, stream=s, check=False)
+        assert rc in (me.ME_OK, me.ME_EEMPTY), rc
+        assert me.me_device_status(s) == me.ME_OK
+        db = [x for x, n in zip(ps, npx) if n > 0]
+        pts = its = n = 0
+        for v, o in zip(vops, outs):
+            h = o.host()
+            msk = np.ones(h["points"].shape, bool) if v is None else ds.cls[v, 1:].cpu().numpy() != 0
+            pts += int(h["points"][msk].astype(np.int64).sum())
+            its += int(h["iters"][msk].astype(np.int64).sum())
+            n += int(msk.sum())
+        res[name] = {"psnr_db": float(np.mean(db)), "points_per_mb": pts / max(n, 1),
+                     "iters_per_mb": its / max(n, 1), "figure_of_merit": figure_of_merit(db, pts / max(n, 1), S)}
+    torch.cuda.synchronize()
+    log(f"{seq.name} {'rect' if rect else 'vop'} S={S}: " + "; ".join(
+        f"{k} {v['psnr_db']:.2f} dB {v['points_per_mb']:.2f} pts" for k, v in res.items()))
+    return res
+
+
+def batched_measurement(torch, steps, warmup):
+    """64 mixed-size streams: per-frame-step graph launches, autotuned."""
+    import paper_1002_1168_amd as me
+    from paper_1002_1168_amd import device as dv
+    from paper_1002_1168_amd import synth
+    seqs = synth.mixed_streams(seed=3, frames=31)
+    pairs = 30
+    ds = [dv.DeviceSequence(q) for q in seqs]
+    units = [(si, v) for si, q in enumerate(seqs) for v in range(q.vops)]
+    out = [dv.Outputs.alloc(pairs, ds[si].hm, ds[si].wm) for si, _ in units]
+    zero = [torch.zeros((ds[si].hm, ds[si].wm, 2), dtype=torch.int16, device="cuda") for si, _ in units]
+    params = me.me_default_params(search_range=16)
+
+    def jobs(i):
+        js = []
+        for u, (si, v) in enumerate(units):
+            d, t = ds[si], i + 1
+            tf = out[u].mv_int[i - 1] if i > 0 else zero[u]
+            js.append(dv.job(d.luma[t], d.luma[t - 1], d.alpha[v, t], d.alpha[v, t - 1], d.cls[v, t], tf, out[u], i))
+        return me.job_array(js)
+
+    step_jobs = [jobs(i) for i in range(pairs)]
+    stream = dv.stream_handle()
+    b = me.Batch(step_jobs[0], params, me.ME_BATCH_AUTOTUNE, stream=stream)
+    cfg = b.config()
+    for i in range(max(warmup, pairs)):
+        b.step(step_jobs[i % pairs])
+    torch.cuda.synchronize()
+    k = max(steps, 3 * pairs)
     t0 = time.perf_counter()
-    reps = 0
-    while True:
-        res = [oracle.pa_sequence(seq, v, op, pairs=wl.pairs) for v in range(wl.V)]
-        reps += 1
-        if time.perf_counter() - t0 >= min_seconds:
-            break
-    dt = (time.perf_counter() - t0) / reps
-    exact = True
-    for v in range(wl.V):
-        for i, r in enumerate(res[v]):
-            for k in ("mv", "mv_int", "cost", "iters", "points"):
-                if not np.array_equal(gpu_hosts[v][k][i], r[k]):
-                    exact = False
-    return dt, reps, exact
+    for i in range(k):
+        b.step(step_jobs[i % pairs])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    status = b.results(check=False)[3]
+    assert status in (me.ME_OK, me.ME_EEMPTY), status
+    b.close()
+    grid = sum(ds[si].hm * ds[si].wm for si, _ in units)
+    log(f"batched mixed streams: {grid * k / dt / 1e6:.1f} M MB/s ({1000 * dt / k:.3f} ms/step, cfg {cfg})")
+    return {"workload": f"mixed64_{len(seqs)}streams_{len(units)}vops_S16", "grid_mbs_per_frame_step": grid,
+            "mb_per_s": grid * k / dt, "ms_per_frame_step": 1000.0 * dt / k, "frame_steps": k, "config": cfg}
 
 
+# ----------------------------------------------------------------------- main
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+    hd_seqs = None
+    if not (a.copy_mib or a.only_batched or a.only_cif):
+        # rendered in forked processes before anything touches the GPU
+        from paper_1002_1168_amd import synth
+        t0 = time.time()
+        hd_seqs = synth.hd_streams(seed=5, frames=a.frames, streams=8, workers=min(8, threads))
+        log(f"generated 8 1920x1088 streams x{a.frames} frames in {time.time() - t0:.1f}s")
     import torch
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    import paper_1002_1168_amd as me
     if a.copy_mib:
         src = torch.randint(0, 255, (a.copy_mib << 20,), dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -449,90 +581,76 @@ def main():
     if a.only_batched:
         print(json.dumps({"batched": batched_measurement(torch, a.steps, a.warmup)}), flush=True)
         return
-    wl = Workload(a.frames)
-    me = wl.me
-    stream = wl.dv.stream_handle()
+    if a.only_cif:
+        print(json.dumps({"cif": cif_measurement(torch, a.steps, a.warmup, learned=False)}), flush=True)
+        return
 
-    ring = SumsRing(torch, me, len(wl.jobs))
-    dt, kern_ms, res = timed(lambda slot: wl.step(stream, ring, slot), ring, a.steps, a.warmup, torch, me, stream,
-                             me.ME_KT_SEARCH)
-    assert me.me_device_status(stream) == me.ME_OK
-    sse, npx, ps, _ = res
-    ms = 1000.0 * dt / a.steps
-    value = wl.grid_mbs * a.steps / dt
-    classes = wl.ds.cls[:, 1:].cpu().numpy()
-    pts, its, nsearch = summarize(wl.out, classes)
-    psnr = float(np.mean(ps))
-    # roofline of the dominant kernel (the pipelined search): integer VALU
-    ops = SAD_OPS * pts + PASS_OPS * (nsearch + its)   # one pass at the BRS winner + one per iteration
-    achieved = ops / (kern_ms * 1e-3) / 1e12
-    log(f"step {ms:.3f} ms, search kernel {kern_ms:.3f} ms, {value / 1e6:.1f} M MB/s, PSNR {psnr:.2f} dB, "
-        f"iters/MB {its / max(nsearch, 1):.3f}, points/MB {pts / max(nsearch, 1):.3f}")
-
-    baselines = {}
-    if not a.no_baselines:
-        for m, name in ((me.ME_ES, "es"), (me.ME_TSS, "tss"), (me.ME_DS, "ds")):
-            bdt, bk, bres = timed(lambda slot, m=m: wl.baseline_step(m, stream, ring, slot), ring,
-                                  max(a.steps // 2, 1), 1, torch, me, stream,
-                                  me.ME_KT_FULL)
-            bpts, _, bn = summarize(wl.base_out[m], classes)
-            steps_b = max(a.steps // 2, 1)
-            entry = {"mb_per_s": wl.grid_mbs * steps_b / bdt, "ms_per_step": 1000.0 * bdt / steps_b,
-                     "search_kernel_ms": bk, "psnr_db": float(np.mean(bres[2])),
-                     "points_per_mb": bpts / max(bn, 1)}
-            if m == me.ME_ES:
-                es_ops = SAD_OPS * bpts
-                ach = es_ops / (bk * 1e-3) / 1e12
-                entry["roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK_INT_TOPS, "unit": "Tops/s",
-                                     "frac": ach / PEAK_INT_TOPS}
-            baselines[name] = entry
-            log(f"{name}: {entry['mb_per_s'] / 1e6:.1f} M MB/s, kernel {bk:.3f} ms, PSNR {entry['psnr_db']:.2f}, "
-                f"points/MB {entry['points_per_mb']:.2f}")
-        assert me.me_device_status(stream) == me.ME_OK
-
-    learned = None
-    if not a.no_learned:
-        learned = learned_measurement(wl, torch, a.steps, a.warmup, psnr, its / max(nsearch, 1))
-
-    batched = None
-    if not a.no_batched:
-        batched = batched_measurement(torch, a.steps, a.warmup)
-
-    hd = None
-    if not a.no_hd:
-        hd = hd_measurement(torch, a.steps)
+    hw = HDWorkload(hd_seqs)
+    forms = {"plain": hd_form(hw, "plain", None, a.steps, a.warmup)}
+    w, wpath = net_weights("proposal_hd_s32.npy")
+    if w is None:
+        w, wpath = net_weights("proposal_cif_s16.npy")
+    if not a.no_learned and w is not None:
+        net = me.Net(w)
+        forms["learned"] = hd_form(hw, "learned", net, a.steps, a.warmup)
+        net.close()
+        lf = forms["learned"]
+        lf["psnr_delta_vs_plain_db"] = lf["psnr_db"] - forms["plain"]["psnr_db"]
+        lf["admitted"] = bool(lf["psnr_delta_vs_plain_db"] >= -0.05)
+        lf["weights"] = wpath
+    admitted = ["plain"] + [f for f in ("learned",) if f in forms and forms[f]["admitted"]]
+    best = max(admitted, key=lambda f: forms[f]["mb_per_s"])
+    r = forms[best]
+    r["frame_steps"] = hw.pairs
+    kern = r["dominant_kernel"]
+    if kern == "pa_kernel":
+        roof = search_roofline(r, "pa_kernel<28>", measured_traffic(
+            "pa_kernel<28>", ("paper_1002_1168_amd/csrc/k_pa.hip", "paper_1002_1168_amd/csrc/me_internal.h"),
+            "profiles/pa_kernel_traffic_hd1920x1088_8streams_S32_halfpel.md"))
+    else:
+        roof = {"kernel": kern, "kernel_ms": r["dominant_kernel_ms"], "bound": None, "achieved": None,
+                "peak": None, "unit": None, "frac": None, "traffic": None}
 
     cpu = None
     if not a.no_cpu_baseline:
-        hosts = [o.host() for o in wl.out]
-        cdt, reps, exact = cpu_baseline(wl, hosts)
-        cpu = {"value": wl.grid_mbs / cdt, "unit": "MB/s", "cores": 1, "kind": "oracle",
-               "sample": f"the whole workload ({wl.V} VOPs x {wl.pairs} pairs: classification, proposed search, "
-                         f"MC/SSE) {reps}x back to back, mean per pass (single thread, C oracle built -O2)",
-               "parity_vs_gpu": "bit-exact" if exact else "MISMATCH"}
-        log(f"oracle: {cdt:.2f}s -> {cpu['value'] / 1e6:.3f} M MB/s, GPU parity {'ok' if exact else 'MISMATCH'}")
+        nsteps = min(10, hw.pairs)
+        t1, tn, exact = cpu_baseline_hd(hw, forms["plain"]["outputs"], nsteps, threads)
+        sample_mbs = hw.grid_mbs * nsteps
+        cpu = {"value": sample_mbs / tn, "unit": "MB/s", "cores": threads, "kind": "oracle",
+               "sample": f"the first {nsteps} of {hw.pairs} frame steps of all 8 streams and {len(hw.units)} VOP "
+                         f"layers ({sample_mbs} grid MBs: classification, the proposed search with half-pel, "
+                         f"MC/SSE; T chained); C oracle built -O2, one thread per (stream, VOP) chain",
+               "single_thread_value": sample_mbs / t1, "host_cpus_visible": len(os.sched_getaffinity(0)),
+               "cpu_model": cpu_model(), "parity_vs_gpu": "bit-exact" if exact else "MISMATCH"}
+        log(f"oracle: {nsteps} frame steps, 1 thread {t1:.2f}s ({cpu['single_thread_value'] / 1e6:.3f} M MB/s), "
+            f"{threads} threads {tn:.2f}s ({cpu['value'] / 1e6:.3f} M MB/s), GPU parity {'ok' if exact else 'MISMATCH'}")
 
+    extras = {}
+    if not a.no_extras:
+        from paper_1002_1168_amd import synth
+        extras["cif"] = cif_measurement(torch, a.steps, a.warmup, learned=not a.no_learned)
+        extras["qcif_vop"] = quality_grid(synth.qcif_ellipse(seed=1, frames=10), 7, False, torch)
+        extras["qcif_rect"] = quality_grid(synth.qcif_ellipse(seed=1, frames=10), 7, True, torch)
+        extras["cif_rect"] = quality_grid(synth.cif_two_vops(seed=2, frames=60), 16, True, torch)
+        extras["batched_mixed64"] = batched_measurement(torch, a.steps, a.warmup)
+
+    for f in forms.values():
+        for k in ("outputs", "pts", "its", "n"):
+            f.pop(k, None)
     line = {
-        "metric": "macroblocks/sec estimated at <=0.05 dB PSNR vs plain; mean iterations/MB",
-        "value": value, "unit": "MB/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u8", "data": "synthetic",
-        "config": {"workload": f"cif352x288_{wl.V}vop_{a.frames}f_S{wl.S}_plain", "frames": a.frames,
-                   "vops": wl.V, "frame_pairs_per_vop": wl.pairs, "search_range": wl.S,
-                   "grid_mbs_per_step": wl.grid_mbs, "searched_mbs_per_step": nsearch},
-        "psnr_db": psnr, "iters_per_mb": its / max(nsearch, 1), "points_per_mb": pts / max(nsearch, 1),
-        "searched_mb_per_s": nsearch * a.steps / dt,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS, "unit": "Tops/s",
-                     "frac": achieved / PEAK_INT_TOPS,
-                     "traffic": measured_traffic("pa2_kernel", ("paper_1002_1168_amd/csrc/k_pa.hip",
-                                                                "paper_1002_1168_amd/csrc/me_internal.h"),
-                                                 "profiles/pa2_kernel_traffic_cif352x288_2vop_300f_S16.md"),
-                     "kernel": "pa2_kernel", "kernel_ms": kern_ms},
+        "metric": METRIC, "value": r["mb_per_s"], "unit": "MB/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"hd1920x1088_8streams_{len(hw.units)}vops_{hw.frames}f_S32_halfpel",
+                   "form": best, "streams": 8, "vop_layers": len(hw.units), "frames": hw.frames,
+                   "frame_steps_per_step": hw.pairs, "search_range": 32, "half_pel": True,
+                   "grid_mbs_per_step": hw.grid_mbs * hw.pairs, "searched_mbs_per_step": r["searched_mbs_per_step"]},
+        "iters_per_mb": r["iters_per_mb"], "psnr_db": r["psnr_db"], "points_per_mb": r["points_per_mb"],
+        "searched_mb_per_s": r["searched_mb_per_s"],
+        "forms": forms,
+        "roofline": roof,
         "cpu_baseline": cpu,
-        "baselines": baselines,
-        "learned": learned,
-        "batched": batched,
-        "hd_batched": hd,
+        "extras": extras,
     }
     print(json.dumps(line), flush=True)
 

@@ -54,10 +54,11 @@ extern "C" {
 #define ME_MB_OPAQUE 1      /* every pixel inside the VOP */
 #define ME_MB_BOUNDARY 2    /* both */
 
-/* baseline methods (Section 1 references [5], [7]; Tables 1-2) */
+/* baseline methods (Section 1 references [5], [6], [7]; Tables 1-2) */
 #define ME_ES 0  /* exhaustive search */
 #define ME_TSS 1 /* three-step search */
 #define ME_DS 2  /* diamond search */
+#define ME_4SS 3 /* four-step search */
 
 typedef struct me_frame {
     const uint8_t *luma;  /* composited luma (device) */
@@ -181,8 +182,12 @@ int me_shape_search(const me_job *jobs, int n, const me_params *params, void *st
  * at (0, 0): ME_ES (all admissible vectors; ties -> smaller |dx|+|dy|, then
  * smaller dy, then smaller dx), ME_TSS (first step 2^(ceil(log2(S+1))-1),
  * halved to 1), ME_DS (large diamond until the centre wins, then the small
- * diamond).  Moves need a strictly smaller SAD.  `points` counts distinct
- * positions evaluated; iters is written 0; t_field and seed are ignored.
+ * diamond), ME_4SS (the 5x5 square of step 2 around the centre until the
+ * centre wins, at most ceil((S-1)/2) squares - three at S = 7 as in [6] -
+ * then the 3x3 square of step 1).  Moves need a strictly smaller SAD; among
+ * the eight points of a pattern the first in row order wins ties.  `points`
+ * counts distinct positions evaluated; iters is written 0; t_field and seed
+ * are ignored.
  */
 int me_full_search(int method, const me_job *jobs, int n, const me_params *params, void *stream);
 
@@ -252,8 +257,10 @@ int me_motion_compensate_sse(const me_job *jobs, int n, uint8_t *const *pred, ui
  * me_batch_config writes the launch configuration in use (ncfg >= 4; a
  * fifth entry when ncfg >= 5): search workers, window staging (1 staged
  * plan, 0 generic), dependency-poll back-off (s_sleep units), MB blocks per
- * CU of the flat kernels, waves per line worker (1, or 2: one works ahead on
- * the next searched pair).
+ * CU of the flat kernels, waves per line worker (1, 2 or 4: the searched
+ * pairs of a line are dealt round-robin to its waves).  With
+ * ME_BATCH_AUTOTUNE a candidate whose run raises the device status word is
+ * dropped (ME_EDEVICE when no candidate runs cleanly).
  * me_batch_destroy waits for the batch's stream and frees it (NULL is a no-op).
  */
 typedef struct me_batch me_batch;
@@ -264,6 +271,22 @@ int me_batch_create(const me_job *jobs, int n, const me_params *params, uint32_t
 int me_batch_step(me_batch *b, const me_job *jobs, int n);
 int me_batch_results(me_batch *b, uint64_t *sse, uint64_t *npix, double *psnr_db, int n);
 int me_batch_config(const me_batch *b, int32_t *cfg, int ncfg);
+/* Force the launch configuration (ncfg == 5, same layout as me_batch_config):
+ * workers 1 .. min(lines, 16 x CUs / waves), staging 0 or 1 (1 needs a
+ * staging plan for this S), poll back-off 1, 2 or 4, flat MBs per CU 4, 8
+ * or 16, waves per line 1, 2 or 4; ME_EINVAL otherwise.  Every
+ * configuration computes the same results.  Waits for the batch's stream
+ * and re-captures the graph (with the kernel timing now in force). */
+int me_batch_set_config(me_batch *b, const int32_t *cfg, int ncfg);
+/* Kernel durations inside the batch's graph: when me_kernel_timing has kind
+ * k (ME_KT_CLASSIFY, ME_KT_SEARCH, ME_KT_MC, ME_KT_NET) on at the time the
+ * graph is captured (me_batch_create, me_batch_set_net, me_batch_set_config),
+ * every replay records an event pair around that kernel on the batch's
+ * stream (the frame step is then captured as several graphs, cut at the
+ * timed kernels, launched back to back with the events between them).
+ * Waits for the replays, writes the sum of their durations (ms) and their
+ * number, and restarts both at zero.  Zero counts when not timed. */
+int me_batch_kernel_time_ms(me_batch *b, int kind, double *total_ms, int *count);
 /* Seed the batch's searches with a proposal network (NULL detaches):
  * every step then runs the network on the opaque MBs between the
  * classification and the search, writing the jobs' seed buffers (so every

@@ -24,7 +24,7 @@ _SRC = os.path.join(_HERE, "me_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 TRANSPARENT, OPAQUE, BOUNDARY = 0, 1, 2
-ES, TSS, DS = 0, 1, 2
+ES, TSS, DS, FSS = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:
@@ -207,7 +207,7 @@ def pa_order(cur, ref, params: Params, order, cur_alpha=None, ref_alpha=None, cl
 
 
 def search(method, cur, ref, params: Params, cls=None):
-    """Baseline search (ES / TSS / DS) on one frame pair."""
+    """Baseline search (ES / TSS / DS / FSS) on one frame pair."""
     p, keep = _pair(cur, ref)
     H, W = keep[0].shape
     out = _outputs(H, W)

@@ -551,11 +551,54 @@ static void search_ds(const or_pair *fp, int S, int x0, int y0, memo *m, int *bx
     *bc = nc;
 }
 
-/* method 0 = exhaustive, 1 = three-step, 2 = diamond; texture SAD on every
- * non-transparent MB, starting at (0, 0). */
+/* Four-step search [6]: the 9-point pattern of step 2 (a 5 x 5 square)
+ * around the origin; while its best point is not the centre the centre moves
+ * there and the square is evaluated again, for at most n5 squares in all
+ * (three at S = 7: the reach 2 n5 + 1 of the squares plus the last step is
+ * then +-7; n5 = ceil((S - 1) / 2), at least one, in general); then the
+ * 3 x 3 square of step 1 around the centre.  Points of a square that were
+ * evaluated before are not counted again; moves need a strictly smaller SAD
+ * and the first point in row order wins ties. */
+static void search_4ss(const or_pair *fp, int S, int x0, int y0, memo *m, int *bx, int *by, uint32_t *bc) {
+    int n5 = S / 2; /* = ceil((S - 1) / 2) */
+    if (n5 < 1) n5 = 1;
+    int cx = 0, cy = 0;
+    uint32_t cc = or_sad(fp, x0, y0, 0, 0);
+    memo_visit(m, 0, 0);
+    for (int round = 0; round < n5 + 1; ++round) {
+        int step = round < n5 ? 2 : 1;
+        int nx = cx, ny = cy;
+        uint32_t nc = cc;
+        for (int j = -1; j <= 1; ++j) {
+            for (int i = -1; i <= 1; ++i) {
+                if (i == 0 && j == 0) continue;
+                int qx = cx + i * step, qy = cy + j * step;
+                if (!feasible(fp, S, x0, y0, qx, qy)) continue;
+                memo_visit(m, qx, qy);
+                uint32_t c = or_sad(fp, x0, y0, qx, qy);
+                if (c < nc) {
+                    nc = c;
+                    nx = qx;
+                    ny = qy;
+                }
+            }
+        }
+        int moved = nx != cx || ny != cy;
+        cx = nx;
+        cy = ny;
+        cc = nc;
+        if (step == 2 && !moved) round = n5 - 1; /* centre won: the step-1 square is next */
+    }
+    *bx = cx;
+    *by = cy;
+    *bc = cc;
+}
+
+/* method 0 = exhaustive, 1 = three-step, 2 = diamond, 3 = four-step; texture
+ * SAD on every non-transparent MB, starting at (0, 0). */
 int or_search(int method, const or_pair *fp, const uint8_t *cls, const or_params *p, int16_t *mv, int16_t *mv_int,
               uint32_t *cost, uint16_t *points) {
-    if (!fp || !p || !mv || !mv_int || method < 0 || method > 2) return -1;
+    if (!fp || !p || !mv || !mv_int || method < 0 || method > 3) return -1;
     if (fp->width % 16 || fp->height % 16 || fp->width <= 0 || fp->height <= 0) return -1;
     int wm = fp->width / 16, hm = fp->height / 16;
     int S = p->search_range;
@@ -576,8 +619,10 @@ int or_search(int method, const or_pair *fp, const uint8_t *cls, const or_params
                     memset(seen, 0, win);
                     if (method == 1)
                         search_tss(fp, S, 16 * h, 16 * v, &m, &bx, &by, &bc);
-                    else
+                    else if (method == 2)
                         search_ds(fp, S, 16 * h, 16 * v, &m, &bx, &by, &bc);
+                    else
+                        search_4ss(fp, S, 16 * h, 16 * v, &m, &bx, &by, &bc);
                     pts = m.count;
                 }
             }

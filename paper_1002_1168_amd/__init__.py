@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libme.so")
 
 ME_OK, ME_EINVAL, ME_EALIGN, ME_EHIP, ME_ENOMEM, ME_EEMPTY, ME_EDEVICE, ME_ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
 ME_MB_TRANSPARENT, ME_MB_OPAQUE, ME_MB_BOUNDARY = 0, 1, 2
-ME_ES, ME_TSS, ME_DS = 0, 1, 2
+ME_ES, ME_TSS, ME_DS, ME_4SS = 0, 1, 2, 3
 ME_KT_CLASSIFY, ME_KT_SEARCH, ME_KT_FULL, ME_KT_MC, ME_KT_NET, ME_KT_NET_TRAIN = 0, 1, 2, 3, 4, 5
 ME_BATCH_SHAPE, ME_BATCH_AUTOTUNE = 1, 2
 ME_NET_PARAMS = 10434
@@ -25,7 +25,7 @@ EXPORTED = ("me_default_params", "me_status_str", "me_shutdown", "me_classify_ba
             "me_shape_search", "me_full_search", "me_motion_compensate_psnr", "me_motion_compensate_sse",
             "me_device_status",
             "me_kernel_timing", "me_kernel_time_ms", "me_batch_create", "me_batch_step", "me_batch_results",
-            "me_batch_config", "me_batch_set_net", "me_batch_destroy", "me_net_create", "me_net_forward", "me_net_train_step",
+            "me_batch_config", "me_batch_set_config", "me_batch_kernel_time_ms", "me_batch_set_net", "me_batch_destroy", "me_net_create", "me_net_forward", "me_net_train_step",
             "me_net_weights", "me_net_destroy", "me_search_schedule")
 
 
@@ -97,6 +97,10 @@ def lib():
         L.me_batch_results.restype = i
         L.me_batch_config.argtypes = [vp, C.POINTER(C.c_int32), i]
         L.me_batch_config.restype = i
+        L.me_batch_set_config.argtypes = [vp, C.POINTER(C.c_int32), i]
+        L.me_batch_set_config.restype = i
+        L.me_batch_kernel_time_ms.argtypes = [vp, i, C.POINTER(C.c_double), C.POINTER(i)]
+        L.me_batch_kernel_time_ms.restype = i
         L.me_batch_set_net.argtypes = [vp, vp]
         L.me_batch_set_net.restype = i
         L.me_batch_destroy.argtypes = [vp]
@@ -262,6 +266,20 @@ class Batch:
         _check(lib().me_batch_config(self.handle, c, 5), "me_batch_config")
         return {"workers": c[0], "staging": "plan" if c[1] else "generic", "poll_sleep": c[2], "flat_per_cu": c[3],
                 "waves_per_line": c[4]}
+
+    def set_config(self, cfg: dict, check=True) -> int:
+        """Force the launch configuration (keys as returned by config())."""
+        c = (C.c_int32 * 5)(int(cfg["workers"]), 1 if cfg["staging"] == "plan" else 0, int(cfg["poll_sleep"]),
+                            int(cfg["flat_per_cu"]), int(cfg["waves_per_line"]))
+        rc = lib().me_batch_set_config(self.handle, c, 5)
+        return _check(rc, "me_batch_set_config") if check else rc
+
+    def kernel_time_ms(self, kind: int):
+        """-> (total ms, replays) of the kernel of ``kind`` inside the graph."""
+        ms, cnt = C.c_double(), C.c_int()
+        _check(lib().me_batch_kernel_time_ms(self.handle, int(kind), C.byref(ms), C.byref(cnt)),
+               "me_batch_kernel_time_ms")
+        return float(ms.value), int(cnt.value)
 
     def close(self) -> None:
         if self.handle:

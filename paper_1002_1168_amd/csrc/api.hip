@@ -268,6 +268,8 @@ int run_pa(const me_job *jobs, int n, const me_params *params, bool shape_only, 
 namespace me {
 namespace host {
 
+bool timing_enabled(int kind) { return kind >= 0 && kind < kTimerKinds && timing_on(kind); }
+
 bool kernel_timer(void *stream, int kind, KernelTimer *out) {
     if (kind < 0 || kind >= kTimerKinds || !timing_on(kind)) return false;
     Workspace *w = nullptr;
@@ -399,7 +401,7 @@ int me_shape_search(const me_job *jobs, int n, const me_params *params, void *st
 }
 
 int me_full_search(int method, const me_job *jobs, int n, const me_params *params, void *stream) {
-    if (method != ME_ES && method != ME_TSS && method != ME_DS) return ME_EINVAL;
+    if (method != ME_ES && method != ME_TSS && method != ME_DS && method != ME_4SS) return ME_EINVAL;
     if (n < 0 || (n > 0 && !jobs)) return ME_EINVAL;
     int rc = check_params(params);
     if (rc) return rc;

@@ -19,6 +19,19 @@
 using namespace me;
 using namespace me::host;
 
+// kinds of kernel timing a batch graph can carry: classification, search,
+// baselines (unused), MC, network forward
+constexpr int kBatchKinds = ME_KT_NET + 1;
+
+// One element of a captured frame step: a graph piece, or (exec null) the
+// start / stop event of a timed kernel kind.
+struct Piece {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int kind = -1;
+    bool start = false;
+};
+
 struct me_batch {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -33,8 +46,17 @@ struct me_batch {
     hipEvent_t ev[2] = {nullptr, nullptr};
     int slot = 0;
     unsigned long long *host_acc = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // The frame step as one graph; with kernel timing on at capture, as a
+    // sequence of graph pieces cut at the timed kernels, replayed with event
+    // records between the pieces (two event sets used alternately, so that
+    // one replay's events are read while the next runs).
+    std::vector<Piece> pieces;
+    uint32_t timed = 0;                           // bit k: kind k (ME_KT_*) is timed
+    KernelTimer tm[2][kBatchKinds];               // event pairs per set and kind
+    bool pending[2] = {false, false};             // a replay with event set i whose events are unread
+    double t_ms[kBatchKinds] = {0, 0, 0, 0, 0};
+    int t_count[kBatchKinds] = {0, 0, 0, 0, 0};
+    long long replays = 0;
     int32_t cfg[5] = {0, 1, 2, 8, 1};  // workers, window staging (1 plan, 0 generic), poll sleep, flat MBs/CU, waves per line
     me_net *net = nullptr;          // proposal network seeding the search (optional)
     uint8_t *net_scratch = nullptr;
@@ -133,26 +155,41 @@ KParams batch_kparams(const me_batch &b, int sleep) {
     return kp;
 }
 
-hipError_t launch_search(const me_batch &b, const Bufs &u, const int32_t *cfg, hipStream_t s) {
+hipError_t launch_search(const me_batch &b, const Bufs &u, const int32_t *cfg, hipStream_t s,
+                         const KernelTimer *t = nullptr) {
     hipError_t e = launch_fill_u32((uint32_t *)u.zero, b.zero_bytes / 4, 0u, s);
     if (e != hipSuccess) return e;
     return launch_pa(u.jobs, b.n, b.plan.total_mbs, u.chains, u.tickets, b.plan.nlines, u.progress, u.counter, u.masks,
-                     b.plan.mask_words, u.pscr, u.status, batch_kparams(b, cfg[2]), cfg[0], s, nullptr,
+                     b.plan.mask_words, u.pscr, u.status, batch_kparams(b, cfg[2]), cfg[0], s, t,
                      cfg[1] == 0, cfg[4]);
 }
 
-// The whole frame step with configuration `cfg` on stream `s`.
-hipError_t launch_step(const me_batch &b, const int32_t *cfg, hipStream_t s) {
+// The whole frame step with configuration `cfg` on stream `s`; `tm` (or
+// null): event pairs per timing kind, used for the kinds set in `timed`.
+hipError_t launch_step(const me_batch &b, const int32_t *cfg, hipStream_t s, const KernelTimer *tm = nullptr,
+                       uint32_t timed = 0) {
+    auto T = [&](int kind) -> const KernelTimer * { return tm && ((timed >> kind) & 1u) ? &tm[kind] : nullptr; };
     const Bufs u = bufs(b);
-    hipError_t e = launch_classify(u.jobs, b.n, b.plan.total_mbs, s, nullptr, cfg[3]);
+    hipError_t e = launch_classify(u.jobs, b.n, b.plan.total_mbs, s, T(ME_KT_CLASSIFY), cfg[3]);
     if (e != hipSuccess) return e;
     if (b.net) {
-        e = net_forward_table(b.net, u.jobs, b.n, b.plan.total_mbs, b.net_scratch, s);
+        e = net_forward_table(b.net, u.jobs, b.n, b.plan.total_mbs, b.net_scratch, s, T(ME_KT_NET));
         if (e != hipSuccess) return e;
     }
-    e = launch_search(b, u, cfg, s);
+    e = launch_search(b, u, cfg, s, T(ME_KT_SEARCH));
     if (e != hipSuccess) return e;
-    return launch_mc(u.jobs, b.n, b.plan.total_mbs, u.part, u.acc, u.status, s, nullptr, cfg[3]);
+    return launch_mc(u.jobs, b.n, b.plan.total_mbs, u.part, u.acc, u.status, s, T(ME_KT_MC), cfg[3]);
+}
+
+// Read and clear the device status word (blocking); true when it was clear.
+bool status_clear(const me_batch &b, const Bufs &u, bool *ok) {
+    uint32_t st = 0;
+    if (hipMemcpyAsync(&st, u.status, 4, hipMemcpyDeviceToHost, b.stream) != hipSuccess) return false;
+    if (hipStreamSynchronize(b.stream) != hipSuccess) return false;
+    *ok = st == 0;
+    if (st && (launch_fill_u32(u.status, 64, 0u, b.stream) != hipSuccess || hipStreamSynchronize(b.stream) != hipSuccess))
+        return false;
+    return true;
 }
 
 // Fastest of three timed runs of `fn` on the batch's stream (ms), or -1.
@@ -201,10 +238,15 @@ int autotune(me_batch &b) {
                     if (wavesn > 1 && sl != 1) continue;  // the several-wave worker polls with a fixed back-off
                     const int32_t c[5] = {w, st, sl, best[3], wavesn};
                     float ms = time_min(b, e0, e1, [&] { return launch_search(b, u, c, b.stream); });
-                    if (ms < 0.f) {
+                    bool clean = false;
+                    if (ms < 0.f || !status_clear(b, u, &clean)) {
                         rc = ME_EHIP;
                         break;
                     }
+                    // a candidate that raised the status word (a dependency wait
+                    // ran out) is dropped: its workers left early, so its time
+                    // says nothing
+                    if (!clean) continue;
                     if (best_ms < 0.f || ms < best_ms) {
                         best_ms = ms;
                         best[0] = w;
@@ -214,6 +256,7 @@ int autotune(me_batch &b) {
                     }
                 }
     }
+    if (rc == ME_OK && best_ms < 0.f) rc = ME_EDEVICE;  // no search configuration ran cleanly
     best_ms = -1.f;
     for (int pc : {4, 8, 16}) {
         if (rc) break;
@@ -222,8 +265,13 @@ int autotune(me_batch &b) {
             if (e != hipSuccess) return e;
             return launch_mc(u.jobs, b.n, b.plan.total_mbs, u.part, u.acc, u.status, b.stream, nullptr, pc);
         });
-        if (ms < 0.f) {
+        bool clean = false;
+        if (ms < 0.f || !status_clear(b, u, &clean)) {
             rc = ME_EHIP;
+            break;
+        }
+        if (!clean) {
+            rc = ME_EDEVICE;
             break;
         }
         if (best_ms < 0.f || ms < best_ms) {
@@ -238,29 +286,137 @@ int autotune(me_batch &b) {
     return rc;
 }
 
+void drop_graphs(me_batch &b) {
+    for (auto &p : b.pieces) {
+        if (p.exec) hipGraphExecDestroy(p.exec);
+        if (p.graph) hipGraphDestroy(p.graph);
+    }
+    b.pieces.clear();
+    b.pending[0] = b.pending[1] = false;
+}
+
+// Capture state while the frame step is recorded in pieces.
+struct CaptureCtx {
+    me_batch *b;
+    hipStream_t cs;
+    hipError_t err;
+};
+
+// End the capture in progress, keep it as a piece (unless it is empty), and
+// start the next one.
+hipError_t cut_piece(CaptureCtx &c) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c.cs, &g);
+    if (e != hipSuccess || !g) return e != hipSuccess ? e : hipErrorUnknown;
+    size_t nodes = 0;
+    e = hipGraphGetNodes(g, nullptr, &nodes);
+    if (e == hipSuccess && nodes > 0) {
+        Piece p;
+        p.graph = g;
+        e = hipGraphInstantiate(&p.exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(g);
+            return e;
+        }
+        c.b->pieces.push_back(p);
+    } else {
+        hipGraphDestroy(g);
+        if (e != hipSuccess) return e;
+    }
+    return hipStreamBeginCapture(c.cs, hipStreamCaptureModeRelaxed);
+}
+
+void split_at_mark(void *ctx, int kind, bool start, hipStream_t) {
+    CaptureCtx &c = *(CaptureCtx *)ctx;
+    if (c.err != hipSuccess) return;
+    c.err = cut_piece(c);
+    Piece p;
+    p.kind = kind;
+    p.start = start;
+    c.b->pieces.push_back(p);
+}
+
+// Sum the event pairs of event set i's last replay (waits for it).
+void harvest(me_batch &b, int i) {
+    if (!b.pending[i]) return;
+    b.pending[i] = false;
+    for (int k = 0; k < kBatchKinds; ++k) {
+        if (!((b.timed >> k) & 1u)) continue;
+        float ms = 0.f;
+        if (hipEventSynchronize(b.tm[i][k].stop) == hipSuccess &&
+            hipEventElapsedTime(&ms, b.tm[i][k].start, b.tm[i][k].stop) == hipSuccess) {
+            b.t_ms[k] += ms;
+            b.t_count[k]++;
+        }
+    }
+}
+
+// Capture the frame step: one graph, or (kernel timing on for some kinds
+// now) graph pieces cut at those kinds' kernels.  Waits for the stream first
+// (earlier replays' events are harvested).
 int capture(me_batch &b) {
+    if (hipStreamSynchronize(b.stream) != hipSuccess) return ME_EHIP;
+    for (int i = 0; i < 2; ++i) harvest(b, i);
+    drop_graphs(b);
+    b.timed = 0;
+    for (int k = 0; k < kBatchKinds; ++k)
+        if (k != ME_KT_FULL && timing_enabled(k) && (k != ME_KT_NET || b.net)) b.timed |= 1u << k;
+    for (int i = 0; i < (b.timed ? 2 : 0); ++i)
+        for (int k = 0; k < kBatchKinds; ++k) {
+            if (!((b.timed >> k) & 1u) || b.tm[i][k].start) continue;
+            if (hipEventCreate(&b.tm[i][k].start) != hipSuccess || hipEventCreate(&b.tm[i][k].stop) != hipSuccess)
+                return ME_EHIP;
+        }
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return ME_EHIP;
+    CaptureCtx ctx{&b, cs, hipSuccess};
+    KernelTimer marks[kBatchKinds];
+    for (int k = 0; k < kBatchKinds; ++k) {
+        marks[k].split = split_at_mark;
+        marks[k].ctx = &ctx;
+        marks[k].kind = k;
+    }
     int rc = ME_OK;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
         rc = ME_EHIP;
     } else {
-        hipError_t e = launch_step(b, b.cfg, cs);
-        hipGraph_t g = nullptr;
-        hipError_t e2 = hipStreamEndCapture(cs, &g);
-        if (e != hipSuccess || e2 != hipSuccess || !g) {
-            rc = ME_EHIP;
-            if (g) hipGraphDestroy(g);
-        } else if (hipGraphInstantiate(&b.exec, g, nullptr, nullptr, 0) != hipSuccess) {
-            rc = ME_EHIP;
-            hipGraphDestroy(g);
-            b.exec = nullptr;
+        hipError_t e = launch_step(b, b.cfg, cs, marks, b.timed);
+        if (e == hipSuccess) e = ctx.err;
+        if (e == hipSuccess) {
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(cs, &g);
+            if (e == hipSuccess && g) {
+                Piece p;
+                p.graph = g;
+                e = hipGraphInstantiate(&p.exec, g, nullptr, nullptr, 0);
+                if (e == hipSuccess) {
+                    b.pieces.push_back(p);
+                } else {
+                    hipGraphDestroy(g);
+                }
+            } else if (e == hipSuccess) {
+                e = hipErrorUnknown;
+            }
         } else {
-            b.graph = g;
+            hipGraph_t g = nullptr;
+            if (hipStreamEndCapture(cs, &g) == hipSuccess && g) hipGraphDestroy(g);
         }
+        if (e != hipSuccess) rc = ME_EHIP;
     }
     hipStreamDestroy(cs);
+    if (rc) drop_graphs(b);
     return rc;
+}
+
+// One replay of the captured frame step on the batch's stream (event set
+// `set` for the timed kinds).
+hipError_t replay(me_batch &b, int set) {
+    for (const Piece &p : b.pieces) {
+        hipError_t e = p.exec ? hipGraphLaunch(p.exec, b.stream)
+                              : hipEventRecord(p.start ? b.tm[set][p.kind].start : b.tm[set][p.kind].stop, b.stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 int upload_table(me_batch &b, const me_job *jobs) {
@@ -278,8 +434,12 @@ int upload_table(me_batch &b, const me_job *jobs) {
 void release(me_batch *b) {
     if (!b) return;
     if (b->stream || b->dev) hipStreamSynchronize(b->stream);
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    drop_graphs(*b);
+    for (auto &row : b->tm)
+        for (auto &t : row) {
+            if (t.start) hipEventDestroy(t.start);
+            if (t.stop) hipEventDestroy(t.stop);
+        }
     for (int s = 0; s < 2; ++s) {
         if (b->ev[s]) hipEventDestroy(b->ev[s]);
         if (b->host[s]) hipHostFree(b->host[s]);
@@ -391,7 +551,11 @@ int me_batch_step(me_batch *b, const me_job *jobs, int n) {
     if (rc) return rc;
     rc = upload_table(*b, jobs);
     if (rc) return rc;
-    if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return ME_EHIP;
+    const int set = (int)(b->replays & 1);
+    harvest(*b, set);  // that event set's previous replay (the other one may still run)
+    if (replay(*b, set) != hipSuccess) return ME_EHIP;
+    b->pending[set] = b->timed != 0;
+    b->replays++;
     b->stepped = true;
     return ME_OK;
 }
@@ -444,10 +608,6 @@ int me_batch_set_net(me_batch *b, me_net *net) {
         b->net_scratch = nullptr;
         return ME_ENOMEM;
     }
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
     b->net = net;
     return capture(*b);
 }
@@ -455,6 +615,33 @@ int me_batch_set_net(me_batch *b, me_net *net) {
 int me_batch_config(const me_batch *b, int32_t *cfg, int ncfg) {
     if (!b || !cfg || ncfg < 4) return ME_EINVAL;
     for (int i = 0; i < std::min(ncfg, 5); ++i) cfg[i] = b->cfg[i];
+    return ME_OK;
+}
+
+int me_batch_set_config(me_batch *b, const int32_t *cfg, int ncfg) {
+    if (!b || !cfg || ncfg != 5) return ME_EINVAL;
+    std::lock_guard<std::mutex> lk(b->mu);
+    const int nlines = b->plan.nlines;
+    const int waves = cfg[4];
+    if (waves != 1 && waves != 2 && waves != 4) return ME_EINVAL;
+    // persistent workers: any count up to one per line (and the wave budget)
+    if (cfg[0] < 1 || cfg[0] > std::min(nlines, pa_worker_cap() / waves)) return ME_EINVAL;
+    if (cfg[1] != 0 && cfg[1] != 1) return ME_EINVAL;
+    if (cfg[1] == 0 && plan_elems(b->params.search_range) <= 0) return ME_EINVAL;
+    if (cfg[2] != 1 && cfg[2] != 2 && cfg[2] != 4) return ME_EINVAL;
+    if (cfg[3] != 4 && cfg[3] != 8 && cfg[3] != 16) return ME_EINVAL;
+    for (int i = 0; i < 5; ++i) b->cfg[i] = cfg[i];
+    return capture(*b);
+}
+
+int me_batch_kernel_time_ms(me_batch *b, int kind, double *total_ms, int *count) {
+    if (!b || !total_ms || !count || kind < 0 || kind >= kBatchKinds) return ME_EINVAL;
+    std::lock_guard<std::mutex> lk(b->mu);
+    for (int i = 0; i < 2; ++i) harvest(*b, i);
+    *total_ms = b->t_ms[kind];
+    *count = b->t_count[kind];
+    b->t_ms[kind] = 0.0;
+    b->t_count[kind] = 0;
     return ME_OK;
 }
 

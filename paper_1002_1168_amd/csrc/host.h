@@ -57,11 +57,13 @@ int build_pa(const me_job *jobs, int n, PaMemo &m);
 // Event pair for the main kernel of a call of timing kind `kind` (ME_KT_*)
 // on `stream`; false when timing is off.
 bool kernel_timer(void *stream, int kind, KernelTimer *out);
+// Whether calls of timing kind `kind` (ME_KT_*) record kernel events now.
+bool timing_enabled(int kind);
 // Network seeds for a job table already on the device (graph-capturable);
 // `scratch` holds net_table_scratch(total_mbs) bytes.
 size_t net_table_scratch(int total_mbs);
 hipError_t net_forward_table(me_net *net, const JobDesc *table, int n, int total_mbs, uint8_t *scratch,
-                             hipStream_t s);
+                             hipStream_t s, const KernelTimer *t = nullptr);
 // Proposal-network seeds into every job's seed buffer (all must be set).
 int net_seed_jobs(me_net *net, const me_job *jobs, int n, void *stream);
 

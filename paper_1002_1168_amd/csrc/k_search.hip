@@ -1,6 +1,7 @@
-// Baseline block matching (Section 1 references [5], [7]; Tables 1-2):
-// exhaustive search (ES), three-step search (TSS), diamond search (DS), on the
-// luma of every non-transparent MB.  No inter-MB dependency: flat grids.
+// Baseline block matching (Section 1 references [5], [6], [7]; Tables 1-2):
+// exhaustive search (ES), three-step search (TSS), four-step search (4SS) and
+// diamond search (DS) on the luma of every non-transparent MB.  No inter-MB
+// dependency: flat grids.
 #include <algorithm>
 
 #include "me_internal.h"
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, con
     }
 }
 
-// TSS / DS.  One wave per MB; each round's candidates are evaluated together
+// TSS / 4SS / DS.  One wave per MB; each round's candidates are evaluated together
 // (lane = row j, quad q; 4 pixels per lane, unaligned dword loads from the
 // L2-resident reference), partial SADs packed two per reduction.  A bitmap of
 // evaluated positions in LDS counts distinct search points.
@@ -306,6 +307,40 @@ __global__ __launch_bounds__(64) void tss_ds_kernel(const JobDesc *jobs, const u
             cx = nx;
             cy = ny;
             cc = nc;
+        }
+    } else if (method == ME_4SS) {
+        // squares of step 2 until the centre wins (at most ceil((S-1)/2) of
+        // them, three at S = 7), then the square of step 1
+        const int n5 = max(S / 2, 1);
+        for (int round = 0; round <= n5; ++round) {
+            const int stp = round < n5 ? 2 : 1;
+            int ox[8], oy[8];
+            int i = 0;
+#pragma unroll
+            for (int jj = -1; jj <= 1; ++jj)
+#pragma unroll
+                for (int ii = -1; ii <= 1; ++ii)
+                    if (ii || jj) {
+                        ox[i] = cx + ii * stp;
+                        oy[i] = cy + jj * stp;
+                        ++i;
+                    }
+            uint32_t c[8];
+            eval_pts<8>(m, ox, oy, c);
+            int nx = cx, ny = cy;
+            uint32_t nc = cc;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (c[q] < nc) {
+                    nc = c[q];
+                    nx = ox[q];
+                    ny = oy[q];
+                }
+            const bool moved = nx != cx || ny != cy;
+            cx = nx;
+            cy = ny;
+            cc = nc;
+            if (stp == 2 && !moved) round = n5 - 1;  // the centre won: the step-1 square is next
         }
     } else {
         for (int guard = 0; guard < 65536; ++guard) {

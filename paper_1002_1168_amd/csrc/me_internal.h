@@ -53,12 +53,23 @@ struct KParams {
 enum : uint32_t { ST_SPIN_TIMEOUT = 1u, ST_BAD_CLASS = 2u, ST_ABORT = 4u };
 
 // ------------------------------------------------------------- launches
-// Optional event pair recorded around the main kernel of a launch (profiling).
+// Optional event pair recorded around the main kernel of a launch
+// (profiling).  With `split` set the launch is being captured into a graph:
+// events recorded during capture add no graph node, so the mark calls
+// split(ctx, kind, start, s) instead, which cuts the capture there; the
+// graph's owner then records the events between the launches of the pieces.
 struct KernelTimer {
     hipEvent_t start = nullptr, stop = nullptr;
+    void (*split)(void *ctx, int kind, bool start, hipStream_t s) = nullptr;
+    void *ctx = nullptr;
+    int kind = 0;
 };
 inline void timer_mark(const KernelTimer *t, bool start, hipStream_t s) {
-    if (t) (void)hipEventRecord(start ? t->start : t->stop, s);
+    if (!t) return;
+    if (t->split)
+        t->split(t->ctx, t->kind, start, s);
+    else
+        (void)hipEventRecord(start ? t->start : t->stop, s);
 }
 
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);

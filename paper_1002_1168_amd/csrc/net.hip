@@ -146,14 +146,15 @@ int net_seed_jobs(me_net *net, const me_job *jobs, int n, void *stream) {
 size_t net_table_scratch(int total_mbs) { return net_list_scratch(total_mbs); }
 
 // Seeds for an already uploaded job table (used inside captured graphs: no
-// allocation, no host synchronisation, no timing events).
+// allocation, no host synchronisation; `t` = events captured around the
+// forward kernel, or none).
 hipError_t net_forward_table(me_net *net, const JobDesc *table, int n, int total_mbs, uint8_t *scratch,
-                             hipStream_t s) {
+                             hipStream_t s, const KernelTimer *t) {
     const uint32_t *list = nullptr, *count = nullptr;
     hipError_t e = launch_net_list(table, n, total_mbs, scratch, &list, &count, s);
     if (e != hipSuccess) return e;
     const int groups = (int)std::min<long long>(total_mbs, (long long)net->cus * 3);
-    return launch_net(false, table, n, list, count, net->P, net->wb, nullptr, groups, s);
+    return launch_net(false, table, n, list, count, net->P, net->wb, nullptr, groups, s, t);
 }
 
 }  // namespace host

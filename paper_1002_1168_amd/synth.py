@@ -380,19 +380,25 @@ def cif_training_set(seed: int, count: int, frames: int = 30) -> list[Sequence]:
     return out
 
 
-def hd_streams(seed: int = 5, frames: int = 60, streams: int = 8) -> list[Sequence]:
-    """1920x1088 streams, 3..6 VOPs with occlusion, real velocities
-    U[-24, 24]^2 rendered bilinearly, search range 32, half-pel."""
+def _hd_one(args) -> Sequence:
+    s, frames, i = args
     W, H = HD1088
+    return make_sequence(s, W, H, frames, _random_vop_shapes(3, 6, W, H, 0.08, 0.25),
+                         "subpel", 24.0, 32, pan_speed=0, half_pel=True, name=f"hd{i}")
+
+
+def hd_streams(seed: int = 5, frames: int = 60, streams: int = 8, workers: int = 1) -> list[Sequence]:
+    """1920x1088 streams, 3..6 VOPs with occlusion, real velocities
+    U[-24, 24]^2 rendered bilinearly, search range 32, half-pel.  Each
+    stream is a pure function of its own seed, so ``workers`` > 1 renders
+    the streams in forked processes with the same bytes."""
     ss = np.random.SeedSequence(seed)
-    out = []
-    for i in range(streams):
-        s = int(ss.spawn(1)[0].generate_state(1)[0])
-        out.append(make_sequence(s, W, H, frames,
-                                 _random_vop_shapes(3, 6, W, H, 0.08, 0.25),
-                                 "subpel", 24.0, 32, pan_speed=0, half_pel=True,
-                                 name=f"hd{i}"))
-    return out
+    args = [(int(ss.spawn(1)[0].generate_state(1)[0]), frames, i) for i in range(streams)]
+    if workers <= 1 or streams <= 1:
+        return [_hd_one(a) for a in args]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(min(workers, streams)) as pool:
+        return pool.map(_hd_one, args, chunksize=1)
 
 
 def random_frames(seed: int, W: int, H: int, frames: int = 2, vops: int = 0,

@@ -89,7 +89,7 @@ def test_bad_jobs():
     assert me.me_texture_recursive([a, b], p, check=False) == me.ME_EINVAL
     c = job(mv=FAKE + 8192)
     assert me.me_texture_recursive([job(), c], p, check=False) == me.ME_EINVAL                  # shared mv_int
-    assert me.me_full_search(3, [job()], p, check=False) == me.ME_EINVAL
+    assert me.me_full_search(4, [job()], p, check=False) == me.ME_EINVAL
     assert me.me_texture_recursive([job()], p, net=C.c_void_p(FAKE), check=False) == me.ME_EINVAL
 
 

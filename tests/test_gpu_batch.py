@@ -212,3 +212,95 @@ def test_batch_with_proposal_network(torch_cuda):
                                  seeds=list(seeds[u].cpu().numpy()))
         want = {k: np.stack([r[k] for r in res]) for k in ("mv", "mv_int", "cost", "iters", "points")}
         assert_same(st.out[u].host(), want, f"net batch unit {u} vs oracle")
+
+
+def forced_configs(nlines, cap16, plan_ok):
+    """Every launch configuration the autotuner can pick for a batch of
+    `nlines` lines: waves 1 / 2 / 4, workers cap, cap/2, cap/4 (at least 1),
+    staging plan / generic, poll back-off 1 / 2 / 4 (one-wave workers only)."""
+    out = []
+    for waves in (1, 2, 4):
+        cap = min(nlines, cap16 // waves)
+        for w in sorted({cap, max(cap // 2, 1), max(cap // 4, 1)}, reverse=True):
+            for staging in (("plan", "generic") if plan_ok else ("generic",)):
+                for sleep in ((1, 2, 4) if waves == 1 else (1,)):
+                    out.append({"workers": w, "staging": staging, "poll_sleep": sleep, "flat_per_cu": 8,
+                                "waves_per_line": waves})
+    return out
+
+
+def test_batch_every_forced_config_matches_oracle(torch_cuda):
+    # the configurations the autotuner chooses between, each forced and
+    # checked against the oracle on the same mixed-size streams (the generic
+    # staging loop and the reduced worker counts included)
+    import torch
+    from paper_1002_1168_amd.device import stream_handle
+    seqs = synth.mixed_streams(seed=26, frames=3, counts=(1, 1, 1))
+    st = Streams(seqs, 2, rect=(1,))
+    p = me.me_default_params(search_range=16)
+    want = st.oracle(p)
+    s = stream_handle()
+    b = me.Batch(st.jobs(0), p, 0, stream=s)
+    try:
+        cap16 = torch.cuda.get_device_properties(0).multi_processor_count * 16
+        nlines = sum(st.ds[si].hm * st.ds[si].wm for si, _ in st.units)
+        cfgs = forced_configs(nlines, cap16, plan_ok=True)
+        assert len(cfgs) >= 20
+        for cfg in cfgs:
+            say("forced config", cfg)
+            b.set_config(cfg)
+            assert b.config() == cfg
+            for i in range(st.pairs):
+                for o in st.out:   # a stale result must not pass (pair i only: i-1 is this step's T)
+                    o.mv[i].fill_(0x5555)
+                    o.mv_int[i].fill_(0x5555)
+                b.step(st.jobs(i))
+                sums = b.results(check=False)
+                assert sums[3] in (me.ME_OK, me.ME_EEMPTY), (cfg, sums[3])
+                check_step(st, i, want, sums, f"forced {cfg}")
+        bad = dict(cfgs[0], waves_per_line=3)
+        assert b.set_config(bad, check=False) == me.ME_EINVAL
+        bad = dict(cfgs[0], workers=0)
+        assert b.set_config(bad, check=False) == me.ME_EINVAL
+    finally:
+        b.close()
+    torch.cuda.synchronize()
+
+
+def test_batch_graph_kernel_timing(torch_cuda):
+    # with timing on at capture, every replay records the search and MC
+    # kernels' events inside the graph; the sums count every replay
+    import torch
+    from paper_1002_1168_amd.device import stream_handle
+    seqs = synth.mixed_streams(seed=27, frames=3, counts=(1, 1, 0))
+    st = Streams(seqs, 2)
+    p = me.me_default_params(search_range=16)
+    s = stream_handle()
+    me.me_kernel_timing(True, kinds=[me.ME_KT_SEARCH, me.ME_KT_MC])
+    try:
+        b = me.Batch(st.jobs(0), p, 0, stream=s)
+    finally:
+        me.me_kernel_timing(False)
+    try:
+        for r in range(5):
+            b.step(st.jobs(r % st.pairs))
+        ms, cnt = b.kernel_time_ms(me.ME_KT_SEARCH)
+        ms_mc, cnt_mc = b.kernel_time_ms(me.ME_KT_MC)
+        assert cnt == 5 and cnt_mc == 5, (cnt, cnt_mc)
+        assert 0 < ms < 1000 and 0 < ms_mc < 1000
+        assert b.kernel_time_ms(me.ME_KT_CLASSIFY) == (0.0, 0)   # not timed
+        assert b.kernel_time_ms(me.ME_KT_SEARCH) == (0.0, 0)     # restarted
+        # results are unchanged by the timing nodes
+        want = st.oracle(p)
+        for i in range(st.pairs):
+            b.step(st.jobs(i))
+            sums = b.results(check=False)
+            check_step(st, i, want, sums, "timed graph")
+        assert b.kernel_time_ms(me.ME_KT_SEARCH)[1] == st.pairs
+        # re-capture without timing: one graph, nothing recorded
+        b.set_config(b.config())
+        b.step(st.jobs(0))
+        assert b.kernel_time_ms(me.ME_KT_SEARCH) == (0.0, 0)
+    finally:
+        b.close()
+    torch.cuda.synchronize()

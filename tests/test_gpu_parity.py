@@ -187,25 +187,25 @@ def check_search(seq, method, S, pairs, vop=0):
         assert (got["iters"][i] == 0).all()
 
 
-@pytest.mark.parametrize("method", [me.ME_ES, me.ME_TSS, me.ME_DS])
+@pytest.mark.parametrize("method", [me.ME_ES, me.ME_TSS, me.ME_DS, me.ME_4SS])
 def test_search_qcif(torch_cuda, method):
     seq = synth.qcif_ellipse()
     check_search(seq, method, 7, seq.frames - 1)
     check_search(seq, method, 7, 3, vop=None)
 
 
-@pytest.mark.parametrize("method", [me.ME_ES, me.ME_TSS, me.ME_DS])
+@pytest.mark.parametrize("method", [me.ME_ES, me.ME_TSS, me.ME_DS, me.ME_4SS])
 def test_search_cif(torch_cuda, method):
     check_search(synth.cif_two_vops(frames=4), method, 16, 3, vop=None)
 
 
-@pytest.mark.parametrize("method", [me.ME_ES, me.ME_TSS, me.ME_DS])
+@pytest.mark.parametrize("method", [me.ME_ES, me.ME_TSS, me.ME_DS, me.ME_4SS])
 @pytest.mark.parametrize("S", [1, 4, 13])
 def test_search_random_tiny(torch_cuda, method, S):
     check_search(synth.random_frames(8, 64, 48, frames=3, vops=1), method, S, 2)
 
 
-@pytest.mark.parametrize("method", [me.ME_ES, me.ME_TSS, me.ME_DS])
+@pytest.mark.parametrize("method", [me.ME_ES, me.ME_TSS, me.ME_DS, me.ME_4SS])
 def test_search_s32_crop(torch_cuda, method):
     seq = synth.hd_streams(frames=2, streams=1)[0]
     seq.luma = np.ascontiguousarray(seq.luma[:, 256:512, 640:960])

@@ -484,6 +484,55 @@ def test_tss_step_sizes_and_bound(orc):
     assert (orc.search(orc.TSS, f[0], f[0], orc.Params(search_range=16))["points"][2:-2, 2:-2] == 41).all()
 
 
+def test_fss_identical_frames_point_counts(orc):
+    # four-step search [6] on identical frames: the centre wins the first
+    # 5 x 5 square at once, then the 3 x 3 square: 1 + 8 + 8 = 17 points
+    for S in (7, 16):
+        f = synth.qcif_ellipse(frames=1).luma[0]
+        out = orc.search(orc.FSS, f, f, orc.Params(search_range=S))
+        assert (out["mv"] == 0).all() and (out["cost"] == 0).all()
+        assert (out["points"][2:-2, 2:-2] == 17).all() and out["points"].max() <= 17
+
+
+def stripe_pair(d, axis, W=128, H=96):
+    """cur = ref shifted by d on a ramp along one axis (ref = 20 + x, or
+    20 + y): the SAD of a candidate is 256 |d - d'| along that axis and does
+    not depend on the other, so every search move is decided by the
+    row-order tie rule across the other axis."""
+    y, x = np.mgrid[0:H, 0:W]
+    if axis == 0:
+        return (20 + x + d).astype(np.uint8), (20 + x).astype(np.uint8)
+    return (20 + y + d).astype(np.uint8), (20 + y).astype(np.uint8)
+
+
+# (S, axis, shift, final vector, points), worked by hand from the four-step
+# rules: a square whose best column (row) lies 2 away moves to the first
+# point of that column (row) in row order, i.e. a corner: 5 new points; a tie
+# with the centre keeps it; the step-1 square adds 8 new points.
+@pytest.mark.parametrize("S,axis,shift,final,pts", [
+    (7, 0, 6, (6, -6), 9 + 5 + 5 + 8),     # three corner moves up-right, centre column wins the 3x3
+    (7, 0, -3, (-3, -3), 9 + 5 + 8),       # one corner move, tie keeps the centre, 3x3 picks (-3, -3)
+    (7, 1, 6, (-6, 6), 9 + 5 + 5 + 8),     # ties across x go to the first (leftmost) column
+    (7, 0, 1, (1, -1), 9 + 8),             # centre wins the first square
+    (16, 0, 11, (11, -11), 9 + 4 * 5 + 5 + 8),  # five moves: more than the textbook's three squares
+])
+def test_fss_stripe_closed_form(orc, S, axis, shift, final, pts):
+    cur, ref = stripe_pair(shift, axis)
+    out = orc.search(orc.FSS, cur, ref, orc.Params(search_range=S))
+    for v in (1, 2, 3):
+        for h in range(1, 6):
+            assert tuple(out["mv_int"][v, h]) == (2 * final[0], 2 * final[1]), (v, h, out["mv_int"][v, h])
+            assert out["cost"][v, h] == 0
+            assert out["points"][v, h] == pts, (v, h, out["points"][v, h])
+
+
+def test_fss_bound_at_s7(orc):
+    # at most 9 + 5 + 5 + 8 = 27 distinct points per MB at +-7
+    f = synth.qcif_ellipse(frames=3).luma
+    for t in (1, 2):
+        assert orc.search(orc.FSS, f[t], f[t - 1], orc.Params(search_range=7))["points"].max() <= 27
+
+
 # ----------------------------------------------------------- half-sample
 def test_half_pel_constant_image_keeps_integer_vector(orc):
     f = np.full((64, 64), 77, np.uint8)
