@@ -225,6 +225,23 @@ int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, u
 int me_motion_compensate_sse(const me_job *jobs, int n, uint8_t *const *pred, uint64_t *sums, void *stream);
 
 /*
+ * me_motion_compensate_sse for callers that cannot allocate (code under HIP
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same prediction, masked SSE and per-job sums (same arguments, errors and
+ * results), with the job table, the per-MB partial sums and the status slot
+ * in a fixed array in device memory - one per GPU, about 4.2 MiB, held until
+ * the process ends - so that no call allocates anything.  The job table is
+ * passed to the device as kernel arguments.  Limits: n <= 1024 jobs and at
+ * most 524288 MBs in all (ME_EINVAL beyond).  Every call on a GPU shares
+ * that GPU's array: calls that overlap on one GPU (other streams, other host
+ * threads) race; calls in order on one stream do not.  Not reported here: a
+ * class byte above 2 (me_motion_compensate_sse raises the device status
+ * word for it); kernel timing does not apply.
+ */
+int me_motion_compensate_sse_noalloc(const me_job *jobs, int n, uint8_t *const *pred, uint64_t *sums,
+                                     void *stream);
+
+/*
  * Batched frame step: many frame pairs (VOP streams of any sizes) per launch,
  * replayed once per frame step as one HIP graph (Fig. 1 applied to every job
  * of the step; classification as in me_classify_babs, search as in

@@ -23,7 +23,7 @@ ME_NET_PARAMS = 10434
 
 EXPORTED = ("me_default_params", "me_status_str", "me_shutdown", "me_classify_babs", "me_texture_recursive",
             "me_shape_search", "me_full_search", "me_motion_compensate_psnr", "me_motion_compensate_sse",
-            "me_device_status",
+            "me_motion_compensate_sse_noalloc", "me_device_status",
             "me_kernel_timing", "me_kernel_time_ms", "me_batch_create", "me_batch_step", "me_batch_results",
             "me_batch_config", "me_batch_set_config", "me_batch_kernel_time_ms", "me_batch_set_net", "me_batch_destroy", "me_net_create", "me_net_forward", "me_net_train_step",
             "me_net_weights", "me_net_destroy", "me_search_schedule")
@@ -83,6 +83,8 @@ def lib():
         L.me_motion_compensate_psnr.restype = i
         L.me_motion_compensate_sse.argtypes = [C.POINTER(me_job), i, C.POINTER(vp), vp, vp]
         L.me_motion_compensate_sse.restype = i
+        L.me_motion_compensate_sse_noalloc.argtypes = [C.POINTER(me_job), i, C.POINTER(vp), vp, vp]
+        L.me_motion_compensate_sse_noalloc.restype = i
         L.me_device_status.argtypes = [vp]
         L.me_device_status.restype = i
         L.me_kernel_timing.argtypes = [i]
@@ -212,6 +214,14 @@ def me_motion_compensate_sse(jobs, sums, pred=None, stream=None, check=True) -> 
     pa = None if pred is None else _arr(C.c_void_p, pred)[0]
     rc = lib().me_motion_compensate_sse(ja, n, pa, sums, stream)
     return _check(rc, "me_motion_compensate_sse") if check else rc
+
+
+def me_motion_compensate_sse_noalloc(jobs, sums, pred=None, stream=None, check=True) -> int:
+    """As me_motion_compensate_sse, with no allocation (fixed device scratch)."""
+    ja, n = _arr(me_job, jobs)
+    pa = None if pred is None else _arr(C.c_void_p, pred)[0]
+    rc = lib().me_motion_compensate_sse_noalloc(ja, n, pa, sums, stream)
+    return _check(rc, "me_motion_compensate_sse_noalloc") if check else rc
 
 
 def me_device_status(stream=None) -> int:

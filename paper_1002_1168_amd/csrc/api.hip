@@ -450,18 +450,8 @@ int mc_descs(const me_job *jobs, int n, uint8_t *const *pred, std::vector<JobDes
     desc.resize(n);
     long long t = 0;
     for (int i = 0; i < n; ++i) {
-        const me_job &j = jobs[i];
-        int rc = check_frame(j.cur, false);
+        int rc = mc_desc(jobs[i], pred ? pred[i] : nullptr, &desc[i]);
         if (rc) return rc;
-        rc = check_frame(j.ref, false);
-        if (rc) return rc;
-        if (j.cur.width != j.ref.width || j.cur.height != j.ref.height || j.cur.stride != j.ref.stride)
-            return ME_EINVAL;
-        if (!j.mv) return ME_EINVAL;
-        if (!al4(j.mv)) return ME_EALIGN;
-        if (pred && pred[i] && !al4(pred[i])) return ME_EALIGN;
-        desc[i] = job_desc(j);
-        desc[i].out_u8 = pred ? pred[i] : nullptr;
         desc[i].mb_base = (int32_t)t;
         t += (long long)desc[i].wm * desc[i].hm;
     }

@@ -52,6 +52,9 @@ int check_params(const me_params *p);
 int check_job(const me_job &j, bool need_alpha);
 KParams kparams(const me_params *p, bool shape_only);
 JobDesc job_desc(const me_job &j);
+// Checked descriptor of one motion-compensation job (prediction out `pred`,
+// nullable); mb_base is left 0.
+int mc_desc(const me_job &j, uint8_t *pred, JobDesc *out);
 // Chains, chain-ordered descriptors and the ticket order of a job set.
 int build_pa(const me_job *jobs, int n, PaMemo &m);
 // Event pair for the main kernel of a call of timing kind `kind` (ME_KT_*)

@@ -101,6 +101,20 @@ JobDesc job_desc(const me_job &j) {
     return d;
 }
 
+int mc_desc(const me_job &j, uint8_t *pred, JobDesc *out) {
+    int rc = check_frame(j.cur, false);
+    if (rc) return rc;
+    rc = check_frame(j.ref, false);
+    if (rc) return rc;
+    if (j.cur.width != j.ref.width || j.cur.height != j.ref.height || j.cur.stride != j.ref.stride) return ME_EINVAL;
+    if (!j.mv) return ME_EINVAL;
+    if (!al4(j.mv)) return ME_EALIGN;
+    if (pred && !al4(pred)) return ME_EALIGN;
+    *out = job_desc(j);
+    out->out_u8 = pred;
+    return ME_OK;
+}
+
 int build_pa(const me_job *jobs, int n, PaMemo &m) {
     // chains: a job whose T field is the mv_int of an earlier job follows it
     std::unordered_map<const void *, int> producer;
