@@ -606,7 +606,7 @@ def main():
     if kern == "pa_kernel":
         roof = search_roofline(r, "pa_kernel<28>", measured_traffic(
             "pa_kernel<28>", ("paper_1002_1168_amd/csrc/k_pa.hip", "paper_1002_1168_amd/csrc/me_internal.h"),
-            "profiles/pa_kernel_traffic_hd1920x1088_8streams_S32_halfpel.md"))
+            "profiles/pa_kernel_hd1920x1088_8streams_S32_halfpel.md"))
     else:
         roof = {"kernel": kern, "kernel_ms": r["dominant_kernel_ms"], "bound": None, "achieved": None,
                 "peak": None, "unit": None, "frac": None, "traffic": None}
