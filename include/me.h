@@ -79,8 +79,14 @@ typedef struct me_params {
                              when any job carries seeds (a dropped seed counts both recursions, and
                              `iters` is a byte), ME_EINVAL otherwise */
     int32_t half_pel;     /* 1: half-sample refinement of texture MBs after the recursion (Section 4) */
-    uint32_t flags;       /* reserved, must be 0 */
+    uint32_t flags;       /* ME_FLAG_* bits below; others must be 0 */
 } me_params;
+
+/* me_params.flags */
+#define ME_FLAG_LINE_WORKERS 0x100u /* schedule the proposed search with line workers (one MB position
+                                       across a chain's pairs) even when no job's T field is written in
+                                       the same call, where row workers (one MB row per wave) are the
+                                       default; the results are the same */
 
 /* One frame pair of one VOP (the unit of Fig. 1's outer loops). */
 typedef struct me_job {
@@ -271,11 +277,13 @@ int me_motion_compensate_sse_noalloc(const me_job *jobs, int n, uint8_t *const *
  * me_motion_compensate_psnr), ME_EEMPTY if a job has no VOP pixel,
  * ME_EDEVICE if a kernel raised the device status word (then cleared).
  *
- * me_batch_config writes the launch configuration in use (ncfg >= 4; a
- * fifth entry when ncfg >= 5): search workers, window staging (1 staged
- * plan, 0 generic), dependency-poll back-off (s_sleep units), MB blocks per
- * CU of the flat kernels, waves per line worker (1, 2 or 4: the searched
- * pairs of a line are dealt round-robin to its waves).  With
+ * me_batch_config writes the launch configuration in use (ncfg >= 4; up
+ * to six entries): search workers, window staging (1 staged plan, 0
+ * generic), dependency-poll back-off (s_sleep units), MB blocks per CU of
+ * the flat kernels, waves per line worker (1, 2 or 4: the searched pairs of
+ * a line are dealt round-robin to its waves; row workers: rows per band),
+ * and the search schedule (1: row workers, one wave per MB row, for job
+ * sets whose T fields all come from earlier calls; 0: line workers).  With
  * ME_BATCH_AUTOTUNE a candidate whose run raises the device status word is
  * dropped (ME_EDEVICE when no candidate runs cleanly).
  * me_batch_destroy waits for the batch's stream and frees it (NULL is a no-op).
@@ -288,12 +296,15 @@ int me_batch_create(const me_job *jobs, int n, const me_params *params, uint32_t
 int me_batch_step(me_batch *b, const me_job *jobs, int n);
 int me_batch_results(me_batch *b, uint64_t *sse, uint64_t *npix, double *psnr_db, int n);
 int me_batch_config(const me_batch *b, int32_t *cfg, int ncfg);
-/* Force the launch configuration (ncfg == 5, same layout as me_batch_config):
- * workers 1 .. min(lines, 16 x CUs / waves), staging 0 or 1 (1 needs a
- * staging plan for this S), poll back-off 1, 2 or 4, flat MBs per CU 4, 8
- * or 16, waves per line 1, 2 or 4; ME_EINVAL otherwise.  Every
- * configuration computes the same results.  Waits for the batch's stream
- * and re-captures the graph (with the kernel timing now in force). */
+/* Force the launch configuration (ncfg 5 or 6, same layout as
+ * me_batch_config; a missing sixth entry means line workers): line workers
+ * 1 .. min(lines, 16 x CUs / waves) with waves per line 1, 2 or 4, or row
+ * workers (sixth entry 1, job sets without chains only) 1 .. the resident
+ * workgroup count with rows per band 4; staging 0 or 1 (1 needs a staging
+ * plan for this S), poll back-off 1, 2 or 4, flat MBs per CU 4, 8 or 16;
+ * ME_EINVAL otherwise.  Every configuration computes the same results.
+ * Waits for the batch's stream and re-captures the graph (with the kernel
+ * timing now in force). */
 int me_batch_set_config(me_batch *b, const int32_t *cfg, int ncfg);
 /* Kernel durations inside the batch's graph: when me_kernel_timing has kind
  * k (ME_KT_CLASSIFY, ME_KT_SEARCH, ME_KT_MC, ME_KT_NET) on at the time the

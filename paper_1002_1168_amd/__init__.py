@@ -19,6 +19,7 @@ ME_MB_TRANSPARENT, ME_MB_OPAQUE, ME_MB_BOUNDARY = 0, 1, 2
 ME_ES, ME_TSS, ME_DS, ME_4SS = 0, 1, 2, 3
 ME_KT_CLASSIFY, ME_KT_SEARCH, ME_KT_FULL, ME_KT_MC, ME_KT_NET, ME_KT_NET_TRAIN = 0, 1, 2, 3, 4, 5
 ME_BATCH_SHAPE, ME_BATCH_AUTOTUNE = 1, 2
+ME_FLAG_LINE_WORKERS = 0x100
 ME_NET_PARAMS = 10434
 
 EXPORTED = ("me_default_params", "me_status_str", "me_shutdown", "me_classify_babs", "me_texture_recursive",
@@ -272,16 +273,17 @@ class Batch:
         self._net = net   # keep it alive while attached
 
     def config(self) -> dict:
-        c = (C.c_int32 * 5)()
-        _check(lib().me_batch_config(self.handle, c, 5), "me_batch_config")
+        c = (C.c_int32 * 6)()
+        _check(lib().me_batch_config(self.handle, c, 6), "me_batch_config")
         return {"workers": c[0], "staging": "plan" if c[1] else "generic", "poll_sleep": c[2], "flat_per_cu": c[3],
-                "waves_per_line": c[4]}
+                "waves_per_line": c[4], "search": "rows" if c[5] else "lines"}
 
     def set_config(self, cfg: dict, check=True) -> int:
         """Force the launch configuration (keys as returned by config())."""
-        c = (C.c_int32 * 5)(int(cfg["workers"]), 1 if cfg["staging"] == "plan" else 0, int(cfg["poll_sleep"]),
-                            int(cfg["flat_per_cu"]), int(cfg["waves_per_line"]))
-        rc = lib().me_batch_set_config(self.handle, c, 5)
+        c = (C.c_int32 * 6)(int(cfg["workers"]), 1 if cfg["staging"] == "plan" else 0, int(cfg["poll_sleep"]),
+                            int(cfg["flat_per_cu"]), int(cfg["waves_per_line"]),
+                            1 if cfg.get("search", "lines") == "rows" else 0)
+        rc = lib().me_batch_set_config(self.handle, c, 6)
         return _check(rc, "me_batch_set_config") if check else rc
 
     def kernel_time_ms(self, kind: int):

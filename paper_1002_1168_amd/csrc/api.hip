@@ -253,10 +253,16 @@ int run_pa(const me_job *jobs, int n, const me_params *params, bool shape_only, 
     uint8_t *base = nullptr, *zb = nullptr, *sb = nullptr;
     rc = upload(*w, A_PA, m.blob, zero, &base, &zb, pa_scratch_bytes(m.nlines), &sb);
     if (rc) return rc;
-    const int waves = lines_waves(m.nlines);
-    int workers = std::min(m.nlines, pa_worker_cap() / waves);
     KernelTimer kt;
     KParams kp = kparams(params, shape_only);
+    if (m.unchained && !(params->flags & ME_FLAG_LINE_WORKERS)) {
+        return hip_err(launch_pa_rows((const JobDesc *)(base + m.o_jobs), (const ChainDesc *)(base + m.o_ch),
+                                      (const uint32_t *)(base + m.o_bands), m.nbands,
+                                      (unsigned long long *)(zb + o_prog), (uint32_t *)(zb + o_ctr), w->status, kp,
+                                      pa_rows_cap(kp.S), w->stream, timer_for(*w, A_PA, &kt) ? &kt : nullptr));
+    }
+    const int waves = lines_waves(m.nlines);
+    int workers = std::min(m.nlines, pa_worker_cap() / waves);
     return hip_err(launch_pa((const JobDesc *)(base + m.o_jobs), m.n, m.total_mbs, (const ChainDesc *)(base + m.o_ch),
                              (const uint32_t *)(base + m.o_tk), m.nlines, (unsigned long long *)(zb + o_prog),
                              (uint32_t *)(zb + o_ctr), (uint32_t *)(zb + o_mask), m.mask_words, sb, w->status, kp,

@@ -41,7 +41,7 @@ struct me_batch {
     PaMemo plan;                    // chain structure, tickets, descriptor template
     std::vector<JobDesc> tmpl;      // chain-ordered descriptors of the creating job set
     uint8_t *dev = nullptr;         // one allocation, layout below
-    size_t o_zero = 0, zero_bytes = 0, o_pscr = 0, o_part = 0, o_acc = 0, o_status = 0;
+    size_t o_zero = 0, zero_bytes = 0, rows_zero_bytes = 0, o_pscr = 0, o_part = 0, o_acc = 0, o_status = 0;
     void *host[2] = {nullptr, nullptr};  // pinned job-table staging
     hipEvent_t ev[2] = {nullptr, nullptr};
     int slot = 0;
@@ -57,7 +57,9 @@ struct me_batch {
     double t_ms[kBatchKinds] = {0, 0, 0, 0, 0};
     int t_count[kBatchKinds] = {0, 0, 0, 0, 0};
     long long replays = 0;
-    int32_t cfg[5] = {0, 1, 2, 8, 1};  // workers, window staging (1 plan, 0 generic), poll sleep, flat MBs/CU, waves per line
+    // workers, window staging (1 plan, 0 generic), poll sleep, flat MBs/CU,
+    // waves per line (row workers: rows per band), row workers (1) or line workers (0)
+    int32_t cfg[6] = {0, 1, 2, 8, 1, 0};
     me_net *net = nullptr;          // proposal network seeding the search (optional)
     uint8_t *net_scratch = nullptr;
     bool stepped = false;
@@ -125,6 +127,7 @@ struct Bufs {
     const JobDesc *jobs;
     const ChainDesc *chains;
     const uint32_t *tickets;
+    const uint32_t *bands;
     uint8_t *zero;
     unsigned long long *progress;
     uint32_t *counter, *masks, *part, *status;
@@ -138,6 +141,7 @@ Bufs bufs(const me_batch &b) {
     r.jobs = (const JobDesc *)(b.dev + m.o_jobs);
     r.chains = (const ChainDesc *)(b.dev + m.o_ch);
     r.tickets = (const uint32_t *)(b.dev + m.o_tk);
+    r.bands = (const uint32_t *)(b.dev + m.o_bands);
     r.zero = b.dev + b.o_zero;
     r.progress = (unsigned long long *)r.zero;
     r.counter = (uint32_t *)(r.zero + align_up((size_t)m.nlines * 8, 256));
@@ -157,6 +161,12 @@ KParams batch_kparams(const me_batch &b, int sleep) {
 
 hipError_t launch_search(const me_batch &b, const Bufs &u, const int32_t *cfg, hipStream_t s,
                          const KernelTimer *t = nullptr) {
+    if (cfg[5]) {  // row workers: only the row progress counts and the ticket counter start at zero
+        hipError_t e = launch_fill_u32((uint32_t *)u.zero, b.rows_zero_bytes / 4, 0u, s);
+        if (e != hipSuccess) return e;
+        return launch_pa_rows(u.jobs, u.chains, u.bands, b.plan.nbands, u.progress, u.counter, u.status,
+                              batch_kparams(b, cfg[2]), cfg[0], s, t, cfg[1] == 0);
+    }
     hipError_t e = launch_fill_u32((uint32_t *)u.zero, b.zero_bytes / 4, 0u, s);
     if (e != hipSuccess) return e;
     return launch_pa(u.jobs, b.n, b.plan.total_mbs, u.chains, u.tickets, b.plan.nlines, u.progress, u.counter, u.masks,
@@ -220,11 +230,34 @@ int autotune(me_batch &b) {
     }
     const Bufs u = bufs(b);
     int rc = ME_OK;
-    int32_t best[5] = {b.cfg[0], b.cfg[1], b.cfg[2], b.cfg[3], b.cfg[4]};
+    int32_t best[6] = {b.cfg[0], b.cfg[1], b.cfg[2], b.cfg[3], b.cfg[4], b.cfg[5]};
     if (launch_classify(u.jobs, b.n, b.plan.total_mbs, b.stream, nullptr, best[3]) != hipSuccess) rc = ME_EHIP;
-    std::vector<int> staging = {1};
-    if (plan_elems(b.params.search_range) > 0) staging.push_back(0);
+    std::vector<int> staging = {0};
+    if (plan_elems(b.params.search_range) > 0) staging.insert(staging.begin(), 1);
     float best_ms = -1.f;
+    // row workers (job sets without chains in the call): workgroups cap, cap/2
+    if (b.plan.unchained && !(b.params.flags & ME_FLAG_LINE_WORKERS)) {
+        const int cap = std::min(b.plan.nbands, pa_rows_cap(b.params.search_range));
+        std::vector<int> workers = {cap};
+        if (cap / 2 >= 64) workers.push_back(cap / 2);
+        for (int w : workers)
+            for (int st : staging)
+                for (int sl : {1, 2}) {
+                    if (rc) break;
+                    const int32_t c[6] = {w, st, sl, best[3], kRowWaves, 1};
+                    float ms = time_min(b, e0, e1, [&] { return launch_search(b, u, c, b.stream); });
+                    bool clean = false;
+                    if (ms < 0.f || !status_clear(b, u, &clean)) {
+                        rc = ME_EHIP;
+                        break;
+                    }
+                    if (!clean) continue;
+                    if (best_ms < 0.f || ms < best_ms) {
+                        best_ms = ms;
+                        for (int i = 0; i < 6; ++i) best[i] = c[i];
+                    }
+                }
+    }
     for (int wavesn : {1, 2, 4}) {
         // workgroups of `wavesn` waves; the same wave budget
         const int cap = std::min(b.plan.nlines, pa_worker_cap() / wavesn);
@@ -236,7 +269,7 @@ int autotune(me_batch &b) {
                 for (int sl : {1, 2, 4}) {
                     if (rc) break;
                     if (wavesn > 1 && sl != 1) continue;  // the several-wave worker polls with a fixed back-off
-                    const int32_t c[5] = {w, st, sl, best[3], wavesn};
+                    const int32_t c[6] = {w, st, sl, best[3], wavesn, 0};
                     float ms = time_min(b, e0, e1, [&] { return launch_search(b, u, c, b.stream); });
                     bool clean = false;
                     if (ms < 0.f || !status_clear(b, u, &clean)) {
@@ -249,10 +282,7 @@ int autotune(me_batch &b) {
                     if (!clean) continue;
                     if (best_ms < 0.f || ms < best_ms) {
                         best_ms = ms;
-                        best[0] = w;
-                        best[1] = st;
-                        best[2] = sl;
-                        best[4] = wavesn;
+                        for (int i = 0; i < 6; ++i) best[i] = c[i];
                     }
                 }
     }
@@ -282,7 +312,7 @@ int autotune(me_batch &b) {
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc == ME_OK)
-        for (int i = 0; i < 5; ++i) b.cfg[i] = best[i];
+        for (int i = 0; i < 6; ++i) b.cfg[i] = best[i];
     return rc;
 }
 
@@ -488,16 +518,19 @@ int me_batch_create(const me_job *jobs, int n, const me_params *params, uint32_t
     // [per-job sums] [status]
     b->o_zero = align_up(m.blob.size(), 256);
     b->zero_bytes = align_up(align_up((size_t)m.nlines * 8, 256) + 256 + (size_t)m.nlines * m.mask_words * 2 * 4, 256);
+    b->rows_zero_bytes = align_up((size_t)m.nlines * 8, 256) + 256;  // progress words (rows use the first) and counter
     b->o_pscr = b->o_zero + b->zero_bytes;
     b->o_part = b->o_pscr + align_up(pa_scratch_bytes(m.nlines), 256);
     b->o_acc = b->o_part + align_up(mc_scratch(m.total_mbs), 256);
     b->o_status = b->o_acc + align_up((size_t)n * 16, 256);
     const size_t total = b->o_status + 256;
     const size_t table = sizeof(JobDesc) * (size_t)n;
-    b->cfg[4] = lines_waves(m.nlines);
-    b->cfg[0] = std::min(m.nlines, pa_worker_cap() / b->cfg[4]);
-    b->cfg[1] = 1;
-    b->cfg[2] = b->cfg[4] > 1 ? 1 : 2;
+    b->cfg[5] = m.unchained && !(params->flags & ME_FLAG_LINE_WORKERS) ? 1 : 0;
+    b->cfg[4] = b->cfg[5] ? kRowWaves : lines_waves(m.nlines);
+    b->cfg[0] = b->cfg[5] ? std::min(m.nbands, pa_rows_cap(params->search_range))
+                          : std::min(m.nlines, pa_worker_cap() / b->cfg[4]);
+    b->cfg[1] = plan_elems(params->search_range) > 0 ? 1 : 0;
+    b->cfg[2] = b->cfg[4] > 1 && !b->cfg[5] ? 1 : 2;
     b->cfg[3] = 8;
     if (hipMalloc(&b->dev, total) != hipSuccess) {
         b->dev = nullptr;
@@ -614,23 +647,32 @@ int me_batch_set_net(me_batch *b, me_net *net) {
 
 int me_batch_config(const me_batch *b, int32_t *cfg, int ncfg) {
     if (!b || !cfg || ncfg < 4) return ME_EINVAL;
-    for (int i = 0; i < std::min(ncfg, 5); ++i) cfg[i] = b->cfg[i];
+    for (int i = 0; i < std::min(ncfg, 6); ++i) cfg[i] = b->cfg[i];
     return ME_OK;
 }
 
 int me_batch_set_config(me_batch *b, const int32_t *cfg, int ncfg) {
-    if (!b || !cfg || ncfg != 5) return ME_EINVAL;
+    if (!b || !cfg || (ncfg != 5 && ncfg != 6)) return ME_EINVAL;
     std::lock_guard<std::mutex> lk(b->mu);
-    const int nlines = b->plan.nlines;
+    const int rows = ncfg == 6 ? cfg[5] : 0;
+    if (rows != 0 && rows != 1) return ME_EINVAL;
     const int waves = cfg[4];
-    if (waves != 1 && waves != 2 && waves != 4) return ME_EINVAL;
-    // persistent workers: any count up to one per line (and the wave budget)
-    if (cfg[0] < 1 || cfg[0] > std::min(nlines, pa_worker_cap() / waves)) return ME_EINVAL;
+    if (rows) {
+        // row workers: job sets without chains in the call; persistent
+        // workgroups of kRowWaves rows, up to the resident count
+        if (!b->plan.unchained || waves != kRowWaves) return ME_EINVAL;
+        if (cfg[0] < 1 || cfg[0] > std::min(b->plan.nbands, pa_rows_cap(b->params.search_range))) return ME_EINVAL;
+    } else {
+        if (waves != 1 && waves != 2 && waves != 4) return ME_EINVAL;
+        // persistent workers: any count up to one per line (and the wave budget)
+        if (cfg[0] < 1 || cfg[0] > std::min(b->plan.nlines, pa_worker_cap() / waves)) return ME_EINVAL;
+    }
     if (cfg[1] != 0 && cfg[1] != 1) return ME_EINVAL;
-    if (cfg[1] == 0 && plan_elems(b->params.search_range) <= 0) return ME_EINVAL;
+    if (cfg[1] == 1 && plan_elems(b->params.search_range) <= 0) return ME_EINVAL;
     if (cfg[2] != 1 && cfg[2] != 2 && cfg[2] != 4) return ME_EINVAL;
     if (cfg[3] != 4 && cfg[3] != 8 && cfg[3] != 16) return ME_EINVAL;
     for (int i = 0; i < 5; ++i) b->cfg[i] = cfg[i];
+    b->cfg[5] = rows;
     return capture(*b);
 }
 

@@ -25,8 +25,10 @@ constexpr int kMaxSeededKmax = 127;
 struct PaMemo {
     std::vector<uint8_t> key;  // jobs + params + mode
     std::vector<uint8_t> blob;
-    size_t o_jobs = 0, o_ch = 0, o_tk = 0;
+    size_t o_jobs = 0, o_ch = 0, o_tk = 0, o_bands = 0;
     int n = 0, total_mbs = 0, nlines = 0, mask_words = 0, nchains = 0;
+    int nbands = 0;          // bands of kRowWaves rows (job sets without chains)
+    bool unchained = false;  // no job's T field is written in the same call
     std::vector<int> order;  // chain-ordered descriptor i describes job order[i]
     std::vector<int> prod;   // per job: the earlier job whose mv_int is its T field, or -1
     bool valid = false;

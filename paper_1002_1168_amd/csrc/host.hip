@@ -43,7 +43,7 @@ int check_params(const me_params *p) {
     if (p->max_step < 1 || p->max_step > p->search_range) return ME_EINVAL;
     if (p->k_max < 0 || p->k_max > 255) return ME_EINVAL;
     if (p->half_pel != 0 && p->half_pel != 1) return ME_EINVAL;
-    if (p->flags != 0) return ME_EINVAL;
+    if (p->flags & ~ME_FLAG_LINE_WORKERS) return ME_EINVAL;
     return ME_OK;
 }
 
@@ -203,10 +203,25 @@ int build_pa(const me_job *jobs, int n, PaMemo &m) {
             for (int h = 0; h < cd[c].wm; ++h)
                 tickets[cnt[h + 2 * v]++] = ((uint32_t)c << 16) | ((uint32_t)v << 8) | (uint32_t)h;
 
+    // bands of kRowWaves MB rows for the row workers (job sets without
+    // chains inside the call), in the order (first row, chain)
+    std::vector<uint32_t> bands;
+    const bool unchained = nc == n;
+    if (unchained) {
+        int maxhm = 0;
+        for (int c = 0; c < nc; ++c) maxhm = std::max(maxhm, (int)cd[c].hm);
+        for (int v0 = 0; v0 < maxhm; v0 += kRowWaves)
+            for (int c = 0; c < nc; ++c)
+                if (v0 < cd[c].hm) bands.push_back(((uint32_t)c << 16) | (uint32_t)v0);
+    }
+
     m.blob.clear();
     m.o_jobs = put(m.blob, ordered.data(), ordered.size());
     m.o_ch = put(m.blob, cd.data(), cd.size());
     m.o_tk = put(m.blob, tickets.data(), tickets.size());
+    m.o_bands = put(m.blob, bands.data(), bands.size());
+    m.nbands = (int)bands.size();
+    m.unchained = unchained;
     m.n = n;
     m.total_mbs = (int)total_mbs;
     m.nlines = (int)nlines;

@@ -34,6 +34,8 @@
 // LDS; the poll and the staging loads are in flight together.  The candidate
 // costs and every gradient pass then read LDS only.  Lane = (row j, quad q)
 // holds 4 pixels; block sums use DPP wave reductions.
+#include <algorithm>
+
 #include "me_internal.h"
 
 namespace me {
@@ -1358,6 +1360,315 @@ __global__ __launch_bounds__(64 * NW) void pa2_kernel(PaArgs a) {
     }
 }
 
+// ------------------------------------------------------------- row workers
+// Job sets with no chain inside the call (every T field is already in
+// memory, as in a batched frame step).  A workgroup of NR waves takes a
+// "band" of NR consecutive MB rows of one job; wave r walks row v0 + r from
+// left to right.  MB (h, v) needs A = the wave's own previous MB (a
+// register), B = (h, v-1) and C = (h+1, v-1) from the wave above through
+// LDS - or, for the band's first row, from the previous band's last row
+// through a per-row progress count in device memory and that row's mv_int
+// array - and T from memory.  Bands are handed out in (first row, job)
+// order, a topological order of these dependencies, so the schedule cannot
+// deadlock at any residency.  A row's transparent MBs get their zero results
+// here (no pre-pass); a neighbour transparent in the pair contributes (0, 0)
+// and is never waited for.  Every wait is bounded; on timeout a status bit
+// is raised and the workers leave.
+
+struct PrArgs {
+    const JobDesc *jobs;  // chain-ordered descriptors (one job per chain)
+    const ChainDesc *chains;
+    const uint32_t *bands;          // chain << 16 | first row, in (first row, chain) order
+    int nbands;
+    unsigned long long *rowprog;    // per chain, from its line_base: MBs of row v done (count in the low half)
+    uint32_t *counter;
+    uint32_t *status;
+    KParams kp;
+    int pitch, rows;
+};
+
+typedef __attribute__((address_space(3))) volatile uint32_t l_vu32;
+
+// Window loads of one MB, issued ahead.  Column-major: the window's dw =
+// pitch / 4 dword columns are spread over the lanes, g = 64 / dw lanes per
+// column; lane l (taken modulo g * dw, so spare lanes repeat the first ones)
+// holds column l % dw and rows l / dw + u * g, u < EM = ceil(rows / g).
+// Only the last element can fall past the window; it repeats the last row
+// (the same bytes to the same place).  The column's frame clamp and edge
+// byte selector are worked out once per MB, so an element costs one offset
+// step, one load and one LDS store; rows are clamped per element only when
+// the window crosses the top or bottom frame edge.
+template <int EM>
+struct RowWin {
+    uint32_t v[EM];
+    uint32_t sel;
+    int shape, edge;  // wave-uniform
+    __device__ __forceinline__ void issue(const uint8_t *P, int st, int W, int H, int x0, int y0, int S, int pitch,
+                                          int rows, bool shape_) {
+        shape = uni(shape_ ? 1 : 0);
+        const int dw = pitch >> 2, g = 64 / dw;
+        const int l = lane() % (g * dw), c = l % dw, r0 = l / dw;
+        const int xx = x0 - S - 1 + 4 * c;
+        const int xc = iclamp(xx, 0, W - 4);
+        edge = __ballot(xx < 0 || xx + 3 > W - 1) != 0ull;
+        sel = (uint32_t)(iclamp(xx, 0, W - 1) - xc) | ((uint32_t)(iclamp(xx + 1, 0, W - 1) - xc) << 8) |
+              ((uint32_t)(iclamp(xx + 2, 0, W - 1) - xc) << 16) | ((uint32_t)(iclamp(xx + 3, 0, W - 1) - xc) << 24);
+        const int wy0 = y0 - S - 1;
+        if (wy0 >= 0 && wy0 + rows <= H) {  // no row clamp (wave-uniform)
+            const uint32_t o0 = (uint32_t)(wy0 + r0) * (uint32_t)st + (uint32_t)xc;
+            const uint32_t gst = (uint32_t)(g * st);
+#pragma unroll
+            for (int u = 0; u < EM - 1; ++u) v[u] = ld4(P + (o0 + (uint32_t)u * gst));
+            const int rl = min(r0 + (EM - 1) * g, rows - 1);
+            v[EM - 1] = ld4(P + ((uint32_t)(wy0 + rl) * (uint32_t)st + (uint32_t)xc));
+        } else {
+#pragma unroll
+            for (int u = 0; u < EM; ++u) {
+                const int r = min(r0 + u * g, rows - 1);
+                v[u] = ld4(P + ((uint32_t)iclamp(wy0 + r, 0, H - 1) * (uint32_t)st + (uint32_t)xc));
+            }
+        }
+    }
+    __device__ __forceinline__ void write(uint32_t *win, int pitch, int rows) {
+        const int dw = pitch >> 2, g = 64 / dw;
+        const int l = lane() % (g * dw), c = l % dw, r0 = l / dw;
+        if (edge) {
+#pragma unroll
+            for (int u = 0; u < EM; ++u) v[u] = __builtin_amdgcn_perm(v[u], v[u], sel);
+        }
+        if (shape) {
+#pragma unroll
+            for (int u = 0; u < EM; ++u) v[u] = bin4(v[u]);
+        }
+        uint32_t *const wl = win + r0 * dw + c;
+        const int gdw = g * dw;
+#pragma unroll
+        for (int u = 0; u < EM - 1; ++u) wl[u * gdw] = v[u];
+        win[min(r0 + (EM - 1) * g, rows - 1) * dw + c] = v[EM - 1];
+    }
+};
+
+// dwords per lane of the column-major window staging for range S (0: the
+// generic loop): ceil(rows / g) where instantiated (S = 7, 16, 32)
+__host__ __device__ inline int row_elems(int S) {
+    const int rows = 2 * S + 18, dw = ((rows + 3) & ~3) >> 2, g = 64 / dw;
+    const int e = g > 0 ? (rows + g - 1) / g : 0;
+    return e == 4 || e == 13 || e == 28 ? e : 0;
+}
+
+// First MB index >= from whose bit is set in the 256-bit row mask m (wm: none).
+__device__ __forceinline__ int next_set(const unsigned long long (&m)[4], int from, int wm) {
+    for (int w = from >> 6; w < 4; ++w) {
+        const int b = from > 64 * w ? from - 64 * w : 0;
+        const unsigned long long x = b >= 64 ? 0ull : (m[w] >> b) << b;
+        if (x) return min(64 * w + __builtin_ctzll(x), wm);
+    }
+    return wm;
+}
+
+__device__ __forceinline__ bool bit_of(const unsigned long long (&m)[4], int h) { return (m[h >> 6] >> (h & 63)) & 1ull; }
+
+template <int EM, int NR>
+__global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
+    extern __shared__ uint32_t lds[];
+    __shared__ int slot;
+    __shared__ int stop;
+    __shared__ int ab;
+    __shared__ int prog[NR];              // per wave: MBs of its row done
+    __shared__ uint32_t vecs[NR * 256];   // per wave: its row's full-pel vectors (half-pel units, packed)
+    short *R = (short *)lds;              // 511 reciprocal entries (Eq. 4-5, Q.12)
+    const int wv = threadIdx.x >> 6;
+    const int wwords = ((a.rows * a.pitch + 16) >> 2) + 4;
+    uint32_t *const win = lds + 256 + wv * wwords;
+    const KParams kp = a.kp;
+    for (int g = threadIdx.x; g < 511; g += 64 * NR) {
+        const int m = abs(g - 255);
+        const int r = (m == 0 || m < 2 * kp.theta) ? 0 : (16384 + m) / (2 * m);
+        R[g] = (short)(g < 255 ? -r : r);
+    }
+    l_vint *const vprog = (l_vint *)prog;
+    l_vu32 *const vvec = (l_vu32 *)vecs;
+    l_vint *const vab = (l_vint *)&ab;
+    const int l = lane(), j = l >> 2, q = l & 3;
+    const int S = kp.S;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            slot = (int)atomicAdd(a.counter, 1u);
+            stop = (int)(ld_relaxed(a.status) & ST_ABORT);
+            ab = 0;
+        }
+        if (threadIdx.x < NR) prog[threadIdx.x] = 0;
+        __syncthreads();
+        const int t = uni(slot);
+        if (t >= a.nbands || uni(stop)) break;  // LDS values: the same decision in every wave
+        const uint32_t tk = a.bands[t];
+        const ChainDesc ch = a.chains[tk >> 16];
+        const int wm = ch.wm, hm = ch.hm;
+        const int v = (int)(tk & 0xFFFF) + wv;
+        bool aborted = false;
+        if (v < hm) {
+            const DescReg D{load_desc(a.jobs + ch.first)};
+            const uint8_t *cls = D.ptr<const uint8_t>(DW(cls));
+            const int W = 16 * wm, H = 16 * hm, st = D.i32(DW(stride));
+            // classes of this row and of the row above: MB h = l + 64 m in lane l
+            unsigned long long srch[4], upn[4], bnd[4];
+            {
+                int cl[4], cu[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int h = l + 64 * m;
+                    cl[m] = h < wm ? (cls ? (int)ldg8(cls + v * wm + h) : ME_MB_OPAQUE) : ME_MB_TRANSPARENT;
+                    cu[m] = (h < wm && v > 0) ? (cls ? (int)ldg8(cls + (v - 1) * wm + h) : ME_MB_OPAQUE)
+                                              : ME_MB_TRANSPARENT;
+                }
+                bool bad = false;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    bad = bad || cl[m] > ME_MB_BOUNDARY;
+                    const bool sr = cl[m] == ME_MB_OPAQUE || cl[m] == ME_MB_BOUNDARY;
+                    srch[m] = __ballot(sr);
+                    bnd[m] = __ballot(sr && (cl[m] == ME_MB_BOUNDARY || kp.shape_only));
+                    upn[m] = __ballot(cu[m] == ME_MB_OPAQUE || cu[m] == ME_MB_BOUNDARY);
+                }
+                if (bad) atomicOr(a.status, ST_BAD_CLASS);
+                // transparent MBs (and bad class bytes, taken as transparent):
+                // zero results; every vector of the row starts at zero in LDS
+                uint32_t *mv = D.ptr<uint32_t>(DW(mv));
+                uint32_t *mvi = D.ptr<uint32_t>(DW(mv_int));
+                uint32_t *co = D.ptr<uint32_t>(DW(cost));
+                uint8_t *it = D.ptr<uint8_t>(DW(iters));
+                uint16_t *pt = D.ptr<uint16_t>(DW(points));
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int h = l + 64 * m;
+                    vvec[wv * 256 + h] = 0u;
+                    if (h < wm && !((srch[m] >> l) & 1ull)) {
+                        const int k = v * wm + h;
+                        ((g_u32 *)mv)[k] = 0u;
+                        ((g_u32 *)mvi)[k] = 0u;
+                        if (co) ((g_u32 *)co)[k] = 0u;
+                        if (it) ((g_u8 *)it)[k] = 0;
+                        if (pt) ((g_u16 *)pt)[k] = 0;
+                    }
+                }
+            }
+            unsigned long long *const gprog = a.rowprog + ch.line_base + v;
+            const bool pub_global = wv == NR - 1 && v + 1 < hm;  // the next band's first row reads it
+            const uint32_t *mvi_up = D.ptr<const uint32_t>(DW(mv_int)) + (v > 0 ? (v - 1) * wm : 0);
+            const uint32_t *tf = D.ptr<const uint32_t>(DW(tf));
+            const uint32_t *seed = D.ptr<const uint32_t>(DW(seed));
+            int h = next_set(srch, 0, wm);
+            // the transparent MBs before the first searched one are done
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            if (l == 0) {
+                vprog[wv] = h;
+                if (pub_global) publish(gprog, (unsigned long long)(uint32_t)h);
+            }
+            RowWin<(EM > 0 ? EM : 1)> nw;
+            uint32_t ncur = 0, nt = 0;
+            // pixels, window and T of searched MB hh, issued ahead
+            auto issue = [&](int hh) {
+                const bool sh = bit_of(bnd, hh);
+                const uint8_t *Pc = sh ? D.ptr<const uint8_t>(DW(cur_a)) : D.ptr<const uint8_t>(DW(cur));
+                const uint8_t *Pr = sh ? D.ptr<const uint8_t>(DW(ref_a)) : D.ptr<const uint8_t>(DW(ref));
+                ncur = ldg32((const uint32_t *)(Pc + (size_t)(16 * v + j) * st + 16 * hh + 4 * q));
+                nt = tf ? ldg32(tf + v * wm + hh) : 0u;
+                if constexpr (EM > 0) nw.issue(Pr, st, W, H, 16 * hh, 16 * v, S, a.pitch, a.rows, sh);
+            };
+            if (h < wm) issue(h);
+            uint32_t lastv = 0u;  // vector of MB h - 1 when it was searched
+            int lasth = -2;
+            while (h < wm) {
+                const int k = v * wm + h;
+                const int x0 = 16 * h, y0 = 16 * v;
+                Ctx c;
+                c.shape = bit_of(bnd, h);
+                if constexpr (EM > 0) {
+                    nw.write(win, a.pitch, a.rows);
+                } else {
+                    const uint8_t *Pr = c.shape ? D.ptr<const uint8_t>(DW(ref_a)) : D.ptr<const uint8_t>(DW(ref));
+                    stage_window(win, a.pitch, a.rows, Pr, st, W, H, x0, y0, S, c.shape);
+                }
+                const uint32_t cur4 = ncur, tv = nt;
+                const int h2 = next_set(srch, h + 1, wm);
+                if (h2 < wm) issue(h2);  // in flight during this MB's search
+                c.win = win;
+                c.R = R;
+                c.pitch = a.pitch;
+                c.S = S;
+                c.off0 = (j + S + 1) * a.pitch + 4 * q + S + 1;
+                c.x0 = x0;
+                c.y0 = y0;
+                c.W = W;
+                c.H = H;
+                c.lox = max(-S, -x0);
+                c.hix = min(S, W - 16 - x0);
+                c.loy = max(-S, -y0);
+                c.hiy = min(S, H - 16 - y0);
+                c.c4 = c.shape ? bin4(cur4) : cur4;
+                // B and C from the row above, once that row is far enough
+                const bool useB = v > 0 && bit_of(upn, h);
+                const bool useC = v > 0 && h + 1 < wm && bit_of(upn, h + 1);
+                const int need = useC ? h + 2 : useB ? h + 1 : 0;
+                uint32_t mB = 0u, mC = 0u;
+                if (need > 0) {
+                    int spins = 0;
+                    for (;;) {
+                        const int got = wv > 0 ? uni(vprog[wv - 1])
+                                               : uni((int)(uint32_t)ld64(a.rowprog + ch.line_base + v - 1));
+                        if (got >= need) break;
+                        if ((spins & 31) == 31 && (uni((int)ld_relaxed(a.status)) & ST_ABORT)) {
+                            aborted = true;
+                            break;
+                        }
+                        if (++spins > kp.spin_limit) {
+                            if (l == 0) atomicOr(a.status, ST_SPIN_TIMEOUT | ST_ABORT);
+                            aborted = true;
+                            break;
+                        }
+                        if (kp.poll_sleep >= 4)
+                            __builtin_amdgcn_s_sleep(4);
+                        else if (kp.poll_sleep == 2)
+                            __builtin_amdgcn_s_sleep(2);
+                        else
+                            __builtin_amdgcn_s_sleep(1);
+                    }
+                    if (aborted) break;
+                    asm volatile("" ::: "memory");  // vector reads stay after the poll
+                    if (wv > 0) {
+                        mB = useB ? (uint32_t)uni((int)vvec[(wv - 1) * 256 + h]) : 0u;
+                        mC = useC ? (uint32_t)uni((int)vvec[(wv - 1) * 256 + h + 1]) : 0u;
+                    } else {
+                        mB = useB ? (uint32_t)uni((int)ld_relaxed(mvi_up + h)) : 0u;
+                        mC = useC ? (uint32_t)uni((int)ld_relaxed(mvi_up + h + 1)) : 0u;
+                    }
+                }
+                const uint32_t mA = lasth == h - 1 ? lastv : 0u;
+                const uint32_t mT = (uint32_t)uni((int)tv);
+                int cx[4] = {mvx_full(mA), mvx_full(mB), mvx_full(mC), mvx_full(mT)};
+                int cy[4] = {mvy_full(mA), mvy_full(mB), mvy_full(mC), mvy_full(mT)};
+                // window writes visible to every lane: one wave, so completing
+                // its LDS writes (and a compiler fence) suffices
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+                const MbOut o = search_mb(seed, c, k, cx, cy, kp);
+                if (l == 0) {
+                    store_result(D, k, o.mv, o.mvi, o.cost, o.iters, o.points);
+                    vvec[wv * 256 + h] = o.mvi;
+                    vprog[wv] = h2;  // h done, and the transparent MBs up to h2
+                    if (pub_global) publish(gprog, (unsigned long long)(uint32_t)h2);
+                }
+                lastv = o.mvi;
+                lasth = h;
+                h = h2;
+            }
+            if (aborted && l == 0) *vab = 1;
+        }
+        __syncthreads();
+        if (uni(*vab)) break;  // the same decision in every wave
+    }
+}
+
 }  // namespace
 
 // elements per lane of the staging plan for range S (0: generic loop)
@@ -1394,6 +1705,44 @@ size_t pa_scratch_bytes(int nlines) {
 size_t pa2_lds_bytes(int S, int waves) {
     const int rows = 2 * S + 18, pitch = (rows + 3) & ~3;
     return 1024 + (size_t)waves * ((size_t)(((rows * pitch + 16) >> 2) + 4) * 4);
+}
+
+size_t pr_lds_bytes(int S) {
+    const int rows = 2 * S + 18, pitch = (rows + 3) & ~3;
+    return 1024 + (size_t)kRowWaves * ((size_t)(((rows * pitch + 16) >> 2) + 4) * 4);
+}
+
+int pa_rows_cap(int S) {
+    int dev = 0, cus = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        lds <= 0)
+        lds = 160 * 1024;
+    const size_t per = pr_lds_bytes(S) + kRowWaves * 256 * 4 + 64;  // dynamic + static LDS of one workgroup
+    const int fit = (int)std::max<size_t>(1, (size_t)lds / per);
+    return cus * std::min(fit, 8);
+}
+
+hipError_t launch_pa_rows(const JobDesc *jobs, const ChainDesc *chains, const uint32_t *bands, int nbands,
+                          unsigned long long *progress, uint32_t *counter, uint32_t *status, const KParams &kp,
+                          int workers, hipStream_t s, const KernelTimer *t, bool generic) {
+    if (nbands <= 0) return hipSuccess;
+    const int rows = 2 * kp.S + 18;
+    PrArgs a{jobs, chains, bands, nbands, progress, counter, status, kp, (rows + 3) & ~3, rows};
+    const size_t lds = pr_lds_bytes(kp.S);
+    const dim3 blk(64 * kRowWaves);
+    workers = std::max(1, std::min(workers, nbands));
+    timer_mark(t, true, s);
+    switch (generic ? 0 : row_elems(kp.S)) {
+        case 4: hipLaunchKernelGGL((pr_kernel<4, kRowWaves>), dim3(workers), blk, lds, s, a); break;
+        case 13: hipLaunchKernelGGL((pr_kernel<13, kRowWaves>), dim3(workers), blk, lds, s, a); break;
+        case 28: hipLaunchKernelGGL((pr_kernel<28, kRowWaves>), dim3(workers), blk, lds, s, a); break;
+        default: hipLaunchKernelGGL((pr_kernel<0, kRowWaves>), dim3(workers), blk, lds, s, a); break;
+    }
+    hipError_t e = hipGetLastError();
+    timer_mark(t, false, s);
+    return e;
 }
 
 namespace {

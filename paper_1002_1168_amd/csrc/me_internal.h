@@ -93,6 +93,16 @@ hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, 
                      uint32_t *status, hipStream_t s, const KernelTimer *t = nullptr, int per_cu = 8);
 size_t mc_scratch(int total_mbs);
 
+// Row workers (job sets without chains inside the call): bands of
+// kRowWaves MB rows, one wave per row.  `bands`: chain << 16 | first row, in
+// (first row, chain) order; `progress` and `counter` zeroed.
+constexpr int kRowWaves = 4;
+hipError_t launch_pa_rows(const JobDesc *jobs, const ChainDesc *chains, const uint32_t *bands, int nbands,
+                          unsigned long long *progress, uint32_t *counter, uint32_t *status, const KParams &kp,
+                          int workers, hipStream_t s, const KernelTimer *t = nullptr, bool generic = false);
+// resident row-worker workgroups the device holds for range S
+int pa_rows_cap(int S);
+
 int pa_worker_cap();
 // Waves per line worker for `nlines` lines: 4 while every line still gets
 // a worker (each wave then has four pairs' time for its own pair), 2 while

@@ -214,18 +214,28 @@ def test_batch_with_proposal_network(torch_cuda):
         assert_same(st.out[u].host(), want, f"net batch unit {u} vs oracle")
 
 
-def forced_configs(nlines, cap16, plan_ok):
+def forced_configs(nlines, cap16, plan_ok, rows_cap=0):
     """Every launch configuration the autotuner can pick for a batch of
-    `nlines` lines: waves 1 / 2 / 4, workers cap, cap/2, cap/4 (at least 1),
-    staging plan / generic, poll back-off 1 / 2 / 4 (one-wave workers only)."""
+    `nlines` lines: line workers with waves 1 / 2 / 4, workers cap, cap/2,
+    cap/4 (at least 1), staging plan / generic, poll back-off 1 / 2 / 4
+    (one-wave workers only); row workers (rows_cap > 0: the resident
+    workgroup count) with cap, cap/2 and a single workgroup, both stagings,
+    back-off 1 / 2."""
     out = []
+    stagings = ("plan", "generic") if plan_ok else ("generic",)
     for waves in (1, 2, 4):
         cap = min(nlines, cap16 // waves)
         for w in sorted({cap, max(cap // 2, 1), max(cap // 4, 1)}, reverse=True):
-            for staging in (("plan", "generic") if plan_ok else ("generic",)):
+            for staging in stagings:
                 for sleep in ((1, 2, 4) if waves == 1 else (1,)):
                     out.append({"workers": w, "staging": staging, "poll_sleep": sleep, "flat_per_cu": 8,
-                                "waves_per_line": waves})
+                                "waves_per_line": waves, "search": "lines"})
+    if rows_cap:
+        for w in sorted({rows_cap, max(rows_cap // 2, 1), 1}, reverse=True):
+            for staging in stagings:
+                for sleep in (1, 2):
+                    out.append({"workers": w, "staging": staging, "poll_sleep": sleep, "flat_per_cu": 8,
+                                "waves_per_line": 4, "search": "rows"})
     return out
 
 
@@ -244,8 +254,10 @@ def test_batch_every_forced_config_matches_oracle(torch_cuda):
     try:
         cap16 = torch.cuda.get_device_properties(0).multi_processor_count * 16
         nlines = sum(st.ds[si].hm * st.ds[si].wm for si, _ in st.units)
-        cfgs = forced_configs(nlines, cap16, plan_ok=True)
-        assert len(cfgs) >= 20
+        cfg0 = b.config()
+        assert cfg0["search"] == "rows"          # the default for a set without chains
+        cfgs = forced_configs(nlines, cap16, plan_ok=True, rows_cap=cfg0["workers"])
+        assert len(cfgs) >= 30
         for cfg in cfgs:
             say("forced config", cfg)
             b.set_config(cfg)

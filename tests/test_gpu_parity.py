@@ -87,6 +87,56 @@ def test_pa_one_call_per_pair_matches(torch_cuda):
     check_pa(seq, [0, 1], me.me_default_params(search_range=16), 5, one_call=False, label="cif-per-pair")
 
 
+# one call per pair: no chain inside a call, so the row workers run (the line
+# workers when forced), T read from the previous call's output
+@pytest.mark.parametrize("flags", [0, me.ME_FLAG_LINE_WORKERS])
+@pytest.mark.parametrize("case", ["qcif", "qcif-rect", "shape", "hd-halfpel", "w4096", "noise", "tiny"])
+def test_pa_per_pair_rows_and_lines(torch_cuda, case, flags):
+    if case == "qcif":
+        seq, vops, p, P, so = synth.qcif_ellipse(), [0], dict(search_range=7), 5, False
+    elif case == "qcif-rect":
+        seq, vops, p, P, so = synth.qcif_ellipse(), [None], dict(search_range=7, k_max=255, max_step=3), 4, False
+    elif case == "shape":
+        seq, vops, p, P, so = synth.cif_two_vops(frames=5), [0, 1], dict(search_range=16), 4, True
+    elif case == "hd-halfpel":
+        seq, vops, p, P, so = synth.hd_streams(frames=3, streams=1)[0], [0, 1, 2], dict(search_range=32, half_pel=1), \
+            2, False
+    elif case == "w4096":
+        seq, vops, p, P, so = synth.random_frames(6, 4096, 48, frames=3, vops=1, search_range=16), [0, None], \
+            dict(search_range=16), 2, False
+    elif case == "noise":
+        seq, vops, p, P, so = synth.random_frames(3, 48, 32, frames=5, vops=1, search_range=4), [0, None], \
+            dict(search_range=4, k_max=255), 4, False
+    else:
+        seq, vops, p, P, so = synth.random_frames(4, 16, 16, frames=3, vops=1, search_range=2), [0, None], \
+            dict(search_range=2), 2, False
+    check_pa(seq, vops, me.me_default_params(flags=flags, **p), P, shape_only=so, one_call=False,
+             label=f"per-pair {case} flags {flags}")
+
+
+def test_pa_rows_bad_class_raises_status(torch_cuda):
+    """The row workers (a single unchained job): a class byte outside 0..2
+    raises the status word, that MB gets the transparent result."""
+    import torch
+    from paper_1002_1168_amd import device as dv
+    seq = synth.qcif_ellipse(frames=3)
+    ds = dseq(seq)
+    gpu_classify(ds)
+    cls = ds.cls[0, 1]
+    opaque = (cls == me.ME_MB_OPAQUE).nonzero()
+    v, h = (int(x) for x in opaque[len(opaque) // 2])
+    cls[v, h] = 9
+    out = dv.Outputs.alloc(1, ds.hm, ds.wm)
+    s = dv.stream_handle()
+    me.me_texture_recursive(ds.pair_jobs(0, out, 1), me.me_default_params(search_range=7), None, stream=s)
+    torch.cuda.synchronize()
+    assert me.me_device_status(s) == me.ME_EDEVICE
+    assert me.me_device_status(s) == me.ME_OK
+    got = out.host()
+    assert (got["mv"][0][v, h] == 0).all() and got["points"][0][v, h] == 0
+    assert (got["points"][0][cls.cpu().numpy() == me.ME_MB_OPAQUE] > 0).all()
+
+
 @pytest.mark.parametrize("over", [dict(eps_q12=2048), dict(max_step=3), dict(theta=2), dict(k_max=0),
                                   dict(k_max=1), dict(k_max=255, max_step=7), dict(eps_q12=65536, theta=1)])
 def test_pa_parameter_variants(torch_cuda, over):
