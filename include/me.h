@@ -231,6 +231,39 @@ int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, u
 int me_motion_compensate_sse(const me_job *jobs, int n, uint8_t *const *pred, uint64_t *sums, void *stream);
 
 /*
+ * Four motion vectors per MB (Section 3.2: MPEG-4 allows four vectors per
+ * macroblock, so the recursive search works on 8 x 8 blocks).  The
+ * block-recursive search of Fig. 1 stays per MB; me_refine_8x8 then applies
+ * the pel-recursive refinement of Eqs. 3-5 to each 8 x 8 block (raster
+ * order: top-left, top-right, bottom-left, bottom-right) of every texture
+ * (opaque) MB, starting from the MB's full-pel vector: the gradient pass
+ * over the block's 64 pixels, the same step, accept and stop rule, the 8 x 8
+ * SAD as cost, the displaced 8 x 8 block inside the frame and |d| <= S; then
+ * (half_pel) the eight half-sample offsets around each block's vector.
+ * Boundary MBs keep their one (shape) vector in all four entries,
+ * transparent MBs get zero vectors.
+ *  jobs      a finished search's jobs: cur, ref, mb_class, mv (the MB's
+ *            final vector, repeated on boundary MBs) and mv_int (the start;
+ *            it must be admissible for the MB, as the search leaves it) are
+ *            read; t_field, seed, cost, iters, points are ignored.
+ *  mv4[i]    device, 4 me_mv per MB (half-pel), required.
+ *  cost4[i], iters4[i], points4[i]  device or NULL (and the arrays of
+ *            pointers themselves nullable): per block the final 8 x 8
+ *            distortion, the recursion candidates evaluated, and the 8 x 8
+ *            blocks compared beyond the start (recursion and half-sample
+ *            candidates); zero for non-texture MBs.
+ * Asynchronous on `stream`.
+ *
+ * me_motion_compensate4_sse: me_motion_compensate_sse with each 8 x 8 block
+ * predicted by its own vector mv4[i] (transparent MBs by (0, 0)); the jobs'
+ * mv is not read.  Same sums, errors and pinned-memory rules.
+ */
+int me_refine_8x8(const me_job *jobs, int n, const me_params *params, me_mv *const *mv4, uint32_t *const *cost4,
+                  uint8_t *const *iters4, uint16_t *const *points4, void *stream);
+int me_motion_compensate4_sse(const me_job *jobs, int n, const me_mv *const *mv4, uint8_t *const *pred,
+                              uint64_t *sums, void *stream);
+
+/*
  * me_motion_compensate_sse for callers that cannot allocate (code under HIP
  * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same prediction, masked SSE and per-job sums (same arguments, errors and
@@ -337,6 +370,7 @@ void me_batch_destroy(me_batch *b);
  *  ME_KT_NET       me_net_forward (also via   network forward kernel (not the MB list)
  *                  me_texture_recursive)
  *  ME_KT_NET_TRAIN me_net_train_step          forward + backward kernel (not the SGD update)
+ *  ME_KT_REFINE8   me_refine_8x8              8 x 8 block refinement kernel
  * me_kernel_timing: on = 0 (off), 1 (every kind), or ME_KT_ONLY(kind) bits
  * OR-ed together (only those kinds: the others record no events, which
  * add a few microseconds between kernels each); ME_EINVAL otherwise.
@@ -351,6 +385,7 @@ void me_batch_destroy(me_batch *b);
 #define ME_KT_MC 3
 #define ME_KT_NET 4
 #define ME_KT_NET_TRAIN 5
+#define ME_KT_REFINE8 6
 #define ME_KT_ONLY(kind) (2 << (kind))
 int me_kernel_timing(int on);
 int me_kernel_time_ms(int kind, void *stream, double *total_ms, int *count);

@@ -97,6 +97,11 @@ def lib():
         L.or_mc_sse.argtypes = [C.POINTER(_Pair), vp, vp, vp,
                                 C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
         L.or_mc_sse.restype = i
+        L.or_prs8.argtypes = [C.POINTER(_Pair), vp, vp, vp, C.POINTER(_Params), vp, vp, vp, vp]
+        L.or_prs8.restype = i
+        L.or_mc4_sse.argtypes = [C.POINTER(_Pair), vp, vp, vp,
+                                 C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+        L.or_mc4_sse.restype = i
         _lib = L
     return _lib
 
@@ -231,6 +236,40 @@ def mc_sse(cur, ref, mv, cur_alpha=None, cls=None, want_pred=False):
     rc = lib().or_mc_sse(C.byref(p), _ptr(cls), _ptr(mvv), _ptr(pred), C.byref(s), C.byref(n))
     if rc:
         raise ValueError("or_mc_sse rejected its arguments")
+    return int(s.value), int(n.value), pred
+
+
+def prs8(cur, ref, params: Params, mv, mv_int, cls=None):
+    """Four-vector mode: the pel-recursive refinement on each 8 x 8 block of
+    the texture MBs from the MB vectors (mv, mv_int: an or_pa result).
+    -> dict mv4 (H/16, W/16, 4, 2), cost4 / iters4 / points4 (H/16, W/16, 4)."""
+    p, keep = _pair(cur, ref)
+    H, W = keep[0].shape
+    hm, wm = H // 16, W // 16
+    out = dict(mv4=np.zeros((hm, wm, 4, 2), np.int16), cost4=np.zeros((hm, wm, 4), np.uint32),
+               iters4=np.zeros((hm, wm, 4), np.uint8), points4=np.zeros((hm, wm, 4), np.uint16))
+    cls = _u8(cls)
+    mvv = np.ascontiguousarray(mv, dtype=np.int16)
+    mvi = np.ascontiguousarray(mv_int, dtype=np.int16)
+    prm = params._c()
+    rc = lib().or_prs8(C.byref(p), _ptr(cls), _ptr(mvv), _ptr(mvi), C.byref(prm), _ptr(out["mv4"]),
+                       _ptr(out["cost4"]), _ptr(out["iters4"]), _ptr(out["points4"]))
+    if rc:
+        raise ValueError("or_prs8 rejected its arguments")
+    return out
+
+
+def mc4_sse(cur, ref, mv4, cur_alpha=None, cls=None, want_pred=False):
+    """MC with four vectors per MB -> (sse, npix, pred or None)."""
+    p, keep = _pair(cur, ref, cur_alpha, None)
+    H, W = keep[0].shape
+    mvv = np.ascontiguousarray(mv4, dtype=np.int16)
+    cls = _u8(cls)
+    pred = np.zeros((H, W), np.uint8) if want_pred else None
+    s, n = C.c_uint64(), C.c_uint64()
+    rc = lib().or_mc4_sse(C.byref(p), _ptr(cls), _ptr(mvv), _ptr(pred), C.byref(s), C.byref(n))
+    if rc:
+        raise ValueError("or_mc4_sse rejected its arguments")
     return int(s.value), int(n.value), pred
 
 

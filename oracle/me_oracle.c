@@ -99,16 +99,18 @@ int or_classify(const uint8_t *alpha, int width, int height, int stride, uint8_t
 }
 
 /* ------------------------------------------------------ block costs */
-/* Section 2 / 3.1: sum of absolute luma differences of the 16x16 block at
+/* Section 2 / 3.1: sum of absolute luma differences of the n x n block at
  * (x0, y0) against the reference block displaced by (dx, dy). */
-uint32_t or_sad(const or_pair *fp, int x0, int y0, int dx, int dy) {
+static uint32_t sad_n(const or_pair *fp, int x0, int y0, int n, int dx, int dy) {
     uint32_t s = 0;
-    for (int j = 0; j < 16; ++j)
-        for (int i = 0; i < 16; ++i)
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i)
             s += (uint32_t)iabs(luma_at(fp->cur_luma, fp->stride, x0 + i, y0 + j) -
                                 luma_at(fp->ref_luma, fp->stride, x0 + i + dx, y0 + j + dy));
     return s;
 }
+
+uint32_t or_sad(const or_pair *fp, int x0, int y0, int dx, int dy) { return sad_n(fp, x0, y0, 16, dx, dy); }
 
 /* Fig. 1, boundary branch: the distortion of two binary alpha blocks is the
  * number of pixels whose inside/outside state differs. */
@@ -128,10 +130,14 @@ static uint32_t block_cost(const or_pair *fp, int shape, int x0, int y0, int dx,
 }
 
 /* A full-pel vector is admissible when |dx|, |dy| <= S and the whole
- * displaced block lies inside the reference frame. */
+ * displaced n x n block lies inside the reference frame. */
+static int feasible_n(const or_pair *fp, int S, int x0, int y0, int n, int dx, int dy) {
+    return iabs(dx) <= S && iabs(dy) <= S && x0 + dx >= 0 && x0 + dx <= fp->width - n && y0 + dy >= 0 &&
+           y0 + dy <= fp->height - n;
+}
+
 static int feasible(const or_pair *fp, int S, int x0, int y0, int dx, int dy) {
-    return iabs(dx) <= S && iabs(dy) <= S && x0 + dx >= 0 && x0 + dx <= fp->width - 16 && y0 + dy >= 0 &&
-           y0 + dy <= fp->height - 16;
+    return feasible_n(fp, S, x0, y0, 16, dx, dy);
 }
 
 /* ------------------------------------ pel-recursive search (Section 3.2) */
@@ -155,11 +161,12 @@ int32_t or_recip(int g, int theta) {
  * frame).  The per-pixel updates e * u are averaged over the pixels whose
  * gradient passes the threshold, per component, in Q.12 (C division).
  */
-void or_prs_pass(const or_pair *fp, int shape, int theta, int x0, int y0, int dx, int dy, int32_t *ux, int32_t *uy) {
+static void prs_pass_n(const or_pair *fp, int shape, int theta, int x0, int y0, int n, int dx, int dy, int32_t *ux,
+                       int32_t *uy) {
     int32_t sx = 0, sy = 0;
     int nx = 0, ny = 0;
-    for (int j = 0; j < 16; ++j) {
-        for (int i = 0; i < 16; ++i) {
+    for (int j = 0; j < n; ++j) {
+        for (int i = 0; i < n; ++i) {
             int px = x0 + i, py = y0 + j;
             int rx = px + dx, ry = py + dy;
             int e = plane_cur(fp, shape, px, py) - plane_ref(fp, shape, rx, ry);
@@ -175,6 +182,10 @@ void or_prs_pass(const or_pair *fp, int shape, int theta, int x0, int y0, int dx
     }
     *ux = nx ? sx / nx : 0;
     *uy = ny ? sy / ny : 0;
+}
+
+void or_prs_pass(const or_pair *fp, int shape, int theta, int x0, int y0, int dx, int dy, int32_t *ux, int32_t *uy) {
+    prs_pass_n(fp, shape, theta, x0, y0, 16, dx, dy, ux, uy);
 }
 
 /* Eq. 3 step in one axis: eps * U in Q.24, rounded half away from zero to
@@ -196,15 +207,15 @@ int or_step(int32_t u, int eps_q12, int max_step) {
  * that does not improve, at a zero update, at the search-window border, or
  * after k_max candidates.  Returns the number of candidates evaluated.
  */
-static int pel_recursion(const or_pair *fp, const or_params *p, int shape, int x0, int y0, int *dx, int *dy,
-                         uint32_t *cost) {
+static int pel_recursion_n(const or_pair *fp, const or_params *p, int shape, int x0, int y0, int n, int *dx, int *dy,
+                           uint32_t *cost) {
     int S = p->search_range;
-    int lox = imax(-S, -x0), hix = imin(S, fp->width - 16 - x0);
-    int loy = imax(-S, -y0), hiy = imin(S, fp->height - 16 - y0);
+    int lox = imax(-S, -x0), hix = imin(S, fp->width - n - x0);
+    int loy = imax(-S, -y0), hiy = imin(S, fp->height - n - y0);
     int it = 0;
     while (it < p->k_max) {
         int32_t ux, uy;
-        or_prs_pass(fp, shape, p->theta, x0, y0, *dx, *dy, &ux, &uy);
+        prs_pass_n(fp, shape, p->theta, x0, y0, n, *dx, *dy, &ux, &uy);
         int sx = or_step(ux, p->eps_q12, p->max_step);
         int sy = or_step(uy, p->eps_q12, p->max_step);
         if (sx == 0 && sy == 0) break;
@@ -212,7 +223,7 @@ static int pel_recursion(const or_pair *fp, const or_params *p, int shape, int x
         int ny = iclamp(*dy + sy, loy, hiy);
         if (nx == *dx && ny == *dy) break;
         ++it;
-        uint32_t c = block_cost(fp, shape, x0, y0, nx, ny);
+        uint32_t c = n == 16 ? block_cost(fp, shape, x0, y0, nx, ny) : sad_n(fp, x0, y0, n, nx, ny);
         if (c < *cost) {
             *dx = nx;
             *dy = ny;
@@ -222,6 +233,11 @@ static int pel_recursion(const or_pair *fp, const or_params *p, int shape, int x
         }
     }
     return it;
+}
+
+static int pel_recursion(const or_pair *fp, const or_params *p, int shape, int x0, int y0, int *dx, int *dy,
+                         uint32_t *cost) {
+    return pel_recursion_n(fp, p, shape, x0, y0, 16, dx, dy, cost);
 }
 
 /* ------------------------------------------- half-sample refinement */
@@ -243,19 +259,28 @@ static int pred_half(const or_pair *fp, int x, int y, int hx, int hy) {
     return (A + B + C + D + 2) >> 2;
 }
 
-uint32_t or_sad_half(const or_pair *fp, int x0, int y0, int hx, int hy) {
+static uint32_t sad_half_n(const or_pair *fp, int x0, int y0, int n, int hx, int hy) {
     uint32_t s = 0;
-    for (int j = 0; j < 16; ++j)
-        for (int i = 0; i < 16; ++i)
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i)
             s += (uint32_t)iabs(luma_at(fp->cur_luma, fp->stride, x0 + i, y0 + j) - pred_half(fp, x0 + i, y0 + j, hx, hy));
     return s;
 }
 
-static int half_feasible(const or_pair *fp, int S, int x0, int y0, int hx, int hy) {
+uint32_t or_sad_half(const or_pair *fp, int x0, int y0, int hx, int hy) { return sad_half_n(fp, x0, y0, 16, hx, hy); }
+
+/* The whole integer footprint of the half-sample prediction of the n x n
+ * block (n + fx columns, n + fy rows) lies in the reference frame. */
+static int half_feasible_n(const or_pair *fp, int S, int x0, int y0, int n, int hx, int hy) {
     if (iabs(hx) > 2 * S || iabs(hy) > 2 * S) return 0;
     int ix = half_to_full(hx), iy = half_to_full(hy);
     int fx = hx - 2 * ix, fy = hy - 2 * iy;
-    return x0 + ix >= 0 && x0 + ix + 15 + fx <= fp->width - 1 && y0 + iy >= 0 && y0 + iy + 15 + fy <= fp->height - 1;
+    return x0 + ix >= 0 && x0 + ix + n - 1 + fx <= fp->width - 1 && y0 + iy >= 0 &&
+           y0 + iy + n - 1 + fy <= fp->height - 1;
+}
+
+static int half_feasible(const or_pair *fp, int S, int x0, int y0, int hx, int hy) {
+    return half_feasible_n(fp, S, x0, y0, 16, hx, hy);
 }
 
 static const int HALF_OFFS[8][2] = {{-1, -1}, {0, -1}, {1, -1}, {-1, 0}, {1, 0}, {-1, 1}, {0, 1}, {1, 1}};
@@ -653,6 +678,110 @@ int or_mc_sse(const or_pair *fp, const uint8_t *cls, const int16_t *mv, uint8_t 
             int hy = c == OR_TRANSPARENT ? 0 : mv[2 * k + 1];
             for (int j = 0; j < 16; ++j) {
                 for (int i = 0; i < 16; ++i) {
+                    int x = 16 * h + i, y = 16 * v + j;
+                    int pv = pred_half(fp, x, y, hx, hy);
+                    if (pred) pred[(size_t)y * fp->stride + x] = (uint8_t)pv;
+                    int in = fp->cur_alpha ? fp->cur_alpha[(size_t)y * fp->stride + x] != 0 : 1;
+                    if (in) {
+                        int d = luma_at(fp->cur_luma, fp->stride, x, y) - pv;
+                        s += (uint64_t)(d * d);
+                        ++n;
+                    }
+                }
+            }
+        }
+    }
+    *sse = s;
+    *npix = n;
+    return 0;
+}
+
+/* ------------------------------------ four vectors per MB (Section 3.2) */
+/*
+ * Section 3.2 notes that MPEG-4 allows four motion vectors per MB and that
+ * the recursive search therefore works on 8 x 8 blocks.  Reading: the
+ * block-recursive search of Fig. 1 stays per MB (its candidates are MB
+ * vectors); the pel-recursive refinement is then applied to each 8 x 8 block
+ * b (raster order: top-left, top-right, bottom-left, bottom-right) of every
+ * texture (opaque) MB, starting from the MB's full-pel vector mv_int: the
+ * same gradient pass over the 64 pixels of the block, the same step, accept
+ * and stop rule, 8 x 8 SAD as the cost, the displaced 8 x 8 block inside the
+ * frame and |d| <= S; then (half_pel) the eight half-sample offsets around
+ * the block's vector.  Boundary MBs keep their one (shape) vector, repeated;
+ * transparent MBs get zero vectors.  Per block: mv4 (half-pel), cost4 (final
+ * 8 x 8 SAD), iters4 (recursion candidates), points4 (8 x 8 blocks compared
+ * beyond the start: recursion candidates and feasible half-sample ones).
+ */
+int or_prs8(const or_pair *fp, const uint8_t *cls, const int16_t *mv, const int16_t *mv_int, const or_params *p,
+            int16_t *mv4, uint32_t *cost4, uint8_t *iters4, uint16_t *points4) {
+    if (!fp || !p || !mv || !mv_int || !mv4) return -1;
+    if (fp->width % 16 || fp->height % 16 || fp->width <= 0 || fp->height <= 0) return -1;
+    int wm = fp->width / 16, hm = fp->height / 16;
+    int S = p->search_range;
+    for (int v = 0; v < hm; ++v) {
+        for (int h = 0; h < wm; ++h) {
+            int k = v * wm + h;
+            int c = cls ? cls[k] : OR_OPAQUE;
+            for (int b = 0; b < 4; ++b) {
+                int q = 4 * k + b;
+                int hx = 0, hy = 0, its = 0, pts = 0;
+                uint32_t cost = 0;
+                if (c == OR_OPAQUE) {
+                    int bx0 = 16 * h + 8 * (b & 1), by0 = 16 * v + 8 * (b >> 1);
+                    int dx = half_to_full(mv_int[2 * k]), dy = half_to_full(mv_int[2 * k + 1]);
+                    cost = sad_n(fp, bx0, by0, 8, dx, dy);
+                    its = pel_recursion_n(fp, p, 0, bx0, by0, 8, &dx, &dy, &cost);
+                    pts = its;
+                    hx = 2 * dx;
+                    hy = 2 * dy;
+                    if (p->half_pel) {
+                        int bhx = hx, bhy = hy;
+                        for (int o = 0; o < 8; ++o) {
+                            int qx = hx + HALF_OFFS[o][0], qy = hy + HALF_OFFS[o][1];
+                            if (!half_feasible_n(fp, S, bx0, by0, 8, qx, qy)) continue;
+                            ++pts;
+                            uint32_t c2 = sad_half_n(fp, bx0, by0, 8, qx, qy);
+                            if (c2 < cost) {
+                                cost = c2;
+                                bhx = qx;
+                                bhy = qy;
+                            }
+                        }
+                        hx = bhx;
+                        hy = bhy;
+                    }
+                } else if (c == OR_BOUNDARY) {
+                    hx = mv[2 * k];
+                    hy = mv[2 * k + 1];
+                }
+                mv4[2 * q] = (int16_t)hx;
+                mv4[2 * q + 1] = (int16_t)hy;
+                if (cost4) cost4[q] = cost;
+                if (iters4) iters4[q] = (uint8_t)its;
+                if (points4) points4[q] = (uint16_t)pts;
+            }
+        }
+    }
+    return 0;
+}
+
+/* Motion compensation with four vectors per MB: each 8 x 8 block predicted
+ * by its own half-pel vector (transparent MBs by (0, 0)); SSE over the VOP
+ * pixels (every pixel for rectangular frames), as or_mc_sse. */
+int or_mc4_sse(const or_pair *fp, const uint8_t *cls, const int16_t *mv4, uint8_t *pred, uint64_t *sse,
+               uint64_t *npix) {
+    if (!fp || !mv4 || !sse || !npix) return -1;
+    int wm = fp->width / 16, hm = fp->height / 16;
+    uint64_t s = 0, n = 0;
+    for (int v = 0; v < hm; ++v) {
+        for (int h = 0; h < wm; ++h) {
+            int k = v * wm + h;
+            int c = cls ? cls[k] : OR_OPAQUE;
+            for (int j = 0; j < 16; ++j) {
+                for (int i = 0; i < 16; ++i) {
+                    int q = 4 * k + 2 * (j / 8) + i / 8;
+                    int hx = c == OR_TRANSPARENT ? 0 : mv4[2 * q];
+                    int hy = c == OR_TRANSPARENT ? 0 : mv4[2 * q + 1];
                     int x = 16 * h + i, y = 16 * v + j;
                     int pv = pred_half(fp, x, y, hx, hy);
                     if (pred) pred[(size_t)y * fp->stride + x] = (uint8_t)pv;

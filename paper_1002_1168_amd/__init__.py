@@ -17,14 +17,14 @@ LIB_PATH = os.path.join(_HERE, "libme.so")
 ME_OK, ME_EINVAL, ME_EALIGN, ME_EHIP, ME_ENOMEM, ME_EEMPTY, ME_EDEVICE, ME_ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
 ME_MB_TRANSPARENT, ME_MB_OPAQUE, ME_MB_BOUNDARY = 0, 1, 2
 ME_ES, ME_TSS, ME_DS, ME_4SS = 0, 1, 2, 3
-ME_KT_CLASSIFY, ME_KT_SEARCH, ME_KT_FULL, ME_KT_MC, ME_KT_NET, ME_KT_NET_TRAIN = 0, 1, 2, 3, 4, 5
+ME_KT_CLASSIFY, ME_KT_SEARCH, ME_KT_FULL, ME_KT_MC, ME_KT_NET, ME_KT_NET_TRAIN, ME_KT_REFINE8 = 0, 1, 2, 3, 4, 5, 6
 ME_BATCH_SHAPE, ME_BATCH_AUTOTUNE = 1, 2
 ME_FLAG_LINE_WORKERS = 0x100
 ME_NET_PARAMS = 10434
 
 EXPORTED = ("me_default_params", "me_status_str", "me_shutdown", "me_classify_babs", "me_texture_recursive",
             "me_shape_search", "me_full_search", "me_motion_compensate_psnr", "me_motion_compensate_sse",
-            "me_motion_compensate_sse_noalloc", "me_device_status",
+            "me_motion_compensate_sse_noalloc", "me_refine_8x8", "me_motion_compensate4_sse", "me_device_status",
             "me_kernel_timing", "me_kernel_time_ms", "me_batch_create", "me_batch_step", "me_batch_results",
             "me_batch_config", "me_batch_set_config", "me_batch_kernel_time_ms", "me_batch_set_net", "me_batch_destroy", "me_net_create", "me_net_forward", "me_net_train_step",
             "me_net_weights", "me_net_destroy", "me_search_schedule")
@@ -84,6 +84,11 @@ def lib():
         L.me_motion_compensate_psnr.restype = i
         L.me_motion_compensate_sse.argtypes = [C.POINTER(me_job), i, C.POINTER(vp), vp, vp]
         L.me_motion_compensate_sse.restype = i
+        L.me_refine_8x8.argtypes = [C.POINTER(me_job), i, C.POINTER(me_params), C.POINTER(vp), C.POINTER(vp),
+                                    C.POINTER(vp), C.POINTER(vp), vp]
+        L.me_refine_8x8.restype = i
+        L.me_motion_compensate4_sse.argtypes = [C.POINTER(me_job), i, C.POINTER(vp), C.POINTER(vp), vp, vp]
+        L.me_motion_compensate4_sse.restype = i
         L.me_motion_compensate_sse_noalloc.argtypes = [C.POINTER(me_job), i, C.POINTER(vp), vp, vp]
         L.me_motion_compensate_sse_noalloc.restype = i
         L.me_device_status.argtypes = [vp]
@@ -215,6 +220,28 @@ def me_motion_compensate_sse(jobs, sums, pred=None, stream=None, check=True) -> 
     pa = None if pred is None else _arr(C.c_void_p, pred)[0]
     rc = lib().me_motion_compensate_sse(ja, n, pa, sums, stream)
     return _check(rc, "me_motion_compensate_sse") if check else rc
+
+
+def me_refine_8x8(jobs, params: me_params, mv4, cost4=None, iters4=None, points4=None, stream=None,
+                  check=True) -> int:
+    """Four vectors per MB: ``mv4`` (and the optional per-block outputs) are
+    lists of device addresses, one per job."""
+    ja, n = _arr(me_job, jobs)
+    m4 = _arr(C.c_void_p, mv4)[0]
+    c4 = None if cost4 is None else _arr(C.c_void_p, cost4)[0]
+    i4 = None if iters4 is None else _arr(C.c_void_p, iters4)[0]
+    p4 = None if points4 is None else _arr(C.c_void_p, points4)[0]
+    rc = lib().me_refine_8x8(ja, n, C.byref(params), m4, c4, i4, p4, stream)
+    return _check(rc, "me_refine_8x8") if check else rc
+
+
+def me_motion_compensate4_sse(jobs, mv4, sums, pred=None, stream=None, check=True) -> int:
+    """MC with four vectors per MB (``mv4``: per-job device addresses)."""
+    ja, n = _arr(me_job, jobs)
+    m4 = _arr(C.c_void_p, mv4)[0]
+    pa = None if pred is None else _arr(C.c_void_p, pred)[0]
+    rc = lib().me_motion_compensate4_sse(ja, n, m4, pa, sums, stream)
+    return _check(rc, "me_motion_compensate4_sse") if check else rc
 
 
 def me_motion_compensate_sse_noalloc(jobs, sums, pred=None, stream=None, check=True) -> int:

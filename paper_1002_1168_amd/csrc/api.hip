@@ -42,8 +42,10 @@ struct Arena {
     bool last_valid = false;
 };
 
-enum ArenaKind { A_CLASSIFY = 0, A_PA = 1, A_SEARCH = 2, A_MC = 3, A_COUNT = 4 };
-constexpr int kTimerKinds = 6;  // the four arena kinds (ME_KT_*), then the network forward and training kernels
+enum ArenaKind { A_CLASSIFY = 0, A_PA = 1, A_SEARCH = 2, A_MC = 3, A_PRS8 = 4, A_COUNT = 5 };
+// timing kinds: the first four arena kinds (ME_KT_*), the network forward and
+// training kernels, then the 8 x 8 refinement
+constexpr int kTimerKinds = 7;
 
 
 // Event pairs of timed launches of one call kind: in flight until their
@@ -527,6 +529,74 @@ int me_motion_compensate_psnr(const me_job *jobs, int n, uint8_t *const *pred, u
         }
     }
     return status;
+}
+
+int me_refine_8x8(const me_job *jobs, int n, const me_params *params, me_mv *const *mv4, uint32_t *const *cost4,
+                  uint8_t *const *iters4, uint16_t *const *points4, void *stream) {
+    if (n < 0 || (n > 0 && (!jobs || !mv4))) return ME_EINVAL;
+    int rc = check_params(params);
+    if (rc) return rc;
+    std::vector<JobDesc> desc(n);
+    long long total = 0;
+    for (int i = 0; i < n; ++i) {
+        rc = check_job(jobs[i], false);
+        if (rc) return rc;
+        if (!mv4[i]) return ME_EINVAL;
+        if (!al4(mv4[i]) || (cost4 && cost4[i] && !al4(cost4[i])) || (points4 && points4[i] && ((uintptr_t)points4[i] & 1u)))
+            return ME_EALIGN;
+        JobDesc &d = desc[i];
+        d = job_desc(jobs[i]);
+        d.tf = (const int16_t *)jobs[i].mv;  // the MB's own vector, kept by boundary MBs
+        d.seed = nullptr;
+        d.mv = (int16_t *)mv4[i];
+        d.mv_int = (int16_t *)jobs[i].mv_int;
+        d.cost = cost4 ? cost4[i] : nullptr;
+        d.iters = iters4 ? iters4[i] : nullptr;
+        d.points = points4 ? points4[i] : nullptr;
+        d.mb_base = (int32_t)total;
+        total += (long long)d.wm * d.hm;
+    }
+    if (total > (1ll << 30)) return ME_EINVAL;
+    if (n == 0) return ME_OK;
+    Workspace *w = nullptr;
+    rc = get_ws(stream, &w);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(w->mu);
+    std::vector<uint8_t> blob;
+    size_t o = put(blob, desc.data(), desc.size());
+    uint8_t *base = nullptr, *zb = nullptr;
+    rc = upload(*w, A_PRS8, blob, 0, &base, &zb);
+    if (rc) return rc;
+    KernelTimer kt;
+    return hip_err(launch_prs8((const JobDesc *)(base + o), n, (int)total, kparams(params, false), w->stream,
+                               timer_for(*w, ME_KT_REFINE8, &kt) ? &kt : nullptr));
+}
+
+int me_motion_compensate4_sse(const me_job *jobs, int n, const me_mv *const *mv4, uint8_t *const *pred,
+                              uint64_t *sums, void *stream) {
+    if (n < 0 || (n > 0 && (!jobs || !sums || !mv4))) return ME_EINVAL;
+    if (((uintptr_t)sums & 7u) != 0) return ME_EALIGN;
+    std::vector<JobDesc> desc;
+    long long total = 0;
+    int rc = mc_descs(jobs, n, pred, desc, &total);
+    if (rc || n == 0) return rc;
+    for (int i = 0; i < n; ++i) {
+        if (!mv4[i]) return ME_EINVAL;
+        if (!al4(mv4[i])) return ME_EALIGN;
+        desc[i].mv = (int16_t *)mv4[i];
+    }
+    Workspace *w = nullptr;
+    rc = get_ws(stream, &w);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(w->mu);
+    std::vector<uint8_t> blob;
+    size_t o = put(blob, desc.data(), desc.size());
+    uint8_t *base = nullptr, *zb = nullptr, *sb = nullptr;
+    rc = upload(*w, A_MC, blob, 0, &base, &zb, mc_scratch((int)total), &sb);
+    if (rc) return rc;
+    KernelTimer kt;
+    return hip_err(launch_mc((const JobDesc *)(base + o), n, (int)total, (uint32_t *)sb, (unsigned long long *)sums,
+                             w->status, w->stream, timer_for(*w, A_MC, &kt) ? &kt : nullptr, 8, true));
 }
 
 int me_motion_compensate_sse(const me_job *jobs, int n, uint8_t *const *pred, uint64_t *sums, void *stream) {

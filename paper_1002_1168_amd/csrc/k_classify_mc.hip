@@ -206,6 +206,10 @@ __device__ __forceinline__ int row_sse(const u32x4 cur, const uint32_t (&p)[4], 
 // part[2 * mb], part[2 * mb + 1].  Eight lanes per MB, lane t predicts rows
 // 2t and 2t+1 (three reference rows at most).  A class byte above 2 raises
 // ST_BAD_CLASS (the MB is still predicted by its vector).
+// FOUR: the job's mv holds four vectors per MB (8 x 8 blocks in raster
+// order); lane t's rows belong to the top or bottom pair, its left 8 pixels
+// to the first block of the pair and its right 8 to the second.
+template <bool FOUR>
 __global__ __launch_bounds__(256) void mc_kernel(const JobDesc *jobs, int n, int total, int chunk, uint32_t *part,
                                                  uint32_t *status) {
     const int t = lane() & 7;
@@ -225,7 +229,7 @@ __global__ __launch_bounds__(256) void mc_kernel(const JobDesc *jobs, int n, int
         const uint32_t cb = ldg8(cls ? cls + k : (const uint8_t *)(mv + k));
         const int cl = cls ? (int)cb : ME_MB_OPAQUE;
         if (on && t == 0 && cl > ME_MB_BOUNDARY) atomicOr(status, ST_BAD_CLASS);
-        const uint32_t w = ldg32(mv + k);
+        const uint32_t w = FOUR ? ldg32(mv + 4 * k + 2 * (t >> 2)) : ldg32(mv + k);
         const size_t o0 = (size_t)y * st + x, o1 = o0 + st;
         const u32x4 c0 = ld16(cur + o0), c1 = ld16(cur + o1);
         uint32_t in0 = 0xFFFFu, in1 = 0xFFFFu;
@@ -240,6 +244,21 @@ __global__ __launch_bounds__(256) void mc_kernel(const JobDesc *jobs, int n, int
         }
         uint32_t p0[4], p1[4];
         predict_rows2(ref, st, W, H, x, y, hx, hy, p0, p1);
+        if constexpr (FOUR) {
+            // the right 8 pixels by the pair's second block vector
+            const uint32_t w2 = ldg32(mv + 4 * k + 2 * (t >> 2) + 1);
+            int hx2 = 0, hy2 = 0;
+            if (cl != ME_MB_TRANSPARENT) {
+                hx2 = (int)(int16_t)(w2 & 0xFFFF);
+                hy2 = (int)(int16_t)(w2 >> 16);
+            }
+            uint32_t q0[4], q1[4];
+            predict_rows2(ref, st, W, H, x, y, hx2, hy2, q0, q1);
+            p0[2] = q0[2];
+            p0[3] = q0[3];
+            p1[2] = q1[2];
+            p1[3] = q1[3];
+        }
         if (on && out) {
             st16(out + o0, p0);
             st16(out + o1, p1);
@@ -314,13 +333,17 @@ hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_
 size_t mc_scratch(int total_mbs) { return (size_t)total_mbs * 8; }
 
 hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, unsigned long long *acc,
-                     uint32_t *status, hipStream_t s, const KernelTimer *t, int per_cu) {
+                     uint32_t *status, hipStream_t s, const KernelTimer *t, int per_cu, bool four) {
     if (total_mbs <= 0) return hipSuccess;
     const int nu = (total_mbs + 7) / 8;
     const int chunk = (flat_chunk(nu, per_cu) + 3) / 4 * 4;
     timer_mark(t, true, s);
-    hipLaunchKernelGGL(mc_kernel, dim3((nu + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk, part,
-                       status);
+    if (four)
+        hipLaunchKernelGGL(mc_kernel<true>, dim3((nu + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk,
+                           part, status);
+    else
+        hipLaunchKernelGGL(mc_kernel<false>, dim3((nu + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs,
+                           chunk, part, status);
     hipError_t e = hipGetLastError();
     timer_mark(t, false, s);
     if (e != hipSuccess) return e;

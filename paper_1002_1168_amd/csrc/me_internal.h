@@ -89,8 +89,16 @@ hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_
                               uint32_t *counters, uint32_t *list, uint32_t *status, hipStream_t s,
                               const KernelTimer *t = nullptr);
 size_t full_search_scratch(int total_mbs);
+// `four`: each job's mv holds four vectors per MB (8 x 8 blocks in raster order)
 hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, unsigned long long *acc,
-                     uint32_t *status, hipStream_t s, const KernelTimer *t = nullptr, int per_cu = 8);
+                     uint32_t *status, hipStream_t s, const KernelTimer *t = nullptr, int per_cu = 8,
+                     bool four = false);
+// Pel-recursive refinement of the 8 x 8 blocks of every texture MB: reads
+// cur, ref, cls, mv_int (start vectors) and tf (the MB's half-pel vector,
+// repeated for boundary MBs); writes four vectors per MB to mv, and per
+// block cost (nullable), iters (nullable), points (nullable).
+hipError_t launch_prs8(const JobDesc *jobs, int n, int total_mbs, const KParams &kp, hipStream_t s,
+                       const KernelTimer *t = nullptr);
 size_t mc_scratch(int total_mbs);
 
 // Row workers (job sets without chains inside the call): bands of

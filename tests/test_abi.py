@@ -140,12 +140,12 @@ def test_async_sse_argument_validation():
 def test_kernel_timing_validation():
     L = me.lib()
     assert L.me_kernel_timing(3) == me.ME_EINVAL      # "every kind" with kind bits
-    assert L.me_kernel_timing(2 << 6) == me.ME_EINVAL  # no such kind
+    assert L.me_kernel_timing(2 << 7) == me.ME_EINVAL  # no such kind
     assert L.me_kernel_timing(-1) == me.ME_EINVAL
     assert L.me_kernel_timing((2 << 1) | (2 << 4)) == me.ME_OK  # search and network only
     assert L.me_kernel_timing(0) == me.ME_OK
     ms, cnt = C.c_double(), C.c_int()
-    assert L.me_kernel_time_ms(6, None, C.byref(ms), C.byref(cnt)) == me.ME_EINVAL
+    assert L.me_kernel_time_ms(7, None, C.byref(ms), C.byref(cnt)) == me.ME_EINVAL
     assert L.me_kernel_time_ms(-1, None, C.byref(ms), C.byref(cnt)) == me.ME_EINVAL
     assert L.me_kernel_time_ms(me.ME_KT_SEARCH, None, None, C.byref(cnt)) == me.ME_EINVAL
 
