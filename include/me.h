@@ -21,7 +21,8 @@
  *  - A full-pel vector d = (dx, dy) predicts cur(x, y) by ref(x+dx, y+dy).
  *    Every me_mv is in HALF-PEL units; integer results are even.
  *  - Admissible vectors: |dx|, |dy| <= search_range and the displaced block
- *    entirely inside the reference frame.
+ *    entirely inside the reference frame (the second condition is dropped
+ *    with ME_FLAG_UNRESTRICTED).
  *  - Every call validates all arguments on the host before touching the GPU
  *    and returns a negative ME_E* code on error (nothing launched).  Calls
  *    are asynchronous on `stream` (a hipStream_t; NULL = default stream)
@@ -83,6 +84,11 @@ typedef struct me_params {
 } me_params;
 
 /* me_params.flags */
+#define ME_FLAG_UNRESTRICTED 0x1u   /* unrestricted vectors (MPEG-4 reference padding; the Section 4
+                                       protocol): a vector is admissible when |dx|, |dy| <= S wherever
+                                       the displaced block lands, the reference being extended by
+                                       repeating its edge pixels (as MC always reads it); applies to
+                                       every search, the half-sample step and me_refine_8x8 */
 #define ME_FLAG_LINE_WORKERS 0x100u /* schedule the proposed search with line workers (one MB position
                                        across a chain's pairs) even when no job's T field is written in
                                        the same call, where row workers (one MB row per wave) are the

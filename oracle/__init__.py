@@ -45,7 +45,8 @@ class _Pair(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("search_range", C.c_int), ("theta", C.c_int), ("eps_q12", C.c_int),
-                ("max_step", C.c_int), ("k_max", C.c_int), ("half_pel", C.c_int)]
+                ("max_step", C.c_int), ("k_max", C.c_int), ("half_pel", C.c_int),
+                ("unrestricted", C.c_int)]
 
 
 @dataclass
@@ -56,10 +57,11 @@ class Params:
     max_step: int = 1
     k_max: int = 8
     half_pel: int = 0
+    unrestricted: int = 0
 
     def _c(self) -> _Params:
         return _Params(self.search_range, self.theta, self.eps_q12, self.max_step,
-                       self.k_max, int(self.half_pel))
+                       self.k_max, int(self.half_pel), int(self.unrestricted))
 
 
 _lib = None
@@ -282,21 +284,23 @@ def psnr_db(sse: int, npix: int) -> float:
     return 10.0 * np.log10(255.0 * 255.0 * npix / sse)
 
 
-def pa_sequence(seq, vop: int | None, params: Params, shape_only=False, pairs=None, seeds=None):
-    """Run the proposed algorithm over consecutive frame pairs (t-1, t) of a
-    synthetic sequence, feeding each pair's full-pel field forward as the
+def pa_sequence(seq, vop: int | None, params: Params, shape_only=False, pairs=None, seeds=None, distance=1):
+    """Run the proposed algorithm over the frame pairs (t - distance, t),
+    t = distance, distance + 1, ... of a synthetic sequence (Section 4 uses a
+    distance of two), feeding each pair's full-pel field forward as the
     temporal candidate of the next.  ``vop=None`` treats frames as
     rectangular.  Returns a list of per-pair dicts (with classes and SSE)."""
-    n = seq.frames - 1 if pairs is None else pairs
+    n = seq.frames - distance if pairs is None else pairs
     res = []
     t_field = None
-    for t in range(1, n + 1):
-        cur, ref = seq.luma[t], seq.luma[t - 1]
+    for i in range(n):
+        t = i + distance
+        cur, ref = seq.luma[t], seq.luma[t - distance]
         ca = ra = cls = None
         if vop is not None:
-            ca, ra = seq.alpha[vop, t], seq.alpha[vop, t - 1]
+            ca, ra = seq.alpha[vop, t], seq.alpha[vop, t - distance]
             cls, _ = classify(ca)
-        sd = None if seeds is None else seeds[t - 1]
+        sd = None if seeds is None else seeds[i]
         out = pa(cur, ref, params, ca, ra, cls, t_field, sd, shape_only)
         out["cls"] = cls
         sse, npx, _ = mc_sse(cur, ref, out["mv"], ca, cls)

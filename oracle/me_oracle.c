@@ -43,6 +43,7 @@ typedef struct {
     int max_step;     /* largest per-axis step of one recursion */
     int k_max;        /* cap on the recursion count */
     int half_pel;     /* 1: half-sample refinement of texture MBs */
+    int unrestricted; /* 1: vectors limited by S only, the reference extended by its edge pixels */
 } or_params;
 
 /* ------------------------------------------------------------ helpers */
@@ -65,7 +66,17 @@ static int plane_cur(const or_pair *fp, int shape, int x, int y) {
     return shape ? shape_at(fp->cur_alpha, fp->stride, x, y) : luma_at(fp->cur_luma, fp->stride, x, y);
 }
 
+/* Reference reads clamp both coordinates to the frame: the reference plane
+ * extended by repeating its edge pixels (MPEG-4's padding for unrestricted
+ * vectors).  With the restricted admissibility every read is in the frame
+ * anyway. */
+static int ref_luma_at(const or_pair *fp, int x, int y) {
+    return luma_at(fp->ref_luma, fp->stride, iclamp(x, 0, fp->width - 1), iclamp(y, 0, fp->height - 1));
+}
+
 static int plane_ref(const or_pair *fp, int shape, int x, int y) {
+    x = iclamp(x, 0, fp->width - 1);
+    y = iclamp(y, 0, fp->height - 1);
     return shape ? shape_at(fp->ref_alpha, fp->stride, x, y) : luma_at(fp->ref_luma, fp->stride, x, y);
 }
 
@@ -106,7 +117,7 @@ static uint32_t sad_n(const or_pair *fp, int x0, int y0, int n, int dx, int dy) 
     for (int j = 0; j < n; ++j)
         for (int i = 0; i < n; ++i)
             s += (uint32_t)iabs(luma_at(fp->cur_luma, fp->stride, x0 + i, y0 + j) -
-                                luma_at(fp->ref_luma, fp->stride, x0 + i + dx, y0 + j + dy));
+                                ref_luma_at(fp, x0 + i + dx, y0 + j + dy));
     return s;
 }
 
@@ -119,7 +130,7 @@ uint32_t or_mismatch(const or_pair *fp, int x0, int y0, int dx, int dy) {
     for (int j = 0; j < 16; ++j)
         for (int i = 0; i < 16; ++i) {
             int a = fp->cur_alpha[(size_t)(y0 + j) * fp->stride + x0 + i] != 0;
-            int b = fp->ref_alpha[(size_t)(y0 + j + dy) * fp->stride + x0 + i + dx] != 0;
+            int b = plane_ref(fp, 1, x0 + i + dx, y0 + j + dy) != 0;
             s += (uint32_t)(a != b);
         }
     return s;
@@ -129,15 +140,28 @@ static uint32_t block_cost(const or_pair *fp, int shape, int x0, int y0, int dx,
     return shape ? or_mismatch(fp, x0, y0, dx, dy) : or_sad(fp, x0, y0, dx, dy);
 }
 
-/* A full-pel vector is admissible when |dx|, |dy| <= S and the whole
- * displaced n x n block lies inside the reference frame. */
-static int feasible_n(const or_pair *fp, int S, int x0, int y0, int n, int dx, int dy) {
-    return iabs(dx) <= S && iabs(dy) <= S && x0 + dx >= 0 && x0 + dx <= fp->width - n && y0 + dy >= 0 &&
-           y0 + dy <= fp->height - n;
+/* A full-pel vector is admissible when |dx|, |dy| <= S and (unless the
+ * reference is extended for unrestricted vectors) the whole displaced n x n
+ * block lies inside the reference frame. */
+static int feasible_n(const or_pair *fp, const or_params *p, int x0, int y0, int n, int dx, int dy) {
+    int S = p->search_range;
+    if (iabs(dx) > S || iabs(dy) > S) return 0;
+    return p->unrestricted ||
+           (x0 + dx >= 0 && x0 + dx <= fp->width - n && y0 + dy >= 0 && y0 + dy <= fp->height - n);
 }
 
-static int feasible(const or_pair *fp, int S, int x0, int y0, int dx, int dy) {
-    return feasible_n(fp, S, x0, y0, 16, dx, dy);
+static int feasible(const or_pair *fp, const or_params *p, int x0, int y0, int dx, int dy) {
+    return feasible_n(fp, p, x0, y0, 16, dx, dy);
+}
+
+/* The admissible box of the n x n block at (x0, y0), per axis. */
+static void box_n(const or_pair *fp, const or_params *p, int x0, int y0, int n, int *lox, int *hix, int *loy,
+                  int *hiy) {
+    int S = p->search_range;
+    *lox = p->unrestricted ? -S : imax(-S, -x0);
+    *hix = p->unrestricted ? S : imin(S, fp->width - n - x0);
+    *loy = p->unrestricted ? -S : imax(-S, -y0);
+    *hiy = p->unrestricted ? S : imin(S, fp->height - n - y0);
 }
 
 /* ------------------------------------ pel-recursive search (Section 3.2) */
@@ -209,9 +233,8 @@ int or_step(int32_t u, int eps_q12, int max_step) {
  */
 static int pel_recursion_n(const or_pair *fp, const or_params *p, int shape, int x0, int y0, int n, int *dx, int *dy,
                            uint32_t *cost) {
-    int S = p->search_range;
-    int lox = imax(-S, -x0), hix = imin(S, fp->width - n - x0);
-    int loy = imax(-S, -y0), hiy = imin(S, fp->height - n - y0);
+    int lox, hix, loy, hiy;
+    box_n(fp, p, x0, y0, n, &lox, &hix, &loy, &hiy);
     int it = 0;
     while (it < p->k_max) {
         int32_t ux, uy;
@@ -271,16 +294,18 @@ uint32_t or_sad_half(const or_pair *fp, int x0, int y0, int hx, int hy) { return
 
 /* The whole integer footprint of the half-sample prediction of the n x n
  * block (n + fx columns, n + fy rows) lies in the reference frame. */
-static int half_feasible_n(const or_pair *fp, int S, int x0, int y0, int n, int hx, int hy) {
+static int half_feasible_n(const or_pair *fp, const or_params *p, int x0, int y0, int n, int hx, int hy) {
+    int S = p->search_range;
     if (iabs(hx) > 2 * S || iabs(hy) > 2 * S) return 0;
+    if (p->unrestricted) return 1;
     int ix = half_to_full(hx), iy = half_to_full(hy);
     int fx = hx - 2 * ix, fy = hy - 2 * iy;
     return x0 + ix >= 0 && x0 + ix + n - 1 + fx <= fp->width - 1 && y0 + iy >= 0 &&
            y0 + iy + n - 1 + fy <= fp->height - 1;
 }
 
-static int half_feasible(const or_pair *fp, int S, int x0, int y0, int hx, int hy) {
-    return half_feasible_n(fp, S, x0, y0, 16, hx, hy);
+static int half_feasible(const or_pair *fp, const or_params *p, int x0, int y0, int hx, int hy) {
+    return half_feasible_n(fp, p, x0, y0, 16, hx, hy);
 }
 
 static const int HALF_OFFS[8][2] = {{-1, -1}, {0, -1}, {1, -1}, {-1, 0}, {1, 0}, {-1, 1}, {0, 1}, {1, 1}};
@@ -296,7 +321,6 @@ static int pa_mb(const or_pair *fp, const uint8_t *cls, const int16_t *t_field, 
                  uint8_t *iters, uint16_t *points) {
     int has_alpha = fp->cur_alpha != NULL && fp->ref_alpha != NULL;
     int wm = fp->width / 16;
-    int S = p->search_range;
     int k = v * wm + h;
     int c = cls ? cls[k] : OR_OPAQUE;
     int x0 = 16 * h, y0 = 16 * v;
@@ -324,7 +348,7 @@ static int pa_mb(const or_pair *fp, const uint8_t *cls, const int16_t *t_field, 
     /* admissible, distinct, in order A, B, C, T */
     int list[4][2], n = 0;
     for (int i = 0; i < 4; ++i) {
-        if (!feasible(fp, S, x0, y0, cand[i][0], cand[i][1])) continue;
+        if (!feasible(fp, p, x0, y0, cand[i][0], cand[i][1])) continue;
         int dup = 0;
         for (int q = 0; q < n; ++q)
             if (list[q][0] == cand[i][0] && list[q][1] == cand[i][1]) dup = 1;
@@ -356,8 +380,8 @@ static int pa_mb(const or_pair *fp, const uint8_t *cls, const int16_t *t_field, 
         /* learned start: clamp into the admissible window, refine,
          * and fall back to the plain recursion when the refined
          * distortion exceeds the BRS minimum by more than 5 % */
-        int lox = imax(-S, -x0), hix = imin(S, fp->width - 16 - x0);
-        int loy = imax(-S, -y0), hiy = imin(S, fp->height - 16 - y0);
+        int lox, hix, loy, hiy;
+        box_n(fp, p, x0, y0, 16, &lox, &hix, &loy, &hiy);
         int sx = iclamp(half_to_full(seed[2 * k]), lox, hix);
         int sy = iclamp(half_to_full(seed[2 * k + 1]), loy, hiy);
         uint32_t sc = block_cost(fp, shape, x0, y0, sx, sy);
@@ -385,7 +409,7 @@ static int pa_mb(const or_pair *fp, const uint8_t *cls, const int16_t *t_field, 
         uint32_t hc = dc;
         for (int o = 0; o < 8; ++o) {
             int qx = hx + HALF_OFFS[o][0], qy = hy + HALF_OFFS[o][1];
-            if (!half_feasible(fp, S, x0, y0, qx, qy)) continue;
+            if (!half_feasible(fp, p, x0, y0, qx, qy)) continue;
             ++pts;
             uint32_t c2 = or_sad_half(fp, x0, y0, qx, qy);
             if (c2 < hc) {
@@ -458,11 +482,13 @@ int or_pa_order(const or_pair *fp, const uint8_t *cls, const int16_t *t_field, c
 /* --------------------------------------------------- baseline searches */
 /* Exhaustive search: every admissible vector; ties broken by the smaller
  * |dx| + |dy|, then the smaller dy, then the smaller dx. */
-static void search_es(const or_pair *fp, int S, int x0, int y0, int *bx, int *by, uint32_t *bc, int *pts) {
+static void search_es(const or_pair *fp, const or_params *p, int x0, int y0, int *bx, int *by, uint32_t *bc,
+                      int *pts) {
+    int S = p->search_range;
     int have = 0, n = 0;
     for (int dy = -S; dy <= S; ++dy) {
         for (int dx = -S; dx <= S; ++dx) {
-            if (!feasible(fp, S, x0, y0, dx, dy)) continue;
+            if (!feasible(fp, p, x0, y0, dx, dy)) continue;
             ++n;
             uint32_t c = or_sad(fp, x0, y0, dx, dy);
             int l1 = iabs(dx) + iabs(dy), bl1 = iabs(*bx) + iabs(*by);
@@ -496,7 +522,9 @@ static void memo_visit(memo *m, int dx, int dy) {
 /* Three-step search: first step 2^(ceil(log2(S+1)) - 1), halved down to 1;
  * each round the eight points around the centre in row order; the centre
  * moves only to a strictly better point (the first one on ties). */
-static void search_tss(const or_pair *fp, int S, int x0, int y0, memo *m, int *bx, int *by, uint32_t *bc) {
+static void search_tss(const or_pair *fp, const or_params *p, int x0, int y0, memo *m, int *bx, int *by,
+                       uint32_t *bc) {
+    int S = p->search_range;
     int p2 = 1;
     while (p2 < S + 1) p2 *= 2;
     int step = p2 / 2;
@@ -510,7 +538,7 @@ static void search_tss(const or_pair *fp, int S, int x0, int y0, memo *m, int *b
             for (int i = -1; i <= 1; ++i) {
                 if (i == 0 && j == 0) continue;
                 int qx = cx + i * step, qy = cy + j * step;
-                if (!feasible(fp, S, x0, y0, qx, qy)) continue;
+                if (!feasible(fp, p, x0, y0, qx, qy)) continue;
                 memo_visit(m, qx, qy);
                 uint32_t c = or_sad(fp, x0, y0, qx, qy);
                 if (c < nc) {
@@ -535,7 +563,8 @@ static const int SDSP[4][2] = {{0, -1}, {-1, 0}, {1, 0}, {0, 1}};
 
 /* Diamond search: the large diamond is repeated until its centre is the
  * best point (moves need a strictly smaller SAD), then one small diamond. */
-static void search_ds(const or_pair *fp, int S, int x0, int y0, memo *m, int *bx, int *by, uint32_t *bc) {
+static void search_ds(const or_pair *fp, const or_params *p, int x0, int y0, memo *m, int *bx, int *by,
+                      uint32_t *bc) {
     int cx = 0, cy = 0;
     uint32_t cc = or_sad(fp, x0, y0, 0, 0);
     memo_visit(m, 0, 0);
@@ -544,7 +573,7 @@ static void search_ds(const or_pair *fp, int S, int x0, int y0, memo *m, int *bx
         uint32_t nc = cc;
         for (int o = 0; o < 8; ++o) {
             int qx = cx + LDSP[o][0], qy = cy + LDSP[o][1];
-            if (!feasible(fp, S, x0, y0, qx, qy)) continue;
+            if (!feasible(fp, p, x0, y0, qx, qy)) continue;
             memo_visit(m, qx, qy);
             uint32_t c = or_sad(fp, x0, y0, qx, qy);
             if (c < nc) {
@@ -562,7 +591,7 @@ static void search_ds(const or_pair *fp, int S, int x0, int y0, memo *m, int *bx
     uint32_t nc = cc;
     for (int o = 0; o < 4; ++o) {
         int qx = cx + SDSP[o][0], qy = cy + SDSP[o][1];
-        if (!feasible(fp, S, x0, y0, qx, qy)) continue;
+        if (!feasible(fp, p, x0, y0, qx, qy)) continue;
         memo_visit(m, qx, qy);
         uint32_t c = or_sad(fp, x0, y0, qx, qy);
         if (c < nc) {
@@ -584,7 +613,9 @@ static void search_ds(const or_pair *fp, int S, int x0, int y0, memo *m, int *bx
  * 3 x 3 square of step 1 around the centre.  Points of a square that were
  * evaluated before are not counted again; moves need a strictly smaller SAD
  * and the first point in row order wins ties. */
-static void search_4ss(const or_pair *fp, int S, int x0, int y0, memo *m, int *bx, int *by, uint32_t *bc) {
+static void search_4ss(const or_pair *fp, const or_params *p, int x0, int y0, memo *m, int *bx, int *by,
+                       uint32_t *bc) {
+    int S = p->search_range;
     int n5 = S / 2; /* = ceil((S - 1) / 2) */
     if (n5 < 1) n5 = 1;
     int cx = 0, cy = 0;
@@ -598,7 +629,7 @@ static void search_4ss(const or_pair *fp, int S, int x0, int y0, memo *m, int *b
             for (int i = -1; i <= 1; ++i) {
                 if (i == 0 && j == 0) continue;
                 int qx = cx + i * step, qy = cy + j * step;
-                if (!feasible(fp, S, x0, y0, qx, qy)) continue;
+                if (!feasible(fp, p, x0, y0, qx, qy)) continue;
                 memo_visit(m, qx, qy);
                 uint32_t c = or_sad(fp, x0, y0, qx, qy);
                 if (c < nc) {
@@ -638,16 +669,16 @@ int or_search(int method, const or_pair *fp, const uint8_t *cls, const or_params
             uint32_t bc = 0;
             if (c != OR_TRANSPARENT) {
                 if (method == 0) {
-                    search_es(fp, S, 16 * h, 16 * v, &bx, &by, &bc, &pts);
+                    search_es(fp, p, 16 * h, 16 * v, &bx, &by, &bc, &pts);
                 } else {
                     memo m = {S, seen, 0};
                     memset(seen, 0, win);
                     if (method == 1)
-                        search_tss(fp, S, 16 * h, 16 * v, &m, &bx, &by, &bc);
+                        search_tss(fp, p, 16 * h, 16 * v, &m, &bx, &by, &bc);
                     else if (method == 2)
-                        search_ds(fp, S, 16 * h, 16 * v, &m, &bx, &by, &bc);
+                        search_ds(fp, p, 16 * h, 16 * v, &m, &bx, &by, &bc);
                     else
-                        search_4ss(fp, S, 16 * h, 16 * v, &m, &bx, &by, &bc);
+                        search_4ss(fp, p, 16 * h, 16 * v, &m, &bx, &by, &bc);
                     pts = m.count;
                 }
             }
@@ -717,7 +748,6 @@ int or_prs8(const or_pair *fp, const uint8_t *cls, const int16_t *mv, const int1
     if (!fp || !p || !mv || !mv_int || !mv4) return -1;
     if (fp->width % 16 || fp->height % 16 || fp->width <= 0 || fp->height <= 0) return -1;
     int wm = fp->width / 16, hm = fp->height / 16;
-    int S = p->search_range;
     for (int v = 0; v < hm; ++v) {
         for (int h = 0; h < wm; ++h) {
             int k = v * wm + h;
@@ -738,7 +768,7 @@ int or_prs8(const or_pair *fp, const uint8_t *cls, const int16_t *mv, const int1
                         int bhx = hx, bhy = hy;
                         for (int o = 0; o < 8; ++o) {
                             int qx = hx + HALF_OFFS[o][0], qy = hy + HALF_OFFS[o][1];
-                            if (!half_feasible_n(fp, S, bx0, by0, 8, qx, qy)) continue;
+                            if (!half_feasible_n(fp, p, bx0, by0, 8, qx, qy)) continue;
                             ++pts;
                             uint32_t c2 = sad_half_n(fp, bx0, by0, 8, qx, qy);
                             if (c2 < cost) {

@@ -264,6 +264,17 @@ struct Ctx {
 
 __device__ __forceinline__ int cost_of(const Ctx &c, int sad) { return c.shape ? sad / 255 : sad; }
 
+// Admissible box of the MB at (x0, y0): |d| <= S with the displaced block in
+// the frame, or (unrestricted vectors) |d| <= S only - the staged window
+// covers every such offset with edge-replicated bytes.
+__device__ __forceinline__ void set_box(Ctx &c, const KParams &kp, int x0, int y0, int W, int H) {
+    const int S = kp.S;
+    c.lox = kp.unrestricted ? -S : max(-S, -x0);
+    c.hix = kp.unrestricted ? S : min(S, W - 16 - x0);
+    c.loy = kp.unrestricted ? -S : max(-S, -y0);
+    c.hiy = kp.unrestricted ? S : min(S, H - 16 - y0);
+}
+
 // One fused pass at full-pel offset (dx, dy): SAD of the block and the
 // gradient sums of Eqs. 3-5 (central differences of the reference at the
 // displaced position).
@@ -357,8 +368,9 @@ __device__ int half_refine(const Ctx &c, const KParams &kp, int dx, int dy, int 
         const int oxr = ox < 0 ? 0 : 1, oyr = oy < 0 ? 0 : 1;  // neighbourhood origin of A
         const int qx = 2 * dx + ox, qy = 2 * dy + oy;
         const int ix = dx + (ox < 0 ? -1 : 0), iy = dy + (oy < 0 ? -1 : 0);
-        feas[o] = abs(qx) <= 2 * kp.S && abs(qy) <= 2 * kp.S && c.x0 + ix >= 0 && c.x0 + ix + 15 + fx <= c.W - 1 &&
-                  c.y0 + iy >= 0 && c.y0 + iy + 15 + fy <= c.H - 1;
+        feas[o] = abs(qx) <= 2 * kp.S && abs(qy) <= 2 * kp.S &&
+                  (kp.unrestricted || (c.x0 + ix >= 0 && c.x0 + ix + 15 + fx <= c.W - 1 && c.y0 + iy >= 0 &&
+                                       c.y0 + iy + 15 + fy <= c.H - 1));
         nfeas += feas[o];
         int s = 0;
 #pragma unroll
@@ -802,10 +814,7 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
             c.y0 = y0;
             c.W = W;
             c.H = H;
-            c.lox = max(-S, -x0);
-            c.hix = min(S, W - 16 - x0);
-            c.loy = max(-S, -y0);
-            c.hiy = min(S, H - 16 - y0);
+            set_box(c, kp, x0, y0, W, H);
             const uint32_t cur4 = pf ? pcur4 : ldg32((const uint32_t *)(Pc + (size_t)(y0 + j) * st + x0 + 4 * q));
             if (!pf) {
                 if constexpr (EM > 0) {
@@ -1074,10 +1083,7 @@ __global__ __launch_bounds__(64 * NW) void pa2_kernel(PaArgs a) {
             c.y0 = y0;
             c.W = W;
             c.H = H;
-            c.lox = max(-S, -x0);
-            c.hix = min(S, W - 16 - x0);
-            c.loy = max(-S, -y0);
-            c.hiy = min(S, H - 16 - y0);
+            set_box(c, kp, x0, y0, W, H);
             const uint32_t cur4 = ldg32((const uint32_t *)(Pc + (size_t)(y0 + j) * st + x0 + 4 * q));
             if constexpr (EM > 0) {
                 uint32_t wv4[EM];
@@ -1602,10 +1608,7 @@ __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
                 c.y0 = y0;
                 c.W = W;
                 c.H = H;
-                c.lox = max(-S, -x0);
-                c.hix = min(S, W - 16 - x0);
-                c.loy = max(-S, -y0);
-                c.hiy = min(S, H - 16 - y0);
+                set_box(c, kp, x0, y0, W, H);
                 c.c4 = c.shape ? bin4(cur4) : cur4;
                 // B and C from the row above, once that row is far enough
                 const bool useB = v > 0 && bit_of(upn, h);

@@ -7,7 +7,7 @@
 // = block b, row j, half q: four pixels), so the four blocks' recursions run
 // side by side and every block sum is a 16-lane DPP reduction.  Reference
 // bytes come straight from global memory (L2), coordinates clamped to the
-// frame.
+// frame (which is also the edge extension of unrestricted vectors).
 #include <algorithm>
 
 #include "me_internal.h"
@@ -128,8 +128,8 @@ __global__ __launch_bounds__(256) void prs8_kernel(const JobDesc *jobs, int n, i
         const uint32_t w0 = ldg32(mvi + k);
         int dx = ((int)(int16_t)(w0 & 0xFFFF)) >> 1, dy = ((int)(int16_t)(w0 >> 16)) >> 1;
         // admissible box of the 8 x 8 block
-        const int lox = max(-S, -bx0), hix = min(S, W - 8 - bx0);
-        const int loy = max(-S, -by0), hiy = min(S, H - 8 - by0);
+        const int lox = kp.unrestricted ? -S : max(-S, -bx0), hix = kp.unrestricted ? S : min(S, W - 8 - bx0);
+        const int loy = kp.unrestricted ? -S : max(-S, -by0), hiy = kp.unrestricted ? S : min(S, H - 8 - by0);
         Pass sw = pass8(p, dx, dy);
         int cost = sw.sad, it = 0;
         bool active = kp.k_max > 0;
@@ -191,8 +191,9 @@ __global__ __launch_bounds__(256) void prs8_kernel(const JobDesc *jobs, int n, i
                 const int oxr = ox < 0 ? 0 : 1, oyr = oy < 0 ? 0 : 1;  // neighbourhood origin of A
                 const int qx = 2 * dx + ox, qy = 2 * dy + oy;
                 const int ix = dx + (ox < 0 ? -1 : 0), iy = dy + (oy < 0 ? -1 : 0);
-                feas[o] = abs(qx) <= 2 * S && abs(qy) <= 2 * S && bx0 + ix >= 0 && bx0 + ix + 7 + fx <= W - 1 &&
-                          by0 + iy >= 0 && by0 + iy + 7 + fy <= H - 1;
+                feas[o] = abs(qx) <= 2 * S && abs(qy) <= 2 * S &&
+                          (kp.unrestricted || (bx0 + ix >= 0 && bx0 + ix + 7 + fx <= W - 1 && by0 + iy >= 0 &&
+                                               by0 + iy + 7 + fy <= H - 1));
                 int s = 0;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {

@@ -95,8 +95,8 @@ __global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, con
     uint32_t *win = lds;              // 4 copies
     uint32_t *curb = lds + 4 * csz;   // 64 dwords
     unsigned long long *red = (unsigned long long *)(curb + 64);  // 4 wave minima
-    // copy 0 from the frame (rows clamped, edge dwords permuted: bytes outside
-    // the frame are never read by an admissible candidate), eight loads in
+    // copy 0 from the frame (rows clamped, edge dwords permuted: the frame
+    // extended by its edge pixels, which unrestricted vectors read), eight loads in
     // flight per thread; copy s dword w = window bytes 4w+s .. 4w+s+3 is then
     // built from copy 0 in LDS
     const int wx0 = x0 - S, wy0 = y0 - S;
@@ -126,8 +126,8 @@ __global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, con
 #pragma unroll
     for (int i = 0; i < 64; ++i) cr[i] = curb[i];
 
-    const int lox = max(-S, -x0), hix = min(S, W - 16 - x0);
-    const int loy = max(-S, -y0), hiy = min(S, H - 16 - y0);
+    const int lox = kp.unrestricted ? -S : max(-S, -x0), hix = kp.unrestricted ? S : min(S, W - 16 - x0);
+    const int loy = kp.unrestricted ? -S : max(-S, -y0), hiy = kp.unrestricted ? S : min(S, H - 16 - y0);
     const int ncol = 2 * S + 1;
     const int ngrp = (ncol + kEsG - 1) / kEsG;
     unsigned long long best = ~0ull;
@@ -195,7 +195,7 @@ __constant__ int kSdsp[4][2] = {{0, -1}, {-1, 0}, {1, 0}, {0, 1}};
 
 struct Mb {
     const uint8_t *ref;
-    int st, x, y;  // this lane's first pixel
+    int st, W, H, x, y;  // frame size, this lane's first pixel
     uint32_t c4;
     int lox, hix, loy, hiy, S;
     uint32_t *memo;
@@ -225,7 +225,9 @@ __device__ __forceinline__ void eval_pts(Mb &m, const int (&ox)[N], const int (&
         ok[i] = feas(m, ox[i], oy[i]);
         part[i] = 0;
         if (ok[i]) {
-            uint32_t r4 = ld4(m.ref + (size_t)(m.y + oy[i]) * m.st + m.x + ox[i]);
+            // coordinates clamped: the frame extended by its edge pixels
+            // (reached only by unrestricted vectors)
+            const uint32_t r4 = ld4_clamped(m.ref + (size_t)iclamp(m.y + oy[i], 0, m.H - 1) * m.st, m.x + ox[i], m.W);
             part[i] = (int)__builtin_amdgcn_sad_u8(m.c4, r4, 0u);
         }
     }
@@ -260,13 +262,15 @@ __global__ __launch_bounds__(64) void tss_ds_kernel(const JobDesc *jobs, const u
     Mb m;
     m.ref = J.ref;
     m.st = J.stride;
+    m.W = J.width;
+    m.H = J.height;
     m.x = x0 + 4 * (l & 3);
     m.y = y0 + (l >> 2);
     m.c4 = *(const uint32_t *)(J.cur + (size_t)m.y * m.st + m.x);
-    m.lox = max(-S, -x0);
-    m.hix = min(S, J.width - 16 - x0);
-    m.loy = max(-S, -y0);
-    m.hiy = min(S, J.height - 16 - y0);
+    m.lox = kp.unrestricted ? -S : max(-S, -x0);
+    m.hix = kp.unrestricted ? S : min(S, J.width - 16 - x0);
+    m.loy = kp.unrestricted ? -S : max(-S, -y0);
+    m.hiy = kp.unrestricted ? S : min(S, J.height - 16 - y0);
     m.S = S;
     m.memo = memo;
     m.pts = 0;

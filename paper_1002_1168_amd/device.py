@@ -88,18 +88,20 @@ class DeviceSequence:
         return fr, cp, bp
 
     def pair_jobs(self, vop: int | None, out: Outputs, pairs=None, chained=True, use_class=True,
-                  seeds: torch.Tensor | None = None) -> list[me_job]:
-        """Jobs for frame pairs (t-1, t), t = 1..P.  ``chained``: each pair's T
-        field is the previous pair's mv_int (the first pair gets none)."""
-        P = self.F - 1 if pairs is None else pairs
+                  seeds: torch.Tensor | None = None, distance: int = 1) -> list[me_job]:
+        """Jobs for frame pairs (t - distance, t), t = distance .. distance + P - 1
+        (reference ``distance`` frames back).  ``chained``: each pair's T field
+        is the previous pair's mv_int (the first pair gets none)."""
+        P = self.F - distance if pairs is None else pairs
         jobs = []
         for i in range(P):
-            t = i + 1
+            t = i + distance
+            r = t - distance
             ca = ra = cls = None
             if vop is not None:
-                ca, ra = self.alpha[vop, t], self.alpha[vop, t - 1]
+                ca, ra = self.alpha[vop, t], self.alpha[vop, r]
                 cls = self.cls[vop, t] if use_class else None
             tf = out.mv_int[i - 1] if (chained and i > 0) else None
             sd = None if seeds is None else seeds[i]
-            jobs.append(job(self.luma[t], self.luma[t - 1], ca, ra, cls, tf, out, i, sd))
+            jobs.append(job(self.luma[t], self.luma[r], ca, ra, cls, tf, out, i, sd))
         return jobs

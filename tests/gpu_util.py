@@ -15,7 +15,8 @@ def say(*a):
 
 
 def oracle_params(p: me.me_params) -> oracle.Params:
-    return oracle.Params(p.search_range, p.theta, p.eps_q12, p.max_step, p.k_max, p.half_pel)
+    return oracle.Params(p.search_range, p.theta, p.eps_q12, p.max_step, p.k_max, p.half_pel,
+                         int(bool(p.flags & me.ME_FLAG_UNRESTRICTED)))
 
 
 def gpu_classify(ds: dv.DeviceSequence):
@@ -26,16 +27,17 @@ def gpu_classify(ds: dv.DeviceSequence):
     assert me.me_device_status(dv.stream_handle()) == me.ME_OK
 
 
-def gpu_pa(ds: dv.DeviceSequence, vops, params, pairs, shape_only=False, one_call=True, chained=True):
-    """PA for the listed VOPs (None = rectangular) over `pairs` pairs.
-    Returns {vop: host outputs}.  With one_call every VOP chain is solved in
-    a single launch; otherwise one call per pair (T read from memory)."""
+def gpu_pa(ds: dv.DeviceSequence, vops, params, pairs, shape_only=False, one_call=True, chained=True, distance=1):
+    """PA for the listed VOPs (None = rectangular) over `pairs` pairs
+    (reference `distance` frames back).  Returns {vop: host outputs}.  With
+    one_call every VOP chain is solved in a single launch; otherwise one
+    call per pair (T read from memory)."""
     import torch
     outs, jobs = {}, []
     for v in vops:
         out = dv.Outputs.alloc(pairs, ds.hm, ds.wm)
         outs[v] = out
-        jobs.append(ds.pair_jobs(v, out, pairs, chained=chained))
+        jobs.append(ds.pair_jobs(v, out, pairs, chained=chained, distance=distance))
     fn = me.me_shape_search if shape_only else me.me_texture_recursive
     s = dv.stream_handle()
     if one_call:
@@ -56,8 +58,9 @@ def gpu_pa(ds: dv.DeviceSequence, vops, params, pairs, shape_only=False, one_cal
     return {v: o.host() for v, o in outs.items()}
 
 
-def oracle_pa(seq, vop, params, pairs, shape_only=False):
-    res = oracle.pa_sequence(seq, vop, oracle_params(params), shape_only=shape_only, pairs=pairs)
+def oracle_pa(seq, vop, params, pairs, shape_only=False, distance=1):
+    res = oracle.pa_sequence(seq, vop, oracle_params(params), shape_only=shape_only, pairs=pairs,
+                             distance=distance)
     return {k: np.stack([r[k] for r in res]) for k in ("mv", "mv_int", "cost", "iters", "points")}
 
 

@@ -41,6 +41,8 @@ CASES = {
     "noise-kmax": (lambda: synth.random_frames(7, 64, 48, frames=3, vops=1, search_range=4), [0, None],
                    dict(search_range=4, k_max=255, max_step=2), 2),
     "eps-half": (lambda: synth.qcif_ellipse(frames=3), [0], dict(search_range=7, eps_q12=2048, k_max=0), 2),
+    "unrestricted": (lambda: synth.qcif_ellipse(frames=4), [0, None],
+                     dict(search_range=7, half_pel=1, flags=me.ME_FLAG_UNRESTRICTED), 3),
 }
 
 

@@ -51,13 +51,13 @@ def test_classify_parity(torch_cuda, maker):
 
 
 # ----------------------------------------------------------- proposed method
-def check_pa(seq, vops, params, pairs, shape_only=False, one_call=True, chained=True, label=""):
+def check_pa(seq, vops, params, pairs, shape_only=False, one_call=True, chained=True, label="", distance=1):
     say("pa", label, seq.name, seq.width, seq.height, "vops", vops, "pairs", pairs, "shape_only", shape_only)
     ds = dseq(seq)
     gpu_classify(ds)
-    got = gpu_pa(ds, vops, params, pairs, shape_only, one_call, chained)
+    got = gpu_pa(ds, vops, params, pairs, shape_only, one_call, chained, distance=distance)
     for v in vops:
-        want = oracle_pa(seq, v, params, pairs, shape_only)
+        want = oracle_pa(seq, v, params, pairs, shape_only, distance=distance)
         assert_same(got[v], want, f"{label} vop {v}")
     return got
 
@@ -112,6 +112,58 @@ def test_pa_per_pair_rows_and_lines(torch_cuda, case, flags):
             dict(search_range=2), 2, False
     check_pa(seq, vops, me.me_default_params(flags=flags, **p), P, shape_only=so, one_call=False,
              label=f"per-pair {case} flags {flags}")
+
+
+# unrestricted vectors (reference padding, Section 4 protocol): the chained
+# launch (line workers), one call per pair (row workers, and line workers
+# forced), shape-only, half-pel at S=32
+@pytest.mark.parametrize("mode", ["chained", "rows", "lines", "shape", "hd-halfpel"])
+def test_pa_unrestricted(torch_cuda, mode):
+    U = me.ME_FLAG_UNRESTRICTED
+    if mode == "hd-halfpel":
+        seq = synth.hd_streams(frames=3, streams=1)[0]
+        check_pa(seq, [0, 1], me.me_default_params(search_range=32, half_pel=1, flags=U), 2, one_call=False,
+                 label="unrestricted hd")
+        return
+    seq = synth.qcif_ellipse(frames=6)
+    p = me.me_default_params(search_range=7, flags=U | (me.ME_FLAG_LINE_WORKERS if mode == "lines" else 0))
+    if mode == "shape":
+        check_pa(synth.cif_two_vops(frames=4), [0, 1], me.me_default_params(search_range=16, flags=U), 3,
+                 shape_only=True, label="unrestricted shape")
+    else:
+        check_pa(seq, [0, None], p, 5, one_call=mode == "chained", label=f"unrestricted {mode}")
+
+
+# the Section 4 protocol: reference frame two back, T from the previous pair
+@pytest.mark.parametrize("one_call", [True, False])
+@pytest.mark.parametrize("flags", [0, me.ME_FLAG_UNRESTRICTED])
+def test_pa_frame_distance_two(torch_cuda, one_call, flags):
+    seq = synth.qcif_ellipse(frames=8)
+    check_pa(seq, [0, None], me.me_default_params(search_range=7, flags=flags), 6, one_call=one_call,
+             label=f"distance 2 flags {flags}", distance=2)
+
+
+@pytest.mark.parametrize("method", [me.ME_ES, me.ME_TSS, me.ME_DS, me.ME_4SS])
+def test_search_unrestricted(torch_cuda, method):
+    import torch
+    from paper_1002_1168_amd import device as dv
+    for seq, S, vop in ((synth.qcif_ellipse(frames=3), 7, None), (synth.cif_two_vops(frames=3), 16, 0)):
+        say("search unrestricted", method, seq.name, S)
+        ds = dseq(seq)
+        if vop is not None:
+            gpu_classify(ds)
+        out = dv.Outputs.alloc(2, ds.hm, ds.wm)
+        p = me.me_default_params(search_range=S, flags=me.ME_FLAG_UNRESTRICTED)
+        me.me_full_search(method, ds.pair_jobs(vop, out, 2, chained=False), p, stream=dv.stream_handle())
+        torch.cuda.synchronize()
+        assert me.me_device_status(dv.stream_handle()) == me.ME_OK
+        got = out.host()
+        for i in range(2):
+            t = i + 1
+            cls = oracle.classify(seq.alpha[vop, t])[0] if vop is not None else None
+            want = oracle.search(method, seq.luma[t], seq.luma[t - 1], oracle_params(p), cls)
+            assert_same({k: got[k][i] for k in got}, want, f"unrestricted method {method} pair {i}",
+                        keys=("mv", "mv_int", "cost", "points"))
 
 
 def test_pa_rows_bad_class_raises_status(torch_cuda):
