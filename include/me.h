@@ -89,6 +89,12 @@ typedef struct me_params {
                                        the displaced block lands, the reference being extended by
                                        repeating its edge pixels (as MC always reads it); applies to
                                        every search, the half-sample step and me_refine_8x8 */
+#define ME_FLAG_T_TEXTURE 0x2u      /* Section 3.1 text: a boundary MB's temporal candidate T is evaluated
+                                       on texture - its spatial candidates A, B, C are scored on the
+                                       BABs (first minimum), and T replaces their winner when its luma
+                                       SAD over the MB's VOP pixels is strictly lower (one more compared
+                                       block); the recursion then runs on the BABs as before.  Used by
+                                       me_texture_recursive (me_shape_search ignores it) */
 #define ME_FLAG_LINE_WORKERS 0x100u /* schedule the proposed search with line workers (one MB position
                                        across a chain's pairs) even when no job's T field is written in
                                        the same call, where row workers (one MB row per wave) are the

@@ -44,6 +44,7 @@ typedef struct {
     int k_max;        /* cap on the recursion count */
     int half_pel;     /* 1: half-sample refinement of texture MBs */
     int unrestricted; /* 1: vectors limited by S only, the reference extended by its edge pixels */
+    int t_texture;    /* 1: Section 3.1 text - a boundary MB's T is scored on texture */
 } or_params;
 
 /* ------------------------------------------------------------ helpers */
@@ -138,6 +139,18 @@ uint32_t or_mismatch(const or_pair *fp, int x0, int y0, int dx, int dy) {
 
 static uint32_t block_cost(const or_pair *fp, int shape, int x0, int y0, int dx, int dy) {
     return shape ? or_mismatch(fp, x0, y0, dx, dy) : or_sad(fp, x0, y0, dx, dy);
+}
+
+/* Luma SAD of the 16 x 16 block at (x0, y0) over the pixels of the current
+ * VOP only (alpha != 0): the texture distortion of a boundary MB. */
+static uint32_t masked_sad(const or_pair *fp, int x0, int y0, int dx, int dy) {
+    uint32_t s = 0;
+    for (int j = 0; j < 16; ++j)
+        for (int i = 0; i < 16; ++i)
+            if (fp->cur_alpha[(size_t)(y0 + j) * fp->stride + x0 + i] != 0)
+                s += (uint32_t)iabs(luma_at(fp->cur_luma, fp->stride, x0 + i, y0 + j) -
+                                    ref_luma_at(fp, x0 + i + dx, y0 + j + dy));
+    return s;
 }
 
 /* A full-pel vector is admissible when |dx|, |dy| <= S and (unless the
@@ -346,7 +359,7 @@ static int pa_mb(const or_pair *fp, const uint8_t *cls, const int16_t *t_field, 
     cand[3][0] = t_field ? half_to_full(t_field[2 * k]) : 0;
     cand[3][1] = t_field ? half_to_full(t_field[2 * k + 1]) : 0;
     /* admissible, distinct, in order A, B, C, T */
-    int list[4][2], n = 0;
+    int list[4][2], n = 0, has_t = 0;
     for (int i = 0; i < 4; ++i) {
         if (!feasible(fp, p, x0, y0, cand[i][0], cand[i][1])) continue;
         int dup = 0;
@@ -356,24 +369,53 @@ static int pa_mb(const or_pair *fp, const uint8_t *cls, const int16_t *t_field, 
             list[n][0] = cand[i][0];
             list[n][1] = cand[i][1];
             ++n;
+            has_t = i == 3;
         }
     }
     if (n == 0) {
         list[0][0] = list[0][1] = 0;
         n = 1;
     }
-    /* Min[...] keeps the first minimum (MATLAB min semantics) */
-    int bx = list[0][0], by = list[0][1];
-    uint32_t bc = block_cost(fp, shape, x0, y0, bx, by);
-    for (int i = 1; i < n; ++i) {
-        uint32_t ci = block_cost(fp, shape, x0, y0, list[i][0], list[i][1]);
-        if (ci < bc) {
-            bc = ci;
-            bx = list[i][0];
-            by = list[i][1];
+    int bx, by, pts = n;
+    uint32_t bc;
+    if (p->t_texture && !shape_only && c == OR_BOUNDARY && has_t && n > 1) {
+        /* Section 3.1, text: the spatial candidates are scored on the
+         * BABs (first minimum), T on texture - T replaces the spatial
+         * winner when its luma SAD over the VOP pixels is strictly lower;
+         * the spatial winner's texture comparison is one more block */
+        bx = list[0][0];
+        by = list[0][1];
+        bc = block_cost(fp, shape, x0, y0, bx, by);
+        for (int i = 1; i < n - 1; ++i) {
+            uint32_t ci = block_cost(fp, shape, x0, y0, list[i][0], list[i][1]);
+            if (ci < bc) {
+                bc = ci;
+                bx = list[i][0];
+                by = list[i][1];
+            }
+        }
+        int tx = list[n - 1][0], ty = list[n - 1][1];
+        if (masked_sad(fp, x0, y0, tx, ty) < masked_sad(fp, x0, y0, bx, by)) {
+            bx = tx;
+            by = ty;
+            bc = block_cost(fp, shape, x0, y0, bx, by);
+        }
+        pts = n + 1;
+    } else {
+        /* Min[...] keeps the first minimum (MATLAB min semantics) */
+        bx = list[0][0];
+        by = list[0][1];
+        bc = block_cost(fp, shape, x0, y0, bx, by);
+        for (int i = 1; i < n; ++i) {
+            uint32_t ci = block_cost(fp, shape, x0, y0, list[i][0], list[i][1]);
+            if (ci < bc) {
+                bc = ci;
+                bx = list[i][0];
+                by = list[i][1];
+            }
         }
     }
-    int pts = n, its = 0;
+    int its = 0;
     int dx = bx, dy = by;
     uint32_t dc = bc;
     if (seed && !shape) {

@@ -260,6 +260,11 @@ struct Ctx {
     uint32_t c4;       // this lane's 4 current pixels
     bool shape;
     int lox, hix, loy, hiy;
+    // texture of a boundary MB, for T scored on texture (Section 3.1 text):
+    // the reference luma, its pitch, this lane's 4 current luma pixels
+    const uint8_t *ref_l;
+    int st;
+    uint32_t tl4;
 };
 
 __device__ __forceinline__ int cost_of(const Ctx &c, int sad) { return c.shape ? sad / 255 : sad; }
@@ -443,19 +448,38 @@ __device__ MbOut search_mb(const uint32_t *seed, const Ctx &c, int k, int (&cx)[
     const int p01 = wave_sum(part[0] | (part[1] << 16));
     const int p23 = wave_sum(part[2] | (part[3] << 16));
     const int costs[4] = {p01 & 0xFFFF, (int)((uint32_t)p01 >> 16), p23 & 0xFFFF, (int)((uint32_t)p23 >> 16)};
-    // Min[...]: the first minimum in list order
+    // Min[...]: the first minimum in list order.  With T scored on texture
+    // (a boundary MB whose list holds T and a spatial entry), the first
+    // minimum of the spatial entries' BAB costs, then T replaces it when its
+    // luma SAD over the VOP pixels is strictly lower.
+    const bool tex_t = kp.t_texture && c.shape && !kp.shape_only && keep[3] && n > 1;
     int dx = 0, dy = 0, bc = 0x7FFFFFFF;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int ci = cost_of(c, costs[i]);
-        if (keep[i] && ci < bc) {
+        if (keep[i] && (i < 3 || !tex_t) && ci < bc) {
             bc = ci;
             dx = cx[i];
             dy = cy[i];
         }
     }
+    if (tex_t) {
+        // c.c4 is the 0/255 mask of the current VOP pixels: both SADs over it
+        const int ry = c.y0 + (lane() >> 2), rx = c.x0 + 4 * (lane() & 3);
+        const uint32_t rs = ld4_clamped(c.ref_l + (size_t)iclamp(ry + dy, 0, c.H - 1) * c.st, rx + dx, c.W);
+        const uint32_t rt = ld4_clamped(c.ref_l + (size_t)iclamp(ry + cy[3], 0, c.H - 1) * c.st, rx + cx[3], c.W);
+        const uint32_t lm = c.tl4 & c.c4;
+        const int ps = (int)__builtin_amdgcn_sad_u8(lm, rs & c.c4, 0u);
+        const int pt = (int)__builtin_amdgcn_sad_u8(lm, rt & c.c4, 0u);
+        const int pk = wave_sum(ps | (pt << 16));
+        if ((int)((uint32_t)pk >> 16) < (pk & 0xFFFF)) {
+            dx = cx[3];
+            dy = cy[3];
+            bc = cost_of(c, costs[3]);
+        }
+    }
     int dc = bc;
-    int pts = n, its = 0;
+    int pts = n + (tex_t ? 1 : 0), its = 0;
     if (seed && !c.shape) {
         const uint32_t w = (uint32_t)uni((int)ldg32(seed + k));
         int sx = iclamp(mvx_full(w), c.lox, c.hix), sy = iclamp(mvy_full(w), c.loy, c.hiy);
@@ -854,6 +878,11 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
                 if (pf) plan.write(win0, pnv, c.shape);
             }
             c.c4 = c.shape ? bin4(cur4) : cur4;
+            if (kp.t_texture && c.shape && !kp.shape_only) {
+                c.ref_l = D.ptr<const uint8_t>(DW(ref));
+                c.st = st;
+                c.tl4 = ldg32((const uint32_t *)(D.ptr<const uint8_t>(DW(cur)) + (size_t)(y0 + j) * st + x0 + 4 * q));
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const uint32_t lo = (uint32_t)uni((int)(uint32_t)val[i]);
@@ -1610,6 +1639,11 @@ __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
                 c.H = H;
                 set_box(c, kp, x0, y0, W, H);
                 c.c4 = c.shape ? bin4(cur4) : cur4;
+                if (kp.t_texture && c.shape && !kp.shape_only) {
+                    c.ref_l = D.ptr<const uint8_t>(DW(ref));
+                    c.st = st;
+                    c.tl4 = ldg32((const uint32_t *)(D.ptr<const uint8_t>(DW(cur)) + (size_t)(y0 + j) * st + x0 + 4 * q));
+                }
                 // B and C from the row above, once that row is far enough
                 const bool useB = v > 0 && bit_of(upn, h);
                 const bool useC = v > 0 && h + 1 < wm && bit_of(upn, h + 1);

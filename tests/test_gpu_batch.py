@@ -316,3 +316,10 @@ def test_batch_graph_kernel_timing(torch_cuda):
     finally:
         b.close()
     torch.cuda.synchronize()
+
+
+def test_batch_t_on_texture(torch_cuda):
+    # the Section 3.1 text reading in the batched frame step (row workers)
+    seqs = synth.mixed_streams(seed=28, frames=4, counts=(1, 2, 1))
+    st = Streams(seqs, 3)
+    run_batch(st, me.me_default_params(search_range=16, flags=me.ME_FLAG_T_TEXTURE), label="t-texture")

@@ -134,6 +134,24 @@ def test_pa_unrestricted(torch_cuda, mode):
         check_pa(seq, [0, None], p, 5, one_call=mode == "chained", label=f"unrestricted {mode}")
 
 
+# the Section 3.1 text reading (a boundary MB's T scored on texture): the
+# chained launch (one-wave line workers), one call per pair (row workers, and
+# line workers forced), with unrestricted vectors, half-pel at S=32
+@pytest.mark.parametrize("mode", ["chained", "rows", "lines", "unrestricted", "hd-halfpel"])
+def test_pa_t_on_texture(torch_cuda, mode):
+    T = me.ME_FLAG_T_TEXTURE
+    if mode == "hd-halfpel":
+        seq = synth.hd_streams(frames=3, streams=1)[0]
+        check_pa(seq, [0, 1, 2], me.me_default_params(search_range=32, half_pel=1, flags=T), 2, one_call=False,
+                 label="t-texture hd")
+        return
+    seq = synth.cif_two_vops(frames=6)
+    flags = T | (me.ME_FLAG_LINE_WORKERS if mode == "lines" else 0) | \
+        (me.ME_FLAG_UNRESTRICTED if mode == "unrestricted" else 0)
+    check_pa(seq, [0, 1], me.me_default_params(search_range=16, flags=flags), 5, one_call=mode == "chained",
+             label=f"t-texture {mode}")
+
+
 # the Section 4 protocol: reference frame two back, T from the previous pair
 @pytest.mark.parametrize("one_call", [True, False])
 @pytest.mark.parametrize("flags", [0, me.ME_FLAG_UNRESTRICTED])
