@@ -49,6 +49,8 @@ extern "C" {
 #define ME_EEMPTY (-5)   /* PSNR over zero pixels */
 #define ME_EDEVICE (-6)  /* device status word set (dependency wait timed out / bad class) */
 #define ME_ENODEV (-7)   /* no usable gfx950 device */
+#define ME_EFORMAT (-8)  /* network checkpoint malformed (size, magic, version, checksum, values) */
+#define ME_EIO (-9)      /* network checkpoint file could not be opened, read or written */
 
 /* MB classes (Section 1) */
 #define ME_MB_TRANSPARENT 0 /* no pixel of the VOP */
@@ -125,38 +127,59 @@ void me_default_params(me_params *p);
  * Learned motion-vector proposal network (an addition to the paper's
  * method: it seeds the pel-recursive search of Section 3.2 for opaque MBs;
  * the block-recursive result stays the fallback, see me_job.seed).
- * Per MB: input 2 x 24 x 24 (the current MB and the frame-clamped
- * reference window [-16, 32) around it, both box-averaged 2x2, a 2x2 sum s
- * as (s - 512) / 512 in bfloat16); conv 3x3 2->32 stride 1 + ReLU; conv 3x3
- * 32->32 stride 2 + ReLU; conv 3x3 32->2 stride 2; mean over the 6 x 6
- * positions = predicted full-pel vector p; seed = 2 * clamp(rint(p), -16, 16)
- * (half-pel).  bfloat16 weights and activations, fp32 accumulation.
- * Parameters (ME_NET_PARAMS floats): W1 (32,3,3,2) | b1 (32) | W2 (32,3,3,32)
- * | b2 (32) | W3 (2,3,3,32) | b3 (2), weights laid out [out][ky][kx][in].
- * The MBs served are the opaque ones (every MB of a job whose mb_class is NULL).
+ * Per MB, at window scale f (2 or 4): input 2 x 24 x 24 (the current MB and
+ * the frame-clamped reference window [-(12f-8), 12f+8) around it - 24f
+ * pixels, [-16, 32) at f = 2 - both box-averaged f x f, an f x f sum s as
+ * (s - 128 f^2) / (128 f^2) in bfloat16); conv 3x3 2->32 stride 1 + ReLU;
+ * conv 3x3 32->32 stride 2 + ReLU; conv 3x3 32->2 stride 2; mean over the
+ * 6 x 6 positions = predicted full-pel vector p; seed = 2 * clamp(rint(p),
+ * -w, w) half-pel with w = 12f - 8.  bfloat16 weights and activations, fp32
+ * accumulation.  Parameters (ME_NET_PARAMS floats): W1 (32,3,3,2) | b1 (32)
+ * | W2 (32,3,3,32) | b2 (32) | W3 (2,3,3,32) | b3 (2), weights laid out
+ * [out][ky][kx][in].  The MBs served are the opaque ones (every MB of a job
+ * whose mb_class is NULL).
  *
  * me_net_create: fp32 master weights from the host array `init` on the
- *   current device (momentum zero).  *out = handle (NULL on error).
+ *   current device (momentum zero), window scale `scale` (2 or 4;
+ *   ME_EINVAL otherwise).  *out = handle (NULL on error).
  * me_net_forward: for every served MB, writes the seed into job.seed (if
  *   set) and p (2 floats at 2*k) into pred[i] (host array of n device
  *   pointers, itself nullable, entries nullable).  Only cur/ref/mb_class/seed
  *   of the jobs are read.  Asynchronous on `stream`.
- * me_net_train_step: one momentum-SGD step on the served MBs of `jobs`,
- *   labels[i] = device field of full-pel vectors in half-pel units (the plain
- *   method's mv_int).  Loss = sum |p - label/2|^2 / (2 B) over the B served
- *   MBs; v = momentum * v + g; w = w - lr * v (0 <= momentum < 1, lr >= 0).
- *   grad (device, ME_NET_PARAMS floats, nullable) receives g; loss (host,
- *   nullable) the loss before the step - then the call blocks.  The gradient
- *   sum is deterministic for a given device and job set.
+ * me_net_backward: the gradient g of the loss over the served MBs of
+ *   `jobs`, labels[i] = device field of full-pel vectors in half-pel units
+ *   (the plain method's mv_int): loss = sum |p - label/2|^2 / (2 B) over the
+ *   B served MBs.  grad (device, ME_NET_PARAMS floats, required) receives g;
+ *   loss (host, nullable) the loss - then the call blocks.  The weights are
+ *   not changed.  The gradient sum is deterministic for a given device and
+ *   job set.
+ * me_net_sgd_step: one momentum-SGD step from the gradient `grad` (device):
+ *   v = momentum * v + grad; w = w - lr * v (0 <= momentum < 1, lr >= 0).
+ * me_net_train_step: me_net_backward then me_net_sgd_step in one call
+ *   (grad nullable here: receives g when set).
  * me_net_weights: blocking copy of the master weights (and momentum, nullable).
+ * me_net_scale: the window scale (ME_EINVAL for NULL).
+ * me_net_save: blocking; writes a checkpoint to `path`: 8-byte magic
+ *   "ME-NET\0\0", u32 version 1, u32 ME_NET_PARAMS, u32 window scale, u32 0,
+ *   the fp32 weights, the fp32 momentum, and the 64-bit FNV-1a hash of every
+ *   preceding byte (little-endian).  ME_EIO when the file cannot be written.
+ * me_net_load: creates a network on the current device from a checkpoint;
+ *   ME_EIO when the file cannot be read, ME_EFORMAT when its size, magic,
+ *   version, parameter count, hash, scale or values are wrong.
  * me_net_destroy: waits for the device and frees (NULL is a no-op).
  */
 #define ME_NET_PARAMS 10434
-int me_net_create(const float *init, me_net **out);
+int me_net_create(const float *init, int32_t scale, me_net **out);
 int me_net_forward(me_net *net, const me_job *jobs, int n, float *const *pred, void *stream);
+int me_net_backward(me_net *net, const me_job *jobs, int n, const me_mv *const *labels, float *grad, double *loss,
+                    void *stream);
+int me_net_sgd_step(me_net *net, const float *grad, float lr, float momentum, void *stream);
 int me_net_train_step(me_net *net, const me_job *jobs, int n, const me_mv *const *labels, float lr, float momentum,
                       float *grad, double *loss, void *stream);
 int me_net_weights(me_net *net, float *weights, float *momentum);
+int me_net_scale(const me_net *net);
+int me_net_save(me_net *net, const char *path);
+int me_net_load(const char *path, me_net **out);
 void me_net_destroy(me_net *net);
 
 /* Human-readable text of a status code (static storage). */

@@ -6,16 +6,18 @@ The paper has no network: the proposal that seeds its pel-recursive search
 (Section 3.2 starts from the block-recursive winner) is an addition of this
 project.  What it computes, per 16x16 macroblock (MB) at (x0, y0):
 
-  input   2 x 24 x 24: channel 0 = the current MB box-averaged 2x2 (8 x 8),
-          centred in a zero 24 x 24 canvas; channel 1 = the reference window
-          of rows/columns [-16, 32) around the MB (frame-clamped), box-
-          averaged 2x2.  A 2x2 sum s maps to (s - 512) / 512.
+  input   2 x 24 x 24, for a window scale f (2 or 4): channel 0 = the
+          current MB box-averaged f x f ((16/f) x (16/f)), centred in a zero
+          24 x 24 canvas; channel 1 = the reference window of rows/columns
+          [-(12f - 8), 12f + 8) around the MB (24f pixels, frame-clamped),
+          box-averaged f x f.  An f x f sum s maps to (s - 128 f^2) / (128 f^2).
+          f = 2 is the window [-16, 32) with (s - 512) / 512.
   conv1   3x3, 2 -> 32 channels, stride 1, zero padding 1, ReLU   (24 x 24)
   conv2   3x3, 32 -> 32, stride 2, padding 1, ReLU                (12 x 12)
   conv3   3x3, 32 -> 2, stride 2, padding 1                       (6 x 6)
   output  p = the mean of conv3 over its 36 positions: the predicted
-          full-pel vector (x, y); the seed is 2 * clip(rint(p), -16, 16) in
-          half-pel units.
+          full-pel vector (x, y); the seed is 2 * clip(rint(p), -w, w) in
+          half-pel units, w = 12f - 8 the window's half-width (16 at f = 2).
   loss    sum over a batch of B MBs of |p - y|^2 / (2B), y = the plain
           method's full-pel vector (labels).
   update  momentum SGD on float32 master weights: v <- mu v + g, w <- w - lr v.
@@ -39,7 +41,12 @@ import numpy as np
 SHAPES = (("W1", (32, 3, 3, 2)), ("b1", (32,)), ("W2", (32, 3, 3, 32)), ("b2", (32,)),
           ("W3", (2, 3, 3, 32)), ("b3", (2,)))
 NPARAM = sum(int(np.prod(s)) for _, s in SHAPES)
-WINDOW = 16  # reference window half-width in full pels
+WINDOW = 16  # reference window half-width in full pels at window scale 2
+
+
+def half_width(scale: int) -> int:
+    """Reference window half-width (full pels) at window scale f: 12 f - 8."""
+    return 12 * scale - 8
 
 
 def unpack(P: np.ndarray) -> dict:
@@ -68,18 +75,19 @@ def _r(x, rnd):
     return bf16(x) if rnd else np.asarray(x, dtype=np.float64)
 
 
-def prep(cur: np.ndarray, ref: np.ndarray, x0: int, y0: int, rnd=True) -> np.ndarray:
-    """Network input (24, 24, 2) of the MB at (x0, y0)."""
+def prep(cur: np.ndarray, ref: np.ndarray, x0: int, y0: int, rnd=True, scale: int = 2) -> np.ndarray:
+    """Network input (24, 24, 2) of the MB at (x0, y0) at window scale f."""
+    f = scale
     H, W = cur.shape
+    n, hw, norm = 16 // f, half_width(f), 128 * f * f
+    o = (24 - n) // 2
     x = np.zeros((24, 24, 2))
     c = cur[y0:y0 + 16, x0:x0 + 16].astype(np.int64)
-    s = c[0::2, 0::2] + c[1::2, 0::2] + c[0::2, 1::2] + c[1::2, 1::2]
-    x[8:16, 8:16, 0] = (s - 512) / 512.0
-    ys = np.clip(np.arange(y0 - WINDOW, y0 + 16 + WINDOW), 0, H - 1)
-    xs = np.clip(np.arange(x0 - WINDOW, x0 + 16 + WINDOW), 0, W - 1)
+    x[o:o + n, o:o + n, 0] = (c.reshape(n, f, n, f).sum(axis=(1, 3)) - norm) / float(norm)
+    ys = np.clip(np.arange(y0 - hw, y0 + 16 + hw), 0, H - 1)
+    xs = np.clip(np.arange(x0 - hw, x0 + 16 + hw), 0, W - 1)
     w = ref[np.ix_(ys, xs)].astype(np.int64)
-    s = w[0::2, 0::2] + w[1::2, 0::2] + w[0::2, 1::2] + w[1::2, 1::2]
-    x[:, :, 1] = (s - 512) / 512.0
+    x[:, :, 1] = (w.reshape(24, f, 24, f).sum(axis=(1, 3)) - norm) / float(norm)
     return _r(x, rnd)
 
 
@@ -177,9 +185,11 @@ def sgd(P, V, g, lr, mu):
     return np.asarray(P, dtype=np.float64) - lr * V2, V2
 
 
-def seed_of(p) -> np.ndarray:
-    """Half-pel seed of predictions p (..., 2): 2 * clip(rint(p), -16, 16)."""
-    return (2 * np.clip(np.rint(np.asarray(p, dtype=np.float64)), -WINDOW, WINDOW)).astype(np.int16)
+def seed_of(p, scale: int = 2) -> np.ndarray:
+    """Half-pel seed of predictions p (..., 2): 2 * clip(rint(p), -w, w),
+    w the window half-width at scale f (16 at f = 2)."""
+    w = half_width(scale)
+    return (2 * np.clip(np.rint(np.asarray(p, dtype=np.float64)), -w, w)).astype(np.int16)
 
 
 def opaque_mbs(cls):

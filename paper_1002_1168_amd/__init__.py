@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libme.so")
 
 ME_OK, ME_EINVAL, ME_EALIGN, ME_EHIP, ME_ENOMEM, ME_EEMPTY, ME_EDEVICE, ME_ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
+ME_EFORMAT, ME_EIO = -8, -9
 ME_MB_TRANSPARENT, ME_MB_OPAQUE, ME_MB_BOUNDARY = 0, 1, 2
 ME_ES, ME_TSS, ME_DS, ME_4SS = 0, 1, 2, 3
 ME_KT_CLASSIFY, ME_KT_SEARCH, ME_KT_FULL, ME_KT_MC, ME_KT_NET, ME_KT_NET_TRAIN, ME_KT_REFINE8 = 0, 1, 2, 3, 4, 5, 6
@@ -26,8 +27,9 @@ EXPORTED = ("me_default_params", "me_status_str", "me_shutdown", "me_classify_ba
             "me_shape_search", "me_full_search", "me_motion_compensate_psnr", "me_motion_compensate_sse",
             "me_motion_compensate_sse_noalloc", "me_refine_8x8", "me_motion_compensate4_sse", "me_device_status",
             "me_kernel_timing", "me_kernel_time_ms", "me_batch_create", "me_batch_step", "me_batch_results",
-            "me_batch_config", "me_batch_set_config", "me_batch_kernel_time_ms", "me_batch_set_net", "me_batch_destroy", "me_net_create", "me_net_forward", "me_net_train_step",
-            "me_net_weights", "me_net_destroy", "me_search_schedule")
+            "me_batch_config", "me_batch_set_config", "me_batch_kernel_time_ms", "me_batch_set_net", "me_batch_destroy", "me_net_create", "me_net_forward", "me_net_backward",
+            "me_net_sgd_step", "me_net_train_step", "me_net_weights", "me_net_scale", "me_net_save", "me_net_load",
+            "me_net_destroy", "me_search_schedule")
 
 
 class MeError(RuntimeError):
@@ -113,8 +115,18 @@ def lib():
         L.me_batch_set_net.restype = i
         L.me_batch_destroy.argtypes = [vp]
         L.me_batch_destroy.restype = None
-        L.me_net_create.argtypes = [C.POINTER(C.c_float), C.POINTER(vp)]
+        L.me_net_create.argtypes = [C.POINTER(C.c_float), C.c_int32, C.POINTER(vp)]
         L.me_net_create.restype = i
+        L.me_net_backward.argtypes = [vp, C.POINTER(me_job), i, C.POINTER(vp), vp, C.POINTER(C.c_double), vp]
+        L.me_net_backward.restype = i
+        L.me_net_sgd_step.argtypes = [vp, vp, C.c_float, C.c_float, vp]
+        L.me_net_sgd_step.restype = i
+        L.me_net_scale.argtypes = [vp]
+        L.me_net_scale.restype = i
+        L.me_net_save.argtypes = [vp, C.c_char_p]
+        L.me_net_save.restype = i
+        L.me_net_load.argtypes = [C.c_char_p, C.POINTER(vp)]
+        L.me_net_load.restype = i
         L.me_net_forward.argtypes = [vp, C.POINTER(me_job), i, C.POINTER(vp), vp]
         L.me_net_forward.restype = i
         L.me_net_train_step.argtypes = [vp, C.POINTER(me_job), i, C.POINTER(vp), C.c_float, C.c_float, vp,
@@ -333,16 +345,47 @@ class Batch:
 
 
 class Net:
-    """The learned motion-vector proposal network (``me_net_*``)."""
+    """The learned motion-vector proposal network (``me_net_*``); ``scale``:
+    window scale 2 (reference window [-16, 32)) or 4 ([-40, 56))."""
 
-    def __init__(self, init):
+    def __init__(self, init, scale: int = 2):
         import numpy as np
         w = np.ascontiguousarray(init, dtype=np.float32)
         if w.shape != (ME_NET_PARAMS,):
             raise MeError(ME_EINVAL, "Net: init must hold ME_NET_PARAMS floats")
         h = C.c_void_p()
-        _check(lib().me_net_create(w.ctypes.data_as(C.POINTER(C.c_float)), C.byref(h)), "me_net_create")
+        _check(lib().me_net_create(w.ctypes.data_as(C.POINTER(C.c_float)), int(scale), C.byref(h)), "me_net_create")
         self.handle = h
+
+    @classmethod
+    def load(cls, path: str) -> "Net":
+        """A network from a checkpoint written by save() (me_net_load)."""
+        h = C.c_void_p()
+        _check(lib().me_net_load(os.fsencode(path), C.byref(h)), f"me_net_load {path}")
+        obj = cls.__new__(cls)
+        obj.handle = h
+        return obj
+
+    def save(self, path: str) -> None:
+        _check(lib().me_net_save(self.handle, os.fsencode(path)), f"me_net_save {path}")
+
+    @property
+    def scale(self) -> int:
+        return int(lib().me_net_scale(self.handle))
+
+    def backward(self, jobs, labels, grad, want_loss=True, stream=None):
+        """Gradient into ``grad`` (device address of ME_NET_PARAMS floats);
+        -> loss (None unless want_loss).  The weights are unchanged."""
+        ja, n = _arr(me_job, jobs)
+        la, _ = _arr(C.c_void_p, labels)
+        loss = C.c_double()
+        _check(lib().me_net_backward(self.handle, ja, n, la, grad, C.byref(loss) if want_loss else None, stream),
+               "me_net_backward")
+        return float(loss.value) if want_loss else None
+
+    def sgd_step(self, grad, lr: float, momentum: float, stream=None) -> None:
+        """Momentum SGD from the gradient at device address ``grad``."""
+        _check(lib().me_net_sgd_step(self.handle, grad, float(lr), float(momentum), stream), "me_net_sgd_step")
 
     def forward(self, jobs, pred=None, stream=None, check=True) -> int:
         """Seeds into the jobs' seed buffers; ``pred``: per-job device

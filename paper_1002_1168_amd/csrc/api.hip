@@ -314,6 +314,8 @@ const char *me_status_str(int s) {
         case ME_EEMPTY: return "PSNR over zero pixels";
         case ME_EDEVICE: return "device status word set";
         case ME_ENODEV: return "no gfx950 device";
+        case ME_EFORMAT: return "network checkpoint malformed";
+        case ME_EIO: return "network checkpoint file not readable or writable";
         default: return "unknown status";
     }
 }

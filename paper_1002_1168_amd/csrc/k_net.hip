@@ -3,14 +3,16 @@
 // (the paper's recursion starts from the block-recursive winner, Section
 // 3.2; the learned start and its 5 % fallback are additions of this
 // library).  Per MB:
-//   input   24x24x2: the current MB box-averaged 2x2 (8x8, centred in a zero
-//           canvas) and the frame-clamped reference window [-16, 32) box-
-//           averaged 2x2; a 2x2 sum s maps to (s - 512) / 512 in bfloat16
+//   input   24x24x2 at window scale f (2 or 4): the current MB box-averaged
+//           f x f ((16/f)^2, centred in a zero canvas) and the frame-clamped
+//           reference window [-(12f-8), 12f+8) box-averaged f x f; an f x f
+//           sum s maps to (s - 128 f^2) / (128 f^2) in bfloat16 (f = 2: the
+//           window [-16, 32), (s - 512) / 512)
 //   conv1   3x3, 2 -> 32, stride 1, pad 1, ReLU   -> 24x24x32 (bf16)
 //   conv2   3x3, 32 -> 32, stride 2, pad 1, ReLU  -> 12x12x32 (bf16)
 //   conv3   3x3, 32 -> 2, stride 2, pad 1         -> 6x6x2 (fp32)
 //   p       mean of conv3 over its 36 positions: the predicted full-pel
-//           vector; seed = 2 * clamp(rint(p), -16, 16) half-pel
+//           vector; seed = 2 * clamp(rint(p), -w, w) half-pel, w = 12f - 8
 // One workgroup (4 waves) takes one MB at a time and keeps every activation
 // in LDS (NHWC, channels innermost).  The convolutions and the two large
 // gradient products are implicit GEMMs on v_mfma_f32_16x16x32_bf16 (bf16
@@ -90,8 +92,8 @@ static_assert(sizeof(NetLds) % 16 == 0 && sizeof(NetLdsTrain) % 16 == 0, "LDS la
 // positions per thread) and summed into LDS later (`write_input`), so the
 // next MB's loads can fly while the current MB is computed.
 struct InPix {
-    uint32_t r[3][4];  // the 2x2 reference pixels of each position
-    uint32_t c[3][2];  // the current pixel pairs of the two rows (centre positions only)
+    uint32_t r[3][4];  // scale 2: the 2x2 reference pixels of each position; scale 4: its four 4-byte rows
+    uint32_t c[3][4];  // the current pixels of the position's rows (centre positions only)
 };
 
 // The fields of a job the network reads, as wave-uniform values (frame
@@ -121,8 +123,33 @@ __device__ __forceinline__ InJob in_job(const JobDesc *J) {
     return j;
 }
 
-__device__ __forceinline__ void issue_input(InPix &v, const InJob &J, int x0, int y0) {
+// Window scale f (2 or 4): canvas position (y, x) averages the f x f reference
+// pixels at rows/columns 12f - 8 before the MB plus f (y, x); the current MB
+// covers the centre (16/f)^2 positions.
+__device__ __forceinline__ void issue_input(InPix &v, const InJob &J, int x0, int y0, int scale) {
     const int W = J.W, H = J.H, st = J.st;
+    if (scale == 4) {
+#pragma unroll
+        for (int sl = 0; sl < 3; ++sl) {
+            const int q = threadIdx.x + kThreads * sl;
+            const int y = q / 24, x = q - (q / 24) * 24;
+            const bool in = q < 576;
+            // clamped coordinates: every address is in the frame
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                v.r[sl][r] = in ? ld4_clamped(J.ref + (size_t)iclamp(y0 - 40 + 4 * y + r, 0, H - 1) * st,
+                                              x0 - 40 + 4 * x, W)
+                                : 0u;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v.c[sl][r] = 0u;
+            if (in && y >= 10 && y < 14 && x >= 10 && x < 14) {
+                const uint8_t *c = J.cur + (size_t)(y0 + 4 * (y - 10)) * st + x0 + 4 * (x - 10);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v.c[sl][r] = ldg32((const uint32_t *)(c + (size_t)r * st));
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int sl = 0; sl < 3; ++sl) {
         const int q = threadIdx.x + kThreads * sl;
@@ -135,7 +162,7 @@ __device__ __forceinline__ void issue_input(InPix &v, const InJob &J, int x0, in
         v.r[sl][1] = in ? ldg8(J.ref + (size_t)ya * st + xb) : 0u;
         v.r[sl][2] = in ? ldg8(J.ref + (size_t)yb * st + xa) : 0u;
         v.r[sl][3] = in ? ldg8(J.ref + (size_t)yb * st + xb) : 0u;
-        v.c[sl][0] = v.c[sl][1] = 0u;
+        v.c[sl][0] = v.c[sl][1] = v.c[sl][2] = v.c[sl][3] = 0u;
         if (in && y >= 8 && y < 16 && x >= 8 && x < 16) {
             const uint8_t *c = J.cur + (size_t)(y0 + 2 * (y - 8)) * st + x0 + 2 * (x - 8);
             v.c[sl][0] = *(const __attribute__((address_space(1))) uint16_t *)c;
@@ -144,28 +171,38 @@ __device__ __forceinline__ void issue_input(InPix &v, const InJob &J, int x0, in
     }
 }
 
-__device__ __forceinline__ void write_input(uint16_t *x0s, const InPix &v) {
+__device__ __forceinline__ void write_input(uint16_t *x0s, const InPix &v, int scale) {
+    // an f x f sum s maps to (s - 128 f^2) / (128 f^2): exact in fp32, then bf16
+    const int norm = scale == 4 ? 2048 : 512;
+    const float inv = scale == 4 ? 1.0f / 2048.0f : 1.0f / 512.0f;
+    const int lo = scale == 4 ? 10 : 8, hi = scale == 4 ? 14 : 16;
 #pragma unroll
     for (int sl = 0; sl < 3; ++sl) {
         const int q = threadIdx.x + kThreads * sl;
         if (q >= 576) continue;
         const int y = q / 24, x = q - (q / 24) * 24;
-        const int s = (int)(v.r[sl][0] + v.r[sl][1] + v.r[sl][2] + v.r[sl][3]);
-        uint32_t c0 = 0;
-        if (y >= 8 && y < 16 && x >= 8 && x < 16) {
-            const int sc = (int)((v.c[sl][0] & 0xFFu) + (v.c[sl][0] >> 8) + (v.c[sl][1] & 0xFFu) + (v.c[sl][1] >> 8));
-            c0 = bf16_bits((float)(sc - 512) * (1.0f / 512.0f));
+        int s = 0, sc = 0;
+        if (scale == 4) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                s += (int)__builtin_amdgcn_sad_u8(v.r[sl][r], 0u, 0u);  // byte sum
+                sc += (int)__builtin_amdgcn_sad_u8(v.c[sl][r], 0u, 0u);
+            }
+        } else {
+            s = (int)(v.r[sl][0] + v.r[sl][1] + v.r[sl][2] + v.r[sl][3]);
+            sc = (int)((v.c[sl][0] & 0xFFu) + (v.c[sl][0] >> 8) + (v.c[sl][1] & 0xFFu) + (v.c[sl][1] >> 8));
         }
+        uint32_t c0 = 0;
+        if (y >= lo && y < hi && x >= lo && x < hi) c0 = bf16_bits((float)(sc - norm) * inv);
         x0s[2 * q] = (uint16_t)c0;
-        x0s[2 * q + 1] = (uint16_t)bf16_bits((float)(s - 512) * (1.0f / 512.0f));
+        x0s[2 * q + 1] = (uint16_t)bf16_bits((float)(s - norm) * inv);
     }
     // every register consumed on every path (lanes past the input included), so
     // no load into them is left in flight for the next MB's loads to wait on
 #pragma unroll
     for (int sl = 0; sl < 3; ++sl) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) asm volatile("" ::"v"(v.r[sl][t]));
-        asm volatile("" ::"v"(v.c[sl][0]), "v"(v.c[sl][1]));
+        for (int t = 0; t < 4; ++t) asm volatile("" ::"v"(v.r[sl][t]), "v"(v.c[sl][t]));
     }
 }
 
@@ -317,6 +354,7 @@ struct NetArgs {
     const float *P;         // fp32 master parameters
     const uint16_t *wb;     // bf16 copies: W1 | W2 | W2 transposed | W3
     float *part;            // training: per-workgroup gradient partials (kNetParams + 1 floats each)
+    int scale;              // window scale f (2 or 4)
 };
 
 // inference: three workgroups per CU (their LDS fits), so at most 168 VGPRs
@@ -360,8 +398,8 @@ __global__ __launch_bounds__(kThreads, TRAIN ? 1 : 3) void net_kernel(NetArgs a)
     InJob ic{};
     bool vc = (int)blockIdx.x < count && decode(blockIdx.x, Jc, kc, ic);
     if (vc) {
-        issue_input(pix, ic, 16 * (kc % ic.wm), 16 * (kc / ic.wm));
-        write_input(F.x0, pix);
+        issue_input(pix, ic, 16 * (kc % ic.wm), 16 * (kc / ic.wm), a.scale);
+        write_input(F.x0, pix, a.scale);
     }
     for (int e = blockIdx.x; e < count; e += gridDim.x) {
         const int en = e + gridDim.x;
@@ -370,7 +408,7 @@ __global__ __launch_bounds__(kThreads, TRAIN ? 1 : 3) void net_kernel(NetArgs a)
         InJob in{};
         const bool vn = en < count && decode(en, Jn, kn, in);
         __syncthreads();  // MB e's input is in LDS
-        if (vn) issue_input(pix, in, 16 * (kn % in.wm), 16 * (kn / in.wm));
+        if (vn) issue_input(pix, in, 16 * (kn % in.wm), 16 * (kn / in.wm), a.scale);
         if (vc) {
             const JobDesc &J = *Jc;
             const int k = kc;
@@ -379,7 +417,8 @@ __global__ __launch_bounds__(kThreads, TRAIN ? 1 : 3) void net_kernel(NetArgs a)
             if constexpr (!TRAIN) {
                 if (threadIdx.x == 0) {
                     if (J.seed) {
-                        const int sx = 2 * iclamp((int)rintf(p0), -16, 16), sy = 2 * iclamp((int)rintf(p1), -16, 16);
+                        const int hw = 12 * a.scale - 8;  // the window's half-width
+                        const int sx = 2 * iclamp((int)rintf(p0), -hw, hw), sy = 2 * iclamp((int)rintf(p1), -hw, hw);
                         *(__attribute__((address_space(1))) uint32_t *)((uint32_t *)J.seed + k) =
                             (uint32_t)(uint16_t)sx | ((uint32_t)(uint16_t)sy << 16);
                     }
@@ -504,7 +543,7 @@ __global__ __launch_bounds__(kThreads, TRAIN ? 1 : 3) void net_kernel(NetArgs a)
             }
         }
         __syncthreads();  // LDS is reused by the next MB
-        if (vn) write_input(F.x0, pix);
+        if (vn) write_input(F.x0, pix, a.scale);
         Jc = Jn;
         kc = kn;
         ic = in;
@@ -558,10 +597,11 @@ __global__ __launch_bounds__(kThreads, TRAIN ? 1 : 3) void net_kernel(NetArgs a)
     }
 }
 
-// Sum of the workgroup partials (fixed order), momentum SGD on the fp32
-// master copy, and the bf16 copies the forward pass reads.
+// Sum of the workgroup partials (fixed order) into the gradient (and the
+// loss); with `apply`, momentum SGD on the fp32 master copy and the bf16
+// copies the forward pass reads.
 __global__ __launch_bounds__(256) void net_sgd_kernel(float *P, float *V, uint16_t *wb, const float *part, int nparts,
-                                                      float lr, float mu, float *grad, double *loss) {
+                                                      float lr, float mu, float *grad, double *loss, int apply) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i > kNetParams) return;
     double s = 0.0;
@@ -572,7 +612,21 @@ __global__ __launch_bounds__(256) void net_sgd_kernel(float *P, float *V, uint16
     }
     const float gi = (float)s;
     if (grad) grad[i] = gi;
+    if (!apply) return;
     const float vi = mu * V[i] + gi;
+    const float wi = P[i] - lr * vi;
+    V[i] = vi;
+    P[i] = wi;
+    net_refresh_one(wi, wb, i);
+}
+
+// Momentum SGD from a given gradient g: v = mu v + g, w = w - lr v, and the
+// bf16 copies.
+__global__ __launch_bounds__(256) void net_apply_kernel(float *P, float *V, uint16_t *wb, const float *g, float lr,
+                                                        float mu) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= kNetParams) return;
+    const float vi = mu * V[i] + g[i];
     const float wi = P[i] - lr * vi;
     V[i] = vi;
     P[i] = wi;
@@ -648,9 +702,9 @@ hipError_t launch_net_list(const JobDesc *jobs, int n, int total_mbs, uint8_t *s
 }
 
 hipError_t launch_net(bool train, const JobDesc *jobs, int n, const uint32_t *list, const uint32_t *count,
-                      const float *P, const uint16_t *wb, float *part, int groups, hipStream_t s,
+                      const float *P, const uint16_t *wb, float *part, int groups, int scale, hipStream_t s,
                       const KernelTimer *t) {
-    NetArgs a{jobs, n, list, count, P, wb, part};
+    NetArgs a{jobs, n, list, count, P, wb, part, scale};
     static bool lds_attr = false;  // dynamic LDS above the default limit for the training kernel
     if (train && !lds_attr) {
         (void)hipFuncSetAttribute((const void *)net_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -668,9 +722,14 @@ hipError_t launch_net(bool train, const JobDesc *jobs, int n, const uint32_t *li
 }
 
 hipError_t launch_net_sgd(float *P, float *V, uint16_t *wb, const float *part, int nparts, float lr, float mu,
-                          float *grad, double *loss, hipStream_t s) {
+                          float *grad, double *loss, hipStream_t s, bool apply) {
     hipLaunchKernelGGL(net_sgd_kernel, dim3((kNetParams + 1 + 255) / 256), dim3(256), 0, s, P, V, wb, part, nparts, lr,
-                       mu, grad, loss);
+                       mu, grad, loss, apply ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_net_apply(float *P, float *V, uint16_t *wb, const float *g, float lr, float mu, hipStream_t s) {
+    hipLaunchKernelGGL(net_apply_kernel, dim3((kNetParams + 255) / 256), dim3(256), 0, s, P, V, wb, g, lr, mu);
     return hipGetLastError();
 }
 

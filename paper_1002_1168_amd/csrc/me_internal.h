@@ -135,10 +135,13 @@ hipError_t launch_net_list(const JobDesc *jobs, int n, int total_mbs, uint8_t *s
                            const uint32_t **count, hipStream_t s);
 // forward (seeds / predictions) or forward + backward into per-workgroup partials
 hipError_t launch_net(bool train, const JobDesc *jobs, int n, const uint32_t *list, const uint32_t *count,
-                      const float *P, const uint16_t *wb, float *part, int groups, hipStream_t s,
+                      const float *P, const uint16_t *wb, float *part, int groups, int scale, hipStream_t s,
                       const KernelTimer *t = nullptr);
+// sum of the partials into grad / loss (nullable); `apply`: momentum SGD too
 hipError_t launch_net_sgd(float *P, float *V, uint16_t *wb, const float *part, int nparts, float lr, float mu,
-                          float *grad, double *loss, hipStream_t s);
+                          float *grad, double *loss, hipStream_t s, bool apply = true);
+// momentum SGD from the gradient g (device)
+hipError_t launch_net_apply(float *P, float *V, uint16_t *wb, const float *g, float lr, float mu, hipStream_t s);
 hipError_t launch_net_refresh(const float *P, uint16_t *wb, hipStream_t s);
 
 }  // namespace me

@@ -1,10 +1,12 @@
 // C ABI of the learned motion-vector proposal network: creation from given
-// initial weights, inference (seeds for the pel-recursive start), one
-// momentum-SGD training step on labelled MBs, weight read-back.
+// initial weights, inference (seeds for the pel-recursive start), the
+// gradient on labelled MBs, a momentum-SGD step (separately or fused),
+// weight read-back, and checkpoints (versioned, checksummed files).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -27,6 +29,7 @@ struct me_net {
     int slot = 0;
     double *host_loss = nullptr;
     int cus = 256;
+    int scale = 2;  // window scale f: reference window [-(12f-8), 12f+8) box-averaged f x f
     std::mutex mu;
 };
 
@@ -154,7 +157,7 @@ hipError_t net_forward_table(me_net *net, const JobDesc *table, int n, int total
     hipError_t e = launch_net_list(table, n, total_mbs, scratch, &list, &count, s);
     if (e != hipSuccess) return e;
     const int groups = (int)std::min<long long>(total_mbs, (long long)net->cus * 3);
-    return launch_net(false, table, n, list, count, net->P, net->wb, nullptr, groups, s, t);
+    return launch_net(false, table, n, list, count, net->P, net->wb, nullptr, groups, net->scale, s, t);
 }
 
 }  // namespace host
@@ -162,18 +165,22 @@ hipError_t net_forward_table(me_net *net, const JobDesc *table, int n, int total
 
 extern "C" {
 
-int me_net_create(const float *init, me_net **out) {
+namespace {
+
+// Device net from host weights and (nullable) momentum.
+int create_net(const float *init, const float *mom, int32_t scale, me_net **out) {
     if (!out) return ME_EINVAL;
     *out = nullptr;
-    if (!init) return ME_EINVAL;
+    if (!init || (scale != 2 && scale != 4)) return ME_EINVAL;
     for (int i = 0; i < kNetParams; ++i)
-        if (!std::isfinite(init[i])) return ME_EINVAL;
+        if (!std::isfinite(init[i]) || (mom && !std::isfinite(mom[i]))) return ME_EINVAL;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || check_device(dev) != ME_OK) return ME_ENODEV;
     int rc = check_lds(dev, false);
     if (rc) return rc;
     me_net *m = new me_net();
     m->device = dev;
+    m->scale = scale;
     hipDeviceGetAttribute(&m->cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (m->cus <= 0) m->cus = 256;
     if (hipMalloc(&m->P, kNetParams * 4) != hipSuccess || hipMalloc(&m->V, kNetParams * 4) != hipSuccess ||
@@ -189,13 +196,74 @@ int me_net_create(const float *init, me_net **out) {
         }
     std::vector<float> zero(kNetParams, 0.f);
     if (hipMemcpy(m->P, init, kNetParams * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(m->V, zero.data(), kNetParams * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->V, mom ? mom : zero.data(), kNetParams * 4, hipMemcpyHostToDevice) != hipSuccess ||
         launch_net_refresh(m->P, m->wb, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         release(m);
         return ME_EHIP;
     }
     *out = m;
     return ME_OK;
+}
+
+// Checkpoint layout (little-endian): 8-byte magic, u32 version, u32 number
+// of parameters, u32 window scale, u32 reserved (0), the fp32 weights, the
+// fp32 momentum, then the 64-bit FNV-1a hash of every byte before it.
+constexpr char kMagic[8] = {'M', 'E', '-', 'N', 'E', 'T', '\0', '\0'};
+constexpr uint32_t kVersion = 1;
+constexpr size_t kHeader = 24;
+constexpr size_t kFileBytes = kHeader + 8 * (size_t)kNetParams + 8;
+
+uint64_t fnv1a64(const uint8_t *p, size_t n) {
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+}  // namespace
+
+int me_net_create(const float *init, int32_t scale, me_net **out) { return create_net(init, nullptr, scale, out); }
+
+int me_net_save(me_net *net, const char *path) {
+    if (!net || !path) return ME_EINVAL;
+    std::vector<uint8_t> buf(kFileBytes, 0);
+    std::memcpy(buf.data(), kMagic, 8);
+    const uint32_t hdr[4] = {kVersion, (uint32_t)kNetParams, (uint32_t)net->scale, 0u};
+    std::memcpy(buf.data() + 8, hdr, 16);
+    int rc = me_net_weights(net, (float *)(buf.data() + kHeader), (float *)(buf.data() + kHeader + 4 * kNetParams));
+    if (rc) return rc;
+    const uint64_t h = fnv1a64(buf.data(), kFileBytes - 8);
+    std::memcpy(buf.data() + kFileBytes - 8, &h, 8);
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return ME_EIO;
+    const bool ok = std::fwrite(buf.data(), 1, buf.size(), f) == buf.size();
+    const bool closed = std::fclose(f) == 0;
+    return ok && closed ? ME_OK : ME_EIO;
+}
+
+int me_net_load(const char *path, me_net **out) {
+    if (!out) return ME_EINVAL;
+    *out = nullptr;
+    if (!path) return ME_EINVAL;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return ME_EIO;
+    std::vector<uint8_t> buf(kFileBytes + 1);
+    const size_t got = std::fread(buf.data(), 1, buf.size(), f);
+    std::fclose(f);
+    if (got != kFileBytes) return ME_EFORMAT;  // truncated or trailing bytes
+    uint32_t hdr[4];
+    std::memcpy(hdr, buf.data() + 8, 16);
+    uint64_t h = 0;
+    std::memcpy(&h, buf.data() + kFileBytes - 8, 8);
+    if (std::memcmp(buf.data(), kMagic, 8) != 0 || hdr[0] != kVersion || hdr[1] != (uint32_t)kNetParams ||
+        hdr[3] != 0u || h != fnv1a64(buf.data(), kFileBytes - 8))
+        return ME_EFORMAT;
+    std::vector<float> w(2 * (size_t)kNetParams);
+    std::memcpy(w.data(), buf.data() + kHeader, 8 * (size_t)kNetParams);
+    const int rc = create_net(w.data(), w.data() + kNetParams, (int32_t)hdr[2], out);
+    return rc == ME_EINVAL ? ME_EFORMAT : rc;
 }
 
 void me_net_destroy(me_net *net) { release(net); }
@@ -228,11 +296,17 @@ int me_net_forward(me_net *net, const me_job *jobs, int n, float *const *pred, v
     const int groups = (int)std::min<long long>(total, (long long)net->cus * 3);
     KernelTimer kt;
     const bool timed = kernel_timer(stream, ME_KT_NET, &kt);
-    return hip_err(launch_net(false, tab, n, list, count, net->P, net->wb, nullptr, groups, s, timed ? &kt : nullptr));
+    return hip_err(launch_net(false, tab, n, list, count, net->P, net->wb, nullptr, groups, net->scale, s,
+                              timed ? &kt : nullptr));
 }
 
-int me_net_train_step(me_net *net, const me_job *jobs, int n, const me_mv *const *labels, float lr, float momentum,
-                      float *grad, double *loss, void *stream) {
+namespace {
+
+// Forward + backward on the served MBs of `jobs` into per-workgroup
+// partials, then their fixed-order sum into `grad` / `loss` (device), and,
+// with `apply`, momentum SGD.  The loss is read back when `loss_host` is set.
+int net_step(me_net *net, const me_job *jobs, int n, const me_mv *const *labels, float lr, float momentum,
+             bool apply, float *grad, double *loss_host, void *stream) {
     if (!net || !labels) return ME_EINVAL;
     if (!std::isfinite(lr) || lr < 0.f || !std::isfinite(momentum) || momentum < 0.f || momentum >= 1.f)
         return ME_EINVAL;
@@ -260,17 +334,42 @@ int me_net_train_step(me_net *net, const me_job *jobs, int n, const me_mv *const
     double *dloss = (double *)(net->buf + o_loss);
     KernelTimer kt;
     const bool timed = kernel_timer(stream, ME_KT_NET_TRAIN, &kt);
-    if (launch_net(true, tab, n, list, count, net->P, net->wb, part, groups, s, timed ? &kt : nullptr) != hipSuccess)
+    if (launch_net(true, tab, n, list, count, net->P, net->wb, part, groups, net->scale, s, timed ? &kt : nullptr) !=
+        hipSuccess)
         return ME_EHIP;
-    if (launch_net_sgd(net->P, net->V, net->wb, part, groups, lr, momentum, grad, dloss, s) != hipSuccess)
+    if (launch_net_sgd(net->P, net->V, net->wb, part, groups, lr, momentum, grad, dloss, s, apply) != hipSuccess)
         return ME_EHIP;
-    if (loss) {
+    if (loss_host) {
         if (hipMemcpyAsync(net->host_loss, dloss, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
             return ME_EHIP;
         if (hipStreamSynchronize(s) != hipSuccess) return ME_EHIP;
-        *loss = *net->host_loss;
+        *loss_host = *net->host_loss;
     }
     return ME_OK;
 }
+
+}  // namespace
+
+int me_net_train_step(me_net *net, const me_job *jobs, int n, const me_mv *const *labels, float lr, float momentum,
+                      float *grad, double *loss, void *stream) {
+    return net_step(net, jobs, n, labels, lr, momentum, true, grad, loss, stream);
+}
+
+int me_net_backward(me_net *net, const me_job *jobs, int n, const me_mv *const *labels, float *grad, double *loss,
+                    void *stream) {
+    if (!grad) return ME_EINVAL;
+    return net_step(net, jobs, n, labels, 0.f, 0.f, false, grad, loss, stream);
+}
+
+int me_net_sgd_step(me_net *net, const float *grad, float lr, float momentum, void *stream) {
+    if (!net || !grad) return ME_EINVAL;
+    if (!std::isfinite(lr) || lr < 0.f || !std::isfinite(momentum) || momentum < 0.f || momentum >= 1.f)
+        return ME_EINVAL;
+    if (!al4(grad)) return ME_EALIGN;
+    std::lock_guard<std::mutex> lk(net->mu);
+    return hip_err(launch_net_apply(net->P, net->V, net->wb, grad, lr, momentum, (hipStream_t)stream));
+}
+
+int me_net_scale(const me_net *net) { return net ? net->scale : ME_EINVAL; }
 
 }  // extern "C"

@@ -177,14 +177,35 @@ def test_net_argument_validation():
     L = me.lib()
     h = C.c_void_p(1)
     w = (C.c_float * me.ME_NET_PARAMS)()
-    assert L.me_net_create(w, None) == me.ME_EINVAL
-    assert L.me_net_create(None, C.byref(h)) == me.ME_EINVAL and h.value is None
+    assert L.me_net_create(w, 2, None) == me.ME_EINVAL
+    assert L.me_net_create(None, 2, C.byref(h)) == me.ME_EINVAL and h.value is None
+    assert L.me_net_create(w, 3, C.byref(h)) == me.ME_EINVAL and h.value is None   # scale 2 or 4 only
     w[5] = float("nan")
-    assert L.me_net_create(w, C.byref(h)) == me.ME_EINVAL
+    assert L.me_net_create(w, 2, C.byref(h)) == me.ME_EINVAL
     ja = (me.me_job * 1)(job())
     assert L.me_net_forward(None, ja, 1, None, None) == me.ME_EINVAL
     labels = (C.c_void_p * 1)(FAKE)
     assert L.me_net_train_step(None, ja, 1, labels, 0.1, 0.9, None, None, None) == me.ME_EINVAL
+    assert L.me_net_backward(None, ja, 1, labels, FAKE, None, None) == me.ME_EINVAL
+    assert L.me_net_sgd_step(None, FAKE, 0.1, 0.9, None) == me.ME_EINVAL
     s = (C.c_float * me.ME_NET_PARAMS)()
     assert L.me_net_weights(None, s, None) == me.ME_EINVAL
+    assert L.me_net_scale(None) == me.ME_EINVAL
+    assert L.me_net_save(None, b"/tmp/x") == me.ME_EINVAL
+    assert L.me_net_load(b"/tmp/x", None) == me.ME_EINVAL
     L.me_net_destroy(None)
+
+
+def test_net_checkpoint_errors_before_any_device_call(tmp_path):
+    # file checks run on the host before a network is created
+    L = me.lib()
+    h = C.c_void_p(1)
+    assert L.me_net_load(str(tmp_path / "missing.menet").encode(), C.byref(h)) == me.ME_EIO and h.value is None
+    bad = tmp_path / "short.menet"
+    bad.write_bytes(b"ME-NET\0\0" + b"\0" * 100)
+    assert L.me_net_load(str(bad).encode(), C.byref(h)) == me.ME_EFORMAT and h.value is None
+    n = 24 + 8 * me.ME_NET_PARAMS + 8
+    wrong = tmp_path / "magic.menet"
+    wrong.write_bytes(b"X" * n)
+    assert L.me_net_load(str(wrong).encode(), C.byref(h)) == me.ME_EFORMAT
+    assert "checkpoint" in me.status_str(me.ME_EFORMAT) and "file" in me.status_str(me.ME_EIO)

@@ -168,16 +168,19 @@ def test_batch_rejects_other_structure(torch_cuda):
         b.close()
 
 
-def test_batch_with_proposal_network(torch_cuda):
+@pytest.mark.parametrize("S,half,scale", [(16, 0, 2), (32, 1, 4)])
+def test_batch_with_proposal_network(torch_cuda, S, half, scale):
     """A network attached to the batch: every step's seeds and results equal
-    the eager network-seeded search, and the oracle's search fed those seeds."""
+    the eager network-seeded search, and the oracle's search fed those seeds
+    (S=16 with the default window; S=32 with half-sample refinement and the
+    scale-4 window, the setting of the 1920x1088 workload)."""
     import torch
     from paper_1002_1168_amd.device import Outputs, job, stream_handle
     seqs = synth.mixed_streams(seed=28, frames=4, counts=(1, 1, 1))
     st = Streams(seqs, 3)
-    p = me.me_default_params(search_range=16)
+    p = me.me_default_params(search_range=S, half_pel=half)
     w = synth.net_init(5)
-    w[-2:] = [0.7, -1.3]
+    w[-2:] = [0.7, -1.3] if scale == 2 else [19.6, -27.2]
     seeds = [torch.zeros((st.pairs, st.ds[si].hm, st.ds[si].wm, 2), dtype=torch.int16, device="cuda")
              for si, _ in st.units]
     eager_out = [Outputs.alloc(st.pairs, st.ds[si].hm, st.ds[si].wm) for si, _ in st.units]
@@ -190,7 +193,7 @@ def test_batch_with_proposal_network(torch_cuda):
         return js
 
     s = stream_handle()
-    net = me.Net(w)
+    net = me.Net(w, scale=scale)
     b = me.Batch(jobs(0, st.out, seeds), p, 0, stream=s)
     try:
         b.set_net(net)

@@ -60,6 +60,26 @@ def test_prep_box_average_and_edge_clamp():
         assert np.array_equal(net.prep(cur, ref, x0, y0), net.bf16(got))
 
 
+def test_prep_scale_four_box_average_and_edge_clamp():
+    # window scale 4: the 96-pixel window [-40, 56) in 4 x 4 means, the
+    # current MB as 4 x 4 means in the canvas centre [10, 14)
+    rng = np.random.default_rng(6)
+    H, W = 64, 80
+    cur = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    ref = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    for x0, y0 in [(0, 0), (64, 48), (32, 16)]:
+        got = net.prep(cur, ref, x0, y0, rnd=False, scale=4)
+        c = cur[y0:y0 + 16, x0:x0 + 16].astype(float).reshape(4, 4, 4, 4).mean(axis=(1, 3))
+        assert np.allclose(got[10:14, 10:14, 0], (c - 128) / 128)
+        mask = np.ones((24, 24), bool)
+        mask[10:14, 10:14] = False
+        assert not got[:, :, 0][mask].any()
+        padded = np.pad(ref.astype(float), 40, mode="edge")
+        win = padded[y0:y0 + 96, x0:x0 + 96].reshape(24, 4, 24, 4).mean(axis=(1, 3))
+        assert np.allclose(got[:, :, 1], (win - 128) / 128)
+    assert net.half_width(2) == 16 and net.half_width(4) == 40
+
+
 def test_finite_difference_gradient():
     """The analytic backward of the float64 network against central
     differences of the loss, on a sample of parameters of every tensor."""
@@ -102,6 +122,8 @@ def test_sgd_closed_form():
 def test_seed_rounding_and_clip():
     p = np.array([[0.5, 1.5], [-2.5, 2.4999], [17.2, -30.0]])
     assert net.seed_of(p).tolist() == [[0, 4], [-4, 4], [32, -32]]
+    p4 = np.array([[17.2, -30.0], [40.4, -41.0]])
+    assert net.seed_of(p4, scale=4).tolist() == [[34, -60], [80, -80]]
 
 
 def test_parameter_count():
