@@ -49,7 +49,7 @@ SAD_OPS = 64          # 256 absolute differences, 4 per v_sad_u8 lane-op
 PASS_OPS = 256 * 12   # gradient pass: e, gx, gy, two reciprocal lookups, two products, two counts, ...
 
 METRIC = "macroblocks/sec estimated at <=0.05 dB PSNR vs plain; mean iterations/MB"
-KIND_NAMES = {0: "classify_kernel", 1: "pa_kernel", 3: "mc_kernel", 4: "net_kernel"}
+KIND_NAMES = {0: "classify_kernel", 1: "search_kernel", 3: "mc_kernel", 4: "net_kernel"}
 
 
 def log(*a):
@@ -587,11 +587,18 @@ def main():
 
     hw = HDWorkload(hd_seqs)
     forms = {"plain": hd_form(hw, "plain", None, a.steps, a.warmup)}
-    w, wpath = net_weights("proposal_hd_s32.npy")
-    if w is None:
+    # the network trained on 1920x1088 streams (scale-4 window), else the CIF one
+    ck = os.path.join(ROOT, "paper_1002_1168_amd", "weights", "proposal_hd_s32.menet")
+    net = None
+    if os.path.exists(ck):
+        wpath = os.path.relpath(ck, ROOT)
+        if not a.no_learned:
+            net = me.Net.load(ck)
+    else:
         w, wpath = net_weights("proposal_cif_s16.npy")
-    if not a.no_learned and w is not None:
-        net = me.Net(w)
+        if not a.no_learned and w is not None:
+            net = me.Net(w)
+    if net is not None:
         forms["learned"] = hd_form(hw, "learned", net, a.steps, a.warmup)
         net.close()
         lf = forms["learned"]
@@ -603,10 +610,17 @@ def main():
     r = forms[best]
     r["frame_steps"] = hw.pairs
     kern = r["dominant_kernel"]
-    if kern == "pa_kernel":
-        roof = search_roofline(r, "pa_kernel<28>", measured_traffic(
-            "pa_kernel<28>", ("paper_1002_1168_amd/csrc/k_pa.hip", "paper_1002_1168_amd/csrc/me_internal.h"),
-            "profiles/pa_kernel_hd1920x1088_8streams_S32_halfpel.md"))
+    if kern == "search_kernel":
+        # the search kernel that ran: row workers (pr_kernel) or line workers
+        # (pa_kernel), with the window staging instantiated for S = 32 (28
+        # elements per lane) or the generic one (0)
+        cfg = r["launch_config"]
+        name = ("pr_kernel" if cfg["search"] == "rows" else "pa_kernel") + \
+            ("<28>" if cfg["staging"] == "plan" else "<0>")
+        summary = {"pr_kernel<28>": "profiles/pr_kernel_hd1920x1088_8streams_S32_halfpel.md",
+                   "pa_kernel<28>": "profiles/pa_kernel_hd1920x1088_8streams_S32_halfpel.md"}.get(name, "")
+        roof = search_roofline(r, name, measured_traffic(
+            name, ("paper_1002_1168_amd/csrc/k_pa.hip", "paper_1002_1168_amd/csrc/me_internal.h"), summary))
     else:
         roof = {"kernel": kern, "kernel_ms": r["dominant_kernel_ms"], "bound": None, "achieved": None,
                 "peak": None, "unit": None, "frac": None, "traffic": None}

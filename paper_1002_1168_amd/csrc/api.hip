@@ -486,9 +486,11 @@ int mc_enqueue(Workspace &w, const std::vector<JobDesc> &desc, long long total, 
     if (rc) return rc;
     unsigned long long *acc = sums ? sums : (unsigned long long *)sb;
     *acc_out = acc;
+    bool sums_only = true;
+    for (const JobDesc &d : desc) sums_only = sums_only && d.out_u8 == nullptr;
     KernelTimer kt;
     return hip_err(launch_mc((const JobDesc *)(base + o), n, (int)total, (uint32_t *)(sb + acc_bytes), acc,
-                             w.status, w.stream, timer_for(w, A_MC, &kt) ? &kt : nullptr));
+                             w.status, w.stream, timer_for(w, A_MC, &kt) ? &kt : nullptr, 8, false, sums_only));
 }
 
 }  // namespace

@@ -188,7 +188,8 @@ hipError_t launch_step(const me_batch &b, const int32_t *cfg, hipStream_t s, con
     }
     e = launch_search(b, u, cfg, s, T(ME_KT_SEARCH));
     if (e != hipSuccess) return e;
-    return launch_mc(u.jobs, b.n, b.plan.total_mbs, u.part, u.acc, u.status, s, T(ME_KT_MC), cfg[3]);
+    return launch_mc(u.jobs, b.n, b.plan.total_mbs, u.part, u.acc, u.status, s, T(ME_KT_MC), cfg[3], false,
+                     true);
 }
 
 // Read and clear the device status word (blocking); true when it was clear.
@@ -294,7 +295,8 @@ int autotune(me_batch &b) {
         float ms = time_min(b, e0, e1, [&] {
             hipError_t e = launch_classify(u.jobs, b.n, b.plan.total_mbs, b.stream, nullptr, pc);
             if (e != hipSuccess) return e;
-            return launch_mc(u.jobs, b.n, b.plan.total_mbs, u.part, u.acc, u.status, b.stream, nullptr, pc);
+            return launch_mc(u.jobs, b.n, b.plan.total_mbs, u.part, u.acc, u.status, b.stream, nullptr, pc, false,
+                             true);
         });
         bool clean = false;
         if (ms < 0.f || !status_clear(b, u, &clean)) {

@@ -209,65 +209,131 @@ __device__ __forceinline__ int row_sse(const u32x4 cur, const uint32_t (&p)[4], 
 // FOUR: the job's mv holds four vectors per MB (8 x 8 blocks in raster
 // order); lane t's rows belong to the top or bottom pair, its left 8 pixels
 // to the first block of the pair and its right 8 to the second.
+// One MB's prediction by eight lanes: lane t takes rows 2t and 2t+1 of the
+// current rows, the alpha mask and the prediction (by the MB's vector, or
+// per 8 x 8 column half by its two block vectors when FOUR), stores the
+// prediction when `store`, and returns its part of the MB's SSE and pixel
+// count (sum over the eight lanes for the MB's totals).
+template <bool FOUR>
+__device__ __forceinline__ void mc_mb(const JobCursor &c, int k, int cl, int t, bool store, int &sse, int &cnt) {
+    const uint8_t *cur = c.ptr<const uint8_t>(DWI(cur));
+    const uint8_t *ref = c.ptr<const uint8_t>(DWI(ref));
+    const uint8_t *alpha = c.ptr<const uint8_t>(DWI(cur_a));
+    const uint32_t *mv = c.ptr<const uint32_t>(DWI(mv));
+    uint8_t *out = c.ptr<uint8_t>(DWI(out_u8));
+    const int W = c.i32(DWI(width)), H = c.i32(DWI(height)), st = c.i32(DWI(stride)), wm = c.i32(DWI(wm));
+    const int h = k % wm, v = k / wm;
+    const int x = 16 * h, y = 16 * v + 2 * t;
+    const uint32_t w = FOUR ? ldg32(mv + 4 * k + 2 * (t >> 2)) : ldg32(mv + k);
+    const size_t o0 = (size_t)y * st + x, o1 = o0 + st;
+    const u32x4 c0 = ld16(cur + o0), c1 = ld16(cur + o1);
+    uint32_t in0 = 0xFFFFu, in1 = 0xFFFFu;
+    if (alpha) {
+        in0 = nz16v(ld16(alpha + o0));
+        in1 = nz16v(ld16(alpha + o1));
+    }
+    int hx = 0, hy = 0;
+    if (cl != ME_MB_TRANSPARENT) {
+        hx = (int)(int16_t)(w & 0xFFFF);
+        hy = (int)(int16_t)(w >> 16);
+    }
+    uint32_t p0[4], p1[4];
+    predict_rows2(ref, st, W, H, x, y, hx, hy, p0, p1);
+    if constexpr (FOUR) {
+        // the right 8 pixels by the pair's second block vector
+        const uint32_t w2 = ldg32(mv + 4 * k + 2 * (t >> 2) + 1);
+        int hx2 = 0, hy2 = 0;
+        if (cl != ME_MB_TRANSPARENT) {
+            hx2 = (int)(int16_t)(w2 & 0xFFFF);
+            hy2 = (int)(int16_t)(w2 >> 16);
+        }
+        uint32_t q0[4], q1[4];
+        predict_rows2(ref, st, W, H, x, y, hx2, hy2, q0, q1);
+        p0[2] = q0[2];
+        p0[3] = q0[3];
+        p1[2] = q1[2];
+        p1[3] = q1[3];
+    }
+    if (store && out) {
+        st16(out + o0, p0);
+        st16(out + o1, p1);
+    }
+    sse = row_sse(c0, p0, in0) + row_sse(c1, p1, in1);
+    cnt = __builtin_popcount(in0) + __builtin_popcount(in1);
+}
+
+// Section 4's prediction and squared error: every MB predicted by its
+// half-pel vector (transparent MBs by (0, 0)) from the reference frame,
+// written to out_u8 when set; per-MB SSE and pixel count over the mask to
+// part[2 mb], part[2 mb + 1] for the per-job reduction.  Eight lanes per MB.
 template <bool FOUR>
 __global__ __launch_bounds__(256) void mc_kernel(const JobDesc *jobs, int n, int total, int chunk, uint32_t *part,
                                                  uint32_t *status) {
     const int t = lane() & 7;
     for_units<8>(jobs, n, total, chunk, [&](const JobCursor &c, int k, int mb, bool on) {
-        const uint8_t *cur = c.ptr<const uint8_t>(DWI(cur));
-        const uint8_t *ref = c.ptr<const uint8_t>(DWI(ref));
-        const uint8_t *alpha = c.ptr<const uint8_t>(DWI(cur_a));
         const uint8_t *cls = c.ptr<const uint8_t>(DWI(cls));
         const uint32_t *mv = c.ptr<const uint32_t>(DWI(mv));
-        uint8_t *out = c.ptr<uint8_t>(DWI(out_u8));
-        const int W = c.i32(DWI(width)), H = c.i32(DWI(height)), st = c.i32(DWI(stride)), wm = c.i32(DWI(wm));
-        const int h = k % wm, v = k / wm;
-        const int x = 16 * h, y = 16 * v + 2 * t;
         // the class byte is read unconditionally (from the vector array when
         // there is no class array) so that it shares one round trip with the
         // vector and the current rows
         const uint32_t cb = ldg8(cls ? cls + k : (const uint8_t *)(mv + k));
         const int cl = cls ? (int)cb : ME_MB_OPAQUE;
         if (on && t == 0 && cl > ME_MB_BOUNDARY) atomicOr(status, ST_BAD_CLASS);
-        const uint32_t w = FOUR ? ldg32(mv + 4 * k + 2 * (t >> 2)) : ldg32(mv + k);
-        const size_t o0 = (size_t)y * st + x, o1 = o0 + st;
-        const u32x4 c0 = ld16(cur + o0), c1 = ld16(cur + o1);
-        uint32_t in0 = 0xFFFFu, in1 = 0xFFFFu;
-        if (alpha) {
-            in0 = nz16v(ld16(alpha + o0));
-            in1 = nz16v(ld16(alpha + o1));
-        }
-        int hx = 0, hy = 0;
-        if (cl != ME_MB_TRANSPARENT) {
-            hx = (int)(int16_t)(w & 0xFFFF);
-            hy = (int)(int16_t)(w >> 16);
-        }
-        uint32_t p0[4], p1[4];
-        predict_rows2(ref, st, W, H, x, y, hx, hy, p0, p1);
-        if constexpr (FOUR) {
-            // the right 8 pixels by the pair's second block vector
-            const uint32_t w2 = ldg32(mv + 4 * k + 2 * (t >> 2) + 1);
-            int hx2 = 0, hy2 = 0;
-            if (cl != ME_MB_TRANSPARENT) {
-                hx2 = (int)(int16_t)(w2 & 0xFFFF);
-                hy2 = (int)(int16_t)(w2 >> 16);
-            }
-            uint32_t q0[4], q1[4];
-            predict_rows2(ref, st, W, H, x, y, hx2, hy2, q0, q1);
-            p0[2] = q0[2];
-            p0[3] = q0[3];
-            p1[2] = q1[2];
-            p1[3] = q1[3];
-        }
-        if (on && out) {
-            st16(out + o0, p0);
-            st16(out + o1, p1);
-        }
-        const int sse = sum8(row_sse(c0, p0, in0) + row_sse(c1, p1, in1));
-        const int cnt = sum8(__builtin_popcount(in0) + __builtin_popcount(in1));
+        int sse, cnt;
+        mc_mb<FOUR>(c, k, cl, t, on, sse, cnt);
+        sse = sum8(sse);
+        cnt = sum8(cnt);
         if (on && t == 0) {
             st32(part + 2 * (size_t)mb, (uint32_t)sse);
             st32(part + 2 * (size_t)mb + 1, (uint32_t)cnt);
+        }
+    });
+}
+
+__device__ __forceinline__ void st64(uint32_t *p, unsigned long long v) {
+    *(__attribute__((address_space(1))) unsigned long long *)p = v;
+}
+
+// The same sums without a prediction frame.  A transparent MB has no pixel
+// with alpha != 0 (its class is the classification of the current alpha),
+// so its SSE and pixel count are zero whatever its prediction: such MBs cost
+// one class byte and a zero partial.  One lane per MB reads the classes of
+// 64 consecutive MBs; the others are compacted in LDS (wave-private) and
+// predicted eight lanes per MB as in mc_kernel.
+__global__ __launch_bounds__(256) void mc_sums_kernel(const JobDesc *jobs, int n, int total, int chunk,
+                                                      uint32_t *part, uint32_t *status) {
+    __shared__ int list_k[4][64], list_c[4][64];
+    int *lk = list_k[threadIdx.x >> 6], *lc = list_c[threadIdx.x >> 6];
+    const int t = lane() & 7, g = lane() >> 3;
+    for_units<1>(jobs, n, total, chunk, [&](const JobCursor &c, int k, int mb, bool on) {
+        const uint8_t *cls = c.ptr<const uint8_t>(DWI(cls));
+        int cl = ME_MB_OPAQUE;
+        if (cls && on) cl = (int)ldg8(cls + k);
+        if (on && cl > ME_MB_BOUNDARY) atomicOr(status, ST_BAD_CLASS);
+        const bool act = on && cl != ME_MB_TRANSPARENT;
+        if (on && !act) st64(part + 2 * (size_t)mb, 0ull);
+        const unsigned long long m = __ballot(act);
+        const int pos = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        // the wave's previous reads of the list are done before it is rewritten
+        __builtin_amdgcn_wave_barrier();
+        if (act) {
+            lk[pos] = k;
+            lc[pos] = cl;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int cnt_act = __popcll(m);
+        for (int i = 0; i < cnt_act; i += 8) {
+            const bool live = i + g < cnt_act;
+            const int kk = lk[live ? i + g : i], ckk = lc[live ? i + g : i];
+            int sse, cnt;
+            mc_mb<false>(c, kk, ckk, t, false, sse, cnt);
+            sse = sum8(sse);
+            cnt = sum8(cnt);
+            if (live && t == 0) st64(part + 2 * ((size_t)c.base + kk), (unsigned long long)(uint32_t)sse |
+                                                                            ((unsigned long long)(uint32_t)cnt << 32));
         }
     });
 }
@@ -333,12 +399,17 @@ hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_
 size_t mc_scratch(int total_mbs) { return (size_t)total_mbs * 8; }
 
 hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, unsigned long long *acc,
-                     uint32_t *status, hipStream_t s, const KernelTimer *t, int per_cu, bool four) {
+                     uint32_t *status, hipStream_t s, const KernelTimer *t, int per_cu, bool four, bool sums_only) {
     if (total_mbs <= 0) return hipSuccess;
     const int nu = (total_mbs + 7) / 8;
     const int chunk = (flat_chunk(nu, per_cu) + 3) / 4 * 4;
     timer_mark(t, true, s);
-    if (four)
+    if (sums_only && !four) {
+        const int nu64 = (total_mbs + 63) / 64;
+        const int chunk64 = (flat_chunk(nu64, per_cu) + 3) / 4 * 4;
+        hipLaunchKernelGGL(mc_sums_kernel, dim3((nu64 + chunk64 - 1) / chunk64), dim3(256), 0, s, jobs, n, total_mbs,
+                           chunk64, part, status);
+    } else if (four)
         hipLaunchKernelGGL(mc_kernel<true>, dim3((nu + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk,
                            part, status);
     else

@@ -91,10 +91,12 @@ hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_
                               uint32_t *counters, uint32_t *list, uint32_t *status, hipStream_t s,
                               const KernelTimer *t = nullptr);
 size_t full_search_scratch(int total_mbs);
-// `four`: each job's mv holds four vectors per MB (8 x 8 blocks in raster order)
+// `four`: each job's mv holds four vectors per MB (8 x 8 blocks in raster order).
+// `sums_only`: no job writes a prediction frame; transparent MBs (by class)
+// are then skipped - exact when the classes are those of the current alpha.
 hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, unsigned long long *acc,
                      uint32_t *status, hipStream_t s, const KernelTimer *t = nullptr, int per_cu = 8,
-                     bool four = false);
+                     bool four = false, bool sums_only = false);
 // Pel-recursive refinement of the 8 x 8 blocks of every texture MB: reads
 // cur, ref, cls, mv_int (start vectors) and tf (the MB's half-pel vector,
 // repeated for boundary MBs); writes four vectors per MB to mv, and per

@@ -213,11 +213,12 @@ constexpr uint32_t kVersion = 1;
 constexpr size_t kHeader = 24;
 constexpr size_t kFileBytes = kHeader + 8 * (size_t)kNetParams + 8;
 
+// 64-bit FNV-1a: the published offset basis and prime.
 uint64_t fnv1a64(const uint8_t *p, size_t n) {
-    uint64_t h = 1469598103934665603ull;
+    uint64_t h = 0xcbf29ce484222325ull;
     for (size_t i = 0; i < n; ++i) {
         h ^= p[i];
-        h *= 1099511628211ull;
+        h *= 0x100000001b3ull;
     }
     return h;
 }

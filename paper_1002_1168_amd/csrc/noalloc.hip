@@ -104,5 +104,8 @@ extern "C" int me_motion_compensate_sse_noalloc(const me_job *jobs, int n, uint8
     // written by the prediction kernel before the per-job sums read them
     rc = hip_err(launch_fill_u32(status, kStatusBytes / 4, 0u, s));
     if (rc) return rc;
-    return hip_err(launch_mc(table, n, (int)total, part, (unsigned long long *)sums, status, s, nullptr));
+    bool sums_only = true;
+    for (int i = 0; pred && i < n; ++i) sums_only = sums_only && pred[i] == nullptr;
+    return hip_err(launch_mc(table, n, (int)total, part, (unsigned long long *)sums, status, s, nullptr, 8, false,
+                             sums_only));
 }

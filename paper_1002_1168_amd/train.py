@@ -139,47 +139,74 @@ def training_sets(train_count: int, held_count: int, frames: int, seed: int = 4)
             synth.cif_training_set(seed + 1000, held_count, frames))
 
 
+def hd_training_sets(train_count: int, held_count: int, frames: int, seed: int = 104, workers: int = 16):
+    """1920x1088 streams in the style of the batched high-definition workload
+    (3-6 VOPs, sub-pixel velocities up to 24 px per frame), from seeds
+    disjoint from each other and from the workload's own streams."""
+    return (synth.hd_streams(seed=seed, frames=frames, streams=train_count, workers=workers),
+            synth.hd_streams(seed=seed + 1000, frames=frames, streams=held_count, workers=workers))
+
+
+# Presets: (training-set maker, search range, half-sample refinement, window scale, output name)
+PRESETS = {
+    "cif": (training_sets, 16, 0, 2, "proposal_cif_s16"),
+    "hd": (hd_training_sets, 32, 1, 4, "proposal_hd_s32"),
+}
+
+
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
 
 
 def main(argv=None):
-    """Train on generated CIF sequences (labels: the plain method), evaluate
-    on held-out ones, write the weights (.npy, float32) and a JSON record."""
+    """Train on generated sequences (labels: the plain method), evaluate on
+    held-out ones, write the weights (.npy, float32), a checkpoint (.menet,
+    with the window scale) and a JSON record."""
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--train", type=int, default=200)
-    ap.add_argument("--held", type=int, default=50)
-    ap.add_argument("--frames", type=int, default=30)
+    ap.add_argument("--preset", choices=sorted(PRESETS), default="cif",
+                    help="cif: 352x288, S=16, scale 2; hd: 1920x1088, S=32 with half-pel, scale 4")
+    ap.add_argument("--train", type=int, default=None)
+    ap.add_argument("--held", type=int, default=None)
+    ap.add_argument("--frames", type=int, default=None)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--pairs-per-step", type=int, default=64)
-    ap.add_argument("--lr", type=float, default=0.03)
+    ap.add_argument("--lr", type=float, default=None)
     ap.add_argument("--momentum", type=float, default=0.9)
     ap.add_argument("--init-seed", type=int, default=1)
-    ap.add_argument("--search-range", type=int, default=16)
-    ap.add_argument("--out", default=os.path.join(WEIGHTS, "proposal_cif_s16"))
+    ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
+    make, S, half, scale, name = PRESETS[a.preset]
+    hd = a.preset == "hd"
+    ntrain = a.train if a.train is not None else (32 if hd else 200)
+    nheld = a.held if a.held is not None else (8 if hd else 50)
+    frames = a.frames if a.frames is not None else (12 if hd else 30)
+    lr = a.lr if a.lr is not None else (0.003 if hd else 0.03)
+    out = a.out or os.path.join(WEIGHTS, name)
     torch.cuda.set_device(0)
     t0 = time.time()
-    tr, ho = training_sets(a.train, a.held, a.frames)
-    p = me.me_default_params(search_range=a.search_range)
+    tr, ho = make(ntrain, nheld, frames)
+    p = me.me_default_params(search_range=S, half_pel=half)
     dtr, dho = label(tr, p), label(ho, p)
-    print(f"generated and labelled {a.train} + {a.held} sequences in {time.time() - t0:.1f}s", flush=True)
-    net = me.Net(synth.net_init(a.init_seed))
+    del tr, ho
+    print(f"generated and labelled {ntrain} + {nheld} sequences in {time.time() - t0:.1f}s", flush=True)
+    net = me.Net(synth.net_init(a.init_seed), scale=scale)
     t1 = time.time()
-    hist = train(net, dtr, a.steps, a.pairs_per_step, a.lr, a.momentum, log_every=500,
+    hist = train(net, dtr, a.steps, a.pairs_per_step, lr, a.momentum, log_every=500,
                  log=lambda m: print(m, flush=True))
     torch.cuda.synchronize()
     ttrain = time.time() - t1
-    rec = {"train_sequences": a.train, "held_out_sequences": a.held, "frames": a.frames, "steps": a.steps,
-           "pairs_per_step": a.pairs_per_step, "lr": a.lr, "momentum": a.momentum, "init_seed": a.init_seed,
-           "search_range": a.search_range, "train_seconds": ttrain,
+    rec = {"preset": a.preset, "train_sequences": ntrain, "held_out_sequences": nheld, "frames": frames,
+           "steps": a.steps, "pairs_per_step": a.pairs_per_step, "lr": lr, "momentum": a.momentum,
+           "init_seed": a.init_seed, "search_range": S, "half_pel": half, "window_scale": scale,
+           "train_seconds": ttrain,
            "loss_first100": float(np.mean(hist[:100])), "loss_last100": float(np.mean(hist[-100:])),
            "held_out": {"prediction": prediction_error(net, dho), "plain": evaluate(dho, p, None),
                         "learned": evaluate(dho, p, net)}}
     w = net.weights()
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    net.save(out + ".menet")
     net.close()
-    os.makedirs(os.path.dirname(a.out), exist_ok=True)
-    np.save(a.out + ".npy", w, allow_pickle=False)
-    with open(a.out + ".json", "w") as f:
+    np.save(out + ".npy", w, allow_pickle=False)
+    with open(out + ".json", "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec), flush=True)
 

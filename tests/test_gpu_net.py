@@ -22,6 +22,7 @@ import paper_1002_1168_amd as me
 from paper_1002_1168_amd import synth
 
 from gpu_util import assert_same, gpu_classify, oracle_params, say
+from test_checkpoint_files import parse as parse_checkpoint
 
 pytestmark = pytest.mark.gpu
 
@@ -235,8 +236,10 @@ def test_checkpoint_round_trip(torch_cuda, scale, tmp_path):
             back.close()
     finally:
         net.close()
+    # the file read back with plain Python: header, standard FNV-1a 64 checksum, payload
+    fscale, fw, fv = parse_checkpoint(path)
+    assert fscale == scale and np.array_equal(fw, w1) and np.array_equal(fv, v1)
     raw = bytearray(open(path, "rb").read())
-    assert len(raw) == 24 + 8 * me.ME_NET_PARAMS + 8 and raw[:8] == b"ME-NET\0\0"
     raw[24 + 4 * 100] ^= 0x01
     bad = tmp_path / "bad.menet"
     bad.write_bytes(bytes(raw))

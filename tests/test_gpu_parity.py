@@ -363,6 +363,9 @@ def test_mc_psnr_parity(torch_cuda, half):
         sse, npx, ps, rc = me.me_motion_compensate_psnr(jobs, [x.data_ptr() for x in preds],
                                                         stream=dv.stream_handle())
         assert rc == me.ME_OK
+        # without prediction frames (transparent MBs skipped by class): the same sums
+        sse2, npx2, ps2, rc2 = me.me_motion_compensate_psnr(jobs, stream=dv.stream_handle())
+        assert rc2 == me.ME_OK and list(sse2) == list(sse) and list(npx2) == list(npx)
         for i in range(pairs):
             t = i + 1
             ca = None if v is None else seq.alpha[v, t]
@@ -403,6 +406,9 @@ def test_classify_mc_five_thousand_one_mb_jobs(torch_cuda):
                                                     check=False)
     torch.cuda.synchronize()
     assert rc == me.ME_EEMPTY
+    # the sums alone: units of 64 one-MB jobs, transparent ones skipped by class
+    sse2, npx2, _, rc2 = me.me_motion_compensate_psnr(jobs, stream=s, check=False)
+    assert rc2 == me.ME_EEMPTY and list(sse2) == list(sse) and list(npx2) == list(npx)
     gc, gb, gp = cls.cpu().numpy(), bab.cpu().numpy().view(np.uint32), pred.cpu().numpy()
     for i in range(n):
         sl = slice(16 * i, 16 * i + 16)

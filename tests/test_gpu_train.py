@@ -1,7 +1,8 @@
 """What training gains: the network trained by the library's own kernels on
 generated CIF sequences (labels = the plain method's vectors) against the
 zero predictor, the untrained network and the plain method, on held-out
-sequences."""
+sequences: prediction error, PSNR, distortion, recursion iterations and
+compared blocks per MB, each printed for plain, untrained and trained."""
 import numpy as np
 import pytest
 
@@ -43,14 +44,21 @@ def test_trained_network_gains(torch_cuda):
     ev_p = T.evaluate(dho, p, None)
     say("loss", np.mean(hist[:200]), "->", np.mean(hist[-200:]))
     say("held-out MAE: zero", e1["mae_zero"], "untrained", e0["mae_net"], "trained", e1["mae_net"])
-    say("plain", ev_p)
-    say("untrained seeds", ev_u)
-    say("trained seeds", ev_l)
+    for name, ev in (("plain", ev_p), ("untrained seeds", ev_u), ("trained seeds", ev_l)):
+        say(f"{name:16s} PSNR {ev['psnr_db']:.4f} dB  cost/MB {ev['cost_per_mb']:.2f}  "
+            f"iters/MB {ev['iters_per_mb']:.4f}  points/MB {ev['points_per_mb']:.3f}")
     assert np.mean(hist[-200:]) < 0.5 * np.mean(hist[:200])
     # the trained proposal predicts the plain method's vectors far better than no motion
     assert e1["mae_net"] < 0.6 * e1["mae_zero"] and e1["mae_net"] < 0.6 * e0["mae_net"]
     # its seeds start the recursion closer: fewer iterations than the untrained seeds
     assert ev_l["iters_per_mb"] < 0.75 * ev_u["iters_per_mb"]
-    # the learned form stays within the admitted PSNR loss of the plain method (it gains here)
+    # the learned form stays within the admitted PSNR loss of the plain method
+    # (it gains a little here) at no higher distortion
     assert ev_l["psnr_db"] >= ev_p["psnr_db"] - 0.05
     assert ev_l["cost_per_mb"] <= ev_p["cost_per_mb"]
+    # What does not hold: fewer iterations than the plain method.  The plain
+    # recursion starts from the best of A, B, C and T, which already sits at
+    # its fixed point for most MBs (about 0.2 iterations per MB here); the
+    # seeded recursion runs whenever the rounded seed misses that point, and
+    # the fallback adds the plain recursion on top.  The measured figures are
+    # printed above; nothing is asserted about them.
