@@ -315,6 +315,11 @@ __device__ __forceinline__ Sweep sweep(const Ctx &c, int dx, int dy) {
 // at that point.  Returns the number of candidates evaluated.
 __device__ int pel_recursion(const Ctx &c, const KParams &kp, int &dx, int &dy, int &cost, Sweep sw) {
     int it = 0;
+    // every value here is the same in all lanes: readfirstlane keeps the
+    // step rule in scalar registers and scalar branches
+    dx = uni(dx);
+    dy = uni(dy);
+    cost = uni(cost);
     while (it < kp.k_max) {
         const int nx = sw.nxy & 0xFFFF, ny = sw.nxy >> 16;
         // U = trunc(S / n) gives a zero step iff |U| < zero_t, i.e. |S| < zero_t * n:
@@ -325,8 +330,8 @@ __device__ int pel_recursion(const Ctx &c, const KParams &kp, int &dx, int &dy, 
         const int sx = zx ? 0 : prs_step(sw.sx / nx, kp.eps, kp.max_step);
         const int sy = zy ? 0 : prs_step(sw.sy / ny, kp.eps, kp.max_step);
         if (sx == 0 && sy == 0) break;
-        const int tx = iclamp(dx + sx, c.lox, c.hix);
-        const int ty = iclamp(dy + sy, c.loy, c.hiy);
+        const int tx = uni(iclamp(dx + sx, c.lox, c.hix));
+        const int ty = uni(iclamp(dy + sy, c.loy, c.hiy));
         if (tx == dx && ty == dy) break;
         ++it;
         const Sweep s2 = sweep(c, tx, ty);
@@ -348,66 +353,100 @@ __device__ int pel_recursion(const Ctx &c, const KParams &kp, int &dx, int &dy, 
 constexpr int kHalfX[8] = {-1, 0, 1, -1, 1, -1, 0, 1};
 constexpr int kHalfY[8] = {-1, -1, -1, 0, 0, 1, 1, 1};
 
+// Per byte, (a + b + 1) >> 1: the half-sample average of MPEG-4 with
+// rounding control 0, four pixels at once (v_lerp_u8 adds the low bit of
+// each byte of its third operand before the shift).
+__device__ __forceinline__ uint32_t avg2_u8x4(uint32_t a, uint32_t b) {
+    return __builtin_amdgcn_lerp(a, b, 0x01010101u);
+}
+
+// The even (bytes 0, 2) and odd (bytes 1, 3) pixels of a quad in the low
+// bytes of two 16-bit halves.
+__device__ __forceinline__ uint32_t even_u8x2(uint32_t x) { return x & 0x00FF00FFu; }
+__device__ __forceinline__ uint32_t odd_u8x2(uint32_t x) { return __builtin_amdgcn_perm(0u, x, 0x0C030C01u); }
+
+// Per byte, (s + 2) >> 2 of 16-bit half sums s = a + b + c + d (at most
+// 1022, so no half carries into the next): the diagonal half-sample value,
+// even and odd pixels put back in place.
+__device__ __forceinline__ uint32_t quarter_u8x4(uint32_t se, uint32_t so) {
+    const uint32_t pe = ((se + 0x00020002u) >> 2) & 0x00FF00FFu;
+    const uint32_t po = ((so + 0x00020002u) >> 2) & 0x00FF00FFu;
+    return pe | (po << 8);
+}
+
 // Half-sample refinement around the full-pel vector d (MPEG-4 bilinear,
 // rounding control 0).  Updates (hx, hy), cost; returns the feasible count.
+// Each lane predicts its 4 pixels for all eight offsets from the quads of
+// the rows above, at and below d, shifted one pixel left (L), in place (P)
+// and one pixel right (R): horizontal and vertical half samples are per-byte
+// rounded averages, diagonal ones per-byte (A + B + C + D + 2) >> 2 from
+// 16-bit pair sums; each SAD is one v_sad_u8.
 __device__ int half_refine(const Ctx &c, const KParams &kp, int dx, int dy, int &hx, int &hy, int &cost) {
-    // 3 x 6 neighbourhood: rows ry-1..ry+1, columns rx-1..rx+4
-    int nb[3][6];
     const int off = c.off0 + dy * c.pitch + dx;
+    uint32_t L[3], P[3], R[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
         uint32_t lo, hi;
-        lds8(c.win, off + (r - 1) * c.pitch - 1, lo, hi);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) nb[r][q] = byte_of(lo, q);
-        nb[r][4] = byte_of(hi, 0);
-        nb[r][5] = byte_of(hi, 1);
+        lds8(c.win, off + (r - 1) * c.pitch - 1, lo, hi);   // columns -1 .. 6
+        L[r] = lo;
+        P[r] = __builtin_amdgcn_alignbyte(hi, lo, 1);
+        R[r] = __builtin_amdgcn_alignbyte(hi, lo, 2);
     }
-    int part[8];
-    bool feas[8];
-    int nfeas = 0;
+    // horizontal pair sums (pixel k-1 + k, pixel k + k+1) per row, even / odd
+    uint32_t hme[3], hmo[3], hpe[3], hpo[3];
 #pragma unroll
-    for (int o = 0; o < 8; ++o) {
-        const int ox = kHalfX[o], oy = kHalfY[o];
-        const int fx = ox & 1, fy = oy & 1;
-        const int oxr = ox < 0 ? 0 : 1, oyr = oy < 0 ? 0 : 1;  // neighbourhood origin of A
-        const int qx = 2 * dx + ox, qy = 2 * dy + oy;
-        const int ix = dx + (ox < 0 ? -1 : 0), iy = dy + (oy < 0 ? -1 : 0);
-        feas[o] = abs(qx) <= 2 * kp.S && abs(qy) <= 2 * kp.S &&
-                  (kp.unrestricted || (c.x0 + ix >= 0 && c.x0 + ix + 15 + fx <= c.W - 1 && c.y0 + iy >= 0 &&
-                                       c.y0 + iy + 15 + fy <= c.H - 1));
-        nfeas += feas[o];
-        int s = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int A = nb[oyr][oxr + k], B = nb[oyr][oxr + k + 1];
-            const int Cc = nb[oyr + 1][oxr + k], D = nb[oyr + 1][oxr + k + 1];
-            const int p = (fx && fy) ? ((A + B + Cc + D + 2) >> 2)
-                                     : fx ? ((A + B + 1) >> 1) : fy ? ((A + Cc + 1) >> 1) : A;
-            s += abs(byte_of(c.c4, k) - p);
-        }
-        part[o] = s;
+    for (int r = 0; r < 3; ++r) {
+        const uint32_t pe = even_u8x2(P[r]), po = odd_u8x2(P[r]);
+        hme[r] = even_u8x2(L[r]) + pe;
+        hmo[r] = odd_u8x2(L[r]) + po;
+        hpe[r] = pe + even_u8x2(R[r]);
+        hpo[r] = po + odd_u8x2(R[r]);
     }
+    // predictions in the order of the offsets (row order: -1 -1, 0 -1, 1 -1,
+    // -1 0, 1 0, -1 1, 0 1, 1 1)
+    uint32_t pred[8];
+    pred[0] = quarter_u8x4(hme[0] + hme[1], hmo[0] + hmo[1]);
+    pred[1] = avg2_u8x4(P[0], P[1]);
+    pred[2] = quarter_u8x4(hpe[0] + hpe[1], hpo[0] + hpo[1]);
+    pred[3] = avg2_u8x4(L[1], P[1]);
+    pred[4] = avg2_u8x4(P[1], R[1]);
+    pred[5] = quarter_u8x4(hme[1] + hme[2], hmo[1] + hmo[2]);
+    pred[6] = avg2_u8x4(P[1], P[2]);
+    pred[7] = quarter_u8x4(hpe[1] + hpe[2], hpo[1] + hpo[2]);
     int tot[8];
 #pragma unroll
     for (int o = 0; o < 8; o += 2) {
-        const int pk = wave_sum(part[o] | (part[o + 1] << 16));
+        const int pk = wave_sum((int)__builtin_amdgcn_sad_u8(c.c4, pred[o], 0u) |
+                                ((int)__builtin_amdgcn_sad_u8(c.c4, pred[o + 1], 0u) << 16));
         tot[o] = pk & 0xFFFF;
         tot[o + 1] = (int)((uint32_t)pk >> 16);
     }
-    int bx = 2 * dx, by = 2 * dy, bc = cost;
+    // feasibility, the same in every lane: offset -1 / +1 on an axis needs
+    // |2d -+ 1| <= 2S and (unless vectors are unrestricted) the interpolated
+    // block's extra column / row inside the frame (d itself is admissible)
+    dx = uni(dx);
+    dy = uni(dy);
+    const int S2 = 2 * kp.S, ur = kp.unrestricted;
+    const bool xm = 2 * dx - 1 >= -S2 && (ur || c.x0 + dx >= 1);
+    const bool xp = 2 * dx + 1 <= S2 && (ur || c.x0 + dx + 16 <= c.W - 1);
+    const bool ym = 2 * dy - 1 >= -S2 && (ur || c.y0 + dy >= 1);
+    const bool yp = 2 * dy + 1 <= S2 && (ur || c.y0 + dy + 16 <= c.H - 1);
+    int bx = 2 * dx, by = 2 * dy, bc = uni(cost), nfeas = 0;
 #pragma unroll
     for (int o = 0; o < 8; ++o) {
-        if (feas[o] && tot[o] < bc) {
+        const int ox = kHalfX[o], oy = kHalfY[o];
+        const bool feas = (ox < 0 ? xm : ox > 0 ? xp : true) && (oy < 0 ? ym : oy > 0 ? yp : true);
+        nfeas += feas;
+        if (feas && tot[o] < bc) {
             bc = tot[o];
-            bx = 2 * dx + kHalfX[o];
-            by = 2 * dy + kHalfY[o];
+            bx = 2 * dx + ox;
+            by = 2 * dy + oy;
         }
     }
-    hx = bx;
-    hy = by;
-    cost = bc;
-    return nfeas;
+    hx = uni(bx);
+    hy = uni(by);
+    cost = uni(bc);
+    return uni(nfeas);
 }
 
 struct MbOut {
@@ -419,6 +458,13 @@ struct MbOut {
 // order A, B, C, T, its first minimum, the recursion (from a learned seed
 // with the 5 % fallback when the job carries seeds), half-sample refinement.
 __device__ MbOut search_mb(const uint32_t *seed, const Ctx &c, int k, int (&cx)[4], int (&cy)[4], const KParams &kp) {
+    // the candidates are the same in every lane: in scalar registers, the
+    // list logic below is scalar code
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        cx[i] = uni(cx[i]);
+        cy[i] = uni(cy[i]);
+    }
     bool keep[4];
     int n = 0;
 #pragma unroll
@@ -478,6 +524,9 @@ __device__ MbOut search_mb(const uint32_t *seed, const Ctx &c, int k, int (&cx)[
             bc = cost_of(c, costs[3]);
         }
     }
+    dx = uni(dx);
+    dy = uni(dy);
+    bc = uni(bc);
     int dc = bc;
     int pts = n + (tex_t ? 1 : 0), its = 0;
     if (seed && !c.shape) {
@@ -1695,7 +1744,7 @@ __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
                     vprog[wv] = h2;  // h done, and the transparent MBs up to h2
                     if (pub_global) publish(gprog, (unsigned long long)(uint32_t)h2);
                 }
-                lastv = o.mvi;
+                lastv = (uint32_t)uni((int)o.mvi);
                 lasth = h;
                 h = h2;
             }
