@@ -1473,6 +1473,25 @@ struct PrArgs {
 
 typedef __attribute__((address_space(3))) volatile uint32_t l_vu32;
 
+// Row progress word (one per MB row of a band-last row): bits 0-8 the count
+// of the row's MBs done (every MB before that position), bits 9-17 and 18-26
+// the positions of the two latest searched MBs (511: none), bits 32-47 and
+// 48-63 their full-pel vectors as two signed bytes each (|d| <= 64).  The
+// result arrays of every other MB before the count are complete when the
+// word is published: a row worker issues an MB's result stores one MB late,
+// before the loads of the window after next, and waits for those loads
+// before it publishes again; the vector-memory counter completes in issue
+// order.
+constexpr uint32_t kNoPos = 511u;
+__device__ __forceinline__ unsigned long long row_word(uint32_t count, uint32_t p, uint32_t vp, uint32_t q, uint32_t vq) {
+    return (unsigned long long)(count | (p << 9) | (q << 18)) | ((unsigned long long)vp << 32) |
+           ((unsigned long long)vq << 48);
+}
+__device__ __forceinline__ uint32_t enc_full(uint32_t mvi) { return enc8(mvx_full(mvi), mvy_full(mvi)); }
+__device__ __forceinline__ uint32_t dec_full(uint32_t e) {
+    return pack_mv(2 * (int)(int8_t)(e & 0xFF), 2 * (int)(int8_t)(e >> 8));
+}
+
 // Window loads of one MB, issued ahead.  Column-major: the window's dw =
 // pitch / 4 dword columns are spread over the lanes, g = 64 / dw lanes per
 // column; lane l (taken modulo g * dw, so spare lanes repeat the first ones)
@@ -1647,7 +1666,7 @@ __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
             asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
             if (l == 0) {
                 vprog[wv] = h;
-                if (pub_global) publish(gprog, (unsigned long long)(uint32_t)h);
+                if (pub_global) publish(gprog, row_word((uint32_t)h, kNoPos, 0u, kNoPos, 0u));
             }
             RowWin<(EM > 0 ? EM : 1)> nw;
             uint32_t ncur = 0, nt = 0;
@@ -1663,6 +1682,13 @@ __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
             if (h < wm) issue(h);
             uint32_t lastv = 0u;  // vector of MB h - 1 when it was searched
             int lasth = -2;
+            // results of the previous searched MB, stored one MB late (after
+            // the next window's loads have arrived): so that waiting for a
+            // window never waits for result stores still in flight
+            bool pend = false;
+            int pk = 0, piters = 0, ppoints = 0;
+            uint32_t pmv = 0u, pmvi = 0u, pcost = 0u;
+            unsigned long long wseen = 0ull;  // the latest row word seen (first row of a band)
             while (h < wm) {
                 const int k = v * wm + h;
                 const int x0 = 16 * h, y0 = 16 * v;
@@ -1676,23 +1702,12 @@ __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
                 }
                 const uint32_t cur4 = ncur, tv = nt;
                 const int h2 = next_set(srch, h + 1, wm);
-                if (h2 < wm) issue(h2);  // in flight during this MB's search
-                c.win = win;
-                c.R = R;
-                c.pitch = a.pitch;
-                c.S = S;
-                c.off0 = (j + S + 1) * a.pitch + 4 * q + S + 1;
-                c.x0 = x0;
-                c.y0 = y0;
-                c.W = W;
-                c.H = H;
-                set_box(c, kp, x0, y0, W, H);
-                c.c4 = c.shape ? bin4(cur4) : cur4;
-                if (kp.t_texture && c.shape && !kp.shape_only) {
-                    c.ref_l = D.ptr<const uint8_t>(DW(ref));
-                    c.st = st;
-                    c.tl4 = ldg32((const uint32_t *)(D.ptr<const uint8_t>(DW(cur)) + (size_t)(y0 + j) * st + x0 + 4 * q));
-                }
+                // the previous searched MB's results (issued before the next
+                // window's loads, so that waiting for that window does not wait
+                // for stores issued after it), then the next window's loads, in
+                // flight during the poll and this MB's search
+                if (pend && l == 0) store_result(D, pk, pmv, pmvi, pcost, piters, ppoints);
+                if (h2 < wm) issue(h2);
                 // B and C from the row above, once that row is far enough
                 const bool useB = v > 0 && bit_of(upn, h);
                 const bool useC = v > 0 && h + 1 < wm && bit_of(upn, h + 1);
@@ -1701,8 +1716,14 @@ __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
                 if (need > 0) {
                     int spins = 0;
                     for (;;) {
-                        const int got = wv > 0 ? uni(vprog[wv - 1])
-                                               : uni((int)(uint32_t)ld64(a.rowprog + ch.line_base + v - 1));
+                        int got;
+                        if (wv > 0) {
+                            got = uni(vprog[wv - 1]);
+                        } else {
+                            if ((int)(uint32_t)(wseen & 0x1FFull) < need)
+                                wseen = (unsigned long long)uni64(ld64(a.rowprog + ch.line_base + v - 1));
+                            got = (int)(uint32_t)(wseen & 0x1FFull);
+                        }
                         if (got >= need) break;
                         if ((spins & 31) == 31 && (uni((int)ld_relaxed(a.status)) & ST_ABORT)) {
                             aborted = true;
@@ -1726,9 +1747,36 @@ __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
                         mB = useB ? (uint32_t)uni((int)vvec[(wv - 1) * 256 + h]) : 0u;
                         mC = useC ? (uint32_t)uni((int)vvec[(wv - 1) * 256 + h + 1]) : 0u;
                     } else {
-                        mB = useB ? (uint32_t)uni((int)ld_relaxed(mvi_up + h)) : 0u;
-                        mC = useC ? (uint32_t)uni((int)ld_relaxed(mvi_up + h + 1)) : 0u;
+                        // the two latest searched MBs come with the word; the
+                        // arrays hold every other one
+                        const uint32_t lo = (uint32_t)wseen, hi = (uint32_t)(wseen >> 32);
+                        const uint32_t p0 = (lo >> 9) & 0x1FFu, p1 = (lo >> 18) & 0x1FFu;
+                        const bool bw = useB && ((uint32_t)h == p0 || (uint32_t)h == p1);
+                        const bool cw = useC && ((uint32_t)(h + 1) == p0 || (uint32_t)(h + 1) == p1);
+                        uint32_t rb = 0u, rc = 0u;
+                        if (useB && !bw) rb = ld_relaxed(mvi_up + h);
+                        if (useC && !cw) rc = ld_relaxed(mvi_up + h + 1);
+                        const uint32_t eb = (uint32_t)h == p0 ? (hi & 0xFFFFu) : (hi >> 16);
+                        const uint32_t ec = (uint32_t)(h + 1) == p0 ? (hi & 0xFFFFu) : (hi >> 16);
+                        mB = !useB ? 0u : bw ? dec_full(eb) : (uint32_t)uni((int)rb);
+                        mC = !useC ? 0u : cw ? dec_full(ec) : (uint32_t)uni((int)rc);
                     }
+                }
+                c.win = win;
+                c.R = R;
+                c.pitch = a.pitch;
+                c.S = S;
+                c.off0 = (j + S + 1) * a.pitch + 4 * q + S + 1;
+                c.x0 = x0;
+                c.y0 = y0;
+                c.W = W;
+                c.H = H;
+                set_box(c, kp, x0, y0, W, H);
+                c.c4 = c.shape ? bin4(cur4) : cur4;
+                if (kp.t_texture && c.shape && !kp.shape_only) {
+                    c.ref_l = D.ptr<const uint8_t>(DW(ref));
+                    c.st = st;
+                    c.tl4 = ldg32((const uint32_t *)(D.ptr<const uint8_t>(DW(cur)) + (size_t)(y0 + j) * st + x0 + 4 * q));
                 }
                 const uint32_t mA = lasth == h - 1 ? lastv : 0u;
                 const uint32_t mT = (uint32_t)uni((int)tv);
@@ -1738,16 +1786,35 @@ __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
                 // its LDS writes (and a compiler fence) suffices
                 asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
                 const MbOut o = search_mb(seed, c, k, cx, cy, kp);
+                const uint32_t ovi = (uint32_t)uni((int)o.mvi);
                 if (l == 0) {
-                    store_result(D, k, o.mv, o.mvi, o.cost, o.iters, o.points);
-                    vvec[wv * 256 + h] = o.mvi;
+                    vvec[wv * 256 + h] = ovi;
                     vprog[wv] = h2;  // h done, and the transparent MBs up to h2
-                    if (pub_global) publish(gprog, (unsigned long long)(uint32_t)h2);
+                    // the word carries h and the searched MB before it; every
+                    // older result was stored before this MB's window arrived
+                    if (pub_global)
+                        __hip_atomic_store(gprog,
+                                           row_word((uint32_t)h2, (uint32_t)h, enc_full(ovi),
+                                                    lasth >= 0 ? (uint32_t)lasth : kNoPos, enc_full(lastv)),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                lastv = (uint32_t)uni((int)o.mvi);
+                pend = true;
+                pk = k;
+                pmv = (uint32_t)uni((int)o.mv);
+                pmvi = ovi;
+                pcost = (uint32_t)uni((int)o.cost);
+                piters = uni(o.iters);
+                ppoints = uni(o.points);
+                lastv = ovi;
                 lasth = h;
                 h = h2;
             }
+            // the row's last results, then (band-last row) a final word once
+            // every store has completed
+            if (pend && l == 0) store_result(D, pk, pmv, pmvi, pcost, piters, ppoints);
+            if (!aborted && pub_global && l == 0)
+                publish(gprog, row_word((uint32_t)wm, lasth >= 0 ? (uint32_t)lasth : kNoPos, enc_full(lastv), kNoPos,
+                                        0u));
             if (aborted && l == 0) *vab = 1;
         }
         __syncthreads();

@@ -205,6 +205,10 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
 }
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ unsigned long long uni64(unsigned long long v) {
+    return (unsigned long long)(uint32_t)uni((int)(uint32_t)v) |
+           ((unsigned long long)(uint32_t)uni((int)(uint32_t)(v >> 32)) << 32);
+}
 
 #define DWI(f) ((int)(offsetof(JobDesc, f) / 4))
 
