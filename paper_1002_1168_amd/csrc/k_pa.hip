@@ -234,19 +234,6 @@ struct Plan {
     }
 };
 
-// 4 window bytes starting at byte offset `off` (any alignment).
-__device__ __forceinline__ uint32_t lds4(const uint32_t *win, int off) {
-    const uint32_t a = win[off >> 2], b = win[(off >> 2) + 1];
-    return __builtin_amdgcn_alignbyte(b, a, off & 3);
-}
-
-// 8 window bytes starting at byte offset `off` (lo = bytes 0..3, hi = 4..7).
-__device__ __forceinline__ void lds8(const uint32_t *win, int off, uint32_t &lo, uint32_t &hi) {
-    const uint32_t a = win[off >> 2], b = win[(off >> 2) + 1], c = win[(off >> 2) + 2];
-    lo = __builtin_amdgcn_alignbyte(b, a, off & 3);
-    hi = __builtin_amdgcn_alignbyte(c, b, off & 3);
-}
-
 struct Sweep {
     int sad, sx, sy, nxy;  // nxy = nx | ny << 16
 };
@@ -256,6 +243,7 @@ struct Ctx {
     const short *R;
     int pitch, S;
     int off0;          // window byte offset of this lane's first pixel at d = 0
+    int bdw, ph;       // off0 = 4 bdw + ph; ph is the same in every lane (the pitch is a multiple of 4)
     int x0, y0, W, H;
     uint32_t c4;       // this lane's 4 current pixels
     bool shape;
@@ -268,6 +256,29 @@ struct Ctx {
 };
 
 __device__ __forceinline__ int cost_of(const Ctx &c, int sad) { return c.shape ? sad / 255 : sad; }
+
+// The lane's window offset plus a wave-uniform offset uo: the byte shift and
+// the dword step are then scalar, and a read is one address add, one
+// two-dword LDS read and one v_alignbyte_b32.
+__device__ __forceinline__ void set_lane_base(Ctx &c, int off0, int S) {
+    c.off0 = off0;
+    c.bdw = off0 >> 2;
+    c.ph = (S + 1) & 3;
+}
+// 4 window bytes at the lane's pixel moved by uo
+__device__ __forceinline__ uint32_t wread4(const Ctx &c, int uo) {
+    const int t = uni(c.ph + uo);
+    const uint32_t *w = c.win + c.bdw + (t >> 2);
+    return __builtin_amdgcn_alignbyte(w[1], w[0], (uint32_t)(t & 3));
+}
+// 8 window bytes at the lane's pixel moved by uo (lo = bytes 0..3, hi = 4..7)
+__device__ __forceinline__ void wread8(const Ctx &c, int uo, uint32_t &lo, uint32_t &hi) {
+    const int t = uni(c.ph + uo);
+    const uint32_t *w = c.win + c.bdw + (t >> 2);
+    const uint32_t a = w[0], b = w[1], d = w[2];
+    lo = __builtin_amdgcn_alignbyte(b, a, (uint32_t)(t & 3));
+    hi = __builtin_amdgcn_alignbyte(d, b, (uint32_t)(t & 3));
+}
 
 // Admissible box of the MB at (x0, y0): |d| <= S with the displaced block in
 // the frame, or (unrestricted vectors) |d| <= S only - the staged window
@@ -284,12 +295,12 @@ __device__ __forceinline__ void set_box(Ctx &c, const KParams &kp, int x0, int y
 // gradient sums of Eqs. 3-5 (central differences of the reference at the
 // displaced position).
 __device__ __forceinline__ Sweep sweep(const Ctx &c, int dx, int dy) {
-    const int off = c.off0 + dy * c.pitch + dx;
+    const int uo = uni(dy * c.pitch + dx);
     uint32_t lo, hi;
-    lds8(c.win, off - 1, lo, hi);                 // bytes rx-1 .. rx+6
+    wread8(c, uo - 1, lo, hi);                    // bytes rx-1 .. rx+6
     const uint32_t m = __builtin_amdgcn_alignbyte(hi, lo, 1);
     const int lf = (int)(lo & 0xFF), rt = (int)((hi >> 8) & 0xFF);
-    const uint32_t up = lds4(c.win, off - c.pitch), dn = lds4(c.win, off + c.pitch);
+    const uint32_t up = wread4(c, uo - c.pitch), dn = wread4(c, uo + c.pitch);
     int sad = (int)__builtin_amdgcn_sad_u8(c.c4, m, 0u);
     int sx = 0, sy = 0, nn = 0;
 #pragma unroll
@@ -382,12 +393,12 @@ __device__ __forceinline__ uint32_t quarter_u8x4(uint32_t se, uint32_t so) {
 // rounded averages, diagonal ones per-byte (A + B + C + D + 2) >> 2 from
 // 16-bit pair sums; each SAD is one v_sad_u8.
 __device__ int half_refine(const Ctx &c, const KParams &kp, int dx, int dy, int &hx, int &hy, int &cost) {
-    const int off = c.off0 + dy * c.pitch + dx;
+    const int uo = uni(dy * c.pitch + dx);
     uint32_t L[3], P[3], R[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
         uint32_t lo, hi;
-        lds8(c.win, off + (r - 1) * c.pitch - 1, lo, hi);   // columns -1 .. 6
+        wread8(c, uo + (r - 1) * c.pitch - 1, lo, hi);   // columns -1 .. 6
         L[r] = lo;
         P[r] = __builtin_amdgcn_alignbyte(hi, lo, 1);
         R[r] = __builtin_amdgcn_alignbyte(hi, lo, 2);
@@ -458,28 +469,31 @@ struct MbOut {
 // order A, B, C, T, its first minimum, the recursion (from a learned seed
 // with the 5 % fallback when the job carries seeds), half-sample refinement.
 __device__ MbOut search_mb(const uint32_t *seed, const Ctx &c, int k, int (&cx)[4], int (&cy)[4], const KParams &kp) {
-    // the candidates are the same in every lane: in scalar registers, the
-    // list logic below is scalar code
+    // the candidates are the same in every lane: in scalar registers, and
+    // the list (admissible, distinct, in order) as a bit mask
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         cx[i] = uni(cx[i]);
         cy[i] = uni(cy[i]);
     }
-    bool keep[4];
-    int n = 0;
+    int keepm = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        bool ok = cx[i] >= c.lox && cx[i] <= c.hix && cy[i] >= c.loy && cy[i] <= c.hiy;
+        int ok = (cx[i] >= c.lox && cx[i] <= c.hix && cy[i] >= c.loy && cy[i] <= c.hiy) ? 1 : 0;
 #pragma unroll
-        for (int p = 0; p < i; ++p) ok = ok && !(keep[p] && cx[p] == cx[i] && cy[p] == cy[i]);
-        keep[i] = ok;
-        n += ok;
+        for (int p = 0; p < i; ++p)
+            if (((keepm >> p) & 1) && cx[p] == cx[i] && cy[p] == cy[i]) ok = 0;
+        keepm |= ok << i;
     }
-    if (n == 0) {
+    keepm = uni(keepm);
+    if (keepm == 0) {
         cx[0] = cy[0] = 0;
-        keep[0] = true;
-        n = 1;
+        keepm = 1;
     }
+    const int n = __builtin_popcount((uint32_t)keepm);
+    bool keep[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) keep[i] = (keepm >> i) & 1;
     // block costs of the list, two 16-bit partial SADs per reduction.  All
     // four are computed without branches (their LDS reads in flight
     // together): an offset clamped to +-S lies inside the staged window, and
@@ -487,7 +501,7 @@ __device__ MbOut search_mb(const uint32_t *seed, const Ctx &c, int k, int (&cx)[
     uint32_t blk[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-        blk[i] = lds4(c.win, c.off0 + iclamp(cy[i], -c.S, c.S) * c.pitch + iclamp(cx[i], -c.S, c.S));
+        blk[i] = wread4(c, iclamp(cy[i], -c.S, c.S) * c.pitch + iclamp(cx[i], -c.S, c.S));
     int part[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) part[i] = (int)__builtin_amdgcn_sad_u8(c.c4, blk[i], 0u);
@@ -882,7 +896,7 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
             c.R = R;
             c.pitch = a.pitch;
             c.S = S;
-            c.off0 = (j + S + 1) * a.pitch + 4 * q + S + 1;
+            set_lane_base(c, (j + S + 1) * a.pitch + 4 * q + S + 1, S);
             c.x0 = x0;
             c.y0 = y0;
             c.W = W;
@@ -1156,7 +1170,7 @@ __global__ __launch_bounds__(64 * NW) void pa2_kernel(PaArgs a) {
             c.R = R;
             c.pitch = a.pitch;
             c.S = S;
-            c.off0 = (j + S + 1) * a.pitch + 4 * q + S + 1;
+            set_lane_base(c, (j + S + 1) * a.pitch + 4 * q + S + 1, S);
             c.x0 = x0;
             c.y0 = y0;
             c.W = W;
@@ -1267,7 +1281,7 @@ __global__ __launch_bounds__(64 * NW) void pa2_kernel(PaArgs a) {
             uint32_t blk[3];
 #pragma unroll
             for (int u = 0; u < 3; ++u)
-                blk[u] = lds4(c.win, c.off0 + iclamp(cy[u], -S, S) * c.pitch + iclamp(cx[u], -S, S));
+                blk[u] = wread4(c, iclamp(cy[u], -S, S) * c.pitch + iclamp(cx[u], -S, S));
             const int p01 = wave_sum((int)__builtin_amdgcn_sad_u8(c.c4, blk[0], 0u) |
                                      ((int)__builtin_amdgcn_sad_u8(c.c4, blk[1], 0u) << 16));
             const int p2 = wave_sum((int)__builtin_amdgcn_sad_u8(c.c4, blk[2], 0u));
@@ -1330,7 +1344,7 @@ __global__ __launch_bounds__(64 * NW) void pa2_kernel(PaArgs a) {
             bool from_spec = nabc > 0;
             if (keepT) {
                 const int ct = cost_of(c, wave_sum((int)__builtin_amdgcn_sad_u8(
-                                              c.c4, lds4(c.win, c.off0 + ty * c.pitch + tx), 0u)));
+                                              c.c4, wread4(c, ty * c.pitch + tx), 0u)));
                 if (ct < wc) {
                     wx = tx;
                     wy = ty;
@@ -1341,7 +1355,7 @@ __global__ __launch_bounds__(64 * NW) void pa2_kernel(PaArgs a) {
             if (n == 0) {  // nothing admissible: (0, 0)
                 n = 1;
                 wx = wy = 0;
-                wc = cost_of(c, wave_sum((int)__builtin_amdgcn_sad_u8(c.c4, lds4(c.win, c.off0), 0u)));
+                wc = cost_of(c, wave_sum((int)__builtin_amdgcn_sad_u8(c.c4, wread4(c, 0), 0u)));
                 from_spec = false;
             }
             int pts = n;
@@ -1766,7 +1780,7 @@ __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
                 c.R = R;
                 c.pitch = a.pitch;
                 c.S = S;
-                c.off0 = (j + S + 1) * a.pitch + 4 * q + S + 1;
+                set_lane_base(c, (j + S + 1) * a.pitch + 4 * q + S + 1, S);
                 c.x0 = x0;
                 c.y0 = y0;
                 c.W = W;
