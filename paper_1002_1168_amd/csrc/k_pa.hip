@@ -1523,6 +1523,9 @@ struct RowWin {
     __device__ __forceinline__ void issue(const uint8_t *P, int st, int W, int H, int x0, int y0, int S, int pitch,
                                           int rows, bool shape_) {
         shape = uni(shape_ ? 1 : 0);
+        // the plane in scalar registers: each load is a 32-bit lane offset
+        // from a scalar base (one add per element)
+        const uint8_t *const Pu = (const uint8_t *)(uintptr_t)uni64((unsigned long long)(uintptr_t)P);
         const int dw = pitch >> 2, g = 64 / dw;
         const int l = lane() % (g * dw), c = l % dw, r0 = l / dw;
         const int xx = x0 - S - 1 + 4 * c;
@@ -1533,16 +1536,16 @@ struct RowWin {
         const int wy0 = y0 - S - 1;
         if (wy0 >= 0 && wy0 + rows <= H) {  // no row clamp (wave-uniform)
             const uint32_t o0 = (uint32_t)(wy0 + r0) * (uint32_t)st + (uint32_t)xc;
-            const uint32_t gst = (uint32_t)(g * st);
+            const uint32_t gst = (uint32_t)uni(g * st);
 #pragma unroll
-            for (int u = 0; u < EM - 1; ++u) v[u] = ld4(P + (o0 + (uint32_t)u * gst));
+            for (int u = 0; u < EM - 1; ++u) v[u] = ld4(Pu + (size_t)(o0 + (uint32_t)u * gst));
             const int rl = min(r0 + (EM - 1) * g, rows - 1);
-            v[EM - 1] = ld4(P + ((uint32_t)(wy0 + rl) * (uint32_t)st + (uint32_t)xc));
+            v[EM - 1] = ld4(Pu + (size_t)((uint32_t)(wy0 + rl) * (uint32_t)st + (uint32_t)xc));
         } else {
 #pragma unroll
             for (int u = 0; u < EM; ++u) {
                 const int r = min(r0 + u * g, rows - 1);
-                v[u] = ld4(P + ((uint32_t)iclamp(wy0 + r, 0, H - 1) * (uint32_t)st + (uint32_t)xc));
+                v[u] = ld4(Pu + (size_t)((uint32_t)iclamp(wy0 + r, 0, H - 1) * (uint32_t)st + (uint32_t)xc));
             }
         }
     }
