@@ -11,20 +11,45 @@ namespace me {
 namespace {
 
 constexpr int kEsThreads = 256;
-constexpr int kEsG = 8;  // candidate rows per thread task (register blocking)
 
-// ES window geometry: rows and columns 16 + 2S, row pitch a power of two
-// (>= (16+2S+3)/4 dwords) so staging needs no divisions, and each of the four
-// byte-shifted copies padded to 8 mod 32 dwords so that the four copies of a
-// dword fall on four different LDS banks.
+// A thread task of ES is one column offset dx and G consecutive row offsets
+// dy (register blocking: every reference row read feeds up to G candidate
+// SADs).  G is picked per range so that the (2S+1) x ceil((2S+1)/G) tasks
+// fill the 256 threads with the fewest SAD instructions per thread: rounds
+// of 256 tasks times G, ties to the larger G (fewer LDS reads per SAD).
+__host__ __device__ inline int es_group(int S) {
+    const int ncol = 2 * S + 1;
+    int best = 4, cost = 1 << 30;
+    for (int G = 4; G <= 8; ++G) {
+        if (G == 7) continue;  // not instantiated
+        const int tasks = ncol * ((ncol + G - 1) / G);
+        const int c = ((tasks + kEsThreads - 1) / kEsThreads) * G;
+        if (c <= cost) {
+            cost = c;
+            best = G;
+        }
+    }
+    return best;
+}
+
+// ES window geometry: 16 + 2S columns; rows 16 + 2S plus padding up to the
+// last row any task reads (ceil((2S+1)/G) G + 15), so the unrolled row loop
+// needs no bounds test (padding rows are never part of a kept candidate);
+// row pitch a power of two (>= (16+2S+3)/4 dwords) so staging needs no
+// divisions, and each of the four byte-shifted copies padded to 8 mod 32
+// dwords so that the four copies of a dword fall on four different LDS banks.
 __host__ __device__ inline int es_pitch_log2(int S) {
     const int need = (16 + 2 * S + 3) >> 2;
     int lg = 0;
     while ((1 << lg) < need) ++lg;
     return lg;
 }
+__host__ __device__ inline int es_rows(int S) {
+    const int ncol = 2 * S + 1, G = es_group(S);
+    return max(16 + 2 * S, ((ncol + G - 1) / G) * G + 15);
+}
 __host__ __device__ inline int es_copy_dwords(int S) {
-    const int raw = (16 + 2 * S) << es_pitch_log2(S);
+    const int raw = es_rows(S) << es_pitch_log2(S);
     return raw + ((8 - raw % 32) + 32) % 32;
 }
 
@@ -39,10 +64,10 @@ __device__ __forceinline__ void write_result(const JobDesc &J, int k, int dx, in
 
 // ES.  One workgroup per MB.  The (16+2S)^2 reference window is staged in LDS
 // as four byte-shifted copies so that a 16-byte row segment at any column is
-// four aligned dword reads.  A thread owns one column offset dx and kEsG
-// consecutive dy: every reference row it reads feeds up to kEsG candidate
-// SADs (v_sad_u8 on packed bytes), with the current block held in registers.
-// Key = (SAD, |dx|+|dy|, dy, dx) lexicographic, packed into 64 bits.
+// four aligned dword reads.  A thread owns one column offset dx and G
+// consecutive dy (es_group): every reference row it reads feeds up to G
+// candidate SADs (v_sad_u8 on packed bytes), with the current block held in
+// registers.  Key = (SAD, |dx|+|dy|, dy, dx) lexicographic, packed into 64 bits.
 // Compaction: one lane per MB.  Transparent MBs get their (zero) result at
 // once; the others are appended to `list` as (job << 16 | MB index).  A class
 // byte above 2 raises ST_BAD_CLASS and the MB is treated as transparent (as
@@ -74,12 +99,47 @@ __global__ __launch_bounds__(256) void compact_kernel(const JobDesc *jobs, int n
     }
 }
 
+// PF = window dwords of copy 0 per thread (span * pitch / 256, rounded up)
+// prefetched for the next MB during the current one's search; 0: loaded
+// when the MB starts.  Instantiated for S = 7, 16 and 32.
+__host__ __device__ inline int es_prefetch(int S) {
+    const int per = (16 + 2 * S) << es_pitch_log2(S);
+    return (per + kEsThreads - 1) / kEsThreads;
+}
+
+template <int G, int PF>
 __global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, const uint32_t *list,
                                                        const uint32_t *count, KParams kp) {
     extern __shared__ uint32_t lds[];
     const int tid = threadIdx.x;
     const int S = kp.S;
     const int nitems = (int)*count;
+    const int span = 16 + 2 * S;      // window rows and columns
+    const int lgp = es_pitch_log2(S);
+    const int pd = 1 << lgp;          // dwords per row per copy
+    const int csz = es_copy_dwords(S);
+    const int per = span << lgp;
+    constexpr bool pf = PF > 0;
+    constexpr int kEsPf = PF > 0 ? PF : 1;
+    // copy 0 of list entry `item`'s window (rows and columns clamped, edge
+    // dwords permuted: the frame extended by its edge pixels, which
+    // unrestricted vectors read): dword idx = u * 256 + tid into nv[u]
+    uint32_t nv[kEsPf];
+    auto fetch = [&](int item) {
+        const uint32_t en = list[item];
+        const JobDesc &Jn = jobs[en >> 16];
+        const int kn = (int)(en & 0xFFFF);
+        const int wxn = 16 * (kn % Jn.wm) - S, wyn = 16 * (kn / Jn.wm) - S;
+#pragma unroll
+        for (int u = 0; u < kEsPf; ++u) {
+            const int idx = min(u * kEsThreads + tid, per - 1);
+            const int r = idx >> lgp, w = idx & (pd - 1);
+            nv[u] = ld4_clamped(Jn.ref + (size_t)iclamp(wyn + r, 0, Jn.height - 1) * Jn.stride, wxn + 4 * w,
+                                Jn.width);
+        }
+    };
+    if constexpr (pf)
+        if ((int)blockIdx.x < nitems) fetch(blockIdx.x);
     // every searched MB costs the same: static striding, no shared counter
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     __syncthreads();  // the previous MB's readers are done with the window
@@ -88,30 +148,30 @@ __global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, con
     const int k = (int)(e & 0xFFFF);
     const int h = k % J.wm, v = k / J.wm;
     const int x0 = 16 * h, y0 = 16 * v, W = J.width, H = J.height, st = J.stride;
-    const int span = 16 + 2 * S;      // window rows and columns
-    const int lgp = es_pitch_log2(S);
-    const int pd = 1 << lgp;          // dwords per row per copy
-    const int csz = es_copy_dwords(S);
     uint32_t *win = lds;              // 4 copies
     uint32_t *curb = lds + 4 * csz;   // 64 dwords
     unsigned long long *red = (unsigned long long *)(curb + 64);  // 4 wave minima
-    // copy 0 from the frame (rows clamped, edge dwords permuted: the frame
-    // extended by its edge pixels, which unrestricted vectors read), eight loads in
-    // flight per thread; copy s dword w = window bytes 4w+s .. 4w+s+3 is then
-    // built from copy 0 in LDS
-    const int wx0 = x0 - S, wy0 = y0 - S;
-    const int per = span << lgp;
-    for (int base = 0; base < per; base += 8 * kEsThreads) {
-        uint32_t v[8];
+    // copy 0 (prefetched, or loaded here for large windows, eight loads in
+    // flight per thread); copy s dword w = window bytes 4w+s .. 4w+s+3 is
+    // then built from copy 0 in LDS
+    if constexpr (pf) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int idx = min(base + u * kEsThreads + tid, per - 1);
-            const int r = idx >> lgp, w = idx & (pd - 1);
-            v[u] = ld4_clamped(J.ref + (size_t)iclamp(wy0 + r, 0, H - 1) * st, wx0 + 4 * w, W);
+        for (int u = 0; u < kEsPf; ++u)
+            if (u * kEsThreads + tid < per) win[u * kEsThreads + tid] = nv[u];
+    } else {
+        const int wx0 = x0 - S, wy0 = y0 - S;
+        for (int base = 0; base < per; base += 8 * kEsThreads) {
+            uint32_t v8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = min(base + u * kEsThreads + tid, per - 1);
+                const int r = idx >> lgp, w = idx & (pd - 1);
+                v8[u] = ld4_clamped(J.ref + (size_t)iclamp(wy0 + r, 0, H - 1) * st, wx0 + 4 * w, W);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (base + u * kEsThreads + tid < per) win[base + u * kEsThreads + tid] = v8[u];
         }
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (base + u * kEsThreads + tid < per) win[base + u * kEsThreads + tid] = v[u];
     }
     __syncthreads();
     for (int idx = tid; idx < per; idx += kEsThreads) {
@@ -125,51 +185,54 @@ __global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, con
     uint32_t cr[64];
 #pragma unroll
     for (int i = 0; i < 64; ++i) cr[i] = curb[i];
+    // the next MB's window loads, in flight during this search
+    if constexpr (pf)
+        if (it + (int)gridDim.x < nitems) fetch(it + gridDim.x);
 
     const int lox = kp.unrestricted ? -S : max(-S, -x0), hix = kp.unrestricted ? S : min(S, W - 16 - x0);
     const int loy = kp.unrestricted ? -S : max(-S, -y0), hiy = kp.unrestricted ? S : min(S, H - 16 - y0);
     const int ncol = 2 * S + 1;
-    const int ngrp = (ncol + kEsG - 1) / kEsG;
+    const int ngrp = (ncol + G - 1) / G;
+    // key = (SAD, |dx| + |dy|, dy + S, dx + S) in lexicographic order: the
+    // first three fields in 32 bits per task (dx is the task's), then dx
     unsigned long long best = ~0ull;
     for (int task = tid; task < ncol * ngrp; task += kEsThreads) {
-        const int cxr = task % ncol;       // dx + S
-        const int dy0 = (task / ncol) * kEsG;  // first dy + S
+        const int cxr = task % ncol;           // dx + S
+        const int dy0 = (task / ncol) * G;     // first dy + S
         const int dx = cxr - S;
         if (dx < lox || dx > hix) continue;
         const uint32_t *cp = win + (cxr & 3) * csz + (cxr >> 2);
-        uint32_t acc[kEsG];
+        uint32_t acc[G];
 #pragma unroll
-        for (int g = 0; g < kEsG; ++g) acc[g] = 0;
+        for (int g = 0; g < G; ++g) acc[g] = 0;
 #pragma unroll
-        for (int r = 0; r < kEsG + 15; ++r) {
-            const int wr = dy0 + r;
-            if (wr < span) {
-                const uint32_t *rp = cp + wr * pd;
-                uint32_t r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
+        for (int r = 0; r < G + 15; ++r) {
+            // rows past the window are padding: read, never kept
+            const uint32_t *rp = cp + (dy0 + r) * pd;
+            const uint32_t r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
 #pragma unroll
-                for (int g = 0; g < kEsG; ++g) {
-                    const int jj = r - g;
-                    if (jj >= 0 && jj < 16) {
-                        uint32_t a = acc[g];
-                        a = __builtin_amdgcn_sad_u8(cr[4 * jj + 0], r0, a);
-                        a = __builtin_amdgcn_sad_u8(cr[4 * jj + 1], r1, a);
-                        a = __builtin_amdgcn_sad_u8(cr[4 * jj + 2], r2, a);
-                        a = __builtin_amdgcn_sad_u8(cr[4 * jj + 3], r3, a);
-                        acc[g] = a;
-                    }
+            for (int g = 0; g < G; ++g) {
+                const int jj = r - g;
+                if (jj >= 0 && jj < 16) {
+                    uint32_t a = acc[g];
+                    a = __builtin_amdgcn_sad_u8(cr[4 * jj + 0], r0, a);
+                    a = __builtin_amdgcn_sad_u8(cr[4 * jj + 1], r1, a);
+                    a = __builtin_amdgcn_sad_u8(cr[4 * jj + 2], r2, a);
+                    a = __builtin_amdgcn_sad_u8(cr[4 * jj + 3], r3, a);
+                    acc[g] = a;
                 }
             }
         }
+        const int adx = abs(dx);
+        uint32_t kb = ~0u;
 #pragma unroll
-        for (int g = 0; g < kEsG; ++g) {
-            const int dy = dy0 + g - S;
-            if (dy0 + g < ncol && dy >= loy && dy <= hiy) {
-                unsigned long long key = ((unsigned long long)acc[g] << 32) |
-                                         ((unsigned long long)(abs(dx) + abs(dy)) << 16) |
-                                         ((unsigned long long)(dy + S) << 8) | (unsigned long long)(dx + S);
-                best = key < best ? key : best;
-            }
+        for (int g = 0; g < G; ++g) {
+            const int dys = dy0 + g, dy = dys - S;
+            const uint32_t key = (acc[g] << 16) | ((uint32_t)(adx + abs(dy)) << 8) | (uint32_t)dys;
+            kb = (dys < ncol && dy >= loy && dy <= hiy && key < kb) ? key : kb;
         }
+        const unsigned long long k64 = ((unsigned long long)kb << 8) | (unsigned long long)cxr;
+        best = kb != ~0u && k64 < best ? k64 : best;
     }
     best = wave_min_u64(best);
     if (lane() == 0) red[tid >> 6] = best;
@@ -177,9 +240,9 @@ __global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, con
     if (tid == 0) {
         unsigned long long b = red[0];
         for (int w = 1; w < kEsThreads / 64; ++w) b = red[w] < b ? red[w] : b;
-        int dx = (int)(b & 0xFF) - S, dy = (int)((b >> 8) & 0xFF) - S;
-        int pts = (hix - lox + 1) * (hiy - loy + 1);
-        write_result(J, k, dx, dy, (uint32_t)(b >> 32), pts);
+        const int dx = (int)(b & 0xFF) - S, dy = (int)((b >> 8) & 0xFF) - S;
+        const int pts = (hix - lox + 1) * (hiy - loy + 1);
+        write_result(J, k, dx, dy, (uint32_t)(b >> 24), pts);
     }
     }
 }
@@ -415,7 +478,17 @@ hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_
     if (method == ME_ES) {
         size_t lds = es_lds_bytes(kp.S);
         int blocks = std::min(total_mbs, cus * 8);
-        hipLaunchKernelGGL(es_kernel, dim3(blocks), dim3(kEsThreads), lds, s, jobs, list, counters, kp);
+        const int G = es_group(kp.S), PF = es_prefetch(kp.S);
+#define ME_ES_LAUNCH(g, pf) \
+    hipLaunchKernelGGL((es_kernel<g, pf>), dim3(blocks), dim3(kEsThreads), lds, s, jobs, list, counters, kp)
+        if (G == 4 && PF == 1) ME_ES_LAUNCH(4, 1);        // S = 7
+        else if (G == 5 && PF == 3) ME_ES_LAUNCH(5, 3);   // S = 16
+        else if (G == 6 && PF == 10) ME_ES_LAUNCH(6, 10); // S = 32
+        else if (G == 4) ME_ES_LAUNCH(4, 0);
+        else if (G == 5) ME_ES_LAUNCH(5, 0);
+        else if (G == 6) ME_ES_LAUNCH(6, 0);
+        else ME_ES_LAUNCH(8, 0);
+#undef ME_ES_LAUNCH
     } else {
         int blocks = std::min(total_mbs, cus * 16);
         hipLaunchKernelGGL(tss_ds_kernel, dim3(blocks), dim3(64), 0, s, jobs, list, counters, kp, method);
