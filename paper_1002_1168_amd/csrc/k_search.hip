@@ -124,12 +124,15 @@ __global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, con
     // copy 0 of list entry `item`'s window (rows and columns clamped, edge
     // dwords permuted: the frame extended by its edge pixels, which
     // unrestricted vectors read): dword idx = u * 256 + tid into nv[u]
-    uint32_t nv[kEsPf];
+    uint32_t nv[kEsPf], ncur = 0u;
     auto fetch = [&](int item) {
         const uint32_t en = list[item];
         const JobDesc &Jn = jobs[en >> 16];
         const int kn = (int)(en & 0xFFFF);
         const int wxn = 16 * (kn % Jn.wm) - S, wyn = 16 * (kn / Jn.wm) - S;
+        // the current block: row tid / 4, dword tid % 4 (threads 0 .. 63)
+        if (tid < 64)
+            ncur = *(const uint32_t *)(Jn.cur + (size_t)(wyn + S + (tid >> 2)) * Jn.stride + wxn + S + 4 * (tid & 3));
 #pragma unroll
         for (int u = 0; u < kEsPf; ++u) {
             const int idx = min(u * kEsThreads + tid, per - 1);
@@ -155,9 +158,22 @@ __global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, con
     // flight per thread); copy s dword w = window bytes 4w+s .. 4w+s+3 is
     // then built from copy 0 in LDS
     if constexpr (pf) {
+        // all four copies from the registers: dword idx + 1 is the next
+        // lane's (a wave's 64 dwords are whole rows, pd dividing 64, and the
+        // dword after a row's last one is 0)
 #pragma unroll
-        for (int u = 0; u < kEsPf; ++u)
-            if (u * kEsThreads + tid < per) win[u * kEsThreads + tid] = nv[u];
+        for (int u = 0; u < kEsPf; ++u) {
+            const int idx = u * kEsThreads + tid;
+            const uint32_t a = nv[u];
+            const uint32_t nb = (uint32_t)__shfl((int)a, (lane() + 1) & 63, 64);
+            const uint32_t b = (idx & (pd - 1)) + 1 < pd ? nb : 0u;
+            if (idx < per) {
+                win[idx] = a;
+                win[csz + idx] = __builtin_amdgcn_alignbyte(b, a, 1);
+                win[2 * csz + idx] = __builtin_amdgcn_alignbyte(b, a, 2);
+                win[3 * csz + idx] = __builtin_amdgcn_alignbyte(b, a, 3);
+            }
+        }
     } else {
         const int wx0 = x0 - S, wy0 = y0 - S;
         for (int base = 0; base < per; base += 8 * kEsThreads) {
@@ -173,14 +189,21 @@ __global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, con
                 if (base + u * kEsThreads + tid < per) win[base + u * kEsThreads + tid] = v8[u];
         }
     }
-    __syncthreads();
-    for (int idx = tid; idx < per; idx += kEsThreads) {
-        const uint32_t a = win[idx], b = (idx & (pd - 1)) + 1 < pd ? win[idx + 1] : 0u;
-        win[csz + idx] = __builtin_amdgcn_alignbyte(b, a, 1);
-        win[2 * csz + idx] = __builtin_amdgcn_alignbyte(b, a, 2);
-        win[3 * csz + idx] = __builtin_amdgcn_alignbyte(b, a, 3);
+    if constexpr (!pf) {
+        __syncthreads();
+        for (int idx = tid; idx < per; idx += kEsThreads) {
+            const uint32_t a = win[idx], b = (idx & (pd - 1)) + 1 < pd ? win[idx + 1] : 0u;
+            win[csz + idx] = __builtin_amdgcn_alignbyte(b, a, 1);
+            win[2 * csz + idx] = __builtin_amdgcn_alignbyte(b, a, 2);
+            win[3 * csz + idx] = __builtin_amdgcn_alignbyte(b, a, 3);
+        }
     }
-    if (tid < 64) curb[tid] = *(const uint32_t *)(J.cur + (size_t)(y0 + (tid >> 2)) * st + x0 + 4 * (tid & 3));
+    if (tid < 64) {
+        if constexpr (pf)
+            curb[tid] = ncur;
+        else
+            curb[tid] = *(const uint32_t *)(J.cur + (size_t)(y0 + (tid >> 2)) * st + x0 + 4 * (tid & 3));
+    }
     __syncthreads();
     uint32_t cr[64];
 #pragma unroll
