@@ -261,7 +261,7 @@ int run_pa(const me_job *jobs, int n, const me_params *params, bool shape_only, 
         return hip_err(launch_pa_rows((const JobDesc *)(base + m.o_jobs), (const ChainDesc *)(base + m.o_ch),
                                       (const uint32_t *)(base + m.o_bands), m.nbands,
                                       (unsigned long long *)(zb + o_prog), (uint32_t *)(zb + o_ctr), w->status, kp,
-                                      pa_rows_cap(kp.S), w->stream, timer_for(*w, A_PA, &kt) ? &kt : nullptr));
+                                      pa_rows_cap(kp.S, kp.half_pel != 0), w->stream, timer_for(*w, A_PA, &kt) ? &kt : nullptr));
     }
     // the several-wave line worker scores every candidate on the MB's own
     // plane; T on texture takes the one-wave worker

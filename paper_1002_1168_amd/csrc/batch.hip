@@ -238,7 +238,7 @@ int autotune(me_batch &b) {
     float best_ms = -1.f;
     // row workers (job sets without chains in the call): workgroups cap, cap/2
     if (b.plan.unchained && !(b.params.flags & ME_FLAG_LINE_WORKERS)) {
-        const int cap = std::min(b.plan.nbands, pa_rows_cap(b.params.search_range));
+        const int cap = std::min(b.plan.nbands, pa_rows_cap(b.params.search_range, b.params.half_pel != 0));
         std::vector<int> workers = {cap};
         if (cap / 2 >= 64) workers.push_back(cap / 2);
         for (int w : workers)
@@ -530,7 +530,7 @@ int me_batch_create(const me_job *jobs, int n, const me_params *params, uint32_t
     const size_t table = sizeof(JobDesc) * (size_t)n;
     b->cfg[5] = m.unchained && !(params->flags & ME_FLAG_LINE_WORKERS) ? 1 : 0;
     b->cfg[4] = b->cfg[5] ? kRowWaves : (params->flags & ME_FLAG_T_TEXTURE) ? 1 : lines_waves(m.nlines);
-    b->cfg[0] = b->cfg[5] ? std::min(m.nbands, pa_rows_cap(params->search_range))
+    b->cfg[0] = b->cfg[5] ? std::min(m.nbands, pa_rows_cap(params->search_range, params->half_pel != 0))
                           : std::min(m.nlines, pa_worker_cap() / b->cfg[4]);
     b->cfg[1] = plan_elems(params->search_range) > 0 ? 1 : 0;
     b->cfg[2] = b->cfg[4] > 1 && !b->cfg[5] ? 1 : 2;
@@ -664,7 +664,7 @@ int me_batch_set_config(me_batch *b, const int32_t *cfg, int ncfg) {
         // row workers: job sets without chains in the call; persistent
         // workgroups of kRowWaves rows, up to the resident count
         if (!b->plan.unchained || waves != kRowWaves) return ME_EINVAL;
-        if (cfg[0] < 1 || cfg[0] > std::min(b->plan.nbands, pa_rows_cap(b->params.search_range))) return ME_EINVAL;
+        if (cfg[0] < 1 || cfg[0] > std::min(b->plan.nbands, pa_rows_cap(b->params.search_range, b->params.half_pel != 0))) return ME_EINVAL;
     } else {
         if (waves != 1 && waves != 2 && waves != 4) return ME_EINVAL;
         if (waves > 1 && (b->params.flags & ME_FLAG_T_TEXTURE)) return ME_EINVAL;

@@ -468,7 +468,8 @@ struct MbOut {
 // Fig. 1 after the candidates are known: the admissible distinct list in the
 // order A, B, C, T, its first minimum, the recursion (from a learned seed
 // with the 5 % fallback when the job carries seeds), half-sample refinement.
-__device__ MbOut search_mb(const uint32_t *seed, const Ctx &c, int k, int (&cx)[4], int (&cy)[4], const KParams &kp) {
+__device__ MbOut search_mb(const uint32_t *seed, const Ctx &c, int k, int (&cx)[4], int (&cy)[4], const KParams &kp,
+                           bool half = true) {
     // the candidates are the same in every lane: in scalar registers, and
     // the list (admissible, distinct, in order) as a bit mask
 #pragma unroll
@@ -569,7 +570,7 @@ __device__ MbOut search_mb(const uint32_t *seed, const Ctx &c, int k, int (&cx)[
         pts += it1;
     }
     int hx = 2 * dx, hy = 2 * dy;
-    if (kp.half_pel && !c.shape) pts += half_refine(c, kp, dx, dy, hx, hy, dc);
+    if (half && kp.half_pel && !c.shape) pts += half_refine(c, kp, dx, dy, hx, hy, dc);
     MbOut o;
     o.mv = pack_mv(hx, hy);
     o.mvi = pack_mv(2 * dx, 2 * dy);
@@ -1588,7 +1589,11 @@ __device__ __forceinline__ int next_set(const unsigned long long (&m)[4], int fr
 
 __device__ __forceinline__ bool bit_of(const unsigned long long (&m)[4], int h) { return (m[h >> 6] >> (h & 63)) & 1ull; }
 
-template <int EM, int NR>
+// DB: two windows per wave, and each MB's half-sample step one MB late (it
+// does not feed any neighbour): the next MB's block-recursive and
+// pel-recursive steps, which do, are not held up by it, and a row waiting
+// for the row above runs it in that wait.
+template <int EM, int NR, bool DB>
 __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
     extern __shared__ uint32_t lds[];
     __shared__ int slot;
@@ -1599,7 +1604,7 @@ __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
     short *R = (short *)lds;              // 511 reciprocal entries (Eq. 4-5, Q.12)
     const int wv = threadIdx.x >> 6;
     const int wwords = ((a.rows * a.pitch + 16) >> 2) + 4;
-    uint32_t *const win = lds + 256 + wv * wwords;
+    uint32_t *const win0 = lds + 256 + wv * (DB ? 2 : 1) * wwords;
     const KParams kp = a.kp;
     for (int g = threadIdx.x; g < 511; g += 64 * NR) {
         const int m = abs(g - 255);
@@ -1705,10 +1710,18 @@ __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
             bool pend = false;
             int pk = 0, piters = 0, ppoints = 0;
             uint32_t pmv = 0u, pmvi = 0u, pcost = 0u;
+            // DB: the previous MB's half-sample step is still to do (its
+            // window is the other buffer, its pixels pc4, position px0, py0,
+            // full-pel vector pdx, pdy)
+            bool phalf = false;
+            int px0 = 0, py0 = 0, pdx = 0, pdy = 0;
+            uint32_t pc4 = 0u;
+            int cb = 0;  // DB: the buffer of this MB's window
             unsigned long long wseen = 0ull;  // the latest row word seen (first row of a band)
             while (h < wm) {
                 const int k = v * wm + h;
                 const int x0 = 16 * h, y0 = 16 * v;
+                uint32_t *const win = win0 + (DB ? cb * wwords : 0);
                 Ctx c;
                 c.shape = bit_of(bnd, h);
                 if constexpr (EM > 0) {
@@ -1716,6 +1729,26 @@ __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
                 } else {
                     const uint8_t *Pr = c.shape ? D.ptr<const uint8_t>(DW(ref_a)) : D.ptr<const uint8_t>(DW(ref));
                     stage_window(win, a.pitch, a.rows, Pr, st, W, H, x0, y0, S, c.shape);
+                }
+                if constexpr (DB) {
+                    // the previous MB's half-sample step, from its window in the other buffer
+                    if (phalf) {
+                        Ctx cp;
+                        cp.win = win0 + (cb ^ 1) * wwords;
+                        cp.pitch = a.pitch;
+                        cp.S = S;
+                        set_lane_base(cp, (j + S + 1) * a.pitch + 4 * q + S + 1, S);
+                        cp.x0 = px0;
+                        cp.y0 = py0;
+                        cp.W = W;
+                        cp.H = H;
+                        cp.c4 = pc4;
+                        cp.shape = false;
+                        int hx = 2 * pdx, hy = 2 * pdy, hc = (int)pcost;
+                        ppoints += half_refine(cp, kp, pdx, pdy, hx, hy, hc);
+                        pmv = pack_mv(hx, hy);
+                        pcost = (uint32_t)hc;
+                    }
                 }
                 const uint32_t cur4 = ncur, tv = nt;
                 const int h2 = next_set(srch, h + 1, wm);
@@ -1802,7 +1835,7 @@ __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
                 // window writes visible to every lane: one wave, so completing
                 // its LDS writes (and a compiler fence) suffices
                 asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-                const MbOut o = search_mb(seed, c, k, cx, cy, kp);
+                const MbOut o = search_mb(seed, c, k, cx, cy, kp, !DB);
                 const uint32_t ovi = (uint32_t)uni((int)o.mvi);
                 if (l == 0) {
                     vvec[wv * 256 + h] = ovi;
@@ -1822,9 +1855,38 @@ __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
                 pcost = (uint32_t)uni((int)o.cost);
                 piters = uni(o.iters);
                 ppoints = uni(o.points);
+                if constexpr (DB) {
+                    phalf = kp.half_pel && !c.shape;
+                    px0 = x0;
+                    py0 = y0;
+                    pdx = uni(o.dx);
+                    pdy = uni(o.dy);
+                    pc4 = c.c4;
+                    cb ^= 1;
+                }
                 lastv = ovi;
                 lasth = h;
                 h = h2;
+            }
+            if constexpr (DB) {
+                // the row's last MB: its half-sample step
+                if (pend && phalf && !aborted) {
+                    Ctx cp;
+                    cp.win = win0 + (cb ^ 1) * wwords;
+                    cp.pitch = a.pitch;
+                    cp.S = S;
+                    set_lane_base(cp, (j + S + 1) * a.pitch + 4 * q + S + 1, S);
+                    cp.x0 = px0;
+                    cp.y0 = py0;
+                    cp.W = W;
+                    cp.H = H;
+                    cp.c4 = pc4;
+                    cp.shape = false;
+                    int hx = 2 * pdx, hy = 2 * pdy, hc = (int)pcost;
+                    ppoints += half_refine(cp, kp, pdx, pdy, hx, hy, hc);
+                    pmv = pack_mv(hx, hy);
+                    pcost = (uint32_t)hc;
+                }
             }
             // the row's last results, then (band-last row) a final word once
             // every store has completed
@@ -1877,19 +1939,31 @@ size_t pa2_lds_bytes(int S, int waves) {
     return 1024 + (size_t)waves * ((size_t)(((rows * pitch + 16) >> 2) + 4) * 4);
 }
 
-size_t pr_lds_bytes(int S) {
+size_t pr_lds_bytes(int S, bool dbl) {
     const int rows = 2 * S + 18, pitch = (rows + 3) & ~3;
-    return 1024 + (size_t)kRowWaves * ((size_t)(((rows * pitch + 16) >> 2) + 4) * 4);
+    return 1024 + (size_t)kRowWaves * (dbl ? 2 : 1) * ((size_t)(((rows * pitch + 16) >> 2) + 4) * 4);
 }
 
-int pa_rows_cap(int S) {
+// Two windows per wave (the half-sample step one MB late) when half-sample
+// refinement is on and the workgroup's LDS still fits.
+bool pr_double(int S, bool half_pel) {
+    if (!half_pel) return false;
+    int dev = 0, lim = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lim <= 0)
+        lim = 64 * 1024;
+    return pr_lds_bytes(S, true) + kRowWaves * 256 * 4 + 64 <= (size_t)lim;
+}
+
+int pa_rows_cap(int S, bool half_pel) {
     int dev = 0, cus = 0, lds = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
         lds <= 0)
         lds = 160 * 1024;
-    const size_t per = pr_lds_bytes(S) + kRowWaves * 256 * 4 + 64;  // dynamic + static LDS of one workgroup
+    // dynamic + static LDS of one workgroup
+    const size_t per = pr_lds_bytes(S, pr_double(S, half_pel)) + kRowWaves * 256 * 4 + 64;
     const int fit = (int)std::max<size_t>(1, (size_t)lds / per);
     return cus * std::min(fit, 8);
 }
@@ -1900,16 +1974,25 @@ hipError_t launch_pa_rows(const JobDesc *jobs, const ChainDesc *chains, const ui
     if (nbands <= 0) return hipSuccess;
     const int rows = 2 * kp.S + 18;
     PrArgs a{jobs, chains, bands, nbands, progress, counter, status, kp, (rows + 3) & ~3, rows};
-    const size_t lds = pr_lds_bytes(kp.S);
+    const bool dbl = pr_double(kp.S, kp.half_pel != 0);
+    const size_t lds = pr_lds_bytes(kp.S, dbl);
     const dim3 blk(64 * kRowWaves);
     workers = std::max(1, std::min(workers, nbands));
     timer_mark(t, true, s);
+#define ME_PR_LAUNCH(em)                                                                               \
+    do {                                                                                               \
+        if (dbl)                                                                                       \
+            hipLaunchKernelGGL((pr_kernel<em, kRowWaves, true>), dim3(workers), blk, lds, s, a);      \
+        else                                                                                           \
+            hipLaunchKernelGGL((pr_kernel<em, kRowWaves, false>), dim3(workers), blk, lds, s, a);     \
+    } while (0)
     switch (generic ? 0 : row_elems(kp.S)) {
-        case 4: hipLaunchKernelGGL((pr_kernel<4, kRowWaves>), dim3(workers), blk, lds, s, a); break;
-        case 13: hipLaunchKernelGGL((pr_kernel<13, kRowWaves>), dim3(workers), blk, lds, s, a); break;
-        case 28: hipLaunchKernelGGL((pr_kernel<28, kRowWaves>), dim3(workers), blk, lds, s, a); break;
-        default: hipLaunchKernelGGL((pr_kernel<0, kRowWaves>), dim3(workers), blk, lds, s, a); break;
+        case 4: ME_PR_LAUNCH(4); break;
+        case 13: ME_PR_LAUNCH(13); break;
+        case 28: ME_PR_LAUNCH(28); break;
+        default: ME_PR_LAUNCH(0); break;
     }
+#undef ME_PR_LAUNCH
     hipError_t e = hipGetLastError();
     timer_mark(t, false, s);
     return e;

@@ -112,8 +112,9 @@ constexpr int kRowWaves = 4;
 hipError_t launch_pa_rows(const JobDesc *jobs, const ChainDesc *chains, const uint32_t *bands, int nbands,
                           unsigned long long *progress, uint32_t *counter, uint32_t *status, const KParams &kp,
                           int workers, hipStream_t s, const KernelTimer *t = nullptr, bool generic = false);
-// resident row-worker workgroups the device holds for range S
-int pa_rows_cap(int S);
+// resident row-worker workgroups the device holds for range S (with half-sample
+// refinement on, the workers keep two windows each when they fit)
+int pa_rows_cap(int S, bool half_pel);
 
 int pa_worker_cap();
 // Waves per line worker for `nlines` lines: 4 while every line still gets

@@ -90,10 +90,20 @@ def test_pa_one_call_per_pair_matches(torch_cuda):
 # one call per pair: no chain inside a call, so the row workers run (the line
 # workers when forced), T read from the previous call's output
 @pytest.mark.parametrize("flags", [0, me.ME_FLAG_LINE_WORKERS])
-@pytest.mark.parametrize("case", ["qcif", "qcif-rect", "shape", "hd-halfpel", "w4096", "noise", "tiny"])
+@pytest.mark.parametrize("case", ["qcif", "qcif-rect", "shape", "hd-halfpel", "cif-halfpel", "qcif-halfpel",
+                                  "noise-halfpel", "w4096", "noise", "tiny"])
 def test_pa_per_pair_rows_and_lines(torch_cuda, case, flags):
+    # the half-pel cases run the row workers with two windows each (each MB's
+    # half-sample step one MB late) at S = 32, 16 and 7
     if case == "qcif":
         seq, vops, p, P, so = synth.qcif_ellipse(), [0], dict(search_range=7), 5, False
+    elif case == "cif-halfpel":
+        seq, vops, p, P, so = synth.cif_two_vops(frames=5), [0, 1, None], dict(search_range=16, half_pel=1), 4, False
+    elif case == "qcif-halfpel":
+        seq, vops, p, P, so = synth.qcif_ellipse(frames=6), [0, None], dict(search_range=7, half_pel=1), 5, False
+    elif case == "noise-halfpel":
+        seq, vops, p, P, so = synth.random_frames(8, 96, 64, frames=4, vops=1, search_range=7), [0, None], \
+            dict(search_range=7, half_pel=1, k_max=255), 3, False
     elif case == "qcif-rect":
         seq, vops, p, P, so = synth.qcif_ellipse(), [None], dict(search_range=7, k_max=255, max_step=3), 4, False
     elif case == "shape":
