@@ -17,7 +17,7 @@ constexpr int kEsThreads = 256;
 // SADs).  G is picked per range so that the (2S+1) x ceil((2S+1)/G) tasks
 // fill the 256 threads with the fewest SAD instructions per thread: rounds
 // of 256 tasks times G, ties to the larger G (fewer LDS reads per SAD).
-__host__ __device__ inline int es_group(int S) {
+__host__ __device__ constexpr int es_group(int S) {
     const int ncol = 2 * S + 1;
     int best = 4, cost = 1 << 30;
     for (int G = 4; G <= 8; ++G) {
@@ -38,20 +38,28 @@ __host__ __device__ inline int es_group(int S) {
 // row pitch a power of two (>= (16+2S+3)/4 dwords) so staging needs no
 // divisions, and each of the four byte-shifted copies padded to 8 mod 32
 // dwords so that the four copies of a dword fall on four different LDS banks.
-__host__ __device__ inline int es_pitch_log2(int S) {
+__host__ __device__ constexpr int es_pitch_log2(int S) {
     const int need = (16 + 2 * S + 3) >> 2;
     int lg = 0;
     while ((1 << lg) < need) ++lg;
     return lg;
 }
-__host__ __device__ inline int es_rows(int S) {
+__host__ __device__ constexpr int es_rows(int S) {
     const int ncol = 2 * S + 1, G = es_group(S);
-    return max(16 + 2 * S, ((ncol + G - 1) / G) * G + 15);
+    const int reach = ((ncol + G - 1) / G) * G + 15;
+    return 16 + 2 * S > reach ? 16 + 2 * S : reach;
 }
-__host__ __device__ inline int es_copy_dwords(int S) {
+__host__ __device__ constexpr int es_copy_dwords(int S) {
     const int raw = es_rows(S) << es_pitch_log2(S);
     return raw + ((8 - raw % 32) + 32) % 32;
 }
+
+// The ranges with a kernel of their own (geometry fixed at compile time).
+constexpr bool es_fixed(int S) { return S == 7 || S == 16 || S == 32; }
+// Dwords of one window buffer: four copies and the 64-dword current block.
+constexpr int es_buffer_dwords(int S) { return 4 * es_copy_dwords(S) + 64; }
+// Two window buffers (one barrier per MB) where both fit in 32 KB.
+constexpr bool es_double(int S) { return 2 * 4 * es_buffer_dwords(S) <= 32768; }
 
 __device__ __forceinline__ void write_result(const JobDesc &J, int k, int dx, int dy, uint32_t cost, int pts) {
     uint32_t w = (uint32_t)(uint16_t)(2 * dx) | ((uint32_t)(uint16_t)(2 * dy) << 16);
@@ -99,15 +107,9 @@ __global__ __launch_bounds__(256) void compact_kernel(const JobDesc *jobs, int n
     }
 }
 
-// PF = window dwords of copy 0 per thread (span * pitch / 256, rounded up)
-// prefetched for the next MB during the current one's search; 0: loaded
-// when the MB starts.  Instantiated for S = 7, 16 and 32.
-__host__ __device__ inline int es_prefetch(int S) {
-    const int per = (16 + 2 * S) << es_pitch_log2(S);
-    return (per + kEsThreads - 1) / kEsThreads;
-}
-
-template <int G, int PF>
+// Ranges without a kernel of their own: S is a kernel argument, the window
+// is loaded when the MB starts, 64-bit keys.
+template <int G>
 __global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, const uint32_t *list,
                                                        const uint32_t *count, KParams kp) {
     extern __shared__ uint32_t lds[];
@@ -119,30 +121,6 @@ __global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, con
     const int pd = 1 << lgp;          // dwords per row per copy
     const int csz = es_copy_dwords(S);
     const int per = span << lgp;
-    constexpr bool pf = PF > 0;
-    constexpr int kEsPf = PF > 0 ? PF : 1;
-    // copy 0 of list entry `item`'s window (rows and columns clamped, edge
-    // dwords permuted: the frame extended by its edge pixels, which
-    // unrestricted vectors read): dword idx = u * 256 + tid into nv[u]
-    uint32_t nv[kEsPf], ncur = 0u;
-    auto fetch = [&](int item) {
-        const uint32_t en = list[item];
-        const JobDesc &Jn = jobs[en >> 16];
-        const int kn = (int)(en & 0xFFFF);
-        const int wxn = 16 * (kn % Jn.wm) - S, wyn = 16 * (kn / Jn.wm) - S;
-        // the current block: row tid / 4, dword tid % 4 (threads 0 .. 63)
-        if (tid < 64)
-            ncur = *(const uint32_t *)(Jn.cur + (size_t)(wyn + S + (tid >> 2)) * Jn.stride + wxn + S + 4 * (tid & 3));
-#pragma unroll
-        for (int u = 0; u < kEsPf; ++u) {
-            const int idx = min(u * kEsThreads + tid, per - 1);
-            const int r = idx >> lgp, w = idx & (pd - 1);
-            nv[u] = ld4_clamped(Jn.ref + (size_t)iclamp(wyn + r, 0, Jn.height - 1) * Jn.stride, wxn + 4 * w,
-                                Jn.width);
-        }
-    };
-    if constexpr (pf)
-        if ((int)blockIdx.x < nitems) fetch(blockIdx.x);
     // every searched MB costs the same: static striding, no shared counter
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     __syncthreads();  // the previous MB's readers are done with the window
@@ -154,63 +132,35 @@ __global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, con
     uint32_t *win = lds;              // 4 copies
     uint32_t *curb = lds + 4 * csz;   // 64 dwords
     unsigned long long *red = (unsigned long long *)(curb + 64);  // 4 wave minima
-    // copy 0 (prefetched, or loaded here for large windows, eight loads in
-    // flight per thread); copy s dword w = window bytes 4w+s .. 4w+s+3 is
-    // then built from copy 0 in LDS
-    if constexpr (pf) {
-        // all four copies from the registers: dword idx + 1 is the next
-        // lane's (a wave's 64 dwords are whole rows, pd dividing 64, and the
-        // dword after a row's last one is 0)
+    // copy 0 (rows and columns clamped, edge dwords permuted: the frame
+    // extended by its edge pixels, which unrestricted vectors read), eight
+    // loads in flight per thread; copy s dword w = window bytes 4w+s ..
+    // 4w+s+3 is then built from copy 0 in LDS
+    const int wx0 = x0 - S, wy0 = y0 - S;
+    for (int base = 0; base < per; base += 8 * kEsThreads) {
+        uint32_t v8[8];
 #pragma unroll
-        for (int u = 0; u < kEsPf; ++u) {
-            const int idx = u * kEsThreads + tid;
-            const uint32_t a = nv[u];
-            const uint32_t nb = (uint32_t)__shfl((int)a, (lane() + 1) & 63, 64);
-            const uint32_t b = (idx & (pd - 1)) + 1 < pd ? nb : 0u;
-            if (idx < per) {
-                win[idx] = a;
-                win[csz + idx] = __builtin_amdgcn_alignbyte(b, a, 1);
-                win[2 * csz + idx] = __builtin_amdgcn_alignbyte(b, a, 2);
-                win[3 * csz + idx] = __builtin_amdgcn_alignbyte(b, a, 3);
-            }
+        for (int u = 0; u < 8; ++u) {
+            const int idx = min(base + u * kEsThreads + tid, per - 1);
+            const int r = idx >> lgp, w = idx & (pd - 1);
+            v8[u] = ld4_clamped(J.ref + (size_t)iclamp(wy0 + r, 0, H - 1) * st, wx0 + 4 * w, W);
         }
-    } else {
-        const int wx0 = x0 - S, wy0 = y0 - S;
-        for (int base = 0; base < per; base += 8 * kEsThreads) {
-            uint32_t v8[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int idx = min(base + u * kEsThreads + tid, per - 1);
-                const int r = idx >> lgp, w = idx & (pd - 1);
-                v8[u] = ld4_clamped(J.ref + (size_t)iclamp(wy0 + r, 0, H - 1) * st, wx0 + 4 * w, W);
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (base + u * kEsThreads + tid < per) win[base + u * kEsThreads + tid] = v8[u];
-        }
+        for (int u = 0; u < 8; ++u)
+            if (base + u * kEsThreads + tid < per) win[base + u * kEsThreads + tid] = v8[u];
     }
-    if constexpr (!pf) {
-        __syncthreads();
-        for (int idx = tid; idx < per; idx += kEsThreads) {
-            const uint32_t a = win[idx], b = (idx & (pd - 1)) + 1 < pd ? win[idx + 1] : 0u;
-            win[csz + idx] = __builtin_amdgcn_alignbyte(b, a, 1);
-            win[2 * csz + idx] = __builtin_amdgcn_alignbyte(b, a, 2);
-            win[3 * csz + idx] = __builtin_amdgcn_alignbyte(b, a, 3);
-        }
+    __syncthreads();
+    for (int idx = tid; idx < per; idx += kEsThreads) {
+        const uint32_t a = win[idx], b = (idx & (pd - 1)) + 1 < pd ? win[idx + 1] : 0u;
+        win[csz + idx] = __builtin_amdgcn_alignbyte(b, a, 1);
+        win[2 * csz + idx] = __builtin_amdgcn_alignbyte(b, a, 2);
+        win[3 * csz + idx] = __builtin_amdgcn_alignbyte(b, a, 3);
     }
-    if (tid < 64) {
-        if constexpr (pf)
-            curb[tid] = ncur;
-        else
-            curb[tid] = *(const uint32_t *)(J.cur + (size_t)(y0 + (tid >> 2)) * st + x0 + 4 * (tid & 3));
-    }
+    if (tid < 64) curb[tid] = *(const uint32_t *)(J.cur + (size_t)(y0 + (tid >> 2)) * st + x0 + 4 * (tid & 3));
     __syncthreads();
     uint32_t cr[64];
 #pragma unroll
     for (int i = 0; i < 64; ++i) cr[i] = curb[i];
-    // the next MB's window loads, in flight during this search
-    if constexpr (pf)
-        if (it + (int)gridDim.x < nitems) fetch(it + gridDim.x);
 
     const int lox = kp.unrestricted ? -S : max(-S, -x0), hix = kp.unrestricted ? S : min(S, W - 16 - x0);
     const int loy = kp.unrestricted ? -S : max(-S, -y0), hiy = kp.unrestricted ? S : min(S, H - 16 - y0);
@@ -267,6 +217,190 @@ __global__ __launch_bounds__(kEsThreads) void es_kernel(const JobDesc *jobs, con
         const int pts = (hix - lox + 1) * (hiy - loy + 1);
         write_result(J, k, dx, dy, (uint32_t)(b >> 24), pts);
     }
+    }
+}
+
+// Minimum over the 64 lanes with DPP row operations; lane 63 holds it.
+__device__ __forceinline__ uint32_t wave_min_to_last(uint32_t v) {
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return v;
+}
+
+// ES for S = 7, 16 and 32: the same tasks as es_kernel with the window
+// geometry fixed at compile time (row offsets become instruction offsets).
+// - Copy 0 of the next MB's window is loaded into registers during the
+//   current MB's search: plain loads when the window lies inside the frame,
+//   edge-clamped ones otherwise.  The four byte-shifted copies are built from
+//   the registers: the next dword of a row is the next lane's (64 is a
+//   multiple of the row pitch); past a row's end it only fills bytes at or
+//   beyond column 16 + 2S, which no candidate reads.
+// - Where two window buffers fit (es_double), the next window is staged into
+//   the other buffer before the MB's one barrier; otherwise after it, behind
+//   a second barrier.
+// - Key per candidate in 31 bits: SAD (16 bits), then |dx| + |dy| (7), dy + S
+//   (7) and whether dx > 0 (1).  With |dx| + |dy| and dy fixed, |dx| is fixed,
+//   so that bit orders the two remaining candidates by dx: the same
+//   lexicographic order (SAD, |dx| + |dy|, dy, dx) as the 64-bit key.
+template <int S>
+__global__ __launch_bounds__(kEsThreads) void es_fixed_kernel(const JobDesc *__restrict__ jobs,
+                                                             const uint32_t *__restrict__ list,
+                                                             const uint32_t *__restrict__ count, KParams kp) {
+    constexpr int span = 16 + 2 * S, ncol = 2 * S + 1, G = es_group(S), lgp = es_pitch_log2(S), pd = 1 << lgp;
+    constexpr int csz = es_copy_dwords(S), per = span << lgp, PF = (per + kEsThreads - 1) / kEsThreads;
+    constexpr int ngrp = (ncol + G - 1) / G, ntask = ncol * ngrp;
+    constexpr bool DB = es_double(S);
+    constexpr int bufw = es_buffer_dwords(S);
+    static_assert(S <= 63 && 64 % pd == 0, "31-bit keys and whole rows per wave");
+    extern __shared__ uint32_t lds[];
+    uint32_t *red = lds + (DB ? 2 : 1) * bufw;  // two sets of 4 wave minima
+    const int tid = threadIdx.x, wave = uni(tid >> 6);
+    const int nitems = (int)*count;
+
+    uint32_t nv[PF] = {}, ncur = 0u;
+    // list entry, MB origin and frame size of the MB fetched last
+    uint32_t ne = 0u;
+    int nx0 = 0, ny0 = 0, nW = 0, nH = 0;
+    // copy 0 of list entry `item`'s window: dword u * 256 + tid into nv[u];
+    // the current block's dword tid into ncur (threads 0 .. 63)
+    auto fetch = [&](int item) {
+        const uint32_t en = list[item];
+        const JobDesc &Jn = jobs[en >> 16];
+        const int kn = (int)(en & 0xFFFF);
+        const int W = Jn.width, H = Jn.height, st = Jn.stride;
+        ne = en;
+        nx0 = 16 * (kn % Jn.wm);
+        ny0 = 16 * (kn / Jn.wm);
+        nW = W;
+        nH = H;
+        const int wx = nx0 - S, wy = ny0 - S;
+        if (tid < 64) ncur = ld4(Jn.cur + (size_t)(wy + S + (tid >> 2)) * st + wx + S + 4 * (tid & 3));
+        const int w = tid & (pd - 1), r0 = tid >> lgp;
+        if (wx >= 0 && wx + 4 * pd <= W && wy >= 0 && wy + span <= H) {
+            const uint8_t *p = Jn.ref + (size_t)(wy + r0) * st + wx + 4 * w;
+#pragma unroll
+            for (int u = 0; u < PF; ++u)
+                if (per % kEsThreads == 0 || u * kEsThreads + tid < per)
+                    nv[u] = ld4(p + (size_t)(u * (kEsThreads >> lgp)) * st);
+        } else {
+#pragma unroll
+            for (int u = 0; u < PF; ++u) {
+                const int r = min(r0 + u * (kEsThreads >> lgp), span - 1);
+                nv[u] = ld4_clamped(Jn.ref + (size_t)iclamp(wy + r, 0, H - 1) * st, wx + 4 * w, W);
+            }
+        }
+    };
+    // the four copies and the current block from the registers
+    auto stage = [&](uint32_t *win) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int idx = u * kEsThreads + tid;
+            const uint32_t a = nv[u];
+            uint32_t b;
+            if constexpr (pd <= 16)
+                b = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)a, 0x101, 0xF, 0xF, true);  // row_shl:1
+            else
+                b = (uint32_t)__shfl((int)a, (lane() + 1) & 63, 64);
+            if (per % kEsThreads == 0 || idx < per) {
+                win[idx] = a;
+                win[csz + idx] = __builtin_amdgcn_alignbyte(b, a, 1);
+                win[2 * csz + idx] = __builtin_amdgcn_alignbyte(b, a, 2);
+                win[3 * csz + idx] = __builtin_amdgcn_alignbyte(b, a, 3);
+            }
+        }
+        if (tid < 64) win[4 * csz + tid] = ncur;
+    };
+    if ((int)blockIdx.x < nitems) {
+        fetch(blockIdx.x);
+        stage(lds);
+    }
+    __syncthreads();
+    int bw = 0, br = 0;  // window buffer, minima set
+    // every searched MB costs the same: static striding, no shared counter
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint32_t *win = lds + bw * bufw;
+        uint32_t cr[64];
+        const uint4 *c4 = (const uint4 *)(win + 4 * csz);  // 16-byte aligned
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const uint4 q = c4[i];
+            cr[4 * i] = q.x;
+            cr[4 * i + 1] = q.y;
+            cr[4 * i + 2] = q.z;
+            cr[4 * i + 3] = q.w;
+        }
+        // this MB (fetched before), then the next one's loads, in flight
+        // during this search
+        const uint32_t e = ne;
+        const int x0 = nx0, y0 = ny0, W = nW, H = nH;
+        const int nxt = it + (int)gridDim.x;
+        if (nxt < nitems) fetch(nxt);
+        const int lox = kp.unrestricted ? -S : max(-S, -x0), hix = kp.unrestricted ? S : min(S, W - 16 - x0);
+        const int loy = kp.unrestricted ? -S : max(-S, -y0), hiy = kp.unrestricted ? S : min(S, H - 16 - y0);
+        // kept rows: dy + S in [loy + S, hiy + S] (padding rows lie above)
+        const uint32_t ylo = (uint32_t)(loy + S), yspan = (uint32_t)(hiy - loy);
+        uint32_t best = ~0u;
+#pragma unroll
+        for (int t0 = 0; t0 < ntask; t0 += kEsThreads) {
+            const int task = t0 + tid;
+            if (ntask % kEsThreads != 0 && task >= ntask) break;
+            const int cxr = task % ncol;        // dx + S
+            const int dy0 = (task / ncol) * G;  // first dy + S
+            const int dx = cxr - S;
+            if (dx < lox || dx > hix) continue;
+            const uint32_t *cp = win + (cxr & 3) * csz + (cxr >> 2) + dy0 * pd;
+            uint32_t acc[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc[g] = 0;
+#pragma unroll
+            for (int r = 0; r < G + 15; ++r) {
+                // rows past the window are padding: read, never kept
+                const uint32_t r0 = cp[r * pd], r1 = cp[r * pd + 1], r2 = cp[r * pd + 2], r3 = cp[r * pd + 3];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const int jj = r - g;
+                    if (jj >= 0 && jj < 16) {
+                        uint32_t a = acc[g];
+                        a = __builtin_amdgcn_sad_u8(cr[4 * jj + 0], r0, a);
+                        a = __builtin_amdgcn_sad_u8(cr[4 * jj + 1], r1, a);
+                        a = __builtin_amdgcn_sad_u8(cr[4 * jj + 2], r2, a);
+                        a = __builtin_amdgcn_sad_u8(cr[4 * jj + 3], r3, a);
+                        acc[g] = a;
+                    }
+                }
+            }
+            const uint32_t adx = (uint32_t)abs(dx), pos = dx > 0 ? 1u : 0u;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int dys = dy0 + g;
+                const uint32_t key = (acc[g] << 15) | ((adx + (uint32_t)abs(dys - S)) << 8) | ((uint32_t)dys << 1) | pos;
+                best = (uint32_t)dys - ylo <= yspan ? min(best, key) : best;
+            }
+        }
+        best = wave_min_to_last(best);
+        if (lane() == 63) red[br * 4 + wave] = best;
+        if constexpr (DB)
+            if (nxt < nitems) stage(lds + (bw ^ 1) * bufw);
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t b = red[br * 4];
+            for (int w = 1; w < kEsThreads / 64; ++w) b = min(b, red[br * 4 + w]);
+            const int dys = (int)((b >> 1) & 127), dy = dys - S;
+            const int adx = (int)((b >> 8) & 127) - abs(dy);
+            const int pts = (hix - lox + 1) * (hiy - loy + 1);
+            write_result(jobs[e >> 16], (int)(e & 0xFFFF), (b & 1) ? adx : -adx, dy, b >> 15, pts);
+        }
+        if constexpr (DB) {
+            bw ^= 1;
+        } else if (nxt < nitems) {
+            stage(lds);
+            __syncthreads();
+        }
+        br ^= 1;
     }
 }
 
@@ -483,7 +617,10 @@ __global__ __launch_bounds__(64) void tss_ds_kernel(const JobDesc *jobs, const u
 
 }  // namespace
 
-size_t es_lds_bytes(int S) { return (size_t)(4 * es_copy_dwords(S) + 64) * 4 + 4 * sizeof(unsigned long long); }
+size_t es_lds_bytes(int S) {
+    if (es_fixed(S)) return (size_t)((es_double(S) ? 2 : 1) * es_buffer_dwords(S) + 8) * 4;
+    return (size_t)es_buffer_dwords(S) * 4 + 4 * sizeof(unsigned long long);
+}
 
 size_t full_search_scratch(int total_mbs) { return (size_t)total_mbs * 4; }
 
@@ -501,16 +638,15 @@ hipError_t launch_full_search(int method, const JobDesc *jobs, int n, int total_
     if (method == ME_ES) {
         size_t lds = es_lds_bytes(kp.S);
         int blocks = std::min(total_mbs, cus * 8);
-        const int G = es_group(kp.S), PF = es_prefetch(kp.S);
-#define ME_ES_LAUNCH(g, pf) \
-    hipLaunchKernelGGL((es_kernel<g, pf>), dim3(blocks), dim3(kEsThreads), lds, s, jobs, list, counters, kp)
-        if (G == 4 && PF == 1) ME_ES_LAUNCH(4, 1);        // S = 7
-        else if (G == 5 && PF == 3) ME_ES_LAUNCH(5, 3);   // S = 16
-        else if (G == 6 && PF == 10) ME_ES_LAUNCH(6, 10); // S = 32
-        else if (G == 4) ME_ES_LAUNCH(4, 0);
-        else if (G == 5) ME_ES_LAUNCH(5, 0);
-        else if (G == 6) ME_ES_LAUNCH(6, 0);
-        else ME_ES_LAUNCH(8, 0);
+#define ME_ES_LAUNCH(kern) hipLaunchKernelGGL((kern), dim3(blocks), dim3(kEsThreads), lds, s, jobs, list, counters, kp)
+        const int G = es_group(kp.S);
+        if (kp.S == 7) ME_ES_LAUNCH(es_fixed_kernel<7>);
+        else if (kp.S == 16) ME_ES_LAUNCH(es_fixed_kernel<16>);
+        else if (kp.S == 32) ME_ES_LAUNCH(es_fixed_kernel<32>);
+        else if (G == 4) ME_ES_LAUNCH(es_kernel<4>);
+        else if (G == 5) ME_ES_LAUNCH(es_kernel<5>);
+        else if (G == 6) ME_ES_LAUNCH(es_kernel<6>);
+        else ME_ES_LAUNCH(es_kernel<8>);
 #undef ME_ES_LAUNCH
     } else {
         int blocks = std::min(total_mbs, cus * 16);
