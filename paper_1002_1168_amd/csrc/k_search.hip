@@ -314,14 +314,27 @@ __global__ __launch_bounds__(kEsThreads) void es_fixed_kernel(const JobDesc *__r
         }
         if (tid < 64) win[4 * csz + tid] = ncur;
     };
-    if ((int)blockIdx.x < nitems) {
-        fetch(blockIdx.x);
+    // This workgroup's MBs.  Workgroups go to the 8 XCDs in turn
+    // (blockIdx.x % 8), each XCD with its own L2, and neighbouring MBs'
+    // windows overlap by two thirds: XCD x takes the x-th eighth of the list,
+    // which its workgroups sweep together (entry first + j * stride), so that
+    // windows loaded at the same time share that L2.  Every searched MB costs
+    // the same: static striding, no shared counter.  Plain striding when the
+    // grid is not a multiple of 8.
+    int first = (int)blockIdx.x, stride = (int)gridDim.x, last = nitems;
+    if (gridDim.x % 8 == 0) {
+        const int x = (int)blockIdx.x & 7, q = (int)blockIdx.x >> 3;
+        stride = (int)gridDim.x >> 3;
+        first = (int)(((long long)nitems * x) >> 3) + q;
+        last = (int)(((long long)nitems * (x + 1)) >> 3);
+    }
+    if (first < last) {
+        fetch(first);
         stage(lds);
     }
     __syncthreads();
     int bw = 0, br = 0;  // window buffer, minima set
-    // every searched MB costs the same: static striding, no shared counter
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    for (int it = first; it < last; it += stride) {
         const uint32_t *win = lds + bw * bufw;
         uint32_t cr[64];
         const uint4 *c4 = (const uint4 *)(win + 4 * csz);  // 16-byte aligned
@@ -337,8 +350,15 @@ __global__ __launch_bounds__(kEsThreads) void es_fixed_kernel(const JobDesc *__r
         // during this search
         const uint32_t e = ne;
         const int x0 = nx0, y0 = ny0, W = nW, H = nH;
-        const int nxt = it + (int)gridDim.x;
-        if (nxt < nitems) fetch(nxt);
+        const int nxt = it + stride;
+        if (nxt < last) fetch(nxt);
+        // this MB's result slot, read before the search (used after the
+        // barrier by thread 0)
+        const JobDesc &Jr = jobs[e >> 16];
+        int16_t *o_mv = Jr.mv, *o_mvi = Jr.mv_int;
+        uint32_t *o_cost = Jr.cost;
+        uint8_t *o_it = Jr.iters;
+        uint16_t *o_pts = Jr.points;
         const int lox = kp.unrestricted ? -S : max(-S, -x0), hix = kp.unrestricted ? S : min(S, W - 16 - x0);
         const int loy = kp.unrestricted ? -S : max(-S, -y0), hiy = kp.unrestricted ? S : min(S, H - 16 - y0);
         // kept rows: dy + S in [loy + S, hiy + S] (padding rows lie above)
@@ -384,7 +404,7 @@ __global__ __launch_bounds__(kEsThreads) void es_fixed_kernel(const JobDesc *__r
         best = wave_min_to_last(best);
         if (lane() == 63) red[br * 4 + wave] = best;
         if constexpr (DB)
-            if (nxt < nitems) stage(lds + (bw ^ 1) * bufw);
+            if (nxt < last) stage(lds + (bw ^ 1) * bufw);
         __syncthreads();
         if (tid == 0) {
             uint32_t b = red[br * 4];
@@ -392,11 +412,17 @@ __global__ __launch_bounds__(kEsThreads) void es_fixed_kernel(const JobDesc *__r
             const int dys = (int)((b >> 1) & 127), dy = dys - S;
             const int adx = (int)((b >> 8) & 127) - abs(dy);
             const int pts = (hix - lox + 1) * (hiy - loy + 1);
-            write_result(jobs[e >> 16], (int)(e & 0xFFFF), (b & 1) ? adx : -adx, dy, b >> 15, pts);
+            const int k = (int)(e & 0xFFFF), dx = (b & 1) ? adx : -adx;
+            const uint32_t mvw = (uint32_t)(uint16_t)(2 * dx) | ((uint32_t)(uint16_t)(2 * dy) << 16);
+            ((uint32_t *)o_mv)[k] = mvw;
+            ((uint32_t *)o_mvi)[k] = mvw;
+            if (o_cost) o_cost[k] = b >> 15;
+            if (o_it) o_it[k] = 0;
+            if (o_pts) o_pts[k] = (uint16_t)pts;
         }
         if constexpr (DB) {
             bw ^= 1;
-        } else if (nxt < nitems) {
+        } else if (nxt < last) {
             stage(lds);
             __syncthreads();
         }
