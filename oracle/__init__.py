@@ -105,6 +105,8 @@ def lib():
         L.or_mc4_sse.argtypes = [C.POINTER(_Pair), vp, vp, vp,
                                  C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
         L.or_mc4_sse.restype = i
+        L.or_pad_vop.argtypes = [vp, vp, i, i, i, vp, i]
+        L.or_pad_vop.restype = i
         _lib = L
     return _lib
 
@@ -274,6 +276,18 @@ def mc4_sse(cur, ref, mv4, cur_alpha=None, cls=None, want_pred=False):
     if rc:
         raise ValueError("or_mc4_sse rejected its arguments")
     return int(s.value), int(n.value), pred
+
+
+def pad_vop(luma, alpha):
+    """MPEG-4 padding of a reference VOP (boundary MBs: repetitive padding,
+    transparent MBs: extended padding) -> padded luma (H, W) u8."""
+    lu, al = _u8(luma), _u8(alpha)
+    H, W = lu.shape
+    out = np.zeros((H, W), np.uint8)
+    rc = lib().or_pad_vop(_ptr(lu), _ptr(al), W, H, W, _ptr(out), W)
+    if rc:
+        raise ValueError("or_pad_vop rejected its arguments")
+    return out
 
 
 def psnr_db(sse: int, npix: int) -> float:

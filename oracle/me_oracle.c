@@ -871,3 +871,106 @@ int or_mc4_sse(const or_pair *fp, const uint8_t *cls, const int16_t *mv4, uint8_
     *npix = n;
     return 0;
 }
+
+/* ------------------------------------------------ reference VOP padding */
+/*
+ * Section 4 protocol: the reference is an MPEG-4 VOP, whose texture outside
+ * the shape is filled before blocks are matched against it (MPEG-4 Visual's
+ * padding of arbitrarily shaped VOPs, on the frame's MB grid).  Inside means
+ * alpha != 0.
+ *  - Opaque MB: copied.
+ *  - Boundary MB, repetitive padding within its 16x16 block.  Along each row,
+ *    a sample outside the shape takes the rounded-up mean of the nearest
+ *    inside samples to its left and right, or the one of them that exists;
+ *    a row with no inside sample stays open.  Then along each column, an open
+ *    sample takes the rounded-up mean of the nearest row-padded samples above
+ *    and below, or the one that exists.
+ *  - Transparent MB, extended padding: the border of the first adjacent MB
+ *    that is not transparent, in the order left, above, right, below, is
+ *    repeated over the block: the left MB's last column along each row, the
+ *    upper MB's last row down each column, the right MB's first column, the
+ *    lower MB's first row.  With no such neighbour, every sample is 128.
+ * `out` (row stride out_stride) must not overlap `luma`.
+ */
+static int pad_mean(int a, int b) { return (a + b + 1) >> 1; }
+
+int or_pad_vop(const uint8_t *luma, const uint8_t *alpha, int width, int height, int stride, uint8_t *out,
+               int out_stride) {
+    if (!luma || !alpha || !out || width <= 0 || height <= 0 || width % 16 || height % 16 || stride < width ||
+        out_stride < width)
+        return -1;
+    int wm = width / 16, hm = height / 16;
+    uint8_t *cls = (uint8_t *)malloc((size_t)wm * hm);
+    if (!cls) return -1;
+    or_classify(alpha, width, height, stride, cls, NULL);
+    /* opaque and boundary MBs */
+    for (int v = 0; v < hm; ++v) {
+        for (int h = 0; h < wm; ++h) {
+            int c = cls[v * wm + h], x0 = 16 * h, y0 = 16 * v;
+            if (c == OR_TRANSPARENT) continue;
+            int val[16][16], in[16][16], row_open[16];
+            for (int j = 0; j < 16; ++j)
+                for (int i = 0; i < 16; ++i) {
+                    val[j][i] = luma_at(luma, stride, x0 + i, y0 + j);
+                    in[j][i] = alpha[(size_t)(y0 + j) * stride + x0 + i] != 0;
+                }
+            if (c == OR_BOUNDARY) {
+                int hp[16][16];
+                for (int j = 0; j < 16; ++j) {
+                    row_open[j] = 1;
+                    for (int i = 0; i < 16; ++i) row_open[j] &= !in[j][i];
+                    for (int i = 0; i < 16; ++i) {
+                        if (in[j][i]) {
+                            hp[j][i] = val[j][i];
+                            continue;
+                        }
+                        int l = i - 1, r = i + 1;
+                        while (l >= 0 && !in[j][l]) --l;
+                        while (r < 16 && !in[j][r]) ++r;
+                        if (l >= 0 && r < 16) hp[j][i] = pad_mean(val[j][l], val[j][r]);
+                        else if (l >= 0) hp[j][i] = val[j][l];
+                        else if (r < 16) hp[j][i] = val[j][r];
+                        else hp[j][i] = -1; /* open */
+                    }
+                }
+                for (int i = 0; i < 16; ++i) {
+                    for (int j = 0; j < 16; ++j) {
+                        if (!row_open[j]) {
+                            val[j][i] = hp[j][i];
+                            continue;
+                        }
+                        int u = j - 1, d = j + 1;
+                        while (u >= 0 && row_open[u]) --u;
+                        while (d < 16 && row_open[d]) ++d;
+                        /* a boundary MB has an inside sample, so some row is filled */
+                        if (u >= 0 && d < 16) val[j][i] = pad_mean(hp[u][i], hp[d][i]);
+                        else if (u >= 0) val[j][i] = hp[u][i];
+                        else val[j][i] = hp[d][i];
+                    }
+                }
+            }
+            for (int j = 0; j < 16; ++j)
+                for (int i = 0; i < 16; ++i) out[(size_t)(y0 + j) * out_stride + x0 + i] = (uint8_t)val[j][i];
+        }
+    }
+    /* transparent MBs, from their padded neighbours */
+    for (int v = 0; v < hm; ++v) {
+        for (int h = 0; h < wm; ++h) {
+            int k = v * wm + h, x0 = 16 * h, y0 = 16 * v;
+            if (cls[k] != OR_TRANSPARENT) continue;
+            for (int j = 0; j < 16; ++j) {
+                for (int i = 0; i < 16; ++i) {
+                    int s;
+                    if (h > 0 && cls[k - 1] != OR_TRANSPARENT) s = out[(size_t)(y0 + j) * out_stride + x0 - 1];
+                    else if (v > 0 && cls[k - wm] != OR_TRANSPARENT) s = out[(size_t)(y0 - 1) * out_stride + x0 + i];
+                    else if (h + 1 < wm && cls[k + 1] != OR_TRANSPARENT) s = out[(size_t)(y0 + j) * out_stride + x0 + 16];
+                    else if (v + 1 < hm && cls[k + wm] != OR_TRANSPARENT) s = out[(size_t)(y0 + 16) * out_stride + x0 + i];
+                    else s = 128;
+                    out[(size_t)(y0 + j) * out_stride + x0 + i] = (uint8_t)s;
+                }
+            }
+        }
+    }
+    free(cls);
+    return 0;
+}
