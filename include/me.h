@@ -202,6 +202,34 @@ int me_classify_babs(const me_frame *frames, int n, uint8_t *const *mb_class, ui
                      void *stream);
 
 /*
+ * Reference VOP padding (Section 4 protocol: the reference is an MPEG-4 VOP,
+ * whose texture outside the shape is filled before blocks are matched
+ * against it; MPEG-4 Visual's padding of arbitrarily shaped VOPs, applied on
+ * the frame's MB grid).  Inside means alpha != 0.
+ *  - Opaque MBs are copied.
+ *  - Boundary MBs: repetitive padding within the 16x16 block.  Along each
+ *    row, a sample outside the shape takes the rounded-up mean of the
+ *    nearest inside samples to its left and right, or the one that exists.
+ *    Rows with no inside sample then take the same rule along each column,
+ *    over the row-padded samples.
+ *  - Transparent MBs: extended padding.  The block repeats the border of the
+ *    first adjacent MB that is not transparent, in the order left, above,
+ *    right, below: the left MB's last column along each row, the upper MB's
+ *    last row down each column, the right MB's first column, the lower MB's
+ *    first row.  With no such neighbour, every sample is 128.
+ *  frames[i].luma, .alpha  the reference frame's luma and this VOP's alpha
+ *                          (device, both required, checked as for
+ *                          me_classify_babs).
+ *  padded[i]   device, caller-owned: height rows of frames[i].stride bytes,
+ *              4-byte aligned; the first width bytes of each row are
+ *              written.  It must not overlap the frame's luma or alpha
+ *              (ME_EINVAL when it is the same address).
+ * Pass padded[i] as the `ref.luma` of the VOP's search and MC jobs.  At most
+ * 65,535 VOPs per call (ME_EINVAL beyond).  Asynchronous on `stream`.
+ */
+int me_pad_vops(const me_frame *frames, int n, uint8_t *const *padded, void *stream);
+
+/*
  * The proposed algorithm (Fig. 1; Sections 3.1-3.2) for n frame pairs.
  * Per MB in raster order: transparent -> zero vector; otherwise the
  * block-recursive search over the candidates A (left), B (up), C (up-right)

@@ -23,7 +23,8 @@ ME_BATCH_SHAPE, ME_BATCH_AUTOTUNE = 1, 2
 ME_FLAG_UNRESTRICTED, ME_FLAG_T_TEXTURE, ME_FLAG_LINE_WORKERS = 0x1, 0x2, 0x100
 ME_NET_PARAMS = 10434
 
-EXPORTED = ("me_default_params", "me_status_str", "me_shutdown", "me_classify_babs", "me_texture_recursive",
+EXPORTED = ("me_default_params", "me_status_str", "me_shutdown", "me_classify_babs", "me_pad_vops",
+            "me_texture_recursive",
             "me_shape_search", "me_full_search", "me_motion_compensate_psnr", "me_motion_compensate_sse",
             "me_motion_compensate_sse_noalloc", "me_refine_8x8", "me_motion_compensate4_sse", "me_device_status",
             "me_kernel_timing", "me_kernel_time_ms", "me_batch_create", "me_batch_step", "me_batch_results",
@@ -75,6 +76,8 @@ def lib():
         L.me_shutdown.restype = None
         L.me_classify_babs.argtypes = [C.POINTER(me_frame), i, C.POINTER(vp), C.POINTER(vp), vp]
         L.me_classify_babs.restype = i
+        L.me_pad_vops.argtypes = [C.POINTER(me_frame), i, C.POINTER(vp), vp]
+        L.me_pad_vops.restype = i
         L.me_texture_recursive.argtypes = [C.POINTER(me_job), i, C.POINTER(me_params), vp, vp]
         L.me_texture_recursive.restype = i
         L.me_shape_search.argtypes = [C.POINTER(me_job), i, C.POINTER(me_params), vp]
@@ -189,6 +192,15 @@ def me_classify_babs(frames, mb_class, bab_bits=None, stream=None, check=True) -
     ba = None if bab_bits is None else _arr(C.c_void_p, bab_bits)[0]
     rc = lib().me_classify_babs(fa, n, ca, ba, stream)
     return _check(rc, "me_classify_babs") if check else rc
+
+
+def me_pad_vops(frames, padded, stream=None, check=True) -> int:
+    """``frames``: me_frame list (reference luma + VOP alpha); ``padded``:
+    device addresses of the padded planes (same stride as each frame)."""
+    fa, n = _arr(me_frame, frames)
+    pa, _ = _arr(C.c_void_p, padded)
+    rc = lib().me_pad_vops(fa, n, pa, stream)
+    return _check(rc, "me_pad_vops") if check else rc
 
 
 def me_texture_recursive(jobs, params: me_params, net=None, stream=None, check=True) -> int:

@@ -17,6 +17,7 @@
 
 namespace me {
 size_t es_lds_bytes(int S);
+hipError_t launch_pad(const JobDesc *jobs, int n, int max_mbs, uint8_t *cls_all, hipStream_t s);
 }
 
 using namespace me;
@@ -42,7 +43,7 @@ struct Arena {
     bool last_valid = false;
 };
 
-enum ArenaKind { A_CLASSIFY = 0, A_PA = 1, A_SEARCH = 2, A_MC = 3, A_PRS8 = 4, A_COUNT = 5 };
+enum ArenaKind { A_CLASSIFY = 0, A_PA = 1, A_SEARCH = 2, A_MC = 3, A_PRS8 = 4, A_PAD = 5, A_COUNT = 6 };
 // timing kinds: the first four arena kinds (ME_KT_*), the network forward and
 // training kernels, then the 8 x 8 refinement
 constexpr int kTimerKinds = 7;
@@ -387,6 +388,46 @@ int me_classify_babs(const me_frame *frames, int n, uint8_t *const *mb_class, ui
     KernelTimer kt;
     return hip_err(launch_classify((const JobDesc *)(base + o), n, (int)total, w->stream,
                                    timer_for(*w, A_CLASSIFY, &kt) ? &kt : nullptr));
+}
+
+int me_pad_vops(const me_frame *frames, int n, uint8_t *const *padded, void *stream) {
+    if (n < 0 || (n > 0 && (!frames || !padded))) return ME_EINVAL;
+    if (n > 65535) return ME_EINVAL;  // one grid row per VOP
+    std::vector<JobDesc> desc(n);
+    long long total = 0;
+    int max_mbs = 0;
+    for (int i = 0; i < n; ++i) {
+        int rc = check_frame(frames[i], true);
+        if (rc) return rc;
+        if (!padded[i] || padded[i] == frames[i].luma || padded[i] == frames[i].alpha) return ME_EINVAL;
+        if (!al4(padded[i])) return ME_EALIGN;
+        JobDesc &d = desc[i];
+        std::memset(&d, 0, sizeof(d));
+        d.cur = frames[i].luma;
+        d.cur_a = frames[i].alpha;
+        d.out_u8 = padded[i];
+        d.width = frames[i].width;
+        d.height = frames[i].height;
+        d.stride = frames[i].stride;
+        d.wm = d.width / 16;
+        d.hm = d.height / 16;
+        d.mb_base = (int32_t)total;
+        d.dep_line_base = -1;
+        total += (long long)d.wm * d.hm;
+        max_mbs = std::max(max_mbs, d.wm * d.hm);
+    }
+    if (total > (1ll << 30)) return ME_EINVAL;
+    if (n == 0) return ME_OK;
+    Workspace *w = nullptr;
+    int rc = get_ws(stream, &w);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(w->mu);
+    std::vector<uint8_t> blob;
+    size_t o = put(blob, desc.data(), desc.size());
+    uint8_t *base = nullptr, *zb = nullptr, *cls = nullptr;
+    rc = upload(*w, A_PAD, blob, 0, &base, &zb, (size_t)total, &cls);
+    if (rc) return rc;
+    return hip_err(launch_pad((const JobDesc *)(base + o), n, max_mbs, cls, w->stream));
 }
 
 int me_texture_recursive(const me_job *jobs, int n, const me_params *params, const me_net *net, void *stream) {

@@ -209,3 +209,18 @@ def test_net_checkpoint_errors_before_any_device_call(tmp_path):
     wrong.write_bytes(b"X" * n)
     assert L.me_net_load(str(wrong).encode(), C.byref(h)) == me.ME_EFORMAT
     assert "checkpoint" in me.status_str(me.ME_EFORMAT) and "file" in me.status_str(me.ME_EIO)
+
+
+def test_pad_argument_validation():
+    """me_pad_vops rejects bad frames, outputs and counts before any device call."""
+    ok = frame(alpha=FAKE + 4096)
+    out = FAKE + 8192
+    assert me.me_pad_vops([], [], check=False) == me.ME_OK
+    assert me.me_pad_vops([frame()], [out], check=False) == me.ME_EINVAL          # no alpha
+    assert me.me_pad_vops([ok], [None], check=False) == me.ME_EINVAL              # no output
+    assert me.me_pad_vops([ok], [FAKE], check=False) == me.ME_EINVAL              # output is the luma
+    assert me.me_pad_vops([ok], [out + 1], check=False) == me.ME_EALIGN           # unaligned output
+    assert me.me_pad_vops([frame(w=40, alpha=FAKE)], [out], check=False) == me.ME_EALIGN
+    assert me.me_pad_vops([frame(stride=66, alpha=FAKE)], [out], check=False) == me.ME_EALIGN
+    assert me.lib().me_pad_vops(None, 1, None, None) == me.ME_EINVAL
+    assert me.lib().me_pad_vops(None, -1, None, None) == me.ME_EINVAL
