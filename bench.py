@@ -15,9 +15,11 @@ block/pel-recursive search and motion compensation + SSE for every
 
 Also reported (under "extras"): the CIF two-VOP sequence (300 frames, +-16)
 as one pipelined launch with the ES / TSS / 4SS / DS baselines, the QCIF
-sequence in the paper's geometry (+-7) and CIF in rectangular mode with
-every method's PSNR, points per MB and figure of merit (Eq. 6), and the
-64-stream mixed-size batch.
+sequence in the paper's geometry (+-7: VOP mode, rectangular mode and the
+Section 4 protocol with frame distance 2, unrestricted vectors and the
+MPEG-4-padded reference) and CIF in rectangular mode with every method's
+PSNR, points per MB and figure of merit (Eq. 6), and the 64-stream
+mixed-size batch.
 
 Prints one JSON line.  Only one GPU is used: --gpus above 1 exits.
 """
@@ -468,24 +470,30 @@ def cif_measurement(torch, steps, warmup, learned=True):
     return out
 
 
-def quality_grid(seq, S, rect, torch):
+def quality_grid(seq, S, rect, torch, protocol=False):
     """Every method on one sequence (VOP mode, or rectangular mode with no
     alpha): mean per-frame PSNR, points and iterations per searched MB and
-    the figure of merit (Eq. 6), as in Tables 1-2."""
+    the figure of merit (Eq. 6), as in Tables 1-2.  ``protocol`` (VOP mode):
+    Section 4's setting as read here - frame distance 2, unrestricted
+    vectors and the MPEG-4-padded reference VOP for search and MC."""
     import paper_1002_1168_amd as me
     from paper_1002_1168_amd import device as dv
     ds = dv.DeviceSequence(seq)
     s = dv.stream_handle()
-    pairs = seq.frames - 1
+    dist = 2 if protocol else 1
+    pairs = seq.frames - dist
     vops = [None] if rect else list(range(seq.vops))
     if not rect:
         fr, cp, bp = ds.classify_frames()
         me.me_classify_babs(fr, cp, bp, stream=s)
-    p = me.me_default_params(search_range=S, half_pel=int(seq.half_pel))
+    refs = ds.padded_refs(stream=s) if protocol else None
+    p = me.me_default_params(search_range=S, half_pel=int(seq.half_pel),
+                             flags=me.ME_FLAG_UNRESTRICTED if protocol else 0)
     res = {}
     for name, m in (("pa", None), ("es", me.ME_ES), ("tss", me.ME_TSS), ("4ss", me.ME_4SS), ("ds", me.ME_DS)):
         outs = [dv.Outputs.alloc(pairs, ds.hm, ds.wm) for _ in vops]
-        jobs = [j for v, o in zip(vops, outs) for j in ds.pair_jobs(v, o, pairs, chained=m is None)]
+        jobs = [j for v, o in zip(vops, outs)
+                for j in ds.pair_jobs(v, o, pairs, chained=m is None, distance=dist, refs=refs)]
         if m is None:
             me.me_texture_recursive(jobs, p, None, stream=s)
         else:
@@ -497,14 +505,14 @@ def quality_grid(seq, S, rect, torch):
         pts = its = n = 0
         for v, o in zip(vops, outs):
             h = o.host()
-            msk = np.ones(h["points"].shape, bool) if v is None else ds.cls[v, 1:].cpu().numpy() != 0
+            msk = np.ones(h["points"].shape, bool) if v is None else ds.cls[v, dist:].cpu().numpy() != 0
             pts += int(h["points"][msk].astype(np.int64).sum())
             its += int(h["iters"][msk].astype(np.int64).sum())
             n += int(msk.sum())
         res[name] = {"psnr_db": float(np.mean(db)), "points_per_mb": pts / max(n, 1),
                      "iters_per_mb": its / max(n, 1), "figure_of_merit": figure_of_merit(db, pts / max(n, 1), S)}
     torch.cuda.synchronize()
-    log(f"{seq.name} {'rect' if rect else 'vop'} S={S}: " + "; ".join(
+    log(f"{seq.name} {'rect' if rect else ('protocol' if protocol else 'vop')} S={S}: " + "; ".join(
         f"{k} {v['psnr_db']:.2f} dB {v['points_per_mb']:.2f} pts" for k, v in res.items()))
     return res
 
@@ -645,6 +653,7 @@ def main():
         extras["cif"] = cif_measurement(torch, a.steps, a.warmup, learned=not a.no_learned)
         extras["qcif_vop"] = quality_grid(synth.qcif_ellipse(seed=1, frames=10), 7, False, torch)
         extras["qcif_rect"] = quality_grid(synth.qcif_ellipse(seed=1, frames=10), 7, True, torch)
+        extras["qcif_protocol"] = quality_grid(synth.qcif_ellipse(seed=1, frames=10), 7, False, torch, protocol=True)
         extras["cif_rect"] = quality_grid(synth.cif_two_vops(seed=2, frames=60), 16, True, torch)
         extras["batched_mixed64"] = batched_measurement(torch, a.steps, a.warmup)
 

@@ -299,12 +299,15 @@ def psnr_db(sse: int, npix: int) -> float:
     return 10.0 * np.log10(255.0 * 255.0 * npix / sse)
 
 
-def pa_sequence(seq, vop: int | None, params: Params, shape_only=False, pairs=None, seeds=None, distance=1):
+def pa_sequence(seq, vop: int | None, params: Params, shape_only=False, pairs=None, seeds=None, distance=1,
+                padded=False):
     """Run the proposed algorithm over the frame pairs (t - distance, t),
     t = distance, distance + 1, ... of a synthetic sequence (Section 4 uses a
     distance of two), feeding each pair's full-pel field forward as the
     temporal candidate of the next.  ``vop=None`` treats frames as
-    rectangular.  Returns a list of per-pair dicts (with classes and SSE)."""
+    rectangular.  ``padded``: the reference luma is the reference VOP after
+    MPEG-4 padding (``pad_vop``), for search and MC alike.  Returns a list of
+    per-pair dicts (with classes and SSE)."""
     n = seq.frames - distance if pairs is None else pairs
     res = []
     t_field = None
@@ -315,6 +318,8 @@ def pa_sequence(seq, vop: int | None, params: Params, shape_only=False, pairs=No
         if vop is not None:
             ca, ra = seq.alpha[vop, t], seq.alpha[vop, t - distance]
             cls, _ = classify(ca)
+            if padded:
+                ref = pad_vop(ref, ra)
         sd = None if seeds is None else seeds[i]
         out = pa(cur, ref, params, ca, ra, cls, t_field, sd, shape_only)
         out["cls"] = cls

@@ -87,11 +87,24 @@ class DeviceSequence:
                 bp.append(ptr(self.bab[v, t]))
         return fr, cp, bp
 
+    def padded_refs(self, stream=None) -> torch.Tensor:
+        """Every (VOP, frame) luma after MPEG-4 reference VOP padding
+        (``me_pad_vops``, one call): (V, F, H, W) uint8 on the device."""
+        from . import me_pad_vops
+        out = torch.empty((self.V, self.F, self.H, self.W), dtype=torch.uint8, device=self.luma.device)
+        frames = [frame(self.luma[t], self.alpha[v, t]) for v in range(self.V) for t in range(self.F)]
+        me_pad_vops(frames, [out[v, t].data_ptr() for v in range(self.V) for t in range(self.F)],
+                    stream=stream_handle() if stream is None else stream)
+        return out
+
     def pair_jobs(self, vop: int | None, out: Outputs, pairs=None, chained=True, use_class=True,
-                  seeds: torch.Tensor | None = None, distance: int = 1) -> list[me_job]:
+                  seeds: torch.Tensor | None = None, distance: int = 1,
+                  refs: torch.Tensor | None = None) -> list[me_job]:
         """Jobs for frame pairs (t - distance, t), t = distance .. distance + P - 1
         (reference ``distance`` frames back).  ``chained``: each pair's T field
-        is the previous pair's mv_int (the first pair gets none)."""
+        is the previous pair's mv_int (the first pair gets none).  ``refs``
+        (V, F, H, W), e.g. from ``padded_refs``: the reference luma of VOP v at
+        frame r is refs[v, r] instead of the frame's luma."""
         P = self.F - distance if pairs is None else pairs
         jobs = []
         for i in range(P):
@@ -103,5 +116,6 @@ class DeviceSequence:
                 cls = self.cls[vop, t] if use_class else None
             tf = out.mv_int[i - 1] if (chained and i > 0) else None
             sd = None if seeds is None else seeds[i]
-            jobs.append(job(self.luma[t], self.luma[r], ca, ra, cls, tf, out, i, sd))
+            rl = refs[vop, r] if (refs is not None and vop is not None) else self.luma[r]
+            jobs.append(job(self.luma[t], rl, ca, ra, cls, tf, out, i, sd))
         return jobs

@@ -27,7 +27,8 @@ def gpu_classify(ds: dv.DeviceSequence):
     assert me.me_device_status(dv.stream_handle()) == me.ME_OK
 
 
-def gpu_pa(ds: dv.DeviceSequence, vops, params, pairs, shape_only=False, one_call=True, chained=True, distance=1):
+def gpu_pa(ds: dv.DeviceSequence, vops, params, pairs, shape_only=False, one_call=True, chained=True, distance=1,
+           refs=None):
     """PA for the listed VOPs (None = rectangular) over `pairs` pairs
     (reference `distance` frames back).  Returns {vop: host outputs}.  With
     one_call every VOP chain is solved in a single launch; otherwise one
@@ -37,7 +38,7 @@ def gpu_pa(ds: dv.DeviceSequence, vops, params, pairs, shape_only=False, one_cal
     for v in vops:
         out = dv.Outputs.alloc(pairs, ds.hm, ds.wm)
         outs[v] = out
-        jobs.append(ds.pair_jobs(v, out, pairs, chained=chained, distance=distance))
+        jobs.append(ds.pair_jobs(v, out, pairs, chained=chained, distance=distance, refs=refs))
     fn = me.me_shape_search if shape_only else me.me_texture_recursive
     s = dv.stream_handle()
     if one_call:
@@ -58,9 +59,9 @@ def gpu_pa(ds: dv.DeviceSequence, vops, params, pairs, shape_only=False, one_cal
     return {v: o.host() for v, o in outs.items()}
 
 
-def oracle_pa(seq, vop, params, pairs, shape_only=False, distance=1):
+def oracle_pa(seq, vop, params, pairs, shape_only=False, distance=1, padded=False):
     res = oracle.pa_sequence(seq, vop, oracle_params(params), shape_only=shape_only, pairs=pairs,
-                             distance=distance)
+                             distance=distance, padded=padded)
     return {k: np.stack([r[k] for r in res]) for k in ("mv", "mv_int", "cost", "iters", "points")}
 
 

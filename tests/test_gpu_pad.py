@@ -156,3 +156,42 @@ def test_search_on_padded_reference(torch_cuda, method):
     got = out.host()
     assert_same({k: got[k][0] for k in got}, want, f"padded reference, method {method}",
                 keys=("mv", "mv_int", "cost", "points"))
+
+
+@pytest.mark.parametrize("case", ["qcif-one-call", "qcif-per-pair", "cif-two-vops"])
+def test_pa_section4_protocol(torch_cuda, case):
+    """Section 4 protocol assembled: frame distance 2, unrestricted vectors
+    and the MPEG-4-padded reference VOP (padded by me_pad_vops, one call for
+    every VOP and frame), against the oracle under the same protocol; SSE and
+    pixel counts of MC over the padded reference too."""
+    import torch
+    from paper_1002_1168_amd import device as dv
+    from gpu_util import gpu_classify, gpu_pa, oracle_pa
+    if case.startswith("qcif"):
+        seq, S, vops = synth.qcif_ellipse(frames=6), 7, [0]
+    else:
+        seq, S, vops = synth.cif_two_vops(frames=5), 16, [0, 1]
+    ds = dv.DeviceSequence(seq)
+    gpu_classify(ds)
+    refs = ds.padded_refs()
+    torch.cuda.synchronize()
+    for v in vops:
+        for t in range(seq.frames):
+            assert np.array_equal(refs[v, t].cpu().numpy(), oracle.pad_vop(seq.luma[t], seq.alpha[v, t])), (v, t)
+    p = me.me_default_params(search_range=S, half_pel=1, flags=me.ME_FLAG_UNRESTRICTED)
+    pairs = seq.frames - 2
+    say("section 4 protocol", case)
+    got = gpu_pa(ds, vops, p, pairs, one_call=case != "qcif-per-pair", distance=2, refs=refs)
+    for v in vops:
+        res = oracle.pa_sequence(seq, v, oracle_params(p), pairs=pairs, distance=2, padded=True)
+        want = {k: np.stack([r[k] for r in res]) for k in ("mv", "mv_int", "cost", "iters", "points")}
+        assert_same(got[v], want, f"{case} vop {v}")
+        # MC over the padded reference with the GPU's vectors
+        out = dv.Outputs.alloc(pairs, ds.hm, ds.wm)
+        out.mv.copy_(torch.from_numpy(got[v]["mv"]).cuda())
+        jobs = [dv.mc_job(ds.luma[i + 2], refs[v, i], ds.alpha[v, i + 2], ds.cls[v, i + 2], out.mv[i])
+                for i in range(pairs)]
+        sse, npx, _, rc = me.me_motion_compensate_psnr(jobs, stream=dv.stream_handle(), check=False)
+        assert rc in (me.ME_OK, me.ME_EEMPTY), rc
+        assert [int(x) for x in sse] == [r["sse"] for r in res]
+        assert [int(x) for x in npx] == [r["npix"] for r in res]
