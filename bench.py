@@ -434,7 +434,8 @@ def cif_measurement(torch, steps, warmup, learned=True):
         if m == me.ME_ES:
             a2 = SAD_OPS * bpts / (bk * 1e-3) / 1e12
             entry["roofline"] = {"bound": "alu", "achieved": a2, "peak": PEAK_INT_TOPS, "unit": "Tops/s",
-                                 "frac": a2 / PEAK_INT_TOPS, "kernel": "es_kernel"}
+                                 "frac": a2 / PEAK_INT_TOPS,
+                                 "kernel": f"es_fixed_kernel<{wl.S}>" if wl.S in (7, 16, 32) else "es_kernel"}
         baselines[name] = entry
         log(f"cif {name}: {entry['mb_per_s'] / 1e6:.1f} M MB/s, kernel {bk:.3f} ms, PSNR {entry['psnr_db']:.2f}, "
             f"points/MB {entry['points_per_mb']:.2f}")
