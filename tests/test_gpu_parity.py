@@ -640,3 +640,12 @@ def test_pa_two_waves_per_line(torch_cuda):
     torch.cuda.synchronize()
     assert me.me_device_status(dv.stream_handle()) == me.ME_OK
     assert_same(out.host(), oracle_pa(s, 0, p, 3), f"{s.name} vop 0")
+
+
+@pytest.mark.parametrize("method", [me.ME_ES, me.ME_TSS, me.ME_DS, me.ME_4SS])
+@pytest.mark.parametrize("S", [20, 24, 26, 64])
+def test_search_wide_ranges(torch_cuda, method, S):
+    """Ranges that take the general ES kernel with G = 8, 5, 6 and 4 rows per
+    task (S = 64: the largest range, a window of 147 rows of 256 bytes in
+    four byte-shifted copies, 151 KB of LDS)."""
+    check_search(synth.random_frames(9, 96, 80, frames=3, vops=1), method, S, 2)
