@@ -649,3 +649,16 @@ def test_search_wide_ranges(torch_cuda, method, S):
     task (S = 64: the largest range, a window of 147 rows of 256 bytes in
     four byte-shifted copies, 151 KB of LDS)."""
     check_search(synth.random_frames(9, 96, 80, frames=3, vops=1), method, S, 2)
+
+
+@pytest.mark.parametrize("S", [20, 40, 64])
+@pytest.mark.parametrize("mode", ["lines", "rows"])
+def test_pa_wide_ranges(torch_cuda, S, mode):
+    """The proposed search at ranges whose windows take the general staging
+    loop (no per-range staging plan), up to S = 64: line workers (pairs
+    chained in one call) and row workers (one call per pair), with and
+    without half-sample refinement, VOP and rectangular."""
+    seq = synth.random_frames(10 + S, 112, 96, frames=4, vops=1, search_range=S)
+    for half in (0, 1):
+        p = me.me_default_params(search_range=S, half_pel=half, k_max=255, max_step=min(S, 3))
+        check_pa(seq, [0, None], p, 3, one_call=mode == "lines", label=f"S={S} half={half} {mode}")
