@@ -338,29 +338,49 @@ __global__ __launch_bounds__(256) void mc_sums_kernel(const JobDesc *jobs, int n
     });
 }
 
-// Per job: the exact 64-bit sums of its MBs' SSE and pixel counts.
-__global__ __launch_bounds__(256) void mc_reduce_kernel(const JobDesc *jobs, const uint32_t *part,
-                                                        unsigned long long *acc) {
-    __shared__ unsigned long long red[2][4];
+// Per job: the exact 64-bit sums of its MBs' SSE and pixel counts.  One
+// 1024-thread block per job; an MB's (SSE, count) pair is one 8-byte load,
+// four loads in flight per thread.
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void mc_reduce_kernel(const JobDesc *jobs, const uint32_t *part,
+                                                                   unsigned long long *acc) {
+    __shared__ unsigned long long red[2][kReduceThreads / 64];
     const JobDesc &J = jobs[blockIdx.x];
     const int nmb = J.wm * J.hm;
-    unsigned long long s = 0, c = 0;
-    for (int i = threadIdx.x; i < nmb; i += 256) {
-        s += part[2 * ((size_t)J.mb_base + i)];
-        c += part[2 * ((size_t)J.mb_base + i) + 1];
+    const unsigned long long *p = (const unsigned long long *)(part + 2 * (size_t)J.mb_base);
+    unsigned long long s[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
+    int i = threadIdx.x;
+    for (; i + 3 * kReduceThreads < nmb; i += 4 * kReduceThreads) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const unsigned long long w = p[i + u * kReduceThreads];
+            s[u] += (uint32_t)w;
+            c[u] += w >> 32;
+        }
     }
+    for (; i < nmb; i += kReduceThreads) {
+        const unsigned long long w = p[i];
+        s[0] += (uint32_t)w;
+        c[0] += w >> 32;
+    }
+    unsigned long long ss = s[0] + s[1] + s[2] + s[3], cc = c[0] + c[1] + c[2] + c[3];
     for (int o = 32; o >= 1; o >>= 1) {
-        s += __shfl_xor(s, o, 64);
-        c += __shfl_xor(c, o, 64);
+        ss += __shfl_xor(ss, o, 64);
+        cc += __shfl_xor(cc, o, 64);
     }
     if (lane() == 0) {
-        red[0][threadIdx.x >> 6] = s;
-        red[1][threadIdx.x >> 6] = c;
+        red[0][threadIdx.x >> 6] = ss;
+        red[1][threadIdx.x >> 6] = cc;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        acc[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-        acc[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+        unsigned long long ts = 0, tc = 0;
+        for (int w = 0; w < kReduceThreads / 64; ++w) {
+            ts += red[0][w];
+            tc += red[1][w];
+        }
+        acc[2 * blockIdx.x] = ts;
+        acc[2 * blockIdx.x + 1] = tc;
     }
 }
 
@@ -418,7 +438,7 @@ hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, 
     hipError_t e = hipGetLastError();
     timer_mark(t, false, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(mc_reduce_kernel, dim3(n), dim3(256), 0, s, jobs, part, acc);
+    hipLaunchKernelGGL(mc_reduce_kernel, dim3(n), dim3(kReduceThreads), 0, s, jobs, part, acc);
     return hipGetLastError();
 }
 
