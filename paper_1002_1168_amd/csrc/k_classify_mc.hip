@@ -339,26 +339,26 @@ __global__ __launch_bounds__(256) void mc_sums_kernel(const JobDesc *jobs, int n
 }
 
 // Per job: the exact 64-bit sums of its MBs' SSE and pixel counts.  One
-// 1024-thread block per job; an MB's (SSE, count) pair is one 8-byte load,
-// four loads in flight per thread.
+// block per job, 64 to 1024 threads (about four MBs per thread); an MB's
+// (SSE, count) pair is one 8-byte load, four loads in flight per thread.
 constexpr int kReduceThreads = 1024;
 __global__ __launch_bounds__(kReduceThreads) void mc_reduce_kernel(const JobDesc *jobs, const uint32_t *part,
                                                                    unsigned long long *acc) {
     __shared__ unsigned long long red[2][kReduceThreads / 64];
     const JobDesc &J = jobs[blockIdx.x];
-    const int nmb = J.wm * J.hm;
+    const int nmb = J.wm * J.hm, nt = (int)blockDim.x;
     const unsigned long long *p = (const unsigned long long *)(part + 2 * (size_t)J.mb_base);
     unsigned long long s[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
     int i = threadIdx.x;
-    for (; i + 3 * kReduceThreads < nmb; i += 4 * kReduceThreads) {
+    for (; i + 3 * nt < nmb; i += 4 * nt) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const unsigned long long w = p[i + u * kReduceThreads];
+            const unsigned long long w = p[i + u * nt];
             s[u] += (uint32_t)w;
             c[u] += w >> 32;
         }
     }
-    for (; i < nmb; i += kReduceThreads) {
+    for (; i < nmb; i += nt) {
         const unsigned long long w = p[i];
         s[0] += (uint32_t)w;
         c[0] += w >> 32;
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(kReduceThreads) void mc_reduce_kernel(const JobDesc
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long ts = 0, tc = 0;
-        for (int w = 0; w < kReduceThreads / 64; ++w) {
+        for (int w = 0; w < nt / 64; ++w) {
             ts += red[0][w];
             tc += red[1][w];
         }
@@ -438,7 +438,9 @@ hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, 
     hipError_t e = hipGetLastError();
     timer_mark(t, false, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(mc_reduce_kernel, dim3(n), dim3(kReduceThreads), 0, s, jobs, part, acc);
+    int th = 64;
+    while (th < kReduceThreads && 4 * th < total_mbs / n) th <<= 1;
+    hipLaunchKernelGGL(mc_reduce_kernel, dim3(n), dim3(th), 0, s, jobs, part, acc);
     return hipGetLastError();
 }
 
