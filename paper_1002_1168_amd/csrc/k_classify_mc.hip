@@ -124,49 +124,56 @@ __global__ __launch_bounds__(256) void classify_kernel(const JobDesc *jobs, int 
     });
 }
 
+// (x + y + 1) >> 1 in each of the four bytes: x + y = 2 (x & y) + (x ^ y),
+// so the rounded-up half is (x | y) - ((x ^ y) >> 1), with no borrow
+// between bytes.
+__device__ __forceinline__ uint32_t avg2_u8x4(uint32_t x, uint32_t y) {
+    return (x | y) - ((x ^ y) >> 1 & 0x7F7F7F7Fu);
+}
+
+// (a + b + c + d + 2) >> 2 in each of the four bytes: the even and the odd
+// bytes summed in 16-bit fields (at most 1022, no carry between fields).
+__device__ __forceinline__ uint32_t avg4_u8x4(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    constexpr uint32_t M = 0x00FF00FFu;
+    const uint32_t ev = (a & M) + (b & M) + (c & M) + (d & M) + 0x00020002u;
+    const uint32_t od = (a >> 8 & M) + (b >> 8 & M) + (c >> 8 & M) + (d >> 8 & M) + 0x00020002u;
+    return (ev >> 2 & M) | (od << 6 & ~M);
+}
+
 // One row of the prediction from reference rows a (at the row's own vertical
 // offset) and c (the row below), 20 bytes each from the integer column:
-// MPEG-4 bilinear interpolation with rounding control 0.
+// MPEG-4 bilinear interpolation with rounding control 0, four pixels per
+// word.  The right neighbours of a word's pixels are the bytes one further
+// along the row (the word and the next one, aligned by one byte).
 __device__ __forceinline__ void bilinear_row(const uint32_t (&a)[5], const uint32_t (&c)[5], int fx, int fy,
                                              uint32_t (&out)[4]) {
-    if (!fx && !fy) {
-#pragma unroll
-        for (int w = 0; w < 4; ++w) out[w] = a[w];
-        return;
-    }
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-        uint32_t o = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int i = 4 * w + b;
-            const int A = byte_of(a[i >> 2], i & 3), B = byte_of(a[(i + 1) >> 2], (i + 1) & 3);
-            const int Cc = byte_of(c[i >> 2], i & 3), D = byte_of(c[(i + 1) >> 2], (i + 1) & 3);
-            const int p = (fx && fy) ? ((A + B + Cc + D + 2) >> 2) : fx ? ((A + B + 1) >> 1) : ((A + Cc + 1) >> 1);
-            o |= (uint32_t)p << (8 * b);
-        }
-        out[w] = o;
+        const uint32_t ar = __builtin_amdgcn_alignbyte(a[w + 1], a[w], 1);
+        const uint32_t cr = __builtin_amdgcn_alignbyte(c[w + 1], c[w], 1);
+        out[w] = fx ? (fy ? avg4_u8x4(a[w], ar, c[w], cr) : avg2_u8x4(a[w], ar)) : (fy ? avg2_u8x4(a[w], c[w]) : a[w]);
     }
 }
 
-// Rows y and y+1 (16 pixels from column x) of the prediction by the half-pel
-// vector (hx, hy): reference rows y+iy .. y+iy+2, coordinates clamped to the
-// frame.  The last row is used only for a vertical half-pel; it is read when
-// some lane of the wave has one (a branch per lane would wait for each of its
-// loads on its own).
-__device__ __forceinline__ void predict_rows2(const uint8_t *ref, int st, int W, int H, int x, int y, int hx,
-                                              int hy, uint32_t (&p0)[4], uint32_t (&p1)[4]) {
+// Rows y .. y+R-1 (16 pixels from column x) of the prediction by the
+// half-pel vector (hx, hy): reference rows y+iy .. y+iy+R, coordinates
+// clamped to the frame.  The last row is used only for a vertical half-pel;
+// it is read when some lane of the wave has one (a branch per lane would wait
+// for each of its loads on its own).
+template <int R>
+__device__ __forceinline__ void predict_rows(const uint8_t *ref, int st, int W, int H, int x, int y, int hx, int hy,
+                                             uint32_t (&p)[R][4]) {
     const int ix = hx >> 1, iy = hy >> 1, fx = hx & 1, fy = hy & 1;
-    uint32_t r[3][5];
+    uint32_t r[R + 1][5];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < R; ++t) {
         const uint8_t *row = ref + (size_t)iclamp(y + iy + t, 0, H - 1) * st;
 #pragma unroll
         for (int w = 0; w < 5; ++w) r[t][w] = ld4_clamped(row, x + ix + 4 * w, W);
     }
     // the loads of the last row in one block, their byte permutes after it
     uint32_t raw[5] = {0u, 0u, 0u, 0u, 0u}, sel[5];
-    const uint8_t *row2 = ref + (size_t)iclamp(y + iy + 2, 0, H - 1) * st;
+    const uint8_t *rowl = ref + (size_t)iclamp(y + iy + R, 0, H - 1) * st;
 #pragma unroll
     for (int w = 0; w < 5; ++w) {
         const int xx = x + ix + 4 * w, xc = iclamp(xx, 0, W - 4);
@@ -176,12 +183,12 @@ __device__ __forceinline__ void predict_rows2(const uint8_t *ref, int st, int W,
     }
     if (__ballot(fy) != 0) {
 #pragma unroll
-        for (int w = 0; w < 5; ++w) raw[w] = ld4(row2 + raw[w]);
+        for (int w = 0; w < 5; ++w) raw[w] = ld4(rowl + raw[w]);
     }
 #pragma unroll
-    for (int w = 0; w < 5; ++w) r[2][w] = __builtin_amdgcn_perm(raw[w], raw[w], sel[w]);
-    bilinear_row(r[0], r[1], fx, fy, p0);
-    bilinear_row(r[1], r[2], fx, fy, p1);
+    for (int w = 0; w < 5; ++w) r[R][w] = __builtin_amdgcn_perm(raw[w], raw[w], sel[w]);
+#pragma unroll
+    for (int t = 0; t < R; ++t) bilinear_row(r[t], r[t + 1], fx, fy, p[t]);
 }
 
 // Squared error of one 16-pixel row over the pixels whose alpha is set: with
@@ -226,19 +233,20 @@ __device__ __forceinline__ void mc_mb(const JobCursor &c, int k, int cl, int t, 
     const int x = 16 * h, y = 16 * v + 2 * t;
     const uint32_t w = FOUR ? ldg32(mv + 4 * k + 2 * (t >> 2)) : ldg32(mv + k);
     const size_t o0 = (size_t)y * st + x, o1 = o0 + st;
-    const u32x4 c0 = ld16(cur + o0), c1 = ld16(cur + o1);
-    uint32_t in0 = 0xFFFFu, in1 = 0xFFFFu;
-    if (alpha) {
-        in0 = nz16v(ld16(alpha + o0));
-        in1 = nz16v(ld16(alpha + o1));
-    }
+    // the alpha rows are loaded unconditionally (the current rows again when
+    // there is no alpha plane) and used last, so that all loads are in flight
+    // together: the scheduler would otherwise wait for each alpha row before
+    // the next one's load
+    const uint8_t *ap = alpha ? alpha : cur;
+    const u32x4 c0 = ld16(cur + o0), c1 = ld16(cur + o1), a0 = ld16(ap + o0), a1 = ld16(ap + o1);
+    __builtin_amdgcn_sched_barrier(0);
     int hx = 0, hy = 0;
     if (cl != ME_MB_TRANSPARENT) {
         hx = (int)(int16_t)(w & 0xFFFF);
         hy = (int)(int16_t)(w >> 16);
     }
-    uint32_t p0[4], p1[4];
-    predict_rows2(ref, st, W, H, x, y, hx, hy, p0, p1);
+    uint32_t p[2][4];
+    predict_rows<2>(ref, st, W, H, x, y, hx, hy, p);
     if constexpr (FOUR) {
         // the right 8 pixels by the pair's second block vector
         const uint32_t w2 = ldg32(mv + 4 * k + 2 * (t >> 2) + 1);
@@ -247,18 +255,19 @@ __device__ __forceinline__ void mc_mb(const JobCursor &c, int k, int cl, int t, 
             hx2 = (int)(int16_t)(w2 & 0xFFFF);
             hy2 = (int)(int16_t)(w2 >> 16);
         }
-        uint32_t q0[4], q1[4];
-        predict_rows2(ref, st, W, H, x, y, hx2, hy2, q0, q1);
-        p0[2] = q0[2];
-        p0[3] = q0[3];
-        p1[2] = q1[2];
-        p1[3] = q1[3];
+        uint32_t q[2][4];
+        predict_rows<2>(ref, st, W, H, x, y, hx2, hy2, q);
+        p[0][2] = q[0][2];
+        p[0][3] = q[0][3];
+        p[1][2] = q[1][2];
+        p[1][3] = q[1][3];
     }
     if (store && out) {
-        st16(out + o0, p0);
-        st16(out + o1, p1);
+        st16(out + o0, p[0]);
+        st16(out + o1, p[1]);
     }
-    sse = row_sse(c0, p0, in0) + row_sse(c1, p1, in1);
+    const uint32_t in0 = alpha ? nz16v(a0) : 0xFFFFu, in1 = alpha ? nz16v(a1) : 0xFFFFu;
+    sse = row_sse(c0, p[0], in0) + row_sse(c1, p[1], in1);
     cnt = __builtin_popcount(in0) + __builtin_popcount(in1);
 }
 
@@ -294,21 +303,59 @@ __device__ __forceinline__ void st64(uint32_t *p, unsigned long long v) {
     *(__attribute__((address_space(1))) unsigned long long *)p = v;
 }
 
+// SSE and pixel count of MB k predicted by the half-pel vector word w, by
+// four lanes: lane t takes rows 4t .. 4t+3.
+__device__ __forceinline__ void mc_sums_mb(const JobCursor &c, int k, uint32_t w, int t, int &sse, int &cnt) {
+    const uint8_t *cur = c.ptr<const uint8_t>(DWI(cur));
+    const uint8_t *ref = c.ptr<const uint8_t>(DWI(ref));
+    const uint8_t *alpha = c.ptr<const uint8_t>(DWI(cur_a));
+    const int W = c.i32(DWI(width)), H = c.i32(DWI(height)), st = c.i32(DWI(stride)), wm = c.i32(DWI(wm));
+    const int x = 16 * (k % wm), y = 16 * (k / wm) + 4 * t;
+    // all loads of the current and alpha rows before any use (alpha rows
+    // unconditionally, the current rows again when there is no alpha plane)
+    const uint8_t *ap = alpha ? alpha : cur;
+    u32x4 cr[4], ar[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        cr[i] = ld16(cur + (size_t)(y + i) * st + x);
+        ar[i] = ld16(ap + (size_t)(y + i) * st + x);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t p[4][4];
+    predict_rows<4>(ref, st, W, H, x, y, (int)(int16_t)(w & 0xFFFF), (int)(int16_t)(w >> 16), p);
+    sse = 0;
+    cnt = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t in = alpha ? nz16v(ar[i]) : 0xFFFFu;
+        sse += row_sse(cr[i], p[i], in);
+        cnt += __builtin_popcount(in);
+    }
+}
+
 // The same sums without a prediction frame.  A transparent MB has no pixel
 // with alpha != 0 (its class is the classification of the current alpha),
 // so its SSE and pixel count are zero whatever its prediction: such MBs cost
-// one class byte and a zero partial.  One lane per MB reads the classes of
-// 64 consecutive MBs; the others are compacted in LDS (wave-private) and
-// predicted eight lanes per MB as in mc_kernel.
+// one class byte and a zero partial.  One lane per MB reads the class and
+// the vector of 64 consecutive MBs in one round trip; the other MBs are
+// compacted in LDS (wave-private) with their vectors and predicted four
+// lanes per MB, 16 MBs per round.
 __global__ __launch_bounds__(256) void mc_sums_kernel(const JobDesc *jobs, int n, int total, int chunk,
                                                       uint32_t *part, uint32_t *status) {
-    __shared__ int list_k[4][64], list_c[4][64];
-    int *lk = list_k[threadIdx.x >> 6], *lc = list_c[threadIdx.x >> 6];
-    const int t = lane() & 7, g = lane() >> 3;
+    __shared__ int list_k[4][64];
+    __shared__ uint32_t list_w[4][64];
+    int *lk = list_k[threadIdx.x >> 6];
+    uint32_t *lw = list_w[threadIdx.x >> 6];
+    const int t = lane() & 3, g = lane() >> 2;
     for_units<1>(jobs, n, total, chunk, [&](const JobCursor &c, int k, int mb, bool on) {
         const uint8_t *cls = c.ptr<const uint8_t>(DWI(cls));
+        const uint32_t *mv = c.ptr<const uint32_t>(DWI(mv));
         int cl = ME_MB_OPAQUE;
-        if (cls && on) cl = (int)ldg8(cls + k);
+        uint32_t w = 0u;
+        if (on) {
+            if (cls) cl = (int)ldg8(cls + k);
+            w = ldg32(mv + k);
+        }
         if (on && cl > ME_MB_BOUNDARY) atomicOr(status, ST_BAD_CLASS);
         const bool act = on && cl != ME_MB_TRANSPARENT;
         if (on && !act) st64(part + 2 * (size_t)mb, 0ull);
@@ -319,19 +366,20 @@ __global__ __launch_bounds__(256) void mc_sums_kernel(const JobDesc *jobs, int n
         __builtin_amdgcn_wave_barrier();
         if (act) {
             lk[pos] = k;
-            lc[pos] = cl;
+            lw[pos] = w;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const int cnt_act = __popcll(m);
-        for (int i = 0; i < cnt_act; i += 8) {
+        for (int i = 0; i < cnt_act; i += 16) {
             const bool live = i + g < cnt_act;
-            const int kk = lk[live ? i + g : i], ckk = lc[live ? i + g : i];
+            const int e = live ? i + g : i;
+            const int kk = lk[e];
             int sse, cnt;
-            mc_mb<false>(c, kk, ckk, t, false, sse, cnt);
-            sse = sum8(sse);
-            cnt = sum8(cnt);
+            mc_sums_mb(c, kk, lw[e], t, sse, cnt);
+            sse = sum4(sse);
+            cnt = sum4(cnt);
             if (live && t == 0) st64(part + 2 * ((size_t)c.base + kk), (unsigned long long)(uint32_t)sse |
                                                                             ((unsigned long long)(uint32_t)cnt << 32));
         }
@@ -398,7 +446,9 @@ hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s) {
 // per_cu blocks per CU.
 int flat_chunk(int total_units, int per_cu) {
     int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
     long long blocks = (long long)(cus > 0 ? cus : 256) * per_cu;
     long long c = (total_units + blocks - 1) / blocks;
     return (int)(c < 1 ? 1 : c);
