@@ -405,9 +405,8 @@ int me_batch_set_config(me_batch *b, const int32_t *cfg, int ncfg);
 /* Kernel durations inside the batch's graph: when me_kernel_timing has kind
  * k (ME_KT_CLASSIFY, ME_KT_SEARCH, ME_KT_MC, ME_KT_NET) on at the time the
  * graph is captured (me_batch_create, me_batch_set_net, me_batch_set_config),
- * every replay records an event pair around that kernel on the batch's
- * stream (the frame step is then captured as several graphs, cut at the
- * timed kernels, launched back to back with the events between them).
+ * every replay records an event pair around that kernel (event-record
+ * nodes of the graph, added in the stream's capture order).
  * Waits for the replays, writes the sum of their durations (ms) and their
  * number, and restarts both at zero.  Zero counts when not timed. */
 int me_batch_kernel_time_ms(me_batch *b, int kind, double *total_ms, int *count);

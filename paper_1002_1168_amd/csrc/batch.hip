@@ -23,15 +23,6 @@ using namespace me::host;
 // baselines (unused), MC, network forward
 constexpr int kBatchKinds = ME_KT_NET + 1;
 
-// One element of a captured frame step: a graph piece, or (exec null) the
-// start / stop event of a timed kernel kind.
-struct Piece {
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int kind = -1;
-    bool start = false;
-};
-
 struct me_batch {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -43,14 +34,14 @@ struct me_batch {
     uint8_t *dev = nullptr;         // one allocation, layout below
     size_t o_zero = 0, zero_bytes = 0, rows_zero_bytes = 0, o_pscr = 0, o_part = 0, o_acc = 0, o_status = 0;
     void *host[2] = {nullptr, nullptr};  // pinned job-table staging
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    int slot = 0;
+    hipEvent_t ev[2] = {nullptr, nullptr};  // recorded after the last untimed use of host[i]
     unsigned long long *host_acc = nullptr;
-    // The frame step as one graph; with kernel timing on at capture, as a
-    // sequence of graph pieces cut at the timed kernels, replayed with event
-    // records between the pieces (two event sets used alternately, so that
-    // one replay's events are read while the next runs).
-    std::vector<Piece> pieces;
+    // The frame step as two graphs used alternately: graph i copies the job
+    // table from host[i], runs the step, and (kernel timing on at capture)
+    // records event set i around the timed kernels as event nodes, so that
+    // one replay's table and events are free while the next replay runs.
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
     uint32_t timed = 0;                           // bit k: kind k (ME_KT_*) is timed
     KernelTimer tm[2][kBatchKinds];               // event pairs per set and kind
     bool pending[2] = {false, false};             // a replay with event set i whose events are unread
@@ -226,7 +217,7 @@ int autotune(me_batch &b) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess) return ME_EHIP;
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return ME_EHIP;
     }
     const Bufs u = bufs(b);
@@ -312,61 +303,51 @@ int autotune(me_batch &b) {
             best[3] = pc;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc == ME_OK)
         for (int i = 0; i < 6; ++i) b.cfg[i] = best[i];
     return rc;
 }
 
 void drop_graphs(me_batch &b) {
-    for (auto &p : b.pieces) {
-        if (p.exec) hipGraphExecDestroy(p.exec);
-        if (p.graph) hipGraphDestroy(p.graph);
+    for (int i = 0; i < 2; ++i) {
+        if (b.exec[i]) (void)hipGraphExecDestroy(b.exec[i]);
+        if (b.graph[i]) (void)hipGraphDestroy(b.graph[i]);
+        b.exec[i] = nullptr;
+        b.graph[i] = nullptr;
     }
-    b.pieces.clear();
     b.pending[0] = b.pending[1] = false;
 }
 
-// Capture state while the frame step is recorded in pieces.
+// Capture state: the event set whose records become event nodes, and the
+// kinds whose stop node was added.
 struct CaptureCtx {
     me_batch *b;
-    hipStream_t cs;
+    int set;
     hipError_t err;
+    uint32_t stopped;
 };
 
-// End the capture in progress, keep it as a piece (unless it is empty), and
-// start the next one.
-hipError_t cut_piece(CaptureCtx &c) {
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(c.cs, &g);
-    if (e != hipSuccess || !g) return e != hipSuccess ? e : hipErrorUnknown;
-    size_t nodes = 0;
-    e = hipGraphGetNodes(g, nullptr, &nodes);
-    if (e == hipSuccess && nodes > 0) {
-        Piece p;
-        p.graph = g;
-        e = hipGraphInstantiate(&p.exec, g, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            hipGraphDestroy(g);
-            return e;
-        }
-        c.b->pieces.push_back(p);
-    } else {
-        hipGraphDestroy(g);
-        if (e != hipSuccess) return e;
-    }
-    return hipStreamBeginCapture(c.cs, hipStreamCaptureModeRelaxed);
-}
-
-void split_at_mark(void *ctx, int kind, bool start, hipStream_t) {
+// A timed kernel's start or stop, added as an event-record node of the
+// graph being captured after the stream's current capture dependencies,
+// which it then replaces.
+void record_node(void *ctx, int kind, bool start, hipStream_t s) {
     CaptureCtx &c = *(CaptureCtx *)ctx;
     if (c.err != hipSuccess) return;
-    c.err = cut_piece(c);
-    Piece p;
-    p.kind = kind;
-    p.start = start;
-    c.b->pieces.push_back(p);
+    const KernelTimer &t = c.b->tm[c.set][kind];
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    unsigned long long id = 0;
+    hipGraph_t g = nullptr;
+    const hipGraphNode_t *deps = nullptr;
+    size_t ndeps = 0;
+    c.err = hipStreamGetCaptureInfo_v2(s, &st, &id, &g, &deps, &ndeps);
+    if (c.err == hipSuccess && (st != hipStreamCaptureStatusActive || !g)) c.err = hipErrorStreamCaptureInvalidated;
+    if (c.err != hipSuccess) return;
+    hipGraphNode_t node = nullptr;
+    c.err = hipGraphAddEventRecordNode(&node, g, deps, ndeps, start ? t.start : t.stop);
+    if (c.err == hipSuccess) c.err = hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies);
+    if (c.err == hipSuccess && !start) c.stopped |= 1u << kind;
 }
 
 // Sum the event pairs of event set i's last replay (waits for it).
@@ -384,9 +365,9 @@ void harvest(me_batch &b, int i) {
     }
 }
 
-// Capture the frame step: one graph, or (kernel timing on for some kinds
-// now) graph pieces cut at those kinds' kernels.  Waits for the stream first
-// (earlier replays' events are harvested).
+// Capture the two graphs of the frame step (kernel timing as now in
+// force).  Waits for the stream first (earlier replays' events are
+// harvested).
 int capture(me_batch &b) {
     if (hipStreamSynchronize(b.stream) != hipSuccess) return ME_EHIP;
     for (int i = 0; i < 2; ++i) harvest(b, i);
@@ -402,84 +383,79 @@ int capture(me_batch &b) {
         }
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return ME_EHIP;
-    CaptureCtx ctx{&b, cs, hipSuccess};
-    KernelTimer marks[kBatchKinds];
-    for (int k = 0; k < kBatchKinds; ++k) {
-        marks[k].split = split_at_mark;
-        marks[k].ctx = &ctx;
-        marks[k].kind = k;
-    }
+    const size_t table = sizeof(JobDesc) * (size_t)b.n;
     int rc = ME_OK;
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
-        rc = ME_EHIP;
-    } else {
-        hipError_t e = launch_step(b, b.cfg, cs, marks, b.timed);
+    uint32_t stopped = b.timed;
+    for (int i = 0; i < 2 && rc == ME_OK; ++i) {
+        CaptureCtx ctx{&b, i, hipSuccess, 0u};
+        KernelTimer marks[kBatchKinds];
+        for (int k = 0; k < kBatchKinds; ++k) {
+            marks[k].split = record_node;
+            marks[k].ctx = &ctx;
+            marks[k].kind = k;
+        }
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+            rc = ME_EHIP;
+            break;
+        }
+        hipError_t e = hipMemcpyAsync(b.dev + b.plan.o_jobs, b.host[i], table, hipMemcpyHostToDevice, cs);
+        if (e == hipSuccess) e = launch_step(b, b.cfg, cs, marks, b.timed);
         if (e == hipSuccess) e = ctx.err;
+        stopped &= ctx.stopped;
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = ee != hipSuccess ? ee : (g ? hipSuccess : hipErrorUnknown);
         if (e == hipSuccess) {
-            hipGraph_t g = nullptr;
-            e = hipStreamEndCapture(cs, &g);
-            if (e == hipSuccess && g) {
-                Piece p;
-                p.graph = g;
-                e = hipGraphInstantiate(&p.exec, g, nullptr, nullptr, 0);
-                if (e == hipSuccess) {
-                    b.pieces.push_back(p);
-                } else {
-                    hipGraphDestroy(g);
-                }
-            } else if (e == hipSuccess) {
-                e = hipErrorUnknown;
-            }
-        } else {
-            hipGraph_t g = nullptr;
-            if (hipStreamEndCapture(cs, &g) == hipSuccess && g) hipGraphDestroy(g);
+            b.graph[i] = g;
+            e = hipGraphInstantiate(&b.exec[i], g, nullptr, nullptr, 0);
+            if (e != hipSuccess) b.exec[i] = nullptr;
+        } else if (g) {
+            (void)hipGraphDestroy(g);
         }
         if (e != hipSuccess) rc = ME_EHIP;
     }
-    hipStreamDestroy(cs);
+    (void)hipStreamDestroy(cs);
+    // timed kinds are those with event nodes in the graphs (a kind whose
+    // kernel was not launched has none)
+    b.timed = rc ? 0u : stopped;
     if (rc) drop_graphs(b);
     return rc;
 }
 
-// One replay of the captured frame step on the batch's stream (event set
-// `set` for the timed kinds).
-hipError_t replay(me_batch &b, int set) {
-    for (const Piece &p : b.pieces) {
-        hipError_t e = p.exec ? hipGraphLaunch(p.exec, b.stream)
-                              : hipEventRecord(p.start ? b.tm[set][p.kind].start : b.tm[set][p.kind].stop, b.stream);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+// Job table i staged for `jobs`: waits until its previous copy is done.
+int stage_table(me_batch &b, const me_job *jobs, int i) {
+    if (hipEventSynchronize(b.ev[i]) != hipSuccess) return ME_EHIP;
+    fill_table(b, jobs, (JobDesc *)b.host[i]);
+    return ME_OK;
 }
 
+// The job table for `jobs` copied outside the graphs (staging 0).
 int upload_table(me_batch &b, const me_job *jobs) {
-    const size_t bytes = sizeof(JobDesc) * (size_t)b.n;
-    const int s = b.slot;
-    b.slot ^= 1;
-    if (hipEventSynchronize(b.ev[s]) != hipSuccess) return ME_EHIP;
-    fill_table(b, jobs, (JobDesc *)b.host[s]);
-    if (hipMemcpyAsync(b.dev + b.plan.o_jobs, b.host[s], bytes, hipMemcpyHostToDevice, b.stream) != hipSuccess)
+    int rc = stage_table(b, jobs, 0);
+    if (rc) return rc;
+    if (hipMemcpyAsync(b.dev + b.plan.o_jobs, b.host[0], sizeof(JobDesc) * (size_t)b.n, hipMemcpyHostToDevice,
+                       b.stream) != hipSuccess)
         return ME_EHIP;
-    if (hipEventRecord(b.ev[s], b.stream) != hipSuccess) return ME_EHIP;
+    if (hipEventRecord(b.ev[0], b.stream) != hipSuccess) return ME_EHIP;
     return ME_OK;
 }
 
 void release(me_batch *b) {
     if (!b) return;
-    if (b->stream || b->dev) hipStreamSynchronize(b->stream);
+    if (b->stream || b->dev) (void)hipStreamSynchronize(b->stream);
     drop_graphs(*b);
     for (auto &row : b->tm)
         for (auto &t : row) {
-            if (t.start) hipEventDestroy(t.start);
-            if (t.stop) hipEventDestroy(t.stop);
+            if (t.start) (void)hipEventDestroy(t.start);
+            if (t.stop) (void)hipEventDestroy(t.stop);
         }
     for (int s = 0; s < 2; ++s) {
-        if (b->ev[s]) hipEventDestroy(b->ev[s]);
-        if (b->host[s]) hipHostFree(b->host[s]);
+        if (b->ev[s]) (void)hipEventDestroy(b->ev[s]);
+        if (b->host[s]) (void)hipHostFree(b->host[s]);
     }
-    if (b->host_acc) hipHostFree(b->host_acc);
-    if (b->net_scratch) hipFree(b->net_scratch);
-    if (b->dev) hipFree(b->dev);
+    if (b->host_acc) (void)hipHostFree(b->host_acc);
+    if (b->net_scratch) (void)hipFree(b->net_scratch);
+    if (b->dev) (void)hipFree(b->dev);
     delete b;
 }
 
@@ -585,11 +561,15 @@ int me_batch_step(me_batch *b, const me_job *jobs, int n) {
     std::lock_guard<std::mutex> lk(b->mu);
     int rc = check_structure(*b, jobs, n);
     if (rc) return rc;
-    rc = upload_table(*b, jobs);
-    if (rc) return rc;
     const int set = (int)(b->replays & 1);
-    harvest(*b, set);  // that event set's previous replay (the other one may still run)
-    if (replay(*b, set) != hipSuccess) return ME_EHIP;
+    harvest(*b, set);  // that set's previous replay (the other one may still run)
+    rc = stage_table(*b, jobs, set);
+    if (rc) return rc;
+    if (hipGraphLaunch(b->exec[set], b->stream) != hipSuccess) return ME_EHIP;
+    // the next use of table `set` waits for this replay's copy: through the
+    // event set's stop events (harvest) when kernels are timed, which come
+    // after the copy, else through ev[set]
+    if (!b->timed && hipEventRecord(b->ev[set], b->stream) != hipSuccess) return ME_EHIP;
     b->pending[set] = b->timed != 0;
     b->replays++;
     b->stepped = true;
