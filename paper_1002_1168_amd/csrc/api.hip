@@ -12,12 +12,12 @@
 #include <unordered_map>
 #include <vector>
 
+#include "flat_kernels.h"
 #include "host.h"
 #include "me_internal.h"
 
 namespace me {
 size_t es_lds_bytes(int S);
-hipError_t launch_pad(const JobDesc *jobs, int n, int max_mbs, uint8_t *cls_all, hipStream_t s);
 }
 
 using namespace me;

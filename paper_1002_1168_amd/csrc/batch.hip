@@ -13,6 +13,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "flat_kernels.h"
 #include "host.h"
 #include "me_internal.h"
 
@@ -32,7 +33,7 @@ struct me_batch {
     PaMemo plan;                    // chain structure, tickets, descriptor template
     std::vector<JobDesc> tmpl;      // chain-ordered descriptors of the creating job set
     uint8_t *dev = nullptr;         // one allocation, layout below
-    size_t o_zero = 0, zero_bytes = 0, rows_zero_bytes = 0, o_pscr = 0, o_part = 0, o_acc = 0, o_status = 0;
+    size_t o_zero = 0, zero_bytes = 0, rows_zero_bytes = 0, o_pscr = 0, o_acc = 0, o_status = 0;
     void *host[2] = {nullptr, nullptr};  // pinned job-table staging
     hipEvent_t ev[2] = {nullptr, nullptr};  // recorded after the last untimed use of host[i]
     unsigned long long *host_acc = nullptr;
@@ -121,7 +122,7 @@ struct Bufs {
     const uint32_t *bands;
     uint8_t *zero;
     unsigned long long *progress;
-    uint32_t *counter, *masks, *part, *status;
+    uint32_t *counter, *masks, *status;
     uint8_t *pscr;
     unsigned long long *acc;
 };
@@ -138,7 +139,6 @@ Bufs bufs(const me_batch &b) {
     r.counter = (uint32_t *)(r.zero + align_up((size_t)m.nlines * 8, 256));
     r.masks = (uint32_t *)((uint8_t *)r.counter + 256);
     r.pscr = b.dev + b.o_pscr;
-    r.part = (uint32_t *)(b.dev + b.o_part);
     r.acc = (unsigned long long *)(b.dev + b.o_acc);
     r.status = (uint32_t *)(b.dev + b.o_status);
     return r;
@@ -150,19 +150,31 @@ KParams batch_kparams(const me_batch &b, int sleep) {
     return kp;
 }
 
+// Words of the search scratch that start at zero: row workers need only the
+// row progress counts and the ticket counter.
+size_t zero_words(const me_batch &b, const int32_t *cfg) { return (cfg[5] ? b.rows_zero_bytes : b.zero_bytes) / 4; }
+
+// The search; `fill`: clear its scratch first (else the caller has).
 hipError_t launch_search(const me_batch &b, const Bufs &u, const int32_t *cfg, hipStream_t s,
-                         const KernelTimer *t = nullptr) {
-    if (cfg[5]) {  // row workers: only the row progress counts and the ticket counter start at zero
-        hipError_t e = launch_fill_u32((uint32_t *)u.zero, b.rows_zero_bytes / 4, 0u, s);
+                         const KernelTimer *t = nullptr, bool fill = true) {
+    if (fill) {
+        hipError_t e = launch_fill_u32((uint32_t *)u.zero, zero_words(b, cfg), 0u, s);
         if (e != hipSuccess) return e;
+    }
+    if (cfg[5])
         return launch_pa_rows(u.jobs, u.chains, u.bands, b.plan.nbands, u.progress, u.counter, u.status,
                               batch_kparams(b, cfg[2]), cfg[0], s, t, cfg[1] == 0);
-    }
-    hipError_t e = launch_fill_u32((uint32_t *)u.zero, b.zero_bytes / 4, 0u, s);
-    if (e != hipSuccess) return e;
     return launch_pa(u.jobs, b.n, b.plan.total_mbs, u.chains, u.tickets, b.plan.nlines, u.progress, u.counter, u.masks,
                      b.plan.mask_words, u.pscr, u.status, batch_kparams(b, cfg[2]), cfg[0], s, t,
                      cfg[1] == 0, cfg[4]);
+}
+
+// Classification, which also clears the search scratch and the per-job
+// sums; MC + SSE adds into those sums.
+hipError_t launch_classify_step(const me_batch &b, const Bufs &u, const int32_t *cfg, hipStream_t s,
+                                const KernelTimer *t, int per_cu) {
+    return launch_classify_zeroing(u.jobs, b.n, b.plan.total_mbs, (uint32_t *)u.zero, zero_words(b, cfg),
+                                   (uint32_t *)u.acc, (size_t)b.n * 4, s, t, per_cu);
 }
 
 // The whole frame step with configuration `cfg` on stream `s`; `tm` (or
@@ -171,16 +183,15 @@ hipError_t launch_step(const me_batch &b, const int32_t *cfg, hipStream_t s, con
                        uint32_t timed = 0) {
     auto T = [&](int kind) -> const KernelTimer * { return tm && ((timed >> kind) & 1u) ? &tm[kind] : nullptr; };
     const Bufs u = bufs(b);
-    hipError_t e = launch_classify(u.jobs, b.n, b.plan.total_mbs, s, T(ME_KT_CLASSIFY), cfg[3]);
+    hipError_t e = launch_classify_step(b, u, cfg, s, T(ME_KT_CLASSIFY), cfg[3]);
     if (e != hipSuccess) return e;
     if (b.net) {
         e = net_forward_table(b.net, u.jobs, b.n, b.plan.total_mbs, b.net_scratch, s, T(ME_KT_NET));
         if (e != hipSuccess) return e;
     }
-    e = launch_search(b, u, cfg, s, T(ME_KT_SEARCH));
+    e = launch_search(b, u, cfg, s, T(ME_KT_SEARCH), false);
     if (e != hipSuccess) return e;
-    return launch_mc(u.jobs, b.n, b.plan.total_mbs, u.part, u.acc, u.status, s, T(ME_KT_MC), cfg[3], false,
-                     true);
+    return launch_mc_sums_acc(u.jobs, b.n, b.plan.total_mbs, u.acc, u.status, s, T(ME_KT_MC), cfg[3]);
 }
 
 // Read and clear the device status word (blocking); true when it was clear.
@@ -284,10 +295,9 @@ int autotune(me_batch &b) {
     for (int pc : {4, 8, 16}) {
         if (rc) break;
         float ms = time_min(b, e0, e1, [&] {
-            hipError_t e = launch_classify(u.jobs, b.n, b.plan.total_mbs, b.stream, nullptr, pc);
+            hipError_t e = launch_classify_step(b, u, best, b.stream, nullptr, pc);
             if (e != hipSuccess) return e;
-            return launch_mc(u.jobs, b.n, b.plan.total_mbs, u.part, u.acc, u.status, b.stream, nullptr, pc, false,
-                             true);
+            return launch_mc_sums_acc(u.jobs, b.n, b.plan.total_mbs, u.acc, u.status, b.stream, nullptr, pc);
         });
         bool clean = false;
         if (ms < 0.f || !status_clear(b, u, &clean)) {
@@ -493,14 +503,13 @@ int me_batch_create(const me_job *jobs, int n, const me_params *params, uint32_t
     const PaMemo &m = b->plan;
     b->tmpl.resize(n);
     std::memcpy(b->tmpl.data(), m.blob.data() + m.o_jobs, sizeof(JobDesc) * (size_t)n);
-    // device layout: [jobs | chains | tickets] [zeroed search scratch] [ticket compaction] [MC partials]
-    // [per-job sums] [status]
+    // device layout: [jobs | chains | tickets] [zeroed search scratch] [ticket compaction] [per-job sums]
+    // [status]
     b->o_zero = align_up(m.blob.size(), 256);
     b->zero_bytes = align_up(align_up((size_t)m.nlines * 8, 256) + 256 + (size_t)m.nlines * m.mask_words * 2 * 4, 256);
     b->rows_zero_bytes = align_up((size_t)m.nlines * 8, 256) + 256;  // progress words (rows use the first) and counter
     b->o_pscr = b->o_zero + b->zero_bytes;
-    b->o_part = b->o_pscr + align_up(pa_scratch_bytes(m.nlines), 256);
-    b->o_acc = b->o_part + align_up(mc_scratch(m.total_mbs), 256);
+    b->o_acc = b->o_pscr + align_up(pa_scratch_bytes(m.nlines), 256);
     b->o_status = b->o_acc + align_up((size_t)n * 16, 256);
     const size_t total = b->o_status + 256;
     const size_t table = sizeof(JobDesc) * (size_t)n;

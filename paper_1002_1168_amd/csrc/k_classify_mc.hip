@@ -4,7 +4,7 @@
 // classification, eight for MC), each lane whole 16-pixel rows, per-MB sums
 // DPP reductions over those lanes (no atomics); the job of a wave's MBs is a
 // wave-uniform cursor, so descriptor fields live in scalar registers.
-#include "me_internal.h"
+#include "flat_kernels.h"
 
 namespace me {
 
@@ -94,8 +94,15 @@ __device__ __forceinline__ uint32_t nz16v(const u32x4 a) {
 // boundary, written to the job's class array; BAB word w = rows 2w, 2w+1
 // with column i at bit (row&1)*16 + i.  Jobs without alpha or without a
 // class array (rectangular frames) are skipped.  Four lanes per MB, lane
-// t reads rows 4t .. 4t+3 and writes BAB words 2t and 2t+1.
-__global__ __launch_bounds__(256) void classify_kernel(const JobDesc *jobs, int n, int total, int chunk) {
+// t reads rows 4t .. 4t+3 and writes BAB words 2t and 2t+1.  The grid
+// also clears z0[0, n0) and z1[0, n1).
+__global__ __launch_bounds__(256) void classify_kernel(const JobDesc *jobs, int n, int total, int chunk, uint32_t *z0,
+                                                       size_t n0, uint32_t *z1, size_t n1) {
+    if (n0 + n1 > 0) {
+        const size_t stride = (size_t)gridDim.x * blockDim.x;
+        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n0; i += stride) st32(z0 + i, 0u);
+        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n1; i += stride) st32(z1 + i, 0u);
+    }
     const int t = lane() & 3;
     for_units<4>(jobs, n, total, chunk, [&](const JobCursor &c, int k, int, bool on) {
         const uint8_t *alpha = c.ptr<const uint8_t>(DWI(cur_a));
@@ -336,12 +343,15 @@ __device__ __forceinline__ void mc_sums_mb(const JobCursor &c, int k, uint32_t w
 // The same sums without a prediction frame.  A transparent MB has no pixel
 // with alpha != 0 (its class is the classification of the current alpha),
 // so its SSE and pixel count are zero whatever its prediction: such MBs cost
-// one class byte and a zero partial.  One lane per MB reads the class and
+// one class byte (and a zero partial).  One lane per MB reads the class and
 // the vector of 64 consecutive MBs in one round trip; the other MBs are
 // compacted in LDS (wave-private) with their vectors and predicted four
 // lanes per MB, 16 MBs per round.
+// ACC: no partials; each wave adds its totals for the job to acc[2 j],
+// acc[2 j + 1] atomically (an SSE total of 64 MBs fits 32 bits).
+template <bool ACC>
 __global__ __launch_bounds__(256) void mc_sums_kernel(const JobDesc *jobs, int n, int total, int chunk,
-                                                      uint32_t *part, uint32_t *status) {
+                                                      uint32_t *part, unsigned long long *acc, uint32_t *status) {
     __shared__ int list_k[4][64];
     __shared__ uint32_t list_w[4][64];
     int *lk = list_k[threadIdx.x >> 6];
@@ -358,7 +368,7 @@ __global__ __launch_bounds__(256) void mc_sums_kernel(const JobDesc *jobs, int n
         }
         if (on && cl > ME_MB_BOUNDARY) atomicOr(status, ST_BAD_CLASS);
         const bool act = on && cl != ME_MB_TRANSPARENT;
-        if (on && !act) st64(part + 2 * (size_t)mb, 0ull);
+        if (!ACC && on && !act) st64(part + 2 * (size_t)mb, 0ull);
         const unsigned long long m = __ballot(act);
         const int pos = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -372,6 +382,7 @@ __global__ __launch_bounds__(256) void mc_sums_kernel(const JobDesc *jobs, int n
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const int cnt_act = __popcll(m);
+        uint32_t job_sse = 0u, job_cnt = 0u;
         for (int i = 0; i < cnt_act; i += 16) {
             const bool live = i + g < cnt_act;
             const int e = live ? i + g : i;
@@ -380,8 +391,23 @@ __global__ __launch_bounds__(256) void mc_sums_kernel(const JobDesc *jobs, int n
             mc_sums_mb(c, kk, lw[e], t, sse, cnt);
             sse = sum4(sse);
             cnt = sum4(cnt);
-            if (live && t == 0) st64(part + 2 * ((size_t)c.base + kk), (unsigned long long)(uint32_t)sse |
-                                                                            ((unsigned long long)(uint32_t)cnt << 32));
+            if (!ACC && live && t == 0)
+                st64(part + 2 * ((size_t)c.base + kk),
+                     (unsigned long long)(uint32_t)sse | ((unsigned long long)(uint32_t)cnt << 32));
+            if (ACC && live && t == 0) {
+                job_sse += (uint32_t)sse;
+                job_cnt += (uint32_t)cnt;
+            }
+        }
+        if (ACC && cnt_act > 0) {
+            for (int o = 32; o >= 1; o >>= 1) {
+                job_sse += __shfl_xor(job_sse, o, 64);
+                job_cnt += __shfl_xor(job_cnt, o, 64);
+            }
+            if (lane() == 0) {
+                atomicAdd(acc + 2 * c.j, (unsigned long long)job_sse);
+                atomicAdd(acc + 2 * c.j + 1, (unsigned long long)job_cnt);
+            }
         }
     });
 }
@@ -454,16 +480,22 @@ int flat_chunk(int total_units, int per_cu) {
     return (int)(c < 1 ? 1 : c);
 }
 
-hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_t s, const KernelTimer *t,
-                           int per_cu) {
+hipError_t launch_classify_zeroing(const JobDesc *jobs, int n, int total_mbs, uint32_t *z0, size_t n0, uint32_t *z1,
+                                   size_t n1, hipStream_t s, const KernelTimer *t, int per_cu) {
     if (total_mbs <= 0) return hipSuccess;
     const int nu = (total_mbs + 15) / 16;
     const int chunk = (flat_chunk(nu, per_cu) + 3) / 4 * 4;
     timer_mark(t, true, s);
-    hipLaunchKernelGGL(classify_kernel, dim3((nu + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk);
+    hipLaunchKernelGGL(classify_kernel, dim3((nu + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk,
+                       z0, n0, z1, n1);
     hipError_t e = hipGetLastError();
     timer_mark(t, false, s);
     return e;
+}
+
+hipError_t launch_classify(const JobDesc *jobs, int n, int total_mbs, hipStream_t s, const KernelTimer *t,
+                           int per_cu) {
+    return launch_classify_zeroing(jobs, n, total_mbs, nullptr, 0, nullptr, 0, s, t, per_cu);
 }
 
 size_t mc_scratch(int total_mbs) { return (size_t)total_mbs * 8; }
@@ -477,8 +509,8 @@ hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, 
     if (sums_only && !four) {
         const int nu64 = (total_mbs + 63) / 64;
         const int chunk64 = (flat_chunk(nu64, per_cu) + 3) / 4 * 4;
-        hipLaunchKernelGGL(mc_sums_kernel, dim3((nu64 + chunk64 - 1) / chunk64), dim3(256), 0, s, jobs, n, total_mbs,
-                           chunk64, part, status);
+        hipLaunchKernelGGL(mc_sums_kernel<false>, dim3((nu64 + chunk64 - 1) / chunk64), dim3(256), 0, s, jobs, n,
+                           total_mbs, chunk64, part, nullptr, status);
     } else if (four)
         hipLaunchKernelGGL(mc_kernel<true>, dim3((nu + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk,
                            part, status);
@@ -492,6 +524,19 @@ hipError_t launch_mc(const JobDesc *jobs, int n, int total_mbs, uint32_t *part, 
     while (th < kReduceThreads && 4 * th < total_mbs / n) th <<= 1;
     hipLaunchKernelGGL(mc_reduce_kernel, dim3(n), dim3(th), 0, s, jobs, part, acc);
     return hipGetLastError();
+}
+
+hipError_t launch_mc_sums_acc(const JobDesc *jobs, int n, int total_mbs, unsigned long long *acc, uint32_t *status,
+                              hipStream_t s, const KernelTimer *t, int per_cu) {
+    if (total_mbs <= 0) return hipSuccess;
+    const int nu64 = (total_mbs + 63) / 64;
+    const int chunk64 = (flat_chunk(nu64, per_cu) + 3) / 4 * 4;
+    timer_mark(t, true, s);
+    hipLaunchKernelGGL(mc_sums_kernel<true>, dim3((nu64 + chunk64 - 1) / chunk64), dim3(256), 0, s, jobs, n,
+                       total_mbs, chunk64, nullptr, acc, status);
+    hipError_t e = hipGetLastError();
+    timer_mark(t, false, s);
+    return e;
 }
 
 }  // namespace me

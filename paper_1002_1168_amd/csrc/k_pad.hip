@@ -13,7 +13,7 @@
 //    repeated over the block; with no such neighbour every sample is 128.
 // Two launches: the first pads the opaque and boundary MBs and records every
 // MB's class, the second the transparent MBs from their padded neighbours.
-#include "me_internal.h"
+#include "flat_kernels.h"
 
 namespace me {
 
@@ -135,8 +135,6 @@ __global__ __launch_bounds__(64) void pad_outer_kernel(const JobDesc *jobs, cons
 
 }  // namespace
 
-// `cls_all` holds total_mbs class bytes (job i's at its mb_base); `max_mbs`
-// is the largest job's MB count.
 hipError_t launch_pad(const JobDesc *jobs, int n, int max_mbs, uint8_t *cls_all, hipStream_t s) {
     if (n <= 0 || max_mbs <= 0) return hipSuccess;
     const dim3 grid((unsigned)((max_mbs + kPadMbs - 1) / kPadMbs), (unsigned)n);
