@@ -93,37 +93,46 @@ __device__ __forceinline__ uint32_t nz16v(const u32x4 a) {
 // n = number of pixels with alpha != 0 -> transparent (0), opaque (256),
 // boundary, written to the job's class array; BAB word w = rows 2w, 2w+1
 // with column i at bit (row&1)*16 + i.  Jobs without alpha or without a
-// class array (rectangular frames) are skipped.  Four lanes per MB, lane
-// t reads rows 4t .. 4t+3 and writes BAB words 2t and 2t+1.  The grid
-// also clears z0[0, n0) and z1[0, n1).
+// class array (rectangular frames) are skipped.  LPM lanes per MB (2 or
+// 4): lane t reads rows R t .. R t + R - 1 (R = 16 / LPM, all loads in
+// flight together) and writes BAB words R t / 2 .. R (t + 1) / 2 - 1.  The
+// grid also clears z0[0, n0) and z1[0, n1).
+constexpr int kClassifyLanes = 2;
+template <int LPM>
 __global__ __launch_bounds__(256) void classify_kernel(const JobDesc *jobs, int n, int total, int chunk, uint32_t *z0,
                                                        size_t n0, uint32_t *z1, size_t n1) {
+    static_assert(LPM == 2 || LPM == 4, "two or four lanes per MB");
+    constexpr int R = 16 / LPM;
     if (n0 + n1 > 0) {
         const size_t stride = (size_t)gridDim.x * blockDim.x;
         for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n0; i += stride) st32(z0 + i, 0u);
         for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n1; i += stride) st32(z1 + i, 0u);
     }
-    const int t = lane() & 3;
-    for_units<4>(jobs, n, total, chunk, [&](const JobCursor &c, int k, int, bool on) {
+    const int t = lane() & (LPM - 1);
+    for_units<LPM>(jobs, n, total, chunk, [&](const JobCursor &c, int k, int, bool on) {
         const uint8_t *alpha = c.ptr<const uint8_t>(DWI(cur_a));
         uint8_t *cls = c.ptr<uint8_t>(DWI(cls));
         if (!alpha || !cls) return;
         uint32_t *bab = c.ptr<uint32_t>(DWI(out_u32));
         const int wm = c.i32(DWI(wm)), st = c.i32(DWI(stride));
         const int h = k % wm, v = k / wm;
-        const uint8_t *row = alpha + (size_t)(16 * v + 4 * t) * st + 16 * h;
-        u32x4 a[4];
+        const uint8_t *row = alpha + (size_t)(16 * v + R * t) * st + 16 * h;
+        u32x4 a[R];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = ld16(row + (size_t)i * st);
-        uint32_t bits[4];
+        for (int i = 0; i < R; ++i) a[i] = ld16(row + (size_t)i * st);
+        uint32_t bits[R];
+        int cnt = 0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) bits[i] = nz16v(a[i]);
-        const int tot = sum4(__builtin_popcount(bits[0]) + __builtin_popcount(bits[1]) +
-                             __builtin_popcount(bits[2]) + __builtin_popcount(bits[3]));
+        for (int i = 0; i < R; ++i) {
+            bits[i] = nz16v(a[i]);
+            cnt += __builtin_popcount(bits[i]);
+        }
+        const int tot = LPM == 4 ? sum4(cnt) : cnt + __builtin_amdgcn_update_dpp(0, cnt, 0xB1, 0xF, 0xF, true);
         if (on) {
             if (bab) {
-                st32(bab + (size_t)k * 8 + 2 * t, bits[0] | (bits[1] << 16));
-                st32(bab + (size_t)k * 8 + 2 * t + 1, bits[2] | (bits[3] << 16));
+#pragma unroll
+                for (int i = 0; i < R / 2; ++i)
+                    st32(bab + (size_t)k * 8 + (R / 2) * t + i, bits[2 * i] | (bits[2 * i + 1] << 16));
             }
             if (t == 0)
                 st8(cls + k, (uint8_t)(tot == 0 ? ME_MB_TRANSPARENT : (tot == 256 ? ME_MB_OPAQUE : ME_MB_BOUNDARY)));
@@ -483,11 +492,12 @@ int flat_chunk(int total_units, int per_cu) {
 hipError_t launch_classify_zeroing(const JobDesc *jobs, int n, int total_mbs, uint32_t *z0, size_t n0, uint32_t *z1,
                                    size_t n1, hipStream_t s, const KernelTimer *t, int per_cu) {
     if (total_mbs <= 0) return hipSuccess;
-    const int nu = (total_mbs + 15) / 16;
+    constexpr int per_unit = 64 / kClassifyLanes;
+    const int nu = (total_mbs + per_unit - 1) / per_unit;
     const int chunk = (flat_chunk(nu, per_cu) + 3) / 4 * 4;
     timer_mark(t, true, s);
-    hipLaunchKernelGGL(classify_kernel, dim3((nu + chunk - 1) / chunk), dim3(256), 0, s, jobs, n, total_mbs, chunk,
-                       z0, n0, z1, n1);
+    hipLaunchKernelGGL(classify_kernel<kClassifyLanes>, dim3((nu + chunk - 1) / chunk), dim3(256), 0, s, jobs, n,
+                       total_mbs, chunk, z0, n0, z1, n1);
     hipError_t e = hipGetLastError();
     timer_mark(t, false, s);
     return e;
