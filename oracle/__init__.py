@@ -46,7 +46,7 @@ class _Pair(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("search_range", C.c_int), ("theta", C.c_int), ("eps_q12", C.c_int),
                 ("max_step", C.c_int), ("k_max", C.c_int), ("half_pel", C.c_int),
-                ("unrestricted", C.c_int), ("t_texture", C.c_int)]
+                ("unrestricted", C.c_int), ("t_texture", C.c_int), ("masked_prs", C.c_int)]
 
 
 @dataclass
@@ -59,10 +59,12 @@ class Params:
     half_pel: int = 0
     unrestricted: int = 0
     t_texture: int = 0
+    masked_prs: int = 0
 
     def _c(self) -> _Params:
         return _Params(self.search_range, self.theta, self.eps_q12, self.max_step,
-                       self.k_max, int(self.half_pel), int(self.unrestricted), int(self.t_texture))
+                       self.k_max, int(self.half_pel), int(self.unrestricted), int(self.t_texture),
+                       int(self.masked_prs))
 
 
 _lib = None

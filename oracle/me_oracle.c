@@ -45,6 +45,7 @@ typedef struct {
     int half_pel;     /* 1: half-sample refinement of texture MBs */
     int unrestricted; /* 1: vectors limited by S only, the reference extended by its edge pixels */
     int t_texture;    /* 1: Section 3.1 text - a boundary MB's T is scored on texture */
+    int masked_prs;   /* 1: a boundary MB's recursion refines on luma over the current VOP's pixels */
 } or_params;
 
 /* ------------------------------------------------------------ helpers */
@@ -197,14 +198,17 @@ int32_t or_recip(int g, int theta) {
  * central differences of the reference at p + d (coordinates clamped to the
  * frame).  The per-pixel updates e * u are averaged over the pixels whose
  * gradient passes the threshold, per component, in Q.12 (C division).
+ * `mask` (NULL: every pixel) restricts the pass to the pixels where it is
+ * non-zero: the current VOP's pixels when a boundary MB refines on texture.
  */
-static void prs_pass_n(const or_pair *fp, int shape, int theta, int x0, int y0, int n, int dx, int dy, int32_t *ux,
-                       int32_t *uy) {
+static void prs_pass_n(const or_pair *fp, int shape, const uint8_t *mask, int theta, int x0, int y0, int n, int dx,
+                       int dy, int32_t *ux, int32_t *uy) {
     int32_t sx = 0, sy = 0;
     int nx = 0, ny = 0;
     for (int j = 0; j < n; ++j) {
         for (int i = 0; i < n; ++i) {
             int px = x0 + i, py = y0 + j;
+            if (mask && mask[(size_t)py * fp->stride + px] == 0) continue;
             int rx = px + dx, ry = py + dy;
             int e = plane_cur(fp, shape, px, py) - plane_ref(fp, shape, rx, ry);
             int gx = plane_ref(fp, shape, imin(rx + 1, fp->width - 1), ry) - plane_ref(fp, shape, imax(rx - 1, 0), ry);
@@ -222,7 +226,7 @@ static void prs_pass_n(const or_pair *fp, int shape, int theta, int x0, int y0, 
 }
 
 void or_prs_pass(const or_pair *fp, int shape, int theta, int x0, int y0, int dx, int dy, int32_t *ux, int32_t *uy) {
-    prs_pass_n(fp, shape, theta, x0, y0, 16, dx, dy, ux, uy);
+    prs_pass_n(fp, shape, NULL, theta, x0, y0, 16, dx, dy, ux, uy);
 }
 
 /* Eq. 3 step in one axis: eps * U in Q.24, rounded half away from zero to
@@ -243,15 +247,17 @@ int or_step(int32_t u, int eps_q12, int max_step) {
  * when its distortion is strictly smaller, and stop at the first candidate
  * that does not improve, at a zero update, at the search-window border, or
  * after k_max candidates.  Returns the number of candidates evaluated.
+ * With `mask` (16 x 16 luma only) the passes and the distortions cover the
+ * pixels where it is non-zero.
  */
-static int pel_recursion_n(const or_pair *fp, const or_params *p, int shape, int x0, int y0, int n, int *dx, int *dy,
-                           uint32_t *cost) {
+static int pel_recursion_n(const or_pair *fp, const or_params *p, int shape, const uint8_t *mask, int x0, int y0,
+                           int n, int *dx, int *dy, uint32_t *cost) {
     int lox, hix, loy, hiy;
     box_n(fp, p, x0, y0, n, &lox, &hix, &loy, &hiy);
     int it = 0;
     while (it < p->k_max) {
         int32_t ux, uy;
-        prs_pass_n(fp, shape, p->theta, x0, y0, n, *dx, *dy, &ux, &uy);
+        prs_pass_n(fp, shape, mask, p->theta, x0, y0, n, *dx, *dy, &ux, &uy);
         int sx = or_step(ux, p->eps_q12, p->max_step);
         int sy = or_step(uy, p->eps_q12, p->max_step);
         if (sx == 0 && sy == 0) break;
@@ -259,7 +265,8 @@ static int pel_recursion_n(const or_pair *fp, const or_params *p, int shape, int
         int ny = iclamp(*dy + sy, loy, hiy);
         if (nx == *dx && ny == *dy) break;
         ++it;
-        uint32_t c = n == 16 ? block_cost(fp, shape, x0, y0, nx, ny) : sad_n(fp, x0, y0, n, nx, ny);
+        uint32_t c = n != 16 ? sad_n(fp, x0, y0, n, nx, ny)
+                              : (mask ? masked_sad(fp, x0, y0, nx, ny) : block_cost(fp, shape, x0, y0, nx, ny));
         if (c < *cost) {
             *dx = nx;
             *dy = ny;
@@ -273,7 +280,7 @@ static int pel_recursion_n(const or_pair *fp, const or_params *p, int shape, int
 
 static int pel_recursion(const or_pair *fp, const or_params *p, int shape, int x0, int y0, int *dx, int *dy,
                          uint32_t *cost) {
-    return pel_recursion_n(fp, p, shape, x0, y0, 16, dx, dy, cost);
+    return pel_recursion_n(fp, p, shape, NULL, x0, y0, 16, dx, dy, cost);
 }
 
 /* ------------------------------------------- half-sample refinement */
@@ -347,6 +354,10 @@ static int pa_mb(const or_pair *fp, const uint8_t *cls, const int16_t *t_field, 
     }
     int shape = shape_only || c == OR_BOUNDARY;
     if (shape && !has_alpha) return -1;
+    /* a reading of Section 3.1 (the temporal candidate of a boundary MB is
+     * evaluated on texture): its recursion refines on texture too, over the
+     * current VOP's pixels */
+    int mprs = p->masked_prs && !shape_only && c == OR_BOUNDARY;
     /* candidates A (left), B (up), C (up-right), T (same MB, previous
      * pair); neighbours outside the MB grid contribute (0, 0) */
     int cand[4][2];
@@ -418,7 +429,15 @@ static int pa_mb(const or_pair *fp, const uint8_t *cls, const int16_t *t_field, 
     int its = 0;
     int dx = bx, dy = by;
     uint32_t dc = bc;
-    if (seed && !shape) {
+    if (mprs) {
+        /* the candidate winner's luma SAD over the VOP pixels starts the
+         * recursion: one more compared block */
+        dc = masked_sad(fp, x0, y0, dx, dy);
+        pts += 1;
+        int it1 = pel_recursion_n(fp, p, 0, fp->cur_alpha, x0, y0, 16, &dx, &dy, &dc);
+        its += it1;
+        pts += it1;
+    } else if (seed && !shape) {
         /* learned start: clamp into the admissible window, refine,
          * and fall back to the plain recursion when the refined
          * distortion exceeds the BRS minimum by more than 5 % */
@@ -802,7 +821,7 @@ int or_prs8(const or_pair *fp, const uint8_t *cls, const int16_t *mv, const int1
                     int bx0 = 16 * h + 8 * (b & 1), by0 = 16 * v + 8 * (b >> 1);
                     int dx = half_to_full(mv_int[2 * k]), dy = half_to_full(mv_int[2 * k + 1]);
                     cost = sad_n(fp, bx0, by0, 8, dx, dy);
-                    its = pel_recursion_n(fp, p, 0, bx0, by0, 8, &dx, &dy, &cost);
+                    its = pel_recursion_n(fp, p, 0, NULL, bx0, by0, 8, &dx, &dy, &cost);
                     pts = its;
                     hx = 2 * dx;
                     hy = 2 * dy;
