@@ -97,6 +97,15 @@ typedef struct me_params {
                                        SAD over the MB's VOP pixels is strictly lower (one more compared
                                        block); the recursion then runs on the BABs as before.  Used by
                                        me_texture_recursive (me_shape_search ignores it) */
+#define ME_FLAG_MASKED_PRS 0x4u     /* a reading of Section 3.1 (T of a boundary MB evaluated on texture):
+                                       a boundary MB's pel recursion (Section 3.2) refines on luma over
+                                       the current VOP's pixels - its start is the candidate winner
+                                       (scored as above) with that winner's luma SAD over the VOP pixels
+                                       (one more compared block), each gradient pass sums only VOP
+                                       pixels, each candidate's distortion is its luma SAD over them,
+                                       and `cost` reports that SAD.  No half-sample step for boundary
+                                       MBs.  Used by me_texture_recursive and the batch
+                                       (me_shape_search ignores it) */
 #define ME_FLAG_LINE_WORKERS 0x100u /* schedule the proposed search with line workers (one MB position
                                        across a chain's pairs) even when no job's T field is written in
                                        the same call, where row workers (one MB row per wave) are the

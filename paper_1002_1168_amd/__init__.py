@@ -20,7 +20,7 @@ ME_MB_TRANSPARENT, ME_MB_OPAQUE, ME_MB_BOUNDARY = 0, 1, 2
 ME_ES, ME_TSS, ME_DS, ME_4SS = 0, 1, 2, 3
 ME_KT_CLASSIFY, ME_KT_SEARCH, ME_KT_FULL, ME_KT_MC, ME_KT_NET, ME_KT_NET_TRAIN, ME_KT_REFINE8 = 0, 1, 2, 3, 4, 5, 6
 ME_BATCH_SHAPE, ME_BATCH_AUTOTUNE = 1, 2
-ME_FLAG_UNRESTRICTED, ME_FLAG_T_TEXTURE, ME_FLAG_LINE_WORKERS = 0x1, 0x2, 0x100
+ME_FLAG_UNRESTRICTED, ME_FLAG_T_TEXTURE, ME_FLAG_MASKED_PRS, ME_FLAG_LINE_WORKERS = 0x1, 0x2, 0x4, 0x100
 ME_NET_PARAMS = 10434
 
 EXPORTED = ("me_default_params", "me_status_str", "me_shutdown", "me_classify_babs", "me_pad_vops",

@@ -266,7 +266,7 @@ int run_pa(const me_job *jobs, int n, const me_params *params, bool shape_only, 
     }
     // the several-wave line worker scores every candidate on the MB's own
     // plane; T on texture takes the one-wave worker
-    const int waves = (params->flags & ME_FLAG_T_TEXTURE) ? 1 : lines_waves(m.nlines);
+    const int waves = one_wave_lines(params->flags) ? 1 : lines_waves(m.nlines);
     int workers = std::min(m.nlines, pa_worker_cap() / waves);
     return hip_err(launch_pa((const JobDesc *)(base + m.o_jobs), m.n, m.total_mbs, (const ChainDesc *)(base + m.o_ch),
                              (const uint32_t *)(base + m.o_tk), m.nlines, (unsigned long long *)(zb + o_prog),

@@ -262,7 +262,7 @@ int autotune(me_batch &b) {
                 }
     }
     for (int wavesn : {1, 2, 4}) {
-        if (wavesn > 1 && (b.params.flags & ME_FLAG_T_TEXTURE)) break;  // the one-wave worker only
+        if (wavesn > 1 && one_wave_lines(b.params.flags)) break;  // the one-wave worker only
         // workgroups of `wavesn` waves; the same wave budget
         const int cap = std::min(b.plan.nlines, pa_worker_cap() / wavesn);
         std::vector<int> workers = {cap};
@@ -514,7 +514,7 @@ int me_batch_create(const me_job *jobs, int n, const me_params *params, uint32_t
     const size_t total = b->o_status + 256;
     const size_t table = sizeof(JobDesc) * (size_t)n;
     b->cfg[5] = m.unchained && !(params->flags & ME_FLAG_LINE_WORKERS) ? 1 : 0;
-    b->cfg[4] = b->cfg[5] ? kRowWaves : (params->flags & ME_FLAG_T_TEXTURE) ? 1 : lines_waves(m.nlines);
+    b->cfg[4] = b->cfg[5] ? kRowWaves : one_wave_lines(params->flags) ? 1 : lines_waves(m.nlines);
     b->cfg[0] = b->cfg[5] ? std::min(m.nbands, pa_rows_cap(params->search_range, params->half_pel != 0))
                           : std::min(m.nlines, pa_worker_cap() / b->cfg[4]);
     b->cfg[1] = plan_elems(params->search_range) > 0 ? 1 : 0;
@@ -656,7 +656,7 @@ int me_batch_set_config(me_batch *b, const int32_t *cfg, int ncfg) {
         if (cfg[0] < 1 || cfg[0] > std::min(b->plan.nbands, pa_rows_cap(b->params.search_range, b->params.half_pel != 0))) return ME_EINVAL;
     } else {
         if (waves != 1 && waves != 2 && waves != 4) return ME_EINVAL;
-        if (waves > 1 && (b->params.flags & ME_FLAG_T_TEXTURE)) return ME_EINVAL;
+        if (waves > 1 && one_wave_lines(b->params.flags)) return ME_EINVAL;
         // persistent workers: any count up to one per line (and the wave budget)
         if (cfg[0] < 1 || cfg[0] > std::min(b->plan.nlines, pa_worker_cap() / waves)) return ME_EINVAL;
     }

@@ -38,6 +38,8 @@ int hip_err(hipError_t e);
 // ME_OK when `dev` is a gfx950 device (cached after the first query).
 int check_device(int dev);
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+// Flags whose boundary-MB texture reads only the one-wave line worker has.
+inline bool one_wave_lines(uint32_t flags) { return (flags & (ME_FLAG_T_TEXTURE | ME_FLAG_MASKED_PRS)) != 0; }
 inline bool al4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
 
 // Append `count` objects to `b` at a 64-byte boundary; returns their offset.

@@ -43,7 +43,8 @@ int check_params(const me_params *p) {
     if (p->max_step < 1 || p->max_step > p->search_range) return ME_EINVAL;
     if (p->k_max < 0 || p->k_max > 255) return ME_EINVAL;
     if (p->half_pel != 0 && p->half_pel != 1) return ME_EINVAL;
-    if (p->flags & ~(ME_FLAG_LINE_WORKERS | ME_FLAG_UNRESTRICTED | ME_FLAG_T_TEXTURE)) return ME_EINVAL;
+    if (p->flags & ~(ME_FLAG_LINE_WORKERS | ME_FLAG_UNRESTRICTED | ME_FLAG_T_TEXTURE | ME_FLAG_MASKED_PRS))
+        return ME_EINVAL;
     return ME_OK;
 }
 
@@ -76,6 +77,7 @@ KParams kparams(const me_params *p, bool shape_only) {
     k.zero_t = p->eps_q12 > 0 ? (int32_t)(((1ll << 23) + p->eps_q12 - 1) / p->eps_q12) : 0x7FFFFFFF;
     k.unrestricted = (p->flags & ME_FLAG_UNRESTRICTED) ? 1 : 0;
     k.t_texture = (p->flags & ME_FLAG_T_TEXTURE) ? 1 : 0;
+    k.masked_prs = (p->flags & ME_FLAG_MASKED_PRS) && !shape_only ? 1 : 0;
     return k;
 }
 

@@ -248,8 +248,9 @@ struct Ctx {
     uint32_t c4;       // this lane's 4 current pixels
     bool shape;
     int lox, hix, loy, hiy;
-    // texture of a boundary MB, for T scored on texture (Section 3.1 text):
-    // the reference luma, its pitch, this lane's 4 current luma pixels
+    // texture of a boundary MB, for T scored on texture (Section 3.1 text) and
+    // the masked-luma recursion: the reference luma, its pitch, this lane's 4
+    // current luma pixels
     const uint8_t *ref_l;
     int st;
     uint32_t tl4;
@@ -322,8 +323,44 @@ __device__ __forceinline__ Sweep sweep(const Ctx &c, int dx, int dy) {
     return s;
 }
 
+// The pass of a boundary MB refined on texture over the current VOP's pixels
+// (c.c4: the 0/255 mask of the lane's 4 pixels, c.tl4: their luma): the
+// luma SAD and the gradient sums of Eqs. 3-5 over the masked pixels only,
+// the reference read from the frame with edge-clamped coordinates.
+__device__ __forceinline__ Sweep sweep_masked(const Ctx &c, int dx, int dy) {
+    const int ry = c.y0 + (lane() >> 2) + dy, rx = c.x0 + 4 * (lane() & 3) + dx;
+    const uint8_t *row = c.ref_l + (size_t)iclamp(ry, 0, c.H - 1) * c.st;
+    const uint32_t lo = ld4_clamped(row, rx - 1, c.W), hi = ld4_clamped(row, rx + 3, c.W);
+    const uint32_t up = ld4_clamped(c.ref_l + (size_t)iclamp(ry - 1, 0, c.H - 1) * c.st, rx, c.W);
+    const uint32_t dn = ld4_clamped(c.ref_l + (size_t)iclamp(ry + 1, 0, c.H - 1) * c.st, rx, c.W);
+    const uint32_t m = __builtin_amdgcn_alignbyte(hi, lo, 1);
+    const int lf = (int)(lo & 0xFF), rt = (int)((hi >> 8) & 0xFF);
+    const int sad = (int)__builtin_amdgcn_sad_u8(c.tl4 & c.c4, m & c.c4, 0u);
+    int sx = 0, sy = 0, nn = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool in = byte_of(c.c4, k) != 0;
+        const int e = byte_of(c.tl4, k) - byte_of(m, k);
+        const int left = k == 0 ? lf : byte_of(m, k - 1);
+        const int right = k == 3 ? rt : byte_of(m, k + 1);
+        const int rgx = in ? c.R[right - left + 255] : 0;
+        const int rgy = in ? c.R[byte_of(dn, k) - byte_of(up, k) + 255] : 0;
+        sx += e * rgx;
+        sy += e * rgy;
+        nn += (rgx != 0) + ((rgy != 0) << 16);
+    }
+    Sweep s;
+    s.sad = wave_sum(sad);
+    s.sx = wave_sum(sx);
+    s.sy = wave_sum(sy);
+    s.nxy = wave_sum(nn);
+    return s;
+}
+
 // Section 3.2 recursion from (dx, dy) with distortion `cost` and pass `sw`
-// at that point.  Returns the number of candidates evaluated.
+// at that point (MASKED: the masked-luma passes of a boundary MB refined on
+// texture).  Returns the number of candidates evaluated.
+template <bool MASKED = false>
 __device__ int pel_recursion(const Ctx &c, const KParams &kp, int &dx, int &dy, int &cost, Sweep sw) {
     int it = 0;
     // every value here is the same in all lanes: readfirstlane keeps the
@@ -345,8 +382,8 @@ __device__ int pel_recursion(const Ctx &c, const KParams &kp, int &dx, int &dy, 
         const int ty = uni(iclamp(dy + sy, c.loy, c.hiy));
         if (tx == dx && ty == dy) break;
         ++it;
-        const Sweep s2 = sweep(c, tx, ty);
-        const int c2 = cost_of(c, s2.sad);
+        const Sweep s2 = MASKED ? sweep_masked(c, tx, ty) : sweep(c, tx, ty);
+        const int c2 = MASKED ? s2.sad : cost_of(c, s2.sad);
         if (c2 < cost) {
             dx = tx;
             dy = ty;
@@ -468,6 +505,9 @@ struct MbOut {
 // Fig. 1 after the candidates are known: the admissible distinct list in the
 // order A, B, C, T, its first minimum, the recursion (from a learned seed
 // with the 5 % fallback when the job carries seeds), half-sample refinement.
+// MP: the instantiation that has the masked-luma recursion of boundary MBs
+// (kp.masked_prs); the others have no code for it.
+template <bool MP = false>
 __device__ MbOut search_mb(const uint32_t *seed, const Ctx &c, int k, int (&cx)[4], int (&cy)[4], const KParams &kp,
                            bool half = true) {
     // the candidates are the same in every lane: in scalar registers, and
@@ -544,7 +584,19 @@ __device__ MbOut search_mb(const uint32_t *seed, const Ctx &c, int k, int (&cx)[
     bc = uni(bc);
     int dc = bc;
     int pts = n + (tex_t ? 1 : 0), its = 0;
-    if (seed && !c.shape) {
+    if (MP && kp.masked_prs && c.shape) {
+        // a boundary MB refined on texture over its VOP pixels (a reading of
+        // Section 3.1): the winner's masked luma SAD (one more compared
+        // block) starts the recursion
+        const Sweep sw = sweep_masked(c, dx, dy);
+        dc = sw.sad;
+        pts += 1;
+        if (kp.k_max > 0) {
+            const int it1 = pel_recursion<true>(c, kp, dx, dy, dc, sw);
+            its += it1;
+            pts += it1;
+        }
+    } else if (seed && !c.shape) {
         const uint32_t w = (uint32_t)uni((int)ldg32(seed + k));
         int sx = iclamp(mvx_full(w), c.lox, c.hix), sy = iclamp(mvy_full(w), c.loy, c.hiy);
         const Sweep sw = sweep(c, sx, sy);
@@ -776,7 +828,7 @@ __global__ __launch_bounds__(256) void pa_scatter_tickets(const uint32_t *ticket
     out[pos] = tickets[t];
 }
 
-template <int EM>
+template <int EM, bool MP = false>
 __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
     extern __shared__ uint32_t lds[];
     __shared__ int slot;
@@ -942,7 +994,7 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
                 if (pf) plan.write(win0, pnv, c.shape);
             }
             c.c4 = c.shape ? bin4(cur4) : cur4;
-            if (kp.t_texture && c.shape && !kp.shape_only) {
+            if ((kp.t_texture || (MP && kp.masked_prs)) && c.shape && !kp.shape_only) {
                 c.ref_l = D.ptr<const uint8_t>(DW(ref));
                 c.st = st;
                 c.tl4 = ldg32((const uint32_t *)(D.ptr<const uint8_t>(DW(cur)) + (size_t)(y0 + j) * st + x0 + 4 * q));
@@ -999,7 +1051,7 @@ __global__ __launch_bounds__(64) void pa_kernel(PaArgs a) {
                     plan.issue(Prn, stn, pnv);
                 }
             }
-            const MbOut o = search_mb(D.ptr<const uint32_t>(DW(seed)), c, k, cx, cy, kp);
+            const MbOut o = search_mb<MP>(D.ptr<const uint32_t>(DW(seed)), c, k, cx, cy, kp);
             // publish: the wait leaves the next pair's loads (at least the
             // EM + 5 most recent vector-memory operations) in flight
             const unsigned long long word = progress_word(need, enc8(o.dx, o.dy), enc8(tx, ty), hist1);
@@ -1593,7 +1645,7 @@ __device__ __forceinline__ bool bit_of(const unsigned long long (&m)[4], int h) 
 // does not feed any neighbour): the next MB's block-recursive and
 // pel-recursive steps, which do, are not held up by it, and a row waiting
 // for the row above runs it in that wait.
-template <int EM, int NR, bool DB>
+template <int EM, int NR, bool DB, bool MP = false>
 __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
     extern __shared__ uint32_t lds[];
     __shared__ int slot;
@@ -1823,7 +1875,7 @@ __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
                 c.H = H;
                 set_box(c, kp, x0, y0, W, H);
                 c.c4 = c.shape ? bin4(cur4) : cur4;
-                if (kp.t_texture && c.shape && !kp.shape_only) {
+                if ((kp.t_texture || (MP && kp.masked_prs)) && c.shape && !kp.shape_only) {
                     c.ref_l = D.ptr<const uint8_t>(DW(ref));
                     c.st = st;
                     c.tl4 = ldg32((const uint32_t *)(D.ptr<const uint8_t>(DW(cur)) + (size_t)(y0 + j) * st + x0 + 4 * q));
@@ -1835,7 +1887,7 @@ __global__ __launch_bounds__(64 * NR) void pr_kernel(PrArgs a) {
                 // window writes visible to every lane: one wave, so completing
                 // its LDS writes (and a compiler fence) suffices
                 asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-                const MbOut o = search_mb(seed, c, k, cx, cy, kp, !DB);
+                const MbOut o = search_mb<MP>(seed, c, k, cx, cy, kp, !DB);
                 const uint32_t ovi = (uint32_t)uni((int)o.mvi);
                 if (l == 0) {
                     vvec[wv * 256 + h] = ovi;
@@ -1986,11 +2038,18 @@ hipError_t launch_pa_rows(const JobDesc *jobs, const ChainDesc *chains, const ui
         else                                                                                           \
             hipLaunchKernelGGL((pr_kernel<em, kRowWaves, false>), dim3(workers), blk, lds, s, a);     \
     } while (0)
-    switch (generic ? 0 : row_elems(kp.S)) {
-        case 4: ME_PR_LAUNCH(4); break;
-        case 13: ME_PR_LAUNCH(13); break;
-        case 28: ME_PR_LAUNCH(28); break;
-        default: ME_PR_LAUNCH(0); break;
+    if (kp.masked_prs) {  // the masked-luma recursion: generic staging only
+        if (dbl)
+            hipLaunchKernelGGL((pr_kernel<0, kRowWaves, true, true>), dim3(workers), blk, lds, s, a);
+        else
+            hipLaunchKernelGGL((pr_kernel<0, kRowWaves, false, true>), dim3(workers), blk, lds, s, a);
+    } else {
+        switch (generic ? 0 : row_elems(kp.S)) {
+            case 4: ME_PR_LAUNCH(4); break;
+            case 13: ME_PR_LAUNCH(13); break;
+            case 28: ME_PR_LAUNCH(28); break;
+            default: ME_PR_LAUNCH(0); break;
+        }
     }
 #undef ME_PR_LAUNCH
     hipError_t e = hipGetLastError();
@@ -2041,6 +2100,8 @@ hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainD
     const int rows = 2 * kp.S + 18;
     PaArgs a{jobs, chains, active, nactive, progress, counter, tmask, bmask, mask_words, status, kp,
              (rows + 3) & ~3, rows};
+    // the several-wave worker reads no texture for boundary MBs
+    if (waves >= 2 && (kp.t_texture || kp.masked_prs)) return hipErrorInvalidValue;
     timer_mark(t, true, s);
     if (waves >= 2) {
         const size_t lds2 = pa2_lds_bytes(kp.S, waves);
@@ -2057,12 +2118,18 @@ hipError_t launch_pa(const JobDesc *jobs, int njobs, int total_mbs, const ChainD
         timer_mark(t, false, s);
         return e;
     }
-    const size_t lds = pa_lds_bytes(kp.S, generic);
-    switch (generic ? 0 : plan_elems(kp.S)) {
-        case 4: hipLaunchKernelGGL(pa_kernel<4>, dim3(workers), dim3(64), lds, s, a); break;
-        case 12: hipLaunchKernelGGL(pa_kernel<12>, dim3(workers), dim3(64), lds, s, a); break;
-        case 28: hipLaunchKernelGGL(pa_kernel<28>, dim3(workers), dim3(64), lds, s, a); break;
-        default: hipLaunchKernelGGL(pa_kernel<0>, dim3(workers), dim3(64), lds, s, a); break;
+    // the masked-luma recursion: generic staging only
+    const bool gen = generic || kp.masked_prs;
+    const size_t lds = pa_lds_bytes(kp.S, gen);
+    if (kp.masked_prs) {
+        hipLaunchKernelGGL((pa_kernel<0, true>), dim3(workers), dim3(64), lds, s, a);
+    } else {
+        switch (gen ? 0 : plan_elems(kp.S)) {
+            case 4: hipLaunchKernelGGL(pa_kernel<4>, dim3(workers), dim3(64), lds, s, a); break;
+            case 12: hipLaunchKernelGGL(pa_kernel<12>, dim3(workers), dim3(64), lds, s, a); break;
+            case 28: hipLaunchKernelGGL(pa_kernel<28>, dim3(workers), dim3(64), lds, s, a); break;
+            default: hipLaunchKernelGGL(pa_kernel<0>, dim3(workers), dim3(64), lds, s, a); break;
+        }
     }
     e = hipGetLastError();
     timer_mark(t, false, s);

@@ -49,6 +49,7 @@ struct KParams {
     int32_t zero_t;      // |trunc(S / n)| < zero_t <=> zero step (eps > 0: ceil(2^23 / eps); eps = 0: INT_MAX)
     int32_t unrestricted;  // 1: vectors limited by S only, the reference extended by its edge pixels
     int32_t t_texture;     // 1: a boundary MB's T scored on texture (Section 3.1 text)
+    int32_t masked_prs;    // 1: a boundary MB's recursion refines on luma over the VOP pixels
 };
 
 // device status word bits

@@ -16,7 +16,8 @@ def say(*a):
 
 def oracle_params(p: me.me_params) -> oracle.Params:
     return oracle.Params(p.search_range, p.theta, p.eps_q12, p.max_step, p.k_max, p.half_pel,
-                         int(bool(p.flags & me.ME_FLAG_UNRESTRICTED)), int(bool(p.flags & me.ME_FLAG_T_TEXTURE)))
+                         int(bool(p.flags & me.ME_FLAG_UNRESTRICTED)), int(bool(p.flags & me.ME_FLAG_T_TEXTURE)),
+                         int(bool(p.flags & me.ME_FLAG_MASKED_PRS)))
 
 
 def gpu_classify(ds: dv.DeviceSequence):

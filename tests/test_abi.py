@@ -55,7 +55,7 @@ def job(**kw):
     (dict(search_range=0), me.ME_EINVAL), (dict(search_range=65), me.ME_EINVAL),
     (dict(theta=0), me.ME_EINVAL), (dict(eps_q12=-1), me.ME_EINVAL),
     (dict(max_step=0), me.ME_EINVAL), (dict(max_step=17), me.ME_EINVAL),
-    (dict(k_max=256), me.ME_EINVAL), (dict(half_pel=2), me.ME_EINVAL), (dict(flags=4), me.ME_EINVAL),
+    (dict(k_max=256), me.ME_EINVAL), (dict(half_pel=2), me.ME_EINVAL), (dict(flags=8), me.ME_EINVAL),
     (dict(flags=0x200), me.ME_EINVAL)])
 def test_bad_params(over, code):
     p = me.me_default_params(**over)

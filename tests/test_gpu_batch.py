@@ -321,6 +321,15 @@ def test_batch_graph_kernel_timing(torch_cuda):
     torch.cuda.synchronize()
 
 
+def test_batch_masked_prs(torch_cuda):
+    # the masked-luma recursion of boundary MBs in the batched frame step
+    # (row workers), with and without T on texture
+    seqs = synth.mixed_streams(seed=29, frames=4, counts=(1, 2, 1))
+    st = Streams(seqs, 3)
+    for flags in (me.ME_FLAG_MASKED_PRS, me.ME_FLAG_MASKED_PRS | me.ME_FLAG_T_TEXTURE):
+        run_batch(st, me.me_default_params(search_range=16, flags=flags), label=f"masked prs {flags}")
+
+
 def test_batch_t_on_texture(torch_cuda):
     # the Section 3.1 text reading in the batched frame step (row workers)
     seqs = synth.mixed_streams(seed=28, frames=4, counts=(1, 2, 1))

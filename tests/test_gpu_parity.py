@@ -162,6 +162,25 @@ def test_pa_t_on_texture(torch_cuda, mode):
              label=f"t-texture {mode}")
 
 
+# the masked-luma reading of a boundary MB's recursion, alone and with T on
+# texture: the chained launch (one-wave line workers), one call per pair (row
+# workers, and line workers forced), unrestricted vectors, half-pel at S=32
+@pytest.mark.parametrize("mode", ["chained", "rows", "lines", "unrestricted", "with-t-texture", "hd-halfpel"])
+def test_pa_masked_prs(torch_cuda, mode):
+    M = me.ME_FLAG_MASKED_PRS
+    if mode == "hd-halfpel":
+        seq = synth.hd_streams(frames=3, streams=1)[0]
+        check_pa(seq, [0, 1, 2], me.me_default_params(search_range=32, half_pel=1, flags=M), 2, one_call=False,
+                 label="masked prs hd")
+        return
+    seq = synth.cif_two_vops(frames=6)
+    flags = M | (me.ME_FLAG_LINE_WORKERS if mode == "lines" else 0) | \
+        (me.ME_FLAG_UNRESTRICTED if mode == "unrestricted" else 0) | \
+        (me.ME_FLAG_T_TEXTURE if mode == "with-t-texture" else 0)
+    check_pa(seq, [0, 1], me.me_default_params(search_range=16, flags=flags), 5, one_call=mode == "chained",
+             label=f"masked prs {mode}")
+
+
 # the Section 4 protocol: reference frame two back, T from the previous pair
 @pytest.mark.parametrize("one_call", [True, False])
 @pytest.mark.parametrize("flags", [0, me.ME_FLAG_UNRESTRICTED])
