@@ -59,8 +59,8 @@ enum : uint32_t { ST_SPIN_TIMEOUT = 1u, ST_BAD_CLASS = 2u, ST_ABORT = 4u };
 // Optional event pair recorded around the main kernel of a launch
 // (profiling).  With `split` set the launch is being captured into a graph:
 // events recorded during capture add no graph node, so the mark calls
-// split(ctx, kind, start, s) instead, which cuts the capture there; the
-// graph's owner then records the events between the launches of the pieces.
+// split(ctx, kind, start, s) instead, and the graph's owner adds the event
+// record to the graph itself.
 struct KernelTimer {
     hipEvent_t start = nullptr, stop = nullptr;
     void (*split)(void *ctx, int kind, bool start, hipStream_t s) = nullptr;
